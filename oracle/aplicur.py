@@ -1,0 +1,198 @@
+"""APLICUR (Alg. 3) and plain damped LSQR, FP64 on the CPU -- test infrastructure.
+
+``aplicur`` takes the steps of Alg. 3 in the paper's order:
+
+  Initialise  A_mu = [A; delta I], b_aug = [b; 0]; S = sparsesign(ceil(1.1 b), m, 8);
+              E_row = Y = S A; I = J = {}; d_cur = inf; x = 0.
+  repeat
+    Part 1    [I, J] = augmentCUR(...) (Alg. 7); C, U = A(I,J)^dagger, R;
+              E_row = Y - Y(:,J) U R; rho = randomized 2-norm bound (Sec. 5.3.1).
+    Part 2    [Q_R, T_R] = augmentQR(Q_R, T_R, A(I+,:)^T) (Alg. 9).
+    Part 3    if d_cur/(rho - eps_cur) >= nu_prec or rho <= eps_cur:
+                 P = CURPreconditioner Part 2 (Alg. 2); nu = inf in the final phase;
+                 x = lsqr(A_mu, b_aug, P, x, eps_lsqr, nu)  (warm start, Sec. 3.2);
+                 d_cur = rho - eps_cur.
+  until rho <= eps_cur.
+
+Readings (all listed in the design doc): delta = sqrt(mu); s = ceil(1.1 b) capped at
+m; eps_cur defaults to 30 sqrt(mu) (3e-7 when mu = 0, Sec. 8.3); the step is
+also final when the rank reaches min(n, max_rank) or the residual is exhausted;
+the final phase stops on the certified normal-equation bound (the
+Paige-Saunders eps_lsqr test, whose running Frobenius estimate of ||A~|| grows
+with the iteration count, is used only in intermediate phases); the requested
+accuracy eta <= tol_ne (eta = ||A^T(b - A x) - mu x|| / ||A^T b||,
+from a fresh FP64 residual) ends the solve as soon as it holds after a phase,
+and after the final phase further warm-started phases with the final P run
+until it holds (the iterative-refinement view of Sec. 3.2).
+Several right-hand sides share the sketch, the CUR sequence and every P (none
+of them reads b); each column runs its own LSQR phases, so the multi-RHS result
+is column-by-column the single-RHS one.
+"""
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import rng
+from .cur import (Preconditioner, augment_cur, augment_qr, core_and_residual,
+                  rho_estimate)
+from .lsqr import STOP_BUDGET, plsqr_phase
+
+
+@dataclass
+class Options:
+    block: int = 20
+    seed: int = 7
+    eps_cur: float = -1.0      # <= 0: default reading
+    nu_prec: float = 10.0
+    nu_lsqr: float = 100.0
+    eps_lsqr: float = 1e-10
+    tol_ne: float = 1e-8
+    max_iter: int = 100000
+    max_rank: int = 0          # <= 0: min(m, n)
+    r_probes: int = 10
+
+
+@dataclass
+class Trace:
+    ranks: list = field(default_factory=list)       # ell after each Part 1
+    rhos: list = field(default_factory=list)
+    rebuild: list = field(default_factory=list)     # whether Part 3 ran
+    phase_iters: list = field(default_factory=list)
+    phase_reason: list = field(default_factory=list)
+    etas: list = field(default_factory=list)        # true eta after each phase
+    I: list = field(default_factory=list)
+    J: list = field(default_factory=list)
+    sigma_hat: list = field(default_factory=list)
+    iters: int = 0
+
+
+def default_eps_cur(mu):
+    return 30.0 * math.sqrt(mu) if mu > 0.0 else 3e-7
+
+
+def sketch_rows(block, m):
+    return max(1, min(m, int(math.ceil(1.1 * block - 1e-12))))
+
+
+def ne_residual(A, b, x, mu):
+    """eta(x) = ||A^T(b - A x) - mu x|| / ||A^T b|| (0 when A^T b = 0)."""
+    atb = float(np.linalg.norm(A.T @ b))
+    if atb == 0.0:
+        return 0.0
+    return float(np.linalg.norm(A.T @ (b - A @ x) - mu * x)) / atb
+
+
+def lsqr_plain(A, b, mu, tol_ne=1e-8, eps_lsqr=0.0, max_iter=100000, x0=None):
+    """Plain damped LSQR on [A; sqrt(mu) I] (P = I), restarted from a fresh
+    residual until eta <= tol_ne; returns (x, iterations)."""
+    n = A.shape[1]
+    delta = math.sqrt(mu)
+    x = np.zeros(n) if x0 is None else x0.copy()
+    atb = float(np.linalg.norm(A.T @ b))
+    if atb == 0.0:
+        return x, 0
+    total = 0
+    while total < max_iter:
+        x, it, _ = plsqr_phase(A, delta, b, x, None, eps_lsqr=eps_lsqr, tol_ne=tol_ne,
+                               atb_norm=atb, baug_norm=float(np.linalg.norm(b)),
+                               max_iter=max_iter - total)
+        total += it
+        if ne_residual(A, b, x, mu) <= tol_ne or it == 0:
+            break
+    return x, total
+
+
+def aplicur(A, b, mu, opts=None, trace=None):
+    """Alg. 3 for one right-hand side; returns x (and fills ``trace``)."""
+    opts = opts or Options()
+    if b.ndim == 2:
+        return np.column_stack([aplicur(A, b[:, k], mu, opts, trace if k == 0 else None)
+                                for k in range(b.shape[1])])
+    A = A.tocsr() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    delta = math.sqrt(mu)
+    eps_cur = opts.eps_cur if opts.eps_cur > 0 else default_eps_cur(mu)
+    max_rank = min(m, n) if opts.max_rank <= 0 else min(opts.max_rank, m, n)
+    # initialisation
+    s = sketch_rows(opts.block, m)
+    S = rng.sparse_sign_matrix(opts.seed, s, m)
+    Y = np.asarray((S @ A).toarray() if sp.issparse(A) else S @ A, dtype=np.float64)
+    probes = rng.gaussian_probes(opts.seed, n, opts.r_probes)
+    E_row = Y.copy()
+    I = np.zeros(0, np.int64)
+    J = np.zeros(0, np.int64)
+    C = W = R = None
+    Q_R = T_R = None
+    d_cur = math.inf
+    x = np.zeros(n)
+    atb = float(np.linalg.norm(A.T @ b))
+    bnorm = float(np.linalg.norm(b))
+    if atb == 0.0:
+        return x
+    total = 0
+    eta = math.inf
+    while True:
+        # Part 1: update CUR
+        I_plus, J_plus, exhausted = augment_cur(A, E_row, I, J, C, W, R, opts.block)
+        if len(J_plus) == 0 and len(J) == 0:
+            break
+        I = np.concatenate([I, I_plus])
+        J = np.concatenate([J, J_plus])
+        C, W, R, E_row = core_and_residual(A, Y, I, J)
+        rho = rho_estimate(E_row, probes)
+        # Part 2: update the QR factorisation of R^T
+        if len(I_plus):
+            Q_R, T_R = augment_qr(Q_R, T_R, A[I_plus, :].T)
+        final = rho <= eps_cur or exhausted or len(J) >= max_rank
+        if trace is not None:
+            trace.ranks.append(len(J))
+            trace.rhos.append(rho)
+            trace.I, trace.J = I.copy(), J.copy()
+        # Part 3: re-precondition and run LSQR
+        gap = rho - eps_cur
+        rebuild = final or (d_cur / gap >= opts.nu_prec)
+        if trace is not None:
+            trace.rebuild.append(rebuild)
+        if rebuild:
+            P = Preconditioner(C, W, Q_R, T_R, delta)
+            nu = math.inf if final else opts.nu_lsqr
+            x, it, why = plsqr_phase(A, delta, b, x, P.inv, nu=nu, sigma_l=P.sigma_l,
+                                     eps_lsqr=0.0 if final else opts.eps_lsqr,
+                                     tol_ne=opts.tol_ne,
+                                     atb_norm=atb, pnorm=P.pnorm, baug_norm=bnorm,
+                                     max_iter=opts.max_iter - total)
+            total += it
+            d_cur = gap
+            eta = ne_residual(A, b, x, mu)
+            if trace is not None:
+                trace.phase_iters.append(it)
+                trace.phase_reason.append(why)
+                trace.etas.append(eta)
+                trace.sigma_hat.append(P.target)
+            if eta <= opts.tol_ne or total >= opts.max_iter:
+                break
+            if final:
+                # refinement phases with the final P until the accuracy holds
+                stalls = 0
+                while eta > opts.tol_ne and total < opts.max_iter and stalls < 3:
+                    eta_prev = eta
+                    x, it, why = plsqr_phase(A, delta, b, x, P.inv, sigma_l=P.sigma_l,
+                                             eps_lsqr=0.0, tol_ne=opts.tol_ne,
+                                             atb_norm=atb, pnorm=P.pnorm, baug_norm=bnorm,
+                                             max_iter=opts.max_iter - total)
+                    total += it
+                    eta = ne_residual(A, b, x, mu)
+                    if trace is not None:
+                        trace.phase_iters.append(it)
+                        trace.phase_reason.append(why)
+                        trace.etas.append(eta)
+                    if it == 0 or why == STOP_BUDGET:
+                        break
+                    stalls = stalls + 1 if eta > 0.5 * eta_prev else 0
+        if final:
+            break
+    if trace is not None:
+        trace.iters = total
+    return x

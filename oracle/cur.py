@@ -1,0 +1,153 @@
+"""CUR building blocks of APLICUR (oracle side) -- test infrastructure.
+
+* ``lupp_pivots``     -- first k row pivots of LU with partial pivoting, the
+                        selection rule of Alg. 7 (``lu(X,'vector')``).  Written
+                        as the textbook right-looking elimination; pinned in the
+                        tests against LAPACK getrf (scipy.linalg.lu_factor).
+* ``augment_cur``     -- Alg. 7 (augmentCUR).
+* ``core_and_residual`` -- C, U = A(I,J)^dagger, R and the sketched residual
+                        E_row = Y - Y(:,J) U R of Alg. 3, Part 1.
+* ``rho_estimate``    -- the randomized 2-norm bound of Sec. 5.3.1 with r probes.
+* ``augment_qr``      -- Alg. 9 (block classical Gram-Schmidt with one
+                        re-orthogonalisation, then QR of the remainder).
+* ``Preconditioner``  -- Alg. 2, Part 2 (SVD-based CUR preconditioner, eq. of
+                        Sec. 3.1 with target level sqrt(sigma_l^2 + delta^2)).
+
+Readings: ties in the pivot search go to the first maximal entry in the
+current row order (LAPACK idamax); a zero pivot column means the residual is
+exhausted and selection stops there; E_col uses the factors from before the
+augmentation (Alg. 7 forms it before the index sets are used to rebuild C, U, R).
+"""
+import math
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+RHO_CONST = 10.0 * math.sqrt(2.0 / math.pi)
+
+
+def _dense(X):
+    return X.toarray() if sp.issparse(X) else np.asarray(X, dtype=np.float64)
+
+
+def lupp_pivots(X, k):
+    """First ``k`` pivot rows of partial-pivoting LU of the r x c matrix X.
+
+    Returns (pivots, k_eff): ``pivots`` are original row indices in pivot
+    order; ``k_eff < k`` when a pivot column is identically zero.
+    """
+    X = np.array(_dense(X), dtype=np.float64, copy=True)
+    r, c = X.shape
+    k = min(k, r, c)
+    order = np.arange(r)  # order[p] = original row now at position p
+    for q in range(k):
+        col = np.abs(X[q:, q])
+        p = q + int(np.argmax(col))  # argmax returns the first maximum
+        if col[p - q] == 0.0:
+            return order[:q].copy(), q
+        if p != q:
+            X[[q, p], :] = X[[p, q], :]
+            order[[q, p]] = order[[p, q]]
+        l = X[q + 1:, q] / X[q, q]
+        X[q + 1:, q] = l
+        X[q + 1:, q + 1:] -= np.outer(l, X[q, q + 1:])
+    return order[:k].copy(), k
+
+
+def augment_cur(A, Y_res, I, J, C, W, R, block):
+    """Alg. 7 (augmentCUR): choose up to ``block`` new column and row indices.
+
+    ``Y_res`` is the current sketched residual E_row (s x n); ``C, W, R`` are
+    A(:,J), A(I,J), A(I,:) of the current approximation (None when empty).
+    Returns (I_plus, J_plus, exhausted).
+    """
+    m, n = A.shape
+    s = Y_res.shape[0]
+    ell = len(J)
+    beff = min(block, n - ell, m - ell, s)
+    if beff <= 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64), True
+    E = np.array(Y_res, copy=True)
+    if ell:
+        E[:, J] = 0.0
+    J_plus, k1 = lupp_pivots(E.T, beff)
+    Acols = _dense(A[:, J_plus])
+    if ell:
+        # E_col = A(:,J+) - C U R(:,J+) with U = W^{-1} (pre-augmentation factors)
+        UR = sla.lu_solve(sla.lu_factor(W), _dense(R[:, J_plus]))
+        E_col = Acols - _dense(C @ UR)
+        E_col[I, :] = 0.0
+    else:
+        E_col = Acols
+    I_plus, k2 = lupp_pivots(E_col, k1)
+    J_plus = J_plus[:k2]
+    return I_plus, J_plus, (k2 < beff)
+
+
+def core_and_residual(A, Y, I, J):
+    """C, W = A(I,J), R and E_row = Y - Y(:,J) W^{-1} R (Alg. 3, Part 1)."""
+    C = A[:, J]
+    R = A[I, :]
+    W = _dense(A[I, :][:, J])
+    lu = sla.lu_factor(W)
+    YJU = sla.lu_solve(lu, Y[:, J].T, trans=1).T  # Y(:,J) W^{-1}
+    E_row = Y - _dense((sp.csr_matrix(YJU) @ R) if sp.issparse(R) else YJU @ R)
+    return C, W, R, E_row
+
+
+def rho_estimate(E_row, probes):
+    """rho = 10 sqrt(2/pi) max_i ||E_row w_i|| (Sec. 5.3.1)."""
+    return RHO_CONST * float(np.max(np.linalg.norm(E_row @ probes, axis=0)))
+
+
+def augment_qr(Q, T, Cnew):
+    """Alg. 9: QR of [Q T, Cnew] from the QR Q T of the old block."""
+    Cnew = _dense(Cnew)
+    if Q is None or Q.shape[1] == 0:
+        Qe, Re = np.linalg.qr(Cnew)
+        sg = np.where(np.diag(Re) < 0, -1.0, 1.0)
+        return Qe * sg, Re * sg[:, None]
+    P1 = Q.T @ Cnew
+    E = Cnew - Q @ P1
+    P2 = Q.T @ E
+    E = E - Q @ P2
+    Qe, Re = np.linalg.qr(E)
+    sg = np.where(np.diag(Re) < 0, -1.0, 1.0)
+    Qe, Re = Qe * sg, Re * sg[:, None]
+    l, p = T.shape[0], Cnew.shape[1]
+    Tn = np.zeros((l + p, l + p))
+    Tn[:l, :l] = T
+    Tn[:l, l:] = P1 + P2
+    Tn[l:, l:] = Re
+    return np.hstack([Q, Qe]), Tn
+
+
+class Preconditioner:
+    """SVD-based CUR preconditioner (Alg. 2, Part 2; Sec. 3.1).
+
+    P = sigma^{-1} V Lam V^T + (I - V V^T),  Lam = sqrt(Sigma^2 + delta^2),
+    sigma = sqrt(sigma_l^2 + delta^2), built from T_C = chol(C^T C),
+    M = T_C U T_R^T = U_M Sigma V_M^T and V = Q_R V_M.
+    """
+
+    def __init__(self, C, W, Q_R, T_R, delta):
+        CtC = _dense(C.T @ C)
+        T_C = np.linalg.cholesky(CtC).T  # upper, T_C^T T_C = C^T C
+        M = T_C @ sla.lu_solve(sla.lu_factor(W), T_R.T)
+        _, sig, VmT = np.linalg.svd(M)
+        self.sigma = sig
+        self.V = Q_R @ VmT.T
+        self.Lam = np.sqrt(sig ** 2 + delta ** 2)
+        self.target = math.sqrt(sig[-1] ** 2 + delta ** 2)
+        self.d = self.target / self.Lam - 1.0
+        self.sigma_l = float(sig[-1])  # unregularised smallest singular value
+        self.pnorm = max(1.0, float(self.Lam[0]) / self.target)
+
+    def inv(self, z):
+        """P^{-1} z = z + V ((sigma/Lam - 1) * (V^T z)); P is symmetric."""
+        return z + self.V @ (self.d * (self.V.T @ z))
+
+    def dense_inverse(self):
+        n = self.V.shape[0]
+        return np.eye(n) + (self.V * self.d) @ self.V.T

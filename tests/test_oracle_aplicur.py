@@ -1,0 +1,121 @@
+"""Pins of the oracle's full procedure (Alg. 3): the solution is the unique
+minimiser (dense QR), the normal-equation invariant holds, the multi-RHS
+reading is column-by-column, and degenerate inputs behave."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle.aplicur import Options, Trace, aplicur, ne_residual
+from oracle.dense import adjoint, gram_solve, solve_dense_qr, solve_normal
+from workloads import synth
+
+
+def _floor(A, mu):
+    Ad = A.toarray() if sp.issparse(A) else A
+    s = np.linalg.svd(Ad, compute_uv=False)
+    kappa = math.sqrt((s[0] ** 2 + mu) / (s[-1] ** 2 + mu))
+    return kappa
+
+
+def test_workload1_small():
+    w = synth.workload(1, 0.25)
+    tr = Trace()
+    x = aplicur(w.A, w.B, w.mu, Options(block=w.block, tol_ne=w.tol), tr)
+    eta = ne_residual(w.A, w.B, x, w.mu)
+    assert eta <= w.tol
+    xr = solve_dense_qr(w.A, w.B, w.mu)
+    # the normal-equation residual pins x only up to eta ||A^T b|| / sigma_min^2
+    smin = np.linalg.svd(w.A, compute_uv=False)[-1]
+    bound = eta * np.linalg.norm(w.A.T @ w.B) / smin ** 2
+    assert np.linalg.norm(x - xr) <= 2 * bound + 1e-9 * np.linalg.norm(xr)
+    assert tr.ranks == sorted(tr.ranks) and tr.rebuild[0] and tr.rebuild[-1]
+    # at a tight tolerance the iterate reaches the dense-QR solution
+    kappa = _floor(w.A, w.mu)
+    x2 = aplicur(w.A, w.B, w.mu, Options(block=w.block, tol_ne=1e-14))
+    assert np.linalg.norm(x2 - xr) / np.linalg.norm(xr) <= 1e3 * kappa * 2.2e-16
+
+
+def test_workload2_small_sparse():
+    w = synth.workload(2, 0.02)
+    tr = Trace()
+    x = aplicur(w.A, w.B, w.mu, Options(block=w.block, tol_ne=w.tol), tr)
+    assert ne_residual(w.A, w.B, x, w.mu) <= w.tol
+    xr = solve_normal(w.A.toarray(), w.B, w.mu)
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-6
+    A = w.A
+    np.testing.assert_allclose(A.T @ (w.B - A @ x), w.mu * x,
+                               atol=1e-7 * np.linalg.norm(A.T @ w.B))
+
+
+def test_residual_monotone_across_phases():
+    r = np.random.default_rng(0)
+    sigma = np.concatenate([np.logspace(2, -2, 10), np.logspace(-4.8, -5, 40)])
+    A = synth.dense_svd(r, 200, 50, sigma)
+    xs, b = synth.consistent_x(r, A, noise=1e-2)
+    mu = 1e-4
+    opts = Options(block=5, tol_ne=1e-12)
+    # true augmented residual after each phase must not increase (Sec. 3.2)
+    res = []
+    orig = aplicur.__globals__["plsqr_phase"]
+
+    def spy(A_, delta, b_, x, pinv, **kw):
+        out = orig(A_, delta, b_, x, pinv, **kw)
+        xn = out[0]
+        res.append(math.hypot(np.linalg.norm(b_ - A_ @ xn), delta * np.linalg.norm(xn)))
+        return out
+    aplicur.__globals__["plsqr_phase"] = spy
+    try:
+        x = aplicur(A, b, mu, opts)
+    finally:
+        aplicur.__globals__["plsqr_phase"] = orig
+    assert len(res) >= 2
+    assert all(res[i + 1] <= res[i] * (1 + 1e-12) for i in range(len(res) - 1))
+    np.testing.assert_allclose(x, solve_dense_qr(A, b, mu), rtol=1e-6)
+
+
+def test_multi_rhs_is_columnwise():
+    w = synth.workload(1, 0.2)
+    B = np.column_stack([w.B, np.random.default_rng(1).standard_normal(w.B.shape[0])])
+    X = aplicur(w.A, B, 1e-6, Options(block=4, tol_ne=1e-9))
+    for k in range(2):
+        xk = aplicur(w.A, B[:, k], 1e-6, Options(block=4, tol_ne=1e-9))
+        np.testing.assert_array_equal(X[:, k], xk)
+
+
+def test_zero_rhs():
+    A = np.random.default_rng(2).standard_normal((30, 8))
+    x = aplicur(A, np.zeros(30), 0.1, Options(block=2))
+    assert np.all(x == 0)
+
+
+def test_rank_cap_same_solution():
+    w = synth.workload(2, 0.02)
+    xr = solve_normal(w.A.toarray(), w.B, w.mu)
+    x = aplicur(w.A, w.B, w.mu, Options(block=w.block, tol_ne=1e-9, max_rank=3 * w.block))
+    assert ne_residual(w.A, w.B, x, w.mu) <= 1e-9
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-6
+
+
+def test_adjoint_matches_finite_differences():
+    r = np.random.default_rng(3)
+    m, n, k, mu = 30, 8, 2, 0.05
+    A = r.standard_normal((m, n))
+    B = r.standard_normal((m, k))
+
+    def loss(A_, B_):
+        X = solve_dense_qr(A_, B_, mu)
+        return float(np.sum(X * X))
+    X = solve_dense_qr(A, B, mu)
+    Z, dB, dA = adjoint(A, X, B, 2.0 * X, mu)
+    # normal-equations route for Z
+    np.testing.assert_allclose(Z, gram_solve(A, 2.0 * X, mu), rtol=1e-10)
+    h = 1e-3
+    for _ in range(6):
+        D = r.standard_normal((m, n)); D /= np.linalg.norm(D)
+        fd = (loss(A + h * D, B) - loss(A - h * D, B)) / (2 * h)
+        assert abs(fd - np.sum(dA * D)) <= 1e-5 * max(1.0, abs(fd))
+        E = r.standard_normal((m, k)); E /= np.linalg.norm(E)
+        fd = (loss(A, B + h * E) - loss(A, B - h * E)) / (2 * h)
+        assert abs(fd - np.sum(dB * E)) <= 1e-5 * max(1.0, abs(fd))

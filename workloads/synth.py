@@ -1,0 +1,154 @@
+"""Synthetic least-squares problems (inputs only; no method arithmetic).
+
+Families follow the test sets of Sec. 6.3 of the paper and the five
+benchmark workloads used by this project:
+
+* ``haar``            -- Haar-distributed orthonormal columns (QR of a Gaussian
+                         with the signs of diag(R) folded in; Mezzadri 2007).
+* ``dense_svd``       -- A = U diag(sigma) V^T with Haar U, V (dense incoherent
+                         family of Sec. 6.3.2).
+* ``sparse_scaled``   -- CSR with a fixed number of distinct uniformly random
+                         columns per row, N(0,1) values, column j scaled by
+                         10^(-decades * j / (n - 1)).
+* ``rbf_kernel``      -- Gaussian RBF kernel matrix exp(-||p_i - p_j||^2 / (2 h^2))
+                         on points uniform in [0,1]^d.
+* ``consistent_x``    -- b = A x* + e with e orthogonal to range(A) (Sec. 6.3.1).
+* ``workload(c, ...)`` -- workload c in 1..5 at full or reduced size.
+
+Seeds: numpy ``Generator(PCG64(1000 c + k))``, k = 0 for A, 1 for B,
+2 for points / problem sizes.
+"""
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = ["rng_for", "haar", "dense_svd", "sparse_scaled", "rbf_kernel", "consistent_x",
+           "workload", "batch_shapes", "Workload"]
+
+
+def rng_for(c, k):
+    return np.random.Generator(np.random.PCG64(1000 * c + k))
+
+
+def haar(rng, m, n):
+    G = rng.standard_normal((m, n))
+    Q, R = np.linalg.qr(G)
+    return Q * np.where(np.diag(R) < 0, -1.0, 1.0)
+
+
+def dense_svd(rng, m, n, sigma):
+    U = haar(rng, m, n)
+    V = haar(rng, n, n)
+    return (U * sigma) @ V.T
+
+
+def sparse_scaled(rng, m, n, per_row, decades):
+    """CSR m x n, ``per_row`` distinct sorted uniform columns per row."""
+    per_row = min(per_row, n)
+    cols = np.empty((m, per_row), dtype=np.int64)
+    pending = np.arange(m)
+    while pending.size:
+        draw = rng.integers(0, n, size=(pending.size, per_row))
+        srt = np.sort(draw, axis=1)
+        ok = np.all(srt[:, 1:] != srt[:, :-1], axis=1) if per_row > 1 else np.ones(pending.size, bool)
+        cols[pending[ok]] = srt[ok]
+        pending = pending[~ok]
+    vals = rng.standard_normal((m, per_row))
+    scale = 10.0 ** (-decades * np.arange(n) / max(n - 1, 1))
+    vals = vals * scale[cols]
+    indptr = np.arange(0, m * per_row + 1, per_row, dtype=np.int64)
+    return sp.csr_matrix((vals.reshape(-1), cols.reshape(-1), indptr), shape=(m, n))
+
+
+def rbf_kernel(rng, npts, dim=8, h=1.0, dtype=np.float32):
+    P = rng.random((npts, dim))
+    sq = np.sum(P * P, axis=1)
+    D2 = np.maximum(sq[:, None] + sq[None, :] - 2.0 * (P @ P.T), 0.0)
+    return np.exp(-D2 / (2.0 * h * h)).astype(dtype)
+
+
+def consistent_x(rng, A, noise=0.0):
+    """b = A x* + e, x* ~ N(0, I), e ~ noise * N(0, I) projected off range(A) twice."""
+    Ad = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
+    m, n = Ad.shape
+    xs = rng.standard_normal(n)
+    b = Ad @ xs
+    if noise > 0.0:
+        Q, _ = np.linalg.qr(Ad)
+        e = rng.standard_normal(m)
+        for _ in range(2):
+            e = e - Q @ (Q.T @ e)
+        b = b + noise * e / np.linalg.norm(e)
+    return xs, b
+
+
+class Workload:
+    def __init__(self, name, A, B, mu, block, tol, dtype):
+        self.name, self.A, self.B, self.mu, self.block, self.tol, self.dtype = \
+            name, A, B, mu, block, tol, dtype
+
+    def __repr__(self):
+        return f"Workload({self.name}, A{self.A.shape}, B{self.B.shape}, mu={self.mu}, b={self.block})"
+
+
+def batch_shapes(count=64, seed_c=4, m_range=(5000, 100000), n_range=(500, 5000)):
+    """Sizes of the batched workload: m ~ U{m_lo..m_hi}, then
+    n ~ U{n_lo..min(n_hi, floor(m/4))}, decay k ~ U[2, 8]."""
+    rng = rng_for(seed_c, 2)
+    out = []
+    for _ in range(count):
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+        n = int(rng.integers(n_range[0], min(n_range[1], m // 4) + 1))
+        k = float(rng.uniform(2.0, 8.0))
+        out.append((m, n, k))
+    return out
+
+
+def workload(c, scale=1.0):
+    """Workload c (1..5).  ``scale`` < 1 shrinks m and n for tests.
+
+    1: dense FP64 2000 x 200, sigma_i = 10^(-6 i / 200), consistent-x with
+       1e-6 Gaussian noise, mu = 0, block 20, tol 1e-10.
+    2: CSR 200000 x 20000, 10 non-zeros per row, column scaling logspace(0,-6),
+       b ~ N(0,1), mu = 1e-4, block 100, tol 1e-8.
+    3: RBF kernel (h = 1) on 40000 points in [0,1]^8, FP32, 16 RHS, mu = 1e-3,
+       block 250, tol 1e-8.
+    4: see ``batch_shapes`` (one problem per call is built by ``batch_problem``).
+    5: dense FP32 100000 x 2000, sigma_i = 10^(-5 i / 2000), 32 RHS, mu = 1e-5,
+       block 100, tol 1e-8.
+    """
+    ra, rb = rng_for(c, 0), rng_for(c, 1)
+    if c == 1:
+        m, n = max(8, int(2000 * scale)), max(4, int(200 * scale))
+        sigma = 10.0 ** (-6.0 * np.arange(1, n + 1) / n)
+        A = dense_svd(ra, m, n, sigma)
+        xs = rb.standard_normal(n)
+        b = A @ xs + 1e-6 * rb.standard_normal(m)
+        return Workload("dense-svd-2000x200", A, b, 0.0, max(2, int(20 * scale)), 1e-10, "f64")
+    if c == 2:
+        m, n = max(16, int(200000 * scale)), max(8, int(20000 * scale))
+        A = sparse_scaled(ra, m, n, 10, 6.0)
+        b = rb.standard_normal(m)
+        return Workload("csr-200000x20000-nnz10", A, b, 1e-4, max(2, int(100 * scale)), 1e-8, "f64")
+    if c == 3:
+        npts = max(16, int(40000 * scale))
+        A = rbf_kernel(rng_for(c, 2), npts)
+        B = rb.standard_normal((npts, 16)).astype(np.float32)
+        return Workload("rbf-kernel-40000", A, B, 1e-3, max(2, int(250 * scale)), 1e-8, "f32")
+    if c == 5:
+        m, n = max(16, int(100000 * scale)), max(8, int(2000 * scale))
+        sigma = 10.0 ** (-5.0 * np.arange(1, n + 1) / n)
+        A = dense_svd(ra, m, n, sigma).astype(np.float32)
+        B = rb.standard_normal((m, 32)).astype(np.float32)
+        return Workload("dense-svd-100000x2000-adjoint", A, B, 1e-5, max(2, int(100 * scale)), 1e-8, "f32")
+    raise ValueError(f"workload {c}: use batch_shapes/batch_problem for the batched workload")
+
+
+def batch_problem(idx, m, n, k, nrhs=8, dtype=np.float32):
+    """Problem ``idx`` of the batched workload (dense FP32, Haar factors)."""
+    r = np.random.Generator(np.random.PCG64(4000 + 17 * idx + 3))
+    sigma = 10.0 ** (-k * np.arange(1, n + 1) / n)
+    A = dense_svd(r, m, n, sigma).astype(dtype)
+    B = r.standard_normal((m, nrhs)).astype(dtype)
+    return A, B
