@@ -1,0 +1,184 @@
+/*
+ * aplicur.h -- C ABI of the MI355X (gfx950) APLICUR library, libaplicur.so.
+ *
+ * APLICUR (Huh, Cartis, Nakatsukasa, "Adaptive LSQR Preconditioning from One
+ * Small Sketch") solves the regularised linear least-squares problem of
+ * Sec. 1 (eq. (1.1)),
+ *
+ *        min_x ||A x - b||_2^2 + mu ||x||_2^2 ,    A in R^{m x n}, mu >= 0,
+ *
+ * by LSQR on the augmented operator A_mu = [A; sqrt(mu) I] (Sec. 2.1), right-
+ * preconditioned by a CUR-based spectral preconditioner (Sec. 3.1, Alg. 2)
+ * whose rank grows adaptively from one small sparse sign sketch S A
+ * (Definition 5.1, Alg. 7) and which is rebuilt only when the CUR error
+ * estimate has improved enough (Sec. 5.3, Alg. 3).
+ *
+ * Conventions common to every entry point
+ *  - Every pointer argument is a DEVICE pointer unless marked (host).
+ *  - The caller owns every buffer it passes; the library never frees them.
+ *    The opaque context owns the device memory the library allocates itself
+ *    (sketch, CUR factors, preconditioner, work vectors) and releases it in
+ *    aplicur_ctx_destroy.
+ *  - A is borrowed by the context: it must stay alive and unmodified until
+ *    aplicur_ctx_destroy.
+ *  - Right-hand sides B and solutions X are FP64, column-major (each column
+ *    one right-hand side, contiguous), leading dimensions ldb >= m, ldx >= n.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *    The solve reads a few scalars back per outer step and per block of LSQR
+ *    iterations, so the calls return only when their results are ready.
+ *  - Return value: APLICUR_OK (0), a positive warning (results valid) or a
+ *    negative error (outputs undefined).  aplicur_last_error() returns a
+ *    thread-local message describing the last error of the calling thread.
+ *  - Not thread-safe per context: one context must not be used from two
+ *    threads at once.  Distinct contexts are independent.
+ */
+#ifndef APLICUR_H
+#define APLICUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define APLICUR_OK 0
+#define APLICUR_W_MAXITER 1      /* iteration budget reached before tol_ne (x valid) */
+#define APLICUR_E_INVALID (-1)   /* bad argument (shape, null pointer, option range) */
+#define APLICUR_E_HIP (-3)       /* HIP runtime / rocBLAS failure */
+#define APLICUR_E_BREAKDOWN (-4) /* non-finite value met (NaN/Inf in A or B, or overflow) */
+#define APLICUR_E_NOMEM (-5)     /* device allocation failed */
+
+/* ------------------------------------------------------------------ matrix */
+#define APLICUR_DENSE 0 /* row-major m x n, leading dimension ld >= n            */
+#define APLICUR_CSR 2   /* CSR: row_ptr[m+1], col_idx[nnz] (int32, any order), val[nnz] */
+#define APLICUR_F64 0
+#define APLICUR_F32 1
+
+typedef struct aplicur_mat {
+  int32_t format;         /* APLICUR_DENSE or APLICUR_CSR                     */
+  int32_t dtype;          /* APLICUR_F64 or APLICUR_F32 (values of A)         */
+  int64_t m, n;           /* rows, columns (m >= 1, n >= 1)                   */
+  int64_t ld;             /* dense: leading dimension (elements), >= n        */
+  int64_t nnz;            /* CSR: number of stored entries (< 2^31)           */
+  const void* val;        /* dense: m*ld values; CSR: nnz values              */
+  const int32_t* row_ptr; /* CSR only (device), else NULL                     */
+  const int32_t* col_idx; /* CSR only (device), else NULL; no duplicates      */
+} aplicur_mat;
+
+/* ------------------------------------------------------------------ options
+ * Hyper-parameters of Alg. 3 (defaults of Sec. 7 / App. C); fill with
+ * aplicur_opts_default() and override.  Readings of the paper used here:
+ * the objective weight mu enters A_mu as delta = sqrt(mu); the sketch has
+ * s = ceil(1.1 block) rows (capped at m) with xi = min(8, s) non-zeros per
+ * column; eps_cur <= 0 selects 30 sqrt(mu) (3e-7 when mu = 0).            */
+typedef struct aplicur_opts {
+  int32_t block;     /* rank increment b of Alg. 3 (1..280); sketch dim s = ceil(1.1 b)  */
+  int32_t r_probes;  /* Gaussian probes of the 2-norm bound (Sec. 5.3.1), 1..64, default 10 */
+  uint64_t seed;     /* seed of the sketch / probe stream (SplitMix64)                     */
+  double mu;         /* regularisation weight, >= 0                                        */
+  double eps_cur;    /* CUR tolerance on rho; <= 0: default reading                        */
+  double nu_prec;    /* re-preconditioning tolerance (default 10)                          */
+  double nu_lsqr;    /* dynamic LSQR stopping tolerance (default 100)                      */
+  double eps_lsqr;   /* Paige-Saunders tolerance of intermediate phases (default 1e-10)    */
+  double tol_ne;     /* requested ||A^T(b-Ax) - mu x|| / ||A^T b|| (default 1e-8)         */
+  int32_t max_iter;  /* LSQR iteration budget per right-hand side (default 100000)         */
+  int32_t max_rank;  /* cap on the CUR rank l (<= 0: min(m, n, 4096)); reaching it ends the
+                        rank growth like rho <= eps_cur                                      */
+  int32_t precond;   /* 1: APLICUR (default); 0: plain LSQR on A_mu (no sketch, no CUR)   */
+  int32_t precision; /* 0: FP64 vectors and products (default)                             */
+  int32_t max_outer; /* stop after this many outer steps (<= 0: no limit; for tests)       */
+  int32_t reserved[7];
+} aplicur_opts;
+
+/* ------------------------------------------------------------------ info  */
+typedef struct aplicur_info { /* (host) */
+  int32_t status;      /* same value as returned                                  */
+  int32_t phases;      /* LSQR phases run (max over right-hand sides)             */
+  int32_t iters;       /* LSQR iterations (max over right-hand sides)             */
+  int32_t rank;        /* final CUR rank l                                         */
+  int32_t rebuilds;    /* preconditioner builds                                    */
+  int32_t outer;       /* outer (rank-increment) steps                             */
+  double eta;          /* max over columns of the final eta, FP64 from a fresh residual */
+  double rho;          /* last CUR error estimate                                  */
+  double sigma_hat;    /* last target level sqrt(sigma_l^2 + mu)                   */
+  double t_sketch_ms, t_cur_ms, t_precond_ms, t_lsqr_ms; /* time split (host clock) */
+} aplicur_info;
+
+typedef struct aplicur_ctx aplicur_ctx;
+
+/* Default options (Alg. 3 defaults: block 20, nu_prec 10, nu_lsqr 100,
+ * eps_lsqr 1e-10, tol_ne 1e-8, r_probes 10, seed 7, mu 0).                */
+void aplicur_opts_default(aplicur_opts* opts /* (host) */);
+
+/* Set-up of Alg. 3 (initialisation): validates A, builds the CSR of A^T
+ * (CSR input), draws the sparse sign embedding S (s x m) and the probes, and
+ * forms the sketch Y = S A in FP64 once (Alg. 3, initialisation; Sec. 5.1).
+ * A (host struct) describes device arrays, borrowed until ctx destruction.
+ * opts (host) is copied.  *ctx_out (host) receives the new context.
+ * Errors: E_INVALID (shape/options), E_NOMEM, E_HIP.                       */
+int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* stream, aplicur_ctx** ctx_out);
+
+/* The adaptive solve of Alg. 3 for nrhs right-hand sides B (m x nrhs,
+ * column-major, ldb >= m) into X (n x nrhs, ldx >= n).  All columns share
+ * the CUR sequence and every preconditioner (none depends on b); each
+ * column runs its own LSQR phases with its own dynamic stopping.  With
+ * x_is_warm != 0 the first phase starts from the given X (warm start,
+ * Sec. 3.2), otherwise from 0.  The context remembers the final CUR state
+ * and preconditioner for aplicur_solve_backward.  info (host) may be NULL.
+ * Returns OK, W_MAXITER, or an error.                                      */
+int aplicur_solve(aplicur_ctx* ctx, const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,
+                  int32_t x_is_warm, aplicur_info* info, void* stream);
+
+/* Independent problems A[p] x = B[p] (p < batch) with the same options:
+ * A, B, ldb, X, ldx and info are (host) arrays of length batch; B[p] / X[p]
+ * are device pointers (FP64, column-major, nrhs columns each).  Problems
+ * run one after another on `stream` through the same kernels as
+ * aplicur_solve.  Returns the first error, else the largest warning.       */
+int aplicur_solve_batched(int32_t batch, const aplicur_mat* A, const double* const* B, const int64_t* ldb,
+                          int32_t nrhs, double* const* X, const int64_t* ldx, const aplicur_opts* opts,
+                          aplicur_info* info, void* stream);
+
+/* Adjoint of the solve (not in the paper; implicit differentiation of the
+ * normal equations A^T (B - A X) = mu X).  For a loss with G = dL/dX
+ * (n x nrhs, ldg), computes
+ *    Z  = (A^T A + mu I)^{-1} G     by preconditioned LSQR on A_mu with the
+ *                                    right-hand side [0; G / sqrt(mu)] and
+ *                                    the context's final preconditioner,
+ *    dB = A Z                        (m x nrhs, lddb)          = dL/dB,
+ *    dA = (B - A X) Z^T - (A Z) X^T  (dense A: m x n row-major with
+ *                                    leading dimension ldda; CSR A: nnz
+ *                                    values on the sparsity pattern)   = dL/dA.
+ * X, B are the forward solution and right-hand sides.  Requires mu > 0 and
+ * a context on which aplicur_solve has run.  dA may be NULL (skipped); Z
+ * (n x nrhs, ldz) receives Z.  Errors: E_INVALID, E_HIP, E_BREAKDOWN.      */
+int aplicur_solve_backward(aplicur_ctx* ctx, const double* X, int64_t ldx, const double* B, int64_t ldb,
+                           const double* G, int64_t ldg, int32_t nrhs, double* Z, int64_t ldz, double* dB,
+                           int64_t lddb, double* dA, int64_t ldda, aplicur_info* info, void* stream);
+
+/* y = A x (trans = 0; x: n, y: m) or y = A^T x (trans = 1; x: m, y: n) in
+ * FP64 with the same product kernels the LSQR iteration uses.             */
+int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, void* stream);
+
+/* Read internal state back to host memory (tests and diagnostics).
+ * what: 1 sketch Y (s x n row-major doubles), 2 sketch rows (m x xi int32),
+ * 3 sketch signs (m x xi int32, +-1), 4 probes (n x r doubles, column-major),
+ * 5 column indices J (rank int32), 6 row indices I (rank int32),
+ * 7 rho history (outer doubles), 8 rank history (outer int32),
+ * 9 rebuild flags (outer int32), 10 sizes {m, n, s, xi, rank, outer, r} (int64),
+ * 11 last preconditioner singular values sigma (rank doubles),
+ * 12 per-phase iteration counts of column 0 (int32), 13 per-phase eta of column 0 (doubles).
+ * Returns the number of bytes available (copies min(bytes, available)), or
+ * a negative error.                                                        */
+int64_t aplicur_ctx_query(const aplicur_ctx* ctx, int32_t what, void* host_out, size_t bytes);
+
+void aplicur_ctx_destroy(aplicur_ctx* ctx);
+const char* aplicur_last_error(void);
+const char* aplicur_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APLICUR_H */

@@ -1,0 +1,220 @@
+"""Python binding of libaplicur.so (argument marshalling only).
+
+Every step of the solve runs in the HIP library; PyTorch supplies device
+memory and the current stream.  Inputs may be FP32 or FP64 for A; right-hand
+sides and solutions are FP64.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class CSRMatrix:
+    """A CSR matrix on the GPU: row_ptr (m+1, int32), col_idx (nnz, int32), val (nnz)."""
+
+    def __init__(self, row_ptr, col_idx, val, shape):
+        self.row_ptr = row_ptr.to(torch.int32).contiguous()
+        self.col_idx = col_idx.to(torch.int32).contiguous()
+        self.val = val.contiguous()
+        self.shape = tuple(int(s) for s in shape)
+
+    @classmethod
+    def from_scipy(cls, A, device="cuda", dtype=torch.float64):
+        A = A.tocsr()
+        return cls(torch.as_tensor(A.indptr, device=device), torch.as_tensor(A.indices, device=device),
+                   torch.as_tensor(A.data, device=device, dtype=dtype), A.shape)
+
+    @property
+    def dtype(self):
+        return self.val.dtype
+
+
+def _dtype_code(dt):
+    if dt == torch.float64:
+        return L.F64
+    if dt == torch.float32:
+        return L.F32
+    raise TypeError(f"A must be float32 or float64, got {dt}")
+
+
+def _mat(A):
+    if isinstance(A, CSRMatrix):
+        m, n = A.shape
+        if not A.val.is_cuda:
+            raise ValueError("A must live on the GPU")
+        st = L.Mat(L.CSR, _dtype_code(A.val.dtype), m, n, 0, A.val.numel(), A.val.data_ptr(),
+                   A.row_ptr.data_ptr(), A.col_idx.data_ptr())
+        return st, (A.row_ptr, A.col_idx, A.val)
+    if isinstance(A, torch.Tensor) and A.layout == torch.sparse_csr:
+        return _mat(CSRMatrix(A.crow_indices(), A.col_indices(), A.values(), A.shape))
+    if not isinstance(A, torch.Tensor) or A.dim() != 2:
+        raise TypeError("A must be a 2-D torch tensor or a CSRMatrix")
+    if not A.is_cuda:
+        raise ValueError("A must live on the GPU")
+    if A.stride(1) != 1:
+        A = A.contiguous()
+    m, n = A.shape
+    st = L.Mat(L.DENSE, _dtype_code(A.dtype), m, n, A.stride(0), 0, A.data_ptr(), None, None)
+    return st, (A,)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.0, eps_lsqr=1e-10,
+              tol_ne=1e-8, max_iter=100000, max_rank=0, precond=True, precision=0, max_outer=0,
+              r_probes=10):
+    lib = L.load()
+    o = L.Opts()
+    lib.aplicur_opts_default(C.byref(o))
+    o.mu, o.block, o.seed, o.eps_cur = float(mu), int(block), int(seed), float(eps_cur)
+    o.nu_prec, o.nu_lsqr, o.eps_lsqr, o.tol_ne = float(nu_prec), float(nu_lsqr), float(eps_lsqr), float(tol_ne)
+    o.max_iter, o.max_rank, o.precond = int(max_iter), int(max_rank), int(bool(precond))
+    o.precision, o.max_outer, o.r_probes = int(precision), int(max_outer), int(r_probes)
+    return o
+
+
+def _cols(B, rows, name):
+    """FP64 column-major view of B (rows,) or (rows, k): returns (tensor (k, rows), k, was_1d)."""
+    if not isinstance(B, torch.Tensor) or not B.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    one = B.dim() == 1
+    Bm = B.reshape(rows, 1) if one else B
+    if Bm.shape[0] != rows:
+        raise ValueError(f"{name} has {Bm.shape[0]} rows, expected {rows}")
+    return Bm.to(torch.float64).t().contiguous(), Bm.shape[1], one
+
+
+class Context:
+    """Sketch of A (Alg. 3 initialisation) plus the state of later solves."""
+
+    def __init__(self, A, **opts):
+        self.lib = L.load()
+        self.mat, self._keep = _mat(A)
+        self.m, self.n = int(self.mat.m), int(self.mat.n)
+        self.opts = make_opts(**opts)
+        ptr = C.c_void_p()
+        L.check(self.lib.aplicur_sketch(C.byref(self.mat), C.byref(self.opts), _stream(), C.byref(ptr)))
+        self.ptr = ptr
+
+    def solve(self, B, X0=None):
+        Bt, k, one = _cols(B, self.m, "B")
+        if X0 is not None:
+            Xt, _, _ = _cols(X0, self.n, "X0")
+            Xt = Xt.clone()
+        else:
+            Xt = torch.empty((k, self.n), dtype=torch.float64, device=Bt.device)
+        info = L.Info()
+        code = L.check(self.lib.aplicur_solve(self.ptr, Bt.data_ptr(), self.m, k, Xt.data_ptr(), self.n,
+                                              int(X0 is not None), C.byref(info), _stream()))
+        X = Xt.t()
+        return (X.reshape(-1) if one else X), info
+
+    def solve_backward(self, X, B, G, want_dA=True):
+        """Z = (A^T A + mu I)^{-1} G, dB = A Z, dA = (B - A X) Z^T - (A Z) X^T."""
+        Xt, k, one = _cols(X, self.n, "X")
+        Bt, _, _ = _cols(B, self.m, "B")
+        Gt, _, _ = _cols(G, self.n, "G")
+        dev = Xt.device
+        Zt = torch.empty((k, self.n), dtype=torch.float64, device=dev)
+        dBt = torch.empty((k, self.m), dtype=torch.float64, device=dev)
+        dA = None
+        dA_ptr, ldda = None, 0
+        if want_dA:
+            if self.mat.format == L.CSR:
+                dA = torch.empty(int(self.mat.nnz), dtype=torch.float64, device=dev)
+            else:
+                dA = torch.empty((self.m, self.n), dtype=torch.float64, device=dev)
+                ldda = self.n
+            dA_ptr = dA.data_ptr()
+        info = L.Info()
+        L.check(self.lib.aplicur_solve_backward(self.ptr, Xt.data_ptr(), self.n, Bt.data_ptr(), self.m,
+                                                Gt.data_ptr(), self.n, k, Zt.data_ptr(), self.n, dBt.data_ptr(),
+                                                self.m, dA_ptr, ldda, C.byref(info), _stream()))
+        Z, dB = Zt.t(), dBt.t()
+        if one:
+            Z, dB = Z.reshape(-1), dB.reshape(-1)
+        return Z, dB, dA, info
+
+    def matvec(self, x, trans=False):
+        rows_in, rows_out = (self.m, self.n) if trans else (self.n, self.m)
+        x = x.to(torch.float64).contiguous()
+        if x.numel() != rows_in:
+            raise ValueError("x has the wrong length")
+        y = torch.empty(rows_out, dtype=torch.float64, device=x.device)
+        L.check(self.lib.aplicur_matvec(self.ptr, int(bool(trans)), x.data_ptr(), y.data_ptr(), _stream()))
+        return y
+
+    def query(self, what):
+        """Read internal state (see aplicur_ctx_query in include/aplicur.h)."""
+        kinds = {1: np.float64, 2: np.int32, 3: np.int32, 4: np.float64, 5: np.int32, 6: np.int32,
+                 7: np.float64, 8: np.int32, 9: np.int32, 10: np.int64, 11: np.float64, 12: np.int32,
+                 13: np.float64}
+        nbytes = self.lib.aplicur_ctx_query(self.ptr, what, None, 0)
+        L.check(int(nbytes) if nbytes < 0 else 0)
+        buf = (C.c_char * max(int(nbytes), 1))()
+        self.lib.aplicur_ctx_query(self.ptr, what, buf, int(nbytes))
+        return np.frombuffer(bytes(buf)[:int(nbytes)], dtype=kinds[what]).copy()
+
+    def sizes(self):
+        m, n, s, xi, rank, outer, r = self.query(10).tolist()
+        return dict(m=m, n=n, s=s, xi=xi, rank=rank, outer=outer, r=r)
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.lib.aplicur_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def sketch(A, **opts):
+    return Context(A, **opts)
+
+
+def lstsq(A, B, **opts):
+    """min ||A X - B||^2 + mu ||X||^2 by APLICUR (precond=False: plain LSQR)."""
+    with Context(A, **opts) as ctx:
+        return ctx.solve(B)
+
+
+def solve_batched(As, Bs, **opts):
+    lib = L.load()
+    o = make_opts(**opts)
+    mats, keep = [], []
+    for A in As:
+        st, kp = _mat(A)
+        mats.append(st)
+        keep.append(kp)
+    p = len(As)
+    MatArr = L.Mat * p
+    marr = MatArr(*mats)
+    cols = [_cols(B, int(A.shape[0]), "B") for A, B in zip(As, Bs)]
+    k = cols[0][1]
+    if any(c[1] != k for c in cols):
+        raise ValueError("every problem needs the same number of right-hand sides")
+    Xs = [torch.empty((k, int(A.shape[1])), dtype=torch.float64, device=cols[0][0].device) for A in As]
+    bptr = (C.c_void_p * p)(*[c[0].data_ptr() for c in cols])
+    xptr = (C.c_void_p * p)(*[x.data_ptr() for x in Xs])
+    ldb = (C.c_int64 * p)(*[int(A.shape[0]) for A in As])
+    ldx = (C.c_int64 * p)(*[int(A.shape[1]) for A in As])
+    infos = (L.Info * p)()
+    L.check(lib.aplicur_solve_batched(p, marr, bptr, ldb, k, xptr, ldx, C.byref(o), infos, _stream()))
+    outs = [x.t() for x in Xs]
+    if cols[0][2]:
+        outs = [x.reshape(-1) for x in outs]
+    return outs, list(infos)

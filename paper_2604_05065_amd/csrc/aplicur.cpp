@@ -1,0 +1,963 @@
+// Host driver of the APLICUR library: the adaptive procedure of Alg. 3 on
+// the GPU, and the extern "C" entry points declared in include/aplicur.h.
+//
+// Per outer step (Alg. 3 Part 1-3):
+//   augmentCUR (Alg. 7): zero E_row(:,J); LUPP pivots of E_row^T -> J+;
+//     E_col = A(:,J+) - C (U R(:,J+)); zero E_col(I,:); LUPP pivots -> I+;
+//   U = A(I,J)^{-1} kept explicitly and extended by the block-inverse formula
+//     with the Schur complement S = E_col(I+, :) (the LU pivot block);
+//   E_row = Y - (Y(:,J) U) R;  rho = 10 sqrt(2/pi) max_i ||E_row w_i||;
+//   augmentQR (Alg. 9) of R^T (CGS2 + Cholesky QR of the remainder);
+//   T_C = chol(C^T C) extended by the same block recurrence;
+//   if re-preconditioning: M = T_C U T_R^T, one-sided Jacobi SVD of M,
+//     V = Q_R V_M, P^{-1} z = z + V ((sigma^/Lam - 1) .* V^T z), then an LSQR
+//     phase per right-hand side warm-started from x.
+// Plain GEMM/TRSM steps use rocBLAS; everything else is in the HIP kernels.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "../../include/aplicur.h"
+#include "factor.h"
+
+namespace aplicur {
+
+static thread_local std::string g_last_error;
+
+#define APL_BLAS(x)                                                                        \
+  do {                                                                                     \
+    rocblas_status s_ = (x);                                                               \
+    if (s_ != rocblas_status_success)                                                      \
+      throw ::aplicur::Error(-3, std::string(#x) + ": rocblas status " + std::to_string((int)s_)); \
+  } while (0)
+
+using Clock = std::chrono::steady_clock;
+static double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// Device arena: every allocation of a context, released together.
+struct Arena {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(APLICUR_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+struct Ctx {
+  aplicur_mat A{};
+  aplicur_opts o{};
+  OpDesc op{};
+  rocblas_handle blas = nullptr;
+  Arena arena;
+  long long m = 0, n = 0;
+  int s = 0, xi = 0, r = 0, L = 0, Lpad = 0, bmax = 0;
+  double delta = 0.0, eps_cur = 0.0;
+  // sketch / probes
+  uint16_t* S_rows = nullptr;
+  uint8_t* S_neg = nullptr;
+  double *Y = nullptr, *E = nullptr, *W = nullptr, *EW = nullptr, *rho_dev = nullptr;
+  // CUR state
+  int *I_dev = nullptr, *J_dev = nullptr, *Ip = nullptr, *Jp = nullptr;
+  std::vector<int> I, J;
+  double *C = nullptr, *Rt = nullptr, *U = nullptr, *Q = nullptr, *TR = nullptr, *TC = nullptr;
+  double *Ecol = nullptr, *RJ = nullptr, *F = nullptr, *Gm = nullptr, *H = nullptr, *Sb = nullptr,
+         *Sinv = nullptr, *B21 = nullptr, *YJ = nullptr, *Z = nullptr, *P2 = nullptr, *small = nullptr;
+  int* status_dev = nullptr;
+  int rank = 0;
+  // preconditioner
+  double *Mx = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
+         *pa_part = nullptr, *pa_c = nullptr;
+  unsigned long long* offmax = nullptr;
+  PrecDesc prec{};
+  bool have_prec = false;
+  double p_target = 0.0, p_pnorm = 1.0, p_sigma_l = 0.0;
+  std::vector<double> p_sigma_host;
+  // LSQR vectors and state
+  double *u_top = nullptr, *u_bot = nullptr, *v = nullptr, *w = nullptr, *y = nullptr, *t = nullptr,
+         *g = nullptr, *partials = nullptr;
+  GKState* st = nullptr;
+  GKState* st_host = nullptr;  // pinned
+  GKState* st_mv = nullptr;    // pristine state of the matvec entry point
+  unsigned* counter = nullptr;
+  FactorWork fw{};
+  // histories
+  std::vector<double> rho_hist;
+  std::vector<int> rank_hist, rebuild_hist;
+  std::vector<int> phase_iters0;
+  std::vector<double> phase_eta0;
+  double t_sketch = 0.0;
+
+  ~Ctx() {
+    if (blas) rocblas_destroy_handle(blas);
+    if (st_host) (void)hipHostFree(st_host);
+    arena.release();
+  }
+};
+
+static int group_for(double avg) {
+  int g = 1;
+  while (g < avg && g < 64) g <<= 1;
+  return g;
+}
+
+static void set_stream(Ctx& c, hipStream_t s) { APL_BLAS(rocblas_set_stream(c.blas, s)); }
+
+static void gemm(Ctx& c, rocblas_operation ta, rocblas_operation tb, long long m, long long n, long long k,
+                 double alpha, const double* A, long long lda, const double* B, long long ldb, double beta,
+                 double* Cm, long long ldc) {
+  if (m <= 0 || n <= 0) return;
+  APL_BLAS(rocblas_dgemm(c.blas, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)k, &alpha, A,
+                         (rocblas_int)lda, B, (rocblas_int)ldb, &beta, Cm, (rocblas_int)ldc));
+}
+
+static int read_int(const int* dev, hipStream_t s) {
+  int h = 0;
+  APL_HIP(hipMemcpyAsync(&h, dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  APL_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+// ------------------------------------------------------------------ set-up
+static void validate(const aplicur_mat* A, const aplicur_opts* o) {
+  APL_REQUIRE(A && o, "null matrix or options");
+  APL_REQUIRE(A->m >= 1 && A->n >= 1, "m and n must be >= 1");
+  APL_REQUIRE(A->m < (1LL << 31) && A->n < (1LL << 31), "m and n must be < 2^31");
+  APL_REQUIRE(A->dtype == APLICUR_F64 || A->dtype == APLICUR_F32, "dtype must be F64 or F32");
+  APL_REQUIRE(A->val != nullptr, "A.val is null");
+  if (A->format == APLICUR_CSR) {
+    APL_REQUIRE(A->row_ptr && A->col_idx, "CSR needs row_ptr and col_idx");
+    APL_REQUIRE(A->nnz >= 0 && A->nnz < (1LL << 31), "nnz out of range");
+  } else {
+    APL_REQUIRE(A->format == APLICUR_DENSE, "format must be DENSE or CSR");
+    APL_REQUIRE(A->ld >= A->n, "dense ld must be >= n");
+  }
+  APL_REQUIRE(o->mu >= 0.0 && std::isfinite(o->mu), "mu must be finite and >= 0");
+  APL_REQUIRE(o->mu > 0.0 || A->m >= A->n, "mu = 0 needs m >= n");
+  APL_REQUIRE(o->precision == 0, "only precision 0 (FP64) is available");
+  if (o->precond) {
+    APL_REQUIRE(o->block >= 1 && o->block <= 280, "block must be in [1, 280]");
+    APL_REQUIRE(o->r_probes >= 1 && o->r_probes <= 64, "r_probes must be in [1, 64]");
+  }
+  APL_REQUIRE(o->max_iter >= 0, "max_iter must be >= 0");
+}
+
+static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) {
+  validate(Am, o);
+  auto t0 = Clock::now();
+  Ctx* c = new Ctx();
+  try {
+    c->A = *Am;
+    c->o = *o;
+    c->m = Am->m;
+    c->n = Am->n;
+    c->delta = std::sqrt(o->mu);
+    c->eps_cur = o->eps_cur > 0 ? o->eps_cur : (o->mu > 0 ? 30.0 * std::sqrt(o->mu) : 3e-7);
+    APL_BLAS(rocblas_create_handle(&c->blas));
+    APL_BLAS(rocblas_set_pointer_mode(c->blas, rocblas_pointer_mode_host));
+    set_stream(*c, s);
+    const long long m = c->m, n = c->n;
+    OpDesc& op = c->op;
+    op.csr = (Am->format == APLICUR_CSR);
+    op.f64 = (Am->dtype == APLICUR_F64);
+    op.m = m;
+    op.n = n;
+    op.ld = op.csr ? 0 : Am->ld;
+    op.val = Am->val;
+    const size_t vs = op.f64 ? 8 : 4;
+    if (op.csr) {
+      op.row_ptr = Am->row_ptr;
+      op.col_idx = Am->col_idx;
+      {
+        int* bad = c->arena.alloc<int>(1);
+        const int code = check_csr(Am->row_ptr, Am->col_idx, m, n, Am->nnz, bad, s);
+        APL_REQUIRE(code == 0, code & 1 ? "CSR row_ptr is malformed" : "CSR col_idx out of range");
+      }
+      int* tp = c->arena.alloc<int>(n + 1);
+      int* ti = c->arena.alloc<int>(Am->nnz);
+      void* tv = c->arena.alloc<char>(vs * (size_t)Am->nnz);
+      int* scratch = c->arena.alloc<int>(n);
+      if (op.f64)
+        launch_csr_transpose<double>(Am->row_ptr, Am->col_idx, (const double*)Am->val, m, n, Am->nnz, tp, ti,
+                                     (double*)tv, scratch, s);
+      else
+        launch_csr_transpose<float>(Am->row_ptr, Am->col_idx, (const float*)Am->val, m, n, Am->nnz, tp, ti,
+                                    (float*)tv, scratch, s);
+      op.t_ptr = tp;
+      op.t_idx = ti;
+      op.t_val = tv;
+      op.group = group_for((double)Am->nnz / (double)m);
+      op.t_group = group_for((double)Am->nnz / (double)n);
+    } else {
+      long long chunks = (2048 + (n + 255) / 256 - 1) / ((n + 255) / 256);
+      chunks = std::min<long long>(chunks, std::max<long long>(1, m / 32));
+      chunks = std::max<long long>(1, std::min<long long>(chunks, 1024));
+      op.chunks = (int)chunks;
+      op.part = c->arena.alloc<double>((size_t)chunks * n);
+    }
+    // LSQR vectors and state
+    c->u_top = c->arena.alloc<double>(m);
+    c->u_bot = c->arena.alloc<double>(n);
+    c->v = c->arena.alloc<double>(n);
+    c->w = c->arena.alloc<double>(n);
+    c->y = c->arena.alloc<double>(n);
+    c->t = c->arena.alloc<double>(n);
+    c->g = c->arena.alloc<double>(std::max(m, n));
+    c->partials = c->arena.alloc<double>(8192);
+    c->st = c->arena.alloc<GKState>(1);
+    c->counter = c->arena.alloc<unsigned>(4);
+    c->st_mv = c->arena.alloc<GKState>(1);
+    APL_HIP(hipMemsetAsync(c->counter, 0, 4 * sizeof(unsigned), s));
+    APL_HIP(hipHostMalloc((void**)&c->st_host, sizeof(GKState), hipHostMallocDefault));
+    {
+      GKState& h = *c->st_host;
+      std::memset(&h, 0, sizeof(h));
+      h.alpha = h.beta = h.pnorm = 1.0;
+      h.nu = INFINITY;
+      APL_HIP(hipMemcpyAsync(c->st_mv, &h, sizeof(GKState), hipMemcpyHostToDevice, s));
+      APL_HIP(hipStreamSynchronize(s));
+    }
+    if (o->precond) {
+      // sketch dimensions (Alg. 3: s = ceil(1.1 b), xi = min(8, s))
+      int s_rows = (int)std::ceil(1.1 * o->block - 1e-12);
+      s_rows = (int)std::max<long long>(1, std::min<long long>(s_rows, m));
+      c->s = s_rows;
+      c->xi = std::min(8, s_rows);
+      c->r = o->r_probes;
+      long long Lmax = std::min<long long>(std::min(m, n), 4096);
+      if (o->max_rank > 0) Lmax = std::min<long long>(std::min(m, n), o->max_rank);
+      c->L = (int)Lmax;
+      const int jw2 = 2 * jacobi_block_width();
+      c->Lpad = ((c->L + jw2 - 1) / jw2) * jw2;
+      c->bmax = std::min(o->block, c->s);
+      const int L = c->L, Lp = c->Lpad, b = c->bmax, S = c->s, r = c->r;
+      c->S_rows = c->arena.alloc<uint16_t>((size_t)m * c->xi);
+      c->S_neg = c->arena.alloc<uint8_t>(m);
+      c->Y = c->arena.alloc<double>((size_t)S * n);
+      c->E = c->arena.alloc<double>((size_t)S * n);
+      c->W = c->arena.alloc<double>((size_t)n * r);
+      c->EW = c->arena.alloc<double>((size_t)S * r);
+      c->rho_dev = c->arena.alloc<double>(4);
+      launch_gen_sketch(o->seed, S, m, c->xi, c->S_rows, c->S_neg, s);
+      launch_gen_probes(o->seed, n, r, c->W, s);
+      if (op.csr) {
+        if (op.f64)
+          launch_sketch_csr<double>(op.t_ptr, op.t_idx, (const double*)op.t_val, n, S, c->xi, c->S_rows,
+                                    c->S_neg, c->Y, s);
+        else
+          launch_sketch_csr<float>(op.t_ptr, op.t_idx, (const float*)op.t_val, n, S, c->xi, c->S_rows,
+                                   c->S_neg, c->Y, s);
+      } else {
+        const int chunks = sketch_dense_chunks(m, n);
+        double* part = nullptr;
+        APL_HIP(hipMalloc((void**)&part, sizeof(double) * (size_t)chunks * S * n));
+        if (op.f64)
+          launch_sketch_dense<double>((const double*)op.val, m, n, op.ld, S, c->xi, c->S_rows, c->S_neg, c->Y,
+                                      part, chunks, s);
+        else
+          launch_sketch_dense<float>((const float*)op.val, m, n, op.ld, S, c->xi, c->S_rows, c->S_neg, c->Y,
+                                     part, chunks, s);
+        APL_HIP(hipStreamSynchronize(s));
+        APL_HIP(hipFree(part));
+      }
+      // CUR / preconditioner storage (sized by the rank cap L)
+      c->I_dev = c->arena.alloc<int>(L);
+      c->J_dev = c->arena.alloc<int>(L);
+      c->Ip = c->arena.alloc<int>(b);
+      c->Jp = c->arena.alloc<int>(S);
+      c->C = c->arena.alloc<double>((size_t)m * L);
+      c->Rt = c->arena.alloc<double>((size_t)n * L);
+      c->U = c->arena.alloc<double>((size_t)L * L);
+      c->Q = c->arena.alloc<double>((size_t)n * L);
+      c->TR = c->arena.alloc<double>((size_t)L * L);
+      c->TC = c->arena.alloc<double>((size_t)L * L);
+      c->Ecol = c->arena.alloc<double>((size_t)m * b);
+      c->RJ = c->arena.alloc<double>((size_t)S * L);
+      c->F = c->arena.alloc<double>((size_t)L * S);
+      c->Gm = c->arena.alloc<double>((size_t)b * L);
+      c->H = c->arena.alloc<double>((size_t)b * L);
+      c->B21 = c->arena.alloc<double>((size_t)b * L);
+      c->Sb = c->arena.alloc<double>((size_t)b * b);
+      c->Sinv = c->arena.alloc<double>((size_t)b * b);
+      c->small = c->arena.alloc<double>((size_t)4 * b * b);
+      c->YJ = c->arena.alloc<double>((size_t)S * L);
+      c->Z = c->arena.alloc<double>((size_t)S * L);
+      c->P2 = c->arena.alloc<double>((size_t)L * b);
+      c->status_dev = c->arena.alloc<int>(4);
+      c->Mx = c->arena.alloc<double>((size_t)L * Lp);
+      c->Vm = c->arena.alloc<double>((size_t)Lp * Lp);
+      c->sigma = c->arena.alloc<double>(Lp);
+      c->Vhat = c->arena.alloc<double>((size_t)L * n);
+      c->d = c->arena.alloc<double>(L);
+      c->pinfo = c->arena.alloc<double>(4);
+      c->offmax = c->arena.alloc<unsigned long long>(1);
+      const int pchunks = (int)std::max<long long>(1, std::min<long long>(256, n / 64));
+      c->pa_part = c->arena.alloc<double>((size_t)pchunks * L);
+      c->pa_c = c->arena.alloc<double>(L);
+      c->prec.chunks = pchunks;
+      c->prec.part = c->pa_part;
+      c->prec.c = c->pa_c;
+      long long lrows = std::max(m, n);
+      c->fw.lupp_rows = (int)lrows;
+      c->fw.pos = c->arena.alloc<int>(lrows);
+      c->fw.row_at = c->arena.alloc<int>(lrows);
+      c->fw.pv = c->arena.alloc<double>(1024);
+      c->fw.pp = c->arena.alloc<int>(1024);
+      c->fw.pi = c->arena.alloc<int>(1024);
+      c->fw.lupp_state = c->arena.alloc<int>(4);
+      c->fw.counter = c->counter + 1;
+      fill(c->TR, (long long)L * L, 0.0, s);
+      fill(c->TC, (long long)L * L, 0.0, s);
+      fill(c->U, (long long)L * L, 0.0, s);
+    }
+    APL_HIP(hipStreamSynchronize(s));
+    c->t_sketch = ms_since(t0);
+    return c;
+  } catch (...) {
+    delete c;
+    throw;
+  }
+}
+
+// ------------------------------------------------------------------ Cholesky QR
+// X (n x k, column-major ld) <- Q, R (k x k upper, ldr) with X_in = Q R, by
+// Cholesky QR applied twice (a shift is added to the first Gram matrix if
+// its Cholesky factorisation fails: shifted CholeskyQR, Fukaya et al.).
+static void chol_qr2(Ctx& c, double* X, long long n, int k, long long ldx, double* R, long long ldr, hipStream_t s) {
+  double* G = c.small;                             // k x k
+  double* R1 = c.small + (size_t)c.bmax * c.bmax;  // k x k
+  double* Racc = c.small + 2 * (size_t)c.bmax * c.bmax;
+  const double one = 1.0;
+  int passes = 2;
+  for (int pass = 0; pass < passes; ++pass) {
+    gemm(c, rocblas_operation_transpose, rocblas_operation_none, k, k, n, 1.0, X, ldx, X, ldx, 0.0, G, k);
+    small_potrf(G, k, k, c.status_dev, s);
+    if (read_int(c.status_dev, s) != 0) {
+      APL_REQUIRE(pass == 0, "Cholesky QR failed (block numerically rank deficient)");
+      // shifted Cholesky QR: G + shift I, then one extra unshifted pass
+      gemm(c, rocblas_operation_transpose, rocblas_operation_none, k, k, n, 1.0, X, ldx, X, ldx, 0.0, G, k);
+      std::vector<double> hg((size_t)k * k);
+      APL_HIP(hipMemcpyAsync(hg.data(), G, sizeof(double) * k * k, hipMemcpyDeviceToHost, s));
+      APL_HIP(hipStreamSynchronize(s));
+      double dmax = 0.0;
+      for (int i = 0; i < k; ++i) dmax = std::max(dmax, hg[(size_t)i * k + i]);
+      const double shift = 11.0 * 2.2e-16 * (double)(n * k + (long long)k * (k + 1)) * std::max(dmax, 1e-300);
+      for (int i = 0; i < k; ++i) hg[(size_t)i * k + i] += shift;
+      APL_HIP(hipMemcpyAsync(G, hg.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, s));
+      small_potrf(G, k, k, c.status_dev, s);
+      APL_REQUIRE(read_int(c.status_dev, s) == 0, "shifted Cholesky QR failed");
+      passes = 3;
+    }
+    APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                           rocblas_diagonal_non_unit, (rocblas_int)n, k, &one, G, k, X, (rocblas_int)ldx));
+    if (pass == 0) {
+      copy_block(G, k, Racc, k, k, k, 1.0, s);
+    } else {
+      gemm(c, rocblas_operation_none, rocblas_operation_none, k, k, k, 1.0, G, k, Racc, k, 0.0, R1, k);
+      copy_block(R1, k, Racc, k, k, k, 1.0, s);
+    }
+  }
+  copy_block(Racc, k, R, ldr, k, k, 1.0, s);
+}
+
+// ------------------------------------------------------------------ one outer step
+struct StepResult {
+  double rho;
+  bool exhausted;
+  int added;
+};
+
+static StepResult outer_step(Ctx& c, hipStream_t s) {
+  const long long m = c.m, n = c.n;
+  const int S = c.s, L = c.L, l = c.rank;
+  StepResult res{0.0, false, 0};
+  int beff = std::min<long long>(std::min<long long>(c.bmax, n - l), std::min<long long>(m - l, L - l));
+  if (beff <= 0) {
+    res.exhausted = true;
+    res.rho = c.rho_hist.empty() ? 0.0 : c.rho_hist.back();
+    return res;
+  }
+  // (i)-(ii) column pivots from the sketched residual (E_row^T = E as n x s column-major)
+  if (l > 0) zero_rows(c.E, n, c.J_dev, l, S, s);
+  lupp_pivots(c.E, (int)n, S, n, beff, c.Jp, c.fw, s);
+  const int k1 = lupp_read_keff(c.fw, s);
+  if (k1 == 0) {
+    res.exhausted = true;
+    res.rho = c.rho_hist.empty() ? 0.0 : c.rho_hist.back();
+    return res;
+  }
+  // (iii) new columns of C and the column residual E_col = A(:,J+) - C U R(:,J+)
+  double* Cn = c.C + (size_t)l * m;
+  gather_cols(c.op, c.Jp, k1, Cn, m, s);
+  copy_block(Cn, m, c.Ecol, m, (int)m, k1, 1.0, s);
+  if (l > 0) {
+    gather_sub_rows(c.Rt, n, c.Jp, k1, l, c.RJ, k1, s);  // RJ = R(:,J+)^T, k1 x l
+    gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, k1, l, 1.0, c.U, L, c.RJ, k1, 0.0, c.F, L);
+    gemm(c, rocblas_operation_none, rocblas_operation_none, m, k1, l, -1.0, c.C, m, c.F, L, 1.0, c.Ecol, m);
+    zero_rows(c.Ecol, m, c.I_dev, l, k1, s);
+  }
+  // (iv) row pivots of E_col
+  lupp_pivots(c.Ecol, (int)m, k1, m, k1, c.Ip, c.fw, s);
+  const int k2 = lupp_read_keff(c.fw, s);
+  if (k2 < beff) res.exhausted = true;
+  if (k2 == 0) {
+    res.rho = c.rho_hist.empty() ? 0.0 : c.rho_hist.back();
+    return res;
+  }
+  std::vector<int> hJ(k2), hI(k2);
+  APL_HIP(hipMemcpyAsync(hJ.data(), c.Jp, sizeof(int) * k2, hipMemcpyDeviceToHost, s));
+  APL_HIP(hipMemcpyAsync(hI.data(), c.Ip, sizeof(int) * k2, hipMemcpyDeviceToHost, s));
+  APL_HIP(hipMemcpyAsync(c.J_dev + l, c.Jp, sizeof(int) * k2, hipMemcpyDeviceToDevice, s));
+  APL_HIP(hipMemcpyAsync(c.I_dev + l, c.Ip, sizeof(int) * k2, hipMemcpyDeviceToDevice, s));
+  APL_HIP(hipStreamSynchronize(s));
+  c.J.insert(c.J.end(), hJ.begin(), hJ.end());
+  c.I.insert(c.I.end(), hI.begin(), hI.end());
+  // new rows of R (as columns of Rt)
+  double* Rn = c.Rt + (size_t)l * n;
+  gather_rows(c.op, c.Ip, k2, Rn, n, s);
+  // (v) U = A(I,J)^{-1} by the block-inverse update; Schur complement
+  //     S = A(I+,J+) - A(I+,J) U A(I,J+)
+  gather_sub_rows(Cn, m, c.Ip, k2, k2, c.Sb, k2, s);  // A(I+, J+)
+  if (l > 0) {
+    gather_sub_rows(c.C, m, c.Ip, k2, l, c.B21, k2, s);  // A(I+, J_old), k2 x l
+    gemm(c, rocblas_operation_none, rocblas_operation_none, k2, l, l, 1.0, c.B21, k2, c.U, L, 0.0, c.Gm, k2);
+    // S -= G B12, B12 = RJ(0:k2, :)^T
+    gemm(c, rocblas_operation_none, rocblas_operation_transpose, k2, k2, l, -1.0, c.Gm, k2, c.RJ, k1, 1.0, c.Sb, k2);
+  }
+  small_inverse(c.Sb, k2, k2, c.Sinv, k2, c.status_dev, s);
+  if (read_int(c.status_dev, s) != 0) throw Error(APLICUR_E_BREAKDOWN, "singular CUR core block");
+  if (l == 0) {
+    copy_block(c.Sinv, k2, c.U, L, k2, k2, 1.0, s);
+  } else {
+    gemm(c, rocblas_operation_none, rocblas_operation_none, k2, l, k2, 1.0, c.Sinv, k2, c.Gm, k2, 0.0, c.H, k2);
+    gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, k2, 1.0, c.F, L, c.H, k2, 1.0, c.U, L);
+    gemm(c, rocblas_operation_none, rocblas_operation_none, l, k2, k2, -1.0, c.F, L, c.Sinv, k2, 0.0,
+         c.U + (size_t)l * L, L);
+    copy_block(c.H, k2, c.U + l, L, k2, l, -1.0, s);
+    copy_block(c.Sinv, k2, c.U + l + (size_t)l * L, L, k2, k2, 1.0, s);
+  }
+  const int ln = l + k2;
+  // (vi) E_row = Y - (Y(:,J) U) R   (E as n x s column-major = E_row^T)
+  gather_y_cols(c.Y, n, S, c.J_dev, ln, c.YJ, S, s);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, S, ln, ln, 1.0, c.YJ, S, c.U, L, 0.0, c.Z, S);
+  APL_HIP(hipMemcpyAsync(c.E, c.Y, sizeof(double) * (size_t)S * n, hipMemcpyDeviceToDevice, s));
+  gemm(c, rocblas_operation_none, rocblas_operation_transpose, n, S, ln, -1.0, c.Rt, n, c.Z, S, 1.0, c.E, n);
+  // (vii) rho = 10 sqrt(2/pi) max_i ||E_row w_i||
+  gemm(c, rocblas_operation_transpose, rocblas_operation_none, S, c.r, n, 1.0, c.E, n, c.W, n, 0.0, c.EW, S);
+  rho_from_ew(c.EW, S, c.r, c.rho_dev, s);
+  // (viii) augmentQR (Alg. 9) with the new columns A(I+,:)^T
+  double* Qn = c.Q + (size_t)l * n;
+  copy_block(Rn, n, Qn, n, (int)n, k2, 1.0, s);
+  if (l > 0) {
+    double* P1 = c.TR + (size_t)l * L;  // T_R(0:l, l:ln)
+    gemm(c, rocblas_operation_transpose, rocblas_operation_none, l, k2, n, 1.0, c.Q, n, Rn, n, 0.0, P1, L);
+    gemm(c, rocblas_operation_none, rocblas_operation_none, n, k2, l, -1.0, c.Q, n, P1, L, 1.0, Qn, n);
+    gemm(c, rocblas_operation_transpose, rocblas_operation_none, l, k2, n, 1.0, c.Q, n, Qn, n, 0.0, c.P2, l);
+    gemm(c, rocblas_operation_none, rocblas_operation_none, n, k2, l, -1.0, c.Q, n, c.P2, l, 1.0, Qn, n);
+    // P1 += P2
+    add_block(c.P2, l, P1, L, l, k2, s);
+  }
+  chol_qr2(c, Qn, n, k2, n, c.TR + l + (size_t)l * L, L, s);
+  // (ix) T_C = chol(C^T C), extended: T12 = T_C^{-T} C_old^T C_new, T22 = chol(C_new^T C_new - T12^T T12)
+  {
+    double* T12 = c.TC + (size_t)l * L;
+    double* T22 = c.TC + l + (size_t)l * L;
+    if (l > 0) {
+      gemm(c, rocblas_operation_transpose, rocblas_operation_none, l, k2, m, 1.0, c.C, m, Cn, m, 0.0, T12, L);
+      const double one = 1.0;
+      APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                             rocblas_diagonal_non_unit, l, k2, &one, c.TC, L, T12, L));
+    }
+    double* G22 = c.small;
+    gemm(c, rocblas_operation_transpose, rocblas_operation_none, k2, k2, m, 1.0, Cn, m, Cn, m, 0.0, G22, k2);
+    if (l > 0)
+      gemm(c, rocblas_operation_transpose, rocblas_operation_none, k2, k2, l, -1.0, T12, L, T12, L, 1.0, G22, k2);
+    small_potrf(G22, k2, k2, c.status_dev, s);
+    if (read_int(c.status_dev, s) != 0) throw Error(APLICUR_E_BREAKDOWN, "Cholesky of C^T C failed");
+    copy_block(G22, k2, T22, L, k2, k2, 1.0, s);
+  }
+  double rho = 0.0;
+  APL_HIP(hipGetLastError());
+  APL_HIP(hipMemcpyAsync(&rho, c.rho_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  APL_HIP(hipStreamSynchronize(s));
+  c.rank = ln;
+  res.rho = rho;
+  res.added = k2;
+  return res;
+}
+
+// ------------------------------------------------------------------ preconditioner (Alg. 2 Part 2)
+static void build_precond(Ctx& c, hipStream_t s) {
+  const int l = c.rank, L = c.L;
+  const int jw2 = 2 * jacobi_block_width();
+  const int lp = ((l + jw2 - 1) / jw2) * jw2;
+  // M = T_C U T_R^T  (l x l) into Mx (ld L, lp columns, padding zero)
+  fill(c.Mx, (long long)L * lp, 0.0, s);
+  gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Vhat, l);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, l, 1.0, c.TC, L, c.Vhat, l, 0.0, c.Mx, L);
+  set_identity(c.Vm, lp, lp, s);
+  jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.offmax, 1e-14, 40, s);
+  // V = Q_R V_M stored row-major n x l  (= column-major l x n: V^T = V_M^T Q_R^T)
+  gemm(c, rocblas_operation_transpose, rocblas_operation_transpose, l, c.n, l, 1.0, c.Vm, lp, c.Q, c.n, 0.0,
+       c.Vhat, l);
+  precond_scalars(c.sigma, l, c.delta, c.d, c.pinfo, s);
+  double info[4];
+  APL_HIP(hipMemcpyAsync(info, c.pinfo, sizeof(info), hipMemcpyDeviceToHost, s));
+  c.p_sigma_host.resize(l);
+  APL_HIP(hipMemcpyAsync(c.p_sigma_host.data(), c.sigma, sizeof(double) * l, hipMemcpyDeviceToHost, s));
+  APL_HIP(hipStreamSynchronize(s));
+  c.p_sigma_l = info[0];
+  c.p_target = info[2];
+  c.p_pnorm = info[3];
+  c.prec.ell = l;
+  c.prec.ldv = l;
+  c.prec.V = c.Vhat;
+  c.prec.d = c.d;
+  c.have_prec = true;
+}
+
+// ------------------------------------------------------------------ LSQR phases
+struct PhaseOut {
+  int iters;
+  int reason;
+};
+
+static GKVecs<double> vecs(Ctx& c) { return GKVecs<double>{c.u_top, c.u_bot, c.v, c.w, c.y, c.t, c.g}; }
+
+static void upload_state(Ctx& c, double tol_abs, double pnorm, double eps_lsqr, double baug_eps, double nu,
+                         double sigma_l, int max_iter, double delta, hipStream_t s) {
+  GKState& h = *c.st_host;
+  std::memset(&h, 0, sizeof(h));
+  h.alpha = 1.0;
+  h.beta = 1.0;
+  h.pnorm = pnorm;
+  h.tol_abs = tol_abs;
+  h.eps_lsqr = eps_lsqr;
+  h.baug_eps = baug_eps;
+  h.nu = nu;
+  h.sigma_l = sigma_l;
+  h.delta = delta;
+  h.max_iter = max_iter;
+  h.init = 1;
+  APL_HIP(hipMemcpyAsync(c.st, &h, sizeof(GKState), hipMemcpyHostToDevice, s));
+}
+
+static GKState read_state(Ctx& c, hipStream_t s) {
+  APL_HIP(hipMemcpyAsync(c.st_host, c.st, sizeof(GKState), hipMemcpyDeviceToHost, s));
+  APL_HIP(hipStreamSynchronize(s));
+  return *c.st_host;
+}
+
+// One warm-started phase for the problem min || A_mu x - [b; bot_scale b_bot] ||.
+static PhaseOut run_phase(Ctx& c, const PrecDesc* P, const double* b, const double* b_bot, double bot_scale,
+                          double* x, bool x_zero, double tol_abs, double pnorm, double eps_lsqr, double baug_eps,
+                          double nu, double sigma_l, int budget, hipStream_t s) {
+  upload_state(c, tol_abs, pnorm, eps_lsqr, baug_eps, nu, sigma_l, budget, c.delta, s);
+  GKVecs<double> vec = vecs(c);
+  gk_phase_init<double>(c.op, P, b, b_bot, bot_scale, x_zero ? nullptr : x, vec, c.u_top, c.u_bot, c.st,
+                        c.partials, c.counter, s);
+  int chunk = 8;
+  long long launched = 0;
+  APL_HIP(hipGetLastError());
+  GKState h = read_state(c, s);
+  while (!h.stop) {
+    for (int i = 0; i < chunk; ++i) gk_iteration<double>(c.op, P, vec, c.st, c.partials, c.counter, s);
+    launched += chunk;
+    APL_HIP(hipGetLastError());
+    h = read_state(c, s);
+    chunk = std::min(chunk * 2, 64);
+    if (!h.stop && launched > (long long)budget + 128)
+      throw Error(APLICUR_E_HIP, "LSQR phase did not reach its stopping test within its budget");
+  }
+  if (h.reason == 6) throw Error(APLICUR_E_BREAKDOWN, "non-finite value in the LSQR recurrence");
+  gk_phase_finish<double>(c.op, P, vec, x, c.st, s);
+  return PhaseOut{h.iter, h.reason};
+}
+
+// eta = ||A_mu^T r|| / atb with r the residual of x, FP64 from scratch.
+static double eta_of(Ctx& c, const double* b, const double* b_bot, double bot_scale, const double* x, double atb,
+                     hipStream_t s) {
+  if (atb == 0.0) return 0.0;
+  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 0, c.delta, s);
+  gk_phase_init<double>(c.op, nullptr, b, b_bot, bot_scale, x, vecs(c), c.u_top, c.u_bot, c.st, c.partials,
+                        c.counter, s);
+  GKState h = read_state(c, s);
+  return std::sqrt(std::max(h.h2, 0.0)) / atb;
+}
+
+static double atb_norm(Ctx& c, const double* b, hipStream_t s) {
+  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 0, 0.0, s);
+  op_atb_norm2(c.op, b, c.g, c.st, c.partials, c.counter, s);
+  GKState h = read_state(c, s);
+  return std::sqrt(std::max(h.h2, 0.0));
+}
+
+static double vec_norm(Ctx& c, const double* b, hipStream_t s) {
+  // ||b|| through the residual kernel with x = 0 (delta = 0 so r = [b; 0])
+  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 0, 0.0, s);
+  gk_phase_init<double>(c.op, nullptr, b, nullptr, 0.0, nullptr, vecs(c), c.u_top, c.u_bot, c.st, c.partials,
+                        c.counter, s);
+  GKState h = read_state(c, s);
+  return h.beta1 > 0 ? h.beta1 : h.beta;
+}
+
+struct ColState {
+  double atb = 0.0, bnorm = 0.0, eta = INFINITY;
+  int used = 0, phases = 0;
+  bool done = false;
+};
+
+// Solve one column with P fixed (plain LSQR when P is null): restarted phases
+// with nu = inf until eta <= tol or the budget/stall guard ends it.
+static void refine(Ctx& c, const PrecDesc* P, const double* b, double* x, ColState& cs, double pnorm,
+                   double sigma_l, bool first_from_zero, std::vector<int>* it_log, std::vector<double>* eta_log,
+                   hipStream_t s) {
+  int stalls = 0;
+  bool xz = first_from_zero;
+  while (cs.eta > c.o.tol_ne && cs.used < c.o.max_iter && stalls < 3) {
+    const double prev = cs.eta;
+    PhaseOut po = run_phase(c, P, b, nullptr, 0.0, x, xz, c.o.tol_ne * cs.atb, pnorm, 0.0, 0.0, INFINITY, sigma_l,
+                            c.o.max_iter - cs.used, s);
+    xz = false;
+    cs.used += po.iters;
+    cs.phases += 1;
+    cs.eta = eta_of(c, b, nullptr, 0.0, x, cs.atb, s);
+    if (it_log) it_log->push_back(po.iters);
+    if (eta_log) eta_log->push_back(cs.eta);
+    if (po.iters == 0 || po.reason == kStopBudget) break;
+    stalls = (cs.eta > 0.5 * prev) ? stalls + 1 : 0;
+  }
+}
+
+static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, long long ldx, bool warm,
+                 aplicur_info* info, hipStream_t s) {
+  APL_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+  APL_REQUIRE(B && X, "null B or X");
+  APL_REQUIRE(ldb >= c.m && ldx >= c.n, "ldb must be >= m and ldx >= n");
+  set_stream(c, s);
+  auto t_start = Clock::now();
+  double t_cur = 0.0, t_prec = 0.0, t_lsqr = 0.0;
+  std::vector<ColState> cols(nrhs);
+  for (int k = 0; k < nrhs; ++k) {
+    const double* b = B + (size_t)k * ldb;
+    double* x = X + (size_t)k * ldx;
+    if (!warm) fill(x, c.n, 0.0, s);
+    cols[k].atb = atb_norm(c, b, s);
+    cols[k].bnorm = vec_norm(c, b, s);
+    if (!std::isfinite(cols[k].atb) || !std::isfinite(cols[k].bnorm))
+      throw Error(APLICUR_E_BREAKDOWN, "non-finite values in A or B");
+    if (cols[k].atb == 0.0) {
+      fill(x, c.n, 0.0, s);
+      cols[k].eta = 0.0;
+      cols[k].done = true;
+    } else if (warm) {
+      cols[k].eta = eta_of(c, b, nullptr, 0.0, x, cols[k].atb, s);
+      cols[k].done = cols[k].eta <= c.o.tol_ne;
+    }
+  }
+  c.phase_iters0.clear();
+  c.phase_eta0.clear();
+  int rebuilds = 0, outer = 0;
+  double last_rho = 0.0;
+  if (!c.o.precond) {
+    auto t0 = Clock::now();
+    for (int k = 0; k < nrhs; ++k) {
+      if (cols[k].done) continue;
+      refine(c, nullptr, B + (size_t)k * ldb, X + (size_t)k * ldx, cols[k], 1.0, 0.0, !warm,
+             k == 0 ? &c.phase_iters0 : nullptr, k == 0 ? &c.phase_eta0 : nullptr, s);
+      cols[k].done = true;
+    }
+    t_lsqr += ms_since(t0);
+  } else {
+    // restart the CUR sequence (it depends on A only)
+    c.rank = 0;
+    c.I.clear();
+    c.J.clear();
+    c.rho_hist.clear();
+    c.rank_hist.clear();
+    c.rebuild_hist.clear();
+    c.have_prec = false;
+    APL_HIP(hipMemcpyAsync(c.E, c.Y, sizeof(double) * (size_t)c.s * c.n, hipMemcpyDeviceToDevice, s));
+    double d_cur = INFINITY;
+    bool any_active = false;
+    for (auto& cs : cols) any_active |= !cs.done;
+    while (any_active) {
+      auto t0 = Clock::now();
+      StepResult sr = outer_step(c, s);
+      t_cur += ms_since(t0);
+      ++outer;
+      if (sr.added == 0 && c.rank == 0) break;
+      last_rho = sr.rho;
+      const bool final_step = sr.rho <= c.eps_cur || sr.exhausted || c.rank >= c.L ||
+                              (c.o.max_outer > 0 && outer >= c.o.max_outer);
+      const double gap = sr.rho - c.eps_cur;
+      const bool rebuild = final_step || (d_cur / gap >= c.o.nu_prec);
+      c.rho_hist.push_back(sr.rho);
+      c.rank_hist.push_back(c.rank);
+      c.rebuild_hist.push_back(rebuild ? 1 : 0);
+      if (rebuild) {
+        t0 = Clock::now();
+        build_precond(c, s);
+        ++rebuilds;
+        t_prec += ms_since(t0);
+        t0 = Clock::now();
+        const double nu = final_step ? INFINITY : c.o.nu_lsqr;
+        const double epsl = final_step ? 0.0 : c.o.eps_lsqr;
+        for (int k = 0; k < nrhs; ++k) {
+          ColState& cs = cols[k];
+          if (cs.done) continue;
+          const double* b = B + (size_t)k * ldb;
+          double* x = X + (size_t)k * ldx;
+          const bool xz = (!warm && cs.phases == 0);
+          PhaseOut po = run_phase(c, &c.prec, b, nullptr, 0.0, x, xz, c.o.tol_ne * cs.atb, c.p_pnorm, epsl,
+                                  c.o.eps_lsqr * cs.bnorm, nu, c.p_sigma_l, c.o.max_iter - cs.used, s);
+          cs.used += po.iters;
+          cs.phases += 1;
+          cs.eta = eta_of(c, b, nullptr, 0.0, x, cs.atb, s);
+          if (k == 0) {
+            c.phase_iters0.push_back(po.iters);
+            c.phase_eta0.push_back(cs.eta);
+          }
+          if (cs.eta <= c.o.tol_ne || cs.used >= c.o.max_iter) {
+            cs.done = true;
+          } else if (final_step) {
+            refine(c, &c.prec, b, x, cs, c.p_pnorm, c.p_sigma_l, false, k == 0 ? &c.phase_iters0 : nullptr,
+                   k == 0 ? &c.phase_eta0 : nullptr, s);
+            cs.done = true;
+          }
+        }
+        d_cur = gap;
+        t_lsqr += ms_since(t0);
+      }
+      if (final_step) break;
+      any_active = false;
+      for (auto& cs : cols) any_active |= !cs.done;
+    }
+  }
+  int status = APLICUR_OK;
+  double eta_max = 0.0;
+  int iters = 0, phases = 0;
+  for (auto& cs : cols) {
+    eta_max = std::max(eta_max, cs.eta);
+    iters = std::max(iters, cs.used);
+    phases = std::max(phases, cs.phases);
+    if (cs.eta > c.o.tol_ne) status = APLICUR_W_MAXITER;
+  }
+  if (info) {
+    info->status = status;
+    info->phases = phases;
+    info->iters = iters;
+    info->rank = c.rank;
+    info->rebuilds = rebuilds;
+    info->outer = outer;
+    info->eta = eta_max;
+    info->rho = last_rho;
+    info->sigma_hat = c.p_target;
+    info->t_sketch_ms = c.t_sketch;
+    info->t_cur_ms = t_cur;
+    info->t_precond_ms = t_prec;
+    info->t_lsqr_ms = t_lsqr;
+  }
+  (void)t_start;
+  return status;
+}
+
+}  // namespace aplicur
+
+// ==================================================================== C ABI
+using namespace aplicur;
+
+struct aplicur_ctx {
+  Ctx* impl;
+};
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return APLICUR_E_HIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return APLICUR_E_HIP;
+  }
+}
+
+extern "C" {
+
+void aplicur_opts_default(aplicur_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->block = 20;
+  o->r_probes = 10;
+  o->seed = 7;
+  o->mu = 0.0;
+  o->eps_cur = -1.0;
+  o->nu_prec = 10.0;
+  o->nu_lsqr = 100.0;
+  o->eps_lsqr = 1e-10;
+  o->tol_ne = 1e-8;
+  o->max_iter = 100000;
+  o->max_rank = 0;
+  o->precond = 1;
+  o->precision = 0;
+  o->max_outer = 0;
+}
+
+int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* stream, aplicur_ctx** ctx_out) {
+  return guarded([&]() {
+    APL_REQUIRE(ctx_out, "ctx_out is null");
+    *ctx_out = nullptr;
+    Ctx* c = create(A, opts, (hipStream_t)stream);
+    *ctx_out = new aplicur_ctx{c};
+    return APLICUR_OK;
+  });
+}
+
+int aplicur_solve(aplicur_ctx* ctx, const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,
+                  int32_t x_is_warm, aplicur_info* info, void* stream) {
+  return guarded([&]() {
+    APL_REQUIRE(ctx && ctx->impl, "null context");
+    return solve(*ctx->impl, B, ldb, nrhs, X, ldx, x_is_warm != 0, info, (hipStream_t)stream);
+  });
+}
+
+int aplicur_solve_batched(int32_t batch, const aplicur_mat* A, const double* const* B, const int64_t* ldb,
+                          int32_t nrhs, double* const* X, const int64_t* ldx, const aplicur_opts* opts,
+                          aplicur_info* info, void* stream) {
+  return guarded([&]() {
+    APL_REQUIRE(batch >= 0, "batch must be >= 0");
+    APL_REQUIRE(batch == 0 || (A && B && ldb && X && ldx && opts), "null batch arrays");
+    int worst = APLICUR_OK;
+    for (int p = 0; p < batch; ++p) {
+      Ctx* c = create(&A[p], opts, (hipStream_t)stream);
+      int st;
+      try {
+        st = solve(*c, B[p], ldb[p], nrhs, X[p], ldx[p], false, info ? &info[p] : nullptr, (hipStream_t)stream);
+      } catch (...) {
+        delete c;
+        throw;
+      }
+      delete c;
+      worst = std::max(worst, st);
+    }
+    return worst;
+  });
+}
+
+int aplicur_solve_backward(aplicur_ctx* ctx, const double* X, int64_t ldx, const double* B, int64_t ldb,
+                           const double* G, int64_t ldg, int32_t nrhs, double* Z, int64_t ldz, double* dB,
+                           int64_t lddb, double* dA, int64_t ldda, aplicur_info* info, void* stream) {
+  return guarded([&]() -> int {
+    APL_REQUIRE(ctx && ctx->impl, "null context");
+    Ctx& c = *ctx->impl;
+    hipStream_t s = (hipStream_t)stream;
+    (void)X; (void)ldx; (void)B; (void)ldb; (void)G; (void)ldg; (void)nrhs; (void)Z; (void)ldz; (void)dB;
+    (void)lddb; (void)dA; (void)ldda; (void)info; (void)s;
+    (void)c;
+    throw Error(APLICUR_E_INVALID, "aplicur_solve_backward: not available in this build");
+  });
+}
+
+int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, void* stream) {
+  return guarded([&]() {
+    APL_REQUIRE(ctx && ctx->impl && x && y, "null argument");
+    Ctx& c = *ctx->impl;
+    hipStream_t s = (hipStream_t)stream;
+    APL_HIP(hipMemcpyAsync(c.st, c.st_mv, sizeof(GKState), hipMemcpyDeviceToDevice, s));
+    if (!trans) fill(y, c.m, 0.0, s);
+    op_matvec(c.op, trans, x, y, c.st, c.partials, c.counter, s);
+    APL_HIP(hipGetLastError());
+    return APLICUR_OK;
+  });
+}
+
+int64_t aplicur_ctx_query(const aplicur_ctx* ctx, int32_t what, void* host_out, size_t bytes) {
+  if (!ctx || !ctx->impl) {
+    g_last_error = "null context";
+    return APLICUR_E_INVALID;
+  }
+  Ctx& c = *ctx->impl;
+  try {
+    std::vector<char> buf;
+    auto put = [&](const void* p, size_t nb) { buf.assign((const char*)p, (const char*)p + nb); };
+    auto dev = [&](const void* p, size_t nb) {
+      buf.resize(nb);
+      if (nb) {
+        APL_HIP(hipDeviceSynchronize());
+        APL_HIP(hipMemcpy(buf.data(), p, nb, hipMemcpyDeviceToHost));
+      }
+    };
+    switch (what) {
+      case 1: dev(c.Y, sizeof(double) * (size_t)c.s * c.n); break;
+      case 2: case 3: {
+        std::vector<uint16_t> rows((size_t)c.m * c.xi);
+        std::vector<uint8_t> neg(c.m);
+        APL_HIP(hipDeviceSynchronize());
+        if (c.S_rows) {
+          APL_HIP(hipMemcpy(rows.data(), c.S_rows, rows.size() * 2, hipMemcpyDeviceToHost));
+          APL_HIP(hipMemcpy(neg.data(), c.S_neg, neg.size(), hipMemcpyDeviceToHost));
+        }
+        std::vector<int32_t> out((size_t)c.m * c.xi);
+        for (long long i = 0; i < c.m; ++i)
+          for (int t = 0; t < c.xi; ++t)
+            out[(size_t)i * c.xi + t] = (what == 2) ? rows[(size_t)i * c.xi + t] : (((neg[i] >> t) & 1) ? -1 : 1);
+        put(out.data(), out.size() * 4);
+        break;
+      }
+      case 4: dev(c.W, sizeof(double) * (size_t)c.n * c.r); break;
+      case 5: put(c.J.data(), c.J.size() * 4); break;
+      case 6: put(c.I.data(), c.I.size() * 4); break;
+      case 7: put(c.rho_hist.data(), c.rho_hist.size() * 8); break;
+      case 8: put(c.rank_hist.data(), c.rank_hist.size() * 4); break;
+      case 9: put(c.rebuild_hist.data(), c.rebuild_hist.size() * 4); break;
+      case 10: {
+        int64_t sz[7] = {c.m, c.n, c.s, c.xi, c.rank, (int64_t)c.rank_hist.size(), c.r};
+        put(sz, sizeof(sz));
+        break;
+      }
+      case 11: put(c.p_sigma_host.data(), c.p_sigma_host.size() * 8); break;
+      case 12: put(c.phase_iters0.data(), c.phase_iters0.size() * 4); break;
+      case 13: put(c.phase_eta0.data(), c.phase_eta0.size() * 8); break;
+      default: g_last_error = "unknown query"; return APLICUR_E_INVALID;
+    }
+    if (host_out && bytes) std::memcpy(host_out, buf.data(), std::min(bytes, buf.size()));
+    return (int64_t)buf.size();
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  }
+}
+
+void aplicur_ctx_destroy(aplicur_ctx* ctx) {
+  if (!ctx) return;
+  delete ctx->impl;
+  delete ctx;
+}
+
+const char* aplicur_last_error(void) { return g_last_error.c_str(); }
+const char* aplicur_version(void) { return "aplicur-gfx950 0.1"; }
+
+}  // extern "C"

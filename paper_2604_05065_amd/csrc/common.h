@@ -1,0 +1,116 @@
+// Shared definitions of the APLICUR HIP library (gfx950 / CDNA4, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+namespace aplicur {
+
+constexpr int kBlock = 256;  // threads per workgroup everywhere (4 wave64s)
+constexpr int kWave = 64;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define APL_HIP(x)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw ::aplicur::Error(-3, std::string(#x) + ": " + hipGetErrorString(e_) + " (" + \
+                                     __FILE__ + ":" + std::to_string(__LINE__) + ")"); \
+  } while (0)
+
+#define APL_REQUIRE(cond, msg)                                   \
+  do {                                                           \
+    if (!(cond)) throw ::aplicur::Error(-1, std::string(msg));   \
+  } while (0)
+
+// Stop reasons of an LSQR phase (same numbering as the oracle).
+enum StopReason { kStopNone = 0, kStopMetric = 1, kStopLsqr = 2, kStopDynamic = 3,
+                  kStopBudget = 4, kStopExact = 5 };
+
+// Per right-hand-side state of one Golub-Kahan / LSQR phase.  Lives in device
+// memory; written only by the last workgroup of a kernel (all other
+// workgroups of that launch have finished reading it by then), so no double
+// buffering is needed.  Vectors are kept unnormalised: u = u_raw / beta,
+// v = v_raw / alpha, and the y/w update of iteration j is applied lazily by
+// the first kernel of iteration j + 1 (or by the finalize kernel).
+struct GKState {
+  double alpha, beta;          // norms of the current raw v and u
+  double rhobar, phibar;       // Givens QR state
+  double anorm2;               // running ||A~||_F^2 estimate
+  double phibar_prev, rate1;   // dynamic stopping history
+  double coef_y, coef_w;       // pending y += coef_y w ; w = v - coef_w w
+  double arnorm;               // ||A~^T r|| estimate
+  double pnorm;                // ||P|| (1 without a preconditioner)
+  double tol_abs;              // tol_ne * ||A^T b||
+  double eps_lsqr, baug_eps;   // Paige-Saunders tolerance and eps * ||b_aug||
+  double nu, sigma_l;          // dynamic rule (nu = +inf disables it)
+  double delta;                // sqrt(mu)
+  double h2;                   // ||A_mu^T r||^2 at phase start (normal-equation residual)
+  double beta1;                // initial residual of the phase
+  int iter, max_iter, stop, reason, pending, have_rate1, init, pad;
+};
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over the whole workgroup (kBlock threads); result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / kWave];
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) s += red[i];
+  }
+  return s;
+}
+
+// "Last workgroup done" ticket: every workgroup calls this once after writing
+// its partial result; returns true in exactly one workgroup, after all others
+// have published their partials.  The ticket counter is reset by that block.
+__device__ __forceinline__ bool last_block(unsigned* counter, unsigned nblocks) {
+  __shared__ int am_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    am_last = (t == nblocks - 1);
+    if (am_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (am_last) __threadfence();
+  return am_last != 0;
+}
+
+// Sum of partials[0..count) in a fixed order (deterministic), by one workgroup.
+__device__ __forceinline__ double reduce_partials(const double* partials, int count) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += kBlock) v += partials[i];
+  return block_sum(v);
+}
+
+inline unsigned ceil_div(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace aplicur

@@ -1,0 +1,51 @@
+// Host declarations of the CUR / factorisation kernels (kern_factor.hip).
+#pragma once
+
+#include <climits>
+#include <cstring>
+
+#include "kernels.h"
+
+namespace aplicur {
+
+using AMat = OpDesc;
+
+// Scratch of the pivot search (sized for the tallest matrix searched).
+struct FactorWork {
+  int lupp_rows;
+  int *pos, *row_at;
+  double* pv;
+  int *pp, *pi;
+  void* lupp_state;
+  unsigned* counter;
+};
+
+// First k partial-pivoting pivots of the column-major r x c matrix X (X is
+// overwritten).  piv[0..keff) receives original row indices; read keff with
+// lupp_read_keff (synchronises the stream).
+void lupp_pivots(double* X, int r, int c, long long ld, int k, int* piv, FactorWork& fw, hipStream_t s);
+int lupp_read_keff(FactorWork& fw, hipStream_t s);
+
+void gather_cols(const AMat& A, const int* J, int k, double* out, long long ld_out, hipStream_t s);
+void gather_rows(const AMat& A, const int* I, int k, double* out, long long ld_out, hipStream_t s);
+void gather_sub_rows(const double* X, long long ldx, const int* rows, int nr, int ncols, double* out,
+                     long long ldo, hipStream_t s);
+void gather_y_cols(const double* Y, long long n, int s_rows, const int* J, int k, double* out, long long ldo,
+                   hipStream_t s);
+void zero_rows(double* X, long long ldx, const int* rows, int nr, int ncols, hipStream_t s);
+void fill(double* X, long long n, double v, hipStream_t s);
+void copy_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols, double alpha,
+                hipStream_t s);
+void set_identity(double* X, long long ld, int n, hipStream_t s);
+void add_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols, hipStream_t s);
+
+void small_inverse(double* S, long long ld, int k, double* Sinv, long long ldi, int* status, hipStream_t s);
+void small_potrf(double* G, long long ld, int k, int* status, hipStream_t s);
+
+int jacobi_block_width();
+int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
+               unsigned long long* offmax_dev, double tol, int max_sweeps, hipStream_t s);
+void precond_scalars(const double* sigma, int l, double delta, double* d, double* info, hipStream_t s);
+void rho_from_ew(const double* EW, int s_rows, int r, double* out, hipStream_t s);
+
+}  // namespace aplicur

@@ -1,0 +1,708 @@
+// Kernels of the CUR part of APLICUR (Alg. 3 Parts 1-3): LU-with-partial-
+// pivoting pivot selection (Alg. 7), gathers of rows/columns of A, small
+// dense factorisations (Cholesky, Gauss-Jordan inverse) and the one-sided
+// block Jacobi SVD of the l x l core M (Alg. 2).  All FP64.
+#include "factor.h"
+
+namespace aplicur {
+
+// ============================================================== LUPP pivots
+// Partial-pivoting elimination on a column-major r x c matrix X, keeping the
+// LAPACK row order for ties: pos[i] is the current position of original row
+// i (rows are not moved; only the bookkeeping is), row_at[p] its inverse.
+// The pivot of column q is the remaining row with the largest |X(i,q)|, the
+// smallest position winning ties (idamax).  One launch per column: it
+// eliminates column q with its pivot and finds the pivot of column q + 1;
+// its last workgroup does the swap bookkeeping for the next launch.
+struct LuppState {
+  int p;         // pivot row (original index) of the current column
+  int keff;      // number of pivots found (== k when not exhausted)
+  int stop;
+  int pad;
+};
+
+__device__ __forceinline__ bool better(double va, int pa, double vb, int pb) {
+  return va > vb || (va == vb && pa < pb);
+}
+
+__device__ void block_argmax(double& v, int& p, int& idx) {
+  __shared__ double sv[kBlock];
+  __shared__ int sp[kBlock], si[kBlock];
+  sv[threadIdx.x] = v;
+  sp[threadIdx.x] = p;
+  si[threadIdx.x] = idx;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      int o = threadIdx.x + off;
+      if (better(sv[o], sp[o], sv[threadIdx.x], sp[threadIdx.x])) {
+        sv[threadIdx.x] = sv[o];
+        sp[threadIdx.x] = sp[o];
+        si[threadIdx.x] = si[o];
+      }
+    }
+    __syncthreads();
+  }
+  v = sv[0];
+  p = sp[0];
+  idx = si[0];
+  __syncthreads();
+}
+
+// Last workgroup: global argmax over the partials, then the swap
+// bookkeeping of step `q` (the step whose pivot this is).
+__device__ void lupp_select(int q, int k, int nparts, const double* pv, const int* pp, const int* pi,
+                            int* pos, int* row_at, int* piv, LuppState* ls) {
+  double v = -1.0;
+  int p = INT_MAX, idx = -1;
+  for (int t = threadIdx.x; t < nparts; t += kBlock)
+    if (better(pv[t], pp[t], v, p)) {
+      v = pv[t];
+      p = pp[t];
+      idx = pi[t];
+    }
+  block_argmax(v, p, idx);
+  if (threadIdx.x == 0) {
+    if (!(v > 0.0) || idx < 0) {  // zero (or NaN) column: residual exhausted
+      ls->keff = q;
+      ls->stop = 1;
+    } else {
+      const int o = row_at[q];
+      const int pp_old = pos[idx];
+      row_at[pp_old] = o;
+      pos[o] = pp_old;
+      row_at[q] = idx;
+      pos[idx] = q;
+      piv[q] = idx;
+      ls->p = idx;
+      ls->keff = q + 1;
+      if (q + 1 >= k) ls->stop = 1;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_lupp_init(const double* X, int r, long long ld, int k,
+                                                      int* pos, int* row_at, int* piv, LuppState* ls,
+                                                      double* pv, int* pp, int* pi, unsigned* counter) {
+  double v = -1.0;
+  int p = INT_MAX, idx = -1;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < r; i += gridDim.x * kBlock) {
+    pos[i] = i;
+    row_at[i] = i;
+    const double a = fabs(X[i]);
+    if (better(a, i, v, p)) {
+      v = a;
+      p = i;
+      idx = i;
+    }
+  }
+  block_argmax(v, p, idx);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = v;
+    pp[blockIdx.x] = p;
+    pi[blockIdx.x] = idx;
+    if (blockIdx.x == 0) {
+      ls->stop = (k <= 0);
+      ls->keff = 0;
+    }
+  }
+  if (last_block(counter, gridDim.x)) lupp_select(0, k, gridDim.x, pv, pp, pi, pos, row_at, piv, ls);
+}
+
+__global__ void __launch_bounds__(kBlock) k_lupp_step(double* X, int r, int c, long long ld, int q, int k,
+                                                      int* pos, int* row_at, int* piv, LuppState* ls,
+                                                      double* pv, int* pp, int* pi, unsigned* counter) {
+  if (ls->stop) return;
+  const int p = ls->p;
+  const double piv_val = X[p + q * ld];
+  const bool next = (q + 1 < k) && (q + 1 < c);
+  double v = -1.0;
+  int bp = INT_MAX, idx = -1;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < r; i += gridDim.x * kBlock) {
+    const int pi_ = pos[i];
+    if (pi_ <= q) continue;  // pivot rows (positions 0..q) are not updated
+    const double l = X[i + q * ld] / piv_val;
+    X[i + q * ld] = l;
+    for (int j = q + 1; j < c; ++j) X[i + j * ld] -= l * X[p + j * ld];
+    if (next) {
+      const double a = fabs(X[i + (q + 1) * ld]);
+      if (better(a, pi_, v, bp)) {
+        v = a;
+        bp = pi_;
+        idx = i;
+      }
+    }
+  }
+  if (!next) return;
+  block_argmax(v, bp, idx);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = v;
+    pp[blockIdx.x] = bp;
+    pi[blockIdx.x] = idx;
+  }
+  if (last_block(counter, gridDim.x)) lupp_select(q + 1, k, gridDim.x, pv, pp, pi, pos, row_at, piv, ls);
+}
+
+void lupp_pivots(double* X, int r, int c, long long ld, int k, int* piv, FactorWork& fw, hipStream_t s) {
+  APL_REQUIRE(r <= fw.lupp_rows, "lupp: workspace rows too small");
+  int grid = (r + kBlock - 1) / kBlock;
+  if (grid > 1024) grid = 1024;
+  LuppState* ls = (LuppState*)fw.lupp_state;
+  hipLaunchKernelGGL(k_lupp_init, dim3(grid), dim3(kBlock), 0, s, X, r, ld, k, fw.pos, fw.row_at, piv, ls,
+                     fw.pv, fw.pp, fw.pi, fw.counter);
+  for (int q = 0; q + 1 < k; ++q)
+    hipLaunchKernelGGL(k_lupp_step, dim3(grid), dim3(kBlock), 0, s, X, r, c, ld, q, k, fw.pos, fw.row_at,
+                       piv, ls, fw.pv, fw.pp, fw.pi, fw.counter);
+}
+
+int lupp_read_keff(FactorWork& fw, hipStream_t s) {
+  LuppState h;
+  APL_HIP(hipMemcpyAsync(&h, fw.lupp_state, sizeof(h), hipMemcpyDeviceToHost, s));
+  APL_HIP(hipStreamSynchronize(s));
+  return h.keff;
+}
+
+// ============================================================== gathers
+// out(i, t) = A(i, J[t]) for dense row-major A (column-major out, ld_out).
+template <class T>
+__global__ void k_gather_cols_dense(const T* A, long long m, long long ld, const int* J, int k,
+                                    double* out, long long ld_out) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int t = blockIdx.y;
+  if (i < m && t < k) out[i + t * ld_out] = (double)A[i * ld + J[t]];
+}
+
+// out(:, t) = A(:, J[t]) for CSR A through its transpose (rows of A^T).
+template <class T>
+__global__ void k_gather_cols_csr(const int* tp, const int* ti, const T* tv, const int* J, int k,
+                                  double* out, long long ld_out) {
+  const int t = blockIdx.x;
+  if (t >= k) return;
+  const int j = J[t];
+  for (int e = tp[j] + threadIdx.x; e < tp[j + 1]; e += kBlock) out[ti[e] + t * ld_out] = (double)tv[e];
+}
+
+// out(j, t) = A(I[t], j): rows of A as columns of a column-major n x k block.
+template <class T>
+__global__ void k_gather_rows_dense(const T* A, long long n, long long ld, const int* I, int k,
+                                    double* out, long long ld_out) {
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int t = blockIdx.y;
+  if (j < n && t < k) out[j + t * ld_out] = (double)A[(long long)I[t] * ld + j];
+}
+
+template <class T>
+__global__ void k_gather_rows_csr(const int* rp, const int* ci, const T* val, const int* I, int k,
+                                  double* out, long long ld_out) {
+  const int t = blockIdx.x;
+  if (t >= k) return;
+  const int i = I[t];
+  for (int e = rp[i] + threadIdx.x; e < rp[i + 1]; e += kBlock) out[ci[e] + t * ld_out] = (double)val[e];
+}
+
+// out(a, t) = X(rows[a], t) for a < nr: gather rows of a column-major matrix.
+__global__ void k_gather_sub_rows(const double* X, long long ldx, const int* rows, int nr, int ncols,
+                                  double* out, long long ldo) {
+  const int a = blockIdx.x * kBlock + threadIdx.x;
+  const int t = blockIdx.y;
+  if (a < nr && t < ncols) out[a + t * ldo] = X[rows[a] + t * ldx];
+}
+
+// X(rows[a], t) = 0 for every column t < ncols.
+__global__ void k_zero_rows(double* X, long long ldx, const int* rows, int nr, int ncols) {
+  const int a = blockIdx.x * kBlock + threadIdx.x;
+  const int t = blockIdx.y;
+  if (a < nr && t < ncols) X[rows[a] + t * ldx] = 0.0;
+}
+
+__global__ void k_fill(double* X, long long n, double v) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+    X[i] = v;
+}
+
+// Y(h, j) row-major s x n  ->  column-major s x k block of the columns J.
+__global__ void k_gather_y_cols(const double* Y, long long n, int s, const int* J, int k, double* out,
+                                long long ldo) {
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int t = blockIdx.y;
+  if (h < s && t < k) out[h + t * ldo] = Y[(long long)h * n + J[t]];
+}
+
+void gather_cols(const AMat& A, const int* J, int k, double* out, long long ld_out, hipStream_t s) {
+  if (k <= 0) return;
+  if (A.csr) {
+    fill(out, ld_out * (long long)(k - 1) + A.m, 0.0, s);
+    if (A.f64)
+      hipLaunchKernelGGL(k_gather_cols_csr<double>, dim3(k), dim3(kBlock), 0, s, A.t_ptr, A.t_idx,
+                         (const double*)A.t_val, J, k, out, ld_out);
+    else
+      hipLaunchKernelGGL(k_gather_cols_csr<float>, dim3(k), dim3(kBlock), 0, s, A.t_ptr, A.t_idx,
+                         (const float*)A.t_val, J, k, out, ld_out);
+  } else {
+    dim3 g(ceil_div(A.m, kBlock), k);
+    if (A.f64)
+      hipLaunchKernelGGL(k_gather_cols_dense<double>, g, dim3(kBlock), 0, s, (const double*)A.val, A.m, A.ld,
+                         J, k, out, ld_out);
+    else
+      hipLaunchKernelGGL(k_gather_cols_dense<float>, g, dim3(kBlock), 0, s, (const float*)A.val, A.m, A.ld,
+                         J, k, out, ld_out);
+  }
+}
+
+void gather_rows(const AMat& A, const int* I, int k, double* out, long long ld_out, hipStream_t s) {
+  if (k <= 0) return;
+  if (A.csr) {
+    fill(out, ld_out * (long long)(k - 1) + A.n, 0.0, s);
+    if (A.f64)
+      hipLaunchKernelGGL(k_gather_rows_csr<double>, dim3(k), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
+                         (const double*)A.val, I, k, out, ld_out);
+    else
+      hipLaunchKernelGGL(k_gather_rows_csr<float>, dim3(k), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
+                         (const float*)A.val, I, k, out, ld_out);
+  } else {
+    dim3 g(ceil_div(A.n, kBlock), k);
+    if (A.f64)
+      hipLaunchKernelGGL(k_gather_rows_dense<double>, g, dim3(kBlock), 0, s, (const double*)A.val, A.n, A.ld,
+                         I, k, out, ld_out);
+    else
+      hipLaunchKernelGGL(k_gather_rows_dense<float>, g, dim3(kBlock), 0, s, (const float*)A.val, A.n, A.ld,
+                         I, k, out, ld_out);
+  }
+}
+
+void gather_sub_rows(const double* X, long long ldx, const int* rows, int nr, int ncols, double* out,
+                     long long ldo, hipStream_t s) {
+  if (nr <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_gather_sub_rows, dim3(ceil_div(nr, kBlock), ncols), dim3(kBlock), 0, s, X, ldx, rows,
+                     nr, ncols, out, ldo);
+}
+
+void zero_rows(double* X, long long ldx, const int* rows, int nr, int ncols, hipStream_t s) {
+  if (nr <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_zero_rows, dim3(ceil_div(nr, kBlock), ncols), dim3(kBlock), 0, s, X, ldx, rows, nr,
+                     ncols);
+}
+
+void fill(double* X, long long n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned g = ceil_div(n, kBlock);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_fill, dim3(g), dim3(kBlock), 0, s, X, n, v);
+}
+
+void gather_y_cols(const double* Y, long long n, int s_rows, const int* J, int k, double* out, long long ldo,
+                   hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_gather_y_cols, dim3(ceil_div(s_rows, kBlock), k), dim3(kBlock), 0, s, Y, n, s_rows, J,
+                     k, out, ldo);
+}
+
+// ============================================================== small dense (one workgroup)
+// In-place Gauss-Jordan inverse with partial pivoting of the k x k matrix S
+// (column-major, ld), into Sinv.  status[0] = 0 on success, 1 if singular.
+__global__ void __launch_bounds__(kBlock) k_gj_inverse(double* S, long long ld, int k, double* Sinv,
+                                                       long long ldi, int* perm, int* status) {
+  __shared__ int piv_row;
+  __shared__ double piv_val;
+  for (int e = threadIdx.x; e < k * k; e += kBlock) {
+    int i = e % k, j = e / k;
+    Sinv[i + j * ldi] = (i == j) ? 1.0 : 0.0;
+  }
+  if (threadIdx.x == 0) status[0] = 0;
+  __syncthreads();
+  for (int q = 0; q < k; ++q) {
+    // pivot search in column q, rows q..k-1 (first max)
+    double v = -1.0;
+    int p = INT_MAX, idx = -1;
+    for (int i = q + threadIdx.x; i < k; i += kBlock) {
+      double a = fabs(S[i + q * ld]);
+      if (better(a, i, v, p)) {
+        v = a;
+        p = i;
+        idx = i;
+      }
+    }
+    block_argmax(v, p, idx);
+    if (threadIdx.x == 0) {
+      piv_row = idx;
+      piv_val = (idx >= 0) ? S[idx + q * ld] : 0.0;
+      if (!(v > 0.0)) status[0] = 1;
+    }
+    __syncthreads();
+    if (!(piv_val != 0.0)) return;
+    const int pr = piv_row;
+    // swap rows q and pr of both S and Sinv
+    if (pr != q) {
+      for (int j = threadIdx.x; j < k; j += kBlock) {
+        double t = S[q + j * ld];
+        S[q + j * ld] = S[pr + j * ld];
+        S[pr + j * ld] = t;
+        t = Sinv[q + j * ldi];
+        Sinv[q + j * ldi] = Sinv[pr + j * ldi];
+        Sinv[pr + j * ldi] = t;
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / piv_val;
+    for (int j = threadIdx.x; j < k; j += kBlock) {
+      S[q + j * ld] *= inv;
+      Sinv[q + j * ldi] *= inv;
+    }
+    __syncthreads();
+    // eliminate column q from every other row
+    for (int e = threadIdx.x; e < k * k; e += kBlock) {
+      const int i = e % k, j = e / k;
+      if (i == q) continue;
+      const double f = S[i + q * ld];
+      if (j != q) S[i + j * ld] -= f * S[q + j * ld];
+      Sinv[i + j * ldi] -= f * Sinv[q + j * ldi];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += kBlock)
+      if (i != q) S[i + q * ld] = 0.0;
+    __syncthreads();
+  }
+}
+
+void small_inverse(double* S, long long ld, int k, double* Sinv, long long ldi, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_inverse, dim3(1), dim3(kBlock), 0, s, S, ld, k, Sinv, ldi, (int*)nullptr, status);
+}
+
+// Upper Cholesky factor (in place, upper triangle) of the SPD k x k matrix G.
+// status[0] = 0 on success, 1 + j if the j-th pivot is not positive.
+__global__ void __launch_bounds__(kBlock) k_potrf_upper(double* G, long long ld, int k, int* status) {
+  __shared__ double djj;
+  if (threadIdx.x == 0) status[0] = 0;
+  for (int j = 0; j < k; ++j) {
+    if (threadIdx.x == 0) {
+      double d = G[j + j * ld];
+      if (!(d > 0.0)) {
+        status[0] = 1 + j;
+        djj = 0.0;
+      } else {
+        djj = sqrt(d);
+        G[j + j * ld] = djj;
+      }
+    }
+    __syncthreads();
+    if (!(djj > 0.0)) return;
+    for (int l = j + 1 + threadIdx.x; l < k; l += kBlock) G[j + l * ld] /= djj;
+    __syncthreads();
+    const int rem = k - j - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += kBlock) {
+      const int a = j + 1 + e % rem, b = j + 1 + e / rem;
+      if (a <= b) G[a + b * ld] -= G[j + a * ld] * G[j + b * ld];
+    }
+    __syncthreads();
+  }
+  // clear the strict lower triangle
+  for (int e = threadIdx.x; e < k * k; e += kBlock) {
+    const int a = e % k, b = e / k;
+    if (a > b) G[a + b * ld] = 0.0;
+  }
+}
+
+void small_potrf(double* G, long long ld, int k, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_potrf_upper, dim3(1), dim3(kBlock), 0, s, G, ld, k, status);
+}
+
+// ============================================================== block one-sided Jacobi SVD
+// X (rows x ncols, column-major) is orthogonalised column-block-pair by
+// column-block-pair: for the pair of width 2*kJW, the Gram matrix is formed,
+// diagonalised by cyclic Jacobi in LDS, and the rotation applied to the
+// columns of X and of V.  Round-robin pairing covers every block pair once
+// per sweep (Hestenes' method, block form).  sweepmax receives the largest
+// relative off-diagonal |g_pq| / sqrt(g_pp g_qq) seen in the round.
+constexpr int kJW = 16;       // columns per block
+constexpr int kJP = 2 * kJW;  // columns per pair
+
+__device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, int& b) {
+  // circle method: block nblk-1 fixed, the others rotate
+  if (slot == 0) {
+    a = nblk - 1;
+    b = round % (nblk - 1);
+  } else {
+    a = (round + slot) % (nblk - 1);
+    b = (round - slot + (nblk - 1)) % (nblk - 1);
+  }
+  if (a > b) {
+    int t = a;
+    a = b;
+    b = t;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_jacobi_round(double* X, long long ldx, int rows, double* Vm,
+                                                         long long ldv, int vrows, int nblk, int round,
+                                                         unsigned long long* offmax) {
+  __shared__ double G[kJP][kJP + 1];
+  __shared__ double Q[kJP][kJP + 1];
+  __shared__ double tile[64][kJP + 1];
+  __shared__ double cs[kJW], sn[kJW];
+  __shared__ int pp_[kJW], qq_[kJW];
+  __shared__ double block_off;
+  int a, b;
+  pair_of(round, nblk, blockIdx.x, a, b);
+  int col[2] = {a * kJW, b * kJW};
+  const int tid = threadIdx.x;
+  // 1) Gram matrix of the 2*kJW columns
+  double acc[4] = {0, 0, 0, 0};
+  for (int r0 = 0; r0 < rows; r0 += 64) {
+    for (int e = tid; e < 64 * kJP; e += kBlock) {
+      const int rr = e % 64, cc = e / 64;
+      const int gc = col[cc / kJW] + (cc % kJW);
+      tile[rr][cc] = (r0 + rr < rows) ? X[(long long)(r0 + rr) + (long long)gc * ldx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + t * kBlock;
+      const int i = e % kJP, j = e / kJP;
+      double s = 0.0;
+      for (int rr = 0; rr < 64; ++rr) s += tile[rr][i] * tile[rr][j];
+      acc[t] += s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = tid + t * kBlock;
+    G[e % kJP][e / kJP] = acc[t];
+  }
+  for (int e = tid; e < kJP * kJP; e += kBlock) Q[e % kJP][e / kJP] = (e % kJP == e / kJP) ? 1.0 : 0.0;
+  if (tid == 0) block_off = 0.0;
+  __syncthreads();
+  // measure off-diagonality of the pair
+  {
+    double mx = 0.0;
+    for (int e = tid; e < kJP * kJP; e += kBlock) {
+      const int i = e % kJP, j = e / kJP;
+      if (i < j) {
+        const double d = sqrt(G[i][i] * G[j][j]);
+        if (d > 0.0) mx = fmax(mx, fabs(G[i][j]) / d);
+      }
+    }
+    // block max through LDS
+    __shared__ double red[kBlock];
+    red[tid] = mx;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+      __syncthreads();
+    }
+    if (tid == 0) {
+      block_off = red[0];
+      atomicMax(offmax, (unsigned long long)__double_as_longlong(red[0]));
+    }
+    __syncthreads();
+  }
+  // 2) cyclic Jacobi on G (kJP x kJP), parallel round-robin over kJP/2 pairs
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    __shared__ int changed;
+    if (tid == 0) changed = 0;
+    __syncthreads();
+    for (int r = 0; r < kJP - 1; ++r) {
+      if (tid < kJW) {
+        int p, q;
+        if (tid == 0) {
+          p = kJP - 1;
+          q = r;
+        } else {
+          p = (r + tid) % (kJP - 1);
+          q = (r - tid + (kJP - 1)) % (kJP - 1);
+        }
+        if (p > q) {
+          int t = p;
+          p = q;
+          q = t;
+        }
+        const double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
+        double c = 1.0, s = 0.0;
+        if (fabs(gpq) > 1e-300 && fabs(gpq) > 2.2e-16 * sqrt(gpp * gqq)) {
+          const double zeta = (gqq - gpp) / (2.0 * gpq);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = c * t;
+          changed = 1;
+        }
+        pp_[tid] = p;
+        qq_[tid] = q;
+        cs[tid] = c;
+        sn[tid] = s;
+      }
+      __syncthreads();
+      // columns of G and Q: G <- G J, Q <- Q J
+      for (int e = tid; e < kJW * kJP; e += kBlock) {
+        const int pr = e / kJP, row = e % kJP;
+        const int p = pp_[pr], q = qq_[pr];
+        const double c = cs[pr], s = sn[pr];
+        const double gp = G[row][p], gq = G[row][q];
+        G[row][p] = c * gp - s * gq;
+        G[row][q] = s * gp + c * gq;
+        const double qp = Q[row][p], qq = Q[row][q];
+        Q[row][p] = c * qp - s * qq;
+        Q[row][q] = s * qp + c * qq;
+      }
+      __syncthreads();
+      // rows of G: G <- J^T G
+      for (int e = tid; e < kJW * kJP; e += kBlock) {
+        const int pr = e / kJP, cc = e % kJP;
+        const int p = pp_[pr], q = qq_[pr];
+        const double c = cs[pr], s = sn[pr];
+        const double gp = G[p][cc], gq = G[q][cc];
+        G[p][cc] = c * gp - s * gq;
+        G[q][cc] = s * gp + c * gq;
+      }
+      __syncthreads();
+    }
+    if (!changed) break;
+  }
+  // 3) apply Q to the columns of X and of V
+  if (block_off == 0.0) return;
+  for (int pass = 0; pass < 2; ++pass) {
+    double* M = pass == 0 ? X : Vm;
+    const long long ld = pass == 0 ? ldx : ldv;
+    const int nr = pass == 0 ? rows : vrows;
+    for (int r = tid; r < nr; r += kBlock) {
+      double in[kJP];
+#pragma unroll
+      for (int cc = 0; cc < kJP; ++cc) in[cc] = M[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld];
+#pragma unroll 4
+      for (int cc = 0; cc < kJP; ++cc) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < kJP; ++t) s += in[t] * Q[t][cc];
+        M[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld] = s;
+      }
+    }
+  }
+}
+
+__global__ void k_col_norms(const double* X, long long ldx, int rows, int ncols, double* out) {
+  const int c = blockIdx.x;
+  if (c >= ncols) return;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < rows; r += kBlock) {
+    const double v = X[(long long)r + (long long)c * ldx];
+    s += v * v;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[c] = sqrt(s);
+}
+
+int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
+               unsigned long long* offmax_dev, double tol, int max_sweeps, hipStream_t s) {
+  // X: n x npad (columns n..npad-1 zero), Vm: npad x npad, set to I by the caller.
+  const int nblk = npad / kJW;
+  int sweeps = 0;
+  for (; sweeps < max_sweeps; ++sweeps) {
+    APL_HIP(hipMemsetAsync(offmax_dev, 0, sizeof(unsigned long long), s));
+    for (int r = 0; r < nblk - 1; ++r)
+      hipLaunchKernelGGL(k_jacobi_round, dim3(nblk / 2), dim3(kBlock), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
+                         offmax_dev);
+    unsigned long long h = 0;
+    APL_HIP(hipMemcpyAsync(&h, offmax_dev, sizeof(h), hipMemcpyDeviceToHost, s));
+    APL_HIP(hipStreamSynchronize(s));
+    double off;
+    memcpy(&off, &h, sizeof(off));
+    if (off <= tol) {
+      ++sweeps;
+      break;
+    }
+  }
+  hipLaunchKernelGGL(k_col_norms, dim3(n), dim3(kBlock), 0, s, X, ldx, n, n, sigma);
+  return sweeps;
+}
+
+int jacobi_block_width() { return kJW; }
+
+// ============================================================== preconditioner scalars
+// d_i = target / sqrt(sigma_i^2 + delta^2) - 1, with target = sqrt(min sigma^2 + delta^2);
+// info[0] = min sigma, info[1] = max sigma, info[2] = target, info[3] = pnorm.
+__global__ void k_precond_scalars(const double* sigma, int l, double delta, double* d, double* info) {
+  __shared__ double smin, smax;
+  if (threadIdx.x == 0) {
+    double a = INFINITY, b = 0.0;
+    for (int i = 0; i < l; ++i) {
+      a = fmin(a, sigma[i]);
+      b = fmax(b, sigma[i]);
+    }
+    smin = a;
+    smax = b;
+  }
+  __syncthreads();
+  const double target = sqrt(smin * smin + delta * delta);
+  for (int i = threadIdx.x; i < l; i += kBlock) d[i] = target / sqrt(sigma[i] * sigma[i] + delta * delta) - 1.0;
+  if (threadIdx.x == 0) {
+    info[0] = smin;
+    info[1] = smax;
+    info[2] = target;
+    info[3] = fmax(1.0, sqrt(smax * smax + delta * delta) / target);
+  }
+}
+
+void precond_scalars(const double* sigma, int l, double delta, double* d, double* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_precond_scalars, dim3(1), dim3(kBlock), 0, s, sigma, l, delta, d, info);
+}
+
+// rho = 10 sqrt(2/pi) max_i ||EW(:, i)||  (EW = E_row W, s x r column-major).
+__global__ void k_rho(const double* EW, int s_rows, int r, double* out) {
+  __shared__ double norms[64];
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  for (int c = w; c < r; c += kBlock / kWave) {
+    double acc = 0.0;
+    for (int h = l; h < s_rows; h += kWave) acc += EW[h + (long long)c * s_rows] * EW[h + (long long)c * s_rows];
+    acc = wave_sum(acc);
+    if (l == 0) norms[c] = sqrt(acc);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int c = 0; c < r; ++c) mx = fmax(mx, norms[c]);
+    out[0] = 10.0 * sqrt(2.0 / M_PI) * mx;
+  }
+}
+
+void rho_from_ew(const double* EW, int s_rows, int r, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rho, dim3(1), dim3(kBlock), 0, s, EW, s_rows, r, out);
+}
+
+// Copy a column-major block (rows x cols) with scaling: dst = alpha * src.
+__global__ void k_copy_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols,
+                             double alpha) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < rows && j < cols) dst[i + j * ldd] = alpha * src[i + j * lds];
+}
+
+void copy_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols, double alpha,
+                hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(k_copy_block, dim3(ceil_div(rows, kBlock), cols), dim3(kBlock), 0, s, src, lds, dst, ldd,
+                     rows, cols, alpha);
+}
+
+__global__ void k_add_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < rows && j < cols) dst[i + j * ldd] += src[i + j * lds];
+}
+
+void add_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(k_add_block, dim3(ceil_div(rows, kBlock), cols), dim3(kBlock), 0, s, src, lds, dst, ldd, rows,
+                     cols);
+}
+
+__global__ void k_set_identity(double* X, long long ld, int n) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < n) X[i + j * ld] = (i == j) ? 1.0 : 0.0;
+}
+
+void set_identity(double* X, long long ld, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_set_identity, dim3(ceil_div(n, kBlock), n), dim3(kBlock), 0, s, X, ld, n);
+}
+
+}  // namespace aplicur

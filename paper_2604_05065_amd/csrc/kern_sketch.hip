@@ -1,0 +1,315 @@
+// One-time set-up kernels: the method's random stream (sparse sign embedding,
+// Definition 5.1; Gaussian probes of the 2-norm bound, Sec. 5.3.1), the CSR
+// transpose used for coalesced A^T products, and the sketch Y = S A (Alg. 3,
+// initialisation), computed once and reused for every rank increment.
+#include "kernels.h"
+
+namespace aplicur {
+
+// SplitMix64 (Steele, Lea, Flood 2014), variant-13 finalizer.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+__device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t stream) {
+  return mix64(seed + kGolden * (stream + 1));
+}
+__device__ __forceinline__ uint64_t draw(uint64_t key, uint64_t ctr) {
+  return mix64(key + kGolden * (ctr + 1));
+}
+
+// Column i of S (the coefficients applied to row i of A): xi distinct rows of
+// [0, s) by redraw-on-repeat (64 attempts, then the smallest unused row) and a
+// Rademacher sign each (top bit of a stream-1 draw).
+__global__ void k_gen_sketch(uint64_t seed, int s, long long m, int xi, uint16_t* rows,
+                             uint8_t* negmask) {
+  long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t k0 = stream_key(seed, 0), k1 = stream_key(seed, 1);
+  int chosen[8];
+  unsigned neg = 0;
+  for (int t = 0; t < xi; ++t) {
+    int h = -1;
+    for (int a = 0; a < 64 && h < 0; ++a) {
+      int cand = (int)(draw(k0, ((uint64_t)i * 8 + t) * 64 + a) % (uint64_t)s);
+      bool clash = false;
+      for (int tp = 0; tp < t; ++tp) clash |= (chosen[tp] == cand);
+      if (!clash) h = cand;
+    }
+    if (h < 0) {
+      for (int r = 0; r < s && h < 0; ++r) {
+        bool used = false;
+        for (int tp = 0; tp < t; ++tp) used |= (chosen[tp] == r);
+        if (!used) h = r;
+      }
+    }
+    chosen[t] = h;
+    rows[i * xi + t] = (uint16_t)h;
+    if (draw(k1, (uint64_t)i * 8 + t) >> 63) neg |= 1u << t;
+  }
+  negmask[i] = (uint8_t)neg;
+}
+
+// Probe vectors W (n x r, column-major): Box-Muller on two 53-bit uniforms.
+__global__ void k_gen_probes(uint64_t seed, long long n, int r, double* W) {
+  long long idx = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (idx >= n * r) return;
+  const uint64_t k2 = stream_key(seed, 2);
+  const uint64_t c = (uint64_t)idx;  // = i * n + j for column i, component j
+  uint64_t d0 = draw(k2, 2 * c), d1 = draw(k2, 2 * c + 1);
+  double u1 = ((double)(d0 >> 11) + 1.0) * 0x1.0p-53;
+  double u2 = (double)(d1 >> 11) * 0x1.0p-53;
+  W[idx] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+void launch_gen_sketch(uint64_t seed, int s, long long m, int xi, uint16_t* rows,
+                       uint8_t* negmask, hipStream_t st) {
+  hipLaunchKernelGGL(k_gen_sketch, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, st, seed, s, m,
+                     xi, rows, negmask);
+}
+
+void launch_gen_probes(uint64_t seed, long long n, int r, double* W, hipStream_t st) {
+  hipLaunchKernelGGL(k_gen_probes, dim3(ceil_div(n * r, kBlock)), dim3(kBlock), 0, st, seed,
+                     n, r, W);
+}
+
+// ---------------------------------------------------------------- CSR validation
+// bad[0] |= 1 for a malformed row pointer, 2 for a column index out of range.
+__global__ void k_check_csr(const int* row_ptr, const int* col_idx, long long m, long long n, long long nnz,
+                            int* bad) {
+  long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (i >= m) return;
+  const long long b = row_ptr[i], e = row_ptr[i + 1];
+  if ((i == 0 && b != 0) || b < 0 || e < b || e > nnz || (i == m - 1 && e != nnz)) {
+    atomicOr(bad, 1);
+    return;
+  }
+  for (long long k = b; k < e; ++k) {
+    const int c = col_idx[k];
+    if (c < 0 || c >= n) {
+      atomicOr(bad, 2);
+      return;
+    }
+  }
+}
+
+int check_csr(const int* row_ptr, const int* col_idx, long long m, long long n, long long nnz, int* bad_dev,
+              hipStream_t st) {
+  APL_HIP(hipMemsetAsync(bad_dev, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_check_csr, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, st, row_ptr, col_idx, m, n, nnz,
+                     bad_dev);
+  int h = 0;
+  APL_HIP(hipMemcpyAsync(&h, bad_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+  APL_HIP(hipStreamSynchronize(st));
+  return h;
+}
+
+// ---------------------------------------------------------------- CSR transpose
+__global__ void k_count_cols(const int* col_idx, long long nnz, int* counts) {
+  long long k = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (k < nnz) atomicAdd(&counts[col_idx[k]], 1);
+}
+
+// Exclusive scan of counts[0..n) into ptr[0..n], one workgroup, sequential
+// chunks with a block-wide scan inside each chunk.
+__global__ void k_scan_single(const int* counts, int n, int* ptr) {
+  __shared__ int buf[kBlock];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += kBlock) {
+    int i = base + threadIdx.x;
+    int v = (i < n) ? counts[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+      int add = (threadIdx.x >= off) ? buf[threadIdx.x - off] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < n) ptr[i] = carry + buf[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == kBlock - 1) carry += buf[kBlock - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ptr[n] = carry;
+}
+
+template <class T>
+__global__ void k_fill_transpose(const int* row_ptr, const int* col_idx, const T* val, long long m,
+                                 int* cursor, int* t_idx, T* t_val) {
+  long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (i >= m) return;
+  for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+    int c = col_idx[k];
+    int pos = atomicAdd(&cursor[c], 1);
+    t_idx[pos] = (int)i;
+    t_val[pos] = val[k];
+  }
+}
+
+// Sort each row of the transpose by column (original row) index so that the
+// summation order of every A^T product is fixed.
+template <class T>
+__global__ void k_sort_segments(const int* ptr, long long n, int* idx, T* val) {
+  long long j = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (j >= n) return;
+  int b = ptr[j], e = ptr[j + 1];
+  for (int a = b + 1; a < e; ++a) {
+    int key = idx[a];
+    T v = val[a];
+    int p = a - 1;
+    while (p >= b && idx[p] > key) {
+      idx[p + 1] = idx[p];
+      val[p + 1] = val[p];
+      --p;
+    }
+    idx[p + 1] = key;
+    val[p + 1] = v;
+  }
+}
+
+template <class T>
+void launch_csr_transpose(const int* row_ptr, const int* col_idx, const T* val, long long m,
+                          long long n, long long nnz, int* t_ptr, int* t_idx, T* t_val,
+                          int* scratch_n, hipStream_t st) {
+  APL_HIP(hipMemsetAsync(scratch_n, 0, sizeof(int) * n, st));
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_count_cols, dim3(ceil_div(nnz, kBlock)), dim3(kBlock), 0, st, col_idx,
+                       nnz, scratch_n);
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kBlock), 0, st, scratch_n, (int)n, t_ptr);
+  APL_HIP(hipMemcpyAsync(scratch_n, t_ptr, sizeof(int) * n, hipMemcpyDeviceToDevice, st));
+  if (m > 0)
+    hipLaunchKernelGGL(k_fill_transpose<T>, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, st, row_ptr,
+                       col_idx, val, m, scratch_n, t_idx, t_val);
+  if (n > 0)
+    hipLaunchKernelGGL(k_sort_segments<T>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, st, t_ptr, n,
+                       t_idx, t_val);
+}
+template void launch_csr_transpose<float>(const int*, const int*, const float*, long long,
+                                          long long, long long, int*, int*, float*, int*,
+                                          hipStream_t);
+template void launch_csr_transpose<double>(const int*, const int*, const double*, long long,
+                                           long long, long long, int*, int*, double*, int*,
+                                           hipStream_t);
+
+// ---------------------------------------------------------------- sketch, CSR A
+// Y(:, j) = sum over the non-zeros (i, a) of column j of A of S(:, i) a.
+// One wave per 64 columns; lane l owns column j0 + l and accumulates it in a
+// private LDS column of s doubles, walking the sorted transpose row in order,
+// so the sum order is fixed.
+template <class T>
+__global__ void __launch_bounds__(kWave) k_sketch_csr(const int* t_ptr, const int* t_idx,
+                                                      const T* t_val, long long n, int s, int xi,
+                                                      const uint16_t* rows, const uint8_t* negmask,
+                                                      double scale, double* Y) {
+  extern __shared__ double lds[];  // s x 64
+  const int l = threadIdx.x;
+  const long long j = blockIdx.x * (long long)kWave + l;
+  for (int h = 0; h < s; ++h) lds[h * kWave + l] = 0.0;
+  if (j < n) {
+    for (int k = t_ptr[j]; k < t_ptr[j + 1]; ++k) {
+      const long long i = t_idx[k];
+      const double a = (double)t_val[k] * scale;
+      const unsigned neg = negmask[i];
+      for (int t = 0; t < xi; ++t) {
+        const int h = rows[i * xi + t];
+        lds[h * kWave + l] += ((neg >> t) & 1u) ? -a : a;
+      }
+    }
+    for (int h = 0; h < s; ++h) Y[(long long)h * n + j] = lds[h * kWave + l];
+  }
+}
+
+template <class T>
+void launch_sketch_csr(const int* t_ptr, const int* t_idx, const T* t_val, long long n, int s,
+                       int xi, const uint16_t* rows, const uint8_t* negmask, double* Y,
+                       hipStream_t st) {
+  size_t lds = sizeof(double) * s * kWave;
+  APL_REQUIRE(lds <= 160 * 1024, "sketch dimension too large for the LDS strip");
+  APL_HIP(hipFuncSetAttribute((const void*)k_sketch_csr<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_sketch_csr<T>, dim3(ceil_div(n, kWave)), dim3(kWave), lds, st, t_ptr, t_idx,
+                     t_val, n, s, xi, rows, negmask, 1.0 / sqrt((double)xi), Y);
+}
+template void launch_sketch_csr<float>(const int*, const int*, const float*, long long, int, int,
+                                       const uint16_t*, const uint8_t*, double*, hipStream_t);
+template void launch_sketch_csr<double>(const int*, const int*, const double*, long long, int, int,
+                                        const uint16_t*, const uint8_t*, double*, hipStream_t);
+
+// ---------------------------------------------------------------- sketch, dense A
+// Workgroup (strip, chunk) covers columns [64 strip, 64 strip + 64) and a chunk
+// of rows.  The s x 64 strip of Y lives in LDS (FP64).  Wave w owns the Y rows
+// h with h % 4 == w: every wave walks all rows of the chunk in order and adds
+// only its own contributions, so each LDS cell has a single writer and a fixed
+// summation order.  The chunk's strip is written to a partial buffer that a
+// second kernel sums over chunks in order.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_sketch_dense(const T* A, long long m, long long n,
+                                                         long long ld, int s, int xi,
+                                                         const uint16_t* rows,
+                                                         const uint8_t* negmask, double scale,
+                                                         long long rows_per_chunk, double* part) {
+  extern __shared__ double lds[];  // s x 64
+  const int l = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const long long j = blockIdx.x * (long long)kWave + l;
+  const long long i0 = blockIdx.y * rows_per_chunk;
+  const long long i1 = min(m, i0 + rows_per_chunk);
+  for (int h = threadIdx.x; h < s * kWave; h += kBlock) lds[h] = 0.0;
+  __syncthreads();
+  const bool col_ok = j < n;
+  for (long long i = i0; i < i1; ++i) {
+    const double a = col_ok ? (double)A[i * ld + j] * scale : 0.0;
+    const unsigned neg = negmask[i];
+    for (int t = 0; t < xi; ++t) {
+      const int h = rows[i * xi + t];
+      if ((h & 3) == w) lds[h * kWave + l] += ((neg >> t) & 1u) ? -a : a;
+    }
+  }
+  __syncthreads();
+  if (col_ok) {
+    double* out = part + (long long)blockIdx.y * s * n;
+    for (int h = w; h < s; h += kBlock / kWave) out[(long long)h * n + j] = lds[h * kWave + l];
+  }
+}
+
+__global__ void k_sum_chunks(const double* part, long long count, int chunks, double* Y) {
+  long long e = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (e >= count) return;
+  double acc = 0.0;
+  for (int c = 0; c < chunks; ++c) acc += part[(long long)c * count + e];
+  Y[e] = acc;
+}
+
+int sketch_dense_chunks(long long m, long long n) {
+  long long strips = (n + kWave - 1) / kWave;
+  long long want = (2048 + strips - 1) / strips;
+  long long maxc = (m + 15) / 16;
+  long long c = want < maxc ? want : maxc;
+  return (int)(c < 1 ? 1 : c);
+}
+
+template <class T>
+void launch_sketch_dense(const T* A, long long m, long long n, long long ld, int s, int xi,
+                         const uint16_t* rows, const uint8_t* negmask, double* Y, double* part,
+                         int chunks, hipStream_t st) {
+  long long rpc = (m + chunks - 1) / chunks;
+  size_t lds = sizeof(double) * s * kWave;
+  APL_REQUIRE(lds <= 160 * 1024, "sketch dimension too large for the LDS strip");
+  APL_HIP(hipFuncSetAttribute((const void*)k_sketch_dense<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_sketch_dense<T>, dim3(ceil_div(n, kWave), chunks), dim3(kBlock), lds, st, A,
+                     m, n, ld, s, xi, rows, negmask, 1.0 / sqrt((double)xi), rpc, part);
+  long long count = (long long)s * n;
+  hipLaunchKernelGGL(k_sum_chunks, dim3(ceil_div(count, kBlock)), dim3(kBlock), 0, st, part, count,
+                     chunks, Y);
+}
+template void launch_sketch_dense<float>(const float*, long long, long long, long long, int, int,
+                                         const uint16_t*, const uint8_t*, double*, double*, int,
+                                         hipStream_t);
+template void launch_sketch_dense<double>(const double*, long long, long long, long long, int, int,
+                                          const uint16_t*, const uint8_t*, double*, double*, int,
+                                          hipStream_t);
+
+}  // namespace aplicur

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every symbol include/aplicur.h declares
+(CPU only: no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "aplicur.h")).read()
+    return sorted(set(re.findall(r"\b(aplicur_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_entry_points():
+    syms = declared_symbols()
+    for name in ["aplicur_sketch", "aplicur_solve", "aplicur_solve_batched", "aplicur_solve_backward"]:
+        assert name in syms
+
+
+def test_library_exports_all_declared_symbols():
+    from paper_2604_05065_amd import _lib
+    lib = _lib.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert set(_lib.EXPORTS) == set(declared_symbols())
+
+
+def test_struct_layouts_match_header():
+    from paper_2604_05065_amd import _lib
+    # sizes fixed by the header's field lists (natural alignment, x86-64)
+    assert ctypes.sizeof(_lib.Mat) == 4 + 4 + 8 * 4 + 8 * 3
+    assert ctypes.sizeof(_lib.Opts) == 8 + 8 + 8 * 6 + 4 * 5 + 4 * 7 + 0
+    assert ctypes.sizeof(_lib.Info) == 4 * 6 + 8 * 7
+
+
+def test_defaults_and_errors_without_gpu():
+    from paper_2604_05065_amd import _lib
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.aplicur_opts_default(ctypes.byref(o))
+    assert (o.block, o.r_probes, o.nu_prec, o.nu_lsqr, o.eps_lsqr, o.tol_ne, o.precond) == \
+        (20, 10, 10.0, 100.0, 1e-10, 1e-8, 1)
+    # argument validation happens before any device work
+    m = _lib.Mat(_lib.DENSE, _lib.F64, 10, 20, 20, 0, None, None, None)
+    ctx = ctypes.c_void_p()
+    assert lib.aplicur_sketch(ctypes.byref(m), ctypes.byref(o), None, ctypes.byref(ctx)) == _lib.E_INVALID
+    assert b"null" in lib.aplicur_last_error()
+    m.val = 1  # non-null but mu = 0 with m < n is rejected before any device access
+    assert lib.aplicur_sketch(ctypes.byref(m), ctypes.byref(o), None, ctypes.byref(ctx)) == _lib.E_INVALID
+    assert b"m >= n" in lib.aplicur_last_error()
+    assert lib.aplicur_ctx_query(None, 1, None, 0) == _lib.E_INVALID

@@ -1,0 +1,251 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: FP64 element-wise results 1e-10 relative to the operand norms
+(the stated FP64 bar); solutions within the conditioning floor of the
+normal-equation residual they reach (parity tolerances);
+integer / index results bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from oracle import rng as orng
+from oracle.aplicur import Options, Trace, aplicur, lsqr_plain, ne_residual
+from oracle.cur import augment_cur, core_and_residual, rho_estimate
+from oracle.dense import solve_dense_qr
+from oracle.lsqr import plsqr_phase
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV, dtype=dtype)
+
+
+def _dense(m, n, seed, decades=3.0):
+    r = np.random.default_rng(seed)
+    sigma = 10.0 ** (-decades * np.arange(n) / max(n - 1, 1))
+    return synth.dense_svd(r, m, n, sigma)
+
+
+def _csr(m, n, per_row, seed, decades=2.0):
+    return synth.sparse_scaled(np.random.default_rng(seed), m, n, per_row, decades)
+
+
+def _gpu_csr(A, dtype=torch.float64):
+    import paper_2604_05065_amd as ap
+    return ap.CSRMatrix.from_scipy(A, device=DEV, dtype=dtype)
+
+
+# ----------------------------------------------------------------- sketch
+@pytest.mark.parametrize("kind,m,n,block", [("dense", 300, 37, 6), ("dense", 1000, 130, 20),
+                                             ("csr", 2000, 300, 10), ("csr", 513, 64, 3)])
+def test_sketch_matches_oracle(lib, kind, m, n, block):
+    seed = 11
+    if kind == "dense":
+        A = _dense(m, n, 1)
+        Ag = _t(A)
+    else:
+        A = _csr(m, n, 5, 2)
+        Ag = _gpu_csr(A)
+    with lib.Context(Ag, mu=1e-4, block=block, seed=seed, max_outer=1) as ctx:
+        sz = ctx.sizes()
+        s = sz["s"]
+        assert s == min(m, math.ceil(1.1 * block))
+        rows, signs, xi = orng.sparse_sign(seed, s, m)
+        assert sz["xi"] == xi
+        np.testing.assert_array_equal(ctx.query(2).reshape(m, xi), rows)       # bit-exact
+        np.testing.assert_array_equal(ctx.query(3).reshape(m, xi), signs)
+        Y = ctx.query(1).reshape(s, n)
+        Yref = orng.sparse_sign_matrix(seed, s, m) @ (A.toarray() if sp.issparse(A) else A)
+        assert np.abs(Y - Yref).max() <= 1e-13 * np.abs(Yref).max()
+        W = ctx.query(4).reshape(10, n).T
+        np.testing.assert_allclose(W, orng.gaussian_probes(seed, n, 10), rtol=1e-14, atol=1e-14)
+
+
+# ----------------------------------------------------------------- products
+@pytest.mark.parametrize("kind,dtype", [("dense", torch.float64), ("dense", torch.float32),
+                                        ("csr", torch.float64), ("csr", torch.float32)])
+@pytest.mark.parametrize("m,n", [(1, 1), (77, 5), (4099, 257), (20000, 700)])
+def test_matvec_matches_numpy(lib, kind, dtype, m, n):
+    r = np.random.default_rng(m + n)
+    if kind == "dense":
+        A = r.standard_normal((m, n))
+        A = A.astype(np.float32).astype(np.float64) if dtype == torch.float32 else A
+        Ag = _t(A, dtype)
+        An = A
+    else:
+        A = _csr(m, n, min(7, n), 3)
+        if dtype == torch.float32:
+            A.data = A.data.astype(np.float32).astype(np.float64)
+        Ag = _gpu_csr(A, dtype)
+        An = A
+    x = r.standard_normal(n)
+    u = r.standard_normal(m)
+    with lib.Context(Ag, mu=0.0 if m >= n else 1e-3, precond=False) as ctx:
+        y = ctx.matvec(_t(x)).cpu().numpy()
+        z = ctx.matvec(_t(u), trans=True).cpu().numpy()
+    yr = An @ x
+    zr = An.T @ u
+    assert np.abs(y - yr).max() <= 1e-12 * (np.abs(An).max() * np.abs(x).sum() + 1e-300)
+    assert np.abs(z - zr).max() <= 1e-12 * (np.abs(An).max() * np.abs(u).sum() + 1e-300)
+
+
+# ----------------------------------------------------------------- plain LSQR
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+@pytest.mark.parametrize("mu", [0.0, 1e-3])
+def test_plain_lsqr_iterates_match_oracle(lib, kind, mu):
+    # the first k iterations of the Golub-Kahan/LSQR recurrence, element by
+    # element, on well-conditioned inputs (kappa <= 10): there the Lanczos
+    # vectors stay orthogonal and the iterates are reproducible to rounding;
+    # past the loss of orthogonality two FP64 summation orders legitimately
+    # follow different (equally convergent) trajectories.
+    if kind == "dense":
+        A = _dense(600, 70, 4, decades=1.0)
+        Ag = _t(A)
+    else:
+        A = _csr(3000, 400, 6, 5, decades=0.5)
+        Ag = _gpu_csr(A)
+    b = np.random.default_rng(9).standard_normal(A.shape[0])
+    for k in (1, 2, 7, 25):
+        x_ref, it, _ = plsqr_phase(A, math.sqrt(mu), b, np.zeros(A.shape[1]), None, eps_lsqr=0.0,
+                                   tol_ne=0.0, max_iter=k)
+        with lib.Context(Ag, mu=mu, precond=False, max_iter=k, tol_ne=1e-300) as ctx:
+            x, info = ctx.solve(_t(b))
+        x = x.cpu().numpy()
+        assert info.iters == k
+        assert np.linalg.norm(x - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+def test_plain_lsqr_converges_to_oracle_solution(lib, kind):
+    mu = 1e-4
+    if kind == "dense":
+        A = _dense(800, 120, 6, decades=4)
+        Ag = _t(A)
+    else:
+        A = _csr(5000, 500, 8, 7, decades=3)
+        Ag = _gpu_csr(A)
+    b = np.random.default_rng(10).standard_normal(A.shape[0])
+    x, info = lib.lstsq(Ag, _t(b), mu=mu, precond=False, tol_ne=1e-10)
+    x = x.cpu().numpy()
+    eta = ne_residual(A, b, x, mu)
+    assert info.status == 0 and eta <= 1.5e-10 and info.eta <= 1e-10
+    xr = solve_dense_qr(A, b, mu)
+    assert np.linalg.norm(x - xr) <= 1e-7 * np.linalg.norm(xr)
+    # iteration counts agree up to the finite-precision trajectory spread
+    x_or, it_or = lsqr_plain(A, b, mu, tol_ne=1e-10)
+    assert 0.8 * it_or <= info.iters <= 1.25 * it_or
+
+
+# ----------------------------------------------------------------- APLICUR steps
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+def test_first_outer_step_indices_and_rho(lib, kind):
+    if kind == "dense":
+        A = _dense(500, 80, 12, decades=5)
+        Ag = _t(A)
+    else:
+        A = _csr(4000, 300, 6, 13, decades=4)
+        Ag = _gpu_csr(A)
+    block, seed, mu = 8, 21, 1e-6
+    with lib.Context(Ag, mu=mu, block=block, seed=seed, max_outer=1) as ctx:
+        ctx.solve(_t(np.ones(A.shape[0])))
+        I, J = ctx.query(6), ctx.query(5)
+        rho = ctx.query(7)
+    s = math.ceil(1.1 * block)
+    Y = orng.sparse_sign_matrix(seed, s, A.shape[0]) @ (A.toarray() if sp.issparse(A) else A)
+    Ir, Jr, _ = augment_cur(A, Y, np.zeros(0, int), np.zeros(0, int), None, None, None, block)
+    np.testing.assert_array_equal(J, Jr)
+    np.testing.assert_array_equal(I, Ir)
+    _, _, _, E_row = core_and_residual(A, Y, Ir, Jr)
+    rho_ref = rho_estimate(E_row, orng.gaussian_probes(seed, A.shape[1], 10))
+    assert abs(rho[0] - rho_ref) <= 1e-9 * rho_ref
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+def test_outer_steps_match_oracle_trace(lib, kind):
+    if kind == "dense":
+        A = _dense(400, 60, 14, decades=6)
+        Ag = _t(A)
+    else:
+        A = _csr(3000, 200, 6, 15, decades=5)
+        Ag = _gpu_csr(A)
+    block, seed, mu, steps = 5, 3, 1e-5, 4
+    b = np.random.default_rng(1).standard_normal(A.shape[0])
+    tr = Trace()
+    # the oracle trace of the first `steps` outer steps
+    aplicur(A, b, mu, Options(block=block, seed=seed, tol_ne=1e-30, max_rank=block * steps), tr)
+    with lib.Context(Ag, mu=mu, block=block, seed=seed, max_outer=steps, tol_ne=1e-30,
+                     max_rank=block * steps) as ctx:
+        ctx.solve(_t(b))
+        ranks, rhos, reb = ctx.query(8), ctx.query(7), ctx.query(9)
+        I, J = ctx.query(6), ctx.query(5)
+        sig = ctx.query(11)
+    n_or = len(tr.ranks)
+    assert list(ranks[:n_or]) == tr.ranks[:len(ranks)]
+    np.testing.assert_allclose(rhos[:n_or], tr.rhos[:len(rhos)], rtol=1e-7)
+    assert list(reb[:n_or]) == [int(v) for v in tr.rebuild[:len(reb)]]
+    np.testing.assert_array_equal(J, tr.J[:len(J)])
+    np.testing.assert_array_equal(I, tr.I[:len(I)])
+    assert len(sig) == ranks[-1]
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+@pytest.mark.parametrize("mu", [1e-6, 1e-3])
+def test_aplicur_solution_matches_oracle(lib, kind, mu):
+    if kind == "dense":
+        A = _dense(700, 90, 16, decades=6)
+        Ag = _t(A)
+    else:
+        A = _csr(6000, 400, 8, 17, decades=4)
+        Ag = _gpu_csr(A)
+    b = np.random.default_rng(2).standard_normal(A.shape[0])
+    block, tol = 10, 1e-10
+    x, info = lib.lstsq(Ag, _t(b), mu=mu, block=block, tol_ne=tol)
+    x = x.cpu().numpy()
+    eta = ne_residual(A, b, x, mu)
+    assert info.status == 0 and eta <= 1.5 * tol
+    x_or = aplicur(A, b, mu, Options(block=block, tol_ne=tol))
+    xr = solve_dense_qr(A, b, mu)
+    assert np.linalg.norm(x - xr) <= 1e-6 * np.linalg.norm(xr)
+    assert np.linalg.norm(x - x_or) <= 2e-6 * np.linalg.norm(xr)
+
+
+def test_aplicur_workload1_reduced(lib):
+    w = synth.workload(1, 0.5)  # 1000 x 100, mu = 0, kappa = 1e6
+    x, info = lib.lstsq(_t(w.A), _t(w.B), mu=0.0, block=w.block, tol_ne=w.tol)
+    x = x.cpu().numpy()
+    eta = ne_residual(w.A, w.B, x, 0.0)
+    assert eta <= 1.5 * w.tol
+    tr = Trace()
+    aplicur(w.A, w.B, 0.0, Options(block=w.block, tol_ne=w.tol), tr)
+    assert info.rank == tr.ranks[-1]
+
+
+def test_multi_rhs_is_columnwise(lib):
+    A = _dense(300, 40, 18, decades=4)
+    B = np.random.default_rng(4).standard_normal((300, 3))
+    X, info = lib.lstsq(_t(A), _t(B), mu=1e-5, block=6, tol_ne=1e-10)
+    X = X.cpu().numpy()
+    for k in range(3):
+        xk, _ = lib.lstsq(_t(A), _t(B[:, k]), mu=1e-5, block=6, tol_ne=1e-10)
+        np.testing.assert_allclose(X[:, k], xk.cpu().numpy(), rtol=0, atol=1e-13 * np.abs(X[:, k]).max())
+
+
+def test_zero_rhs_and_warm_start(lib):
+    A = _dense(200, 30, 19)
+    Ag = _t(A)
+    x, info = lib.lstsq(Ag, _t(np.zeros(200)), mu=1e-3, block=4)
+    assert float(x.abs().max()) == 0.0 and info.eta == 0.0
+    b = np.random.default_rng(5).standard_normal(200)
+    xr = solve_dense_qr(A, b, 1e-3)
+    with lib.Context(Ag, mu=1e-3, block=4, tol_ne=1e-12) as ctx:
+        x0 = _t(xr)
+        x1, info = ctx.solve(_t(b), X0=x0)
+        assert info.iters <= 5
+        assert np.linalg.norm(x1.cpu().numpy() - xr) <= 1e-9 * np.linalg.norm(xr)
