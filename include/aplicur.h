@@ -161,6 +161,14 @@ int aplicur_solve_backward(aplicur_ctx* ctx, const double* X, int64_t ldx, const
  * FP64 with the same product kernels the LSQR iteration uses.             */
 int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, void* stream);
 
+/* Times `reps` back-to-back launches of the product kernel(s) of
+ * aplicur_matvec (the same kernels the LSQR iteration uses) with HIP events
+ * recorded on `stream`, after one warm-up launch; *us_per_launch (host)
+ * receives the mean duration in microseconds.  y is scratch (its final
+ * contents are unspecified).  For measurement only.                        */
+int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* stream,
+                         double* us_per_launch);
+
 /* Read internal state back to host memory (tests and diagnostics).
  * what: 1 sketch Y (s x n row-major doubles), 2 sketch rows (m x xi int32),
  * 3 sketch signs (m x xi int32, +-1), 4 probes (n x r doubles, column-major),

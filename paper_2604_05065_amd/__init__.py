@@ -2,11 +2,10 @@
 
 The solver lives in libaplicur.so (hand-written gfx950 HIP kernels plus a
 C++ driver, see include/aplicur.h); this package is its Python binding.
-Importing it requires the built library -- there is no CPU fallback.
+Every entry point loads the built library and fails loudly if it is missing
+-- there is no CPU fallback.
 """
-from ._lib import AplicurError, load as _load
+from ._lib import AplicurError, load as load_library
 from .api import Context, CSRMatrix, lstsq, make_opts, sketch, solve_batched
 
-_load()
-
-__all__ = ["AplicurError", "Context", "CSRMatrix", "lstsq", "make_opts", "sketch", "solve_batched"]
+__all__ = ["AplicurError", "load_library", "Context", "CSRMatrix", "lstsq", "make_opts", "sketch", "solve_batched"]

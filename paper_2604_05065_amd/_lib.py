@@ -39,7 +39,7 @@ class Info(C.Structure):
 
 
 EXPORTS = ["aplicur_opts_default", "aplicur_sketch", "aplicur_solve", "aplicur_solve_batched",
-           "aplicur_solve_backward", "aplicur_matvec", "aplicur_ctx_query", "aplicur_ctx_destroy",
+           "aplicur_solve_backward", "aplicur_matvec", "aplicur_time_product", "aplicur_ctx_query", "aplicur_ctx_destroy",
            "aplicur_last_error", "aplicur_version"]
 
 _lib = None
@@ -68,6 +68,8 @@ def load():
     lib.aplicur_solve_backward.restype = C.c_int
     lib.aplicur_matvec.argtypes = [vp, i32, dp, dp, vp]
     lib.aplicur_matvec.restype = C.c_int
+    lib.aplicur_time_product.argtypes = [vp, i32, dp, dp, i32, vp, C.POINTER(C.c_double)]
+    lib.aplicur_time_product.restype = C.c_int
     lib.aplicur_ctx_query.argtypes = [vp, i32, vp, C.c_size_t]
     lib.aplicur_ctx_query.restype = i64
     lib.aplicur_ctx_destroy.argtypes = [vp]

@@ -149,6 +149,15 @@ class Context:
         L.check(self.lib.aplicur_matvec(self.ptr, int(bool(trans)), x.data_ptr(), y.data_ptr(), _stream()))
         return y
 
+    def time_product(self, x, trans=False, reps=100):
+        """Mean duration (us) of one launch of the A (or A^T) product kernel."""
+        x = x.to(torch.float64).contiguous()
+        y = torch.empty(self.n if trans else self.m, dtype=torch.float64, device=x.device)
+        us = C.c_double()
+        L.check(self.lib.aplicur_time_product(self.ptr, int(bool(trans)), x.data_ptr(), y.data_ptr(), int(reps),
+                                              _stream(), C.byref(us)))
+        return us.value
+
     def query(self, what):
         """Read internal state (see aplicur_ctx_query in include/aplicur.h)."""
         kinds = {1: np.float64, 2: np.int32, 3: np.int32, 4: np.float64, 5: np.int32, 6: np.int32,

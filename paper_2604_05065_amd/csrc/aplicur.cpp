@@ -93,10 +93,11 @@ struct Ctx {
   std::vector<double> p_sigma_host;
   // LSQR vectors and state
   double *u_top = nullptr, *u_bot = nullptr, *v = nullptr, *w = nullptr, *y = nullptr, *t = nullptr,
-         *g = nullptr, *partials = nullptr;
-  GKState* st = nullptr;
-  GKState* st_host = nullptr;  // pinned
-  GKState* st_mv = nullptr;    // pristine state of the matvec entry point
+         *g = nullptr;
+  GKWork wk{};
+  GKState* st = nullptr;       // two state slots
+  GKState* st_host = nullptr;  // pinned, two slots
+  GKState* st_mv = nullptr;    // two slots of the matvec entry point (alpha = beta = 1, delta = 0)
   unsigned* counter = nullptr;
   FactorWork fw{};
   // histories
@@ -221,18 +222,20 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
     c->y = c->arena.alloc<double>(n);
     c->t = c->arena.alloc<double>(n);
     c->g = c->arena.alloc<double>(std::max(m, n));
-    c->partials = c->arena.alloc<double>(8192);
-    c->st = c->arena.alloc<GKState>(1);
+    c->wk.alpha_part = c->arena.alloc<double>(4096);
+    c->wk.beta_part = c->arena.alloc<double>(4096);
+    c->st = c->arena.alloc<GKState>(2);
     c->counter = c->arena.alloc<unsigned>(4);
-    c->st_mv = c->arena.alloc<GKState>(1);
+    c->st_mv = c->arena.alloc<GKState>(2);
     APL_HIP(hipMemsetAsync(c->counter, 0, 4 * sizeof(unsigned), s));
-    APL_HIP(hipHostMalloc((void**)&c->st_host, sizeof(GKState), hipHostMallocDefault));
+    APL_HIP(hipHostMalloc((void**)&c->st_host, 2 * sizeof(GKState), hipHostMallocDefault));
     {
-      GKState& h = *c->st_host;
+      GKState& h = c->st_host[0];
       std::memset(&h, 0, sizeof(h));
       h.alpha = h.beta = h.pnorm = 1.0;
       h.nu = INFINITY;
-      APL_HIP(hipMemcpyAsync(c->st_mv, &h, sizeof(GKState), hipMemcpyHostToDevice, s));
+      c->st_host[1] = h;
+      APL_HIP(hipMemcpyAsync(c->st_mv, c->st_host, 2 * sizeof(GKState), hipMemcpyHostToDevice, s));
       APL_HIP(hipStreamSynchronize(s));
     }
     if (o->precond) {
@@ -317,11 +320,11 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       c->prec.c = c->pa_c;
       long long lrows = std::max(m, n);
       c->fw.lupp_rows = (int)lrows;
-      c->fw.pos = c->arena.alloc<int>(lrows);
-      c->fw.row_at = c->arena.alloc<int>(lrows);
-      c->fw.pv = c->arena.alloc<double>(1024);
-      c->fw.pp = c->arena.alloc<int>(1024);
-      c->fw.pi = c->arena.alloc<int>(1024);
+      c->fw.pos = c->arena.alloc<int>(2 * lrows);
+      c->fw.row_at = c->arena.alloc<int>(2 * lrows);
+      c->fw.pv = c->arena.alloc<double>(2048);
+      c->fw.pp = c->arena.alloc<int>(2048);
+      c->fw.pi = c->arena.alloc<int>(2048);
       c->fw.lupp_state = c->arena.alloc<int>(4);
       c->fw.counter = c->counter + 1;
       fill(c->TR, (long long)L * L, 0.0, s);
@@ -544,7 +547,7 @@ static GKVecs<double> vecs(Ctx& c) { return GKVecs<double>{c.u_top, c.u_bot, c.v
 
 static void upload_state(Ctx& c, double tol_abs, double pnorm, double eps_lsqr, double baug_eps, double nu,
                          double sigma_l, int max_iter, double delta, hipStream_t s) {
-  GKState& h = *c.st_host;
+  GKState& h = c.st_host[0];
   std::memset(&h, 0, sizeof(h));
   h.alpha = 1.0;
   h.beta = 1.0;
@@ -557,13 +560,21 @@ static void upload_state(Ctx& c, double tol_abs, double pnorm, double eps_lsqr, 
   h.delta = delta;
   h.max_iter = max_iter;
   h.init = 1;
-  APL_HIP(hipMemcpyAsync(c.st, &h, sizeof(GKState), hipMemcpyHostToDevice, s));
+  c.st_host[1] = h;
+  APL_HIP(hipMemcpyAsync(c.st, c.st_host, 2 * sizeof(GKState), hipMemcpyHostToDevice, s));
 }
 
+// Both slots; the returned state is slot 0 with the stop flag / reason of
+// either slot.
 static GKState read_state(Ctx& c, hipStream_t s) {
-  APL_HIP(hipMemcpyAsync(c.st_host, c.st, sizeof(GKState), hipMemcpyDeviceToHost, s));
+  APL_HIP(hipMemcpyAsync(c.st_host, c.st, 2 * sizeof(GKState), hipMemcpyDeviceToHost, s));
   APL_HIP(hipStreamSynchronize(s));
-  return *c.st_host;
+  GKState h = c.st_host[0];
+  if (!h.stop && c.st_host[1].stop) {
+    h.stop = 1;
+    h.reason = c.st_host[1].reason;
+  }
+  return h;
 }
 
 // One warm-started phase for the problem min || A_mu x - [b; bot_scale b_bot] ||.
@@ -572,14 +583,13 @@ static PhaseOut run_phase(Ctx& c, const PrecDesc* P, const double* b, const doub
                           double nu, double sigma_l, int budget, hipStream_t s) {
   upload_state(c, tol_abs, pnorm, eps_lsqr, baug_eps, nu, sigma_l, budget, c.delta, s);
   GKVecs<double> vec = vecs(c);
-  gk_phase_init<double>(c.op, P, b, b_bot, bot_scale, x_zero ? nullptr : x, vec, c.u_top, c.u_bot, c.st,
-                        c.partials, c.counter, s);
+  gk_phase_init<double>(c.op, P, b, b_bot, bot_scale, x_zero ? nullptr : x, vec, c.u_top, c.u_bot, c.st, c.wk, s);
   int chunk = 8;
   long long launched = 0;
   APL_HIP(hipGetLastError());
   GKState h = read_state(c, s);
   while (!h.stop) {
-    for (int i = 0; i < chunk; ++i) gk_iteration<double>(c.op, P, vec, c.st, c.partials, c.counter, s);
+    for (int i = 0; i < chunk; ++i) gk_iteration<double>(c.op, P, vec, c.st, c.wk, s);
     launched += chunk;
     APL_HIP(hipGetLastError());
     h = read_state(c, s);
@@ -596,27 +606,24 @@ static PhaseOut run_phase(Ctx& c, const PrecDesc* P, const double* b, const doub
 static double eta_of(Ctx& c, const double* b, const double* b_bot, double bot_scale, const double* x, double atb,
                      hipStream_t s) {
   if (atb == 0.0) return 0.0;
-  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 0, c.delta, s);
-  gk_phase_init<double>(c.op, nullptr, b, b_bot, bot_scale, x, vecs(c), c.u_top, c.u_bot, c.st, c.partials,
-                        c.counter, s);
+  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 1, c.delta, s);
+  gk_normal_residual(c.op, b, b_bot, bot_scale, x, vecs(c), c.st, c.wk, s);
   GKState h = read_state(c, s);
   return std::sqrt(std::max(h.h2, 0.0)) / atb;
 }
 
 static double atb_norm(Ctx& c, const double* b, hipStream_t s) {
-  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 0, 0.0, s);
-  op_atb_norm2(c.op, b, c.g, c.st, c.partials, c.counter, s);
+  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 1, 0.0, s);
+  op_atb_norm2(c.op, b, c.g, c.st, c.wk, s);
   GKState h = read_state(c, s);
   return std::sqrt(std::max(h.h2, 0.0));
 }
 
 static double vec_norm(Ctx& c, const double* b, hipStream_t s) {
-  // ||b|| through the residual kernel with x = 0 (delta = 0 so r = [b; 0])
-  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 0, 0.0, s);
-  gk_phase_init<double>(c.op, nullptr, b, nullptr, 0.0, nullptr, vecs(c), c.u_top, c.u_bot, c.st, c.partials,
-                        c.counter, s);
+  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 1, 0.0, s);
+  op_norm(c.op, b, c.u_top, c.st, c.wk, s);
   GKState h = read_state(c, s);
-  return h.beta1 > 0 ? h.beta1 : h.beta;
+  return h.beta1;
 }
 
 struct ColState {
@@ -886,10 +893,34 @@ int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, 
     APL_REQUIRE(ctx && ctx->impl && x && y, "null argument");
     Ctx& c = *ctx->impl;
     hipStream_t s = (hipStream_t)stream;
-    APL_HIP(hipMemcpyAsync(c.st, c.st_mv, sizeof(GKState), hipMemcpyDeviceToDevice, s));
     if (!trans) fill(y, c.m, 0.0, s);
-    op_matvec(c.op, trans, x, y, c.st, c.partials, c.counter, s);
+    op_matvec(c.op, trans, x, y, c.st_mv, c.wk, s);
     APL_HIP(hipGetLastError());
+    return APLICUR_OK;
+  });
+}
+
+int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* stream,
+                         double* us_per_launch) {
+  return guarded([&]() {
+    APL_REQUIRE(ctx && ctx->impl && x && y && us_per_launch && reps >= 1, "bad argument");
+    Ctx& c = *ctx->impl;
+    hipStream_t s = (hipStream_t)stream;
+    fill(y, trans ? c.n : c.m, 0.0, s);
+    op_matvec(c.op, trans, x, y, c.st_mv, c.wk, s);  // warm-up launch
+    hipEvent_t e0, e1;
+    APL_HIP(hipEventCreate(&e0));
+    APL_HIP(hipEventCreate(&e1));
+    APL_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) op_matvec(c.op, trans, x, y, c.st_mv, c.wk, s);
+    APL_HIP(hipEventRecord(e1, s));
+    APL_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    APL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    APL_HIP(hipGetLastError());
+    *us_per_launch = 1e3 * (double)ms / reps;
     return APLICUR_OK;
   });
 }

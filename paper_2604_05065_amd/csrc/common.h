@@ -87,6 +87,30 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
+// Sum of partials[0..count), computed redundantly by every workgroup that
+// needs it, in a fixed order (thread-strided sums, shuffle tree, waves in
+// order), so every workgroup obtains the bitwise-identical value.  Returned
+// to all threads of the workgroup.  Reading partials written by the previous
+// kernel needs no fence: the kernel boundary orders them.
+__device__ __forceinline__ double reduce_all(const double* partials, int count) {
+  __shared__ double red[kBlock / kWave];
+  __shared__ double result;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += kBlock) v += partials[i];
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) s += red[i];
+    result = s;
+  }
+  __syncthreads();
+  return result;
+}
+
 // "Last workgroup done" ticket: every workgroup calls this once after writing
 // its partial result; returns true in exactly one workgroup, after all others
 // have published their partials.  The ticket counter is reset by that block.

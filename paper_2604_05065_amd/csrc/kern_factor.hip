@@ -9,16 +9,16 @@ namespace aplicur {
 // ============================================================== LUPP pivots
 // Partial-pivoting elimination on a column-major r x c matrix X, keeping the
 // LAPACK row order for ties: pos[i] is the current position of original row
-// i (rows are not moved; only the bookkeeping is), row_at[p] its inverse.
-// The pivot of column q is the remaining row with the largest |X(i,q)|, the
-// smallest position winning ties (idamax).  One launch per column: it
-// eliminates column q with its pivot and finds the pivot of column q + 1;
-// its last workgroup does the swap bookkeeping for the next launch.
+// i and row_at[p] its inverse (rows are not moved; only this bookkeeping
+// is).  The pivot of column q is the remaining row with the largest
+// |X(i,q)|, the smallest position winning ties (as idamax does).  One launch
+// per column: every workgroup reduces the previous launch's per-workgroup
+// argmax candidates itself (fixed order, no fences), applies the row swap of
+// step q to double-buffered copies of pos/row_at, eliminates column q and
+// proposes the pivot candidates of column q + 1.
 struct LuppState {
-  int p;         // pivot row (original index) of the current column
-  int keff;      // number of pivots found (== k when not exhausted)
-  int stop;
-  int pad;
+  int keff;  // pivots found so far
+  int stop;  // set when done or when a pivot column is zero (exhausted)
 };
 
 __device__ __forceinline__ bool better(double va, int pa, double vb, int pb) {
@@ -49,41 +49,23 @@ __device__ void block_argmax(double& v, int& p, int& idx) {
   __syncthreads();
 }
 
-// Last workgroup: global argmax over the partials, then the swap
-// bookkeeping of step `q` (the step whose pivot this is).
-__device__ void lupp_select(int q, int k, int nparts, const double* pv, const int* pp, const int* pi,
-                            int* pos, int* row_at, int* piv, LuppState* ls) {
-  double v = -1.0;
-  int p = INT_MAX, idx = -1;
-  for (int t = threadIdx.x; t < nparts; t += kBlock)
-    if (better(pv[t], pp[t], v, p)) {
-      v = pv[t];
-      p = pp[t];
-      idx = pi[t];
+// Every workgroup: the global best of the previous launch's candidates.
+__device__ void argmax_all(const double* pv, const int* pp, const int* pi, int count, double& v, int& idx) {
+  double bv = -1.0;
+  int bp = INT_MAX, bi = -1;
+  for (int t = threadIdx.x; t < count; t += kBlock)
+    if (better(pv[t], pp[t], bv, bp)) {
+      bv = pv[t];
+      bp = pp[t];
+      bi = pi[t];
     }
-  block_argmax(v, p, idx);
-  if (threadIdx.x == 0) {
-    if (!(v > 0.0) || idx < 0) {  // zero (or NaN) column: residual exhausted
-      ls->keff = q;
-      ls->stop = 1;
-    } else {
-      const int o = row_at[q];
-      const int pp_old = pos[idx];
-      row_at[pp_old] = o;
-      pos[o] = pp_old;
-      row_at[q] = idx;
-      pos[idx] = q;
-      piv[q] = idx;
-      ls->p = idx;
-      ls->keff = q + 1;
-      if (q + 1 >= k) ls->stop = 1;
-    }
-  }
+  block_argmax(bv, bp, bi);
+  v = bv;
+  idx = bi;
 }
 
-__global__ void __launch_bounds__(kBlock) k_lupp_init(const double* X, int r, long long ld, int k,
-                                                      int* pos, int* row_at, int* piv, LuppState* ls,
-                                                      double* pv, int* pp, int* pi, unsigned* counter) {
+__global__ void __launch_bounds__(kBlock) k_lupp_init(const double* X, int r, int k, int* pos, int* row_at,
+                                                      LuppState* ls, double* pv, int* pp, int* pi) {
   double v = -1.0;
   int p = INT_MAX, idx = -1;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < r; i += gridDim.x * kBlock) {
@@ -102,45 +84,60 @@ __global__ void __launch_bounds__(kBlock) k_lupp_init(const double* X, int r, lo
     pp[blockIdx.x] = p;
     pi[blockIdx.x] = idx;
     if (blockIdx.x == 0) {
-      ls->stop = (k <= 0);
       ls->keff = 0;
+      ls->stop = (k <= 0);
     }
   }
-  if (last_block(counter, gridDim.x)) lupp_select(0, k, gridDim.x, pv, pp, pi, pos, row_at, piv, ls);
 }
 
-__global__ void __launch_bounds__(kBlock) k_lupp_step(double* X, int r, int c, long long ld, int q, int k,
-                                                      int* pos, int* row_at, int* piv, LuppState* ls,
-                                                      double* pv, int* pp, int* pi, unsigned* counter) {
+__global__ void __launch_bounds__(kBlock)
+    k_lupp_step(double* X, int r, int c, long long ld, int q, int k, const int* pos_cur, const int* row_cur,
+                int* pos_nxt, int* row_nxt, int* piv, LuppState* ls, const double* pv_in, const int* pp_in,
+                const int* pi_in, double* pv_out, int* pp_out, int* pi_out) {
   if (ls->stop) return;
-  const int p = ls->p;
+  double vmax;
+  int p;
+  argmax_all(pv_in, pp_in, pi_in, gridDim.x, vmax, p);
+  if (!(vmax > 0.0) || p < 0) {  // zero (or NaN) pivot column: residual exhausted
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ls->keff = q;
+      ls->stop = 1;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    piv[q] = p;
+    ls->keff = q + 1;
+    if (q + 1 >= k || q + 1 >= c) ls->stop = 1;
+  }
+  if (q + 1 >= k || q + 1 >= c) return;  // last pivot found: no elimination needed
+  const int o = row_cur[q];               // row currently at position q
+  const int pp = pos_cur[p];              // current position of the pivot row
   const double piv_val = X[p + q * ld];
-  const bool next = (q + 1 < k) && (q + 1 < c);
   double v = -1.0;
   int bp = INT_MAX, idx = -1;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < r; i += gridDim.x * kBlock) {
-    const int pi_ = pos[i];
-    if (pi_ <= q) continue;  // pivot rows (positions 0..q) are not updated
+    const int pi_old = pos_cur[i];
+    const int pn = (i == p) ? q : ((i == o) ? pp : pi_old);
+    pos_nxt[i] = pn;
+    row_nxt[i] = (i == q) ? p : ((i == pp) ? o : row_cur[i]);
+    if (pn <= q) continue;  // pivot rows (positions 0..q) are not updated
     const double l = X[i + q * ld] / piv_val;
     X[i + q * ld] = l;
     for (int j = q + 1; j < c; ++j) X[i + j * ld] -= l * X[p + j * ld];
-    if (next) {
-      const double a = fabs(X[i + (q + 1) * ld]);
-      if (better(a, pi_, v, bp)) {
-        v = a;
-        bp = pi_;
-        idx = i;
-      }
+    const double a = fabs(X[i + (q + 1) * ld]);
+    if (better(a, pn, v, bp)) {
+      v = a;
+      bp = pn;
+      idx = i;
     }
   }
-  if (!next) return;
   block_argmax(v, bp, idx);
   if (threadIdx.x == 0) {
-    pv[blockIdx.x] = v;
-    pp[blockIdx.x] = bp;
-    pi[blockIdx.x] = idx;
+    pv_out[blockIdx.x] = v;
+    pp_out[blockIdx.x] = bp;
+    pi_out[blockIdx.x] = idx;
   }
-  if (last_block(counter, gridDim.x)) lupp_select(q + 1, k, gridDim.x, pv, pp, pi, pos, row_at, piv, ls);
 }
 
 void lupp_pivots(double* X, int r, int c, long long ld, int k, int* piv, FactorWork& fw, hipStream_t s) {
@@ -148,11 +145,18 @@ void lupp_pivots(double* X, int r, int c, long long ld, int k, int* piv, FactorW
   int grid = (r + kBlock - 1) / kBlock;
   if (grid > 1024) grid = 1024;
   LuppState* ls = (LuppState*)fw.lupp_state;
-  hipLaunchKernelGGL(k_lupp_init, dim3(grid), dim3(kBlock), 0, s, X, r, ld, k, fw.pos, fw.row_at, piv, ls,
-                     fw.pv, fw.pp, fw.pi, fw.counter);
-  for (int q = 0; q + 1 < k; ++q)
-    hipLaunchKernelGGL(k_lupp_step, dim3(grid), dim3(kBlock), 0, s, X, r, c, ld, q, k, fw.pos, fw.row_at,
-                       piv, ls, fw.pv, fw.pp, fw.pi, fw.counter);
+  // two buffers each for pos/row_at and for the candidates
+  int* pos[2] = {fw.pos, fw.pos + r};
+  int* row[2] = {fw.row_at, fw.row_at + r};
+  double* pv[2] = {fw.pv, fw.pv + 1024};
+  int* pp[2] = {fw.pp, fw.pp + 1024};
+  int* pi[2] = {fw.pi, fw.pi + 1024};
+  hipLaunchKernelGGL(k_lupp_init, dim3(grid), dim3(kBlock), 0, s, X, r, k, pos[0], row[0], ls, pv[0], pp[0], pi[0]);
+  for (int q = 0; q < k; ++q) {
+    const int a = q & 1, b = a ^ 1;
+    hipLaunchKernelGGL(k_lupp_step, dim3(grid), dim3(kBlock), 0, s, X, r, c, ld, q, k, pos[a], row[a], pos[b],
+                       row[b], piv, ls, pv[a], pp[a], pi[a], pv[b], pp[b], pi[b]);
+  }
 }
 
 int lupp_read_keff(FactorWork& fw, hipStream_t s) {

@@ -59,23 +59,33 @@ struct GKVecs {
   V *u_top, *u_bot, *v, *w, *y, *t, *g;
 };
 
+// Partial-sum buffers of the fence-free reductions (alpha: norms of v, beta:
+// norms of u) and the number of partials the last producer wrote.
+struct GKWork {
+  double* alpha_part;
+  double* beta_part;
+  unsigned alpha_count, beta_count;
+};
+
+// st points to the two state slots (see kern_gk.hip).
 template <class V>
-void gk_iteration(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, GKState* st, double* partials,
-                  unsigned* counter, hipStream_t s);
+void gk_iteration(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s);
 // Phase start: r = [b - A x; bot_scale b_bot - delta x] in FP64 (b or b_bot may be
-// null = 0; x null = 0), beta = ||r||, ||A_mu^T r||^2 -> st->h2, v = P^{-T} A_mu^T u.
+// null = 0; x null = 0), beta_1 = ||r||, v_1 = P^{-T} A_mu^T u_1 (alpha finished by
+// the first kernel of the first iteration).
 template <class V>
-void gk_phase_init(const OpDesc& A, const PrecDesc* P, const double* b, const double* b_bot,
-                   double bot_scale, const double* x, GKVecs<V> vec, double* r_top64, double* r_bot64,
-                   GKState* st, double* partials, unsigned* counter, hipStream_t s);
+void gk_phase_init(const OpDesc& A, const PrecDesc* P, const double* b, const double* b_bot, double bot_scale,
+                   const double* x, GKVecs<V> vec, double* r_top64, double* r_bot64, GKState* st, GKWork& wk,
+                   hipStream_t s);
+// Phase end: x += P^{-1} y.
 template <class V>
-void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* x, GKState* st,
-                     hipStream_t s);
-// ||A^T b||^2 -> st->h2 (and optional y = A x / A^T x products for the matvec entry point)
-void op_atb_norm2(const OpDesc& A, const double* b, double* tmp_n, GKState* st, double* partials,
-                  unsigned* counter, hipStream_t s);
-void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st,
-               double* partials, unsigned* counter, hipStream_t s);
+void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* x, GKState* st, hipStream_t s);
+// ||A_mu^T r||^2 -> st[0].h2 for r = [b - A x; bot_scale b_bot - delta x].
+void gk_normal_residual(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
+                        GKVecs<double> vec, GKState* st, GKWork& wk, hipStream_t s);
+void op_atb_norm2(const OpDesc& A, const double* b, double* tmp_n, GKState* st, GKWork& wk, hipStream_t s);
+void op_norm(const OpDesc& A, const double* b, double* tmp_m, GKState* st, GKWork& wk, hipStream_t s);
+void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s);
 template <class V>
 void fill_zero(V* p, long long n, hipStream_t s);
 

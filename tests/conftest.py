@@ -19,4 +19,5 @@ def lib():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2604_05065_amd as ap
+    ap.load_library()  # fails loudly when the HIP library is missing
     return ap
