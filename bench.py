@@ -37,8 +37,9 @@ def spmv_bytes(m, n, nnz, vbytes=8):
 
 
 def time_matvec(ctx, x, trans, reps):
-    """ms per launch of the product kernel, from HIP events recorded by the
-    library on the launch stream around `reps` back-to-back launches."""
+    """ms per launch of the A (trans=False) or A^T product kernel, from HIP
+    events recorded by the library on the launch stream around each launch,
+    with A and A^T products alternating as in the LSQR iteration."""
     return ctx.time_product(x, trans=trans, reps=reps) * 1e-3
 
 
@@ -128,7 +129,7 @@ def main():
         uv = torch.randn(m, device="cuda", dtype=torch.float64)
         reps = 200
         t_a = time_matvec(ctx, xv, False, reps)
-        t_at = time_matvec(ctx, uv, True, reps)
+        t_at = time_matvec(ctx, xv, True, reps)
     nnz = A.nnz
     bytes_a = spmv_bytes(m, n, nnz)
     bytes_at = nnz * 12 + (n + 1) * 4 + m * 8 + n * 8

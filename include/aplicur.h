@@ -161,11 +161,12 @@ int aplicur_solve_backward(aplicur_ctx* ctx, const double* X, int64_t ldx, const
  * FP64 with the same product kernels the LSQR iteration uses.             */
 int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, void* stream);
 
-/* Times `reps` back-to-back launches of the product kernel(s) of
- * aplicur_matvec (the same kernels the LSQR iteration uses) with HIP events
- * recorded on `stream`, after one warm-up launch; *us_per_launch (host)
- * receives the mean duration in microseconds.  y is scratch (its final
- * contents are unspecified).  For measurement only.                        */
+/* Measures the product kernels the LSQR iteration uses: `reps` rounds of
+ * y = A x - y followed by s = A^T y (s: library scratch), alternating as in
+ * the iteration, with a HIP event pair recorded on `stream` around every
+ * launch of the A product (trans = 0) or of the A^T product (trans = 1).
+ * x: n doubles, y: m doubles (scratch; final contents unspecified).
+ * *us_per_launch (host) receives the mean duration in microseconds.        */
 int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* stream,
                          double* us_per_launch);
 

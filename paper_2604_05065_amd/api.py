@@ -150,9 +150,12 @@ class Context:
         return y
 
     def time_product(self, x, trans=False, reps=100):
-        """Mean duration (us) of one launch of the A (or A^T) product kernel."""
+        """Mean duration (us) of one launch of the A (or A^T) product kernel,
+        A and A^T products alternating; x has n entries."""
         x = x.to(torch.float64).contiguous()
-        y = torch.empty(self.n if trans else self.m, dtype=torch.float64, device=x.device)
+        if x.numel() != self.n:
+            raise ValueError("x must have n entries")
+        y = torch.empty(self.m, dtype=torch.float64, device=x.device)
         us = C.c_double()
         L.check(self.lib.aplicur_time_product(self.ptr, int(bool(trans)), x.data_ptr(), y.data_ptr(), int(reps),
                                               _stream(), C.byref(us)))

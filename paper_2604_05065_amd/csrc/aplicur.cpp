@@ -87,6 +87,8 @@ struct Ctx {
   double *Mx = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
          *pa_part = nullptr, *pa_c = nullptr;
   unsigned long long* offmax = nullptr;
+  double* splitk = nullptr;
+  size_t splitk_count = 0;
   PrecDesc prec{};
   bool have_prec = false;
   double p_target = 0.0, p_pnorm = 1.0, p_sigma_l = 0.0;
@@ -122,12 +124,49 @@ static int group_for(double avg) {
 
 static void set_stream(Ctx& c, hipStream_t s) { APL_BLAS(rocblas_set_stream(c.blas, s)); }
 
+// Split-K scratch for tall-skinny C = A^T B products (inner dimension m or n
+// of A, only a few columns): rocBLAS tiles the output only, so these run on
+// a handful of workgroups; here the inner dimension is cut into chunks run
+// as one strided-batched GEMM and the chunk results are summed in order.
+static double* splitk_ws(Ctx& c, size_t count);
+
 static void gemm(Ctx& c, rocblas_operation ta, rocblas_operation tb, long long m, long long n, long long k,
                  double alpha, const double* A, long long lda, const double* B, long long ldb, double beta,
                  double* Cm, long long ldc) {
   if (m <= 0 || n <= 0) return;
+  const long long mn = m * n;
+  if (ta == rocblas_operation_transpose && tb == rocblas_operation_none && k >= 16384 && mn <= (1LL << 21)) {
+    long long P = std::min<long long>(64, k / 4096);
+    P = std::min<long long>(P, std::max<long long>(2, (8LL << 20) / mn));
+    if (P >= 2) {
+      const long long kc = (k + P - 1) / P;
+      const long long full = k / kc;                 // chunks of exactly kc rows
+      const long long rem = k - full * kc;
+      const long long nparts = full + (rem > 0 ? 1 : 0);
+      double* W = splitk_ws(c, (size_t)(nparts * mn));
+      const double one = 1.0, zero = 0.0;
+      APL_BLAS(rocblas_dgemm_strided_batched(c.blas, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)kc, &one, A,
+                                             (rocblas_int)lda, kc, B, (rocblas_int)ldb, kc, &zero, W, (rocblas_int)m, mn,
+                                             (rocblas_int)full));
+      if (rem > 0)
+        APL_BLAS(rocblas_dgemm(c.blas, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)rem, &one, A + full * kc,
+                               (rocblas_int)lda, B + full * kc, (rocblas_int)ldb, &zero, W + full * mn, (rocblas_int)m));
+      hipStream_t s;
+      APL_BLAS(rocblas_get_stream(c.blas, &s));
+      splitk_reduce(W, (int)nparts, m, n, alpha, beta, Cm, ldc, s);
+      return;
+    }
+  }
   APL_BLAS(rocblas_dgemm(c.blas, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)k, &alpha, A,
                          (rocblas_int)lda, B, (rocblas_int)ldb, &beta, Cm, (rocblas_int)ldc));
+}
+
+static double* splitk_ws(Ctx& c, size_t count) {
+  if (count > c.splitk_count) {
+    c.splitk = c.arena.alloc<double>(count);
+    c.splitk_count = count;
+  }
+  return c.splitk;
 }
 
 static int read_int(const int* dev, hipStream_t s) {
@@ -205,6 +244,13 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       op.t_ptr = tp;
       op.t_idx = ti;
       op.t_val = tv;
+      op.nnz = Am->nnz;
+      int* rbA = c->arena.alloc<int>(stream_blocks(Am->nnz) + 1);
+      int* rbT = c->arena.alloc<int>(stream_blocks(Am->nnz) + 1);
+      build_row_blocks(Am->row_ptr, m, Am->nnz, rbA, s);
+      build_row_blocks(tp, n, Am->nnz, rbT, s);
+      op.rb = rbA;
+      op.t_rb = rbT;
       op.group = group_for((double)Am->nnz / (double)m);
       op.t_group = group_for((double)Am->nnz / (double)n);
     } else {
@@ -222,8 +268,11 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
     c->y = c->arena.alloc<double>(n);
     c->t = c->arena.alloc<double>(n);
     c->g = c->arena.alloc<double>(std::max(m, n));
-    c->wk.alpha_part = c->arena.alloc<double>(4096);
-    c->wk.beta_part = c->arena.alloc<double>(4096);
+    {
+      const long long parts = 16384 + 256 + (op.csr ? stream_blocks(Am->nnz) : 0);
+      c->wk.alpha_part = c->arena.alloc<double>(parts);
+      c->wk.beta_part = c->arena.alloc<double>(parts);
+    }
     c->st = c->arena.alloc<GKState>(2);
     c->counter = c->arena.alloc<unsigned>(4);
     c->st_mv = c->arena.alloc<GKState>(2);
@@ -569,12 +618,7 @@ static void upload_state(Ctx& c, double tol_abs, double pnorm, double eps_lsqr, 
 static GKState read_state(Ctx& c, hipStream_t s) {
   APL_HIP(hipMemcpyAsync(c.st_host, c.st, 2 * sizeof(GKState), hipMemcpyDeviceToHost, s));
   APL_HIP(hipStreamSynchronize(s));
-  GKState h = c.st_host[0];
-  if (!h.stop && c.st_host[1].stop) {
-    h.stop = 1;
-    h.reason = c.st_host[1].reason;
-  }
-  return h;
+  return c.st_host[0];
 }
 
 // One warm-started phase for the problem min || A_mu x - [b; bot_scale b_bot] ||.
@@ -623,7 +667,7 @@ static double vec_norm(Ctx& c, const double* b, hipStream_t s) {
   upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 1, 0.0, s);
   op_norm(c.op, b, c.u_top, c.st, c.wk, s);
   GKState h = read_state(c, s);
-  return h.beta1;
+  return h.beta;
 }
 
 struct ColState {
@@ -906,21 +950,35 @@ int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, doubl
     APL_REQUIRE(ctx && ctx->impl && x && y && us_per_launch && reps >= 1, "bad argument");
     Ctx& c = *ctx->impl;
     hipStream_t s = (hipStream_t)stream;
-    fill(y, trans ? c.n : c.m, 0.0, s);
-    op_matvec(c.op, trans, x, y, c.st_mv, c.wk, s);  // warm-up launch
-    hipEvent_t e0, e1;
-    APL_HIP(hipEventCreate(&e0));
-    APL_HIP(hipEventCreate(&e1));
-    APL_HIP(hipEventRecord(e0, s));
-    for (int i = 0; i < reps; ++i) op_matvec(c.op, trans, x, y, c.st_mv, c.wk, s);
-    APL_HIP(hipEventRecord(e1, s));
-    APL_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    APL_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // y (m) = A x - y ; scratch (n) = A^T y, alternating as in the LSQR loop
+    fill(y, c.m, 0.0, s);
+    op_matvec(c.op, 0, x, y, c.st_mv, c.wk, s);
+    op_matvec(c.op, 1, y, c.g, c.st_mv, c.wk, s);
+    std::vector<hipEvent_t> ev(2 * (size_t)reps);
+    for (auto& e : ev) APL_HIP(hipEventCreate(&e));
+    for (int i = 0; i < reps; ++i) {
+      if (!trans) {
+        APL_HIP(hipEventRecord(ev[2 * i], s));
+        op_matvec(c.op, 0, x, y, c.st_mv, c.wk, s);
+        APL_HIP(hipEventRecord(ev[2 * i + 1], s));
+        op_matvec(c.op, 1, y, c.g, c.st_mv, c.wk, s);
+      } else {
+        op_matvec(c.op, 0, x, y, c.st_mv, c.wk, s);
+        APL_HIP(hipEventRecord(ev[2 * i], s));
+        op_matvec(c.op, 1, y, c.g, c.st_mv, c.wk, s);
+        APL_HIP(hipEventRecord(ev[2 * i + 1], s));
+      }
+    }
+    APL_HIP(hipEventSynchronize(ev.back()));
+    double tot = 0.0;
+    for (int i = 0; i < reps; ++i) {
+      float ms = 0.f;
+      APL_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      tot += ms;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
     APL_HIP(hipGetLastError());
-    *us_per_launch = 1e3 * (double)ms / reps;
+    *us_per_launch = 1e3 * tot / reps;
     return APLICUR_OK;
   });
 }

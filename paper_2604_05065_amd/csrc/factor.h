@@ -36,6 +36,8 @@ void zero_rows(double* X, long long ldx, const int* rows, int nr, int ncols, hip
 void fill(double* X, long long n, double v, hipStream_t s);
 void copy_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols, double alpha,
                 hipStream_t s);
+void splitk_reduce(const double* W, int parts, long long m, long long n, double alpha, double beta, double* C,
+                   long long ldc, hipStream_t s);
 void set_identity(double* X, long long ld, int n, hipStream_t s);
 void add_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols, hipStream_t s);
 

@@ -698,6 +698,26 @@ void add_block(const double* src, long long lds, double* dst, long long ldd, int
                      cols);
 }
 
+// C = alpha * sum_p W_p + beta * C  (W_p: m x n column-major, summed in order)
+__global__ void k_splitk_reduce(const double* W, int parts, long long m, long long n, double alpha, double beta,
+                                double* C, long long ldc) {
+  const long long mn = m * n;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < mn; e += (long long)gridDim.x * kBlock) {
+    double acc = 0.0;
+    for (int p = 0; p < parts; ++p) acc += W[(long long)p * mn + e];
+    const long long i = e % m, j = e / m;
+    double* out = C + i + j * ldc;
+    *out = beta == 0.0 ? alpha * acc : alpha * acc + beta * *out;
+  }
+}
+
+void splitk_reduce(const double* W, int parts, long long m, long long n, double alpha, double beta, double* C,
+                   long long ldc, hipStream_t s) {
+  unsigned g = ceil_div(m * n, kBlock);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(g), dim3(kBlock), 0, s, W, parts, m, n, alpha, beta, C, ldc);
+}
+
 __global__ void k_set_identity(double* X, long long ld, int n) {
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
   const int j = blockIdx.y;

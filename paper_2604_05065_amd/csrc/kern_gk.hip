@@ -6,22 +6,19 @@
 //     alpha v = A~^T u - beta  v      (backward kernel; then P^{-T})
 //     Givens rotation, y += (phi/rho) w, w = v - (theta/rho) w.
 //
-// Reductions without fences: a kernel that produces a norm writes one
-// partial sum per workgroup; every workgroup of the next (consuming) kernel
-// sums those partials itself in a fixed order, so all workgroups hold the
-// bitwise-identical scalar and take identical decisions.  The FP64 scalar
-// state lives in two slots: slot 0 is written by the kernel that finishes
-// alpha (forward kernel, or the P^{-1} kernel with a preconditioner), slot 1
-// by the backward kernel that finishes beta; a kernel never reads the slot
-// it writes.  Normalisation by 1/beta and 1/alpha is folded into the next
-// consumer; the Givens update of iteration j and the y/w update are done by
-// the first kernel of iteration j + 1, which also evaluates the stopping
-// tests of Sec. 5.3.2 and, on stopping, applies the last y update itself.
+// Reductions without fences or atomics: a kernel that produces a norm writes
+// one partial sum per workgroup (grids sized for full occupancy), and a
+// one-workgroup "finish" kernel sums them in a fixed order and updates the
+// FP64 scalar state (beta; or alpha with the Givens rotation and the
+// stopping tests of Sec. 5.3.2).  Only finish kernels write the state, so the
+// products read it without races.  Normalisation by 1/beta and 1/alpha is
+// folded into the next consumer, and the y/w update of iteration j is applied
+// by the first kernel of iteration j + 1 (or by the phase-end kernel).
 #include "kernels.h"
 
 namespace aplicur {
 
-constexpr int kMaxGrid = 1024;
+constexpr int kMaxGrid = 16384;
 
 // ---------------------------------------------------------------- scalar update
 // One LSQR scalar step on a state copy: the initial step (alpha_1, beta_1) or
@@ -101,27 +98,53 @@ __device__ void scalar_step(GKState& s, double alpha) {
   }
 }
 
-__device__ __forceinline__ bool stopped(const GKState* st) { return st[0].stop || st[1].stop; }
+__device__ __forceinline__ bool stopped(const GKState* st) { return st->stop != 0; }
 
-// Load slot `in` into LDS; when `alpha_part` is given, finish alpha from the
-// partials and take the scalar step; workgroup 0 stores the result in `out`.
-__device__ __forceinline__ void load_and_step(GKState& s, const GKState* in, GKState* out,
-                                              const double* alpha_part, int alpha_count) {
-  if (threadIdx.x == 0) s = *in;
+// ---------------------------------------------------------------- finish kernels
+// One workgroup (1024 threads): sums the partials of the producing kernel in
+// a fixed order and updates the state.
+enum FinMode { kFinBeta = 0, kFinAlpha = 1 };
+
+__global__ void __launch_bounds__(1024) k_finish(GKState* st, const double* part, int count, int mode) {
+  __shared__ double red[1024 / kWave];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += 1024) v += part[i];
+  v = wave_sum(v);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
   __syncthreads();
-  if (alpha_part) {
-    const double a2 = reduce_all(alpha_part, alpha_count);
-    if (threadIdx.x == 0) scalar_step(s, sqrt(a2));
-    __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0) *out = s;
+  if (threadIdx.x != 0) return;
+  double tot = 0.0;
+  for (int i = 0; i < 1024 / kWave; ++i) tot += red[i];
+  GKState s = *st;
+  if (s.stop) return;
+  if (mode == kFinBeta) {
+    const double b = sqrt(tot);
+    s.pending = 0;  // the forward kernel has applied the y/w update
+    s.beta = b;
+    if (!(b == b) || isinf(b)) {
+      s.stop = 1;
+      s.reason = 6;
+    } else if (b == 0.0) {
+      if (s.init) {  // zero residual at the phase start: nothing to do
+        s.beta1 = 0.0;
+        s.stop = 1;
+        s.reason = kStopExact;
+      } else {
+        scalar_step(s, 0.0);  // exact solution: last y update, then stop
+      }
+    }
+  } else {
+    scalar_step(s, sqrt(tot));
   }
+  *st = s;
 }
 
-// ---------------------------------------------------------------- CSR row dot
+// ---------------------------------------------------------------- CSR products
+// CSR row dot with G lanes (used by the residual kernel).
 template <class TA, class V, class X>
 __device__ __forceinline__ V csr_dot(const int* __restrict__ rp, const int* __restrict__ ci,
-                                     const TA* __restrict__ val, const X* __restrict__ x, long long row,
-                                     int lane, int G) {
+                                     const TA* __restrict__ val, const X* __restrict__ x, long long row, int lane,
+                                     int G) {
   V acc = 0;
   const int b = rp[row], e = rp[row + 1];
   for (int k = b + lane; k < e; k += G) acc += (V)val[k] * (V)x[ci[k]];
@@ -129,95 +152,137 @@ __device__ __forceinline__ V csr_dot(const int* __restrict__ rp, const int* __re
   return acc;
 }
 
-// Forward modes: GK_PLAIN finishes alpha and takes the scalar step (no
-// preconditioner); GK_PRE reads alpha from slot 0 (finished by the P^{-1}
-// kernel); MATVEC uses the state as given (alpha = beta = 1, delta = 0).
-enum FwdMode { kFwdPlain = 0, kFwdPre = 1, kFwdMatvec = 2 };
+// CSR-stream product (after Greathouse & Daga, SC'14): workgroup j owns the
+// rows whose first non-zero lies in [j T, (j + 1) T) (precomputed row
+// blocks rb).  The workgroup loads the products val * x[col] of all its
+// non-zeros with coalesced loads into LDS, then groups of G lanes (G chosen
+// from the rows per workgroup) sum each row from LDS in a fixed order and
+// call epi(row, dot) once per row (lane 0 of the group).  Rows whose
+// non-zeros do not fit the LDS buffer are summed straight from memory by
+// the whole workgroup.  Returns nothing; the epilogue accumulates its own
+// norm partial.
+constexpr int kStreamT = 1024;   // target non-zeros per workgroup
+constexpr int kStreamCap = 4096; // LDS products per workgroup (32 KiB)
+
+template <class V, class TA, class X, class Epi>
+__device__ __forceinline__ void csr_stream(const int* __restrict__ rb, const int* __restrict__ rp,
+                                           const int* __restrict__ ci, const TA* __restrict__ val,
+                                           const X* __restrict__ x, int blk, Epi&& epi) {
+  __shared__ V prod[kStreamCap];
+  const int r0 = rb[blk], r1 = rb[blk + 1];
+  if (r0 >= r1) return;
+  const int k0 = rp[r0], k1 = rp[r1];
+  const int cnt = k1 - k0;
+  const int rows = r1 - r0;
+  if (cnt <= kStreamCap) {
+#pragma unroll 4
+    for (int e = threadIdx.x; e < cnt; e += kBlock) prod[e] = (V)val[k0 + e] * (V)x[ci[k0 + e]];
+    __syncthreads();
+    int G = 1;
+    while (G < 64 && G * 2 * rows <= kBlock) G *= 2;
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G, ngrp = kBlock / G;
+    for (int ri = grp; ri < rows; ri += ngrp) {
+      const int r = r0 + ri;
+      const int a = rp[r] - k0, z = rp[r + 1] - k0;
+      V acc = 0;
+      for (int e = a + lane; e < z; e += G) acc += prod[e];
+      for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+      if (lane == 0) epi(r, acc);
+    }
+  } else {
+    for (int r = r0; r < r1; ++r) {
+      V acc = 0;
+      for (int k = rp[r] + threadIdx.x; k < rp[r + 1]; k += kBlock) acc += (V)val[k] * (V)x[ci[k]];
+      __shared__ double red[kBlock / kWave];
+      double v = wave_sum((double)acc);
+      __syncthreads();
+      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kBlock / kWave; ++i) t += red[i];
+        epi(r, (V)t);
+      }
+    }
+  }
+}
+
+// Row blocks of the stream product: rb[j] = first row r with rp[r] >= j T
+// (j = 0 .. nb - 1) and rb[nb] = m, nb = nnz / T + 1.
+__global__ void k_row_blocks(const int* rp, long long m, int T, int* rb, int nb) {
+  const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (r > m) return;
+  const long long hi = (long long)rp[r] / T;
+  const long long lo = (r == 0) ? 0 : (long long)rp[r - 1] / T + 1;
+  for (long long j = lo; j <= hi && j < nb; ++j) rb[j] = (int)r;
+  if (r == m) rb[nb] = (int)m;
+}
+
+int stream_blocks(long long nnz) { return (int)(nnz / kStreamT) + 1; }
+
+void build_row_blocks(const int* rp, long long m, long long nnz, int* rb, hipStream_t s) {
+  const int nb = stream_blocks(nnz);
+  hipLaunchKernelGGL(k_row_blocks, dim3(ceil_div(m + 1, kBlock)), dim3(kBlock), 0, s, rp, m, kStreamT, rb, nb);
+}
 
 // Bottom (n-length) part of the forward kernel: u_bot update and the y/w
-// update of the previous iteration (or, on stopping, the last y update).
+// update of the previous iteration.
 template <class V>
 __device__ __forceinline__ double fwd_bottom(long long j, const V* tin, V* u_bot, const V* v, V* w, V* y,
-                                             const GKState& s, V ts, V cu, bool do_pending) {
+                                             double delta, V ts, V cu, bool pend, V cy, V cw) {
   double sq = 0.0;
-  if (s.delta > 0.0) {
-    const V ub = (V)s.delta * (tin[j] * ts) - cu * u_bot[j];
+  if (delta > 0.0) {
+    const V ub = (V)delta * (tin[j] * ts) - cu * u_bot[j];
     u_bot[j] = ub;
     sq = (double)ub * (double)ub;
   }
-  if (do_pending && s.pending) {
+  if (pend) {
     const V vj = v[j] * ts;
     const V wj = w[j];
-    y[j] += (V)s.coef_y * wj;
-    w[j] = vj - (V)s.coef_w * wj;
+    y[j] += cy * wj;
+    w[j] = vj - cw * wj;
   }
   return sq;
 }
 
-template <class V>
-__device__ __forceinline__ void final_y_update(long long n, V* y, const V* w, const GKState& s, int first_block,
-                                               int nblocks) {
-  if (!s.pending) return;
-  for (long long j = (long long)(blockIdx.x - first_block) * kBlock + threadIdx.x; j < n;
-       j += (long long)nblocks * kBlock)
-    y[j] += (V)s.coef_y * w[j];
-}
-
-// u_top <- A (tin / alpha) - (alpha / beta) u_top ; u_bot <- delta tin/alpha - (alpha/beta) u_bot
-template <class TA, class V, int MODE>
+// u_top <- A (tin / alpha) - (alpha / beta) u_top ; u_bot <- delta tin/alpha - (alpha/beta) u_bot;
+// partials of ||u||^2.  `pend_ok`: apply the pending y/w update (no preconditioner).
+template <class TA, class V>
 __global__ void __launch_bounds__(kBlock)
-    k_fwd_csr(const int* __restrict__ rp, const int* __restrict__ ci, const TA* __restrict__ val, long long m,
-              long long n, const V* tin, V* u_top, V* u_bot, const V* v, V* w, V* y, GKState* st,
-              const double* alpha_part, int alpha_count, double* beta_part, int G, int row_blocks) {
-  __shared__ GKState s;
-  if (MODE != kFwdMatvec && stopped(st)) return;
-  load_and_step(s, MODE == kFwdPlain ? &st[1] : &st[0], &st[0], MODE == kFwdPlain ? alpha_part : nullptr,
-                alpha_count);
-  const bool bottom = (int)blockIdx.x >= row_blocks;
-  const int nb = gridDim.x - row_blocks;
-  if (MODE == kFwdPlain && s.stop) {
-    if (bottom) final_y_update<V>(n, y, w, s, row_blocks, nb);
-    return;
-  }
-  const V ts = (V)(1.0 / s.alpha), cu = (V)(s.alpha / s.beta);
+    k_fwd_csr(const int* __restrict__ rb, const int* __restrict__ rp, const int* __restrict__ ci,
+              const TA* __restrict__ val, long long m, long long n, const V* tin, V* u_top, V* u_bot, const V* v, V* w,
+              V* y, const GKState* st, double* beta_part, int row_blocks, int pend_ok) {
+  if (stopped(st)) return;
+  const double alpha = st->alpha, beta = st->beta, delta = st->delta;
+  const V ts = (V)(1.0 / alpha), cu = (V)(alpha / beta);
   double sq = 0.0;
-  if (!bottom) {
-    const int rpb = kBlock / G, lane = threadIdx.x % G;
-    for (long long row = (long long)blockIdx.x * rpb + threadIdx.x / G; row < m; row += (long long)row_blocks * rpb) {
-      const V dot = csr_dot<TA, V>(rp, ci, val, tin, row, lane, G);
-      if (lane == 0) {
-        const V un = dot * ts - cu * u_top[row];
-        u_top[row] = un;
-        sq += (double)un * (double)un;
-      }
-    }
+  if ((int)blockIdx.x < row_blocks) {
+    csr_stream<V>(rb, rp, ci, val, tin, blockIdx.x, [&](int r, V dot) {
+      const V un = dot * ts - cu * u_top[r];
+      u_top[r] = un;
+      sq += (double)un * (double)un;
+    });
   } else {
+    const bool pend = pend_ok && st->pending;
+    const V cy = (V)st->coef_y, cw = (V)st->coef_w;
+    const int nb = gridDim.x - row_blocks;
     for (long long j = (long long)(blockIdx.x - row_blocks) * kBlock + threadIdx.x; j < n; j += (long long)nb * kBlock)
-      sq += fwd_bottom<V>(j, tin, u_bot, v, w, y, s, ts, cu, MODE == kFwdPlain);
+      sq += fwd_bottom<V>(j, tin, u_bot, v, w, y, delta, ts, cu, pend, cy, cw);
   }
   const double bs = block_sum(sq);
   if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
 }
 
 // Dense row-major A: one wave per row.
-template <class TA, class V, int MODE>
+template <class TA, class V>
 __global__ void __launch_bounds__(kBlock)
-    k_fwd_dense(const TA* __restrict__ A, long long m, long long n, long long ld, const V* tin, V* u_top,
-                V* u_bot, const V* v, V* w, V* y, GKState* st, const double* alpha_part, int alpha_count,
-                double* beta_part, int row_blocks) {
-  __shared__ GKState s;
-  if (MODE != kFwdMatvec && stopped(st)) return;
-  load_and_step(s, MODE == kFwdPlain ? &st[1] : &st[0], &st[0], MODE == kFwdPlain ? alpha_part : nullptr,
-                alpha_count);
-  const bool bottom = (int)blockIdx.x >= row_blocks;
-  const int nb = gridDim.x - row_blocks;
-  if (MODE == kFwdPlain && s.stop) {
-    if (bottom) final_y_update<V>(n, y, w, s, row_blocks, nb);
-    return;
-  }
-  const V ts = (V)(1.0 / s.alpha), cu = (V)(s.alpha / s.beta);
+    k_fwd_dense(const TA* __restrict__ A, long long m, long long n, long long ld, const V* tin, V* u_top, V* u_bot,
+                const V* v, V* w, V* y, const GKState* st, double* beta_part, int row_blocks, int pend_ok) {
+  if (stopped(st)) return;
+  const double alpha = st->alpha, beta = st->beta, delta = st->delta;
+  const V ts = (V)(1.0 / alpha), cu = (V)(alpha / beta);
   double sq = 0.0;
-  if (!bottom) {
+  if ((int)blockIdx.x < row_blocks) {
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     constexpr int rpb = kBlock / kWave;
     for (long long row = (long long)blockIdx.x * rpb + wv; row < m; row += (long long)row_blocks * rpb) {
@@ -232,24 +297,26 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
   } else {
+    const bool pend = pend_ok && st->pending;
+    const V cy = (V)st->coef_y, cw = (V)st->coef_w;
+    const int nb = gridDim.x - row_blocks;
     for (long long j = (long long)(blockIdx.x - row_blocks) * kBlock + threadIdx.x; j < n; j += (long long)nb * kBlock)
-      sq += fwd_bottom<V>(j, tin, u_bot, v, w, y, s, ts, cu, MODE == kFwdPlain);
+      sq += fwd_bottom<V>(j, tin, u_bot, v, w, y, delta, ts, cu, pend, cy, cw);
   }
   const double bs = block_sum(sq);
   if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
 }
 
-// Backward: beta from the forward partials (or the state when beta_part is
-// null), g = (A^T u_top + delta u_bot) / beta.  PLAIN: v_raw <- g -
-// (beta/alpha) v_raw (g at the phase start); otherwise g is stored for
-// P^{-T}.  Partials of the produced vector's squared norm go to alpha_part.
+// Backward epilogue: g = (dot + delta u_bot) / beta.  PLAIN: v_raw <- g -
+// (beta/alpha) v_raw (g at the phase start); otherwise g is stored for P^{-T}.
+// Returns the squared entry for the norm partials.
 template <class V, bool PLAIN>
-__device__ __forceinline__ double bwd_epilogue(long long j, V dot, const V* u_bot, V* v, V* g, const GKState& s,
-                                               V ib, V cv) {
+__device__ __forceinline__ double bwd_epilogue(long long j, V dot, const V* u_bot, V* v, V* g, double delta, V ib,
+                                               V cv, int init) {
   V gj = dot * ib;
-  if (s.delta > 0.0) gj += (V)s.delta * u_bot[j] * ib;
+  if (delta > 0.0) gj += (V)delta * u_bot[j] * ib;
   if (PLAIN) {
-    const V vn = s.init ? gj : gj - cv * v[j];
+    const V vn = init ? gj : gj - cv * v[j];
     v[j] = vn;
     return (double)vn * (double)vn;
   } else {
@@ -258,50 +325,18 @@ __device__ __forceinline__ double bwd_epilogue(long long j, V dot, const V* u_bo
   }
 }
 
-// Returns false when the kernel must not do its work (stopped / beta == 0).
-__device__ __forceinline__ bool bwd_prologue(GKState& s, GKState* st, const double* beta_part, int beta_count,
-                                             double* alpha_part) {
-  if (threadIdx.x == 0) s = st[0];
-  __syncthreads();
-  if (beta_part) {
-    const double b2 = reduce_all(beta_part, beta_count);
-    if (threadIdx.x == 0) {
-      const double b = sqrt(b2);
-      s.beta = b;
-      if (!(b == b) || isinf(b)) {
-        s.stop = 1;
-        s.reason = 6;
-      } else if (b == 0.0 && s.init) {
-        s.stop = 1;  // zero residual at the phase start: nothing to do
-        s.reason = kStopExact;
-      }
-    }
-    __syncthreads();
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) st[1] = s;
-  if (s.stop) return false;
-  if (s.beta == 0.0) {  // exact solution reached: alpha = 0 ends the phase in the next kernel
-    if (threadIdx.x == 0) alpha_part[blockIdx.x] = 0.0;
-    return false;
-  }
-  return true;
-}
-
 template <class TA, class V, bool PLAIN>
 __global__ void __launch_bounds__(kBlock)
-    k_bwd_csr(const int* __restrict__ tp, const int* __restrict__ ti, const TA* __restrict__ tv, long long n,
-              const V* u_top, const V* u_bot, V* v, V* g, GKState* st, const double* beta_part, int beta_count,
-              double* alpha_part, int G) {
-  __shared__ GKState s;
+    k_bwd_csr(const int* __restrict__ trb, const int* __restrict__ tp, const int* __restrict__ ti,
+              const TA* __restrict__ tv, long long n, const V* u_top, const V* u_bot, V* v, V* g, const GKState* st,
+              double* alpha_part) {
   if (stopped(st)) return;
-  if (!bwd_prologue(s, st, beta_part, beta_count, alpha_part)) return;
-  const V ib = (V)(1.0 / s.beta), cv = (V)(s.beta / s.alpha);
+  const double beta = st->beta, alpha = st->alpha, delta = st->delta;
+  const int init = st->init;
+  const V ib = (V)(1.0 / beta), cv = (V)(beta / alpha);
   double sq = 0.0;
-  const int rpb = kBlock / G, lane = threadIdx.x % G;
-  for (long long j = (long long)blockIdx.x * rpb + threadIdx.x / G; j < n; j += (long long)gridDim.x * rpb) {
-    const V dot = csr_dot<TA, V>(tp, ti, tv, u_top, j, lane, G);
-    if (lane == 0) sq += bwd_epilogue<V, PLAIN>(j, dot, u_bot, v, g, s, ib, cv);
-  }
+  csr_stream<V>(trb, tp, ti, tv, u_top, blockIdx.x,
+                [&](int j, V dot) { sq += bwd_epilogue<V, PLAIN>(j, dot, u_bot, v, g, delta, ib, cv, init); });
   const double bs = block_sum(sq);
   if (threadIdx.x == 0) alpha_part[blockIdx.x] = bs;
 }
@@ -324,16 +359,16 @@ __global__ void __launch_bounds__(kBlock)
 template <class V, bool PLAIN>
 __global__ void __launch_bounds__(kBlock)
     k_bwd_dense_red(const double* __restrict__ part, int chunks, long long n, const V* u_bot, V* v, V* g,
-                    GKState* st, const double* beta_part, int beta_count, double* alpha_part) {
-  __shared__ GKState s;
+                    const GKState* st, double* alpha_part) {
   if (stopped(st)) return;
-  if (!bwd_prologue(s, st, beta_part, beta_count, alpha_part)) return;
-  const V ib = (V)(1.0 / s.beta), cv = (V)(s.beta / s.alpha);
+  const double beta = st->beta, alpha = st->alpha, delta = st->delta;
+  const int init = st->init;
+  const V ib = (V)(1.0 / beta), cv = (V)(beta / alpha);
   double sq = 0.0;
   for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < n; j += (long long)gridDim.x * kBlock) {
     double acc = 0.0;
     for (int c = 0; c < chunks; ++c) acc += part[(long long)c * n + j];
-    sq += bwd_epilogue<V, PLAIN>(j, (V)acc, u_bot, v, g, s, ib, cv);
+    sq += bwd_epilogue<V, PLAIN>(j, (V)acc, u_bot, v, g, delta, ib, cv, init);
   }
   const double bs = block_sum(sq);
   if (threadIdx.x == 0) alpha_part[blockIdx.x] = bs;
@@ -374,21 +409,14 @@ __device__ __forceinline__ double vrow_dot(const double* __restrict__ Vh, long l
   return wave_sum(acc);
 }
 
-// First kernel of a preconditioned iteration: finishes alpha (partials of
-// the previous P^{-T} kernel), takes the scalar step, applies the y/w update,
-// and forms t = v_raw + V c (= P^{-1} v_raw).
+// t = v_raw + V c  (= P^{-1} v_raw) and the pending y/w update.
 template <class V>
 __global__ void __launch_bounds__(kBlock)
     k_pa_fwd(const double* __restrict__ Vh, long long n, int ell, long long ldv, const double* __restrict__ c,
-             const V* v, V* t, V* w, V* y, GKState* st, const double* alpha_part, int alpha_count) {
-  __shared__ GKState s;
+             const V* v, V* t, V* w, V* y, const GKState* st) {
   if (stopped(st)) return;
-  load_and_step(s, &st[1], &st[0], alpha_part, alpha_count);
-  if (s.stop) {
-    final_y_update<V>(n, y, w, s, 0, gridDim.x);
-    return;
-  }
-  const double ia = 1.0 / s.alpha;
+  const bool pend = st->pending;
+  const double cy = st->coef_y, cw = st->coef_w, ia = 1.0 / st->alpha;
   const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   constexpr int rpb = kBlock / kWave;
   for (long long i = (long long)blockIdx.x * rpb + wv; i < n; i += (long long)gridDim.x * rpb) {
@@ -396,25 +424,24 @@ __global__ void __launch_bounds__(kBlock)
     if (lane == 0) {
       const V vi = v[i];
       t[i] = (V)((double)vi + dot);
-      if (s.pending) {
+      if (pend) {
         const V wi = w[i];
-        y[i] += (V)s.coef_y * wi;
-        w[i] = (V)((double)vi * ia) - (V)s.coef_w * wi;
+        y[i] += (V)cy * wi;
+        w[i] = (V)((double)vi * ia) - (V)cw * wi;
       }
     }
   }
 }
 
 // v_raw <- (g + V c) - (beta/alpha) v_raw  (g + V c at the phase start);
-// partials of ||v_raw||^2 for the next iteration's alpha.
+// partials of ||v_raw||^2.
 template <class V>
 __global__ void __launch_bounds__(kBlock)
     k_pa_bwd(const double* __restrict__ Vh, long long n, int ell, long long ldv, const double* __restrict__ c,
              const V* g, V* v, const GKState* st, double* alpha_part) {
   if (stopped(st)) return;
-  const GKState& s = st[1];
-  const int init = s.init;
-  const double cv = s.beta / s.alpha;
+  const int init = st->init;
+  const double cv = st->beta / st->alpha;
   const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   constexpr int rpb = kBlock / kWave;
   double sq = 0.0;
@@ -444,16 +471,16 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// ---------------------------------------------------------------- phase start / helpers
+// ---------------------------------------------------------------- phase start / end
 // r_top = b - A x (FP64, values widened), r_bot = bot_scale b_bot - delta x;
-// partials of ||r||^2 into beta_part.
+// partials of ||r||^2.
 template <class TA>
 __global__ void __launch_bounds__(kBlock)
     k_resid_csr(const int* __restrict__ rp, const int* __restrict__ ci, const TA* __restrict__ val, long long m,
                 long long n, const double* __restrict__ b, const double* b_bot, double bot_scale, const double* x,
                 int x_zero, double* r_top, double* r_bot, const GKState* st, double* beta_part, int G,
                 int row_blocks) {
-  const double delta = st[0].delta;
+  const double delta = st->delta;
   double sq = 0.0;
   if ((int)blockIdx.x < row_blocks) {
     const int rpb = kBlock / G, lane = threadIdx.x % G;
@@ -483,7 +510,7 @@ __global__ void __launch_bounds__(kBlock)
     k_resid_dense(const TA* __restrict__ A, long long m, long long n, long long ld, const double* __restrict__ b,
                   const double* b_bot, double bot_scale, const double* x, int x_zero, double* r_top, double* r_bot,
                   const GKState* st, double* beta_part, int row_blocks) {
-  const double delta = st[0].delta;
+  const double delta = st->delta;
   double sq = 0.0;
   if ((int)blockIdx.x < row_blocks) {
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -514,20 +541,13 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
 }
 
-// One workgroup: finish a reduction into the state.  mode 0: alpha and the
-// scalar step (slot 1 -> slot 0); mode 1: beta1 = sqrt(sum) in slot 0.
-__global__ void __launch_bounds__(kBlock) k_consume(GKState* st, const double* part, int count, int mode) {
-  __shared__ GKState s;
-  const double tot = reduce_all(part, count);
-  if (threadIdx.x == 0) {
-    s = mode == 0 ? st[1] : st[0];
-    if (mode == 0) {
-      if (!s.stop) scalar_step(s, sqrt(tot));
-    } else {
-      s.beta1 = sqrt(tot);
-    }
-    st[0] = s;
-  }
+// Phase end: the last pending y update (w is not needed afterwards).
+template <class V>
+__global__ void k_finalize(long long n, V* y, const V* w, const GKState* st) {
+  if (!st->pending) return;
+  const V cy = (V)st->coef_y;
+  for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < n; j += (long long)gridDim.x * kBlock)
+    y[j] += cy * w[j];
 }
 
 template <class V>
@@ -562,76 +582,71 @@ static unsigned nbottom(long long n) {
   return (unsigned)(b > 256 ? 256 : b);
 }
 static unsigned fwd_row_blocks(const OpDesc& A) {
-  if (A.csr) {
-    const int rpb = kBlock / A.group;
-    return clamp_grid((A.m + rpb - 1) / rpb);
-  }
+  if (A.csr) return (unsigned)stream_blocks(A.nnz);
   return clamp_grid((A.m + 3) / 4);
 }
-static unsigned fwd_grid(const OpDesc& A) { return fwd_row_blocks(A) + nbottom(A.n); }
 static unsigned bwd_grid(const OpDesc& A) {
-  if (A.csr) {
-    const int rpb = kBlock / A.t_group;
-    return clamp_grid((A.n + rpb - 1) / rpb);
-  }
+  if (A.csr) return (unsigned)stream_blocks(A.nnz);
   return clamp_grid(ceil_div(A.n, kBlock));
 }
 static unsigned rows_grid(long long n) { return clamp_grid((n + 3) / 4); }
 
-template <class V, int MODE>
-static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s) {
+static void finish(GKState* st, GKWork& wk, int mode, hipStream_t s) {
+  if (mode == kFinBeta)
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, st, wk.beta_part, (int)wk.beta_count, mode);
+  else
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, st, wk.alpha_part, (int)wk.alpha_count, mode);
+}
+
+template <class V>
+static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, const GKState* st, GKWork& wk, int pend_ok,
+                       hipStream_t s) {
   const unsigned rb = fwd_row_blocks(A);
   const unsigned grid = rb + nbottom(A.n);
-  const int ac = (int)wk.alpha_count;
   if (A.csr) {
     if (A.f64)
-      hipLaunchKernelGGL((k_fwd_csr<double, V, MODE>), dim3(grid), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
+      hipLaunchKernelGGL((k_fwd_csr<double, V>), dim3(grid), dim3(kBlock), 0, s, A.rb, A.row_ptr, A.col_idx,
                          (const double*)A.val, A.m, A.n, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st,
-                         wk.alpha_part, ac, wk.beta_part, A.group, (int)rb);
+                         wk.beta_part, (int)rb, pend_ok);
     else
-      hipLaunchKernelGGL((k_fwd_csr<float, V, MODE>), dim3(grid), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
+      hipLaunchKernelGGL((k_fwd_csr<float, V>), dim3(grid), dim3(kBlock), 0, s, A.rb, A.row_ptr, A.col_idx,
                          (const float*)A.val, A.m, A.n, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st,
-                         wk.alpha_part, ac, wk.beta_part, A.group, (int)rb);
+                         wk.beta_part, (int)rb, pend_ok);
   } else {
     if (A.f64)
-      hipLaunchKernelGGL((k_fwd_dense<double, V, MODE>), dim3(grid), dim3(kBlock), 0, s, (const double*)A.val, A.m,
-                         A.n, A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st, wk.alpha_part, ac,
-                         wk.beta_part, (int)rb);
+      hipLaunchKernelGGL((k_fwd_dense<double, V>), dim3(grid), dim3(kBlock), 0, s, (const double*)A.val, A.m, A.n,
+                         A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st, wk.beta_part, (int)rb, pend_ok);
     else
-      hipLaunchKernelGGL((k_fwd_dense<float, V, MODE>), dim3(grid), dim3(kBlock), 0, s, (const float*)A.val, A.m,
-                         A.n, A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st, wk.alpha_part, ac,
-                         wk.beta_part, (int)rb);
+      hipLaunchKernelGGL((k_fwd_dense<float, V>), dim3(grid), dim3(kBlock), 0, s, (const float*)A.val, A.m, A.n,
+                         A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st, wk.beta_part, (int)rb, pend_ok);
   }
   wk.beta_count = grid;
 }
 
-// beta_from_part: finish beta from wk.beta_part (else the state's beta is used).
 template <class V, bool PLAIN>
-static void launch_bwd(const OpDesc& A, const V* u_top, const V* u_bot, V* v, V* g, GKState* st, GKWork& wk,
-                       bool beta_from_part, hipStream_t s) {
-  const double* bp = beta_from_part ? wk.beta_part : nullptr;
-  const int bc = (int)wk.beta_count;
+static void launch_bwd(const OpDesc& A, const V* u_top, const V* u_bot, V* v, V* g, const GKState* st, GKWork& wk,
+                       hipStream_t s) {
   if (A.csr) {
     const unsigned grid = bwd_grid(A);
     if (A.f64)
-      hipLaunchKernelGGL((k_bwd_csr<double, V, PLAIN>), dim3(grid), dim3(kBlock), 0, s, A.t_ptr, A.t_idx,
-                         (const double*)A.t_val, A.n, u_top, u_bot, v, g, st, bp, bc, wk.alpha_part, A.t_group);
+      hipLaunchKernelGGL((k_bwd_csr<double, V, PLAIN>), dim3(grid), dim3(kBlock), 0, s, A.t_rb, A.t_ptr, A.t_idx,
+                         (const double*)A.t_val, A.n, u_top, u_bot, v, g, st, wk.alpha_part);
     else
-      hipLaunchKernelGGL((k_bwd_csr<float, V, PLAIN>), dim3(grid), dim3(kBlock), 0, s, A.t_ptr, A.t_idx,
-                         (const float*)A.t_val, A.n, u_top, u_bot, v, g, st, bp, bc, wk.alpha_part, A.t_group);
+      hipLaunchKernelGGL((k_bwd_csr<float, V, PLAIN>), dim3(grid), dim3(kBlock), 0, s, A.t_rb, A.t_ptr, A.t_idx,
+                         (const float*)A.t_val, A.n, u_top, u_bot, v, g, st, wk.alpha_part);
     wk.alpha_count = grid;
   } else {
     const long long rpc = (A.m + A.chunks - 1) / A.chunks;
     dim3 g1(ceil_div(A.n, kBlock), A.chunks);
     if (A.f64)
       hipLaunchKernelGGL((k_bwd_dense_part<double, V>), g1, dim3(kBlock), 0, s, (const double*)A.val, A.m, A.n, A.ld,
-                         u_top, A.part, rpc, (const GKState*)st);
+                         u_top, A.part, rpc, st);
     else
       hipLaunchKernelGGL((k_bwd_dense_part<float, V>), g1, dim3(kBlock), 0, s, (const float*)A.val, A.m, A.n, A.ld,
-                         u_top, A.part, rpc, (const GKState*)st);
+                         u_top, A.part, rpc, st);
     const unsigned grid = bwd_grid(A);
     hipLaunchKernelGGL((k_bwd_dense_red<V, PLAIN>), dim3(grid), dim3(kBlock), 0, s, A.part, A.chunks, A.n, u_bot, v,
-                       g, st, bp, bc, wk.alpha_part);
+                       g, st, wk.alpha_part);
     wk.alpha_count = grid;
   }
 }
@@ -646,47 +661,55 @@ static void launch_pa_c(const PrecDesc& P, long long n, const V* z, const GKStat
 }
 
 template <class V>
-void gk_iteration(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s) {
-  if (!P) {
-    launch_fwd<V, kFwdPlain>(A, vec.v, vec, st, wk, s);
-    launch_bwd<V, true>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, true, s);
-    return;
-  }
-  launch_pa_c<V>(*P, A.n, vec.v, st, s);
-  const unsigned rg = rows_grid(A.n);
-  hipLaunchKernelGGL((k_pa_fwd<V>), dim3(rg), dim3(kBlock), 0, s, P->V, A.n, P->ell, P->ldv, P->c, vec.v, vec.t,
-                     vec.w, vec.y, st, wk.alpha_part, (int)wk.alpha_count);
-  launch_fwd<V, kFwdPre>(A, vec.t, vec, st, wk, s);
-  launch_bwd<V, false>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, true, s);
-  launch_pa_c<V>(*P, A.n, vec.g, st, s);
-  hipLaunchKernelGGL((k_pa_bwd<V>), dim3(rg), dim3(kBlock), 0, s, P->V, A.n, P->ell, P->ldv, P->c, vec.g, vec.v,
-                     (const GKState*)st, wk.alpha_part);
+static void launch_pa_bwd(const PrecDesc& P, long long n, const V* g, V* v, const GKState* st, GKWork& wk,
+                          hipStream_t s) {
+  const unsigned rg = rows_grid(n);
+  hipLaunchKernelGGL((k_pa_bwd<V>), dim3(rg), dim3(kBlock), 0, s, P.V, n, P.ell, P.ldv, P.c, g, v, st,
+                     wk.alpha_part);
   wk.alpha_count = rg;
 }
 
+template <class V>
+void gk_iteration(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s) {
+  if (!P) {
+    launch_fwd<V>(A, vec.v, vec, st, wk, 1, s);
+    finish(st, wk, kFinBeta, s);
+    launch_bwd<V, true>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, s);
+    finish(st, wk, kFinAlpha, s);
+    return;
+  }
+  launch_pa_c<V>(*P, A.n, vec.v, st, s);
+  hipLaunchKernelGGL((k_pa_fwd<V>), dim3(rows_grid(A.n)), dim3(kBlock), 0, s, P->V, A.n, P->ell, P->ldv, P->c, vec.v,
+                     vec.t, vec.w, vec.y, (const GKState*)st);
+  launch_fwd<V>(A, vec.t, vec, st, wk, 0, s);
+  finish(st, wk, kFinBeta, s);
+  launch_bwd<V, false>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, s);
+  launch_pa_c<V>(*P, A.n, vec.g, st, s);
+  launch_pa_bwd<V>(*P, A.n, vec.g, vec.v, st, wk, s);
+  finish(st, wk, kFinAlpha, s);
+}
+
 static void launch_resid(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
-                         double* r_top, double* r_bot, GKState* st, GKWork& wk, hipStream_t s) {
+                         double* r_top, double* r_bot, const GKState* st, GKWork& wk, hipStream_t s) {
   const int x_zero = (x == nullptr);
-  const unsigned rb = fwd_row_blocks(A);
+  const unsigned rb = A.csr ? clamp_grid((A.m + (kBlock / A.group) - 1) / (kBlock / A.group)) : fwd_row_blocks(A);
   const unsigned grid = rb + nbottom(A.n);
   if (A.csr) {
     if (A.f64)
       hipLaunchKernelGGL((k_resid_csr<double>), dim3(grid), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
-                         (const double*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot,
-                         (const GKState*)st, wk.beta_part, A.group, (int)rb);
+                         (const double*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, st,
+                         wk.beta_part, A.group, (int)rb);
     else
       hipLaunchKernelGGL((k_resid_csr<float>), dim3(grid), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
-                         (const float*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot,
-                         (const GKState*)st, wk.beta_part, A.group, (int)rb);
+                         (const float*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, st,
+                         wk.beta_part, A.group, (int)rb);
   } else {
     if (A.f64)
       hipLaunchKernelGGL((k_resid_dense<double>), dim3(grid), dim3(kBlock), 0, s, (const double*)A.val, A.m, A.n,
-                         A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, (const GKState*)st, wk.beta_part,
-                         (int)rb);
+                         A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, st, wk.beta_part, (int)rb);
     else
       hipLaunchKernelGGL((k_resid_dense<float>), dim3(grid), dim3(kBlock), 0, s, (const float*)A.val, A.m, A.n,
-                         A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, (const GKState*)st, wk.beta_part,
-                         (int)rb);
+                         A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, st, wk.beta_part, (int)rb);
   }
   wk.beta_count = grid;
 }
@@ -697,24 +720,23 @@ void gk_phase_init(const OpDesc& A, const PrecDesc* P, const double* b, const do
                    hipStream_t s) {
   static_assert(sizeof(V) == 8, "only the FP64 vector path is implemented here");
   launch_resid(A, b, b_bot, bot_scale, x, r_top64, r_bot64, st, wk, s);
+  finish(st, wk, kFinBeta, s);
   fill_zero<V>(vec.y, A.n, s);
   fill_zero<V>(vec.w, A.n, s);
   if (!P) {
-    launch_bwd<V, true>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, true, s);
+    launch_bwd<V, true>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, s);
   } else {
-    launch_bwd<V, false>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, true, s);
+    launch_bwd<V, false>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, s);
     launch_pa_c<V>(*P, A.n, vec.g, st, s);
-    const unsigned rg = rows_grid(A.n);
-    hipLaunchKernelGGL((k_pa_bwd<V>), dim3(rg), dim3(kBlock), 0, s, P->V, A.n, P->ell, P->ldv, P->c, vec.g, vec.v,
-                       (const GKState*)st, wk.alpha_part);
-    wk.alpha_count = rg;
+    launch_pa_bwd<V>(*P, A.n, vec.g, vec.v, st, wk, s);
   }
+  finish(st, wk, kFinAlpha, s);
 }
 
 template <class V>
 void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* x, GKState* st, hipStream_t s) {
-  (void)st;
   const unsigned g = clamp_grid(ceil_div(A.n, kBlock));
+  hipLaunchKernelGGL((k_finalize<V>), dim3(g), dim3(kBlock), 0, s, A.n, vec.y, vec.w, (const GKState*)st);
   if (!P) {
     hipLaunchKernelGGL((k_axpy_x<V>), dim3(g), dim3(kBlock), 0, s, A.n, vec.y, x);
   } else {
@@ -730,35 +752,36 @@ template void gk_phase_init<double>(const OpDesc&, const PrecDesc*, const double
 template void gk_phase_finish<double>(const OpDesc&, const PrecDesc*, GKVecs<double>, double*, GKState*,
                                       hipStream_t);
 
-// eta support: ||A_mu^T r|| for r = [b - A x; -delta x] into st[0].h2 (and
-// ||r|| into st[0].beta1), through the plain phase-start kernels.
+// ||A_mu^T r||^2 -> st->h2 for r = [b - A x; bot_scale b_bot - delta x]: the
+// plain phase start (its initial scalar step stores (alpha_1 beta_1)^2).
 void gk_normal_residual(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
                         GKVecs<double> vec, GKState* st, GKWork& wk, hipStream_t s) {
   launch_resid(A, b, b_bot, bot_scale, x, vec.u_top, vec.u_bot, st, wk, s);
-  launch_bwd<double, true>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, true, s);
-  hipLaunchKernelGGL(k_consume, dim3(1), dim3(kBlock), 0, s, st, wk.alpha_part, (int)wk.alpha_count, 0);
+  finish(st, wk, kFinBeta, s);
+  launch_bwd<double, true>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, s);
+  finish(st, wk, kFinAlpha, s);
 }
 
-// ||A^T b||^2 -> st[0].h2 (state: beta = 1, delta = 0, init = 1).
+// ||A^T b||^2 -> st->h2 (state: beta = 1, delta = 0, init = 1).
 void op_atb_norm2(const OpDesc& A, const double* b, double* tmp_n, GKState* st, GKWork& wk, hipStream_t s) {
-  launch_bwd<double, false>(A, b, nullptr, nullptr, tmp_n, st, wk, false, s);
-  hipLaunchKernelGGL(k_consume, dim3(1), dim3(kBlock), 0, s, st, wk.alpha_part, (int)wk.alpha_count, 0);
+  launch_bwd<double, false>(A, b, nullptr, nullptr, tmp_n, st, wk, s);
+  finish(st, wk, kFinAlpha, s);
 }
 
-// ||b||^2 -> st[0].beta1 (state: delta = 0).
+// ||b|| -> st->beta (state: delta = 0, init = 1).
 void op_norm(const OpDesc& A, const double* b, double* tmp_m, GKState* st, GKWork& wk, hipStream_t s) {
   launch_resid(A, b, nullptr, 0.0, nullptr, tmp_m, nullptr, st, wk, s);
-  hipLaunchKernelGGL(k_consume, dim3(1), dim3(kBlock), 0, s, st, wk.beta_part, (int)wk.beta_count, 1);
+  finish(st, wk, kFinBeta, s);
 }
 
-// y = A x (trans = 0; y = A x - y_prev, the LSQR forward kernel with alpha =
-// beta = 1, delta = 0) or y = A^T x (trans = 1), state slots as given.
+// y = A x - y_prev (trans = 0; the LSQR forward kernel with alpha = beta = 1,
+// delta = 0) or y = A^T x (trans = 1); state as given, not modified.
 void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s) {
   if (!trans) {
     GKVecs<double> vec{y, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    launch_fwd<double, kFwdMatvec>(A, x, vec, st, wk, s);
+    launch_fwd<double>(A, x, vec, st, wk, 0, s);
   } else {
-    launch_bwd<double, false>(A, x, nullptr, nullptr, y, st, wk, false, s);
+    launch_bwd<double, false>(A, x, nullptr, nullptr, y, st, wk, s);
   }
 }
 

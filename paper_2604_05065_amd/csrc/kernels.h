@@ -31,7 +31,8 @@ void launch_sketch_dense(const T* A, long long m, long long n, long long ld, int
 struct OpDesc {
   int csr;            // 1: CSR, 0: dense row-major
   int f64;            // 1: values are double, 0: float
-  long long m, n, ld;
+  long long m, n, ld, nnz;
+  const int *rb, *t_rb;          // row blocks of the CSR-stream products (A, A^T)
   const int *row_ptr, *col_idx;  // CSR of A
   const void* val;
   const int *t_ptr, *t_idx;      // CSR of A^T
@@ -88,5 +89,7 @@ void op_norm(const OpDesc& A, const double* b, double* tmp_m, GKState* st, GKWor
 void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s);
 template <class V>
 void fill_zero(V* p, long long n, hipStream_t s);
+int stream_blocks(long long nnz);
+void build_row_blocks(const int* rp, long long m, long long nnz, int* rb, hipStream_t s);
 
 }  // namespace aplicur
