@@ -85,7 +85,9 @@ struct Ctx {
   int rank = 0;
   // preconditioner
   double *Mx = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
-         *pa_part = nullptr, *pa_c = nullptr;
+         *pa_part = nullptr, *pa_c = nullptr, *Kc = nullptr, *Kr = nullptr, *pc1 = nullptr, *pc2 = nullptr;
+  int *rr_ptr = nullptr, *rr_idx = nullptr, *rt_ptr = nullptr, *rt_idx = nullptr, *rscratch = nullptr;
+  double *rr_val = nullptr, *rt_val = nullptr;
   unsigned long long* offmax = nullptr;
   double* splitk = nullptr;
   size_t splitk_count = 0;
@@ -245,10 +247,11 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       op.t_idx = ti;
       op.t_val = tv;
       op.nnz = Am->nnz;
-      int* rbA = c->arena.alloc<int>(stream_blocks(Am->nnz) + 1);
-      int* rbT = c->arena.alloc<int>(stream_blocks(Am->nnz) + 1);
-      build_row_blocks(Am->row_ptr, m, Am->nnz, rbA, s);
-      build_row_blocks(tp, n, Am->nnz, rbT, s);
+      op.stream_t = stream_t(Am->nnz);
+      int* rbA = c->arena.alloc<int>(row_block_words(Am->nnz, op.stream_t));
+      int* rbT = c->arena.alloc<int>(row_block_words(Am->nnz, op.stream_t));
+      build_row_blocks(Am->row_ptr, m, Am->nnz, op.stream_t, rbA, s);
+      build_row_blocks(tp, n, Am->nnz, op.stream_t, rbT, s);
       op.rb = rbA;
       op.t_rb = rbT;
       op.group = group_for((double)Am->nnz / (double)m);
@@ -269,7 +272,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
     c->t = c->arena.alloc<double>(n);
     c->g = c->arena.alloc<double>(std::max(m, n));
     {
-      const long long parts = 16384 + 256 + (op.csr ? stream_blocks(Am->nnz) : 0);
+      const long long parts = 16384 + 256 + (op.csr ? stream_blocks(Am->nnz, op.stream_t) : 0);
       c->wk.alpha_part = c->arena.alloc<double>(parts);
       c->wk.beta_part = c->arena.alloc<double>(parts);
     }
@@ -357,16 +360,43 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       c->Mx = c->arena.alloc<double>((size_t)L * Lp);
       c->Vm = c->arena.alloc<double>((size_t)Lp * Lp);
       c->sigma = c->arena.alloc<double>(Lp);
-      c->Vhat = c->arena.alloc<double>((size_t)L * n);
+      c->Kc = c->arena.alloc<double>((size_t)L * L);
+      c->Kr = c->arena.alloc<double>((size_t)L * L);
       c->d = c->arena.alloc<double>(L);
       c->pinfo = c->arena.alloc<double>(4);
       c->offmax = c->arena.alloc<unsigned long long>(1);
-      const int pchunks = (int)std::max<long long>(1, std::min<long long>(256, n / 64));
-      c->pa_part = c->arena.alloc<double>((size_t)pchunks * L);
       c->pa_c = c->arena.alloc<double>(L);
-      c->prec.chunks = pchunks;
-      c->prec.part = c->pa_part;
       c->prec.c = c->pa_c;
+      c->prec.d = c->d;
+      if (op.csr) {
+        // implicit P-apply: R = A(I,:) and its transpose, capacity nnz(A)
+        c->prec.implicit = 1;
+        c->rr_ptr = c->arena.alloc<int>(L + 1);
+        c->rr_idx = c->arena.alloc<int>(Am->nnz);
+        c->rr_val = c->arena.alloc<double>(Am->nnz);
+        c->rt_ptr = c->arena.alloc<int>(n + 1);
+        c->rt_idx = c->arena.alloc<int>(Am->nnz);
+        c->rt_val = c->arena.alloc<double>(Am->nnz);
+        c->rscratch = c->arena.alloc<int>(std::max<long long>(n, L));
+        c->pc1 = c->arena.alloc<double>(L);
+        c->pc2 = c->arena.alloc<double>(L);
+        c->prec.I = c->I_dev;
+        c->prec.Kt = c->Kc;
+        c->prec.Kr = c->Kr;
+        c->prec.rt_ptr = c->rt_ptr;
+        c->prec.rt_idx = c->rt_idx;
+        c->prec.rt_val = c->rt_val;
+        c->prec.c1 = c->pc1;
+        c->prec.c2 = c->pc2;
+      } else {
+        c->prec.implicit = 0;
+        c->Vhat = c->arena.alloc<double>((size_t)L * n);
+        const int pchunks = (int)std::max<long long>(1, std::min<long long>(256, n / 64));
+        c->pa_part = c->arena.alloc<double>((size_t)pchunks * L);
+        c->prec.chunks = pchunks;
+        c->prec.part = c->pa_part;
+        c->prec.V = c->Vhat;
+      }
       long long lrows = std::max(m, n);
       c->fw.lupp_rows = (int)lrows;
       c->fw.pos = c->arena.alloc<int>(2 * lrows);
@@ -563,13 +593,33 @@ static void build_precond(Ctx& c, hipStream_t s) {
   const int lp = ((l + jw2 - 1) / jw2) * jw2;
   // M = T_C U T_R^T  (l x l) into Mx (ld L, lp columns, padding zero)
   fill(c.Mx, (long long)L * lp, 0.0, s);
-  gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Vhat, l);
-  gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, l, 1.0, c.TC, L, c.Vhat, l, 0.0, c.Mx, L);
+  gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Kr, l);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Mx, L);
   set_identity(c.Vm, lp, lp, s);
   jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.offmax, 1e-14, 40, s);
-  // V = Q_R V_M stored row-major n x l  (= column-major l x n: V^T = V_M^T Q_R^T)
-  gemm(c, rocblas_operation_transpose, rocblas_operation_transpose, l, c.n, l, 1.0, c.Vm, lp, c.Q, c.n, 0.0,
-       c.Vhat, l);
+  if (c.prec.implicit) {
+    // K = T_R^{-1} V_M (column-major, ld l: the row-major K^T) and K row-major
+    copy_block(c.Vm, lp, c.Kc, l, l, l, 1.0, s);
+    const double one = 1.0;
+    APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                           rocblas_diagonal_non_unit, l, l, &one, c.TR, L, c.Kc, l));
+    transpose_square(c.Kc, l, c.Kr, l, s);
+    // CSR of R = A(I,:) and of R^T
+    long long nnzR;
+    if (c.op.f64)
+      nnzR = launch_gather_csr_rows<double>(c.op.row_ptr, c.op.col_idx, (const double*)c.op.val, c.I_dev, l,
+                                            c.rr_ptr, c.rr_idx, c.rr_val, c.op.nnz, c.rscratch, s);
+    else
+      nnzR = launch_gather_csr_rows<float>(c.op.row_ptr, c.op.col_idx, (const float*)c.op.val, c.I_dev, l,
+                                           c.rr_ptr, c.rr_idx, c.rr_val, c.op.nnz, c.rscratch, s);
+    launch_csr_transpose<double>(c.rr_ptr, c.rr_idx, c.rr_val, l, c.n, nnzR, c.rt_ptr, c.rt_idx, c.rt_val,
+                                 c.rscratch, s);
+  } else {
+    // V = Q_R V_M stored row-major n x l  (= column-major l x n: V^T = V_M^T Q_R^T)
+    gemm(c, rocblas_operation_transpose, rocblas_operation_transpose, l, c.n, l, 1.0, c.Vm, lp, c.Q, c.n, 0.0,
+         c.Vhat, l);
+    c.prec.ldv = l;
+  }
   precond_scalars(c.sigma, l, c.delta, c.d, c.pinfo, s);
   double info[4];
   APL_HIP(hipMemcpyAsync(info, c.pinfo, sizeof(info), hipMemcpyDeviceToHost, s));
@@ -580,9 +630,6 @@ static void build_precond(Ctx& c, hipStream_t s) {
   c.p_target = info[2];
   c.p_pnorm = info[3];
   c.prec.ell = l;
-  c.prec.ldv = l;
-  c.prec.V = c.Vhat;
-  c.prec.d = c.d;
   c.have_prec = true;
 }
 
@@ -613,11 +660,12 @@ static void upload_state(Ctx& c, double tol_abs, double pnorm, double eps_lsqr, 
   APL_HIP(hipMemcpyAsync(c.st, c.st_host, 2 * sizeof(GKState), hipMemcpyHostToDevice, s));
 }
 
-// Both slots; the returned state is slot 0 with the stop flag / reason of
-// either slot.
+// Both slots; the returned state is slot 0 unless only slot 1 carries the
+// stop flag (a stop found while finishing beta).
 static GKState read_state(Ctx& c, hipStream_t s) {
   APL_HIP(hipMemcpyAsync(c.st_host, c.st, 2 * sizeof(GKState), hipMemcpyDeviceToHost, s));
   APL_HIP(hipStreamSynchronize(s));
+  if (c.st_host[1].stop && !c.st_host[0].stop) return c.st_host[1];
   return c.st_host[0];
 }
 

@@ -39,6 +39,8 @@ void copy_block(const double* src, long long lds, double* dst, long long ldd, in
 void splitk_reduce(const double* W, int parts, long long m, long long n, double alpha, double beta, double* C,
                    long long ldc, hipStream_t s);
 void set_identity(double* X, long long ld, int n, hipStream_t s);
+// dst (n x n, ld n) = src^T (src n x n, ld lds).
+void transpose_square(const double* src, long long lds, double* dst, int n, hipStream_t s);
 void add_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols, hipStream_t s);
 
 void small_inverse(double* S, long long ld, int k, double* Sinv, long long ldi, int* status, hipStream_t s);

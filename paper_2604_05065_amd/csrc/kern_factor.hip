@@ -729,4 +729,27 @@ void set_identity(double* X, long long ld, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_set_identity, dim3(ceil_div(n, kBlock), n), dim3(kBlock), 0, s, X, ld, n);
 }
 
+// Column-major dst = src^T (n x n): dst[i n + j] = src[j lds + i], 32 x 32
+// tiles through LDS so that both the loads and the stores are coalesced.
+__global__ void __launch_bounds__(kBlock) k_transpose(const double* src, long long lds, double* dst, int n) {
+  __shared__ double tile[32][33];
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int r = ty; r < 32; r += kBlock / 32) {
+    const int i = bi + tx, j = bj + r;
+    tile[tx][r] = (i < n && j < n) ? src[(long long)j * lds + i] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += kBlock / 32) {
+    const int i = bi + r, j = bj + tx;
+    if (i < n && j < n) dst[(long long)i * n + j] = tile[r][tx];
+  }
+}
+
+void transpose_square(const double* src, long long lds, double* dst, int n, hipStream_t s) {
+  if (n <= 0) return;
+  dim3 g(ceil_div(n, 32), ceil_div(n, 32));
+  hipLaunchKernelGGL(k_transpose, g, dim3(kBlock), 0, s, src, lds, dst, n);
+}
+
 }  // namespace aplicur

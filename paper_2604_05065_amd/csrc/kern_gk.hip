@@ -3,22 +3,32 @@
 // A_mu = [A; delta I]  (delta = sqrt(mu)), one iteration being
 //
 //     beta u  = A~ v   - alpha u      (forward kernel; P^{-1} v first if P != I)
-//     alpha v = A~^T u - beta  v      (backward kernel; then P^{-T})
+//     alpha v = A~^T u - beta  v      (backward kernel; then P^{-T} = P^{-1})
 //     Givens rotation, y += (phi/rho) w, w = v - (theta/rho) w.
 //
-// Reductions without fences or atomics: a kernel that produces a norm writes
-// one partial sum per workgroup (grids sized for full occupancy), and a
-// one-workgroup "finish" kernel sums them in a fixed order and updates the
-// FP64 scalar state (beta; or alpha with the Givens rotation and the
-// stopping tests of Sec. 5.3.2).  Only finish kernels write the state, so the
-// products read it without races.  Normalisation by 1/beta and 1/alpha is
-// folded into the next consumer, and the y/w update of iteration j is applied
-// by the first kernel of iteration j + 1 (or by the phase-end kernel).
+// Reductions without fences, atomics or extra launches.  A kernel that
+// produces a norm writes one partial sum per workgroup.  Every workgroup of
+// the kernel that consumes the norm loads those partials together with its
+// own first operands, sums them in a fixed order (thread-strided sums, a
+// shuffle tree, the waves in order) so that all workgroups hold the
+// bitwise-identical scalar, and advances its private copy of the FP64 state
+// with it (the same arithmetic in every thread).  The state has two slots:
+// slot 0 is written by the kernel that finishes alpha and takes the Givens
+// step with the stopping tests of Sec. 5.3.2, slot 1 by the kernel that
+// finishes beta; a kernel reads only the slot it does not write, and only
+// workgroup 0 stores, so there is no race.  A stopped state is copied
+// forward by the next kernels until the host sees it.  Normalisation by
+// 1/beta and 1/alpha is folded into the consumers, and the y/w update of
+// iteration j is applied by the first kernel of iteration j + 1, which on
+// stopping applies the last y update itself.
 #include "kernels.h"
 
 namespace aplicur {
 
-constexpr int kMaxGrid = 16384;
+constexpr int kMaxGrid = 4096;                // grid-stride kernels
+constexpr int kStreamCap = 2048;              // CSR-stream: LDS products per workgroup
+constexpr int kPer = kStreamCap / kBlock;     // products per thread
+constexpr int kRowsMaxGrid = 512;             // row-wise P-apply kernels (their partials are re-read)
 
 // ---------------------------------------------------------------- scalar update
 // One LSQR scalar step on a state copy: the initial step (alpha_1, beta_1) or
@@ -98,191 +108,344 @@ __device__ void scalar_step(GKState& s, double alpha) {
   }
 }
 
-__device__ __forceinline__ bool stopped(const GKState* st) { return st->stop != 0; }
-
-// ---------------------------------------------------------------- finish kernels
-// One workgroup (1024 threads): sums the partials of the producing kernel in
-// a fixed order and updates the state.
-enum FinMode { kFinBeta = 0, kFinAlpha = 1 };
-
-__global__ void __launch_bounds__(1024) k_finish(GKState* st, const double* part, int count, int mode) {
-  __shared__ double red[1024 / kWave];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < count; i += 1024) v += part[i];
-  v = wave_sum(v);
-  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  double tot = 0.0;
-  for (int i = 0; i < 1024 / kWave; ++i) tot += red[i];
-  GKState s = *st;
-  if (s.stop) return;
-  if (mode == kFinBeta) {
-    const double b = sqrt(tot);
-    s.pending = 0;  // the forward kernel has applied the y/w update
-    s.beta = b;
-    if (!(b == b) || isinf(b)) {
-      s.stop = 1;
-      s.reason = 6;
-    } else if (b == 0.0) {
-      if (s.init) {  // zero residual at the phase start: nothing to do
-        s.beta1 = 0.0;
-        s.stop = 1;
-        s.reason = kStopExact;
-      } else {
-        scalar_step(s, 0.0);  // exact solution: last y update, then stop
-      }
-    }
-  } else {
-    scalar_step(s, sqrt(tot));
+// beta = sqrt(sum of squares); flags non-finite values and a zero residual
+// at the phase start (nothing to do).
+__device__ __forceinline__ void beta_step(GKState& s, double b2) {
+  const double b = sqrt(b2);
+  s.beta = b;
+  if (!(b == b) || isinf(b)) {
+    s.stop = 1;
+    s.reason = 6;
+  } else if (b == 0.0 && s.init) {
+    s.beta1 = 0.0;
+    s.stop = 1;
+    s.reason = kStopExact;
   }
-  *st = s;
 }
 
-// ---------------------------------------------------------------- CSR products
-// CSR row dot with G lanes (used by the residual kernel).
-template <class TA, class V, class X>
-__device__ __forceinline__ V csr_dot(const int* __restrict__ rp, const int* __restrict__ ci,
-                                     const TA* __restrict__ val, const X* __restrict__ x, long long row, int lane,
-                                     int G) {
-  V acc = 0;
-  const int b = rp[row], e = rp[row + 1];
-  for (int k = b + lane; k < e; k += G) acc += (V)val[k] * (V)x[ci[k]];
-  for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-  return acc;
+// ---------------------------------------------------------------- consumer reductions
+// This thread's share of the producer partials part[0..count), in a fixed
+// order.  load() issues the first kShare * kBlock loads without using their
+// values (indices clamped into range), so that the caller's next loads issue
+// before the first wait; sum() masks and adds them.  Partials beyond the first
+// round (grids above kShare * kBlock workgroups) are summed at once.
+constexpr int kShare = 8;
+struct Share {
+  double t[kShare];
+  double rest;
+  int count;
+  __device__ __forceinline__ void load(const double* __restrict__ part, int count_) {
+    count = part ? count_ : 0;
+    rest = 0.0;
+    if (count <= 0) return;
+#pragma unroll
+    for (int q = 0; q < kShare; ++q) t[q] = part[min(q * kBlock + (int)threadIdx.x, count - 1)];
+    for (int i = kShare * kBlock + threadIdx.x; i < count; i += kBlock) rest += part[i];
+  }
+  __device__ __forceinline__ double sum() const {
+    double v = 0.0;
+    if (count <= 0) return v;
+#pragma unroll
+    for (int q = 0; q < kShare; ++q) v += (q * kBlock + (int)threadIdx.x < count) ? t[q] : 0.0;
+    return v + rest;
+  }
+};
+
+// Wave sums into red[]; the caller's barrier follows.
+__device__ __forceinline__ void publish(const Share& sh, double* red) {
+  const double v = wave_sum(sh.sum());
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
 }
 
-// CSR-stream product (after Greathouse & Daga, SC'14): workgroup j owns the
-// rows whose first non-zero lies in [j T, (j + 1) T) (precomputed row
-// blocks rb).  The workgroup loads the products val * x[col] of all its
-// non-zeros with coalesced loads into LDS, then groups of G lanes (G chosen
-// from the rows per workgroup) sum each row from LDS in a fixed order and
-// call epi(row, dot) once per row (lane 0 of the group).  Rows whose
-// non-zeros do not fit the LDS buffer are summed straight from memory by
-// the whole workgroup.  Returns nothing; the epilogue accumulates its own
-// norm partial.
-constexpr int kStreamT = 1024;   // target non-zeros per workgroup
-constexpr int kStreamCap = 4096; // LDS products per workgroup (32 KiB)
+__device__ __forceinline__ double settled(const double* red) {
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBlock / kWave; ++i) t += red[i];
+  return t;
+}
 
-template <class V, class TA, class X, class Epi>
-__device__ __forceinline__ void csr_stream(const int* __restrict__ rb, const int* __restrict__ rp,
+__device__ __forceinline__ void store_state(GKState* out, const GKState& s) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------- CSR-stream product
+// After Greathouse & Daga (SC'14): workgroup j owns the rows whose first
+// non-zero lies in [j T, (j + 1) T) (row blocks rbk[j] = {first row, its
+// first non-zero}).  In one dependent stage after rbk it loads its
+// non-zeros' values and columns, and each group of G lanes loads the
+// pointers and two epilogue operands (`pre`) of its first row; then it
+// gathers x[col], stores the products in LDS and, after the one barrier
+// (shared with the producer-partial reduction and `settle`, which advances
+// the state and may end the kernel), the groups sum their rows in a fixed
+// order and call epi(row, dot, pre0, pre1) in lane 0.  Row blocks whose
+// non-zeros exceed the LDS buffer (a row longer than about T) take a direct
+// workgroup-per-row path.  Returns false when `settle` ended the kernel.
+// The caller loads the row-block bounds a = rbk[j], b = rbk[j + 1] in its
+// first stage, together with the producer partials and the state.
+struct RowBlk {
+  int r0, k0;
+};
+
+template <class V, class TA, class X, class Pre, class Settle, class Epi>
+__device__ __forceinline__ bool csr_stream(RowBlk a, RowBlk b, const int* __restrict__ rp,
                                            const int* __restrict__ ci, const TA* __restrict__ val,
-                                           const X* __restrict__ x, int blk, Epi&& epi) {
+                                           const X* __restrict__ x, const Share& share, Pre&& pre,
+                                           Settle&& settle, Epi&& epi) {
   __shared__ V prod[kStreamCap];
-  const int r0 = rb[blk], r1 = rb[blk + 1];
-  if (r0 >= r1) return;
-  const int k0 = rp[r0], k1 = rp[r1];
-  const int cnt = k1 - k0;
-  const int rows = r1 - r0;
-  if (cnt <= kStreamCap) {
-#pragma unroll 4
-    for (int e = threadIdx.x; e < cnt; e += kBlock) prod[e] = (V)val[k0 + e] * (V)x[ci[k0 + e]];
-    __syncthreads();
-    int G = 1;
-    while (G < 64 && G * 2 * rows <= kBlock) G *= 2;
-    const int lane = threadIdx.x % G, grp = threadIdx.x / G, ngrp = kBlock / G;
+  __shared__ double red[kBlock / kWave];
+  const int r0 = a.r0, k0 = a.k0, rows = b.r0 - a.r0, cnt = b.k0 - a.k0;
+  const bool staged = cnt <= kStreamCap;
+  int G = 1;
+  while (G < 64 && G * 2 * rows <= kBlock) G *= 2;
+  const int lane = threadIdx.x % G, grp = threadIdx.x / G, ngrp = kBlock / G;
+  // Loads without branches (indices clamped into range, the matrix has at
+  // least one row), so that they all issue before the first wait.
+  const int rr = rows > 0 ? r0 + min(grp, rows - 1) : 0;
+  int lo = rp[rr] - k0, hi = rp[rr + 1] - k0;
+  V q0, q1;
+  pre(rr, q0, q1);
+  if (staged && cnt > 0) {
+    int cidx[kPer];
+    TA vv[kPer];
+    V xv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      const int idx = k0 + min(e, cnt - 1);
+      cidx[q] = ci[idx];
+      const TA t = val[idx];
+      vv[q] = e < cnt ? t : (TA)0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) xv[q] = (V)x[cidx[q]];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) prod[threadIdx.x + q * kBlock] = (V)vv[q] * xv[q];
+  }
+  publish(share, red);
+  __syncthreads();
+  if (!settle(settled(red))) return false;
+  if (staged) {
     for (int ri = grp; ri < rows; ri += ngrp) {
-      const int r = r0 + ri;
-      const int a = rp[r] - k0, z = rp[r + 1] - k0;
+      if (ri != grp) {
+        lo = rp[r0 + ri] - k0;
+        hi = rp[r0 + ri + 1] - k0;
+        pre(r0 + ri, q0, q1);
+      }
       V acc = 0;
-      for (int e = a + lane; e < z; e += G) acc += prod[e];
+      for (int e = lo + lane; e < hi; e += G) acc += prod[e];
       for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-      if (lane == 0) epi(r, acc);
+      if (lane == 0) epi(r0 + ri, acc, q0, q1);
     }
   } else {
-    for (int r = r0; r < r1; ++r) {
+    __shared__ double red2[kBlock / kWave];
+    for (int r = r0; r < r0 + rows; ++r) {
       V acc = 0;
-      for (int k = rp[r] + threadIdx.x; k < rp[r + 1]; k += kBlock) acc += (V)val[k] * (V)x[ci[k]];
-      __shared__ double red[kBlock / kWave];
-      double v = wave_sum((double)acc);
+      const int kb = rp[r], ke = rp[r + 1];
+      for (int k = kb + threadIdx.x; k < ke; k += kBlock) acc += (V)val[k] * (V)x[ci[k]];
+      const double v = wave_sum((double)acc);
       __syncthreads();
-      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+      if (threadIdx.x % kWave == 0) red2[threadIdx.x / kWave] = v;
       __syncthreads();
       if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kBlock / kWave; ++i) t += red[i];
-        epi(r, (V)t);
+        V p0 = 0, p1 = 0;
+        pre(r, p0, p1);
+        epi(r, (V)settled(red2), p0, p1);
       }
     }
   }
+  return true;
 }
 
-// Row blocks of the stream product: rb[j] = first row r with rp[r] >= j T
-// (j = 0 .. nb - 1) and rb[nb] = m, nb = nnz / T + 1.
-__global__ void k_row_blocks(const int* rp, long long m, int T, int* rb, int nb) {
+// rbk[j] = {first row r with rp[r] >= j T, rp[r]} (j < nb), rbk[nb] = {m, nnz},
+// nb = nnz / T + 1 (the last workgroup also owns trailing empty rows).
+__global__ void k_row_blocks(const int* rp, long long m, int T, RowBlk* rbk, int nb) {
   const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (r > m) return;
   const long long hi = (long long)rp[r] / T;
   const long long lo = (r == 0) ? 0 : (long long)rp[r - 1] / T + 1;
-  for (long long j = lo; j <= hi && j < nb; ++j) rb[j] = (int)r;
-  if (r == m) rb[nb] = (int)m;
+  for (long long j = lo; j <= hi && j < nb; ++j) rbk[j] = RowBlk{(int)r, rp[r]};
+  if (r == m) rbk[nb] = RowBlk{(int)m, rp[m]};
 }
 
-int stream_blocks(long long nnz) { return (int)(nnz / kStreamT) + 1; }
-
-void build_row_blocks(const int* rp, long long m, long long nnz, int* rb, hipStream_t s) {
-  const int nb = stream_blocks(nnz);
-  hipLaunchKernelGGL(k_row_blocks, dim3(ceil_div(m + 1, kBlock)), dim3(kBlock), 0, s, rp, m, kStreamT, rb, nb);
-}
-
-// Bottom (n-length) part of the forward kernel: u_bot update and the y/w
-// update of the previous iteration.
-template <class V>
-__device__ __forceinline__ double fwd_bottom(long long j, const V* tin, V* u_bot, const V* v, V* w, V* y,
-                                             double delta, V ts, V cu, bool pend, V cy, V cw) {
-  double sq = 0.0;
-  if (delta > 0.0) {
-    const V ub = (V)delta * (tin[j] * ts) - cu * u_bot[j];
-    u_bot[j] = ub;
-    sq = (double)ub * (double)ub;
+// Non-zeros per workgroup T: the grid of a product (nnz / T + 1 row blocks
+// plus the bottom blocks) should be resident at once (about 7 workgroups per
+// CU at this kernel's LDS and register use), so T grows from 1024 with nnz up
+// to 1536, which leaves LDS room for a row tail of 512 non-zeros.
+int stream_t(long long nnz) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cus = v;
   }
-  if (pend) {
-    const V vj = v[j] * ts;
-    const V wj = w[j];
-    y[j] += cy * wj;
-    w[j] = vj - cw * wj;
+  const long long resident = 7LL * cus - 64;
+  long long t = (nnz + resident - 1) / resident;
+  if (t < 1024) t = 1024;
+  if (t > 1536) t = 1536;
+  return (int)t;
+}
+int stream_blocks(long long nnz, int T) { return (int)(nnz / T) + 1; }
+long long row_block_words(long long nnz, int T) { return 2LL * (stream_blocks(nnz, T) + 1); }
+
+void build_row_blocks(const int* rp, long long m, long long nnz, int T, int* rb, hipStream_t s) {
+  const int nb = stream_blocks(nnz, T);
+  hipLaunchKernelGGL(k_row_blocks, dim3(ceil_div(m + 1, kBlock)), dim3(kBlock), 0, s, rp, m, T, (RowBlk*)rb, nb);
+}
+
+// ---------------------------------------------------------------- forward kernels
+// Modes: PLAIN finishes alpha from the backward kernel's partials (slot 1 ->
+// slot 0) and applies the y/w update; PRE reads slot 0 (alpha finished by
+// the P^{-1} kernel); MATVEC uses slot 0 as given (alpha = beta = 1).
+enum FwdMode { kFwdPlain = 0, kFwdPre = 1, kFwdMatvec = 2 };
+
+template <class V>
+__device__ __forceinline__ void final_y(long long n, V* y, const V* w, const GKState& s, long long first,
+                                        long long stride) {
+  if (!s.pending) return;
+  const V cy = (V)s.coef_y;
+  for (long long j = first; j < n; j += stride) y[j] += cy * w[j];
+}
+
+// Bottom rows of the forward kernel: u_bot <- delta tin/alpha - (alpha/beta) u_bot,
+// and the y/w update of the previous iteration (PLAIN).
+template <class V, int MODE>
+__device__ __forceinline__ double fwd_bottom(long long n, const V* tin, V* u_bot, const V* v, V* w, V* y,
+                                             GKState& s, GKState* __restrict__ st_out, const Share& share,
+                                             long long first,
+                                             long long stride) {
+  __shared__ double red[kBlock / kWave];
+  const double delta = s.delta;
+  V t0 = 0, ub0 = 0, v0 = 0, w0 = 0, y0 = 0;
+  const long long j0 = first < n ? first : n - 1;  // in range (n >= 1); unused if first >= n
+  if (MODE != kFwdMatvec) {
+    t0 = tin[j0];
+    ub0 = u_bot[j0];
+  }
+  if (MODE == kFwdPlain) {
+    v0 = v[j0];
+    w0 = w[j0];
+    y0 = y[j0];
+  }
+  publish(share, red);
+  __syncthreads();
+  if (MODE == kFwdPlain) {
+    scalar_step(s, sqrt(settled(red)));
+    store_state(st_out, s);
+    if (s.stop) {
+      final_y<V>(n, y, w, s, first, stride);
+      return -1.0;
+    }
+  }
+  const V ts = (V)(1.0 / s.alpha), cu = (V)(s.alpha / s.beta);
+  const bool pend = (MODE == kFwdPlain) && s.pending;
+  const V cy = (V)s.coef_y, cw = (V)s.coef_w;
+  double sq = 0.0;
+  for (long long j = first; j < n; j += stride) {
+    V tj = t0, ubj = ub0, vj = v0, wj = w0, yj = y0;
+    if (j != first) {
+      if (delta > 0.0) {
+        tj = tin[j];
+        ubj = u_bot[j];
+      }
+      if (pend) {
+        vj = v[j];
+        wj = w[j];
+        yj = y[j];
+      }
+    }
+    if (delta > 0.0) {
+      const V ub = (V)delta * (tj * ts) - cu * ubj;
+      u_bot[j] = ub;
+      sq += (double)ub * (double)ub;
+    }
+    if (pend) {
+      y[j] = yj + cy * wj;
+      w[j] = vj * ts - cw * wj;
+    }
   }
   return sq;
 }
 
-// u_top <- A (tin / alpha) - (alpha / beta) u_top ; u_bot <- delta tin/alpha - (alpha/beta) u_bot;
-// partials of ||u||^2.  `pend_ok`: apply the pending y/w update (no preconditioner).
-template <class TA, class V>
+// u_top <- A (tin / alpha) - (alpha / beta) u_top ; u_bot likewise; partials of ||u||^2.
+template <class TA, class V, int MODE>
 __global__ void __launch_bounds__(kBlock)
-    k_fwd_csr(const int* __restrict__ rb, const int* __restrict__ rp, const int* __restrict__ ci,
-              const TA* __restrict__ val, long long m, long long n, const V* tin, V* u_top, V* u_bot, const V* v, V* w,
-              V* y, const GKState* st, double* beta_part, int row_blocks, int pend_ok) {
-  if (stopped(st)) return;
-  const double alpha = st->alpha, beta = st->beta, delta = st->delta;
-  const V ts = (V)(1.0 / alpha), cu = (V)(alpha / beta);
+    k_fwd_csr(const RowBlk* __restrict__ rbk, const int* __restrict__ rp, const int* __restrict__ ci,
+              const TA* __restrict__ val, long long n, const V* tin, V* u_top, V* u_bot, const V* v, V* w, V* y,
+              const GKState* __restrict__ st_in, GKState* __restrict__ st_out, const double* alpha_part,
+              int alpha_count, double* beta_part, int row_blocks) {
+  const bool rows_part = (int)blockIdx.x < row_blocks;
+  RowBlk ra{0, 0}, rb{0, 0};
+  if (rows_part) {
+    ra = rbk[blockIdx.x];
+    rb = rbk[blockIdx.x + 1];
+  }
+  GKState s = *st_in;
+  Share share;
+  share.load(MODE == kFwdPlain ? alpha_part : nullptr, alpha_count);
+  if (MODE != kFwdMatvec && s.stop) {
+    if (MODE == kFwdPlain) store_state(st_out, s);
+    return;
+  }
   double sq = 0.0;
-  if ((int)blockIdx.x < row_blocks) {
-    csr_stream<V>(rb, rp, ci, val, tin, blockIdx.x, [&](int r, V dot) {
-      const V un = dot * ts - cu * u_top[r];
-      u_top[r] = un;
-      sq += (double)un * (double)un;
-    });
+  if (rows_part) {
+    V ts = 0, cu = 0;
+    const bool ran = csr_stream<V>(
+        ra, rb, rp, ci, val, tin, share,
+        [&](int r, V& q0, V& q1) {
+          q0 = u_top[r];
+          q1 = 0;
+        },
+        [&](double total) {
+          if (MODE == kFwdPlain) {
+            scalar_step(s, sqrt(total));
+            store_state(st_out, s);
+          }
+          ts = (V)(1.0 / s.alpha);
+          cu = (V)(s.alpha / s.beta);
+          return !s.stop;
+        },
+        [&](int r, V dot, V q0, V) {
+          const V un = dot * ts - cu * q0;
+          u_top[r] = un;
+          sq += (double)un * (double)un;
+        });
+    if (!ran) return;
   } else {
-    const bool pend = pend_ok && st->pending;
-    const V cy = (V)st->coef_y, cw = (V)st->coef_w;
-    const int nb = gridDim.x - row_blocks;
-    for (long long j = (long long)(blockIdx.x - row_blocks) * kBlock + threadIdx.x; j < n; j += (long long)nb * kBlock)
-      sq += fwd_bottom<V>(j, tin, u_bot, v, w, y, delta, ts, cu, pend, cy, cw);
+    const long long stride = (long long)(gridDim.x - row_blocks) * kBlock;
+    sq = fwd_bottom<V, MODE>(n, tin, u_bot, v, w, y, s, st_out, share,
+                             (long long)(blockIdx.x - row_blocks) * kBlock + threadIdx.x, stride);
+    if (MODE == kFwdPlain && s.stop) return;
   }
   const double bs = block_sum(sq);
   if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
 }
 
-// Dense row-major A: one wave per row.
-template <class TA, class V>
+// Dense row-major A: one wave per row (grid-stride).
+template <class TA, class V, int MODE>
 __global__ void __launch_bounds__(kBlock)
     k_fwd_dense(const TA* __restrict__ A, long long m, long long n, long long ld, const V* tin, V* u_top, V* u_bot,
-                const V* v, V* w, V* y, const GKState* st, double* beta_part, int row_blocks, int pend_ok) {
-  if (stopped(st)) return;
-  const double alpha = st->alpha, beta = st->beta, delta = st->delta;
-  const V ts = (V)(1.0 / alpha), cu = (V)(alpha / beta);
+                const V* v, V* w, V* y, const GKState* __restrict__ st_in, GKState* __restrict__ st_out,
+                const double* alpha_part, int alpha_count, double* beta_part, int row_blocks) {
+  GKState s = *st_in;
+  Share share;
+  share.load(MODE == kFwdPlain ? alpha_part : nullptr, alpha_count);
+  if (MODE != kFwdMatvec && s.stop) {
+    if (MODE == kFwdPlain) store_state(st_out, s);
+    return;
+  }
   double sq = 0.0;
   if ((int)blockIdx.x < row_blocks) {
+    __shared__ double red[kBlock / kWave];
+    publish(share, red);
+    __syncthreads();
+    if (MODE == kFwdPlain) {
+      scalar_step(s, sqrt(settled(red)));
+      store_state(st_out, s);
+      if (s.stop) return;
+    }
+    const V ts = (V)(1.0 / s.alpha), cu = (V)(s.alpha / s.beta);
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     constexpr int rpb = kBlock / kWave;
     for (long long row = (long long)blockIdx.x * rpb + wv; row < m; row += (long long)row_blocks * rpb) {
@@ -297,26 +460,29 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
   } else {
-    const bool pend = pend_ok && st->pending;
-    const V cy = (V)st->coef_y, cw = (V)st->coef_w;
-    const int nb = gridDim.x - row_blocks;
-    for (long long j = (long long)(blockIdx.x - row_blocks) * kBlock + threadIdx.x; j < n; j += (long long)nb * kBlock)
-      sq += fwd_bottom<V>(j, tin, u_bot, v, w, y, delta, ts, cu, pend, cy, cw);
+    const long long stride = (long long)(gridDim.x - row_blocks) * kBlock;
+    sq = fwd_bottom<V, MODE>(n, tin, u_bot, v, w, y, s, st_out, share,
+                             (long long)(blockIdx.x - row_blocks) * kBlock + threadIdx.x, stride);
+    if (MODE == kFwdPlain && s.stop) return;
   }
   const double bs = block_sum(sq);
   if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
 }
 
-// Backward epilogue: g = (dot + delta u_bot) / beta.  PLAIN: v_raw <- g -
-// (beta/alpha) v_raw (g at the phase start); otherwise g is stored for P^{-T}.
-// Returns the squared entry for the norm partials.
+// ---------------------------------------------------------------- backward kernels
+// beta from the forward (or residual) partials (slot 0 -> slot 1), unless
+// beta_part is null (then the state's beta is kept); g = (A^T u_top +
+// delta u_bot) / beta.  PLAIN: v_raw <- g - (beta/alpha) v_raw (g at the
+// phase start); otherwise g is stored for P^{-T}.  Partials of the produced
+// vector's squared norm; zero partials when beta = 0 (exact solution: the
+// next alpha is 0 and the scalar step stops).
 template <class V, bool PLAIN>
-__device__ __forceinline__ double bwd_epilogue(long long j, V dot, const V* u_bot, V* v, V* g, double delta, V ib,
-                                               V cv, int init) {
+__device__ __forceinline__ double bwd_epilogue(long long j, V dot, V ubj, V vj, V* v, V* g, double delta, V ib, V cv,
+                                               int init) {
   V gj = dot * ib;
-  if (delta > 0.0) gj += (V)delta * u_bot[j] * ib;
+  if (delta > 0.0) gj += (V)delta * ubj * ib;
   if (PLAIN) {
-    const V vn = init ? gj : gj - cv * v[j];
+    const V vn = init ? gj : gj - cv * vj;
     v[j] = vn;
     return (double)vn * (double)vn;
   } else {
@@ -325,18 +491,67 @@ __device__ __forceinline__ double bwd_epilogue(long long j, V dot, const V* u_bo
   }
 }
 
-template <class TA, class V, bool PLAIN>
+struct BwdScal {
+  double ib, cv;
+  bool zero;
+};
+
+// Finishes beta from `total` (or keeps the state's beta); workgroup 0
+// stores the advanced state.
+__device__ __forceinline__ bool bwd_settle(const GKState* __restrict__ st_in, GKState* __restrict__ st_out,
+                                          bool finish_beta, double total, BwdScal& k) {
+  double beta = st_in->beta;
+  int stop = 0;
+  if (finish_beta) {
+    beta = sqrt(total);
+    stop = !(beta == beta) || isinf(beta) || (beta == 0.0 && st_in->init);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    GKState o = *st_in;
+    if (finish_beta) beta_step(o, total);
+    *st_out = o;
+  }
+  if (stop) return false;
+  if (beta == 0.0) {
+    k.zero = true;
+    return false;
+  }
+  k.ib = 1.0 / beta;
+  k.cv = beta / st_in->alpha;
+  return true;
+}
+
+template <class TA, class V, bool PLAIN, bool BOT>
 __global__ void __launch_bounds__(kBlock)
-    k_bwd_csr(const int* __restrict__ trb, const int* __restrict__ tp, const int* __restrict__ ti,
-              const TA* __restrict__ tv, long long n, const V* u_top, const V* u_bot, V* v, V* g, const GKState* st,
-              double* alpha_part) {
-  if (stopped(st)) return;
-  const double beta = st->beta, alpha = st->alpha, delta = st->delta;
-  const int init = st->init;
-  const V ib = (V)(1.0 / beta), cv = (V)(beta / alpha);
+    k_bwd_csr(const RowBlk* __restrict__ trbk, const int* __restrict__ tp, const int* __restrict__ ti,
+              const TA* __restrict__ tv, const V* u_top, const V* u_bot, V* v, V* g,
+              const GKState* __restrict__ st_in, GKState* __restrict__ st_out, const double* beta_part,
+              int beta_count, double* alpha_part) {
+  const RowBlk ra = trbk[blockIdx.x], rb = trbk[blockIdx.x + 1];
+  const int stop0 = st_in->stop, init = st_in->init;
+  const double delta = st_in->delta;
+  Share share;
+  share.load(beta_part, beta_count);
+  if (stop0) {
+    store_state(st_out, *st_in);
+    return;
+  }
+  BwdScal k{0.0, 0.0, false};
   double sq = 0.0;
-  csr_stream<V>(trb, tp, ti, tv, u_top, blockIdx.x,
-                [&](int j, V dot) { sq += bwd_epilogue<V, PLAIN>(j, dot, u_bot, v, g, delta, ib, cv, init); });
+  const bool ran = csr_stream<V>(
+      ra, rb, tp, ti, tv, u_top, share,
+      [&](int j, V& q0, V& q1) {
+        q0 = BOT ? u_bot[j] : (V)0;
+        q1 = PLAIN ? v[j] : (V)0;
+      },
+      [&](double total) { return bwd_settle(st_in, st_out, beta_part != nullptr, total, k); },
+      [&](int j, V dot, V q0, V q1) {
+        sq += bwd_epilogue<V, PLAIN>(j, dot, q0, q1, v, g, delta, (V)k.ib, (V)k.cv, init);
+      });
+  if (!ran) {
+    if (k.zero && threadIdx.x == 0) alpha_part[blockIdx.x] = 0.0;
+    return;
+  }
   const double bs = block_sum(sq);
   if (threadIdx.x == 0) alpha_part[blockIdx.x] = bs;
 }
@@ -345,8 +560,8 @@ __global__ void __launch_bounds__(kBlock)
 template <class TA, class V>
 __global__ void __launch_bounds__(kBlock)
     k_bwd_dense_part(const TA* __restrict__ A, long long m, long long n, long long ld, const V* __restrict__ u_top,
-                     double* part, long long rpc, const GKState* st) {
-  if (st && stopped(st)) return;
+                     double* part, long long rpc, const GKState* __restrict__ sl) {
+  if (sl && sl->stop) return;
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= n) return;
   const long long i0 = (long long)blockIdx.y * rpc;
@@ -359,29 +574,47 @@ __global__ void __launch_bounds__(kBlock)
 template <class V, bool PLAIN>
 __global__ void __launch_bounds__(kBlock)
     k_bwd_dense_red(const double* __restrict__ part, int chunks, long long n, const V* u_bot, V* v, V* g,
-                    const GKState* st, double* alpha_part) {
-  if (stopped(st)) return;
-  const double beta = st->beta, alpha = st->alpha, delta = st->delta;
-  const int init = st->init;
-  const V ib = (V)(1.0 / beta), cv = (V)(beta / alpha);
+                    const GKState* __restrict__ st_in, GKState* __restrict__ st_out, const double* beta_part,
+                    int beta_count, double* alpha_part) {
+  __shared__ double red[kBlock / kWave];
+  Share share;
+  share.load(beta_part, beta_count);
+  if (st_in->stop) {
+    store_state(st_out, *st_in);
+    return;
+  }
+  BwdScal k{0.0, 0.0, false};
+  publish(share, red);
+  __syncthreads();
+  if (!bwd_settle(st_in, st_out, beta_part != nullptr, settled(red), k)) {
+    if (k.zero && threadIdx.x == 0) alpha_part[blockIdx.x] = 0.0;
+    return;
+  }
+  const double delta = st_in->delta;
+  const int init = st_in->init;
   double sq = 0.0;
   for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < n; j += (long long)gridDim.x * kBlock) {
     double acc = 0.0;
     for (int c = 0; c < chunks; ++c) acc += part[(long long)c * n + j];
-    sq += bwd_epilogue<V, PLAIN>(j, (V)acc, u_bot, v, g, delta, ib, cv, init);
+    const V ubj = delta > 0.0 ? u_bot[j] : (V)0;
+    const V vj = (PLAIN && !init) ? v[j] : (V)0;
+    sq += bwd_epilogue<V, PLAIN>(j, (V)acc, ubj, vj, v, g, delta, (V)k.ib, (V)k.cv, init);
   }
   const double bs = block_sum(sq);
   if (threadIdx.x == 0) alpha_part[blockIdx.x] = bs;
 }
 
-// ---------------------------------------------------------------- explicit P apply
-// c = d .* (V^T z): chunk partials (threads along the ell columns of the
-// row-major V), then an ordered sum over chunks.
+// ---------------------------------------------------------------- P^{-1} coefficients
+// Both forms apply P^{-1} z = z + V (d .* (V^T z)) with V = Q_R V_M.
+// Explicit (dense A): V row-major n x ell; c = d .* (V^T z) by chunk partials
+// and an ordered chunk sum.  Implicit (CSR A): Q_R = R^T T_R^{-1} with
+// R = A(I,:), so V = R^T K, K = T_R^{-1} V_M (ell x ell); c1 = R z,
+// w = d .* (K^T c1), c = K w, and the consumer adds R^T c.
 template <class V>
 __global__ void __launch_bounds__(kBlock)
     k_pa_part(const double* __restrict__ Vh, long long n, int ell, long long ldv, const V* __restrict__ z,
-              double* part, long long rpc, const GKState* st) {
-  if (st && stopped(st)) return;
+              double* part, long long rpc, const GKState* sl) {
+  if (sl && sl->stop) return;
   const int k = blockIdx.x * kBlock + threadIdx.x;
   if (k >= ell) return;
   const long long i0 = (long long)blockIdx.y * rpc;
@@ -391,16 +624,62 @@ __global__ void __launch_bounds__(kBlock)
   part[(long long)blockIdx.y * ell + k] = acc;
 }
 
-__global__ void k_pa_red(const double* __restrict__ part, int chunks, int ell, const double* __restrict__ d,
-                         double* c, const GKState* st) {
-  if (st && stopped(st)) return;
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= ell) return;
+// 64 columns per workgroup, the four waves take chunks q, q + 4, ... and are
+// summed in order.
+__global__ void __launch_bounds__(kBlock)
+    k_pa_red(const double* __restrict__ part, int chunks, int ell, const double* __restrict__ d, double* c,
+             const GKState* sl) {
+  __shared__ double acc4[kBlock / kWave][kWave];
+  if (sl && sl->stop) return;
+  const int col = blockIdx.x * kWave + threadIdx.x % kWave, q = threadIdx.x / kWave;
   double acc = 0.0;
-  for (int ch = 0; ch < chunks; ++ch) acc += part[(long long)ch * ell + k];
-  c[k] = d[k] * acc;
+  if (col < ell) {
+#pragma unroll 4
+    for (int ch = q; ch < chunks; ch += kBlock / kWave) acc += part[(long long)ch * ell + col];
+  }
+  acc4[q][threadIdx.x % kWave] = acc;
+  __syncthreads();
+  if (q == 0 && col < ell) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) t += acc4[i][threadIdx.x];
+    c[col] = d[col] * t;
+  }
 }
 
+// c1[k] = A(I[k], :) . z  (groups of 16 lanes per row).
+template <class TA, class V>
+__global__ void __launch_bounds__(kBlock)
+    k_pr_rz(const int* __restrict__ rp, const int* __restrict__ ci, const TA* __restrict__ val,
+            const int* __restrict__ I, int ell, const V* __restrict__ z, double* c1, const GKState* sl) {
+  constexpr int G = 16;
+  if (sl && sl->stop) return;
+  const int k = blockIdx.x * (kBlock / G) + threadIdx.x / G, lane = threadIdx.x % G;
+  if (k >= ell) return;  // whole groups leave together
+  const int r = I[k];
+  double acc = 0.0;
+  for (int e = rp[r] + lane; e < rp[r + 1]; e += G) acc += (double)val[e] * (double)z[ci[e]];
+  for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  if (lane == 0) c1[k] = acc;
+}
+
+// y = diag(dscale) M x (dscale may be null), M row-major ell x ell; one wave per row.
+__global__ void __launch_bounds__(kBlock)
+    k_pr_gemv(const double* __restrict__ M, int ell, const double* __restrict__ x, const double* __restrict__ dscale,
+              double* y, const GKState* sl) {
+  if (sl && sl->stop) return;
+  const int row = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (row >= ell) return;
+  const double* a = M + (long long)row * ell;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int k = lane; k < ell; k += kWave) acc += a[k] * x[k];
+  acc = wave_sum(acc);
+  if (lane == 0) y[row] = dscale ? dscale[row] * acc : acc;
+}
+
+// (P^{-1} - I) z at row j: the explicit row dot V(j,:) . c (one wave) or the
+// implicit R^T row (one thread).
 __device__ __forceinline__ double vrow_dot(const double* __restrict__ Vh, long long ldv, int ell,
                                            const double* __restrict__ c, long long i, int lane) {
   double acc = 0.0;
@@ -409,66 +688,89 @@ __device__ __forceinline__ double vrow_dot(const double* __restrict__ Vh, long l
   return wave_sum(acc);
 }
 
-// t = v_raw + V c  (= P^{-1} v_raw) and the pending y/w update.
-template <class V>
-__global__ void __launch_bounds__(kBlock)
-    k_pa_fwd(const double* __restrict__ Vh, long long n, int ell, long long ldv, const double* __restrict__ c,
-             const V* v, V* t, V* w, V* y, const GKState* st) {
-  if (stopped(st)) return;
-  const bool pend = st->pending;
-  const double cy = st->coef_y, cw = st->coef_w, ia = 1.0 / st->alpha;
-  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  constexpr int rpb = kBlock / kWave;
-  for (long long i = (long long)blockIdx.x * rpb + wv; i < n; i += (long long)gridDim.x * rpb) {
-    const double dot = vrow_dot(Vh, ldv, ell, c, i, lane);
-    if (lane == 0) {
-      const V vi = v[i];
-      t[i] = (V)((double)vi + dot);
-      if (pend) {
-        const V wi = w[i];
-        y[i] += (V)cy * wi;
-        w[i] = (V)((double)vi * ia) - (V)cw * wi;
-      }
+__device__ __forceinline__ double rt_dot(const int* __restrict__ tp, const int* __restrict__ ti,
+                                         const double* __restrict__ tv, const double* __restrict__ c, long long j) {
+  double acc = 0.0;
+  for (int e = tp[j]; e < tp[j + 1]; ++e) acc += tv[e] * c[ti[e]];
+  return acc;
+}
+
+// Row loop of the P-apply consumers: one wave per row (explicit) or one
+// thread per row (implicit); f(j, dot) runs in one lane per row.
+template <class F>
+__device__ __forceinline__ void prec_rows(const PrecDesc& P, long long n, F&& f) {
+  if (!P.implicit) {
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    constexpr int rpb = kBlock / kWave;
+    for (long long i = (long long)blockIdx.x * rpb + wv; i < n; i += (long long)gridDim.x * rpb) {
+      const double dot = vrow_dot(P.V, P.ldv, P.ell, P.c, i, lane);
+      if (lane == 0) f(i, dot);
     }
+  } else {
+    for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < n; j += (long long)gridDim.x * kBlock)
+      f(j, rt_dot(P.rt_ptr, P.rt_idx, P.rt_val, P.c, j));
   }
 }
 
-// v_raw <- (g + V c) - (beta/alpha) v_raw  (g + V c at the phase start);
-// partials of ||v_raw||^2.
+// First kernel of a preconditioned iteration: finishes alpha (partials of
+// the previous P^{-T} kernel; slot 1 -> slot 0), takes the scalar step,
+// applies the y/w update and forms t = P^{-1} v_raw = v_raw + (P^{-1} - I) v_raw.
 template <class V>
 __global__ void __launch_bounds__(kBlock)
-    k_pa_bwd(const double* __restrict__ Vh, long long n, int ell, long long ldv, const double* __restrict__ c,
-             const V* g, V* v, const GKState* st, double* alpha_part) {
-  if (stopped(st)) return;
-  const int init = st->init;
-  const double cv = st->beta / st->alpha;
-  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  constexpr int rpb = kBlock / kWave;
-  double sq = 0.0;
-  for (long long i = (long long)blockIdx.x * rpb + wv; i < n; i += (long long)gridDim.x * rpb) {
-    const double dot = vrow_dot(Vh, ldv, ell, c, i, lane);
-    if (lane == 0) {
-      const double pg = (double)g[i] + dot;
-      const V vn = init ? (V)pg : (V)(pg - cv * (double)v[i]);
-      v[i] = vn;
-      sq += (double)vn * (double)vn;
-    }
+    k_pa_fwd(const PrecDesc P, long long n, const V* v, V* t, V* w, V* y, const GKState* __restrict__ st_in,
+             GKState* __restrict__ st_out, const double* alpha_part, int alpha_count) {
+  __shared__ double red[kBlock / kWave];
+  GKState s = *st_in;
+  Share share;
+  share.load(alpha_part, alpha_count);
+  if (s.stop) {
+    store_state(st_out, s);
+    return;
   }
+  publish(share, red);
+  __syncthreads();
+  scalar_step(s, sqrt(settled(red)));
+  store_state(st_out, s);
+  if (s.stop) {
+    final_y<V>(n, y, w, s, (long long)blockIdx.x * kBlock + threadIdx.x, (long long)gridDim.x * kBlock);
+    return;
+  }
+  const bool pend = s.pending;
+  const double cy = s.coef_y, cw = s.coef_w, ia = 1.0 / s.alpha;
+  prec_rows(P, n, [&](long long i, double dot) {
+    const V vi = v[i];
+    t[i] = (V)((double)vi + dot);
+    if (pend) {
+      const V wi = w[i];
+      y[i] += (V)cy * wi;
+      w[i] = (V)((double)vi * ia) - (V)cw * wi;
+    }
+  });
+}
+
+// v_raw <- P^{-1} g - (beta/alpha) v_raw  (P^{-1} g at the phase start);
+// partials of ||v_raw||^2 (slot 1 holds beta).
+template <class V>
+__global__ void __launch_bounds__(kBlock)
+    k_pa_bwd(const PrecDesc P, long long n, const V* g, V* v, const GKState* __restrict__ sl, double* alpha_part) {
+  if (sl->stop) return;
+  const int init = sl->init;
+  const double cv = sl->beta / sl->alpha;
+  double sq = 0.0;
+  prec_rows(P, n, [&](long long i, double dot) {
+    const double pg = (double)g[i] + dot;
+    const V vn = init ? (V)pg : (V)(pg - cv * (double)v[i]);
+    v[i] = vn;
+    sq += (double)vn * (double)vn;
+  });
   const double bs = block_sum(sq);
   if (threadIdx.x == 0) alpha_part[blockIdx.x] = bs;
 }
 
-// x += y + V c  (x in FP64).
+// x += P^{-1} y  (x in FP64).
 template <class V>
-__global__ void __launch_bounds__(kBlock)
-    k_pa_x(const double* __restrict__ Vh, long long n, int ell, long long ldv, const double* __restrict__ c,
-           const V* y, double* x) {
-  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  constexpr int rpb = kBlock / kWave;
-  for (long long i = (long long)blockIdx.x * rpb + wv; i < n; i += (long long)gridDim.x * rpb) {
-    const double dot = vrow_dot(Vh, ldv, ell, c, i, lane);
-    if (lane == 0) x[i] += (double)y[i] + dot;
-  }
+__global__ void __launch_bounds__(kBlock) k_pa_x(const PrecDesc P, long long n, const V* y, double* x) {
+  prec_rows(P, n, [&](long long i, double dot) { x[i] += (double)y[i] + dot; });
 }
 
 // ---------------------------------------------------------------- phase start / end
@@ -476,21 +778,35 @@ __global__ void __launch_bounds__(kBlock)
 // partials of ||r||^2.
 template <class TA>
 __global__ void __launch_bounds__(kBlock)
-    k_resid_csr(const int* __restrict__ rp, const int* __restrict__ ci, const TA* __restrict__ val, long long m,
-                long long n, const double* __restrict__ b, const double* b_bot, double bot_scale, const double* x,
-                int x_zero, double* r_top, double* r_bot, const GKState* st, double* beta_part, int G,
-                int row_blocks) {
-  const double delta = st->delta;
+    k_resid_csr(const RowBlk* __restrict__ rbk, const int* __restrict__ rp, const int* __restrict__ ci,
+                const TA* __restrict__ val, long long m, long long n, const double* __restrict__ b,
+                const double* b_bot, double bot_scale, const double* x, int x_zero, double* r_top, double* r_bot,
+                const GKState* __restrict__ sl, double* beta_part, int row_blocks) {
+  const double delta = sl->delta;
   double sq = 0.0;
   if ((int)blockIdx.x < row_blocks) {
-    const int rpb = kBlock / G, lane = threadIdx.x % G;
-    for (long long row = (long long)blockIdx.x * rpb + threadIdx.x / G; row < m; row += (long long)row_blocks * rpb) {
-      const double dot = x_zero ? 0.0 : csr_dot<TA, double>(rp, ci, val, x, row, lane, G);
-      if (lane == 0) {
-        const double r = (b ? b[row] : 0.0) - dot;
-        r_top[row] = r;
-        sq += r * r;
+    const RowBlk a = rbk[blockIdx.x], bb = rbk[blockIdx.x + 1];
+    if (x_zero) {
+      for (int r = a.r0 + threadIdx.x; r < bb.r0; r += kBlock) {
+        const double rr = b ? b[r] : 0.0;
+        r_top[r] = rr;
+        sq += rr * rr;
       }
+    } else {
+      Share none;
+      none.load(nullptr, 0);
+      csr_stream<double>(
+          a, bb, rp, ci, val, x, none,
+          [&](int r, double& q0, double& q1) {
+            q0 = b ? b[r] : 0.0;
+            q1 = 0.0;
+          },
+          [&](double) { return true; },
+          [&](int r, double dot, double q0, double) {
+            const double rr = q0 - dot;
+            r_top[r] = rr;
+            sq += rr * rr;
+          });
     }
   } else if (delta > 0.0) {
     const int nb = gridDim.x - row_blocks;
@@ -509,8 +825,8 @@ template <class TA>
 __global__ void __launch_bounds__(kBlock)
     k_resid_dense(const TA* __restrict__ A, long long m, long long n, long long ld, const double* __restrict__ b,
                   const double* b_bot, double bot_scale, const double* x, int x_zero, double* r_top, double* r_bot,
-                  const GKState* st, double* beta_part, int row_blocks) {
-  const double delta = st->delta;
+                  const GKState* __restrict__ sl, double* beta_part, int row_blocks) {
+  const double delta = sl->delta;
   double sq = 0.0;
   if ((int)blockIdx.x < row_blocks) {
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -541,13 +857,23 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
 }
 
-// Phase end: the last pending y update (w is not needed afterwards).
-template <class V>
-__global__ void k_finalize(long long n, V* y, const V* w, const GKState* st) {
-  if (!st->pending) return;
-  const V cy = (V)st->coef_y;
-  for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < n; j += (long long)gridDim.x * kBlock)
-    y[j] += cy * w[j];
+// One workgroup: finish a reduction into slot 0.  mode 0: alpha and the
+// scalar step (slot 1 -> slot 0); mode 1: beta (slot 0 -> slot 0).
+__global__ void __launch_bounds__(kBlock) k_consume(GKState* st, const double* part, int count, int mode) {
+  __shared__ double red[kBlock / kWave];
+  GKState s = st[mode == 0 ? 1 : 0];
+  Share share;
+  share.load(part, count);
+  publish(share, red);
+  __syncthreads();
+  if (!s.stop) {
+    if (mode == 0)
+      scalar_step(s, sqrt(settled(red)));
+    else
+      beta_step(s, settled(red));
+  }
+  __syncthreads();
+  store_state(&st[0], s);
 }
 
 template <class V>
@@ -572,144 +898,164 @@ template void fill_zero<double>(double*, long long, hipStream_t);
 template void fill_zero<float>(float*, long long, hipStream_t);
 
 // ---------------------------------------------------------------- host launchers
-static unsigned clamp_grid(long long want) {
+static unsigned clamp_grid(long long want, long long cap = kMaxGrid) {
   if (want < 1) return 1;
-  return (unsigned)(want > kMaxGrid ? kMaxGrid : want);
+  return (unsigned)(want > cap ? cap : want);
 }
-static unsigned nbottom(long long n) {
-  long long b = (n + kBlock - 1) / kBlock;
-  if (b < 1) b = 1;
-  return (unsigned)(b > 256 ? 256 : b);
-}
+static unsigned nbottom(long long n) { return clamp_grid(ceil_div(n, kBlock), 64); }
 static unsigned fwd_row_blocks(const OpDesc& A) {
-  if (A.csr) return (unsigned)stream_blocks(A.nnz);
+  if (A.csr) return (unsigned)stream_blocks(A.nnz, A.stream_t);
   return clamp_grid((A.m + 3) / 4);
 }
 static unsigned bwd_grid(const OpDesc& A) {
-  if (A.csr) return (unsigned)stream_blocks(A.nnz);
-  return clamp_grid(ceil_div(A.n, kBlock));
+  if (A.csr) return (unsigned)stream_blocks(A.nnz, A.stream_t);
+  return clamp_grid(ceil_div(A.n, kBlock), 1024);
 }
-static unsigned rows_grid(long long n) { return clamp_grid((n + 3) / 4); }
-
-static void finish(GKState* st, GKWork& wk, int mode, hipStream_t s) {
-  if (mode == kFinBeta)
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, st, wk.beta_part, (int)wk.beta_count, mode);
-  else
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, st, wk.alpha_part, (int)wk.alpha_count, mode);
+static unsigned prec_grid(const PrecDesc& P, long long n) {
+  return P.implicit ? clamp_grid(ceil_div(n, kBlock), kRowsMaxGrid) : clamp_grid((n + 3) / 4, kRowsMaxGrid);
 }
 
-template <class V>
-static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, const GKState* st, GKWork& wk, int pend_ok,
-                       hipStream_t s) {
+template <class V, int MODE>
+static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s) {
   const unsigned rb = fwd_row_blocks(A);
   const unsigned grid = rb + nbottom(A.n);
+  const int ac = (int)wk.alpha_count;
+  const GKState* sin = st + (MODE == kFwdPlain ? 1 : 0);
+  GKState* sout = (MODE == kFwdPlain) ? st : nullptr;
   if (A.csr) {
+    const RowBlk* rbk = (const RowBlk*)A.rb;
     if (A.f64)
-      hipLaunchKernelGGL((k_fwd_csr<double, V>), dim3(grid), dim3(kBlock), 0, s, A.rb, A.row_ptr, A.col_idx,
-                         (const double*)A.val, A.m, A.n, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st,
-                         wk.beta_part, (int)rb, pend_ok);
+      hipLaunchKernelGGL((k_fwd_csr<double, V, MODE>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
+                         (const double*)A.val, A.n, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, sin,
+                         sout, wk.alpha_part, ac, wk.beta_part, (int)rb);
     else
-      hipLaunchKernelGGL((k_fwd_csr<float, V>), dim3(grid), dim3(kBlock), 0, s, A.rb, A.row_ptr, A.col_idx,
-                         (const float*)A.val, A.m, A.n, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st,
-                         wk.beta_part, (int)rb, pend_ok);
+      hipLaunchKernelGGL((k_fwd_csr<float, V, MODE>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
+                         (const float*)A.val, A.n, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, sin,
+                         sout, wk.alpha_part, ac, wk.beta_part, (int)rb);
   } else {
     if (A.f64)
-      hipLaunchKernelGGL((k_fwd_dense<double, V>), dim3(grid), dim3(kBlock), 0, s, (const double*)A.val, A.m, A.n,
-                         A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st, wk.beta_part, (int)rb, pend_ok);
+      hipLaunchKernelGGL((k_fwd_dense<double, V, MODE>), dim3(grid), dim3(kBlock), 0, s, (const double*)A.val, A.m,
+                         A.n, A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, sin, sout, wk.alpha_part,
+                         ac, wk.beta_part, (int)rb);
     else
-      hipLaunchKernelGGL((k_fwd_dense<float, V>), dim3(grid), dim3(kBlock), 0, s, (const float*)A.val, A.m, A.n,
-                         A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, st, wk.beta_part, (int)rb, pend_ok);
+      hipLaunchKernelGGL((k_fwd_dense<float, V, MODE>), dim3(grid), dim3(kBlock), 0, s, (const float*)A.val, A.m,
+                         A.n, A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, sin, sout, wk.alpha_part,
+                         ac, wk.beta_part, (int)rb);
   }
   wk.beta_count = grid;
 }
 
+// beta_from_part: finish beta from wk.beta_part (else the state's beta is kept).
 template <class V, bool PLAIN>
-static void launch_bwd(const OpDesc& A, const V* u_top, const V* u_bot, V* v, V* g, const GKState* st, GKWork& wk,
-                       hipStream_t s) {
+static void launch_bwd(const OpDesc& A, const V* u_top, const V* u_bot, V* v, V* g, GKState* st, GKWork& wk,
+                       bool beta_from_part, hipStream_t s) {
+  const double* bp = beta_from_part ? wk.beta_part : nullptr;
+  const int bc = (int)wk.beta_count;
+  const unsigned grid = bwd_grid(A);
   if (A.csr) {
-    const unsigned grid = bwd_grid(A);
-    if (A.f64)
-      hipLaunchKernelGGL((k_bwd_csr<double, V, PLAIN>), dim3(grid), dim3(kBlock), 0, s, A.t_rb, A.t_ptr, A.t_idx,
-                         (const double*)A.t_val, A.n, u_top, u_bot, v, g, st, wk.alpha_part);
-    else
-      hipLaunchKernelGGL((k_bwd_csr<float, V, PLAIN>), dim3(grid), dim3(kBlock), 0, s, A.t_rb, A.t_ptr, A.t_idx,
-                         (const float*)A.t_val, A.n, u_top, u_bot, v, g, st, wk.alpha_part);
-    wk.alpha_count = grid;
+    const RowBlk* trbk = (const RowBlk*)A.t_rb;
+    if (A.f64) {
+      if (u_bot)
+        hipLaunchKernelGGL((k_bwd_csr<double, V, PLAIN, true>), dim3(grid), dim3(kBlock), 0, s, trbk, A.t_ptr,
+                           A.t_idx, (const double*)A.t_val, u_top, u_bot, v, g, (const GKState*)st, st + 1, bp, bc,
+                           wk.alpha_part);
+      else
+        hipLaunchKernelGGL((k_bwd_csr<double, V, PLAIN, false>), dim3(grid), dim3(kBlock), 0, s, trbk, A.t_ptr,
+                           A.t_idx, (const double*)A.t_val, u_top, u_bot, v, g, (const GKState*)st, st + 1, bp, bc,
+                           wk.alpha_part);
+    } else {
+      if (u_bot)
+        hipLaunchKernelGGL((k_bwd_csr<float, V, PLAIN, true>), dim3(grid), dim3(kBlock), 0, s, trbk, A.t_ptr,
+                           A.t_idx, (const float*)A.t_val, u_top, u_bot, v, g, (const GKState*)st, st + 1, bp, bc,
+                           wk.alpha_part);
+      else
+        hipLaunchKernelGGL((k_bwd_csr<float, V, PLAIN, false>), dim3(grid), dim3(kBlock), 0, s, trbk, A.t_ptr,
+                           A.t_idx, (const float*)A.t_val, u_top, u_bot, v, g, (const GKState*)st, st + 1, bp, bc,
+                           wk.alpha_part);
+    }
   } else {
     const long long rpc = (A.m + A.chunks - 1) / A.chunks;
     dim3 g1(ceil_div(A.n, kBlock), A.chunks);
     if (A.f64)
       hipLaunchKernelGGL((k_bwd_dense_part<double, V>), g1, dim3(kBlock), 0, s, (const double*)A.val, A.m, A.n, A.ld,
-                         u_top, A.part, rpc, st);
+                         u_top, A.part, rpc, (const GKState*)st);
     else
       hipLaunchKernelGGL((k_bwd_dense_part<float, V>), g1, dim3(kBlock), 0, s, (const float*)A.val, A.m, A.n, A.ld,
-                         u_top, A.part, rpc, st);
-    const unsigned grid = bwd_grid(A);
+                         u_top, A.part, rpc, (const GKState*)st);
     hipLaunchKernelGGL((k_bwd_dense_red<V, PLAIN>), dim3(grid), dim3(kBlock), 0, s, A.part, A.chunks, A.n, u_bot, v,
-                       g, st, wk.alpha_part);
-    wk.alpha_count = grid;
+                       g, (const GKState*)st, st + 1, bp, bc, wk.alpha_part);
   }
+  wk.alpha_count = grid;
 }
 
+// P.c <- the coefficients of (P^{-1} - I) z (stop check on slot sl, or none).
 template <class V>
-static void launch_pa_c(const PrecDesc& P, long long n, const V* z, const GKState* st, hipStream_t s) {
-  const long long rpc = (n + P.chunks - 1) / P.chunks;
-  hipLaunchKernelGGL((k_pa_part<V>), dim3(ceil_div(P.ell, kBlock), P.chunks), dim3(kBlock), 0, s, P.V, n, P.ell,
-                     P.ldv, z, P.part, rpc, st);
-  hipLaunchKernelGGL(k_pa_red, dim3(ceil_div(P.ell, kBlock)), dim3(kBlock), 0, s, P.part, P.chunks, P.ell, P.d, P.c,
-                     st);
-}
-
-template <class V>
-static void launch_pa_bwd(const PrecDesc& P, long long n, const V* g, V* v, const GKState* st, GKWork& wk,
-                          hipStream_t s) {
-  const unsigned rg = rows_grid(n);
-  hipLaunchKernelGGL((k_pa_bwd<V>), dim3(rg), dim3(kBlock), 0, s, P.V, n, P.ell, P.ldv, P.c, g, v, st,
-                     wk.alpha_part);
-  wk.alpha_count = rg;
+static void launch_pcoef(const OpDesc& A, const PrecDesc& P, long long n, const V* z, const GKState* sl,
+                         hipStream_t s) {
+  if (!P.implicit) {
+    const long long rpc = (n + P.chunks - 1) / P.chunks;
+    hipLaunchKernelGGL((k_pa_part<V>), dim3(ceil_div(P.ell, kBlock), P.chunks), dim3(kBlock), 0, s, P.V, n, P.ell,
+                       P.ldv, z, P.part, rpc, sl);
+    hipLaunchKernelGGL(k_pa_red, dim3(ceil_div(P.ell, kWave)), dim3(kBlock), 0, s, P.part, P.chunks, P.ell, P.d,
+                       P.c, sl);
+    return;
+  }
+  const unsigned g1 = ceil_div(P.ell, kBlock / 16);
+  if (A.f64)
+    hipLaunchKernelGGL((k_pr_rz<double, V>), dim3(g1), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
+                       (const double*)A.val, P.I, P.ell, z, P.c1, sl);
+  else
+    hipLaunchKernelGGL((k_pr_rz<float, V>), dim3(g1), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
+                       (const float*)A.val, P.I, P.ell, z, P.c1, sl);
+  const unsigned g2 = ceil_div(P.ell, kBlock / kWave);
+  hipLaunchKernelGGL(k_pr_gemv, dim3(g2), dim3(kBlock), 0, s, P.Kt, P.ell, (const double*)P.c1, P.d, P.c2, sl);
+  hipLaunchKernelGGL(k_pr_gemv, dim3(g2), dim3(kBlock), 0, s, P.Kr, P.ell, (const double*)P.c2,
+                     (const double*)nullptr, P.c, sl);
 }
 
 template <class V>
 void gk_iteration(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s) {
   if (!P) {
-    launch_fwd<V>(A, vec.v, vec, st, wk, 1, s);
-    finish(st, wk, kFinBeta, s);
-    launch_bwd<V, true>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, s);
-    finish(st, wk, kFinAlpha, s);
+    launch_fwd<V, kFwdPlain>(A, vec.v, vec, st, wk, s);
+    launch_bwd<V, true>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, true, s);
     return;
   }
-  launch_pa_c<V>(*P, A.n, vec.v, st, s);
-  hipLaunchKernelGGL((k_pa_fwd<V>), dim3(rows_grid(A.n)), dim3(kBlock), 0, s, P->V, A.n, P->ell, P->ldv, P->c, vec.v,
-                     vec.t, vec.w, vec.y, (const GKState*)st);
-  launch_fwd<V>(A, vec.t, vec, st, wk, 0, s);
-  finish(st, wk, kFinBeta, s);
-  launch_bwd<V, false>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, s);
-  launch_pa_c<V>(*P, A.n, vec.g, st, s);
-  launch_pa_bwd<V>(*P, A.n, vec.g, vec.v, st, wk, s);
-  finish(st, wk, kFinAlpha, s);
+  const unsigned pg = prec_grid(*P, A.n);
+  launch_pcoef<V>(A, *P, A.n, vec.v, &st[1], s);
+  hipLaunchKernelGGL((k_pa_fwd<V>), dim3(pg), dim3(kBlock), 0, s, *P, A.n, (const V*)vec.v, vec.t, vec.w, vec.y,
+                     (const GKState*)(st + 1), st, (const double*)wk.alpha_part, (int)wk.alpha_count);
+  launch_fwd<V, kFwdPre>(A, vec.t, vec, st, wk, s);
+  launch_bwd<V, false>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, true, s);
+  launch_pcoef<V>(A, *P, A.n, vec.g, &st[1], s);
+  hipLaunchKernelGGL((k_pa_bwd<V>), dim3(pg), dim3(kBlock), 0, s, *P, A.n, (const V*)vec.g, vec.v,
+                     (const GKState*)(st + 1), wk.alpha_part);
+  wk.alpha_count = pg;
 }
 
 static void launch_resid(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
-                         double* r_top, double* r_bot, const GKState* st, GKWork& wk, hipStream_t s) {
+                         double* r_top, double* r_bot, GKState* st, GKWork& wk, hipStream_t s) {
   const int x_zero = (x == nullptr);
-  const unsigned rb = A.csr ? clamp_grid((A.m + (kBlock / A.group) - 1) / (kBlock / A.group)) : fwd_row_blocks(A);
+  const unsigned rb = fwd_row_blocks(A);
   const unsigned grid = rb + nbottom(A.n);
   if (A.csr) {
+    const RowBlk* rbk = (const RowBlk*)A.rb;
     if (A.f64)
-      hipLaunchKernelGGL((k_resid_csr<double>), dim3(grid), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
-                         (const double*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, st,
-                         wk.beta_part, A.group, (int)rb);
+      hipLaunchKernelGGL((k_resid_csr<double>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
+                         (const double*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot,
+                         (const GKState*)st, wk.beta_part, (int)rb);
     else
-      hipLaunchKernelGGL((k_resid_csr<float>), dim3(grid), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
-                         (const float*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, st,
-                         wk.beta_part, A.group, (int)rb);
+      hipLaunchKernelGGL((k_resid_csr<float>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
+                         (const float*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot,
+                         (const GKState*)st, wk.beta_part, (int)rb);
   } else {
     if (A.f64)
       hipLaunchKernelGGL((k_resid_dense<double>), dim3(grid), dim3(kBlock), 0, s, (const double*)A.val, A.m, A.n,
-                         A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, st, wk.beta_part, (int)rb);
+                         A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, (const GKState*)st, wk.beta_part,
+                         (int)rb);
     else
       hipLaunchKernelGGL((k_resid_dense<float>), dim3(grid), dim3(kBlock), 0, s, (const float*)A.val, A.m, A.n,
-                         A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, st, wk.beta_part, (int)rb);
+                         A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, (const GKState*)st, wk.beta_part,
+                         (int)rb);
   }
   wk.beta_count = grid;
 }
@@ -720,29 +1066,30 @@ void gk_phase_init(const OpDesc& A, const PrecDesc* P, const double* b, const do
                    hipStream_t s) {
   static_assert(sizeof(V) == 8, "only the FP64 vector path is implemented here");
   launch_resid(A, b, b_bot, bot_scale, x, r_top64, r_bot64, st, wk, s);
-  finish(st, wk, kFinBeta, s);
   fill_zero<V>(vec.y, A.n, s);
   fill_zero<V>(vec.w, A.n, s);
   if (!P) {
-    launch_bwd<V, true>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, s);
+    launch_bwd<V, true>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, true, s);
   } else {
-    launch_bwd<V, false>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, s);
-    launch_pa_c<V>(*P, A.n, vec.g, st, s);
-    launch_pa_bwd<V>(*P, A.n, vec.g, vec.v, st, wk, s);
+    launch_bwd<V, false>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, true, s);
+    launch_pcoef<V>(A, *P, A.n, vec.g, &st[1], s);
+    const unsigned pg = prec_grid(*P, A.n);
+    hipLaunchKernelGGL((k_pa_bwd<V>), dim3(pg), dim3(kBlock), 0, s, *P, A.n, (const V*)vec.g, vec.v,
+                       (const GKState*)(st + 1), wk.alpha_part);
+    wk.alpha_count = pg;
   }
-  finish(st, wk, kFinAlpha, s);
 }
 
+// x += P^{-1} y.  The last y update was applied by the kernel that stopped.
 template <class V>
 void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* x, GKState* st, hipStream_t s) {
-  const unsigned g = clamp_grid(ceil_div(A.n, kBlock));
-  hipLaunchKernelGGL((k_finalize<V>), dim3(g), dim3(kBlock), 0, s, A.n, vec.y, vec.w, (const GKState*)st);
+  (void)st;
   if (!P) {
-    hipLaunchKernelGGL((k_axpy_x<V>), dim3(g), dim3(kBlock), 0, s, A.n, vec.y, x);
+    hipLaunchKernelGGL((k_axpy_x<V>), dim3(clamp_grid(ceil_div(A.n, kBlock))), dim3(kBlock), 0, s, A.n,
+                       (const V*)vec.y, x);
   } else {
-    launch_pa_c<V>(*P, A.n, vec.y, nullptr, s);
-    hipLaunchKernelGGL((k_pa_x<V>), dim3(rows_grid(A.n)), dim3(kBlock), 0, s, P->V, A.n, P->ell, P->ldv, P->c, vec.y,
-                       x);
+    launch_pcoef<V>(A, *P, A.n, vec.y, nullptr, s);
+    hipLaunchKernelGGL((k_pa_x<V>), dim3(prec_grid(*P, A.n)), dim3(kBlock), 0, s, *P, A.n, (const V*)vec.y, x);
   }
 }
 
@@ -752,36 +1099,37 @@ template void gk_phase_init<double>(const OpDesc&, const PrecDesc*, const double
 template void gk_phase_finish<double>(const OpDesc&, const PrecDesc*, GKVecs<double>, double*, GKState*,
                                       hipStream_t);
 
-// ||A_mu^T r||^2 -> st->h2 for r = [b - A x; bot_scale b_bot - delta x]: the
-// plain phase start (its initial scalar step stores (alpha_1 beta_1)^2).
+// ||A_mu^T r||^2 -> slot 0 h2 for r = [b - A x; bot_scale b_bot - delta x]:
+// the plain phase start followed by its initial scalar step.
 void gk_normal_residual(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
                         GKVecs<double> vec, GKState* st, GKWork& wk, hipStream_t s) {
   launch_resid(A, b, b_bot, bot_scale, x, vec.u_top, vec.u_bot, st, wk, s);
-  finish(st, wk, kFinBeta, s);
-  launch_bwd<double, true>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, s);
-  finish(st, wk, kFinAlpha, s);
+  launch_bwd<double, true>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, true, s);
+  hipLaunchKernelGGL(k_consume, dim3(1), dim3(kBlock), 0, s, st, (const double*)wk.alpha_part, (int)wk.alpha_count,
+                     0);
 }
 
-// ||A^T b||^2 -> st->h2 (state: beta = 1, delta = 0, init = 1).
+// ||A^T b||^2 -> slot 0 h2 (state: beta = 1, delta = 0, init = 1).
 void op_atb_norm2(const OpDesc& A, const double* b, double* tmp_n, GKState* st, GKWork& wk, hipStream_t s) {
-  launch_bwd<double, false>(A, b, nullptr, nullptr, tmp_n, st, wk, s);
-  finish(st, wk, kFinAlpha, s);
+  launch_bwd<double, false>(A, b, nullptr, nullptr, tmp_n, st, wk, false, s);
+  hipLaunchKernelGGL(k_consume, dim3(1), dim3(kBlock), 0, s, st, (const double*)wk.alpha_part, (int)wk.alpha_count,
+                     0);
 }
 
-// ||b|| -> st->beta (state: delta = 0, init = 1).
+// ||b|| -> slot 0 beta (state: delta = 0, init = 1).
 void op_norm(const OpDesc& A, const double* b, double* tmp_m, GKState* st, GKWork& wk, hipStream_t s) {
   launch_resid(A, b, nullptr, 0.0, nullptr, tmp_m, nullptr, st, wk, s);
-  finish(st, wk, kFinBeta, s);
+  hipLaunchKernelGGL(k_consume, dim3(1), dim3(kBlock), 0, s, st, (const double*)wk.beta_part, (int)wk.beta_count, 1);
 }
 
-// y = A x - y_prev (trans = 0; the LSQR forward kernel with alpha = beta = 1,
-// delta = 0) or y = A^T x (trans = 1); state as given, not modified.
+// y = A x - y_prev (trans = 0: the LSQR forward kernel with alpha = beta = 1,
+// delta = 0) or y = A^T x (trans = 1); the slots hold that state.
 void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s) {
   if (!trans) {
     GKVecs<double> vec{y, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    launch_fwd<double>(A, x, vec, st, wk, 0, s);
+    launch_fwd<double, kFwdMatvec>(A, x, vec, st, wk, s);
   } else {
-    launch_bwd<double, false>(A, x, nullptr, nullptr, y, st, wk, s);
+    launch_bwd<double, false>(A, x, nullptr, nullptr, y, st, wk, false, s);
   }
 }
 

@@ -196,6 +196,45 @@ template void launch_csr_transpose<double>(const int*, const int*, const double*
                                            long long, long long, int*, int*, double*, int*,
                                            hipStream_t);
 
+// ---------------------------------------------------------------- row subset of a CSR matrix
+__global__ void k_rows_len(const int* rp, const int* I, int ell, int* len) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < ell) len[k] = rp[I[k] + 1] - rp[I[k]];
+}
+
+template <class T>
+__global__ void k_copy_rows(const int* rp, const int* ci, const T* val, const int* I, int ell, const int* r_ptr,
+                            int* r_idx, double* r_val) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= ell) return;
+  const int src = rp[I[k]], len = rp[I[k] + 1] - src, dst = r_ptr[k];
+  for (int e = 0; e < len; ++e) {
+    r_idx[dst + e] = ci[src + e];
+    r_val[dst + e] = (double)val[src + e];
+  }
+}
+
+template <class T>
+long long launch_gather_csr_rows(const int* row_ptr, const int* col_idx, const T* val, const int* I, int ell,
+                                 int* r_ptr, int* r_idx, double* r_val, long long cap, int* scratch,
+                                 hipStream_t st) {
+  const unsigned g = ceil_div(ell > 0 ? ell : 1, kBlock);
+  if (ell > 0) hipLaunchKernelGGL(k_rows_len, dim3(g), dim3(kBlock), 0, st, row_ptr, I, ell, scratch);
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kBlock), 0, st, (const int*)scratch, ell, r_ptr);
+  int nnz = 0;
+  APL_HIP(hipMemcpyAsync(&nnz, r_ptr + ell, sizeof(int), hipMemcpyDeviceToHost, st));
+  APL_HIP(hipStreamSynchronize(st));
+  if (nnz > cap) throw Error(-1, "row subset exceeds its reserved capacity");
+  if (ell > 0)
+    hipLaunchKernelGGL(k_copy_rows<T>, dim3(g), dim3(kBlock), 0, st, row_ptr, col_idx, val, I, ell,
+                       (const int*)r_ptr, r_idx, r_val);
+  return nnz;
+}
+template long long launch_gather_csr_rows<float>(const int*, const int*, const float*, const int*, int, int*, int*,
+                                                 double*, long long, int*, hipStream_t);
+template long long launch_gather_csr_rows<double>(const int*, const int*, const double*, const int*, int, int*,
+                                                  int*, double*, long long, int*, hipStream_t);
+
 // ---------------------------------------------------------------- sketch, CSR A
 // Y(:, j) = sum over the non-zeros (i, a) of column j of A of S(:, i) a.
 // One wave per 64 columns; lane l owns column j0 + l and accumulates it in a

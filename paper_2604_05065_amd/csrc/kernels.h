@@ -15,6 +15,12 @@ template <class T>
 void launch_csr_transpose(const int* row_ptr, const int* col_idx, const T* val, long long m,
                           long long n, long long nnz, int* t_ptr, int* t_idx, T* t_val,
                           int* scratch_n, hipStream_t st);
+// CSR of R = A(I[0..ell), :) with FP64 values; returns nnz(R) (synchronises
+// the stream); fails if it would exceed cap.
+template <class T>
+long long launch_gather_csr_rows(const int* row_ptr, const int* col_idx, const T* val, const int* I, int ell,
+                                 int* r_ptr, int* r_idx, double* r_val, long long cap, int* scratch,
+                                 hipStream_t st);
 template <class T>
 void launch_sketch_csr(const int* t_ptr, const int* t_idx, const T* t_val, long long n, int s,
                        int xi, const uint16_t* rows, const uint8_t* negmask, double* Y,
@@ -33,6 +39,7 @@ struct OpDesc {
   int f64;            // 1: values are double, 0: float
   long long m, n, ld, nnz;
   const int *rb, *t_rb;          // row blocks of the CSR-stream products (A, A^T)
+  int stream_t;                  // non-zeros per row block
   const int *row_ptr, *col_idx;  // CSR of A
   const void* val;
   const int *t_ptr, *t_idx;      // CSR of A^T
@@ -43,15 +50,27 @@ struct OpDesc {
   int chunks;         // row chunks of the dense A^T product
 };
 
-// Preconditioner in explicit form: P^{-1} z = z + V (d .* (V^T z)), V row-major n x ell.
+// Preconditioner P^{-1} z = z + V (d .* (V^T z)), V = Q_R V_M (n x ell).
+// Explicit form (dense A): V row-major n x ell.  Implicit form (CSR A): with
+// R = A(I,:) and Q_R = R^T T_R^{-1}, V = R^T K, K = T_R^{-1} V_M; the
+// coefficients are c1 = R z, c2 = d .* (K^T c1), c = K c2 and the row pass
+// adds R^T c (CSR of R^T).
 struct PrecDesc {
+  int implicit;
   int ell;
+  const double* d;
+  double* c;      // ell
+  // explicit
   long long ldv;
   const double* V;
-  const double* d;
   double* part;   // chunks x ell
   int chunks;
-  double* c;      // ell
+  // implicit
+  const int* I;                    // rows of A forming R
+  const double *Kt, *Kr;           // K^T and K, row-major ell x ell
+  const int *rt_ptr, *rt_idx;      // CSR of R^T (n rows)
+  const double* rt_val;
+  double *c1, *c2;                 // ell
 };
 
 // Work vectors of one right-hand side (precision V = double or float).
@@ -68,7 +87,8 @@ struct GKWork {
   unsigned alpha_count, beta_count;
 };
 
-// st points to the two state slots (see kern_gk.hip).
+// st points to the two state slots: slot 0 is written by the kernel that
+// finishes alpha (scalar step), slot 1 by the kernel that finishes beta.
 template <class V>
 void gk_iteration(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s);
 // Phase start: r = [b - A x; bot_scale b_bot - delta x] in FP64 (b or b_bot may be
@@ -89,7 +109,12 @@ void op_norm(const OpDesc& A, const double* b, double* tmp_m, GKState* st, GKWor
 void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s);
 template <class V>
 void fill_zero(V* p, long long n, hipStream_t s);
-int stream_blocks(long long nnz);
-void build_row_blocks(const int* rp, long long m, long long nnz, int* rb, hipStream_t s);
+// CSR-stream products: non-zeros per workgroup for a matrix, workgroups, and
+// the ints of a row-block array ({first row, its first non-zero} per
+// workgroup, plus the end).
+int stream_t(long long nnz);
+int stream_blocks(long long nnz, int T);
+long long row_block_words(long long nnz, int T);
+void build_row_blocks(const int* rp, long long m, long long nnz, int T, int* rb, hipStream_t s);
 
 }  // namespace aplicur

@@ -249,3 +249,35 @@ def test_zero_rhs_and_warm_start(lib):
         x1, info = ctx.solve(_t(b), X0=x0)
         assert info.iters <= 5
         assert np.linalg.norm(x1.cpu().numpy() - xr) <= 1e-9 * np.linalg.norm(xr)
+
+
+# ----------------------------------------------------------------- full size (the benchmark workload)
+@pytest.fixture(scope="module")
+def workload2():
+    return synth.workload(2, 1.0)  # CSR 200000 x 20000, 2.0e6 non-zeros, mu = 1e-4
+
+
+def test_full_size_products(lib, workload2):
+    A = workload2.A
+    m, n = A.shape
+    r = np.random.default_rng(21)
+    x, u = r.standard_normal(n), r.standard_normal(m)
+    with lib.Context(_gpu_csr(A), mu=workload2.mu, precond=False) as ctx:
+        y = ctx.matvec(_t(x)).cpu().numpy()
+        z = ctx.matvec(_t(u), trans=True).cpu().numpy()
+    yr, zr = A @ x, A.T @ u
+    assert np.abs(y - yr).max() <= 1e-13 * (abs(A).max() * np.abs(x).max() * 10)
+    assert np.abs(z - zr).max() <= 1e-13 * (abs(A).max() * np.abs(u).max() * abs(A).getnnz(axis=0).max())
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_full_size_solve_reaches_tolerance(lib, workload2, precond):
+    """At the benchmark size the solution is checked through the normal-equation
+    residual recomputed on the CPU in FP64 (the oracle's metric)."""
+    w = workload2
+    x, info = lib.lstsq(_gpu_csr(w.A), _t(w.B), mu=w.mu, block=w.block, tol_ne=w.tol, precond=precond,
+                        max_rank=512)
+    eta = ne_residual(w.A, w.B, x.cpu().numpy(), w.mu)
+    assert info.status == 0
+    assert eta <= 1.05 * w.tol
+    assert abs(eta - info.eta) <= 1e-3 * w.tol
