@@ -204,6 +204,44 @@ def lstsq(A, B, **opts):
         return ctx.solve(B)
 
 
+class LstsqFunction(torch.autograd.Function):
+    """X = argmin ||A X - B||^2 + mu ||X||^2 with gradients for A and B
+    through the adjoint solve of the library (aplicur_solve_backward).
+
+    apply(a_val, B, structure, opts): a_val is the dense A (CUDA tensor) or the
+    values of a CSR matrix whose row_ptr/col_idx/shape come from `structure`
+    (a CSRMatrix, None for dense A); the gradient of a_val is dense (m x n) or
+    lives on the sparsity pattern (nnz values)."""
+
+    @staticmethod
+    def forward(fctx, a_val, B, structure, opts):
+        A = a_val if structure is None else CSRMatrix(structure.row_ptr, structure.col_idx, a_val, structure.shape)
+        ctx = Context(A, **opts)
+        X, info = ctx.solve(B)
+        L.check(info.status)
+        fctx.lib_ctx = ctx
+        fctx.a_dtype, fctx.b_dtype = a_val.dtype, B.dtype
+        fctx.save_for_backward(X, B)
+        return X
+
+    @staticmethod
+    def backward(fctx, G):
+        X, B = fctx.saved_tensors
+        want_dA = bool(fctx.needs_input_grad[0])
+        _, dB, dA, _ = fctx.lib_ctx.solve_backward(X, B, G.contiguous(), want_dA=want_dA)
+        gA = dA.to(fctx.a_dtype) if want_dA else None
+        gB = dB.to(fctx.b_dtype).reshape(B.shape) if fctx.needs_input_grad[1] else None
+        return gA, gB, None, None
+
+
+def lstsq_autograd(A, B, **opts):
+    """Differentiable lstsq: A is a dense CUDA tensor or a CSRMatrix (its
+    `val` may require grad), B a CUDA tensor (m,) or (m, k)."""
+    if isinstance(A, CSRMatrix):
+        return LstsqFunction.apply(A.val, B, A, opts)
+    return LstsqFunction.apply(A, B, None, opts)
+
+
 def solve_batched(As, Bs, **opts):
     lib = L.load()
     o = make_opts(**opts)

@@ -713,7 +713,15 @@ static double atb_norm(Ctx& c, const double* b, hipStream_t s) {
 
 static double vec_norm(Ctx& c, const double* b, hipStream_t s) {
   upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 1, 0.0, s);
-  op_norm(c.op, b, c.u_top, c.st, c.wk, s);
+  op_norm(c.op, b, nullptr, 0.0, c.u_top, c.u_bot, c.st, c.wk, s);
+  GKState h = read_state(c, s);
+  return h.beta;
+}
+
+// ||g|| of an n-vector (the bottom block of [0; g], delta = 1).
+static double vec_norm_n(Ctx& c, const double* g, hipStream_t s) {
+  upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 1, 1.0, s);
+  op_norm(c.op, nullptr, g, 1.0, c.u_top, c.u_bot, c.st, c.wk, s);
   GKState h = read_state(c, s);
   return h.beta;
 }
@@ -724,21 +732,27 @@ struct ColState {
   bool done = false;
 };
 
+// Right-hand side of one column: [b; bot_scale b_bot] (b or b_bot may be null).
+struct Rhs {
+  const double* b;
+  const double* b_bot;
+  double bot_scale;
+};
+
 // Solve one column with P fixed (plain LSQR when P is null): restarted phases
 // with nu = inf until eta <= tol or the budget/stall guard ends it.
-static void refine(Ctx& c, const PrecDesc* P, const double* b, double* x, ColState& cs, double pnorm,
-                   double sigma_l, bool first_from_zero, std::vector<int>* it_log, std::vector<double>* eta_log,
-                   hipStream_t s) {
+static void refine(Ctx& c, const PrecDesc* P, Rhs r, double* x, ColState& cs, double pnorm, double sigma_l,
+                   bool first_from_zero, std::vector<int>* it_log, std::vector<double>* eta_log, hipStream_t s) {
   int stalls = 0;
   bool xz = first_from_zero;
   while (cs.eta > c.o.tol_ne && cs.used < c.o.max_iter && stalls < 3) {
     const double prev = cs.eta;
-    PhaseOut po = run_phase(c, P, b, nullptr, 0.0, x, xz, c.o.tol_ne * cs.atb, pnorm, 0.0, 0.0, INFINITY, sigma_l,
-                            c.o.max_iter - cs.used, s);
+    PhaseOut po = run_phase(c, P, r.b, r.b_bot, r.bot_scale, x, xz, c.o.tol_ne * cs.atb, pnorm, 0.0, 0.0, INFINITY,
+                            sigma_l, c.o.max_iter - cs.used, s);
     xz = false;
     cs.used += po.iters;
     cs.phases += 1;
-    cs.eta = eta_of(c, b, nullptr, 0.0, x, cs.atb, s);
+    cs.eta = eta_of(c, r.b, r.b_bot, r.bot_scale, x, cs.atb, s);
     if (it_log) it_log->push_back(po.iters);
     if (eta_log) eta_log->push_back(cs.eta);
     if (po.iters == 0 || po.reason == kStopBudget) break;
@@ -780,7 +794,7 @@ static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, lo
     auto t0 = Clock::now();
     for (int k = 0; k < nrhs; ++k) {
       if (cols[k].done) continue;
-      refine(c, nullptr, B + (size_t)k * ldb, X + (size_t)k * ldx, cols[k], 1.0, 0.0, !warm,
+      refine(c, nullptr, Rhs{B + (size_t)k * ldb, nullptr, 0.0}, X + (size_t)k * ldx, cols[k], 1.0, 0.0, !warm,
              k == 0 ? &c.phase_iters0 : nullptr, k == 0 ? &c.phase_eta0 : nullptr, s);
       cols[k].done = true;
     }
@@ -838,8 +852,8 @@ static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, lo
           if (cs.eta <= c.o.tol_ne || cs.used >= c.o.max_iter) {
             cs.done = true;
           } else if (final_step) {
-            refine(c, &c.prec, b, x, cs, c.p_pnorm, c.p_sigma_l, false, k == 0 ? &c.phase_iters0 : nullptr,
-                   k == 0 ? &c.phase_eta0 : nullptr, s);
+            refine(c, &c.prec, Rhs{b, nullptr, 0.0}, x, cs, c.p_pnorm, c.p_sigma_l, false,
+                   k == 0 ? &c.phase_iters0 : nullptr, k == 0 ? &c.phase_eta0 : nullptr, s);
             cs.done = true;
           }
         }
@@ -876,6 +890,94 @@ static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, lo
     info->t_lsqr_ms = t_lsqr;
   }
   (void)t_start;
+  return status;
+}
+
+// ------------------------------------------------------------------ adjoint
+// Z = (A^T A + mu I)^{-1} G as min || A_mu Z - [0; G / delta] || by LSQR
+// phases with the context's last preconditioner (plain LSQR if it has none),
+// to eta_adj = ||G - (A^T A + mu I) Z|| / ||G|| <= tol_ne; then dB = A Z and
+// dA = (B - A X) Z^T - (A Z) X^T (implicit differentiation of the normal
+// equations; not part of the paper's method).
+static int solve_backward(Ctx& c, const double* X, long long ldx, const double* B, long long ldb, const double* G,
+                          long long ldg, int nrhs, double* Z, long long ldz, double* dB, long long lddb, double* dA,
+                          long long ldda, aplicur_info* info, hipStream_t s) {
+  APL_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+  APL_REQUIRE(c.delta > 0.0, "the adjoint needs mu > 0");
+  APL_REQUIRE(G && Z && dB, "null G, Z or dB");
+  APL_REQUIRE(ldg >= c.n && ldz >= c.n && lddb >= c.m, "leading dimensions too small");
+  if (dA) {
+    APL_REQUIRE(X && B, "dA needs X and B");
+    APL_REQUIRE(ldx >= c.n && ldb >= c.m, "leading dimensions too small");
+    APL_REQUIRE(c.op.csr || ldda >= c.n, "ldda must be >= n for dense A");
+  }
+  set_stream(c, s);
+  auto t0 = Clock::now();
+  const PrecDesc* P = c.have_prec ? &c.prec : nullptr;
+  const double pnorm = c.have_prec ? c.p_pnorm : 1.0, sigma_l = c.have_prec ? c.p_sigma_l : 0.0;
+  int status = APLICUR_OK, iters = 0, phases = 0;
+  double eta_max = 0.0;
+  for (int k = 0; k < nrhs; ++k) {
+    const double* g = G + (size_t)k * ldg;
+    double* z = Z + (size_t)k * ldz;
+    fill(z, c.n, 0.0, s);
+    ColState cs;
+    cs.atb = vec_norm_n(c, g, s);
+    if (!std::isfinite(cs.atb)) throw Error(APLICUR_E_BREAKDOWN, "non-finite values in G");
+    if (cs.atb > 0.0)
+      refine(c, P, Rhs{nullptr, g, 1.0 / c.delta}, z, cs, pnorm, sigma_l, true, nullptr, nullptr, s);
+    else
+      cs.eta = 0.0;
+    if (cs.eta > c.o.tol_ne) status = APLICUR_W_MAXITER;
+    eta_max = std::max(eta_max, cs.eta);
+    iters = std::max(iters, cs.used);
+    phases = std::max(phases, cs.phases);
+    // dB = A z
+    double* db = dB + (size_t)k * lddb;
+    fill(db, c.m, 0.0, s);
+    op_matvec(c.op, 0, z, db, c.st_mv, c.wk, s);
+  }
+  if (dA) {
+    // R = B - A X (m x k), then the rank-2k gradient
+    double* work = nullptr;
+    APL_HIP(hipMalloc((void**)&work, sizeof(double) * (size_t)c.m * nrhs * 2));
+    try {
+      double* AX = work;
+      double* R = work + (size_t)c.m * nrhs;
+      for (int k = 0; k < nrhs; ++k) {
+        fill(AX + (size_t)k * c.m, c.m, 0.0, s);
+        op_matvec(c.op, 0, X + (size_t)k * ldx, AX + (size_t)k * c.m, c.st_mv, c.wk, s);
+      }
+      sub_cols(B, ldb, AX, c.m, R, c.m, c.m, nrhs, s);
+      if (c.op.csr) {
+        grad_csr(c.op.row_ptr, c.op.col_idx, c.m, nrhs, R, c.m, Z, ldz, dB, lddb, X, ldx, dA, s);
+      } else {
+        // row-major dA (m x n) is the column-major n x m matrix dA^T = Z R^T - X (AZ)^T
+        gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.n, c.m, nrhs, 1.0, Z, ldz, R, c.m, 0.0, dA,
+             ldda);
+        gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.n, c.m, nrhs, -1.0, X, ldx, dB, lddb, 1.0, dA,
+             ldda);
+      }
+      APL_HIP(hipGetLastError());
+      APL_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipFree(work);
+      throw;
+    }
+    APL_HIP(hipFree(work));
+  }
+  APL_HIP(hipGetLastError());
+  APL_HIP(hipStreamSynchronize(s));
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = status;
+    info->phases = phases;
+    info->iters = iters;
+    info->rank = c.rank;
+    info->eta = eta_max;
+    info->sigma_hat = c.p_target;
+    info->t_lsqr_ms = ms_since(t0);
+  }
   return status;
 }
 
@@ -971,12 +1073,8 @@ int aplicur_solve_backward(aplicur_ctx* ctx, const double* X, int64_t ldx, const
                            int64_t lddb, double* dA, int64_t ldda, aplicur_info* info, void* stream) {
   return guarded([&]() -> int {
     APL_REQUIRE(ctx && ctx->impl, "null context");
-    Ctx& c = *ctx->impl;
-    hipStream_t s = (hipStream_t)stream;
-    (void)X; (void)ldx; (void)B; (void)ldb; (void)G; (void)ldg; (void)nrhs; (void)Z; (void)ldz; (void)dB;
-    (void)lddb; (void)dA; (void)ldda; (void)info; (void)s;
-    (void)c;
-    throw Error(APLICUR_E_INVALID, "aplicur_solve_backward: not available in this build");
+    return solve_backward(*ctx->impl, X, ldx, B, ldb, G, ldg, nrhs, Z, ldz, dB, lddb, dA, ldda, info,
+                          (hipStream_t)stream);
   });
 }
 

@@ -39,6 +39,14 @@ void copy_block(const double* src, long long lds, double* dst, long long ldd, in
 void splitk_reduce(const double* W, int parts, long long m, long long n, double alpha, double beta, double* C,
                    long long ldc, hipStream_t s);
 void set_identity(double* X, long long ld, int n, hipStream_t s);
+// R (m x k, ldr) = B - AX (column-major).
+void sub_cols(const double* B, long long ldb, const double* AX, long long ldax, double* R, long long ldr, long long m,
+              int k, hipStream_t s);
+// Gradient on a CSR pattern: dA_e = sum_q R(i,q) Z(j,q) - AZ(i,q) X(j,q) for every
+// non-zero e = (i, j), column-major R (m x k), Z, X (n x k), AZ (m x k).
+void grad_csr(const int* row_ptr, const int* col_idx, long long m, int k, const double* R, long long ldr,
+              const double* Z, long long ldz, const double* AZ, long long ldaz, const double* X, long long ldx,
+              double* dA, hipStream_t s);
 // dst (n x n, ld n) = src^T (src n x n, ld lds).
 void transpose_square(const double* src, long long lds, double* dst, int n, hipStream_t s);
 void add_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols, hipStream_t s);

@@ -752,4 +752,40 @@ void transpose_square(const double* src, long long lds, double* dst, int n, hipS
   hipLaunchKernelGGL(k_transpose, g, dim3(kBlock), 0, s, src, lds, dst, n);
 }
 
+// ---------------------------------------------------------------- adjoint helpers
+__global__ void k_sub_cols(const double* B, long long ldb, const double* AX, long long ldax, double* R, long long ldr,
+                           long long m, int k) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i < m && q < k) R[q * ldr + i] = B[q * ldb + i] - AX[q * ldax + i];
+}
+
+void sub_cols(const double* B, long long ldb, const double* AX, long long ldax, double* R, long long ldr, long long m,
+              int k, hipStream_t s) {
+  if (m <= 0 || k <= 0) return;
+  hipLaunchKernelGGL(k_sub_cols, dim3(ceil_div(m, kBlock), k), dim3(kBlock), 0, s, B, ldb, AX, ldax, R, ldr, m, k);
+}
+
+// One thread per row: the row's non-zeros, each a k-term sum.
+__global__ void k_grad_csr(const int* rp, const int* ci, long long m, int k, const double* R, long long ldr,
+                           const double* Z, long long ldz, const double* AZ, long long ldaz, const double* X,
+                           long long ldx, double* dA) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= m) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const long long j = ci[e];
+    double acc = 0.0;
+    for (int q = 0; q < k; ++q) acc += R[q * ldr + i] * Z[q * ldz + j] - AZ[q * ldaz + i] * X[q * ldx + j];
+    dA[e] = acc;
+  }
+}
+
+void grad_csr(const int* row_ptr, const int* col_idx, long long m, int k, const double* R, long long ldr,
+              const double* Z, long long ldz, const double* AZ, long long ldaz, const double* X, long long ldx,
+              double* dA, hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_grad_csr, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, s, row_ptr, col_idx, m, k, R, ldr, Z, ldz,
+                     AZ, ldaz, X, ldx, dA);
+}
+
 }  // namespace aplicur

@@ -1116,9 +1116,11 @@ void op_atb_norm2(const OpDesc& A, const double* b, double* tmp_n, GKState* st, 
                      0);
 }
 
-// ||b|| -> slot 0 beta (state: delta = 0, init = 1).
-void op_norm(const OpDesc& A, const double* b, double* tmp_m, GKState* st, GKWork& wk, hipStream_t s) {
-  launch_resid(A, b, nullptr, 0.0, nullptr, tmp_m, nullptr, st, wk, s);
+// ||[b; bot_scale b_bot]|| -> slot 0 beta (state: init = 1; the bottom part
+// counts only when the state's delta > 0; b or b_bot may be null = 0).
+void op_norm(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, double* tmp_m, double* tmp_n,
+             GKState* st, GKWork& wk, hipStream_t s) {
+  launch_resid(A, b, b_bot, bot_scale, nullptr, tmp_m, tmp_n, st, wk, s);
   hipLaunchKernelGGL(k_consume, dim3(1), dim3(kBlock), 0, s, st, (const double*)wk.beta_part, (int)wk.beta_count, 1);
 }
 

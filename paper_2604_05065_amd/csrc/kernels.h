@@ -105,7 +105,8 @@ void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* 
 void gk_normal_residual(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
                         GKVecs<double> vec, GKState* st, GKWork& wk, hipStream_t s);
 void op_atb_norm2(const OpDesc& A, const double* b, double* tmp_n, GKState* st, GKWork& wk, hipStream_t s);
-void op_norm(const OpDesc& A, const double* b, double* tmp_m, GKState* st, GKWork& wk, hipStream_t s);
+void op_norm(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, double* tmp_m, double* tmp_n,
+             GKState* st, GKWork& wk, hipStream_t s);
 void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s);
 template <class V>
 void fill_zero(V* p, long long n, hipStream_t s);
