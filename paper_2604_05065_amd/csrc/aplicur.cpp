@@ -95,9 +95,13 @@ struct Ctx {
   bool have_prec = false;
   double p_target = 0.0, p_pnorm = 1.0, p_sigma_l = 0.0;
   std::vector<double> p_sigma_host;
-  // LSQR vectors and state
+  // LSQR vectors and state (FP64; FP32 copies for the low-precision phases)
   double *u_top = nullptr, *u_bot = nullptr, *v = nullptr, *w = nullptr, *y = nullptr, *t = nullptr,
          *g = nullptr;
+  bool fp32 = false;
+  OpDesc op32{};  // the same matrix with FP32 values (precision 1)
+  float *u_top32 = nullptr, *u_bot32 = nullptr, *v32 = nullptr, *w32 = nullptr, *y32 = nullptr, *t32 = nullptr,
+        *g32 = nullptr;
   GKWork wk{};
   GKState* st = nullptr;       // two state slots
   GKState* st_host = nullptr;  // pinned, two slots
@@ -194,7 +198,7 @@ static void validate(const aplicur_mat* A, const aplicur_opts* o) {
   }
   APL_REQUIRE(o->mu >= 0.0 && std::isfinite(o->mu), "mu must be finite and >= 0");
   APL_REQUIRE(o->mu > 0.0 || A->m >= A->n, "mu = 0 needs m >= n");
-  APL_REQUIRE(o->precision == 0, "only precision 0 (FP64) is available");
+  APL_REQUIRE(o->precision == 0 || o->precision == 1, "precision must be 0 (FP64) or 1 (FP32 phases, FP64 refinement)");
   if (o->precond) {
     APL_REQUIRE(o->block >= 1 && o->block <= 280, "block must be in [1, 280]");
     APL_REQUIRE(o->r_probes >= 1 && o->r_probes <= 64, "r_probes must be in [1, 64]");
@@ -262,6 +266,34 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       chunks = std::max<long long>(1, std::min<long long>(chunks, 1024));
       op.chunks = (int)chunks;
       op.part = c->arena.alloc<double>((size_t)chunks * n);
+    }
+    if (o->precision == 1) {
+      // FP32 copy of the values (the CSR structure is shared)
+      c->fp32 = true;
+      c->op32 = op;
+      c->op32.f64 = 0;
+      if (op.f64) {
+        if (op.csr) {
+          float* v32 = c->arena.alloc<float>(Am->nnz);
+          float* t32 = c->arena.alloc<float>(Am->nnz);
+          to_f32((const double*)op.val, 0, v32, 0, 1, Am->nnz, s);
+          to_f32((const double*)op.t_val, 0, t32, 0, 1, Am->nnz, s);
+          c->op32.val = v32;
+          c->op32.t_val = t32;
+        } else {
+          float* a32 = c->arena.alloc<float>((size_t)m * n);
+          to_f32((const double*)op.val, op.ld, a32, n, m, n, s);
+          c->op32.val = a32;
+          c->op32.ld = n;
+        }
+      }
+      c->u_top32 = c->arena.alloc<float>(m);
+      c->u_bot32 = c->arena.alloc<float>(n);
+      c->v32 = c->arena.alloc<float>(n);
+      c->w32 = c->arena.alloc<float>(n);
+      c->y32 = c->arena.alloc<float>(n);
+      c->t32 = c->arena.alloc<float>(n);
+      c->g32 = c->arena.alloc<float>(std::max(m, n));
     }
     // LSQR vectors and state
     c->u_top = c->arena.alloc<double>(m);
@@ -642,9 +674,10 @@ struct PhaseOut {
 static GKVecs<double> vecs(Ctx& c) { return GKVecs<double>{c.u_top, c.u_bot, c.v, c.w, c.y, c.t, c.g}; }
 
 static void upload_state(Ctx& c, double tol_abs, double pnorm, double eps_lsqr, double baug_eps, double nu,
-                         double sigma_l, int max_iter, double delta, hipStream_t s) {
+                         double sigma_l, int max_iter, double delta, hipStream_t s, double rel_tol = 0.0) {
   GKState& h = c.st_host[0];
   std::memset(&h, 0, sizeof(h));
+  h.rel_tol = rel_tol;
   h.alpha = 1.0;
   h.beta = 1.0;
   h.pnorm = pnorm;
@@ -656,8 +689,7 @@ static void upload_state(Ctx& c, double tol_abs, double pnorm, double eps_lsqr, 
   h.delta = delta;
   h.max_iter = max_iter;
   h.init = 1;
-  c.st_host[1] = h;
-  APL_HIP(hipMemcpyAsync(c.st, c.st_host, 2 * sizeof(GKState), hipMemcpyHostToDevice, s));
+  set_state(c.st, h, s);
 }
 
 // Both slots; the returned state is slot 0 unless only slot 1 carries the
@@ -669,29 +701,60 @@ static GKState read_state(Ctx& c, hipStream_t s) {
   return c.st_host[0];
 }
 
-// One warm-started phase for the problem min || A_mu x - [b; bot_scale b_bot] ||.
-static PhaseOut run_phase(Ctx& c, const PrecDesc* P, const double* b, const double* b_bot, double bot_scale,
-                          double* x, bool x_zero, double tol_abs, double pnorm, double eps_lsqr, double baug_eps,
-                          double nu, double sigma_l, int budget, hipStream_t s) {
-  upload_state(c, tol_abs, pnorm, eps_lsqr, baug_eps, nu, sigma_l, budget, c.delta, s);
-  GKVecs<double> vec = vecs(c);
-  gk_phase_init<double>(c.op, P, b, b_bot, bot_scale, x_zero ? nullptr : x, vec, c.u_top, c.u_bot, c.st, c.wk, s);
+// Relative reduction of the preconditioned normal residual that ends an FP32
+// phase: below it the FP32 recurrences stop converging, and the next phase
+// restarts from the FP64 residual (iterative refinement).
+constexpr double kFp32PhaseRelTol = 1e-5;
+
+template <class V>
+static PhaseOut run_phase_t(Ctx& c, const OpDesc& A, GKVecs<V> vec, const PrecDesc* P, const double* b,
+                            const double* b_bot, double bot_scale, double* x, bool x_zero, hipStream_t s) {
+  gk_phase_init<V>(c.op, A, P, b, b_bot, bot_scale, x_zero ? nullptr : x, vec, c.st, c.wk, s);
   int chunk = 8;
   long long launched = 0;
   APL_HIP(hipGetLastError());
   GKState h = read_state(c, s);
+  const long long budget = h.max_iter;
   while (!h.stop) {
-    for (int i = 0; i < chunk; ++i) gk_iteration<double>(c.op, P, vec, c.st, c.wk, s);
+    for (int i = 0; i < chunk; ++i) gk_iteration<V>(A, P, vec, c.st, c.wk, s);
     launched += chunk;
     APL_HIP(hipGetLastError());
     h = read_state(c, s);
     chunk = std::min(chunk * 2, 64);
-    if (!h.stop && launched > (long long)budget + 128)
+    if (!h.stop && launched > budget + 128)
       throw Error(APLICUR_E_HIP, "LSQR phase did not reach its stopping test within its budget");
   }
   if (h.reason == 6) throw Error(APLICUR_E_BREAKDOWN, "non-finite value in the LSQR recurrence");
-  gk_phase_finish<double>(c.op, P, vec, x, c.st, s);
+  gk_phase_finish<V>(A, P, vec, x, c.st, s);
   return PhaseOut{h.iter, h.reason};
+}
+
+// One warm-started phase for the problem min || A_mu x - [b; bot_scale b_bot] ||
+// (FP64, or FP32 recurrences from an FP64 residual with precision 1).
+static PhaseOut run_phase(Ctx& c, const PrecDesc* P, const double* b, const double* b_bot, double bot_scale,
+                          double* x, bool x_zero, double tol_abs, double pnorm, double eps_lsqr, double baug_eps,
+                          double nu, double sigma_l, int budget, hipStream_t s) {
+  const GKVecs<float> v32{c.u_top32, c.u_bot32, c.v32, c.w32, c.y32, c.t32, c.g32};
+  const bool refinement = std::isinf(nu) && eps_lsqr == 0.0;  // final / refinement phases
+  if (c.fp32 && (x_zero || !refinement || c.delta > 0.0)) {
+    if (!x_zero && refinement) {
+      // FP32 refinement phase: the correction d = (A^T A + mu I)^{-1} s with
+      // s = A_mu^T r (FP64) solves min || A_mu d - [0; s / delta] ||, whose
+      // right-hand side shrinks with the normal residual (the residual r
+      // itself stays at the least-squares residual, which FP32 cannot
+      // resolve to the requested eta).  Intermediate phases (dynamic stop)
+      // keep the warm-restart form of Sec. 3.2 below.
+      upload_state(c, 0.0, 1.0, 0.0, 0.0, INFINITY, 0.0, 1, c.delta, s);
+      gk_normal_vector(c.op, b, b_bot, bot_scale, x, c.u_top, c.u_bot, c.g, c.st, c.wk, s);
+      upload_state(c, tol_abs, pnorm, eps_lsqr, baug_eps, nu, sigma_l, budget, c.delta, s, kFp32PhaseRelTol);
+      return run_phase_t<float>(c, c.op32, v32, P, nullptr, c.g, 1.0 / c.delta, x, true, s);
+    }
+    upload_state(c, tol_abs, pnorm, eps_lsqr, baug_eps, nu, sigma_l, budget, c.delta, s, kFp32PhaseRelTol);
+    return run_phase_t<float>(c, c.op32, v32, P, b, b_bot, bot_scale, x, x_zero, s);
+  }
+  // FP64 phase (also the refinement phases of precision 1 when mu = 0)
+  upload_state(c, tol_abs, pnorm, eps_lsqr, baug_eps, nu, sigma_l, budget, c.delta, s);
+  return run_phase_t<double>(c, c.op, vecs(c), P, b, b_bot, bot_scale, x, x_zero, s);
 }
 
 // eta = ||A_mu^T r|| / atb with r the residual of x, FP64 from scratch.

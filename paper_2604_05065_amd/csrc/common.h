@@ -35,12 +35,12 @@ struct Error : std::runtime_error {
 enum StopReason { kStopNone = 0, kStopMetric = 1, kStopLsqr = 2, kStopDynamic = 3,
                   kStopBudget = 4, kStopExact = 5 };
 
-// Per right-hand-side state of one Golub-Kahan / LSQR phase.  Lives in device
-// memory; written only by the last workgroup of a kernel (all other
-// workgroups of that launch have finished reading it by then), so no double
-// buffering is needed.  Vectors are kept unnormalised: u = u_raw / beta,
+// Per right-hand-side state of one Golub-Kahan / LSQR phase, FP64 in every
+// precision mode.  Lives in device memory as two slots (see kern_gk.hip):
+// the kernel that finishes alpha writes slot 0, the one that finishes beta
+// writes slot 1.  Vectors are kept unnormalised: u = u_raw / beta,
 // v = v_raw / alpha, and the y/w update of iteration j is applied lazily by
-// the first kernel of iteration j + 1 (or by the finalize kernel).
+// the first kernel of iteration j + 1.
 struct GKState {
   double alpha, beta;          // norms of the current raw v and u
   double rhobar, phibar;       // Givens QR state
@@ -55,6 +55,7 @@ struct GKState {
   double delta;                // sqrt(mu)
   double h2;                   // ||A_mu^T r||^2 at phase start (normal-equation residual)
   double beta1;                // initial residual of the phase
+  double rel_tol;              // phase ends when ||A~^T r|| <= rel_tol * its start (low-precision phases; 0: off)
   int iter, max_iter, stop, reason, pending, have_rate1, init, pad;
 };
 
@@ -85,54 +86,6 @@ __device__ __forceinline__ double block_sum(double v) {
     for (int i = 0; i < kBlock / kWave; ++i) s += red[i];
   }
   return s;
-}
-
-// Sum of partials[0..count), computed redundantly by every workgroup that
-// needs it, in a fixed order (thread-strided sums, shuffle tree, waves in
-// order), so every workgroup obtains the bitwise-identical value.  Returned
-// to all threads of the workgroup.  Reading partials written by the previous
-// kernel needs no fence: the kernel boundary orders them.
-__device__ __forceinline__ double reduce_all(const double* partials, int count) {
-  __shared__ double red[kBlock / kWave];
-  __shared__ double result;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < count; i += kBlock) v += partials[i];
-  v = wave_sum(v);
-  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i) s += red[i];
-    result = s;
-  }
-  __syncthreads();
-  return result;
-}
-
-// "Last workgroup done" ticket: every workgroup calls this once after writing
-// its partial result; returns true in exactly one workgroup, after all others
-// have published their partials.  The ticket counter is reset by that block.
-__device__ __forceinline__ bool last_block(unsigned* counter, unsigned nblocks) {
-  __shared__ int am_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (t == nblocks - 1);
-    if (am_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  if (am_last) __threadfence();
-  return am_last != 0;
-}
-
-// Sum of partials[0..count) in a fixed order (deterministic), by one workgroup.
-__device__ __forceinline__ double reduce_partials(const double* partials, int count) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < count; i += kBlock) v += partials[i];
-  return block_sum(v);
 }
 
 inline unsigned ceil_div(long long a, long long b) { return (unsigned)((a + b - 1) / b); }

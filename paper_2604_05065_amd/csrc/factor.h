@@ -39,6 +39,9 @@ void copy_block(const double* src, long long lds, double* dst, long long ldd, in
 void splitk_reduce(const double* W, int parts, long long m, long long n, double alpha, double beta, double* C,
                    long long ldc, hipStream_t s);
 void set_identity(double* X, long long ld, int n, hipStream_t s);
+// dst (rows x cols, row-major, ldd) = (float) src (row-major, lds); contiguous when rows = 1.
+void to_f32(const double* src, long long lds, float* dst, long long ldd, long long rows, long long cols,
+            hipStream_t s);
 // R (m x k, ldr) = B - AX (column-major).
 void sub_cols(const double* B, long long ldb, const double* AX, long long ldax, double* R, long long ldr, long long m,
               int k, hipStream_t s);

@@ -752,6 +752,23 @@ void transpose_square(const double* src, long long lds, double* dst, int n, hipS
   hipLaunchKernelGGL(k_transpose, g, dim3(kBlock), 0, s, src, lds, dst, n);
 }
 
+// ---------------------------------------------------------------- FP32 copies
+__global__ void k_to_f32(const double* src, long long lds, float* dst, long long ldd, long long rows, long long cols) {
+  const long long total = rows * cols;
+  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total; t += (long long)gridDim.x * kBlock) {
+    const long long i = t / cols, j = t % cols;
+    dst[i * ldd + j] = (float)src[i * lds + j];
+  }
+}
+
+void to_f32(const double* src, long long lds, float* dst, long long ldd, long long rows, long long cols,
+            hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  long long g = (rows * cols + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)g), dim3(kBlock), 0, s, src, lds, dst, ldd, rows, cols);
+}
+
 // ---------------------------------------------------------------- adjoint helpers
 __global__ void k_sub_cols(const double* B, long long ldb, const double* AX, long long ldax, double* R, long long ldr,
                            long long m, int k) {

@@ -86,7 +86,7 @@ __device__ void scalar_step(GKState& s, double alpha) {
   int reason = kStopNone;
   if (beta == 0.0 || alpha == 0.0) {
     reason = kStopExact;
-  } else if (s.pnorm * arnorm <= s.tol_abs) {
+  } else if (s.pnorm * arnorm <= s.tol_abs || arnorm <= s.rel_tol * sqrt(s.h2)) {
     reason = kStopMetric;
   } else if (s.eps_lsqr > 0.0 && (arnorm <= s.eps_lsqr * sqrt(s.anorm2) * phibar || phibar <= s.baug_eps)) {
     reason = kStopLsqr;
@@ -776,11 +776,11 @@ __global__ void __launch_bounds__(kBlock) k_pa_x(const PrecDesc P, long long n, 
 // ---------------------------------------------------------------- phase start / end
 // r_top = b - A x (FP64, values widened), r_bot = bot_scale b_bot - delta x;
 // partials of ||r||^2.
-template <class TA>
+template <class TA, class RV>
 __global__ void __launch_bounds__(kBlock)
     k_resid_csr(const RowBlk* __restrict__ rbk, const int* __restrict__ rp, const int* __restrict__ ci,
                 const TA* __restrict__ val, long long m, long long n, const double* __restrict__ b,
-                const double* b_bot, double bot_scale, const double* x, int x_zero, double* r_top, double* r_bot,
+                const double* b_bot, double bot_scale, const double* x, int x_zero, RV* r_top, RV* r_bot,
                 const GKState* __restrict__ sl, double* beta_part, int row_blocks) {
   const double delta = sl->delta;
   double sq = 0.0;
@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(kBlock)
     if (x_zero) {
       for (int r = a.r0 + threadIdx.x; r < bb.r0; r += kBlock) {
         const double rr = b ? b[r] : 0.0;
-        r_top[r] = rr;
+        r_top[r] = (RV)rr;
         sq += rr * rr;
       }
     } else {
@@ -804,7 +804,7 @@ __global__ void __launch_bounds__(kBlock)
           [&](double) { return true; },
           [&](int r, double dot, double q0, double) {
             const double rr = q0 - dot;
-            r_top[r] = rr;
+            r_top[r] = (RV)rr;
             sq += rr * rr;
           });
     }
@@ -813,7 +813,7 @@ __global__ void __launch_bounds__(kBlock)
     for (long long j = (long long)(blockIdx.x - row_blocks) * kBlock + threadIdx.x; j < n; j += (long long)nb * kBlock) {
       double r = x_zero ? 0.0 : -delta * x[j];
       if (b_bot) r += bot_scale * b_bot[j];
-      r_bot[j] = r;
+      r_bot[j] = (RV)r;
       sq += r * r;
     }
   }
@@ -821,10 +821,10 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
 }
 
-template <class TA>
+template <class TA, class RV>
 __global__ void __launch_bounds__(kBlock)
     k_resid_dense(const TA* __restrict__ A, long long m, long long n, long long ld, const double* __restrict__ b,
-                  const double* b_bot, double bot_scale, const double* x, int x_zero, double* r_top, double* r_bot,
+                  const double* b_bot, double bot_scale, const double* x, int x_zero, RV* r_top, RV* r_bot,
                   const GKState* __restrict__ sl, double* beta_part, int row_blocks) {
   const double delta = sl->delta;
   double sq = 0.0;
@@ -840,7 +840,7 @@ __global__ void __launch_bounds__(kBlock)
       }
       if (lane == 0) {
         const double r = (b ? b[row] : 0.0) - acc;
-        r_top[row] = r;
+        r_top[row] = (RV)r;
         sq += r * r;
       }
     }
@@ -849,7 +849,7 @@ __global__ void __launch_bounds__(kBlock)
     for (long long j = (long long)(blockIdx.x - row_blocks) * kBlock + threadIdx.x; j < n; j += (long long)nb * kBlock) {
       double r = x_zero ? 0.0 : -delta * x[j];
       if (b_bot) r += bot_scale * b_bot[j];
-      r_bot[j] = r;
+      r_bot[j] = (RV)r;
       sq += r * r;
     }
   }
@@ -1032,28 +1032,29 @@ void gk_iteration(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, GKState* st
   wk.alpha_count = pg;
 }
 
+template <class RV>
 static void launch_resid(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
-                         double* r_top, double* r_bot, GKState* st, GKWork& wk, hipStream_t s) {
+                         RV* r_top, RV* r_bot, GKState* st, GKWork& wk, hipStream_t s) {
   const int x_zero = (x == nullptr);
   const unsigned rb = fwd_row_blocks(A);
   const unsigned grid = rb + nbottom(A.n);
   if (A.csr) {
     const RowBlk* rbk = (const RowBlk*)A.rb;
     if (A.f64)
-      hipLaunchKernelGGL((k_resid_csr<double>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
+      hipLaunchKernelGGL((k_resid_csr<double, RV>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
                          (const double*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot,
                          (const GKState*)st, wk.beta_part, (int)rb);
     else
-      hipLaunchKernelGGL((k_resid_csr<float>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
+      hipLaunchKernelGGL((k_resid_csr<float, RV>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
                          (const float*)A.val, A.m, A.n, b, b_bot, bot_scale, x, x_zero, r_top, r_bot,
                          (const GKState*)st, wk.beta_part, (int)rb);
   } else {
     if (A.f64)
-      hipLaunchKernelGGL((k_resid_dense<double>), dim3(grid), dim3(kBlock), 0, s, (const double*)A.val, A.m, A.n,
+      hipLaunchKernelGGL((k_resid_dense<double, RV>), dim3(grid), dim3(kBlock), 0, s, (const double*)A.val, A.m, A.n,
                          A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, (const GKState*)st, wk.beta_part,
                          (int)rb);
     else
-      hipLaunchKernelGGL((k_resid_dense<float>), dim3(grid), dim3(kBlock), 0, s, (const float*)A.val, A.m, A.n,
+      hipLaunchKernelGGL((k_resid_dense<float, RV>), dim3(grid), dim3(kBlock), 0, s, (const float*)A.val, A.m, A.n,
                          A.ld, b, b_bot, bot_scale, x, x_zero, r_top, r_bot, (const GKState*)st, wk.beta_part,
                          (int)rb);
   }
@@ -1061,17 +1062,15 @@ static void launch_resid(const OpDesc& A, const double* b, const double* b_bot, 
 }
 
 template <class V>
-void gk_phase_init(const OpDesc& A, const PrecDesc* P, const double* b, const double* b_bot, double bot_scale,
-                   const double* x, GKVecs<V> vec, double* r_top64, double* r_bot64, GKState* st, GKWork& wk,
-                   hipStream_t s) {
-  static_assert(sizeof(V) == 8, "only the FP64 vector path is implemented here");
-  launch_resid(A, b, b_bot, bot_scale, x, r_top64, r_bot64, st, wk, s);
+void gk_phase_init(const OpDesc& Ares, const OpDesc& A, const PrecDesc* P, const double* b, const double* b_bot,
+                   double bot_scale, const double* x, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s) {
+  launch_resid<V>(Ares, b, b_bot, bot_scale, x, vec.u_top, vec.u_bot, st, wk, s);
   fill_zero<V>(vec.y, A.n, s);
   fill_zero<V>(vec.w, A.n, s);
   if (!P) {
-    launch_bwd<V, true>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, true, s);
+    launch_bwd<V, true>(A, (const V*)vec.u_top, (const V*)vec.u_bot, vec.v, vec.g, st, wk, true, s);
   } else {
-    launch_bwd<V, false>(A, (const V*)r_top64, (const V*)r_bot64, vec.v, vec.g, st, wk, true, s);
+    launch_bwd<V, false>(A, (const V*)vec.u_top, (const V*)vec.u_bot, vec.v, vec.g, st, wk, true, s);
     launch_pcoef<V>(A, *P, A.n, vec.g, &st[1], s);
     const unsigned pg = prec_grid(*P, A.n);
     hipLaunchKernelGGL((k_pa_bwd<V>), dim3(pg), dim3(kBlock), 0, s, *P, A.n, (const V*)vec.g, vec.v,
@@ -1094,19 +1093,45 @@ void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* 
 }
 
 template void gk_iteration<double>(const OpDesc&, const PrecDesc*, GKVecs<double>, GKState*, GKWork&, hipStream_t);
-template void gk_phase_init<double>(const OpDesc&, const PrecDesc*, const double*, const double*, double,
-                                    const double*, GKVecs<double>, double*, double*, GKState*, GKWork&, hipStream_t);
+template void gk_iteration<float>(const OpDesc&, const PrecDesc*, GKVecs<float>, GKState*, GKWork&, hipStream_t);
+template void gk_phase_init<double>(const OpDesc&, const OpDesc&, const PrecDesc*, const double*, const double*,
+                                    double, const double*, GKVecs<double>, GKState*, GKWork&, hipStream_t);
+template void gk_phase_init<float>(const OpDesc&, const OpDesc&, const PrecDesc*, const double*, const double*,
+                                   double, const double*, GKVecs<float>, GKState*, GKWork&, hipStream_t);
 template void gk_phase_finish<double>(const OpDesc&, const PrecDesc*, GKVecs<double>, double*, GKState*,
                                       hipStream_t);
+template void gk_phase_finish<float>(const OpDesc&, const PrecDesc*, GKVecs<float>, double*, GKState*,
+                                     hipStream_t);
 
 // ||A_mu^T r||^2 -> slot 0 h2 for r = [b - A x; bot_scale b_bot - delta x]:
 // the plain phase start followed by its initial scalar step.
 void gk_normal_residual(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
                         GKVecs<double> vec, GKState* st, GKWork& wk, hipStream_t s) {
-  launch_resid(A, b, b_bot, bot_scale, x, vec.u_top, vec.u_bot, st, wk, s);
+  launch_resid<double>(A, b, b_bot, bot_scale, x, vec.u_top, vec.u_bot, st, wk, s);
   launch_bwd<double, true>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, true, s);
   hipLaunchKernelGGL(k_consume, dim3(1), dim3(kBlock), 0, s, st, (const double*)wk.alpha_part, (int)wk.alpha_count,
                      0);
+}
+
+// g = A_mu^T [b - A x; bot_scale b_bot - delta x] in FP64 (state: beta = 1);
+// r_top, r_bot receive the residual.
+void gk_normal_vector(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
+                      double* r_top, double* r_bot, double* g, GKState* st, GKWork& wk, hipStream_t s) {
+  launch_resid<double>(A, b, b_bot, bot_scale, x, r_top, r_bot, st, wk, s);
+  launch_bwd<double, false>(A, r_top, r_bot, nullptr, g, st, wk, false, s);
+}
+
+// Both state slots <- h (by value through the kernel arguments, so the host
+// copy may change as soon as the launch returns).
+__global__ void k_set_state(GKState* st, GKState h) {
+  if (threadIdx.x == 0) {
+    st[0] = h;
+    st[1] = h;
+  }
+}
+
+void set_state(GKState* st, const GKState& h, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, h);
 }
 
 // ||A^T b||^2 -> slot 0 h2 (state: beta = 1, delta = 0, init = 1).
@@ -1120,7 +1145,7 @@ void op_atb_norm2(const OpDesc& A, const double* b, double* tmp_n, GKState* st, 
 // counts only when the state's delta > 0; b or b_bot may be null = 0).
 void op_norm(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, double* tmp_m, double* tmp_n,
              GKState* st, GKWork& wk, hipStream_t s) {
-  launch_resid(A, b, b_bot, bot_scale, nullptr, tmp_m, tmp_n, st, wk, s);
+  launch_resid<double>(A, b, b_bot, bot_scale, nullptr, tmp_m, tmp_n, st, wk, s);
   hipLaunchKernelGGL(k_consume, dim3(1), dim3(kBlock), 0, s, st, (const double*)wk.beta_part, (int)wk.beta_count, 1);
 }
 

@@ -91,19 +91,23 @@ struct GKWork {
 // finishes alpha (scalar step), slot 1 by the kernel that finishes beta.
 template <class V>
 void gk_iteration(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s);
-// Phase start: r = [b - A x; bot_scale b_bot - delta x] in FP64 (b or b_bot may be
-// null = 0; x null = 0), beta_1 = ||r||, v_1 = P^{-T} A_mu^T u_1 (alpha finished by
-// the first kernel of the first iteration).
+// Phase start: r = [b - A x; bot_scale b_bot - delta x] computed in FP64 with
+// Ares (b or b_bot may be null = 0; x null = 0) and stored in vec.u (type V),
+// beta_1 = ||r||, v_1 = P^{-T} A_mu^T u_1 with A (alpha finished by the first
+// kernel of the first iteration).  Ares and A describe the same matrix; A
+// may hold FP32 values for the low-precision phases.
 template <class V>
-void gk_phase_init(const OpDesc& A, const PrecDesc* P, const double* b, const double* b_bot, double bot_scale,
-                   const double* x, GKVecs<V> vec, double* r_top64, double* r_bot64, GKState* st, GKWork& wk,
-                   hipStream_t s);
+void gk_phase_init(const OpDesc& Ares, const OpDesc& A, const PrecDesc* P, const double* b, const double* b_bot,
+                   double bot_scale, const double* x, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s);
 // Phase end: x += P^{-1} y.
 template <class V>
 void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* x, GKState* st, hipStream_t s);
 // ||A_mu^T r||^2 -> st[0].h2 for r = [b - A x; bot_scale b_bot - delta x].
 void gk_normal_residual(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
                         GKVecs<double> vec, GKState* st, GKWork& wk, hipStream_t s);
+void gk_normal_vector(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
+                      double* r_top, double* r_bot, double* g, GKState* st, GKWork& wk, hipStream_t s);
+void set_state(GKState* st, const GKState& h, hipStream_t s);
 void op_atb_norm2(const OpDesc& A, const double* b, double* tmp_n, GKState* st, GKWork& wk, hipStream_t s);
 void op_norm(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, double* tmp_m, double* tmp_n,
              GKState* st, GKWork& wk, hipStream_t s);
