@@ -135,7 +135,8 @@ def aplicur(A, b, mu, opts=None, trace=None):
     eta = math.inf
     while True:
         # Part 1: update CUR
-        I_plus, J_plus, exhausted = augment_cur(A, E_row, I, J, C, W, R, opts.block)
+        # the rank cap also limits the last increment (reading: l never exceeds max_rank)
+        I_plus, J_plus, exhausted = augment_cur(A, E_row, I, J, C, W, R, min(opts.block, max_rank - len(J)))
         if len(J_plus) == 0 and len(J) == 0:
             break
         I = np.concatenate([I, I_plus])

@@ -281,3 +281,19 @@ def test_full_size_solve_reaches_tolerance(lib, workload2, precond):
     assert info.status == 0
     assert eta <= 1.05 * w.tol
     assert abs(eta - info.eta) <= 1e-3 * w.tol
+
+
+def test_rank_cap_matches_oracle(lib):
+    """The rank cap cuts the last increment on both sides (ranks 10, 20, 25)."""
+    A = synth.dense_svd(np.random.default_rng(9), 300, 80, 10.0 ** (-8 * np.arange(80) / 79))
+    b = np.random.default_rng(10).standard_normal(300)
+    tr = Trace()
+    x_or = aplicur(A, b, 1e-12, Options(block=10, tol_ne=1e-10, max_rank=25), tr)
+    with lib.Context(_t(A), mu=1e-12, block=10, tol_ne=1e-10, max_rank=25) as ctx:
+        x, info = ctx.solve(_t(b))
+        ranks = ctx.query(8).tolist()
+        np.testing.assert_array_equal(np.sort(ctx.query(5)), np.sort(tr.J))
+        np.testing.assert_array_equal(np.sort(ctx.query(6)), np.sort(tr.I))
+    assert ranks == tr.ranks == [10, 20, 25]
+    assert info.eta <= 1.5e-10
+    assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-6 * np.linalg.norm(x_or)

@@ -98,6 +98,17 @@ def test_rank_cap_same_solution():
     assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-6
 
 
+def test_rank_cap_limits_the_last_increment():
+    """A cap that is not a multiple of the block ends the growth exactly at
+    the cap (the last increment is cut), like the GPU library's rank cap."""
+    A = synth.dense_svd(np.random.default_rng(9), 300, 80, 10.0 ** (-8 * np.arange(80) / 79))
+    b = np.random.default_rng(10).standard_normal(300)
+    tr = Trace()
+    aplicur(A, b, 1e-12, Options(block=10, tol_ne=1e-10, max_rank=25), tr)
+    assert tr.ranks == [10, 20, 25]
+    assert tr.rebuild[-1]
+
+
 def test_adjoint_matches_finite_differences():
     r = np.random.default_rng(3)
     m, n, k, mu = 30, 8, 2, 0.05
