@@ -1,20 +1,27 @@
-"""Benchmark: time to 1e-8 relative normal-equation residual on the sparse
-ill-conditioned workload, plus A / A^T matvec bandwidth against the HBM roofline.
+"""Benchmark: time to a 1e-8 relative normal-equation residual on the sparse
+ill-conditioned workload, plus the A / A^T product bandwidth against the HBM
+roofline.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--scale S]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-compare]
+                    [--max-rank L] [--products-only]
 
-Workload: CSR A 200000 x 20000, 10 distinct uniformly random columns per row,
-N(0,1) values, column j scaled by 10^(-6 j/(n-1)); b ~ N(0,1); mu = 1e-4;
-block 100 (sketch dimension s = 110); FP64; eta <= 1e-8.  One step is one
-whole APLICUR solve (sketch + adaptive CUR + preconditioned LSQR phases) with
-A and b already resident in HBM.  Plain GPU LSQR (same kernels, P = I) to the
-same eta is timed beside it.  One JSON line is printed on stdout; progress
-goes to stderr.
+Workload: CSR A 200000 x 20000 with 10 distinct uniformly random columns per
+row (2.0e6 non-zeros), N(0,1) values, column j scaled by 10^(-6 j/(n-1));
+b ~ N(0,1); mu = 1e-4; block 100 (sketch dimension s = 110); FP64.  One step
+is one whole APLICUR solve (sketch + adaptive CUR + preconditioned LSQR
+phases, FP64) to eta <= 1e-8 with A and b already resident in HBM.  Plain
+GPU LSQR (same kernels, P = I) and the FP32-phase variants to the same eta
+are timed beside it.  One JSON line on stdout; progress on stderr.
+
+--products-only runs just the timed A / A^T product loop and a 256 MiB copy
+of known size (for hardware-counter runs).
 """
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -23,30 +30,48 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "time to 1e-8 rel. NE residual & A/A^T matvec GB/s; batched+adjoint vs plain"
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_05065_amd", "csrc", "kern_gk.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "spmv_csr_200000x20000_counters.txt")
+PRODUCT_REPS = 200
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(m, n, nnz, vbytes=8):
-    """Algorithmic bytes of one CSR product y = A x: values + column indices +
-    row pointers + x (each entry once) + y read and written (the fused
-    epilogue reads the previous vector)."""
-    return nnz * (vbytes + 4) + (m + 1) * 4 + n * 8 + 2 * m * 8
+def spmv_bytes(rows, cols, nnz, vbytes=8):
+    """Algorithmic bytes of one CSR product y = A x - y_prev (the product
+    kernel with its epilogue): values and column indices once, row pointers
+    once, x once, y read and written."""
+    return nnz * (vbytes + 4) + (rows + 1) * 4 + cols * 8 + 2 * rows * 8
 
 
-def time_matvec(ctx, x, trans, reps):
-    """ms per launch of the A (trans=False) or A^T product kernel, from HIP
-    events recorded by the library on the launch stream around each launch,
-    with A and A^T products alternating as in the LSQR iteration."""
-    return ctx.time_product(x, trans=trans, reps=reps) * 1e-3
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
-def cpu_baseline(A, b, mu, budget_s=15.0):
-    """Oracle plain damped LSQR on the full matrix for a bounded number of
-    iterations (about budget_s seconds), scaled to the iteration count the
-    oracle needs to reach eta <= 1e-8 (estimated from the GPU count)."""
+def counter_traffic():
+    """HBM bytes per launch of the A-product kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel
+    calibration), or None when it is missing or was taken on other kernel
+    source."""
+    try:
+        txt = open(COUNTERS).read()
+    except OSError:
+        return None
+    h = re.search(r"^kernel_source_sha1:\s*(\S+)", txt, re.M)
+    t = re.search(r"^traffic_bytes_per_launch_A:\s*([0-9.eE+]+)", txt, re.M)
+    if not h or not t or h.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(A, b, mu, plain_iters, budget_s=15.0):
+    """The oracle's plain damped LSQR (scipy CSR products, single-threaded)
+    on the full matrix for a bounded number of iterations (about budget_s
+    seconds), scaled to the iterations plain LSQR needs to reach the
+    tolerance (the GPU plain run's count: the same recurrence)."""
     import numpy as np
     from oracle.lsqr import plsqr_phase
     try:
@@ -62,50 +87,77 @@ def cpu_baseline(A, b, mu, budget_s=15.0):
     t0 = time.perf_counter()
     plsqr_phase(A, math.sqrt(mu), b, np.zeros(n), None, eps_lsqr=0.0, tol_ne=0.0, max_iter=k)
     per = (time.perf_counter() - t0) / k
-    return per, k, threads
+    value = per * plain_iters * 1e3
+    return {"value": round(value, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle plain damped LSQR (R1), {k} iterations on the full 200000 x 20000 matrix "
+                       f"({per * 1e3:.2f} ms/iteration, scipy CSR products), scaled to the {plain_iters} "
+                       f"iterations plain LSQR needs for eta <= 1e-8")}
 
 
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
-    ap_.add_argument("--steps", type=int, default=2)
+    ap_.add_argument("--steps", type=int, default=3)
     ap_.add_argument("--warmup", type=int, default=1)
-    ap_.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
-    ap_.add_argument("--max-rank", type=int, default=0)
+    ap_.add_argument("--max-rank", type=int, default=256)
     ap_.add_argument("--no-cpu", action="store_true")
-    ap_.add_argument("--no-plain", action="store_true")
+    ap_.add_argument("--no-compare", action="store_true")
+    ap_.add_argument("--products-only", action="store_true")
     args = ap_.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is a "
-              "design note, not a measured configuration.", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): every problem here fits one MI355X and "
+              "the multi-GPU layout is a design note, not a measured configuration.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2604_05065_amd as ap
     from workloads import synth
 
     t0 = time.time()
-    w = synth.workload(2, args.scale)
+    w = synth.workload(2, 1.0)
     A, b, mu, block, tol = w.A, w.B, w.mu, w.block, w.tol
     m, n = A.shape
-    log(f"[bench] workload {w} generated in {time.time() - t0:.1f}s")
+    nnz = int(A.nnz)
+    log(f"[bench] workload {m}x{n} nnz={nnz} generated in {time.time() - t0:.1f}s")
     Ag = ap.CSRMatrix.from_scipy(A, device="cuda", dtype=torch.float64)
     bg = torch.as_tensor(b, device="cuda")
+
+    # ---- A and A^T products: the LSQR product kernels, HIP events on their launch stream
+    with ap.Context(Ag, precond=False, mu=mu) as ctx:
+        xv = torch.randn(n, device="cuda", dtype=torch.float64)
+        ctx.time_product(xv, trans=False, reps=10)
+        us_a = ctx.time_product(xv, trans=False, reps=PRODUCT_REPS)
+        us_at = ctx.time_product(xv, trans=True, reps=PRODUCT_REPS)
+    bytes_a = spmv_bytes(m, n, nnz)
+    bytes_at = spmv_bytes(n, m, nnz) - n * 8  # A^T kernel stores its output without reading it
+    gbs_a = bytes_a / (us_a * 1e-6) / 1e9
+    gbs_at = bytes_at / (us_at * 1e-6) / 1e9
+    log(f"[bench] A x: {us_a:.2f} us/launch -> {gbs_a:.0f} GB/s; A^T u: {us_at:.2f} us -> {gbs_at:.0f} GB/s")
+    if args.products_only:
+        big = torch.empty(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(big)
+        for _ in range(3):
+            dst.copy_(big)
+        torch.cuda.synchronize()
+        print(json.dumps({"us_A": us_a, "us_AT": us_at, "bytes_A": bytes_a, "bytes_AT": bytes_at,
+                          "copy_bytes_each_way": big.numel() * 8}), flush=True)
+        return
+
     opts = dict(mu=mu, block=block, tol_ne=tol, seed=7, max_rank=args.max_rank)
 
-    def run_once(precond):
+    def run_once(precond, precision=0):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        with ap.Context(Ag, precond=precond, **opts) as ctx:
-            x, info = ctx.solve(bg)
+        with ap.Context(Ag, precond=precond, precision=precision, **opts) as c:
+            x, info = c.solve(bg)
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3, x, info
 
     for i in range(args.warmup):
         ms, _, info = run_once(True)
         log(f"[bench] warmup {i}: {ms:.1f} ms rank={info.rank} iters={info.iters} eta={info.eta:.2e}")
+    torch.cuda.synchronize()
     times, infos = [], []
     for i in range(args.steps):
         ms, x, info = run_once(True)
@@ -116,57 +168,49 @@ def main():
             f"precond {info.t_precond_ms:.1f}, lsqr {info.t_lsqr_ms:.1f} ms)")
     ms_step = sum(times) / len(times)
     info = infos[-1]
+    if info.status != 0 or info.eta > tol:
+        log(f"[bench] WARNING: the solve did not reach eta <= {tol:g} (status {info.status})")
 
-    plain_ms, plain_info = None, None
-    if not args.no_plain:
-        plain_ms, _, plain_info = run_once(False)
-        log(f"[bench] plain LSQR: {plain_ms:.1f} ms iters={plain_info.iters} eta={plain_info.eta:.2e}")
-
-    # A and A^T products: the CSR kernels of the LSQR loop, timed with events
-    # on the stream they are launched on (the current torch stream)
-    with ap.Context(Ag, precond=False, mu=mu) as ctx:
-        xv = torch.randn(n, device="cuda", dtype=torch.float64)
-        uv = torch.randn(m, device="cuda", dtype=torch.float64)
-        reps = 200
-        t_a = time_matvec(ctx, xv, False, reps)
-        t_at = time_matvec(ctx, xv, True, reps)
-    nnz = A.nnz
-    bytes_a = spmv_bytes(m, n, nnz)
-    bytes_at = nnz * 12 + (n + 1) * 4 + m * 8 + n * 8
-    gbs_a = bytes_a / (t_a * 1e-3) / 1e9
-    gbs_at = bytes_at / (t_at * 1e-3) / 1e9
-    log(f"[bench] A x: {t_a * 1e3:.1f} us/launch seq -> {gbs_a:.0f} GB/s; A^T u: {t_at * 1e3:.1f} us -> {gbs_at:.0f} GB/s")
+    compare = {}
+    plain_iters = None
+    if not args.no_compare:
+        for name, pc, prec in (("plain_lsqr_f64", False, 0), ("plain_lsqr_f32_ir", False, 1),
+                               ("aplicur_f32_ir", True, 1)):
+            run_once(pc, prec)
+            ms, _, inf = run_once(pc, prec)
+            compare[name] = {"ms": round(ms, 2), "iters": inf.iters, "phases": inf.phases, "eta": inf.eta,
+                             "rank": inf.rank}
+            if name == "plain_lsqr_f64":
+                plain_iters = inf.iters
+            log(f"[bench] {name}: {ms:.1f} ms iters={inf.iters} phases={inf.phases} eta={inf.eta:.2e}")
 
     cpu = None
     if not args.no_cpu:
-        per, k, threads = cpu_baseline(A, b, mu)
-        est_iters = plain_info.iters if plain_info is not None else info.iters
-        cpu = {"value": per * est_iters * 1e3, "unit": "ms", "cores": threads, "kind": "oracle",
-               "sample": f"oracle plain damped LSQR, {k} iterations on the full matrix "
-                         f"({per * 1e3:.2f} ms/iteration, scipy CSR products), scaled to the "
-                         f"{est_iters} iterations plain LSQR needs to reach eta <= {tol:g}"}
-        log(f"[bench] cpu baseline: {per * 1e3:.2f} ms/iter x {est_iters} = {cpu['value']:.0f} ms")
+        cpu = cpu_baseline(A, b, mu, plain_iters or 8400)
+        log(f"[bench] cpu baseline: {cpu['value']:.0f} ms ({cpu['sample']})")
 
+    traffic = counter_traffic()
     out = {
         "metric": METRIC, "value": round(ms_step, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"csr-{m}x{n}-nnz10-colscale1e-6 mu={mu:g} block={block} tol={tol:g} "
-                               f"(APLICUR solve incl. sketch; FP64)",
-                   "m": m, "n": n, "nnz": int(nnz), "mu": mu, "block": block, "tol_ne": tol,
+        "config": {"workload": (f"APLICUR solve to eta<=1e-8 (sketch+CUR+preconditioned LSQR), CSR {m}x{n}, "
+                                f"10 random columns per row, column scaling 1e-6, mu={mu:g}, block {block}, "
+                                f"rank cap {args.max_rank}, FP64"),
+                   "m": m, "n": n, "nnz": nnz, "mu": mu, "block": block, "tol_ne": tol,
                    "max_rank": args.max_rank},
         "roofline": {"bound": "hbm", "achieved": round(gbs_a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs_a / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_fwd_csr<double,double> (A x with fused LSQR epilogue)",
-                     "bytes_per_launch": int(bytes_a), "us_per_launch": round(t_a * 1e3, 2)},
+                     "frac": round(gbs_a / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_fwd_csr (A x - y, CSR-stream, FP64)",
+                     "bytes_per_launch": int(bytes_a), "us_per_launch": round(us_a, 3)},
         "cpu_baseline": cpu,
         "aplicur": {"rank": info.rank, "phases": info.phases, "iters": info.iters, "outer": info.outer,
-                    "rebuilds": info.rebuilds, "eta": info.eta, "t_sketch_ms": info.t_sketch_ms,
-                    "t_cur_ms": info.t_cur_ms, "t_precond_ms": info.t_precond_ms,
-                    "t_lsqr_ms": info.t_lsqr_ms},
-        "plain_lsqr": None if plain_info is None else {"ms": round(plain_ms, 3), "iters": plain_info.iters,
-                                                       "eta": plain_info.eta},
-        "matvec_gbs": {"A": round(gbs_a, 1), "AT": round(gbs_at, 1)},
+                    "rebuilds": info.rebuilds, "eta": info.eta, "t_sketch_ms": round(info.t_sketch_ms, 2),
+                    "t_cur_ms": round(info.t_cur_ms, 2), "t_precond_ms": round(info.t_precond_ms, 2),
+                    "t_lsqr_ms": round(info.t_lsqr_ms, 2)},
+        "compare": compare or None,
+        "matvec": {"A_us": round(us_a, 3), "A_GBs": round(gbs_a, 1), "AT_us": round(us_at, 3),
+                   "AT_GBs": round(gbs_at, 1), "AT_bytes": int(bytes_at)},
     }
     print(json.dumps(out), flush=True)
 

@@ -1167,15 +1167,11 @@ int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, doubl
     for (auto& e : ev) APL_HIP(hipEventCreate(&e));
     for (int i = 0; i < reps; ++i) {
       if (!trans) {
-        APL_HIP(hipEventRecord(ev[2 * i], s));
-        op_matvec(c.op, 0, x, y, c.st_mv, c.wk, s);
-        APL_HIP(hipEventRecord(ev[2 * i + 1], s));
+        op_matvec(c.op, 0, x, y, c.st_mv, c.wk, s, ev[2 * i], ev[2 * i + 1]);
         op_matvec(c.op, 1, y, c.g, c.st_mv, c.wk, s);
       } else {
         op_matvec(c.op, 0, x, y, c.st_mv, c.wk, s);
-        APL_HIP(hipEventRecord(ev[2 * i], s));
-        op_matvec(c.op, 1, y, c.g, c.st_mv, c.wk, s);
-        APL_HIP(hipEventRecord(ev[2 * i + 1], s));
+        op_matvec(c.op, 1, y, c.g, c.st_mv, c.wk, s, ev[2 * i], ev[2 * i + 1]);
       }
     }
     APL_HIP(hipEventSynchronize(ev.back()));

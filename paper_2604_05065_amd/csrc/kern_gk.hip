@@ -21,6 +21,8 @@
 // 1/beta and 1/alpha is folded into the consumers, and the y/w update of
 // iteration j is applied by the first kernel of iteration j + 1, which on
 // stopping applies the last y update itself.
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace aplicur {
@@ -915,8 +917,19 @@ static unsigned prec_grid(const PrecDesc& P, long long n) {
   return P.implicit ? clamp_grid(ceil_div(n, kBlock), kRowsMaxGrid) : clamp_grid((n + 3) / 4, kRowsMaxGrid);
 }
 
+// Launch; with events, through the dispatch-timed launch (the events take the
+// kernel's own start and end timestamps, as a kernel trace does).
+template <class F, class... Args>
+static void launch_k(F kern, dim3 g, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kern, g, dim3(kBlock), 0, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kern, g, dim3(kBlock), 0, s, args...);
+}
+
 template <class V, int MODE>
-static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s) {
+static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, GKState* st, GKWork& wk, hipStream_t s,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const unsigned rb = fwd_row_blocks(A);
   const unsigned grid = rb + nbottom(A.n);
   const int ac = (int)wk.alpha_count;
@@ -925,22 +938,22 @@ static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, GKState* st
   if (A.csr) {
     const RowBlk* rbk = (const RowBlk*)A.rb;
     if (A.f64)
-      hipLaunchKernelGGL((k_fwd_csr<double, V, MODE>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
-                         (const double*)A.val, A.n, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, sin,
-                         sout, wk.alpha_part, ac, wk.beta_part, (int)rb);
+      launch_k(k_fwd_csr<double, V, MODE>, dim3(grid), s, e0, e1, rbk, A.row_ptr, A.col_idx, (const double*)A.val,
+               A.n, tin, vec.u_top, vec.u_bot, (const V*)vec.v, vec.w, vec.y, sin, sout,
+               (const double*)wk.alpha_part, ac, wk.beta_part, (int)rb);
     else
-      hipLaunchKernelGGL((k_fwd_csr<float, V, MODE>), dim3(grid), dim3(kBlock), 0, s, rbk, A.row_ptr, A.col_idx,
-                         (const float*)A.val, A.n, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, sin,
-                         sout, wk.alpha_part, ac, wk.beta_part, (int)rb);
+      launch_k(k_fwd_csr<float, V, MODE>, dim3(grid), s, e0, e1, rbk, A.row_ptr, A.col_idx, (const float*)A.val,
+               A.n, tin, vec.u_top, vec.u_bot, (const V*)vec.v, vec.w, vec.y, sin, sout,
+               (const double*)wk.alpha_part, ac, wk.beta_part, (int)rb);
   } else {
     if (A.f64)
-      hipLaunchKernelGGL((k_fwd_dense<double, V, MODE>), dim3(grid), dim3(kBlock), 0, s, (const double*)A.val, A.m,
-                         A.n, A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, sin, sout, wk.alpha_part,
-                         ac, wk.beta_part, (int)rb);
+      launch_k(k_fwd_dense<double, V, MODE>, dim3(grid), s, e0, e1, (const double*)A.val, A.m, A.n, A.ld, tin,
+               vec.u_top, vec.u_bot, (const V*)vec.v, vec.w, vec.y, sin, sout, (const double*)wk.alpha_part, ac,
+               wk.beta_part, (int)rb);
     else
-      hipLaunchKernelGGL((k_fwd_dense<float, V, MODE>), dim3(grid), dim3(kBlock), 0, s, (const float*)A.val, A.m,
-                         A.n, A.ld, tin, vec.u_top, vec.u_bot, vec.v, vec.w, vec.y, sin, sout, wk.alpha_part,
-                         ac, wk.beta_part, (int)rb);
+      launch_k(k_fwd_dense<float, V, MODE>, dim3(grid), s, e0, e1, (const float*)A.val, A.m, A.n, A.ld, tin,
+               vec.u_top, vec.u_bot, (const V*)vec.v, vec.w, vec.y, sin, sout, (const double*)wk.alpha_part, ac,
+               wk.beta_part, (int)rb);
   }
   wk.beta_count = grid;
 }
@@ -948,42 +961,40 @@ static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, GKState* st
 // beta_from_part: finish beta from wk.beta_part (else the state's beta is kept).
 template <class V, bool PLAIN>
 static void launch_bwd(const OpDesc& A, const V* u_top, const V* u_bot, V* v, V* g, GKState* st, GKWork& wk,
-                       bool beta_from_part, hipStream_t s) {
+                       bool beta_from_part, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const double* bp = beta_from_part ? wk.beta_part : nullptr;
   const int bc = (int)wk.beta_count;
   const unsigned grid = bwd_grid(A);
   if (A.csr) {
     const RowBlk* trbk = (const RowBlk*)A.t_rb;
+    const GKState* sin = st;
+    GKState* sout = st + 1;
     if (A.f64) {
       if (u_bot)
-        hipLaunchKernelGGL((k_bwd_csr<double, V, PLAIN, true>), dim3(grid), dim3(kBlock), 0, s, trbk, A.t_ptr,
-                           A.t_idx, (const double*)A.t_val, u_top, u_bot, v, g, (const GKState*)st, st + 1, bp, bc,
-                           wk.alpha_part);
+        launch_k(k_bwd_csr<double, V, PLAIN, true>, dim3(grid), s, e0, e1, trbk, A.t_ptr, A.t_idx,
+                 (const double*)A.t_val, u_top, u_bot, v, g, sin, sout, bp, bc, wk.alpha_part);
       else
-        hipLaunchKernelGGL((k_bwd_csr<double, V, PLAIN, false>), dim3(grid), dim3(kBlock), 0, s, trbk, A.t_ptr,
-                           A.t_idx, (const double*)A.t_val, u_top, u_bot, v, g, (const GKState*)st, st + 1, bp, bc,
-                           wk.alpha_part);
+        launch_k(k_bwd_csr<double, V, PLAIN, false>, dim3(grid), s, e0, e1, trbk, A.t_ptr, A.t_idx,
+                 (const double*)A.t_val, u_top, u_bot, v, g, sin, sout, bp, bc, wk.alpha_part);
     } else {
       if (u_bot)
-        hipLaunchKernelGGL((k_bwd_csr<float, V, PLAIN, true>), dim3(grid), dim3(kBlock), 0, s, trbk, A.t_ptr,
-                           A.t_idx, (const float*)A.t_val, u_top, u_bot, v, g, (const GKState*)st, st + 1, bp, bc,
-                           wk.alpha_part);
+        launch_k(k_bwd_csr<float, V, PLAIN, true>, dim3(grid), s, e0, e1, trbk, A.t_ptr, A.t_idx,
+                 (const float*)A.t_val, u_top, u_bot, v, g, sin, sout, bp, bc, wk.alpha_part);
       else
-        hipLaunchKernelGGL((k_bwd_csr<float, V, PLAIN, false>), dim3(grid), dim3(kBlock), 0, s, trbk, A.t_ptr,
-                           A.t_idx, (const float*)A.t_val, u_top, u_bot, v, g, (const GKState*)st, st + 1, bp, bc,
-                           wk.alpha_part);
+        launch_k(k_bwd_csr<float, V, PLAIN, false>, dim3(grid), s, e0, e1, trbk, A.t_ptr, A.t_idx,
+                 (const float*)A.t_val, u_top, u_bot, v, g, sin, sout, bp, bc, wk.alpha_part);
     }
   } else {
     const long long rpc = (A.m + A.chunks - 1) / A.chunks;
     dim3 g1(ceil_div(A.n, kBlock), A.chunks);
     if (A.f64)
-      hipLaunchKernelGGL((k_bwd_dense_part<double, V>), g1, dim3(kBlock), 0, s, (const double*)A.val, A.m, A.n, A.ld,
-                         u_top, A.part, rpc, (const GKState*)st);
+      launch_k(k_bwd_dense_part<double, V>, g1, s, e0, nullptr, (const double*)A.val, A.m, A.n, A.ld, u_top, A.part,
+               rpc, (const GKState*)st);
     else
-      hipLaunchKernelGGL((k_bwd_dense_part<float, V>), g1, dim3(kBlock), 0, s, (const float*)A.val, A.m, A.n, A.ld,
-                         u_top, A.part, rpc, (const GKState*)st);
-    hipLaunchKernelGGL((k_bwd_dense_red<V, PLAIN>), dim3(grid), dim3(kBlock), 0, s, A.part, A.chunks, A.n, u_bot, v,
-                       g, (const GKState*)st, st + 1, bp, bc, wk.alpha_part);
+      launch_k(k_bwd_dense_part<float, V>, g1, s, e0, nullptr, (const float*)A.val, A.m, A.n, A.ld, u_top, A.part,
+               rpc, (const GKState*)st);
+    launch_k(k_bwd_dense_red<V, PLAIN>, dim3(grid), s, nullptr, e1, (const double*)A.part, A.chunks, A.n, u_bot, v,
+             g, (const GKState*)st, st + 1, bp, bc, wk.alpha_part);
   }
   wk.alpha_count = grid;
 }
@@ -1150,13 +1161,15 @@ void op_norm(const OpDesc& A, const double* b, const double* b_bot, double bot_s
 }
 
 // y = A x - y_prev (trans = 0: the LSQR forward kernel with alpha = beta = 1,
-// delta = 0) or y = A^T x (trans = 1); the slots hold that state.
-void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s) {
+// delta = 0) or y = A^T x (trans = 1); the slots hold that state.  With
+// events e0/e1 the product's own start and end are recorded.
+void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s,
+               hipEvent_t e0, hipEvent_t e1) {
   if (!trans) {
     GKVecs<double> vec{y, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    launch_fwd<double, kFwdMatvec>(A, x, vec, st, wk, s);
+    launch_fwd<double, kFwdMatvec>(A, x, vec, st, wk, s, e0, e1);
   } else {
-    launch_bwd<double, false>(A, x, nullptr, nullptr, y, st, wk, false, s);
+    launch_bwd<double, false>(A, x, nullptr, nullptr, y, st, wk, false, s, e0, e1);
   }
 }
 

@@ -111,7 +111,8 @@ void set_state(GKState* st, const GKState& h, hipStream_t s);
 void op_atb_norm2(const OpDesc& A, const double* b, double* tmp_n, GKState* st, GKWork& wk, hipStream_t s);
 void op_norm(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, double* tmp_m, double* tmp_n,
              GKState* st, GKWork& wk, hipStream_t s);
-void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s);
+void op_matvec(const OpDesc& A, int trans, const double* x, double* y, GKState* st, GKWork& wk, hipStream_t s,
+               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <class V>
 void fill_zero(V* p, long long n, hipStream_t s);
 // CSR-stream products: non-zeros per workgroup for a matrix, workgroups, and
