@@ -89,7 +89,14 @@ typedef struct aplicur_opts {
   int32_t precond;   /* 1: APLICUR (default); 0: plain LSQR on A_mu (no sketch, no CUR)   */
   int32_t precision; /* 0: FP64 vectors and products (default)                             */
   int32_t max_outer; /* stop after this many outer steps (<= 0: no limit; for tests)       */
-  int32_t reserved[7];
+  int32_t workers;   /* aplicur_solve_batched: problems in flight at once, each on a stream
+                        of its own (<= 0: 4)                                                  */
+  int32_t tune;      /* 1: time candidate workgroup tiles of the product kernels on this
+                        matrix at set-up and keep the fastest (cached per shape); 0: fixed
+                        heuristic tiles.  Tiles change the summation order, not the method */
+  int32_t graphs;    /* 1: replay the LSQR iterations as captured HIP graphs (same kernels,
+                        same arithmetic); 0: launch each kernel                             */
+  int32_t reserved[4];
 } aplicur_opts;
 
 /* ------------------------------------------------------------------ info  */

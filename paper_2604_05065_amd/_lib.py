@@ -25,7 +25,8 @@ class Opts(C.Structure):
                 ("eps_cur", C.c_double), ("nu_prec", C.c_double), ("nu_lsqr", C.c_double),
                 ("eps_lsqr", C.c_double), ("tol_ne", C.c_double), ("max_iter", C.c_int32),
                 ("max_rank", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
-                ("max_outer", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("max_outer", C.c_int32), ("workers", C.c_int32), ("tune", C.c_int32),
+                ("graphs", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Info(C.Structure):

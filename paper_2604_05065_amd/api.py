@@ -67,7 +67,7 @@ def _stream():
 
 def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.0, eps_lsqr=1e-10,
               tol_ne=1e-8, max_iter=100000, max_rank=0, precond=True, precision=0, max_outer=0,
-              r_probes=10):
+              r_probes=10, workers=0, tune=0, graphs=0):
     lib = L.load()
     o = L.Opts()
     lib.aplicur_opts_default(C.byref(o))
@@ -75,6 +75,7 @@ def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.
     o.nu_prec, o.nu_lsqr, o.eps_lsqr, o.tol_ne = float(nu_prec), float(nu_lsqr), float(eps_lsqr), float(tol_ne)
     o.max_iter, o.max_rank, o.precond = int(max_iter), int(max_rank), int(bool(precond))
     o.precision, o.max_outer, o.r_probes = int(precision), int(max_outer), int(r_probes)
+    o.workers, o.tune, o.graphs = int(workers), int(bool(tune)), int(bool(graphs))
     return o
 
 
@@ -242,9 +243,12 @@ def lstsq_autograd(A, B, **opts):
     return LstsqFunction.apply(A, B, None, opts)
 
 
-def solve_batched(As, Bs, **opts):
+def solve_batched(As, Bs, workers=0, tune=True, graphs=True, **opts):
+    """Independent problems min ||A_p X_p - B_p||^2 + mu ||X_p||^2 (same
+    options, same number of right-hand sides), solved concurrently by the
+    library's worker streams; returns ([X_p], [info_p])."""
     lib = L.load()
-    o = make_opts(**opts)
+    o = make_opts(workers=workers, tune=tune, graphs=graphs, **opts)
     mats, keep = [], []
     for A in As:
         st, kp = _mat(A)

@@ -16,10 +16,16 @@
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/aplicur.h"
@@ -114,8 +120,12 @@ struct Ctx {
   std::vector<int> phase_iters0;
   std::vector<double> phase_eta0;
   double t_sketch = 0.0;
+  // captured LSQR iteration chunk (graphs option) and the key it was captured for
+  hipGraphExec_t gexec = nullptr;
+  long long gkey = -1;
 
   ~Ctx() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
     if (blas) rocblas_destroy_handle(blas);
     if (st_host) (void)hipHostFree(st_host);
     arena.release();
@@ -206,6 +216,94 @@ static void validate(const aplicur_mat* A, const aplicur_opts* o) {
   APL_REQUIRE(o->max_iter >= 0, "max_iter must be >= 0");
 }
 
+// ------------------------------------------------------------------ product tiles
+// Row chunks of the dense A^T product (partial column sums over m / chunks
+// rows each, then an ordered sum): about 2048 workgroups in all.
+static int dense_chunks(long long m, long long n) {
+  long long chunks = (2048 + (n + 255) / 256 - 1) / ((n + 255) / 256);
+  chunks = std::min<long long>(chunks, std::max<long long>(1, m / 32));
+  return (int)std::max<long long>(1, std::min<long long>(chunks, 1024));
+}
+
+// Candidate non-zeros per CSR-stream workgroup (LDS holds 2048 products).
+static constexpr int kTileT[3] = {1024, 1280, 1536};
+
+// Mean of the fastest launches of the A product plus the A^T product, in
+// microseconds, with A and A^T alternating as in the iteration (dispatch-timed events).
+static double time_pair(Ctx& c, int reps, hipStream_t s) {
+  std::vector<hipEvent_t> ev(4);
+  for (auto& e : ev) APL_HIP(hipEventCreate(&e));
+  double best_a = 1e30, best_t = 1e30;
+  for (int i = 0; i < reps; ++i) {
+    op_matvec(c.op, 0, c.v, c.u_top, c.st_mv, c.wk, s, ev[0], ev[1]);
+    op_matvec(c.op, 1, c.u_top, c.g, c.st_mv, c.wk, s, ev[2], ev[3]);
+    APL_HIP(hipEventSynchronize(ev[3]));
+    float a = 0.f, t = 0.f;
+    APL_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+    APL_HIP(hipEventElapsedTime(&t, ev[2], ev[3]));
+    if (i > 0) {  // the first round warms the caches
+      best_a = std::min(best_a, (double)a);
+      best_t = std::min(best_t, (double)t);
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return 1e3 * (best_a + best_t);
+}
+
+static std::mutex g_tile_mu;
+static std::map<std::tuple<int, int, long long, long long, long long>, int> g_tile_cache;
+
+// Autotuner: times each candidate tile of the product kernels on this matrix
+// (CSR: non-zeros per workgroup; dense: row chunks of A^T) and keeps the
+// fastest; the choice is cached per shape for the process.
+static void tune_tiles(Ctx& c, hipStream_t s) {
+  OpDesc& op = c.op;
+  const auto key = std::make_tuple(op.csr, op.f64, op.m, op.n, op.csr ? op.nnz : op.ld);
+  int choice = -1;
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tile_cache.find(key);
+    if (it != g_tile_cache.end()) choice = it->second;
+  }
+  std::vector<int> cand;
+  if (op.csr)
+    cand.assign(std::begin(kTileT), std::end(kTileT));
+  else
+    for (int f : {1, 2, 4})
+      for (int d : {1, 2})
+        if (f == 1 || d == 1) cand.push_back(std::max(1, std::min(1024, op.chunks * f / d)));
+  auto apply = [&](int v) {
+    if (op.csr) {
+      op.stream_t = v;
+      build_row_blocks(op.row_ptr, op.m, op.nnz, v, (int*)op.rb, s);
+      build_row_blocks(op.t_ptr, op.n, op.nnz, v, (int*)op.t_rb, s);
+    } else {
+      op.chunks = v;
+    }
+  };
+  if (choice < 0) {
+    fill(c.v, c.n, 1.0, s);
+    fill(c.u_top, c.m, 0.0, s);
+    double best = 1e30;
+    for (int v : cand) {
+      apply(v);
+      const double us = time_pair(c, 6, s);
+      if (us < best) {
+        best = us;
+        choice = v;
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tile_cache[key] = choice;
+  }
+  apply(choice);
+  if (c.fp32) {
+    c.op32.stream_t = op.stream_t;
+    c.op32.chunks = op.chunks;
+  }
+  APL_HIP(hipStreamSynchronize(s));
+}
+
 static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) {
   validate(Am, o);
   auto t0 = Clock::now();
@@ -252,8 +350,9 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       op.t_val = tv;
       op.nnz = Am->nnz;
       op.stream_t = stream_t(Am->nnz);
-      int* rbA = c->arena.alloc<int>(row_block_words(Am->nnz, op.stream_t));
-      int* rbT = c->arena.alloc<int>(row_block_words(Am->nnz, op.stream_t));
+      // sized for the smallest tile the autotuner may pick
+      int* rbA = c->arena.alloc<int>(row_block_words(Am->nnz, kTileT[0]));
+      int* rbT = c->arena.alloc<int>(row_block_words(Am->nnz, kTileT[0]));
       build_row_blocks(Am->row_ptr, m, Am->nnz, op.stream_t, rbA, s);
       build_row_blocks(tp, n, Am->nnz, op.stream_t, rbT, s);
       op.rb = rbA;
@@ -261,11 +360,8 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       op.group = group_for((double)Am->nnz / (double)m);
       op.t_group = group_for((double)Am->nnz / (double)n);
     } else {
-      long long chunks = (2048 + (n + 255) / 256 - 1) / ((n + 255) / 256);
-      chunks = std::min<long long>(chunks, std::max<long long>(1, m / 32));
-      chunks = std::max<long long>(1, std::min<long long>(chunks, 1024));
-      op.chunks = (int)chunks;
-      op.part = c->arena.alloc<double>((size_t)chunks * n);
+      op.chunks = dense_chunks(m, n);
+      op.part = c->arena.alloc<double>((size_t)std::min(1024, 4 * op.chunks) * n);
     }
     if (o->precision == 1) {
       // FP32 copy of the values (the CSR structure is shared)
@@ -304,7 +400,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
     c->t = c->arena.alloc<double>(n);
     c->g = c->arena.alloc<double>(std::max(m, n));
     {
-      const long long parts = 16384 + 256 + (op.csr ? stream_blocks(Am->nnz, op.stream_t) : 0);
+      const long long parts = 16384 + 256 + (op.csr ? stream_blocks(Am->nnz, kTileT[0]) : 0);
       c->wk.alpha_part = c->arena.alloc<double>(parts);
       c->wk.beta_part = c->arena.alloc<double>(parts);
     }
@@ -322,6 +418,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       APL_HIP(hipMemcpyAsync(c->st_mv, c->st_host, 2 * sizeof(GKState), hipMemcpyHostToDevice, s));
       APL_HIP(hipStreamSynchronize(s));
     }
+    if (o->tune) tune_tiles(*c, s);
     if (o->precond) {
       // sketch dimensions (Alg. 3: s = ceil(1.1 b), xi = min(8, s))
       int s_rows = (int)std::ceil(1.1 * o->block - 1e-12);
@@ -706,6 +803,40 @@ static GKState read_state(Ctx& c, hipStream_t s) {
 // restarts from the FP64 residual (iterative refinement).
 constexpr double kFp32PhaseRelTol = 1e-5;
 
+// Iterations per captured graph (graphs option).
+constexpr int kGraphChunk = 16;
+
+// The captured chunk of kGraphChunk iterations for this operator / P /
+// precision, captured again when any of them changes.  Capture needs a
+// stream other than the legacy default stream; returns null there.
+template <class V>
+static hipGraphExec_t phase_graph(Ctx& c, const OpDesc& A, GKVecs<V> vec, const PrecDesc* P, hipStream_t s) {
+  if (s == nullptr) return nullptr;
+  const long long key = (long long)sizeof(V) * 1000000007LL + (P ? 1 + 2LL * P->ell + (P->implicit ? 1 : 0) : 0) +
+                        (A.f64 ? 0 : 500000000LL);
+  if (c.gexec && c.gkey == key) return c.gexec;
+  if (c.gexec) {
+    APL_HIP(hipGraphExecDestroy(c.gexec));
+    c.gexec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  APL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < kGraphChunk; ++i) gk_iteration<V>(A, P, vec, c.st, c.wk, s);
+  const hipError_t e1 = hipGetLastError();
+  const hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    throw Error(APLICUR_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) throw Error(APLICUR_E_HIP, std::string("graph instantiation failed: ") + hipGetErrorString(e3));
+  c.gexec = ex;
+  c.gkey = key;
+  return ex;
+}
+
 template <class V>
 static PhaseOut run_phase_t(Ctx& c, const OpDesc& A, GKVecs<V> vec, const PrecDesc* P, const double* b,
                             const double* b_bot, double bot_scale, double* x, bool x_zero, hipStream_t s) {
@@ -713,14 +844,20 @@ static PhaseOut run_phase_t(Ctx& c, const OpDesc& A, GKVecs<V> vec, const PrecDe
   int chunk = 8;
   long long launched = 0;
   APL_HIP(hipGetLastError());
+  hipGraphExec_t gx = c.o.graphs ? phase_graph<V>(c, A, vec, P, s) : nullptr;
   GKState h = read_state(c, s);
   const long long budget = h.max_iter;
   while (!h.stop) {
-    for (int i = 0; i < chunk; ++i) gk_iteration<V>(A, P, vec, c.st, c.wk, s);
-    launched += chunk;
+    if (gx) {
+      APL_HIP(hipGraphLaunch(gx, s));
+      launched += kGraphChunk;
+    } else {
+      for (int i = 0; i < chunk; ++i) gk_iteration<V>(A, P, vec, c.st, c.wk, s);
+      launched += chunk;
+      chunk = std::min(chunk * 2, 64);
+    }
     APL_HIP(hipGetLastError());
     h = read_state(c, s);
-    chunk = std::min(chunk * 2, 64);
     if (!h.stop && launched > budget + 128)
       throw Error(APLICUR_E_HIP, "LSQR phase did not reach its stopping test within its budget");
   }
@@ -1044,6 +1181,78 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
   return status;
 }
 
+// ------------------------------------------------------------------ batched solves
+// Independent problems, largest first (by stored entries), taken from a
+// shared counter by `workers` host threads; each thread owns a HIP stream
+// (default priority) that first waits for the caller's stream, and runs
+// whole problems on it (context, solve, release).  Every problem uses the
+// same kernels as aplicur_solve; with the graphs option its LSQR iterations
+// replay as captured graphs on that stream.  Returns after all streams are
+// done; the first error (in problem order) is rethrown.
+static int solve_batched(int batch, const aplicur_mat* A, const double* const* B, const int64_t* ldb, int nrhs,
+                         double* const* X, const int64_t* ldx, const aplicur_opts& o, aplicur_info* info,
+                         hipStream_t caller) {
+  for (int p = 0; p < batch; ++p) validate(&A[p], &o);
+  std::vector<int> order(batch);
+  std::iota(order.begin(), order.end(), 0);
+  auto work = [&](int p) {
+    return A[p].format == APLICUR_CSR ? (double)A[p].nnz : (double)A[p].m * (double)A[p].n;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  const int workers = std::max(1, std::min(batch, o.workers > 0 ? o.workers : 4));
+  int dev = 0;
+  APL_HIP(hipGetDevice(&dev));
+  hipEvent_t ready = nullptr;
+  APL_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  APL_HIP(hipEventRecord(ready, caller));
+  std::atomic<int> next{0};
+  std::vector<int> status(batch, APLICUR_OK), code(batch, 0);
+  std::vector<std::string> msg(batch);
+  auto worker = [&]() {
+    hipStream_t s = nullptr;
+    if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamWaitEvent(s, ready, 0) != hipSuccess) {
+      const int i = next.fetch_add(1);
+      if (i < batch) {
+        code[order[i]] = APLICUR_E_HIP;
+        msg[order[i]] = "could not set up a worker stream";
+      }
+      if (s) (void)hipStreamDestroy(s);
+      return;
+    }
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= batch) break;
+      const int p = order[i];
+      Ctx* c = nullptr;
+      try {
+        c = create(&A[p], &o, s);
+        status[p] = solve(*c, B[p], ldb[p], nrhs, X[p], ldx[p], false, info ? &info[p] : nullptr, s);
+      } catch (const Error& e) {
+        code[p] = e.code;
+        msg[p] = e.what();
+      } catch (const std::exception& e) {
+        code[p] = APLICUR_E_HIP;
+        msg[p] = e.what();
+      }
+      delete c;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < workers; ++w) pool.emplace_back(worker);
+  worker();
+  for (auto& t : pool) t.join();
+  (void)hipEventDestroy(ready);
+  int worst = APLICUR_OK;
+  for (int p = 0; p < batch; ++p) {
+    if (code[p] != 0) throw Error(code[p], "problem " + std::to_string(p) + ": " + msg[p]);
+    worst = std::max(worst, status[p]);
+  }
+  return worst;
+}
+
 }  // namespace aplicur
 
 // ==================================================================== C ABI
@@ -1113,21 +1322,9 @@ int aplicur_solve_batched(int32_t batch, const aplicur_mat* A, const double* con
                           aplicur_info* info, void* stream) {
   return guarded([&]() {
     APL_REQUIRE(batch >= 0, "batch must be >= 0");
-    APL_REQUIRE(batch == 0 || (A && B && ldb && X && ldx && opts), "null batch arrays");
-    int worst = APLICUR_OK;
-    for (int p = 0; p < batch; ++p) {
-      Ctx* c = create(&A[p], opts, (hipStream_t)stream);
-      int st;
-      try {
-        st = solve(*c, B[p], ldb[p], nrhs, X[p], ldx[p], false, info ? &info[p] : nullptr, (hipStream_t)stream);
-      } catch (...) {
-        delete c;
-        throw;
-      }
-      delete c;
-      worst = std::max(worst, st);
-    }
-    return worst;
+    if (batch == 0) return (int)APLICUR_OK;
+    APL_REQUIRE(A && B && ldb && X && ldx && opts, "null batch arrays");
+    return solve_batched(batch, A, B, ldb, nrhs, X, ldx, *opts, info, (hipStream_t)stream);
   });
 }
 

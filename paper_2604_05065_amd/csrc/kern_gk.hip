@@ -274,14 +274,13 @@ __global__ void k_row_blocks(const int* rp, long long m, int T, RowBlk* rbk, int
 // CU at this kernel's LDS and register use), so T grows from 1024 with nnz up
 // to 1536, which leaves LDS room for a row tail of 512 non-zeros.
 int stream_t(long long nnz) {
-  static int cus = 0;
-  if (cus == 0) {
+  static const int cus = []() {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
       v = 256;
-    cus = v;
-  }
+    return v;
+  }();
   const long long resident = 7LL * cus - 64;
   long long t = (nnz + resident - 1) / resident;
   if (t < 1024) t = 1024;
