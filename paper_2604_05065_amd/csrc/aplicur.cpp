@@ -24,6 +24,7 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <shared_mutex>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -35,8 +36,17 @@ namespace aplicur {
 
 static thread_local std::string g_last_error;
 
+// Host calls that may synchronise with the legacy stream behind the scenes
+// (allocation and release, library handles, library calls, which may load or
+// set up kernels on first use) hold this lock shared; capturing a graph holds
+// it exclusively, because such a call from another thread during a capture
+// is an error.
+static std::shared_mutex g_capture_mu;
+using SyncGuard = std::shared_lock<std::shared_mutex>;
+
 #define APL_BLAS(x)                                                                        \
   do {                                                                                     \
+    SyncGuard blas_guard_(g_capture_mu);                                                   \
     rocblas_status s_ = (x);                                                               \
     if (s_ != rocblas_status_success)                                                      \
       throw ::aplicur::Error(-3, std::string(#x) + ": rocblas status " + std::to_string((int)s_)); \
@@ -54,6 +64,7 @@ struct Arena {
   T* alloc(size_t count) {
     if (count == 0) count = 1;
     void* p = nullptr;
+    SyncGuard g(g_capture_mu);
     hipError_t e = hipMalloc(&p, count * sizeof(T));
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -63,6 +74,7 @@ struct Arena {
     return (T*)p;
   }
   void release() {
+    SyncGuard g(g_capture_mu);
     for (void* p : ptrs) (void)hipFree(p);
     ptrs.clear();
   }
@@ -125,9 +137,12 @@ struct Ctx {
   long long gkey = -1;
 
   ~Ctx() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (blas) rocblas_destroy_handle(blas);
-    if (st_host) (void)hipHostFree(st_host);
+    {
+      SyncGuard g(g_capture_mu);
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      if (blas) rocblas_destroy_handle(blas);
+      if (st_host) (void)hipHostFree(st_host);
+    }
     arena.release();
   }
 };
@@ -232,7 +247,10 @@ static constexpr int kTileT[3] = {1024, 1280, 1536};
 // microseconds, with A and A^T alternating as in the iteration (dispatch-timed events).
 static double time_pair(Ctx& c, int reps, hipStream_t s) {
   std::vector<hipEvent_t> ev(4);
-  for (auto& e : ev) APL_HIP(hipEventCreate(&e));
+  {
+    SyncGuard g(g_capture_mu);
+    for (auto& e : ev) APL_HIP(hipEventCreate(&e));
+  }
   double best_a = 1e30, best_t = 1e30;
   for (int i = 0; i < reps; ++i) {
     op_matvec(c.op, 0, c.v, c.u_top, c.st_mv, c.wk, s, ev[0], ev[1]);
@@ -246,6 +264,7 @@ static double time_pair(Ctx& c, int reps, hipStream_t s) {
       best_t = std::min(best_t, (double)t);
     }
   }
+  SyncGuard g(g_capture_mu);
   for (auto& e : ev) (void)hipEventDestroy(e);
   return 1e3 * (best_a + best_t);
 }
@@ -408,7 +427,10 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
     c->counter = c->arena.alloc<unsigned>(4);
     c->st_mv = c->arena.alloc<GKState>(2);
     APL_HIP(hipMemsetAsync(c->counter, 0, 4 * sizeof(unsigned), s));
-    APL_HIP(hipHostMalloc((void**)&c->st_host, 2 * sizeof(GKState), hipHostMallocDefault));
+    {
+      SyncGuard g(g_capture_mu);
+      APL_HIP(hipHostMalloc((void**)&c->st_host, 2 * sizeof(GKState), hipHostMallocDefault));
+    }
     {
       GKState& h = c->st_host[0];
       std::memset(&h, 0, sizeof(h));
@@ -452,7 +474,10 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       } else {
         const int chunks = sketch_dense_chunks(m, n);
         double* part = nullptr;
-        APL_HIP(hipMalloc((void**)&part, sizeof(double) * (size_t)chunks * S * n));
+        {
+          SyncGuard g(g_capture_mu);
+          APL_HIP(hipMalloc((void**)&part, sizeof(double) * (size_t)chunks * S * n));
+        }
         if (op.f64)
           launch_sketch_dense<double>((const double*)op.val, m, n, op.ld, S, c->xi, c->S_rows, c->S_neg, c->Y,
                                       part, chunks, s);
@@ -460,6 +485,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
           launch_sketch_dense<float>((const float*)op.val, m, n, op.ld, S, c->xi, c->S_rows, c->S_neg, c->Y,
                                      part, chunks, s);
         APL_HIP(hipStreamSynchronize(s));
+        SyncGuard g(g_capture_mu);
         APL_HIP(hipFree(part));
       }
       // CUR / preconditioner storage (sized by the rank cap L)
@@ -816,10 +842,12 @@ static hipGraphExec_t phase_graph(Ctx& c, const OpDesc& A, GKVecs<V> vec, const 
                         (A.f64 ? 0 : 500000000LL);
   if (c.gexec && c.gkey == key) return c.gexec;
   if (c.gexec) {
+    SyncGuard gd(g_capture_mu);
     APL_HIP(hipGraphExecDestroy(c.gexec));
     c.gexec = nullptr;
   }
   hipGraph_t g = nullptr;
+  std::unique_lock<std::shared_mutex> excl(g_capture_mu);
   APL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   for (int i = 0; i < kGraphChunk; ++i) gk_iteration<V>(A, P, vec, c.st, c.wk, s);
   const hipError_t e1 = hipGetLastError();
@@ -828,6 +856,8 @@ static hipGraphExec_t phase_graph(Ctx& c, const OpDesc& A, GKVecs<V> vec, const 
     if (g) (void)hipGraphDestroy(g);
     throw Error(APLICUR_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   }
+  excl.unlock();
+  SyncGuard gi(g_capture_mu);
   hipGraphExec_t ex = nullptr;
   const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -1140,7 +1170,10 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
   if (dA) {
     // R = B - A X (m x k), then the rank-2k gradient
     double* work = nullptr;
-    APL_HIP(hipMalloc((void**)&work, sizeof(double) * (size_t)c.m * nrhs * 2));
+    {
+      SyncGuard g(g_capture_mu);
+      APL_HIP(hipMalloc((void**)&work, sizeof(double) * (size_t)c.m * nrhs * 2));
+    }
     try {
       double* AX = work;
       double* R = work + (size_t)c.m * nrhs;
@@ -1161,9 +1194,11 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
       APL_HIP(hipGetLastError());
       APL_HIP(hipStreamSynchronize(s));
     } catch (...) {
+      SyncGuard g(g_capture_mu);
       (void)hipFree(work);
       throw;
     }
+    SyncGuard g(g_capture_mu);
     APL_HIP(hipFree(work));
   }
   APL_HIP(hipGetLastError());
@@ -1210,8 +1245,13 @@ static int solve_batched(int batch, const aplicur_mat* A, const double* const* B
   std::vector<std::string> msg(batch);
   auto worker = [&]() {
     hipStream_t s = nullptr;
-    if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamWaitEvent(s, ready, 0) != hipSuccess) {
+    bool ok;
+    {
+      SyncGuard g(g_capture_mu);
+      ok = hipSetDevice(dev) == hipSuccess && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+           hipStreamWaitEvent(s, ready, 0) == hipSuccess;
+    }
+    if (!ok) {
       const int i = next.fetch_add(1);
       if (i < batch) {
         code[order[i]] = APLICUR_E_HIP;
@@ -1238,6 +1278,7 @@ static int solve_batched(int batch, const aplicur_mat* A, const double* const* B
       delete c;
     }
     (void)hipStreamSynchronize(s);
+    SyncGuard g(g_capture_mu);
     (void)hipStreamDestroy(s);
   };
   std::vector<std::thread> pool;

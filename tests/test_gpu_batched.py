@@ -56,6 +56,19 @@ def test_batched_equals_one_at_a_time(lib, precond):
             assert ne_residual(A, B[:, k], X[:, k].cpu().numpy(), OPTS["mu"]) <= 1.5 * OPTS["tol_ne"]
 
 
+def test_batched_many_workers_capture_while_others_set_up(lib):
+    """Eight workers: graph captures overlap other workers' context set-up,
+    library calls and releases (guarded by the library)."""
+    probs = _batch(count=12, nrhs=1)
+    As = [_gpu(lib, A) for A, _ in probs]
+    Bs = [_t(B[:, 0]) for _, B in probs]
+    for tune in (True, False):
+        Xs, infos = lib.solve_batched(As, Bs, workers=8, tune=tune, graphs=True, **OPTS)
+        for (A, B), X, info in zip(probs, Xs, infos):
+            assert info.status == 0
+            assert ne_residual(A, B[:, 0], X.cpu().numpy(), OPTS["mu"]) <= 1.5 * OPTS["tol_ne"]
+
+
 def test_batched_tuned_tiles(lib):
     """With autotuned tiles the summation order may differ; the solutions
     still meet the tolerance and agree with dense QR."""
