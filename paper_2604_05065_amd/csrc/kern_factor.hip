@@ -416,9 +416,16 @@ void small_potrf(double* G, long long ld, int k, int* status, hipStream_t s) {
 // diagonalised by cyclic Jacobi in LDS, and the rotation applied to the
 // columns of X and of V.  Round-robin pairing covers every block pair once
 // per sweep (Hestenes' method, block form).  sweepmax receives the largest
-// relative off-diagonal |g_pq| / sqrt(g_pp g_qq) seen in the round.
-constexpr int kJW = 16;       // columns per block
+// relative off-diagonal |g_pq| / sqrt(g_pp g_qq) seen in the round.  Each
+// round takes a few inner sweeps on the pair's Gram matrix only (the outer
+// sweeps repeat the pairing until the whole matrix is orthogonal), and a
+// pair that is already orthogonal to the skip level leaves X and V as they are.
+constexpr int kJW = 8;        // columns per block
 constexpr int kJP = 2 * kJW;  // columns per pair
+constexpr int kJInner = 1;    // inner sweeps per pair and round
+constexpr int kJT = 512;      // threads per pair
+constexpr int kJR = 64;       // rows per Gram tile
+constexpr int kJGE = (kJP * kJP + kJT - 1) / kJT;  // Gram entries per thread
 
 __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, int& b) {
   // circle method: block nblk-1 fixed, the others rotate
@@ -436,12 +443,12 @@ __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, i
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_jacobi_round(double* X, long long ldx, int rows, double* Vm,
+__global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, int rows, double* Vm,
                                                          long long ldv, int vrows, int nblk, int round,
-                                                         unsigned long long* offmax) {
+                                                         unsigned long long* offmax, double skip) {
   __shared__ double G[kJP][kJP + 1];
   __shared__ double Q[kJP][kJP + 1];
-  __shared__ double tile[64][kJP + 1];
+  __shared__ double tile[kJR][kJP + 1];
   __shared__ double cs[kJW], sn[kJW];
   __shared__ int pp_[kJW], qq_[kJW];
   __shared__ double block_off;
@@ -450,36 +457,40 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_round(double* X, long long ld
   int col[2] = {a * kJW, b * kJW};
   const int tid = threadIdx.x;
   // 1) Gram matrix of the 2*kJW columns
-  double acc[4] = {0, 0, 0, 0};
-  for (int r0 = 0; r0 < rows; r0 += 64) {
-    for (int e = tid; e < 64 * kJP; e += kBlock) {
-      const int rr = e % 64, cc = e / 64;
+  double acc[kJGE];
+#pragma unroll
+  for (int t = 0; t < kJGE; ++t) acc[t] = 0.0;
+  for (int r0 = 0; r0 < rows; r0 += kJR) {
+    for (int e = tid; e < kJR * kJP; e += kJT) {
+      const int rr = e % kJR, cc = e / kJR;
       const int gc = col[cc / kJW] + (cc % kJW);
       tile[rr][cc] = (r0 + rr < rows) ? X[(long long)(r0 + rr) + (long long)gc * ldx] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int e = tid + t * kBlock;
-      const int i = e % kJP, j = e / kJP;
-      double s = 0.0;
-      for (int rr = 0; rr < 64; ++rr) s += tile[rr][i] * tile[rr][j];
-      acc[t] += s;
+    for (int t = 0; t < kJGE; ++t) {
+      const int e = tid + t * kJT;
+      if (e < kJP * kJP) {
+        const int i = e % kJP, j = e / kJP;
+        double s = 0.0;
+        for (int rr = 0; rr < kJR; ++rr) s += tile[rr][i] * tile[rr][j];
+        acc[t] += s;
+      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int e = tid + t * kBlock;
-    G[e % kJP][e / kJP] = acc[t];
+  for (int t = 0; t < kJGE; ++t) {
+    const int e = tid + t * kJT;
+    if (e < kJP * kJP) G[e % kJP][e / kJP] = acc[t];
   }
-  for (int e = tid; e < kJP * kJP; e += kBlock) Q[e % kJP][e / kJP] = (e % kJP == e / kJP) ? 1.0 : 0.0;
+  for (int e = tid; e < kJP * kJP; e += kJT) Q[e % kJP][e / kJP] = (e % kJP == e / kJP) ? 1.0 : 0.0;
   if (tid == 0) block_off = 0.0;
   __syncthreads();
   // measure off-diagonality of the pair
   {
     double mx = 0.0;
-    for (int e = tid; e < kJP * kJP; e += kBlock) {
+    for (int e = tid; e < kJP * kJP; e += kJT) {
       const int i = e % kJP, j = e / kJP;
       if (i < j) {
         const double d = sqrt(G[i][i] * G[j][j]);
@@ -487,10 +498,10 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_round(double* X, long long ld
       }
     }
     // block max through LDS
-    __shared__ double red[kBlock];
+    __shared__ double red[kJT];
     red[tid] = mx;
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
+    for (int off = kJT / 2; off > 0; off >>= 1) {
       if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
       __syncthreads();
     }
@@ -501,7 +512,8 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_round(double* X, long long ld
     __syncthreads();
   }
   // 2) cyclic Jacobi on G (kJP x kJP), parallel round-robin over kJP/2 pairs
-  for (int sweep = 0; sweep < 12; ++sweep) {
+  if (block_off <= skip) return;
+  for (int sweep = 0; sweep < kJInner; ++sweep) {
     __shared__ int changed;
     if (tid == 0) changed = 0;
     __syncthreads();
@@ -536,7 +548,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_round(double* X, long long ld
       }
       __syncthreads();
       // columns of G and Q: G <- G J, Q <- Q J
-      for (int e = tid; e < kJW * kJP; e += kBlock) {
+      for (int e = tid; e < kJW * kJP; e += kJT) {
         const int pr = e / kJP, row = e % kJP;
         const int p = pp_[pr], q = qq_[pr];
         const double c = cs[pr], s = sn[pr];
@@ -549,7 +561,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_round(double* X, long long ld
       }
       __syncthreads();
       // rows of G: G <- J^T G
-      for (int e = tid; e < kJW * kJP; e += kBlock) {
+      for (int e = tid; e < kJW * kJP; e += kJT) {
         const int pr = e / kJP, cc = e % kJP;
         const int p = pp_[pr], q = qq_[pr];
         const double c = cs[pr], s = sn[pr];
@@ -562,12 +574,11 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_round(double* X, long long ld
     if (!changed) break;
   }
   // 3) apply Q to the columns of X and of V
-  if (block_off == 0.0) return;
   for (int pass = 0; pass < 2; ++pass) {
     double* M = pass == 0 ? X : Vm;
     const long long ld = pass == 0 ? ldx : ldv;
     const int nr = pass == 0 ? rows : vrows;
-    for (int r = tid; r < nr; r += kBlock) {
+    for (int r = tid; r < nr; r += kJT) {
       double in[kJP];
 #pragma unroll
       for (int cc = 0; cc < kJP; ++cc) in[cc] = M[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld];
@@ -602,8 +613,8 @@ int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long 
   for (; sweeps < max_sweeps; ++sweeps) {
     APL_HIP(hipMemsetAsync(offmax_dev, 0, sizeof(unsigned long long), s));
     for (int r = 0; r < nblk - 1; ++r)
-      hipLaunchKernelGGL(k_jacobi_round, dim3(nblk / 2), dim3(kBlock), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
-                         offmax_dev);
+      hipLaunchKernelGGL(k_jacobi_round, dim3(nblk / 2), dim3(kJT), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
+                         offmax_dev, 0.01 * tol);
     unsigned long long h = 0;
     APL_HIP(hipMemcpyAsync(&h, offmax_dev, sizeof(h), hipMemcpyDeviceToHost, s));
     APL_HIP(hipStreamSynchronize(s));
