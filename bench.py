@@ -94,6 +94,57 @@ def cpu_baseline(A, b, mu, plain_iters, budget_s=15.0):
                        f"iterations plain LSQR needs for eta <= 1e-8")}
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3, out
+
+
+def bench_batched(ap, synth, torch, count=16, scale=0.25, nrhs=2):
+    """The batched workload at 1/4 of its sizes (m ~ U{1250..25000}, n ~
+    U{125..min(1250, m/4)}, sigma_i = 10^(-k i/n), k ~ U[2,8], FP32, 2 RHS,
+    mu = 1e-6, block 50): one batched call (worker streams, graph replay,
+    tuned tiles) against one-at-a-time APLICUR and one-at-a-time plain LSQR."""
+    shapes = synth.batch_shapes(count, m_range=(int(5000 * scale), int(100000 * scale)),
+                                n_range=(int(500 * scale), int(5000 * scale)))
+    probs = [synth.dense_svd_gpu(4000 + i, m, n, k, nrhs) for i, (m, n, k) in enumerate(shapes)]
+    opts = dict(mu=1e-6, block=50, tol_ne=1e-8)
+    As, Bs = [p[0] for p in probs], [p[1] for p in probs]
+    ap.solve_batched(As[:2], Bs[:2], workers=2, **opts)  # warm-up
+    ms_b, (_, infos) = _timed(torch, lambda: ap.solve_batched(As, Bs, workers=8, **opts))
+    ms_s, inf_s = _timed(torch, lambda: [ap.lstsq(A, B, **opts)[1] for A, B in zip(As, Bs)])
+    ms_p, inf_p = _timed(torch, lambda: [ap.lstsq(A, B, precond=False, **opts)[1] for A, B in zip(As, Bs)])
+    ok = all(i.status == 0 for i in list(infos) + inf_s + inf_p)
+    log(f"[bench] batched {count} problems: batched {ms_b:.0f} ms, one-at-a-time APLICUR {ms_s:.0f} ms, "
+        f"plain LSQR {ms_p:.0f} ms (all converged: {ok})")
+    return {"problems": count, "nrhs": nrhs, "sum_mn": int(sum(m * n for m, n, _ in shapes)),
+            "batched_ms": round(ms_b, 1), "sequential_aplicur_ms": round(ms_s, 1),
+            "sequential_plain_ms": round(ms_p, 1), "workers": 8, "all_converged": ok,
+            "max_iters_aplicur": max(i.iters for i in inf_s), "max_iters_plain": max(i.iters for i in inf_p)}
+
+
+def bench_adjoint(ap, synth, torch, m=25000, n=500, nrhs=4):
+    """The adjoint workload at 1/4 of its sizes (dense FP32 25000 x 500,
+    sigma_i = 10^(-5 i/n), 4 RHS, mu = 1e-5, block 100; L = sum X^2): forward
+    APLICUR, backward with the final preconditioner, and the same backward
+    with plain LSQR (no preconditioner)."""
+    A, B = synth.dense_svd_gpu(5000, m, n, 5.0, nrhs)
+    opts = dict(mu=1e-5, block=100, tol_ne=1e-8)
+    with ap.Context(A, **opts) as ctx:
+        ms_f, (X, info) = _timed(torch, lambda: ctx.solve(B))
+        ms_b, (Z, dB, dA, binfo) = _timed(torch, lambda: ctx.solve_backward(X, B, 2.0 * X))
+    with ap.Context(A, precond=False, **opts) as ctx:
+        X0, _ = ctx.solve(B)
+        ms_p, (_, _, _, pinfo) = _timed(torch, lambda: ctx.solve_backward(X0, B, 2.0 * X0))
+    log(f"[bench] adjoint {m}x{n}: forward {ms_f:.0f} ms, backward {ms_b:.0f} ms (eta {binfo.eta:.1e}, "
+        f"{binfo.iters} it), plain backward {ms_p:.0f} ms ({pinfo.iters} it)")
+    return {"m": m, "n": n, "nrhs": nrhs, "forward_ms": round(ms_f, 1), "backward_ms": round(ms_b, 1),
+            "backward_eta": binfo.eta, "backward_iters": binfo.iters, "plain_backward_ms": round(ms_p, 1),
+            "plain_backward_iters": pinfo.iters, "rank": info.rank}
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -103,6 +154,7 @@ def main():
     ap_.add_argument("--no-cpu", action="store_true")
     ap_.add_argument("--no-compare", action="store_true")
     ap_.add_argument("--products-only", action="store_true")
+    ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
     args = ap_.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): every problem here fits one MI355X and "
@@ -184,6 +236,11 @@ def main():
                 plain_iters = inf.iters
             log(f"[bench] {name}: {ms:.1f} ms iters={inf.iters} phases={inf.phases} eta={inf.eta:.2e}")
 
+    batched = adjoint = None
+    if not args.no_extensions:
+        batched = bench_batched(ap, synth, torch)
+        adjoint = bench_adjoint(ap, synth, torch)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(A, b, mu, plain_iters or 8400)
@@ -209,6 +266,8 @@ def main():
                     "t_cur_ms": round(info.t_cur_ms, 2), "t_precond_ms": round(info.t_precond_ms, 2),
                     "t_lsqr_ms": round(info.t_lsqr_ms, 2)},
         "compare": compare or None,
+        "batched": batched,
+        "adjoint": adjoint,
         "matvec": {"A_us": round(us_a, 3), "A_GBs": round(gbs_a, 1), "AT_us": round(us_at, 3),
                    "AT_GBs": round(gbs_at, 1), "AT_bytes": int(bytes_at)},
     }

@@ -24,7 +24,7 @@ import numpy as np
 import scipy.sparse as sp
 
 __all__ = ["rng_for", "haar", "dense_svd", "sparse_scaled", "rbf_kernel", "consistent_x",
-           "workload", "batch_shapes", "Workload"]
+           "workload", "batch_shapes", "Workload", "dense_svd_gpu"]
 
 
 def rng_for(c, k):
@@ -152,3 +152,20 @@ def batch_problem(idx, m, n, k, nrhs=8, dtype=np.float32):
     A = dense_svd(r, m, n, sigma).astype(dtype)
     B = r.standard_normal((m, nrhs)).astype(dtype)
     return A, B
+
+
+def dense_svd_gpu(seed, m, n, decades, nrhs, dtype="float32"):
+    """Dense A = U diag(10^(-decades i / n)) V^T (Haar U, V from QR of
+    Gaussians) and B (m x nrhs, N(0,1)) generated on the GPU with torch
+    (seeded; for the large batched and adjoint workloads, where host QR is too
+    slow).  Returns (A, B) as CUDA tensors, A in `dtype`, B in float64."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed))
+    U, _ = torch.linalg.qr(torch.randn(m, n, device="cuda", dtype=torch.float64, generator=g))
+    V, _ = torch.linalg.qr(torch.randn(n, n, device="cuda", dtype=torch.float64, generator=g))
+    sig = 10.0 ** (-float(decades) * torch.arange(1, n + 1, device="cuda", dtype=torch.float64) / n)
+    A = ((U * sig) @ V.T).to(getattr(torch, dtype)).contiguous()
+    B = torch.randn(m, nrhs, device="cuda", dtype=torch.float64, generator=g)
+    return A, B
+
