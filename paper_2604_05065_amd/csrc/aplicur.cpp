@@ -103,7 +103,8 @@ struct Ctx {
   int rank = 0;
   // preconditioner
   double *Mx = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
-         *pa_part = nullptr, *pa_c = nullptr, *Kc = nullptr, *Kr = nullptr, *pc1 = nullptr, *pc2 = nullptr;
+         *pa_part = nullptr, *pa_c = nullptr, *Kc = nullptr, *Kr = nullptr, *pc1 = nullptr, *pc2 = nullptr,
+         *M2 = nullptr;
   int *rr_ptr = nullptr, *rr_idx = nullptr, *rt_ptr = nullptr, *rt_idx = nullptr, *rscratch = nullptr;
   double *rr_val = nullptr, *rt_val = nullptr;
   unsigned long long* offmax = nullptr;
@@ -325,6 +326,10 @@ static void tune_tiles(Ctx& c, hipStream_t s) {
 
 static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) {
   validate(Am, o);
+  {
+    SyncGuard g(g_capture_mu);
+    gk_prepare();
+  }
   auto t0 = Clock::now();
   Ctx* c = new Ctx();
   try {
@@ -374,6 +379,14 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       int* rbT = c->arena.alloc<int>(row_block_words(Am->nnz, kTileT[0]));
       build_row_blocks(Am->row_ptr, m, Am->nnz, op.stream_t, rbA, s);
       build_row_blocks(tp, n, Am->nnz, op.stream_t, rbT, s);
+      // LDS-resident A x when x fits one workgroup's LDS (FP64 vectors need n <= about 19900)
+      {
+        const int tl = lx_stream_t(Am->nnz);
+        int* rbL = c->arena.alloc<int>(row_block_words(Am->nnz, tl));
+        build_row_blocks(Am->row_ptr, m, Am->nnz, tl, rbL, s);
+        op.lx_rb = rbL;
+        op.lx_grid = stream_blocks(Am->nnz, tl);
+      }
       op.rb = rbA;
       op.t_rb = rbT;
       op.group = group_for((double)Am->nnz / (double)m);
@@ -535,6 +548,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
         c->rscratch = c->arena.alloc<int>(std::max<long long>(n, L));
         c->pc1 = c->arena.alloc<double>(L);
         c->pc2 = c->arena.alloc<double>(L);
+        c->M2 = c->arena.alloc<double>((size_t)L * L);
         c->prec.I = c->I_dev;
         c->prec.Kt = c->Kc;
         c->prec.Kr = c->Kr;
@@ -742,6 +756,9 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ preconditioner (Alg. 2 Part 2)
+// Largest diagonal ratio of T_R for which the one-product form M2 is used.
+constexpr double kM2MaxDiagRatio = 1e3;
+
 static void build_precond(Ctx& c, hipStream_t s) {
   const int l = c.rank, L = c.L;
   const int jw2 = 2 * jacobi_block_width();
@@ -752,13 +769,33 @@ static void build_precond(Ctx& c, hipStream_t s) {
   gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Mx, L);
   set_identity(c.Vm, lp, lp, s);
   jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.offmax, 1e-14, 40, s);
+  precond_scalars(c.sigma, l, c.delta, c.d, c.pinfo, s);
   if (c.prec.implicit) {
     // K = T_R^{-1} V_M (column-major, ld l: the row-major K^T) and K row-major
     copy_block(c.Vm, lp, c.Kc, l, l, l, 1.0, s);
     const double one = 1.0;
     APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
                            rocblas_diagonal_non_unit, l, l, &one, c.TR, L, c.Kc, l));
-    transpose_square(c.Kc, l, c.Kr, l, s);
+    // M2 = K diag(d) K^T replaces the two K products when T_R is well
+    // conditioned (its rounding error grows with cond(T_R)^2, the two-product
+    // form's with cond(T_R)); the diagonal ratio of T_R is the indicator.
+    std::vector<double> diag(l);
+    APL_HIP(hipMemcpy2DAsync(diag.data(), sizeof(double), c.TR, (size_t)(L + 1) * sizeof(double), sizeof(double), l,
+                             hipMemcpyDeviceToHost, s));
+    APL_HIP(hipStreamSynchronize(s));
+    double dmin = INFINITY, dmax = 0.0;
+    for (double v : diag) {
+      dmin = std::min(dmin, std::fabs(v));
+      dmax = std::max(dmax, std::fabs(v));
+    }
+    if (dmin > 0.0 && dmax / dmin <= kM2MaxDiagRatio) {
+      scale_cols(c.Kc, l, l, l, c.d, c.Kr, s);
+      gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.Kr, l, c.Kc, l, 0.0, c.M2, l);
+      c.prec.M2 = c.M2;
+    } else {
+      transpose_square(c.Kc, l, c.Kr, l, s);
+      c.prec.M2 = nullptr;
+    }
     // CSR of R = A(I,:) and of R^T
     long long nnzR;
     if (c.op.f64)
@@ -775,7 +812,6 @@ static void build_precond(Ctx& c, hipStream_t s) {
          c.Vhat, l);
     c.prec.ldv = l;
   }
-  precond_scalars(c.sigma, l, c.delta, c.d, c.pinfo, s);
   double info[4];
   APL_HIP(hipMemcpyAsync(info, c.pinfo, sizeof(info), hipMemcpyDeviceToHost, s));
   c.p_sigma_host.resize(l);

@@ -763,6 +763,22 @@ void transpose_square(const double* src, long long lds, double* dst, int n, hipS
   hipLaunchKernelGGL(k_transpose, g, dim3(kBlock), 0, s, src, lds, dst, n);
 }
 
+// ---------------------------------------------------------------- column scaling
+__global__ void k_scale_cols(const double* X, long long ld, int rows, int cols, const double* d, double* out) {
+  const long long total = (long long)rows * cols;
+  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total; t += (long long)gridDim.x * kBlock) {
+    const long long i = t % rows, j = t / rows;
+    out[i + j * ld] = X[i + j * ld] * d[j];
+  }
+}
+
+void scale_cols(const double* X, long long ld, int rows, int cols, const double* d, double* out, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  long long g = ((long long)rows * cols + kBlock - 1) / kBlock;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)g), dim3(kBlock), 0, s, X, ld, rows, cols, d, out);
+}
+
 // ---------------------------------------------------------------- FP32 copies
 __global__ void k_to_f32(const double* src, long long lds, float* dst, long long ldd, long long rows, long long cols) {
   const long long total = rows * cols;

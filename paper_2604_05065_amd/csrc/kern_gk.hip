@@ -23,6 +23,8 @@
 // stopping applies the last y update itself.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace aplicur {
@@ -132,8 +134,9 @@ __device__ __forceinline__ void beta_step(GKState& s, double b2) {
 // before the first wait; sum() masks and adds them.  Partials beyond the first
 // round (grids above kShare * kBlock workgroups) are summed at once.
 constexpr int kShare = 8;
-struct Share {
-  double t[kShare];
+template <int NT = kBlock, int KS = kShare>
+struct ShareT {
+  double t[KS];
   double rest;
   int count;
   __device__ __forceinline__ void load(const double* __restrict__ part, int count_) {
@@ -141,29 +144,43 @@ struct Share {
     rest = 0.0;
     if (count <= 0) return;
 #pragma unroll
-    for (int q = 0; q < kShare; ++q) t[q] = part[min(q * kBlock + (int)threadIdx.x, count - 1)];
-    for (int i = kShare * kBlock + threadIdx.x; i < count; i += kBlock) rest += part[i];
+    for (int q = 0; q < KS; ++q) t[q] = part[min(q * NT + (int)threadIdx.x, count - 1)];
+    for (int i = KS * NT + threadIdx.x; i < count; i += NT) rest += part[i];
   }
   __device__ __forceinline__ double sum() const {
     double v = 0.0;
     if (count <= 0) return v;
 #pragma unroll
-    for (int q = 0; q < kShare; ++q) v += (q * kBlock + (int)threadIdx.x < count) ? t[q] : 0.0;
+    for (int q = 0; q < KS; ++q) v += (q * NT + (int)threadIdx.x < count) ? t[q] : 0.0;
     return v + rest;
   }
 };
+using Share = ShareT<>;
 
 // Wave sums into red[]; the caller's barrier follows.
-__device__ __forceinline__ void publish(const Share& sh, double* red) {
+template <class SH>
+__device__ __forceinline__ void publish(const SH& sh, double* red) {
   const double v = wave_sum(sh.sum());
   if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
 }
 
+template <int NT = kBlock>
 __device__ __forceinline__ double settled(const double* red) {
   double t = 0.0;
 #pragma unroll
-  for (int i = 0; i < kBlock / kWave; ++i) t += red[i];
+  for (int i = 0; i < NT / kWave; ++i) t += red[i];
   return t;
+}
+
+// Sum over a workgroup of NT threads; valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum_t(double v) {
+  __shared__ double red[NT / kWave];
+  v = wave_sum(v);
+  __syncthreads();
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  return threadIdx.x == 0 ? settled<NT>(red) : 0.0;
 }
 
 __device__ __forceinline__ void store_state(GKState* out, const GKState& s) {
@@ -420,6 +437,126 @@ __global__ void __launch_bounds__(kBlock)
     if (MODE == kFwdPlain && s.stop) return;
   }
   const double bs = block_sum(sq);
+  if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
+}
+
+// A x with x resident in LDS (n values fit one workgroup's LDS): one
+// 1024-thread workgroup per CU and row block (rows starting in its window of
+// nnz / grid non-zeros).  Stage 1 loads x into LDS together with the row-block
+// pair, the producer partials and the state; each thread then takes one row
+// (rows beyond 1024 loop), loads its pointers and its first kLxChunk values
+// and columns at once, and sums val * x[col] from LDS in row order.  The
+// workgroup also owns a slice of the n bottom rows (u_bot and the y/w update).
+constexpr int kLxT = 1024;
+constexpr int kLxChunk = 12;
+
+template <class TA, class V, int MODE>
+__global__ void __launch_bounds__(kLxT)
+    k_fwd_csr_lx(const RowBlk* __restrict__ rbk, const int* __restrict__ rp, const int* __restrict__ ci,
+                 const TA* __restrict__ val, long long n, const V* tin, V* u_top, V* u_bot, const V* v, V* w, V* y,
+                 const GKState* __restrict__ st_in, GKState* __restrict__ st_out, const double* alpha_part,
+                 int alpha_count, double* beta_part) {
+  extern __shared__ double lx_raw[];
+  V* xs = (V*)lx_raw;
+  __shared__ double red[kLxT / kWave];
+  const RowBlk ra = rbk[blockIdx.x], rb = rbk[blockIdx.x + 1];
+  GKState s = *st_in;
+  const double delta = st_in->delta;
+  ShareT<kLxT, 2> share;
+  share.load(MODE == kFwdPlain ? alpha_part : nullptr, alpha_count);
+  if (MODE != kFwdMatvec && s.stop) {
+    if (MODE == kFwdPlain) store_state(st_out, s);
+    return;
+  }
+  // x -> LDS, 12 loads per thread in flight
+  for (long long base = threadIdx.x; base < n; base += (long long)kLxT * 12) {
+    V tmp[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) tmp[q] = tin[min(base + (long long)q * kLxT, n - 1)];
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+      if (base + (long long)q * kLxT < n) xs[base + (long long)q * kLxT] = tmp[q];
+  }
+  // bottom slice [j0, j1) of the n rows
+  const long long per = (n + gridDim.x - 1) / gridDim.x;
+  const long long j0 = (long long)blockIdx.x * per, j1 = min(n, j0 + per);
+  const long long jb = j0 + threadIdx.x;
+  V bt = 0, bub = 0, bv = 0, bw = 0, by = 0;
+  if (MODE != kFwdMatvec && jb < j1) {
+    bt = tin[jb];
+    bub = u_bot[jb];
+    if (MODE == kFwdPlain) {
+      bv = v[jb];
+      bw = w[jb];
+      by = y[jb];
+    }
+  }
+  const int r0 = ra.r0, rows = rb.r0 - ra.r0;
+  double sq = 0.0;
+  bool go = true;
+  V ts = 0, cu = 0, cy = 0, cw = 0;
+  bool pend = false;
+  for (int rbase = 0; rbase < rows || rbase == 0; rbase += kLxT) {
+    const int ri = rbase + threadIdx.x;
+    const bool mine = ri < rows;
+    const int r = r0 + (mine ? ri : 0);
+    int k = 0, kend = 0;
+    V uo = 0;
+    if (mine) {
+      k = rp[r];
+      kend = rp[r + 1];
+      uo = u_top[r];
+    }
+    int cidx[kLxChunk];
+    TA vv[kLxChunk];
+#pragma unroll
+    for (int q = 0; q < kLxChunk; ++q) {
+      const int e = min(k + q, max(kend - 1, 0));
+      cidx[q] = mine && k + q < kend ? ci[e] : 0;
+      vv[q] = mine && k + q < kend ? val[e] : (TA)0;
+    }
+    if (rbase == 0) {
+      // x in LDS and the producer reduction: one barrier
+      publish(share, red);
+      __syncthreads();
+      if (MODE == kFwdPlain) {
+        scalar_step(s, sqrt(settled<kLxT>(red)));
+        store_state(st_out, s);
+        if (s.stop) {
+          if (jb < j1 && s.pending) y[jb] = by + (V)s.coef_y * bw;
+          go = false;
+        }
+      }
+      ts = (V)(1.0 / s.alpha);
+      cu = (V)(s.alpha / s.beta);
+      pend = (MODE == kFwdPlain) && s.pending;
+      cy = (V)s.coef_y;
+      cw = (V)s.coef_w;
+    }
+    if (!go) return;
+    V acc = 0;
+#pragma unroll
+    for (int q = 0; q < kLxChunk; ++q) acc += (V)vv[q] * xs[cidx[q]];
+    for (int e = k + kLxChunk; e < kend; ++e) acc += (V)val[e] * xs[ci[e]];
+    if (mine) {
+      const V un = acc * ts - cu * uo;
+      u_top[r] = un;
+      sq += (double)un * (double)un;
+    }
+    if (rows == 0) break;
+  }
+  if (MODE != kFwdMatvec && jb < j1) {
+    if (delta > 0.0) {
+      const V ub = (V)delta * (bt * ts) - cu * bub;
+      u_bot[jb] = ub;
+      sq += (double)ub * (double)ub;
+    }
+    if (pend) {
+      y[jb] = by + cy * bw;
+      w[jb] = bv * ts - cw * bw;
+    }
+  }
+  const double bs = block_sum_t<kLxT>(sq);
   if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
 }
 
@@ -919,11 +1056,56 @@ static unsigned prec_grid(const PrecDesc& P, long long n) {
 // Launch; with events, through the dispatch-timed launch (the events take the
 // kernel's own start and end timestamps, as a kernel trace does).
 template <class F, class... Args>
-static void launch_k(F kern, dim3 g, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+static void launch_kx(F kern, dim3 g, dim3 b, unsigned shm, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                      Args... args) {
   if (e0 || e1)
-    hipExtLaunchKernelGGL(kern, g, dim3(kBlock), 0, s, e0, e1, 0, args...);
+    hipExtLaunchKernelGGL(kern, g, b, shm, s, e0, e1, 0, args...);
   else
-    hipLaunchKernelGGL(kern, g, dim3(kBlock), 0, s, args...);
+    hipLaunchKernelGGL(kern, g, b, shm, s, args...);
+}
+template <class F, class... Args>
+static void launch_k(F kern, dim3 g, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+  launch_kx(kern, g, dim3(kBlock), 0u, s, e0, e1, args...);
+}
+
+// LDS available to the x copy of the LDS-resident forward kernel, and the
+// size from which it beats the CSR-stream kernel (below it, loading x into
+// every workgroup's LDS costs more than the gathers it saves).
+constexpr long long kLxMaxBytes = 160 * 1024 - 1024;
+constexpr long long kLxMinNnz = 1500000;
+
+template <class TA, class V>
+static void lx_attr() {
+  (void)hipFuncSetAttribute((const void*)k_fwd_csr_lx<TA, V, kFwdPlain>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kLxMaxBytes);
+  (void)hipFuncSetAttribute((const void*)k_fwd_csr_lx<TA, V, kFwdPre>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kLxMaxBytes);
+  (void)hipFuncSetAttribute((const void*)k_fwd_csr_lx<TA, V, kFwdMatvec>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLxMaxBytes);
+}
+
+// Once per process: kernel attributes (the LDS-resident kernel's dynamic LDS).
+void gk_prepare() {
+  static const bool done = []() {
+    lx_attr<double, double>();
+    lx_attr<float, double>();
+    lx_attr<double, float>();
+    lx_attr<float, float>();
+    return true;
+  }();
+  (void)done;
+}
+
+// Row blocks of the LDS-resident forward kernel: one per CU, balanced by non-zeros.
+int lx_stream_t(long long nnz) {
+  static const int cus = []() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    return v;
+  }();
+  return (int)std::max<long long>(1, (nnz + cus - 1) / cus);
 }
 
 template <class V, int MODE>
@@ -934,6 +1116,21 @@ static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, GKState* st
   const int ac = (int)wk.alpha_count;
   const GKState* sin = st + (MODE == kFwdPlain ? 1 : 0);
   GKState* sout = (MODE == kFwdPlain) ? st : nullptr;
+  if (A.csr && A.lx_rb && A.nnz >= kLxMinNnz && A.n * (long long)sizeof(V) <= kLxMaxBytes) {
+    const RowBlk* lrb = (const RowBlk*)A.lx_rb;
+    const unsigned lg = (unsigned)A.lx_grid;
+    const unsigned shm = (unsigned)(A.n * sizeof(V));
+    if (A.f64)
+      launch_kx(k_fwd_csr_lx<double, V, MODE>, dim3(lg), dim3(kLxT), shm, s, e0, e1, lrb, A.row_ptr, A.col_idx,
+                (const double*)A.val, A.n, tin, vec.u_top, vec.u_bot, (const V*)vec.v, vec.w, vec.y, sin, sout,
+                (const double*)wk.alpha_part, ac, wk.beta_part);
+    else
+      launch_kx(k_fwd_csr_lx<float, V, MODE>, dim3(lg), dim3(kLxT), shm, s, e0, e1, lrb, A.row_ptr, A.col_idx,
+                (const float*)A.val, A.n, tin, vec.u_top, vec.u_bot, (const V*)vec.v, vec.w, vec.y, sin, sout,
+                (const double*)wk.alpha_part, ac, wk.beta_part);
+    wk.beta_count = lg;
+    return;
+  }
   if (A.csr) {
     const RowBlk* rbk = (const RowBlk*)A.rb;
     if (A.f64)
@@ -1018,6 +1215,11 @@ static void launch_pcoef(const OpDesc& A, const PrecDesc& P, long long n, const 
     hipLaunchKernelGGL((k_pr_rz<float, V>), dim3(g1), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
                        (const float*)A.val, P.I, P.ell, z, P.c1, sl);
   const unsigned g2 = ceil_div(P.ell, kBlock / kWave);
+  if (P.M2) {
+    hipLaunchKernelGGL(k_pr_gemv, dim3(g2), dim3(kBlock), 0, s, P.M2, P.ell, (const double*)P.c1,
+                       (const double*)nullptr, P.c, sl);
+    return;
+  }
   hipLaunchKernelGGL(k_pr_gemv, dim3(g2), dim3(kBlock), 0, s, P.Kt, P.ell, (const double*)P.c1, P.d, P.c2, sl);
   hipLaunchKernelGGL(k_pr_gemv, dim3(g2), dim3(kBlock), 0, s, P.Kr, P.ell, (const double*)P.c2,
                      (const double*)nullptr, P.c, sl);

@@ -40,6 +40,8 @@ struct OpDesc {
   long long m, n, ld, nnz;
   const int *rb, *t_rb;          // row blocks of the CSR-stream products (A, A^T)
   int stream_t;                  // non-zeros per row block
+  const int* lx_rb;              // row blocks of the LDS-resident A x kernel (null: not used)
+  int lx_grid;                   // its workgroups
   const int *row_ptr, *col_idx;  // CSR of A
   const void* val;
   const int *t_ptr, *t_idx;      // CSR of A^T
@@ -53,8 +55,9 @@ struct OpDesc {
 // Preconditioner P^{-1} z = z + V (d .* (V^T z)), V = Q_R V_M (n x ell).
 // Explicit form (dense A): V row-major n x ell.  Implicit form (CSR A): with
 // R = A(I,:) and Q_R = R^T T_R^{-1}, V = R^T K, K = T_R^{-1} V_M; the
-// coefficients are c1 = R z, c2 = d .* (K^T c1), c = K c2 and the row pass
-// adds R^T c (CSR of R^T).
+// coefficients are c1 = R z, c2 = d .* (K^T c1), c = K c2 (or c = M2 c1 with
+// M2 = K diag(d) K^T, one product instead of two, when R is well conditioned)
+// and the row pass adds R^T c (CSR of R^T).
 struct PrecDesc {
   int implicit;
   int ell;
@@ -68,6 +71,7 @@ struct PrecDesc {
   // implicit
   const int* I;                    // rows of A forming R
   const double *Kt, *Kr;           // K^T and K, row-major ell x ell
+  const double* M2;                // K diag(d) K^T (ell x ell) when used instead of Kt / Kr, else null
   const int *rt_ptr, *rt_idx;      // CSR of R^T (n rows)
   const double* rt_val;
   double *c1, *c2;                 // ell
@@ -119,6 +123,8 @@ void fill_zero(V* p, long long n, hipStream_t s);
 // the ints of a row-block array ({first row, its first non-zero} per
 // workgroup, plus the end).
 int stream_t(long long nnz);
+int lx_stream_t(long long nnz);  // non-zeros per row block of the LDS-resident A x kernel
+void gk_prepare();               // once per process: kernel attributes
 int stream_blocks(long long nnz, int T);
 long long row_block_words(long long nnz, int T);
 void build_row_blocks(const int* rp, long long m, long long nnz, int T, int* rb, hipStream_t s);
