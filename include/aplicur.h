@@ -87,7 +87,9 @@ typedef struct aplicur_opts {
   int32_t max_rank;  /* cap on the CUR rank l (<= 0: min(m, n, 4096)); reaching it ends the
                         rank growth like rho <= eps_cur                                      */
   int32_t precond;   /* 1: APLICUR (default); 0: plain LSQR on A_mu (no sketch, no CUR)   */
-  int32_t precision; /* 0: FP64 vectors and products (default)                             */
+  int32_t precision; /* 0: FP64 vectors and products (default); 1: FP32 LSQR phases (FP32
+                        values and vectors, FP64 scalars and reductions) with FP64
+                        refinement (an extension, not in the paper)                        */
   int32_t max_outer; /* stop after this many outer steps (<= 0: no limit; for tests)       */
   int32_t workers;   /* aplicur_solve_batched: problems in flight at once, each on a stream
                         of its own (<= 0: 4)                                                  */
@@ -138,11 +140,16 @@ int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* stream,
 int aplicur_solve(aplicur_ctx* ctx, const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,
                   int32_t x_is_warm, aplicur_info* info, void* stream);
 
-/* Independent problems A[p] x = B[p] (p < batch) with the same options:
- * A, B, ldb, X, ldx and info are (host) arrays of length batch; B[p] / X[p]
- * are device pointers (FP64, column-major, nrhs columns each).  Problems
- * run one after another on `stream` through the same kernels as
- * aplicur_solve.  Returns the first error, else the largest warning.       */
+/* Independent problems A[p] x = B[p] (p < batch) with the same options
+ * (batching is an extension, not in the paper): A, B, ldb, X, ldx and info
+ * are (host) arrays of length batch; B[p] / X[p] are device pointers (FP64,
+ * column-major, nrhs columns each).  opts.workers host threads each own a
+ * HIP stream (default priority) that first waits for `stream`, and take
+ * whole problems, largest first; each problem runs Alg. 3 through the same
+ * kernels as aplicur_solve (opts.graphs: its LSQR iterations replay as HIP
+ * graphs; opts.tune: product tiles autotuned per shape).  All work is done
+ * when the call returns.  Every problem is validated before any work starts.
+ * Returns the first error (naming the problem), else the largest warning.  */
 int aplicur_solve_batched(int32_t batch, const aplicur_mat* A, const double* const* B, const int64_t* ldb,
                           int32_t nrhs, double* const* X, const int64_t* ldx, const aplicur_opts* opts,
                           aplicur_info* info, void* stream);
@@ -170,8 +177,9 @@ int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, 
 
 /* Measures the product kernels the LSQR iteration uses: `reps` rounds of
  * y = A x - y followed by s = A^T y (s: library scratch), alternating as in
- * the iteration, with a HIP event pair recorded on `stream` around every
- * launch of the A product (trans = 0) or of the A^T product (trans = 1).
+ * the iteration, with a HIP event pair attached to every dispatch of the A
+ * product (trans = 0) or of the A^T product (trans = 1) on `stream`
+ * (hipExtLaunchKernelGGL start/stop events).
  * x: n doubles, y: m doubles (scratch; final contents unspecified).
  * *us_per_launch (host) receives the mean duration in microseconds.        */
 int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* stream,
