@@ -258,7 +258,7 @@ def main():
                    "max_rank": args.max_rank},
         "roofline": {"bound": "hbm", "achieved": round(gbs_a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs_a / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_fwd_csr_lx (A x - y with x resident in LDS, FP64)",
+                     "kernel": "k_fwd_sell_lx (A x - y, SELL-64 copy of A, x resident in LDS, FP64)",
                      "bytes_per_launch": int(bytes_a), "us_per_launch": round(us_a, 3)},
         "cpu_baseline": cpu,
         "aplicur": {"rank": info.rank, "phases": info.phases, "iters": info.iters, "outer": info.outer,

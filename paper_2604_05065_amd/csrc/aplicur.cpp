@@ -387,6 +387,37 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
         op.lx_rb = rbL;
         op.lx_grid = stream_blocks(Am->nnz, tl);
       }
+      // SELL-64 copy for it when padding the 64-row slices adds at most a quarter
+      if (Am->nnz >= kLxMinNnz && n * 4 <= kLxMaxBytes) {
+        const long long ns = (m + 63) / 64;
+        int* wid = c->arena.alloc<int>(ns);
+        std::vector<int> wh;
+        const long long padded = sell_widths(Am->row_ptr, m, wid, wh, s);
+        if (padded <= Am->nnz + Am->nnz / 4 && padded < (1LL << 31)) {
+          std::vector<int> offh(ns);
+          long long acc = 0;
+          for (long long i = 0; i < ns; ++i) {
+            offh[i] = (int)acc;
+            acc += (long long)wh[i] * 64;
+          }
+          int* off = c->arena.alloc<int>(ns);
+          APL_HIP(hipMemcpyAsync(off, offh.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+          int* sci = c->arena.alloc<int>(std::max<long long>(1, padded));
+          void* sval = c->arena.alloc<char>(vs * (size_t)std::max<long long>(1, padded));
+          if (op.f64)
+            sell_fill<double>(Am->row_ptr, Am->col_idx, (const double*)Am->val, m, off, wid, sci, (double*)sval, s);
+          else
+            sell_fill<float>(Am->row_ptr, Am->col_idx, (const float*)Am->val, m, off, wid, sci, (float*)sval, s);
+          APL_HIP(hipStreamSynchronize(s));  // offh is pageable host memory
+          op.sell_off = off;
+          op.sell_w = wid;
+          op.sell_ci = sci;
+          op.sell_val = sval;
+          op.sell_slices = (int)ns;
+          op.sell_padded = padded;
+          sell_layout(ns, n, &op.sell_spw, &op.sell_grid);
+        }
+      }
       op.rb = rbA;
       op.t_rb = rbT;
       op.group = group_for((double)Am->nnz / (double)m);
@@ -408,6 +439,11 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
           to_f32((const double*)op.t_val, 0, t32, 0, 1, Am->nnz, s);
           c->op32.val = v32;
           c->op32.t_val = t32;
+          if (op.sell_val) {
+            float* s32 = c->arena.alloc<float>(std::max<long long>(1, op.sell_padded));
+            to_f32((const double*)op.sell_val, 0, s32, 0, 1, op.sell_padded, s);
+            c->op32.sell_val = s32;
+          }
         } else {
           float* a32 = c->arena.alloc<float>((size_t)m * n);
           to_f32((const double*)op.val, op.ld, a32, n, m, n, s);

@@ -24,6 +24,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "kernels.h"
 
@@ -560,6 +561,137 @@ __global__ void __launch_bounds__(kLxT)
   if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
 }
 
+// A x in sliced ELL (SELL-64) with x resident in LDS.  Slice s holds rows
+// [64 s, 64 s + 64) padded to the slice's longest row (width w_s), column-major
+// inside the slice: entry q of row 64 s + l at off_s + 64 q + l (padding: column
+// 0, value 0).  One wave per slice, one lane per row: the value and column
+// loads are fully coalesced and need only (off_s, w_s), so a workgroup's loads
+// form two dependent stages (slice bounds, then values / columns) next to the
+// copy of x into LDS.  Sums run in entry order (the CSR row order).
+template <class TA, class V, int MODE>
+__global__ void __launch_bounds__(kLxT)
+    k_fwd_sell_lx(const int* __restrict__ soff, const int* __restrict__ swid, int nslices, int spw,
+                  const int* __restrict__ sci, const TA* __restrict__ sval, long long m, long long n, const V* tin,
+                  V* u_top, V* u_bot, const V* v, V* w, V* y, const GKState* __restrict__ st_in,
+                  GKState* __restrict__ st_out, const double* alpha_part, int alpha_count, double* beta_part) {
+  extern __shared__ double lx_raw[];
+  V* xs = (V*)lx_raw;
+  __shared__ double red[kLxT / kWave];
+  GKState s = *st_in;
+  const double delta = st_in->delta;
+  ShareT<kLxT, 2> share;
+  share.load(MODE == kFwdPlain ? alpha_part : nullptr, alpha_count);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  const int sl0 = blockIdx.x * spw;
+  const int sl1 = min(nslices, sl0 + spw);
+  // first slice of this wave: bounds and the row's epilogue operand
+  const int sa = sl0 + wave;
+  const bool has_a = sa < sl1;
+  int off = 0, wid = 0;
+  if (has_a) {
+    off = soff[sa];
+    wid = swid[sa];
+  }
+  const long long ra = (long long)sa * kWave + lane;
+  V uo = 0;
+  if (has_a && ra < m) uo = u_top[ra];
+  if (MODE != kFwdMatvec && s.stop) {
+    if (MODE == kFwdPlain) store_state(st_out, s);
+    return;
+  }
+  // x -> LDS, 12 loads per thread in flight
+  for (long long base = threadIdx.x; base < n; base += (long long)kLxT * 12) {
+    V tmp[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) tmp[q] = tin[min(base + (long long)q * kLxT, n - 1)];
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+      if (base + (long long)q * kLxT < n) xs[base + (long long)q * kLxT] = tmp[q];
+  }
+  // bottom slice [j0, j1) of the n rows
+  const long long per = (n + gridDim.x - 1) / gridDim.x;
+  const long long j0 = (long long)blockIdx.x * per, j1 = min(n, j0 + per);
+  const long long jb = j0 + threadIdx.x;
+  V bt = 0, bub = 0, bv = 0, bw = 0, by = 0;
+  if (MODE != kFwdMatvec && jb < j1) {
+    bt = tin[jb];
+    bub = u_bot[jb];
+    if (MODE == kFwdPlain) {
+      bv = v[jb];
+      bw = w[jb];
+      by = y[jb];
+    }
+  }
+  // values and columns of the first slice
+  int cidx[kLxChunk];
+  TA vv[kLxChunk];
+#pragma unroll
+  for (int q = 0; q < kLxChunk; ++q) {
+    const bool in = q < wid;
+    const long long e = (long long)off + (long long)(in ? q : 0) * kWave + lane;
+    cidx[q] = in ? sci[e] : 0;
+    vv[q] = in ? sval[e] : (TA)0;
+  }
+  publish(share, red);
+  __syncthreads();
+  V ts, cu, cy = 0, cw = 0;
+  bool pend = false;
+  if (MODE == kFwdPlain) {
+    scalar_step(s, sqrt(settled<kLxT>(red)));
+    store_state(st_out, s);
+    if (s.stop) {
+      if (jb < j1 && s.pending) y[jb] = by + (V)s.coef_y * bw;
+      return;
+    }
+  }
+  ts = (V)(1.0 / s.alpha);
+  cu = (V)(s.alpha / s.beta);
+  pend = (MODE == kFwdPlain) && s.pending;
+  cy = (V)s.coef_y;
+  cw = (V)s.coef_w;
+  double sq = 0.0;
+  for (int sl = sa; sl < sl1; sl += kLxT / kWave) {
+    const long long r = (long long)sl * kWave + lane;
+    if (sl != sa) {
+      off = soff[sl];
+      wid = swid[sl];
+      uo = r < m ? u_top[r] : (V)0;
+#pragma unroll
+      for (int q = 0; q < kLxChunk; ++q) {
+        const bool in = q < wid;
+        const long long e = (long long)off + (long long)(in ? q : 0) * kWave + lane;
+        cidx[q] = in ? sci[e] : 0;
+        vv[q] = in ? sval[e] : (TA)0;
+      }
+    }
+    V acc = 0;
+#pragma unroll
+    for (int q = 0; q < kLxChunk; ++q) acc += (V)vv[q] * xs[cidx[q]];
+    for (int q = kLxChunk; q < wid; ++q) {
+      const long long e = (long long)off + (long long)q * kWave + lane;
+      acc += (V)sval[e] * xs[sci[e]];
+    }
+    if (r < m) {
+      const V un = acc * ts - cu * uo;
+      u_top[r] = un;
+      sq += (double)un * (double)un;
+    }
+  }
+  if (MODE != kFwdMatvec && jb < j1) {
+    if (delta > 0.0) {
+      const V ub = (V)delta * (bt * ts) - cu * bub;
+      u_bot[jb] = ub;
+      sq += (double)ub * (double)ub;
+    }
+    if (pend) {
+      y[jb] = by + cy * bw;
+      w[jb] = bv * ts - cw * bw;
+    }
+  }
+  const double bs = block_sum_t<kLxT>(sq);
+  if (threadIdx.x == 0) beta_part[blockIdx.x] = bs;
+}
+
 // Dense row-major A: one wave per row (grid-stride).
 template <class TA, class V, int MODE>
 __global__ void __launch_bounds__(kBlock)
@@ -1071,8 +1203,6 @@ static void launch_k(F kern, dim3 g, hipStream_t s, hipEvent_t e0, hipEvent_t e1
 // LDS available to the x copy of the LDS-resident forward kernel, and the
 // size from which it beats the CSR-stream kernel (below it, loading x into
 // every workgroup's LDS costs more than the gathers it saves).
-constexpr long long kLxMaxBytes = 160 * 1024 - 1024;
-constexpr long long kLxMinNnz = 1500000;
 
 template <class TA, class V>
 static void lx_attr() {
@@ -1082,7 +1212,63 @@ static void lx_attr() {
                             (int)kLxMaxBytes);
   (void)hipFuncSetAttribute((const void*)k_fwd_csr_lx<TA, V, kFwdMatvec>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLxMaxBytes);
+  (void)hipFuncSetAttribute((const void*)k_fwd_sell_lx<TA, V, kFwdPlain>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kLxMaxBytes);
+  (void)hipFuncSetAttribute((const void*)k_fwd_sell_lx<TA, V, kFwdPre>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kLxMaxBytes);
+  (void)hipFuncSetAttribute((const void*)k_fwd_sell_lx<TA, V, kFwdMatvec>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLxMaxBytes);
 }
+
+// ---------------------------------------------------------------- SELL-64 copy of a CSR matrix
+__global__ void k_sell_widths(const int* rp, long long m, int* wid) {
+  const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+  int len = r < m ? rp[r + 1] - rp[r] : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, kWave));
+  if (threadIdx.x % kWave == 0 && r - threadIdx.x % kWave < m) wid[r / kWave] = len;
+}
+
+template <class TA>
+__global__ void k_sell_fill(const int* rp, const int* ci, const TA* val, long long m, const int* off, const int* wid,
+                            int* sci, TA* sval) {
+  const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long sl = r / kWave;
+  const int lane = (int)(r % kWave);
+  if (sl >= (m + kWave - 1) / kWave) return;
+  const int b = r < m ? rp[r] : 0, len = r < m ? rp[r + 1] - b : 0;
+  const long long base = off[sl];
+  for (int q = 0; q < wid[sl]; ++q) {
+    const long long e = base + (long long)q * kWave + lane;
+    sci[e] = q < len ? ci[b + q] : 0;
+    sval[e] = q < len ? val[b + q] : (TA)0;
+  }
+}
+
+// Widths of the SELL-64 slices of (rp, m) into wid (host vector); returns the
+// padded entry count.
+long long sell_widths(const int* rp, long long m, int* wid_dev, std::vector<int>& wid_host, hipStream_t s) {
+  const long long ns = (m + kWave - 1) / kWave;
+  hipLaunchKernelGGL(k_sell_widths, dim3(ceil_div(ns * kWave, kBlock)), dim3(kBlock), 0, s, rp, m, wid_dev);
+  wid_host.resize(ns);
+  APL_HIP(hipMemcpyAsync(wid_host.data(), wid_dev, sizeof(int) * ns, hipMemcpyDeviceToHost, s));
+  APL_HIP(hipStreamSynchronize(s));
+  long long total = 0;
+  for (int w : wid_host) total += (long long)w * kWave;
+  return total;
+}
+
+template <class TA>
+void sell_fill(const int* rp, const int* ci, const TA* val, long long m, const int* off_dev, const int* wid_dev,
+               int* sci, TA* sval, hipStream_t s) {
+  const long long ns = (m + kWave - 1) / kWave;
+  hipLaunchKernelGGL(k_sell_fill<TA>, dim3(ceil_div(ns * kWave, kBlock)), dim3(kBlock), 0, s, rp, ci, val, m, off_dev,
+                     wid_dev, sci, sval);
+}
+template void sell_fill<double>(const int*, const int*, const double*, long long, const int*, const int*, int*,
+                                double*, hipStream_t);
+template void sell_fill<float>(const int*, const int*, const float*, long long, const int*, const int*, int*, float*,
+                               hipStream_t);
 
 // Once per process: kernel attributes (the LDS-resident kernel's dynamic LDS).
 void gk_prepare() {
@@ -1096,8 +1282,7 @@ void gk_prepare() {
   (void)done;
 }
 
-// Row blocks of the LDS-resident forward kernel: one per CU, balanced by non-zeros.
-int lx_stream_t(long long nnz) {
+static int device_cus() {
   static const int cus = []() {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1105,7 +1290,18 @@ int lx_stream_t(long long nnz) {
       v = 256;
     return v;
   }();
-  return (int)std::max<long long>(1, (nnz + cus - 1) / cus);
+  return cus;
+}
+
+// Row blocks of the LDS-resident forward kernel: one per CU, balanced by non-zeros.
+int lx_stream_t(long long nnz) { return (int)std::max<long long>(1, (nnz + device_cus() - 1) / device_cus()); }
+
+// SELL-64 launch: about one workgroup per CU, and enough workgroups that each
+// owns at most kLxT of the n bottom rows.
+void sell_layout(long long nslices, long long n, int* spw, int* grid) {
+  const long long per = std::max<long long>(1, (nslices + device_cus() - 1) / device_cus());
+  *spw = (int)per;
+  *grid = (int)std::max<long long>(std::max<long long>(1, (nslices + per - 1) / per), (n + kLxT - 1) / kLxT);
 }
 
 template <class V, int MODE>
@@ -1116,6 +1312,20 @@ static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, GKState* st
   const int ac = (int)wk.alpha_count;
   const GKState* sin = st + (MODE == kFwdPlain ? 1 : 0);
   GKState* sout = (MODE == kFwdPlain) ? st : nullptr;
+  if (A.csr && A.sell_off && A.nnz >= kLxMinNnz && A.n * (long long)sizeof(V) <= kLxMaxBytes) {
+    const unsigned lg = (unsigned)A.sell_grid;
+    const unsigned shm = (unsigned)(A.n * sizeof(V));
+    if (A.f64)
+      launch_kx(k_fwd_sell_lx<double, V, MODE>, dim3(lg), dim3(kLxT), shm, s, e0, e1, A.sell_off, A.sell_w,
+                A.sell_slices, A.sell_spw, A.sell_ci, (const double*)A.sell_val, A.m, A.n, tin, vec.u_top, vec.u_bot,
+                (const V*)vec.v, vec.w, vec.y, sin, sout, (const double*)wk.alpha_part, ac, wk.beta_part);
+    else
+      launch_kx(k_fwd_sell_lx<float, V, MODE>, dim3(lg), dim3(kLxT), shm, s, e0, e1, A.sell_off, A.sell_w,
+                A.sell_slices, A.sell_spw, A.sell_ci, (const float*)A.sell_val, A.m, A.n, tin, vec.u_top, vec.u_bot,
+                (const V*)vec.v, vec.w, vec.y, sin, sout, (const double*)wk.alpha_part, ac, wk.beta_part);
+    wk.beta_count = lg;
+    return;
+  }
   if (A.csr && A.lx_rb && A.nnz >= kLxMinNnz && A.n * (long long)sizeof(V) <= kLxMaxBytes) {
     const RowBlk* lrb = (const RowBlk*)A.lx_rb;
     const unsigned lg = (unsigned)A.lx_grid;

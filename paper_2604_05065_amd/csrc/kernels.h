@@ -1,6 +1,8 @@
 // Launch functions of the APLICUR HIP kernels (host side declarations).
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace aplicur {
@@ -42,6 +44,11 @@ struct OpDesc {
   int stream_t;                  // non-zeros per row block
   const int* lx_rb;              // row blocks of the LDS-resident A x kernel (null: not used)
   int lx_grid;                   // its workgroups
+  // SELL-64 copy of A for the LDS-resident A x kernel (null: not built)
+  const int *sell_off, *sell_w, *sell_ci;
+  const void* sell_val;
+  int sell_slices, sell_spw, sell_grid;  // slices, slices per workgroup, workgroups
+  long long sell_padded;                 // entries including padding
   const int *row_ptr, *col_idx;  // CSR of A
   const void* val;
   const int *t_ptr, *t_idx;      // CSR of A^T
@@ -124,7 +131,18 @@ void fill_zero(V* p, long long n, hipStream_t s);
 // workgroup, plus the end).
 int stream_t(long long nnz);
 int lx_stream_t(long long nnz);  // non-zeros per row block of the LDS-resident A x kernel
+// LDS-resident A x: used for CSR with at least kLxMinNnz non-zeros when n
+// vector entries fit kLxMaxBytes of dynamic LDS.
+constexpr long long kLxMaxBytes = 160 * 1024 - 1024;
+constexpr long long kLxMinNnz = 1500000;
+// SELL-64 launch shape: slices per workgroup and workgroups.
+void sell_layout(long long nslices, long long n, int* spw, int* grid);
 void gk_prepare();               // once per process: kernel attributes
+// SELL-64 copy: slice widths (returns padded entries), then the fill.
+long long sell_widths(const int* rp, long long m, int* wid_dev, std::vector<int>& wid_host, hipStream_t s);
+template <class TA>
+void sell_fill(const int* rp, const int* ci, const TA* val, long long m, const int* off_dev, const int* wid_dev,
+               int* sci, TA* sval, hipStream_t s);
 int stream_blocks(long long nnz, int T);
 long long row_block_words(long long nnz, int T);
 void build_row_blocks(const int* rp, long long m, long long nnz, int T, int* rb, hipStream_t s);

@@ -270,6 +270,51 @@ def test_full_size_products(lib, workload2):
     assert np.abs(z - zr).max() <= 1e-13 * (abs(A).max() * np.abs(u).max() * abs(A).getnnz(axis=0).max())
 
 
+def _lds_case(shape):
+    r = np.random.default_rng(33)
+    m, n = 150037, 16000  # m not a multiple of the 64-row slices
+    lens = r.integers(8, 14, m)
+    if shape == "skewed_rows":
+        lens[r.choice(m, 200, replace=False)] = 3000  # padding the slices would cost far more than a quarter
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    ci = r.integers(0, n, int(rp[-1]))
+    val = r.standard_normal(int(rp[-1])) * np.exp(r.uniform(-3, 3, int(rp[-1])))
+    return sp.csr_matrix((val, ci, rp), shape=(m, n))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", ["uniform_rows", "skewed_rows"])
+def test_lds_resident_products(lib, shape, dtype):
+    """A x with x held in LDS (at least 1.5e6 non-zeros, n small enough):
+    through the SELL-64 copy when rows are near-uniform, through the CSR row
+    blocks when a few long rows would make the padding too large."""
+    A = _lds_case(shape)
+    if dtype == torch.float32:
+        A = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
+    m, n = A.shape
+    r = np.random.default_rng(22)
+    x, u = r.standard_normal(n), r.standard_normal(m)
+    with lib.Context(_gpu_csr(A, dtype), mu=1e-4, precond=False) as ctx:
+        y = ctx.matvec(_t(x)).cpu().numpy()
+        z = ctx.matvec(_t(u), trans=True).cpu().numpy()
+    yr, zr = A @ x, A.T @ u
+    absA = abs(A)
+    assert np.abs(y - yr).max() <= 1e-13 * (absA @ np.abs(x)).max()
+    assert np.abs(z - zr).max() <= 1e-13 * (absA.T @ np.abs(u)).max()
+
+
+def test_full_size_fp32_phases(lib, workload2):
+    """FP32 LSQR phases (FP32 values, A x from the FP32 SELL copy) with FP64
+    refinement reach the FP64 tolerance at the benchmark size."""
+    w = workload2
+    x, info = lib.lstsq(_gpu_csr(w.A), _t(w.B), mu=w.mu, block=w.block, tol_ne=w.tol, precond=True,
+                        max_rank=256, precision=1)
+    eta = ne_residual(w.A, w.B, x.cpu().numpy(), w.mu)
+    assert info.status == 0
+    assert eta <= 1.05 * w.tol
+    assert abs(eta - info.eta) <= 1e-3 * w.tol
+
+
 @pytest.mark.parametrize("precond", [False, True])
 def test_full_size_solve_reaches_tolerance(lib, workload2, precond):
     """At the benchmark size the solution is checked through the normal-equation
