@@ -98,7 +98,10 @@ typedef struct aplicur_opts {
                         heuristic tiles.  Tiles change the summation order, not the method */
   int32_t graphs;    /* 1: replay the LSQR iterations as captured HIP graphs (same kernels,
                         same arithmetic); 0: launch each kernel                             */
-  int32_t reserved[4];
+  int32_t columns;   /* 1: one right-hand side at a time even where the blocked path applies
+                        (several right-hand sides of a dense A, precision 0); 0: blocked
+                        there (default).  Same method and stopping tests per column        */
+  int32_t reserved[3];
 } aplicur_opts;
 
 /* ------------------------------------------------------------------ info  */
@@ -132,7 +135,11 @@ int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* stream,
 /* The adaptive solve of Alg. 3 for nrhs right-hand sides B (m x nrhs,
  * column-major, ldb >= m) into X (n x nrhs, ldx >= n).  All columns share
  * the CUR sequence and every preconditioner (none depends on b); each
- * column runs its own LSQR phases with its own dynamic stopping.  With
+ * column runs its own LSQR recurrences with its own dynamic stopping.  For
+ * a dense A with nrhs >= 2 and precision 0 the columns run together, up to
+ * 64 at a time, sharing each product (one pass over A per iteration for
+ * the group; A^T products read a transposed copy of A made on first use,
+ * held until the context is destroyed); otherwise one column at a time.  With
  * x_is_warm != 0 the first phase starts from the given X (warm start,
  * Sec. 3.2), otherwise from 0.  The context remembers the final CUR state
  * and preconditioner for aplicur_solve_backward.  info (host) may be NULL.
@@ -174,6 +181,16 @@ int aplicur_solve_backward(aplicur_ctx* ctx, const double* X, int64_t ldx, const
 /* y = A x (trans = 0; x: n, y: m) or y = A^T x (trans = 1; x: m, y: n) in
  * FP64 with the same product kernels the LSQR iteration uses.             */
 int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, void* stream);
+
+/* Y[:, j] = A X[:, j] (trans = 0) or A^T X[:, j] (trans = 1) for j < k: X and
+ * Y device, FP64, column-major with leading dimensions ldx >= (trans ? m : n)
+ * and ldy >= (trans ? n : m).  Dense A: one pass over A (or over its
+ * transposed copy, made on first use) for up to 64 columns at a time, the
+ * product on MFMA with FP64 accumulation of the FP32/FP64 values (the
+ * products of the blocked multi-right-hand-side LSQR, Sec. 2.2); CSR A: one
+ * product per column.  Enqueued on `stream`.                                */
+int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx, int32_t k, double* Y, int64_t ldy,
+                   void* stream);
 
 /* Measures the product kernels the LSQR iteration uses: `reps` rounds of
  * y = A x - y followed by s = A^T y (s: library scratch), alternating as in

@@ -26,7 +26,7 @@ class Opts(C.Structure):
                 ("eps_lsqr", C.c_double), ("tol_ne", C.c_double), ("max_iter", C.c_int32),
                 ("max_rank", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
                 ("max_outer", C.c_int32), ("workers", C.c_int32), ("tune", C.c_int32),
-                ("graphs", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("graphs", C.c_int32), ("columns", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Info(C.Structure):
@@ -40,7 +40,7 @@ class Info(C.Structure):
 
 
 EXPORTS = ["aplicur_opts_default", "aplicur_sketch", "aplicur_solve", "aplicur_solve_batched",
-           "aplicur_solve_backward", "aplicur_matvec", "aplicur_time_product", "aplicur_ctx_query", "aplicur_ctx_destroy",
+           "aplicur_solve_backward", "aplicur_matvec", "aplicur_matmat", "aplicur_time_product", "aplicur_ctx_query", "aplicur_ctx_destroy",
            "aplicur_last_error", "aplicur_version"]
 
 _lib = None
@@ -69,6 +69,8 @@ def load():
     lib.aplicur_solve_backward.restype = C.c_int
     lib.aplicur_matvec.argtypes = [vp, i32, dp, dp, vp]
     lib.aplicur_matvec.restype = C.c_int
+    lib.aplicur_matmat.argtypes = [vp, i32, dp, i64, i32, dp, i64, vp]
+    lib.aplicur_matmat.restype = C.c_int
     lib.aplicur_time_product.argtypes = [vp, i32, dp, dp, i32, vp, C.POINTER(C.c_double)]
     lib.aplicur_time_product.restype = C.c_int
     lib.aplicur_ctx_query.argtypes = [vp, i32, vp, C.c_size_t]

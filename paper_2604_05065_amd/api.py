@@ -67,7 +67,7 @@ def _stream():
 
 def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.0, eps_lsqr=1e-10,
               tol_ne=1e-8, max_iter=100000, max_rank=0, precond=True, precision=0, max_outer=0,
-              r_probes=10, workers=0, tune=0, graphs=0):
+              r_probes=10, workers=0, tune=0, graphs=0, columns=0):
     lib = L.load()
     o = L.Opts()
     lib.aplicur_opts_default(C.byref(o))
@@ -76,6 +76,7 @@ def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.
     o.max_iter, o.max_rank, o.precond = int(max_iter), int(max_rank), int(bool(precond))
     o.precision, o.max_outer, o.r_probes = int(precision), int(max_outer), int(r_probes)
     o.workers, o.tune, o.graphs = int(workers), int(bool(tune)), int(bool(graphs))
+    o.columns = int(bool(columns))
     return o
 
 
@@ -149,6 +150,16 @@ class Context:
         y = torch.empty(rows_out, dtype=torch.float64, device=x.device)
         L.check(self.lib.aplicur_matvec(self.ptr, int(bool(trans)), x.data_ptr(), y.data_ptr(), _stream()))
         return y
+
+    def matmat(self, X, trans=False):
+        """A X (or A^T X) for the columns of X (rows x k, or a vector)."""
+        rows_in, rows_out = (self.m, self.n) if trans else (self.n, self.m)
+        Xt, k, one = _cols(X, rows_in, "X")
+        Yt = torch.empty((k, rows_out), dtype=torch.float64, device=Xt.device)
+        L.check(self.lib.aplicur_matmat(self.ptr, int(bool(trans)), Xt.data_ptr(), rows_in, k, Yt.data_ptr(),
+                                        rows_out, _stream()))
+        Y = Yt.t()
+        return Y.reshape(-1) if one else Y
 
     def time_product(self, x, trans=False, reps=100):
         """Mean duration (us) of one launch of the A (or A^T) product kernel,

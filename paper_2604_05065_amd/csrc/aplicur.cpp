@@ -22,6 +22,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <shared_mutex>
@@ -30,6 +31,7 @@
 #include <vector>
 
 #include "../../include/aplicur.h"
+#include "blk.h"
 #include "factor.h"
 
 namespace aplicur {
@@ -78,6 +80,25 @@ struct Arena {
     for (void* p : ptrs) (void)hipFree(p);
     ptrs.clear();
   }
+};
+
+// Buffers of the blocked path (several right-hand sides of a dense A),
+// allocated on first use for kp columns.
+struct Blk {
+  int kp = 0;
+  void* At = nullptr;  // A^T, n x ldt row-major
+  long long ldt = 0;
+  double* Vt = nullptr;  // V^T of the explicit P, ell x ldvt row-major
+  long long ldvt = 0, vt_gen = -1;
+  double *Bp = nullptr, *Bbot = nullptr, *Xp = nullptr, *tm = nullptr, *tn = nullptr;
+  BlkVecs<double> vec{};
+  BlkWork wk{};
+  BlkOp op{};
+  GKState* st = nullptr;
+  GKState* st_up = nullptr;    // pinned, 2 kp (uploads)
+  GKState* st_down = nullptr;  // pinned, 2 kp (read-backs)
+  double* norm_host = nullptr; // pinned, kBlkMaxGrid x kp
+  int S1max = 1, S2max = 1;
 };
 
 struct Ctx {
@@ -136,6 +157,9 @@ struct Ctx {
   // captured LSQR iteration chunk (graphs option) and the key it was captured for
   hipGraphExec_t gexec = nullptr;
   long long gkey = -1;
+  // blocked path and the generation of the preconditioner it last saw
+  std::unique_ptr<Blk> blk;
+  long long prec_gen = 0;
 
   ~Ctx() {
     {
@@ -143,6 +167,11 @@ struct Ctx {
       if (gexec) (void)hipGraphExecDestroy(gexec);
       if (blas) rocblas_destroy_handle(blas);
       if (st_host) (void)hipHostFree(st_host);
+      if (blk) {
+        if (blk->st_up) (void)hipHostFree(blk->st_up);
+        if (blk->st_down) (void)hipHostFree(blk->st_down);
+        if (blk->norm_host) (void)hipHostFree(blk->norm_host);
+      }
     }
     arena.release();
   }
@@ -858,6 +887,7 @@ static void build_precond(Ctx& c, hipStream_t s) {
   c.p_pnorm = info[3];
   c.prec.ell = l;
   c.have_prec = true;
+  ++c.prec_gen;
 }
 
 // ------------------------------------------------------------------ LSQR phases
@@ -1062,14 +1092,94 @@ static void refine(Ctx& c, const PrecDesc* P, Rhs r, double* x, ColState& cs, do
   }
 }
 
+// Times and counters of one solve.
+struct SolveLog {
+  double t_cur = 0.0, t_prec = 0.0, t_lsqr = 0.0, last_rho = 0.0;
+  int rebuilds = 0, outer = 0;
+};
+
+// The outer loop of Alg. 3 (CUR increments, the re-preconditioning test and
+// P rebuilds).  After each rebuild, phases(final_step, nu, eps_lsqr) runs the
+// LSQR work of the columns still active and returns whether any remains.
+template <class Phases>
+static void outer_loop(Ctx& c, hipStream_t s, SolveLog& lg, Phases&& phases) {
+  // restart the CUR sequence (it depends on A only)
+  c.rank = 0;
+  c.I.clear();
+  c.J.clear();
+  c.rho_hist.clear();
+  c.rank_hist.clear();
+  c.rebuild_hist.clear();
+  c.have_prec = false;
+  APL_HIP(hipMemcpyAsync(c.E, c.Y, sizeof(double) * (size_t)c.s * c.n, hipMemcpyDeviceToDevice, s));
+  double d_cur = INFINITY;
+  for (;;) {
+    auto t0 = Clock::now();
+    StepResult sr = outer_step(c, s);
+    lg.t_cur += ms_since(t0);
+    ++lg.outer;
+    if (sr.added == 0 && c.rank == 0) break;
+    lg.last_rho = sr.rho;
+    const bool final_step = sr.rho <= c.eps_cur || sr.exhausted || c.rank >= c.L ||
+                            (c.o.max_outer > 0 && lg.outer >= c.o.max_outer);
+    const double gap = sr.rho - c.eps_cur;
+    const bool rebuild = final_step || (d_cur / gap >= c.o.nu_prec);
+    c.rho_hist.push_back(sr.rho);
+    c.rank_hist.push_back(c.rank);
+    c.rebuild_hist.push_back(rebuild ? 1 : 0);
+    bool any_active = true;
+    if (rebuild) {
+      t0 = Clock::now();
+      build_precond(c, s);
+      ++lg.rebuilds;
+      lg.t_prec += ms_since(t0);
+      t0 = Clock::now();
+      any_active = phases(final_step, final_step ? INFINITY : c.o.nu_lsqr, final_step ? 0.0 : c.o.eps_lsqr);
+      d_cur = gap;
+      lg.t_lsqr += ms_since(t0);
+    }
+    if (final_step || !any_active) break;
+  }
+}
+
+static void fill_info(Ctx& c, const std::vector<ColState>& cols, const SolveLog& lg, aplicur_info* info, int& status) {
+  status = APLICUR_OK;
+  double eta_max = 0.0;
+  int iters = 0, phases = 0;
+  for (auto& cs : cols) {
+    eta_max = std::max(eta_max, cs.eta);
+    iters = std::max(iters, cs.used);
+    phases = std::max(phases, cs.phases);
+    if (cs.eta > c.o.tol_ne) status = APLICUR_W_MAXITER;
+  }
+  if (info) {
+    info->status = status;
+    info->phases = phases;
+    info->iters = iters;
+    info->rank = c.rank;
+    info->rebuilds = lg.rebuilds;
+    info->outer = lg.outer;
+    info->eta = eta_max;
+    info->rho = lg.last_rho;
+    info->sigma_hat = c.p_target;
+    info->t_sketch_ms = c.t_sketch;
+    info->t_cur_ms = lg.t_cur;
+    info->t_precond_ms = lg.t_prec;
+    info->t_lsqr_ms = lg.t_lsqr;
+  }
+}
+
+static bool use_blocked(const Ctx& c, int nrhs);
+static int solve_blocked(Ctx& c, const double* B, long long ldb, int nrhs, double* X, long long ldx, bool warm,
+                         aplicur_info* info, hipStream_t s);
+
 static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, long long ldx, bool warm,
                  aplicur_info* info, hipStream_t s) {
   APL_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
   APL_REQUIRE(B && X, "null B or X");
   APL_REQUIRE(ldb >= c.m && ldx >= c.n, "ldb must be >= m and ldx >= n");
   set_stream(c, s);
-  auto t_start = Clock::now();
-  double t_cur = 0.0, t_prec = 0.0, t_lsqr = 0.0;
+  if (use_blocked(c, nrhs)) return solve_blocked(c, B, ldb, nrhs, X, ldx, warm, info, s);
   std::vector<ColState> cols(nrhs);
   for (int k = 0; k < nrhs; ++k) {
     const double* b = B + (size_t)k * ldb;
@@ -1090,8 +1200,9 @@ static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, lo
   }
   c.phase_iters0.clear();
   c.phase_eta0.clear();
-  int rebuilds = 0, outer = 0;
-  double last_rho = 0.0;
+  SolveLog lg;
+  bool any_active = false;
+  for (auto& cs : cols) any_active |= !cs.done;
   if (!c.o.precond) {
     auto t0 = Clock::now();
     for (int k = 0; k < nrhs; ++k) {
@@ -1100,99 +1211,387 @@ static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, lo
              k == 0 ? &c.phase_iters0 : nullptr, k == 0 ? &c.phase_eta0 : nullptr, s);
       cols[k].done = true;
     }
-    t_lsqr += ms_since(t0);
-  } else {
-    // restart the CUR sequence (it depends on A only)
-    c.rank = 0;
-    c.I.clear();
-    c.J.clear();
-    c.rho_hist.clear();
-    c.rank_hist.clear();
-    c.rebuild_hist.clear();
-    c.have_prec = false;
-    APL_HIP(hipMemcpyAsync(c.E, c.Y, sizeof(double) * (size_t)c.s * c.n, hipMemcpyDeviceToDevice, s));
-    double d_cur = INFINITY;
-    bool any_active = false;
-    for (auto& cs : cols) any_active |= !cs.done;
-    while (any_active) {
-      auto t0 = Clock::now();
-      StepResult sr = outer_step(c, s);
-      t_cur += ms_since(t0);
-      ++outer;
-      if (sr.added == 0 && c.rank == 0) break;
-      last_rho = sr.rho;
-      const bool final_step = sr.rho <= c.eps_cur || sr.exhausted || c.rank >= c.L ||
-                              (c.o.max_outer > 0 && outer >= c.o.max_outer);
-      const double gap = sr.rho - c.eps_cur;
-      const bool rebuild = final_step || (d_cur / gap >= c.o.nu_prec);
-      c.rho_hist.push_back(sr.rho);
-      c.rank_hist.push_back(c.rank);
-      c.rebuild_hist.push_back(rebuild ? 1 : 0);
-      if (rebuild) {
-        t0 = Clock::now();
-        build_precond(c, s);
-        ++rebuilds;
-        t_prec += ms_since(t0);
-        t0 = Clock::now();
-        const double nu = final_step ? INFINITY : c.o.nu_lsqr;
-        const double epsl = final_step ? 0.0 : c.o.eps_lsqr;
-        for (int k = 0; k < nrhs; ++k) {
-          ColState& cs = cols[k];
-          if (cs.done) continue;
-          const double* b = B + (size_t)k * ldb;
-          double* x = X + (size_t)k * ldx;
-          const bool xz = (!warm && cs.phases == 0);
-          PhaseOut po = run_phase(c, &c.prec, b, nullptr, 0.0, x, xz, c.o.tol_ne * cs.atb, c.p_pnorm, epsl,
-                                  c.o.eps_lsqr * cs.bnorm, nu, c.p_sigma_l, c.o.max_iter - cs.used, s);
-          cs.used += po.iters;
-          cs.phases += 1;
-          cs.eta = eta_of(c, b, nullptr, 0.0, x, cs.atb, s);
-          if (k == 0) {
-            c.phase_iters0.push_back(po.iters);
-            c.phase_eta0.push_back(cs.eta);
-          }
-          if (cs.eta <= c.o.tol_ne || cs.used >= c.o.max_iter) {
-            cs.done = true;
-          } else if (final_step) {
-            refine(c, &c.prec, Rhs{b, nullptr, 0.0}, x, cs, c.p_pnorm, c.p_sigma_l, false,
-                   k == 0 ? &c.phase_iters0 : nullptr, k == 0 ? &c.phase_eta0 : nullptr, s);
-            cs.done = true;
-          }
+    lg.t_lsqr += ms_since(t0);
+  } else if (any_active) {
+    outer_loop(c, s, lg, [&](bool final_step, double nu, double epsl) {
+      bool active = false;
+      for (int k = 0; k < nrhs; ++k) {
+        ColState& cs = cols[k];
+        if (cs.done) continue;
+        const double* b = B + (size_t)k * ldb;
+        double* x = X + (size_t)k * ldx;
+        const bool xz = (!warm && cs.phases == 0);
+        PhaseOut po = run_phase(c, &c.prec, b, nullptr, 0.0, x, xz, c.o.tol_ne * cs.atb, c.p_pnorm, epsl,
+                                c.o.eps_lsqr * cs.bnorm, nu, c.p_sigma_l, c.o.max_iter - cs.used, s);
+        cs.used += po.iters;
+        cs.phases += 1;
+        cs.eta = eta_of(c, b, nullptr, 0.0, x, cs.atb, s);
+        if (k == 0) {
+          c.phase_iters0.push_back(po.iters);
+          c.phase_eta0.push_back(cs.eta);
         }
-        d_cur = gap;
-        t_lsqr += ms_since(t0);
+        if (cs.eta <= c.o.tol_ne || cs.used >= c.o.max_iter) {
+          cs.done = true;
+        } else if (final_step) {
+          refine(c, &c.prec, Rhs{b, nullptr, 0.0}, x, cs, c.p_pnorm, c.p_sigma_l, false,
+                 k == 0 ? &c.phase_iters0 : nullptr, k == 0 ? &c.phase_eta0 : nullptr, s);
+          cs.done = true;
+        }
+        active |= !cs.done;
       }
-      if (final_step) break;
-      any_active = false;
-      for (auto& cs : cols) any_active |= !cs.done;
-    }
+      return active;
+    });
   }
   int status = APLICUR_OK;
-  double eta_max = 0.0;
-  int iters = 0, phases = 0;
-  for (auto& cs : cols) {
-    eta_max = std::max(eta_max, cs.eta);
-    iters = std::max(iters, cs.used);
-    phases = std::max(phases, cs.phases);
-    if (cs.eta > c.o.tol_ne) status = APLICUR_W_MAXITER;
-  }
-  if (info) {
-    info->status = status;
-    info->phases = phases;
-    info->iters = iters;
-    info->rank = c.rank;
-    info->rebuilds = rebuilds;
-    info->outer = outer;
-    info->eta = eta_max;
-    info->rho = last_rho;
-    info->sigma_hat = c.p_target;
-    info->t_sketch_ms = c.t_sketch;
-    info->t_cur_ms = t_cur;
-    info->t_precond_ms = t_prec;
-    info->t_lsqr_ms = t_lsqr;
-  }
-  (void)t_start;
+  fill_info(c, cols, lg, info, status);
   return status;
+}
+
+// ------------------------------------------------------------------ blocked path
+// Several right-hand sides of a dense A: groups of up to 64 columns run their
+// LSQR recurrences together, the products as MFMA matrix products (A read
+// once per iteration for the whole group instead of once per column).  Same
+// phases, stopping tests and refinement as the column path, per column.
+constexpr int kBlkMaxCols = 64;
+
+static bool use_blocked(const Ctx& c, int nrhs) {
+  return nrhs >= 2 && !c.op.csr && !c.fp32 && !c.o.columns;
+}
+
+static int blk_kp(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+
+static void ensure_blk(Ctx& c, int kp, hipStream_t s) {
+  if (!c.blk) c.blk = std::make_unique<Blk>();
+  Blk& b = *c.blk;
+  const long long m = c.m, n = c.n;
+  const size_t vs = c.op.f64 ? 8 : 4;
+  if (!b.At) {
+    b.ldt = (m + 3) / 4 * 4;
+    b.At = c.arena.alloc<char>(vs * (size_t)n * b.ldt);
+    if (c.op.f64)
+      transpose_rect<double>((const double*)c.op.val, m, n, c.op.ld, (double*)b.At, b.ldt, s);
+    else
+      transpose_rect<float>((const float*)c.op.val, m, n, c.op.ld, (float*)b.At, b.ldt, s);
+    b.op.A = c.op.val;
+    b.op.At = b.At;
+    b.op.m = m;
+    b.op.n = n;
+    b.op.ld = c.op.ld;
+    b.op.ldt = b.ldt;
+    b.op.f64 = c.op.f64;
+    b.op.Sm = gemm_splits(m, n);
+    b.op.Sn = gemm_splits(n, m);
+  }
+  if (b.kp >= kp) return;
+  b.kp = kp;
+  const int L = std::max(c.L, 1);
+  b.S1max = 64;
+  b.S2max = gemm_splits(n, L);
+  b.Bp = c.arena.alloc<double>((size_t)m * kp);
+  b.Bbot = c.arena.alloc<double>((size_t)n * kp);
+  b.Xp = c.arena.alloc<double>((size_t)n * kp);
+  b.tm = c.arena.alloc<double>((size_t)m * kp);
+  b.tn = c.arena.alloc<double>((size_t)n * kp);
+  b.vec.u_top = c.arena.alloc<double>((size_t)m * kp);
+  b.vec.u_bot = c.arena.alloc<double>((size_t)n * kp);
+  b.vec.v = c.arena.alloc<double>((size_t)n * kp);
+  b.vec.w = c.arena.alloc<double>((size_t)n * kp);
+  b.vec.y = c.arena.alloc<double>((size_t)n * kp);
+  b.vec.t = c.arena.alloc<double>((size_t)n * kp);
+  b.vec.g = c.arena.alloc<double>((size_t)n * kp);
+  b.wk.pm = c.arena.alloc<double>((size_t)b.op.Sm * m * kp);
+  b.wk.pn = c.arena.alloc<double>((size_t)b.op.Sn * n * kp);
+  if (c.o.precond) {
+    b.wk.pl = c.arena.alloc<double>((size_t)b.S1max * L * kp);
+    b.wk.pc = c.arena.alloc<double>((size_t)L * kp);
+    b.wk.pq = c.arena.alloc<double>((size_t)b.S2max * n * kp);
+  }
+  b.wk.beta_part = c.arena.alloc<double>((size_t)kBlkMaxGrid * kp);
+  b.wk.alpha_part = c.arena.alloc<double>((size_t)kBlkMaxGrid * kp);
+  b.wk.norm_part = c.arena.alloc<double>((size_t)kBlkMaxGrid * kp);
+  b.st = c.arena.alloc<GKState>(2 * kp);
+  SyncGuard g(g_capture_mu);
+  if (b.st_up) (void)hipHostFree(b.st_up);
+  if (b.st_down) (void)hipHostFree(b.st_down);
+  if (b.norm_host) (void)hipHostFree(b.norm_host);
+  b.st_up = b.st_down = nullptr;
+  b.norm_host = nullptr;
+  APL_HIP(hipHostMalloc((void**)&b.st_up, sizeof(GKState) * 2 * kp, hipHostMallocDefault));
+  APL_HIP(hipHostMalloc((void**)&b.st_down, sizeof(GKState) * 2 * kp, hipHostMallocDefault));
+  APL_HIP(hipHostMalloc((void**)&b.norm_host, sizeof(double) * kBlkMaxGrid * kp, hipHostMallocDefault));
+}
+
+// The explicit P for the blocked kernels (V^T refreshed after each rebuild).
+static BlkPrec blk_prec(Ctx& c, hipStream_t s) {
+  Blk& b = *c.blk;
+  const int l = c.prec.ell;
+  if (!b.Vt) {
+    b.ldvt = (c.n + 1) / 2 * 2;
+    b.Vt = c.arena.alloc<double>((size_t)std::max(c.L, 1) * b.ldvt);
+  }
+  if (b.vt_gen != c.prec_gen) {
+    // V^T (l x n row-major) is V = Q_R V_M column-major
+    const int jw2 = 2 * jacobi_block_width();
+    const int lp = ((l + jw2 - 1) / jw2) * jw2;
+    gemm(c, rocblas_operation_none, rocblas_operation_none, c.n, l, l, 1.0, c.Q, c.n, c.Vm, lp, 0.0, b.Vt, b.ldvt);
+    b.vt_gen = c.prec_gen;
+  }
+  BlkPrec P{};
+  P.V = c.prec.V;
+  P.Vt = b.Vt;
+  P.d = c.prec.d;
+  P.ldv = c.prec.ldv;
+  P.ldvt = b.ldvt;
+  P.ell = l;
+  P.S1 = std::min(b.S1max, gemm_splits(l, c.n));
+  P.S2 = std::min(b.S2max, gemm_splits(c.n, l));
+  return P;
+}
+
+// Per-column norms (sqrt of the column sums of the norm partials).
+static std::vector<double> blk_col_norms(Ctx& c, int k, int mode, const double* B, const double* Bbot, double bs,
+                                         const double* X, hipStream_t s) {
+  Blk& b = *c.blk;
+  const int kp = b.kp;
+  const int cnt = blk_norms(b.op, kp, mode, B, Bbot, bs, X, c.delta, b.tm, b.tn, b.wk, s);
+  APL_HIP(hipMemcpyAsync(b.norm_host, b.wk.norm_part, sizeof(double) * cnt * kp, hipMemcpyDeviceToHost, s));
+  APL_HIP(hipStreamSynchronize(s));
+  std::vector<double> out(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    double t = 0.0;
+    for (int w = 0; w < cnt; ++w) t += b.norm_host[(size_t)w * kp + j];
+    out[j] = std::sqrt(std::max(t, 0.0));
+  }
+  return out;
+}
+
+// Stopping parameters of one column for one phase (inactive: starts stopped).
+struct BlkParam {
+  bool active = false;
+  double tol_abs = 0.0, pnorm = 1.0, eps_lsqr = 0.0, baug_eps = 0.0, nu = INFINITY, sigma_l = 0.0;
+  int budget = 0;
+};
+
+// One warm-started phase for the active columns of min || A_mu X - [B; bs Bbot] ||.
+static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::vector<BlkParam>& prm,
+                                           const double* Bbot, double bs, bool x_zero, hipStream_t s) {
+  Blk& b = *c.blk;
+  const int kp = b.kp, k = (int)prm.size();
+  long long budget = 0;
+  for (int j = 0; j < kp; ++j) {
+    GKState& h = b.st_up[j];
+    std::memset(&h, 0, sizeof(h));
+    h.alpha = 1.0;
+    h.beta = 1.0;
+    h.delta = c.delta;
+    if (j < k && prm[j].active) {
+      const BlkParam& q = prm[j];
+      h.pnorm = q.pnorm;
+      h.tol_abs = q.tol_abs;
+      h.eps_lsqr = q.eps_lsqr;
+      h.baug_eps = q.baug_eps;
+      h.nu = q.nu;
+      h.sigma_l = q.sigma_l;
+      h.max_iter = q.budget;
+      h.init = 1;
+      budget = std::max<long long>(budget, q.budget);
+    } else {
+      h.stop = 1;
+      h.nu = INFINITY;
+    }
+    b.st_up[kp + j] = h;
+  }
+  APL_HIP(hipMemcpyAsync(b.st, b.st_up, sizeof(GKState) * 2 * kp, hipMemcpyHostToDevice, s));
+  blk_phase_init<double>(b.op, P, kp, b.Bp, Bbot, bs, b.Xp, x_zero, c.delta, b.vec, b.st, b.wk, s);
+  auto read = [&]() {
+    APL_HIP(hipMemcpyAsync(b.st_down, b.st, sizeof(GKState) * 2 * kp, hipMemcpyDeviceToHost, s));
+    APL_HIP(hipStreamSynchronize(s));
+    bool all = true;
+    for (int j = 0; j < k; ++j) {
+      if (!prm[j].active) continue;
+      const GKState& h0 = b.st_down[j];
+      const GKState& h1 = b.st_down[kp + j];
+      all &= (h0.stop || h1.stop);
+    }
+    return all;
+  };
+  int chunk = 8;
+  long long launched = 0;
+  APL_HIP(hipGetLastError());
+  bool done = read();
+  while (!done) {
+    for (int i = 0; i < chunk; ++i) blk_iteration<double>(b.op, P, kp, c.delta, b.vec, b.st, b.wk, s);
+    launched += chunk;
+    chunk = std::min(chunk * 2, 64);
+    APL_HIP(hipGetLastError());
+    done = read();
+    if (!done && launched > budget + 128)
+      throw Error(APLICUR_E_HIP, "blocked LSQR phase did not reach its stopping tests within its budget");
+  }
+  std::vector<PhaseOut> out(k, PhaseOut{0, kStopNone});
+  for (int j = 0; j < k; ++j) {
+    if (!prm[j].active) continue;
+    const GKState& h0 = b.st_down[j];
+    const GKState& h1 = b.st_down[kp + j];
+    const GKState& h = (h1.stop && !h0.stop) ? h1 : h0;
+    if (h.reason == 6) throw Error(APLICUR_E_BREAKDOWN, "non-finite value in the LSQR recurrence");
+    out[j] = PhaseOut{h.iter, h.reason};
+  }
+  blk_phase_finish<double>(b.op, P, kp, b.vec, b.Xp, b.wk, s);
+  return out;
+}
+
+// Restarted phases with nu = inf for every column not yet done, until each
+// reaches eta <= tol or its budget / stall guard (the column path's refine).
+static void refine_blk(Ctx& c, const BlkPrec* P, std::vector<ColState>& cols, const double* Bbot, double bs,
+                       double pnorm, double sigma_l, bool first_from_zero, hipStream_t s) {
+  const int k = (int)cols.size();
+  std::vector<int> stalls(k, 0);
+  std::vector<bool> live(k);
+  for (int j = 0; j < k; ++j) live[j] = !cols[j].done;
+  bool xz = first_from_zero;
+  for (;;) {
+    std::vector<BlkParam> prm(k);
+    bool any = false;
+    for (int j = 0; j < k; ++j) {
+      ColState& cs = cols[j];
+      if (live[j] && !(cs.eta > c.o.tol_ne && cs.used < c.o.max_iter && stalls[j] < 3)) live[j] = false;
+      if (!live[j]) continue;
+      BlkParam& q = prm[j];
+      q.active = true;
+      q.tol_abs = c.o.tol_ne * cs.atb;
+      q.pnorm = pnorm;
+      q.sigma_l = sigma_l;
+      q.budget = c.o.max_iter - cs.used;
+      any = true;
+    }
+    if (!any) break;
+    std::vector<double> prev(k);
+    for (int j = 0; j < k; ++j) prev[j] = cols[j].eta;
+    std::vector<PhaseOut> po = run_phase_blk(c, P, prm, Bbot, bs, xz, s);
+    xz = false;
+    std::vector<double> eta = blk_col_norms(c, k, 2, c.blk->Bp, Bbot, bs, c.blk->Xp, s);
+    for (int j = 0; j < k; ++j) {
+      if (!prm[j].active) continue;
+      ColState& cs = cols[j];
+      cs.used += po[j].iters;
+      cs.phases += 1;
+      cs.eta = eta[j] / cs.atb;
+      if (po[j].iters == 0 || po[j].reason == kStopBudget) live[j] = false;
+      stalls[j] = (cs.eta > 0.5 * prev[j]) ? stalls[j] + 1 : 0;
+    }
+  }
+  for (auto& cs : cols) cs.done = true;
+}
+
+static int solve_blocked(Ctx& c, const double* B, long long ldb, int nrhs, double* X, long long ldx, bool warm,
+                         aplicur_info* info, hipStream_t s) {
+  std::vector<ColState> all(nrhs);
+  SolveLog lg;
+  c.phase_iters0.clear();
+  c.phase_eta0.clear();
+  for (int g0 = 0; g0 < nrhs; g0 += kBlkMaxCols) {
+    const int k = std::min(kBlkMaxCols, nrhs - g0);
+    const int kp = blk_kp(k);
+    ensure_blk(c, kp, s);
+    Blk& b = *c.blk;
+    pack_cols(B + (size_t)g0 * ldb, ldb, c.m, k, b.Bp, b.kp, s);
+    if (warm)
+      pack_cols(X + (size_t)g0 * ldx, ldx, c.n, k, b.Xp, b.kp, s);
+    else
+      fill(b.Xp, c.n * b.kp, 0.0, s);
+    std::vector<ColState> cols(k);
+    const std::vector<double> atb = blk_col_norms(c, k, 1, b.Bp, nullptr, 0.0, nullptr, s);
+    const std::vector<double> bn = blk_col_norms(c, k, 0, b.Bp, nullptr, 0.0, nullptr, s);
+    std::vector<double> eta0;
+    if (warm) eta0 = blk_col_norms(c, k, 2, b.Bp, nullptr, 0.0, b.Xp, s);
+    for (int j = 0; j < k; ++j) {
+      ColState& cs = cols[j];
+      cs.atb = atb[j];
+      cs.bnorm = bn[j];
+      if (!std::isfinite(cs.atb) || !std::isfinite(cs.bnorm))
+        throw Error(APLICUR_E_BREAKDOWN, "non-finite values in A or B");
+      if (cs.atb == 0.0) {
+        cs.eta = 0.0;
+        cs.done = true;
+      } else if (warm) {
+        cs.eta = eta0[j] / cs.atb;
+        cs.done = cs.eta <= c.o.tol_ne;
+      }
+    }
+    bool any_active = false;
+    for (auto& cs : cols) any_active |= !cs.done;
+    SolveLog gl;
+    if (!c.o.precond) {
+      auto t0 = Clock::now();
+      refine_blk(c, nullptr, cols, nullptr, 0.0, 1.0, 0.0, !warm, s);
+      gl.t_lsqr += ms_since(t0);
+    } else if (any_active) {
+      outer_loop(c, s, gl, [&](bool final_step, double nu, double epsl) {
+        const BlkPrec P = blk_prec(c, s);
+        std::vector<BlkParam> prm(k);
+        bool xz = !warm;
+        for (int j = 0; j < k; ++j) {
+          ColState& cs = cols[j];
+          if (cs.done) continue;
+          xz &= (cs.phases == 0);
+          BlkParam& q = prm[j];
+          q.active = true;
+          q.tol_abs = c.o.tol_ne * cs.atb;
+          q.pnorm = c.p_pnorm;
+          q.eps_lsqr = epsl;
+          q.baug_eps = c.o.eps_lsqr * cs.bnorm;
+          q.nu = nu;
+          q.sigma_l = c.p_sigma_l;
+          q.budget = c.o.max_iter - cs.used;
+        }
+        std::vector<PhaseOut> po = run_phase_blk(c, &P, prm, nullptr, 0.0, xz, s);
+        const std::vector<double> eta = blk_col_norms(c, k, 2, c.blk->Bp, nullptr, 0.0, c.blk->Xp, s);
+        bool rest = false;
+        for (int j = 0; j < k; ++j) {
+          if (!prm[j].active) continue;
+          ColState& cs = cols[j];
+          cs.used += po[j].iters;
+          cs.phases += 1;
+          cs.eta = eta[j] / cs.atb;
+          if (cs.eta <= c.o.tol_ne || cs.used >= c.o.max_iter) cs.done = true;
+          rest |= !cs.done;
+        }
+        if (final_step && rest) refine_blk(c, &P, cols, nullptr, 0.0, c.p_pnorm, c.p_sigma_l, false, s);
+        bool active = false;
+        for (auto& cs : cols) active |= !cs.done;
+        return active;
+      });
+    }
+    unpack_cols(b.Xp, b.kp, c.n, k, X + (size_t)g0 * ldx, ldx, s);
+    for (int j = 0; j < k; ++j)
+      if (cols[j].atb == 0.0) fill(X + (size_t)(g0 + j) * ldx, c.n, 0.0, s);
+    for (int j = 0; j < k; ++j) all[g0 + j] = cols[j];
+    lg.t_cur += gl.t_cur;
+    lg.t_prec += gl.t_prec;
+    lg.t_lsqr += gl.t_lsqr;
+    lg.rebuilds += gl.rebuilds;
+    lg.outer += gl.outer;
+    lg.last_rho = gl.last_rho;
+  }
+  APL_HIP(hipStreamSynchronize(s));
+  int status = APLICUR_OK;
+  fill_info(c, all, lg, info, status);
+  return status;
+}
+
+// Y = A X (trans 0) or A^T X (trans 1) for k columns (column-major), in
+// groups of up to 64 columns through the blocked products (dense A).
+static void blk_apply(Ctx& c, int trans, const double* X, long long ldx, int k, double* Y, long long ldy,
+                      hipStream_t s) {
+  for (int g0 = 0; g0 < k; g0 += kBlkMaxCols) {
+    const int kg = std::min(kBlkMaxCols, k - g0);
+    ensure_blk(c, blk_kp(kg), s);
+    Blk& b = *c.blk;
+    double* in = trans ? b.tm : b.tn;
+    pack_cols(X + (size_t)g0 * ldx, ldx, trans ? c.m : c.n, kg, in, b.kp, s);
+    blk_matmat(b.op, trans != 0, in, b.kp, kg, Y + (size_t)g0 * ldy, ldy, s, (double*)(trans ? b.wk.pn : b.wk.pm));
+  }
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -1219,7 +1618,38 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
   const double pnorm = c.have_prec ? c.p_pnorm : 1.0, sigma_l = c.have_prec ? c.p_sigma_l : 0.0;
   int status = APLICUR_OK, iters = 0, phases = 0;
   double eta_max = 0.0;
-  for (int k = 0; k < nrhs; ++k) {
+  const bool blocked = use_blocked(c, nrhs);
+  for (int g0 = 0; blocked && g0 < nrhs; g0 += kBlkMaxCols) {
+    // the k columns of Z together (blocked path)
+    const int kg = std::min(kBlkMaxCols, nrhs - g0);
+    ensure_blk(c, blk_kp(kg), s);
+    Blk& b = *c.blk;
+    BlkPrec Pb{};
+    if (c.have_prec) Pb = blk_prec(c, s);
+    fill(b.Bp, c.m * b.kp, 0.0, s);
+    fill(b.Xp, c.n * b.kp, 0.0, s);
+    pack_cols(G + (size_t)g0 * ldg, ldg, c.n, kg, b.Bbot, b.kp, s);
+    const std::vector<double> gn = blk_col_norms(c, kg, 3, b.Bp, b.Bbot, 0.0, nullptr, s);
+    std::vector<ColState> cols(kg);
+    for (int j = 0; j < kg; ++j) {
+      cols[j].atb = gn[j];
+      if (!std::isfinite(gn[j])) throw Error(APLICUR_E_BREAKDOWN, "non-finite values in G");
+      if (gn[j] == 0.0) {
+        cols[j].eta = 0.0;
+        cols[j].done = true;
+      }
+    }
+    refine_blk(c, c.have_prec ? &Pb : nullptr, cols, b.Bbot, 1.0 / c.delta, pnorm, sigma_l, true, s);
+    unpack_cols(b.Xp, b.kp, c.n, kg, Z + (size_t)g0 * ldz, ldz, s);
+    for (auto& cs : cols) {
+      if (cs.eta > c.o.tol_ne) status = APLICUR_W_MAXITER;
+      eta_max = std::max(eta_max, cs.eta);
+      iters = std::max(iters, cs.used);
+      phases = std::max(phases, cs.phases);
+    }
+  }
+  if (blocked) blk_apply(c, 0, Z, ldz, nrhs, dB, lddb, s);  // dB = A Z
+  for (int k = 0; !blocked && k < nrhs; ++k) {
     const double* g = G + (size_t)k * ldg;
     double* z = Z + (size_t)k * ldz;
     fill(z, c.n, 0.0, s);
@@ -1249,9 +1679,13 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
     try {
       double* AX = work;
       double* R = work + (size_t)c.m * nrhs;
-      for (int k = 0; k < nrhs; ++k) {
-        fill(AX + (size_t)k * c.m, c.m, 0.0, s);
-        op_matvec(c.op, 0, X + (size_t)k * ldx, AX + (size_t)k * c.m, c.st_mv, c.wk, s);
+      if (blocked) {
+        blk_apply(c, 0, X, ldx, nrhs, AX, c.m, s);
+      } else {
+        for (int k = 0; k < nrhs; ++k) {
+          fill(AX + (size_t)k * c.m, c.m, 0.0, s);
+          op_matvec(c.op, 0, X + (size_t)k * ldx, AX + (size_t)k * c.m, c.st_mv, c.wk, s);
+        }
       }
       sub_cols(B, ldb, AX, c.m, R, c.m, c.m, nrhs, s);
       if (c.op.csr) {
@@ -1458,6 +1892,29 @@ int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, 
     hipStream_t s = (hipStream_t)stream;
     if (!trans) fill(y, c.m, 0.0, s);
     op_matvec(c.op, trans, x, y, c.st_mv, c.wk, s);
+    APL_HIP(hipGetLastError());
+    return APLICUR_OK;
+  });
+}
+
+int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx, int32_t k, double* Y, int64_t ldy,
+                   void* stream) {
+  return guarded([&]() {
+    APL_REQUIRE(ctx && ctx->impl && X && Y, "null argument");
+    Ctx& c = *ctx->impl;
+    APL_REQUIRE(k >= 1, "k must be >= 1");
+    APL_REQUIRE(ldx >= (trans ? c.m : c.n) && ldy >= (trans ? c.n : c.m), "leading dimensions too small");
+    hipStream_t s = (hipStream_t)stream;
+    set_stream(c, s);
+    if (c.op.csr) {
+      for (int j = 0; j < k; ++j) {
+        double* y = Y + (size_t)j * ldy;
+        if (!trans) fill(y, c.m, 0.0, s);
+        op_matvec(c.op, trans, X + (size_t)j * ldx, y, c.st_mv, c.wk, s);
+      }
+    } else {
+      blk_apply(c, trans, X, ldx, k, Y, ldy, s);
+    }
     APL_HIP(hipGetLastError());
     return APLICUR_OK;
   });

@@ -1,0 +1,744 @@
+// Blocked Golub-Kahan / LSQR kernels for several right-hand sides of a dense A
+// (the recurrences of Sec. 2.2 per column, the products shared).
+//
+// Products.  A t, A^T u and the two products of the explicit P^{-1} are all
+// "row-streaming" products out = M In with M row-major (A, its transposed
+// copy, V^T or V) and In a row-major block of kp <= 64 columns.  They run on
+// the 16x16x4 MFMA (FP64, or FP32 for FP32 blocks): a wave owns 32 rows of M
+// and all kp columns, each step covers 32 entries of the reduction index, and
+// lane (i, q) = (lane % 16, lane / 16) holds M[row i][j0 + 8q .. j0 + 8q + 7],
+// loaded as one contiguous 32- or 64-byte piece, so a wave's load covers 16
+// whole 128-byte lines of M.  The reduction index is split into S chunks
+// (grid.y) when the rows alone give too few workgroups; the chunk partials are
+// summed in order by the consuming kernel, which also does the element-wise
+// LSQR work of the single-column kernels and the per-column reductions.
+//
+// Reductions.  As in the single-column kernels, a producing kernel writes one
+// partial per workgroup and column, and every workgroup of the consumer sums
+// them in a fixed order, so all workgroups hold bitwise-identical scalars;
+// threads c < kp advance the state of column c.
+#include "blk.h"
+
+#include <cstdint>
+
+namespace aplicur {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <class ACC>
+struct Mfma;
+// row(q, r): the output row that register r of lane (i, q) holds (column i).
+template <>
+struct Mfma<double> {
+  using acc_t = f64x4;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int r) { return q + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  using acc_t = f32x4;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int r) { return 4 * q + r; }
+};
+
+// Eight consecutive values, 16-byte aligned, widened to ACC.
+template <class TA, class ACC>
+__device__ __forceinline__ void load8(const TA* __restrict__ p, ACC* a) {
+  if constexpr (sizeof(TA) == 4) {
+    const float4 u = ((const float4*)p)[0], v = ((const float4*)p)[1];
+    a[0] = (ACC)u.x; a[1] = (ACC)u.y; a[2] = (ACC)u.z; a[3] = (ACC)u.w;
+    a[4] = (ACC)v.x; a[5] = (ACC)v.y; a[6] = (ACC)v.z; a[7] = (ACC)v.w;
+  } else {
+    const double2 u0 = ((const double2*)p)[0], u1 = ((const double2*)p)[1];
+    const double2 u2 = ((const double2*)p)[2], u3 = ((const double2*)p)[3];
+    a[0] = (ACC)u0.x; a[1] = (ACC)u0.y; a[2] = (ACC)u1.x; a[3] = (ACC)u1.y;
+    a[4] = (ACC)u2.x; a[5] = (ACC)u2.y; a[6] = (ACC)u3.x; a[7] = (ACC)u3.y;
+  }
+}
+
+constexpr int kGT = 2;                               // 16-row tiles per wave
+constexpr int kGRows = (kBlock / kWave) * kGT * 16;  // rows per workgroup
+constexpr int kGStep = 32;                           // reduction entries per step
+
+// MFMA 16x16x4 operands: A lane (i, q) holds row i, reduction entry q; B lane
+// (i, q) holds entry q, column i; D lane (i, q) register r holds column i of
+// row Mfma::row(q, r) (q + 4r for FP64: measured on gfx950; 4q + r for FP32).
+// Here entry q of MFMA e is reduction index j0 + 8q + e.
+template <class TA, class TB, class ACC, int NB, bool VEC>
+__global__ void __launch_bounds__(kBlock)
+    k_rows_gemm(const TA* __restrict__ M, long long rows, long long cols, long long ld, const TB* __restrict__ In,
+                ACC* __restrict__ out, long long kchunk) {
+  using MF = Mfma<ACC>;
+  using acc_t = typename MF::acc_t;
+  constexpr int KP = NB * 16;
+  acc_t acc[kGT][NB];
+#pragma unroll
+  for (int t = 0; t < kGT; ++t)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[t][b] = acc_t{0, 0, 0, 0};
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int li = lane % 16, lq = lane / 16;
+  const long long row0 = (long long)blockIdx.x * kGRows + (long long)wave * (kGT * 16);
+  const long long jb = (long long)blockIdx.y * kchunk;
+  const long long je = min(cols, jb + kchunk);
+  const TA* mrow[kGT];
+#pragma unroll
+  for (int t = 0; t < kGT; ++t) mrow[t] = M + min(row0 + t * 16 + li, rows - 1) * ld;
+  for (long long j0 = jb; j0 < je; j0 += kGStep) {
+    const long long jl = j0 + 8 * lq;
+    ACC a[kGT][8], b[NB][8];
+    if (VEC && j0 + kGStep <= je) {
+#pragma unroll
+      for (int t = 0; t < kGT; ++t) load8<TA, ACC>(mrow[t] + jl, a[t]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) b[nb][e] = (ACC)In[(jl + e) * KP + nb * 16 + li];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const long long j = jl + e;
+        const bool in = j < je;
+        const long long jc = in ? j : je - 1;
+#pragma unroll
+        for (int t = 0; t < kGT; ++t) a[t][e] = in ? (ACC)mrow[t][jc] : (ACC)0;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) b[nb][e] = in ? (ACC)In[jc * KP + nb * 16 + li] : (ACC)0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+      for (int t = 0; t < kGT; ++t)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[t][nb] = MF::op(a[t][e], b[nb][e], acc[t][nb]);
+  }
+  ACC* o = out + (long long)blockIdx.y * rows * KP;
+#pragma unroll
+  for (int t = 0; t < kGT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long row = row0 + t * 16 + MF::row(lq, r);
+      if (row < rows) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) o[row * KP + nb * 16 + li] = acc[t][nb][r];
+      }
+    }
+}
+
+int gemm_splits(long long rows, long long cols) {
+  const long long gx = ceil_div(rows, kGRows);
+  long long S = (1024 + gx - 1) / gx;  // about four workgroups per CU
+  S = std::min<long long>(S, std::max<long long>(1, cols / 512));
+  return (int)std::max<long long>(1, std::min<long long>(S, 64));
+}
+
+template <class TA, class TB, class ACC, int NB>
+static void rows_gemm_nb(const TA* M, long long rows, long long cols, long long ld, const TB* In, ACC* out, int S,
+                         hipStream_t s) {
+  const long long per = ceil_div(cols, S);
+  const long long kchunk = ((per + kGStep - 1) / kGStep) * kGStep;
+  const bool vec = ((uintptr_t)M % 16 == 0) && ((ld * (long long)sizeof(TA)) % 16 == 0);
+  const dim3 g(ceil_div(rows, kGRows), S);
+  if (vec)
+    hipLaunchKernelGGL((k_rows_gemm<TA, TB, ACC, NB, true>), g, dim3(kBlock), 0, s, M, rows, cols, ld, In, out, kchunk);
+  else
+    hipLaunchKernelGGL((k_rows_gemm<TA, TB, ACC, NB, false>), g, dim3(kBlock), 0, s, M, rows, cols, ld, In, out,
+                       kchunk);
+}
+
+template <class TA, class TB, class ACC>
+void rows_gemm(const TA* M, long long rows, long long cols, long long ld, const TB* In, int kp, ACC* out, int S,
+               hipStream_t s) {
+  APL_REQUIRE(rows >= 1 && cols >= 1 && S >= 1, "rows_gemm: empty product");
+  switch (kp) {
+    case 16: rows_gemm_nb<TA, TB, ACC, 1>(M, rows, cols, ld, In, out, S, s); break;
+    case 32: rows_gemm_nb<TA, TB, ACC, 2>(M, rows, cols, ld, In, out, S, s); break;
+    case 64: rows_gemm_nb<TA, TB, ACC, 4>(M, rows, cols, ld, In, out, S, s); break;
+    default: APL_REQUIRE(false, "rows_gemm: kp must be 16, 32 or 64");
+  }
+}
+template void rows_gemm<double, double, double>(const double*, long long, long long, long long, const double*, int,
+                                                double*, int, hipStream_t);
+template void rows_gemm<float, double, double>(const float*, long long, long long, long long, const double*, int,
+                                               double*, int, hipStream_t);
+template void rows_gemm<float, float, float>(const float*, long long, long long, long long, const float*, int, float*,
+                                             int, hipStream_t);
+template void rows_gemm<double, float, double>(const double*, long long, long long, long long, const float*, int,
+                                               double*, int, hipStream_t);
+
+// ---------------------------------------------------------------- layout helpers
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+    k_transpose_rect(const T* __restrict__ A, long long m, long long n, long long lda, T* __restrict__ At,
+                     long long ldt) {
+  __shared__ T tile[32][33];
+  const long long i0 = (long long)blockIdx.y * 32, j0 = (long long)blockIdx.x * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int r = ty; r < 32; r += kBlock / 32) {
+    const long long i = i0 + r, j = j0 + tx;
+    if (i < m && j < n) tile[r][tx] = A[i * lda + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += kBlock / 32) {
+    const long long j = j0 + r, i = i0 + tx;
+    if (j < n && i < m) At[j * ldt + i] = tile[tx][r];
+  }
+}
+
+template <class T>
+void transpose_rect(const T* A, long long m, long long n, long long lda, T* At, long long ldt, hipStream_t s) {
+  APL_REQUIRE(ceil_div(m, 32) <= 65535, "transpose_rect: too many rows");
+  hipLaunchKernelGGL((k_transpose_rect<T>), dim3(ceil_div(n, 32), ceil_div(m, 32)), dim3(kBlock), 0, s, A, m, n, lda,
+                     At, ldt);
+}
+template void transpose_rect<double>(const double*, long long, long long, long long, double*, long long, hipStream_t);
+template void transpose_rect<float>(const float*, long long, long long, long long, float*, long long, hipStream_t);
+
+__global__ void k_pack_cols(const double* __restrict__ X, long long ldx, long long rows, int k, double* __restrict__ Xp,
+                            int kp) {
+  const long long total = rows * kp;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total; e += (long long)gridDim.x * kBlock) {
+    const long long r = e / kp;
+    const int c = (int)(e % kp);
+    Xp[e] = c < k ? X[(long long)c * ldx + r] : 0.0;
+  }
+}
+
+__global__ void k_unpack_cols(const double* __restrict__ Xp, int kp, long long rows, int k, double* __restrict__ X,
+                              long long ldx) {
+  const long long total = rows * k;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total; e += (long long)gridDim.x * kBlock) {
+    const int c = (int)(e / rows);
+    const long long r = e % rows;
+    X[(long long)c * ldx + r] = Xp[r * kp + c];
+  }
+}
+
+// Y[:, c] = sum of the S planes of part (rows x kp) at column c, for c < k.
+__global__ void k_planes_to_cols(const double* __restrict__ part, int S, long long rows, int kp, int k,
+                                 double* __restrict__ Y, long long ldy) {
+  const long long total = rows * k, plane = rows * kp;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total; e += (long long)gridDim.x * kBlock) {
+    const int c = (int)(e / rows);
+    const long long r = e % rows;
+    double acc = part[r * kp + c];
+    for (int q = 1; q < S; ++q) acc += part[(long long)q * plane + r * kp + c];
+    Y[(long long)c * ldy + r] = acc;
+  }
+}
+
+static unsigned elem_grid(long long count, long long cap = 4096) {
+  long long g = ceil_div(count, kBlock);
+  if (g < 1) g = 1;
+  return (unsigned)(g > cap ? cap : g);
+}
+
+void pack_cols(const double* X, long long ldx, long long rows, int k, double* Xp, int kp, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_cols, dim3(elem_grid(rows * kp)), dim3(kBlock), 0, s, X, ldx, rows, k, Xp, kp);
+}
+void unpack_cols(const double* Xp, int kp, long long rows, int k, double* X, long long ldx, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_cols, dim3(elem_grid(rows * k)), dim3(kBlock), 0, s, Xp, kp, rows, k, X, ldx);
+}
+
+void blk_matmat(const BlkOp& A, bool trans, const double* In, int kp, int k, double* Y, long long ldy, hipStream_t s,
+                double* part) {
+  const long long rows = trans ? A.n : A.m, cols = trans ? A.m : A.n, ld = trans ? A.ldt : A.ld;
+  const void* M = trans ? A.At : A.A;
+  const int S = trans ? A.Sn : A.Sm;
+  if (A.f64)
+    rows_gemm<double, double, double>((const double*)M, rows, cols, ld, In, kp, part, S, s);
+  else
+    rows_gemm<float, double, double>((const float*)M, rows, cols, ld, In, kp, part, S, s);
+  hipLaunchKernelGGL(k_planes_to_cols, dim3(elem_grid(rows * k)), dim3(kBlock), 0, s, (const double*)part, S, rows, kp,
+                     k, Y, ldy);
+}
+
+// ---------------------------------------------------------------- per-column reductions
+// out[c] = sum over w < count of part[w kp + c], in a fixed order (thread
+// c + kp q takes w = q, q + NS, ...; then q in order).  All threads call.
+template <int KP>
+__device__ __forceinline__ void col_sums(const double* __restrict__ part, int count, double* lds, double* out) {
+  constexpr int NS = kBlock / KP;
+  const int c = threadIdx.x % KP, q = threadIdx.x / KP;
+  double acc = 0.0;
+  if (part) {
+#pragma unroll 4
+    for (int w = q; w < count; w += NS) acc += part[(long long)w * KP + c];
+  }
+  lds[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < KP) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) t += lds[i * KP + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// This workgroup's partial of column (threadIdx.x % kp): part_out[blockIdx.x kp + c].
+template <int KP>
+__device__ __forceinline__ void col_partials(double sq, double* lds, double* part_out) {
+  constexpr int NS = kBlock / KP;
+  __syncthreads();
+  lds[threadIdx.x] = sq;
+  __syncthreads();
+  if (threadIdx.x < KP) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) t += lds[i * KP + threadIdx.x];
+    part_out[(long long)blockIdx.x * KP + threadIdx.x] = t;
+  }
+}
+
+// Sum of the S chunk planes of a product at element e.
+template <class V>
+__device__ __forceinline__ V plane_sum(const V* __restrict__ part, int S, long long plane, long long e) {
+  V acc = part[e];
+  for (int s = 1; s < S; ++s) acc += part[(long long)s * plane + e];
+  return acc;
+}
+
+// Per-column scalars shared through LDS.
+struct BlkScal {
+  double ts, cu, cy, cw, ib, cv;
+  int active, pend, fin, init;
+};
+
+// ---------------------------------------------------------------- phase start
+// r_top = B - (A X) (FP64 partials; B when pm is null), r_bot = bs Bbot - delta X;
+// partials of ||r||^2 per column.
+template <class RV, int KP>
+__global__ void __launch_bounds__(kBlock)
+    k_blk_resid(const double* __restrict__ pm, int S, long long m, long long n, const double* __restrict__ B,
+                const double* Bbot, double bs, const double* X, double delta, RV* r_top, RV* r_bot,
+                double* beta_part) {
+  __shared__ double lds[kBlock];
+  const long long stride = (long long)gridDim.x * kBlock;
+  double sq = 0.0;
+  const long long mp = m * KP, np = n * KP;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < mp; e += stride) {
+    const double r = (B ? B[e] : 0.0) - (pm ? plane_sum(pm, S, mp, e) : 0.0);
+    r_top[e] = (RV)r;
+    sq += r * r;
+  }
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < np; e += stride) {
+    double r = X ? -delta * X[e] : 0.0;
+    if (Bbot) r += bs * Bbot[e];
+    r_bot[e] = (RV)r;
+    sq += r * r;
+  }
+  col_partials<KP>(sq, lds, beta_part);
+}
+
+// ---------------------------------------------------------------- forward
+// u_top <- (A tin) / alpha - (alpha / beta) u_top, u_bot likewise, partials of
+// ||u||^2.  PLAIN finishes alpha (slot 1 -> slot 0), takes the scalar step and
+// applies the previous y/w update; PRE uses slot 0 as the P^{-1} kernel left it.
+template <class V, int KP, int MODE>
+__global__ void __launch_bounds__(kBlock)
+    k_blk_fwd(const V* __restrict__ pm, int S, long long m, long long n, double delta, const V* tin, V* u_top,
+              V* u_bot, const V* v, V* w, V* y, const GKState* __restrict__ st_in, GKState* __restrict__ st_out,
+              const double* alpha_part, int alpha_count, double* beta_part) {
+  __shared__ double lds[kBlock];
+  __shared__ double a2[KP];
+  __shared__ BlkScal sc[KP];
+  if (MODE == kFwdPlain) col_sums<KP>(alpha_part, alpha_count, lds, a2);
+  if (threadIdx.x < KP) {
+    const int c = threadIdx.x;
+    GKState s = st_in[c];
+    BlkScal k{};
+    if (!s.stop) {
+      if (MODE == kFwdPlain) scalar_step(s, sqrt(a2[c]));
+      if (s.stop) {
+        k.fin = s.pending;
+        k.cy = s.coef_y;
+      } else {
+        k.active = 1;
+        k.ts = 1.0 / s.alpha;
+        k.cu = s.alpha / s.beta;
+        k.pend = (MODE == kFwdPlain) && s.pending;
+        k.cy = s.coef_y;
+        k.cw = s.coef_w;
+      }
+    }
+    if (MODE == kFwdPlain && blockIdx.x == 0) st_out[c] = s;
+    sc[c] = k;
+  }
+  __syncthreads();
+  const BlkScal k = sc[threadIdx.x % KP];
+  const V ts = (V)k.ts, cu = (V)k.cu, cy = (V)k.cy, cw = (V)k.cw;
+  const long long stride = (long long)gridDim.x * kBlock;
+  double sq = 0.0;
+  if (k.active) {
+    const long long mp = m * KP;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < mp; e += stride) {
+      const V un = plane_sum(pm, S, mp, e) * ts - cu * u_top[e];
+      u_top[e] = un;
+      sq += (double)un * (double)un;
+    }
+  }
+  if (k.active || k.fin) {
+    const long long np = n * KP;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < np; e += stride) {
+      if (k.active) {
+        if (delta > 0.0) {
+          const V ub = (V)delta * (tin[e] * ts) - cu * u_bot[e];
+          u_bot[e] = ub;
+          sq += (double)ub * (double)ub;
+        }
+        if (k.pend) {
+          const V we = w[e];
+          y[e] += cy * we;
+          w[e] = v[e] * ts - cw * we;
+        }
+      } else {
+        y[e] += cy * w[e];
+      }
+    }
+  }
+  col_partials<KP>(sq, lds, beta_part);
+}
+
+// ---------------------------------------------------------------- backward
+// beta from the forward partials (slot 0 -> slot 1); g = (A^T u_top + delta
+// u_bot) / beta.  PLAIN: v <- g - (beta / alpha) v (g at the phase start) and
+// partials of ||v||^2; otherwise g is stored for P^{-T}.
+template <class V, int KP, bool PLAIN>
+__global__ void __launch_bounds__(kBlock)
+    k_blk_bwd(const V* __restrict__ pn, int S, long long n, double delta, const V* u_bot, V* v, V* g,
+              const GKState* __restrict__ st_in, GKState* __restrict__ st_out, const double* beta_part, int beta_count,
+              double* alpha_part) {
+  __shared__ double lds[kBlock];
+  __shared__ double b2[KP];
+  __shared__ BlkScal sc[KP];
+  col_sums<KP>(beta_part, beta_count, lds, b2);
+  if (threadIdx.x < KP) {
+    const int c = threadIdx.x;
+    GKState s = st_in[c];
+    BlkScal k{};
+    if (!s.stop) {
+      const double beta = sqrt(b2[c]);
+      const bool bad = !(beta == beta) || isinf(beta) || (beta == 0.0 && s.init);
+      const double alpha = s.alpha;
+      k.init = s.init;
+      beta_step(s, b2[c]);
+      if (!bad && beta != 0.0) {
+        k.active = 1;
+        k.ib = 1.0 / beta;
+        k.cv = beta / alpha;
+      }
+    }
+    if (blockIdx.x == 0) st_out[c] = s;
+    sc[c] = k;
+  }
+  __syncthreads();
+  const BlkScal k = sc[threadIdx.x % KP];
+  const V ib = (V)k.ib, cv = (V)k.cv;
+  double sq = 0.0;
+  if (k.active) {
+    const long long np = n * KP;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < np; e += (long long)gridDim.x * kBlock) {
+      V ge = plane_sum(pn, S, np, e) * ib;
+      if (delta > 0.0) ge += (V)delta * u_bot[e] * ib;
+      if (PLAIN) {
+        const V vn = k.init ? ge : ge - cv * v[e];
+        v[e] = vn;
+        sq += (double)vn * (double)vn;
+      } else {
+        g[e] = ge;
+      }
+    }
+  }
+  if (PLAIN) col_partials<KP>(sq, lds, alpha_part);
+}
+
+// ---------------------------------------------------------------- explicit P^{-1}
+// c = d .* (sum of the S planes of V^T z), ell x kp.
+template <int KP>
+__global__ void __launch_bounds__(kBlock)
+    k_blk_pcoef(const double* __restrict__ pl, int S, int ell, const double* __restrict__ d, double* c) {
+  const long long lp = (long long)ell * KP;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < lp; e += (long long)gridDim.x * kBlock)
+    c[e] = d[e / KP] * plane_sum(pl, S, lp, e);
+}
+
+// First kernel of a preconditioned iteration: alpha (slot 1 -> slot 0), the
+// scalar step, the y/w update and t = v + V c.
+template <class V, int KP>
+__global__ void __launch_bounds__(kBlock)
+    k_blk_pa_fwd(const double* __restrict__ pq, int S, long long n, const V* v, V* t, V* w, V* y,
+                 const GKState* __restrict__ st_in, GKState* __restrict__ st_out, const double* alpha_part,
+                 int alpha_count) {
+  __shared__ double lds[kBlock];
+  __shared__ double a2[KP];
+  __shared__ BlkScal sc[KP];
+  col_sums<KP>(alpha_part, alpha_count, lds, a2);
+  if (threadIdx.x < KP) {
+    const int c = threadIdx.x;
+    GKState s = st_in[c];
+    BlkScal k{};
+    if (!s.stop) {
+      scalar_step(s, sqrt(a2[c]));
+      if (s.stop) {
+        k.fin = s.pending;
+        k.cy = s.coef_y;
+      } else {
+        k.active = 1;
+        k.pend = s.pending;
+        k.cy = s.coef_y;
+        k.cw = s.coef_w;
+        k.ts = 1.0 / s.alpha;
+      }
+    }
+    if (blockIdx.x == 0) st_out[c] = s;
+    sc[c] = k;
+  }
+  __syncthreads();
+  const BlkScal k = sc[threadIdx.x % KP];
+  if (!k.active && !k.fin) return;
+  const long long np = n * KP;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < np; e += (long long)gridDim.x * kBlock) {
+    if (k.active) {
+      const V ve = v[e];
+      t[e] = (V)((double)ve + plane_sum(pq, S, np, e));
+      if (k.pend) {
+        const V we = w[e];
+        y[e] += (V)k.cy * we;
+        w[e] = (V)((double)ve * k.ts) - (V)k.cw * we;
+      }
+    } else {
+      y[e] += (V)k.cy * w[e];
+    }
+  }
+}
+
+// v <- (g + V c) - (beta / alpha) v  (g + V c at the phase start); partials of
+// ||v||^2 (slot 1 holds beta).
+template <class V, int KP>
+__global__ void __launch_bounds__(kBlock)
+    k_blk_pa_bwd(const double* __restrict__ pq, int S, long long n, const V* g, V* v, const GKState* __restrict__ sl,
+                 double* alpha_part) {
+  __shared__ double lds[kBlock];
+  __shared__ BlkScal sc[KP];
+  if (threadIdx.x < KP) {
+    const GKState& s = sl[threadIdx.x];
+    BlkScal k{};
+    if (!s.stop) {
+      k.active = 1;
+      k.init = s.init;
+      k.cv = s.beta / s.alpha;
+    }
+    sc[threadIdx.x] = k;
+  }
+  __syncthreads();
+  const BlkScal k = sc[threadIdx.x % KP];
+  double sq = 0.0;
+  if (k.active) {
+    const long long np = n * KP;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < np; e += (long long)gridDim.x * kBlock) {
+      const double pg = (double)g[e] + plane_sum(pq, S, np, e);
+      const V vn = k.init ? (V)pg : (V)(pg - k.cv * (double)v[e]);
+      v[e] = vn;
+      sq += (double)vn * (double)vn;
+    }
+  }
+  col_partials<KP>(sq, lds, alpha_part);
+}
+
+// X += y (+ V c when pq is given), FP64.
+template <class V>
+__global__ void __launch_bounds__(kBlock)
+    k_blk_add_x(const double* __restrict__ pq, int S, long long count, const V* __restrict__ y, double* X) {
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < count; e += (long long)gridDim.x * kBlock)
+    X[e] += (double)y[e] + (pq ? plane_sum(pq, S, count, e) : 0.0);
+}
+
+// ---------------------------------------------------------------- norms
+// Column partials of ||a||^2 over rows x kp (a given), or of
+// ||plane sum of pn + delta r_bot||^2 (the normal residual) when pn is given.
+template <int KP>
+__global__ void __launch_bounds__(kBlock)
+    k_blk_colsq(const double* __restrict__ a, const double* __restrict__ pn, int S, long long rows, double delta,
+                const double* __restrict__ r_bot, double* part) {
+  __shared__ double lds[kBlock];
+  const long long np = rows * KP;
+  double sq = 0.0;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < np; e += (long long)gridDim.x * kBlock) {
+    double x;
+    if (pn) {
+      x = plane_sum(pn, S, np, e);
+      if (r_bot) x += delta * r_bot[e];
+    } else {
+      x = a[e];
+    }
+    sq += x * x;
+  }
+  col_partials<KP>(sq, lds, part);
+}
+
+// ---------------------------------------------------------------- host launchers
+#define BLK_KP_SWITCH(kp, CALL)                            \
+  switch (kp) {                                            \
+    case 16: { constexpr int KP = 16; CALL; } break;       \
+    case 32: { constexpr int KP = 32; CALL; } break;       \
+    case 64: { constexpr int KP = 64; CALL; } break;       \
+    default: APL_REQUIRE(false, "blocked path: kp must be 16, 32 or 64"); \
+  }
+
+static unsigned blk_grid(long long rows, int kp) { return elem_grid(rows * kp, kBlkMaxGrid); }
+
+// A t (tin: n x kp) into the partials pm (Sm planes), or A^T u into pn.
+template <class V>
+static void blk_prod(const BlkOp& A, bool trans, const V* in, int kp, V* out, hipStream_t s) {
+  const long long rows = trans ? A.n : A.m, cols = trans ? A.m : A.n, ld = trans ? A.ldt : A.ld;
+  const void* M = trans ? A.At : A.A;
+  const int S = trans ? A.Sn : A.Sm;
+  if (A.f64)
+    rows_gemm<double, V, V>((const double*)M, rows, cols, ld, in, kp, out, S, s);
+  else
+    rows_gemm<float, V, V>((const float*)M, rows, cols, ld, in, kp, out, S, s);
+}
+
+// c = d .* V^T z, then pq = V c (S2 planes).
+template <class V>
+static void blk_pcoef(const BlkOp& A, const BlkPrec& P, int kp, const V* z, BlkWork& wk, hipStream_t s) {
+  rows_gemm<double, V, double>(P.Vt, P.ell, A.n, P.ldvt, z, kp, wk.pl, P.S1, s);
+  BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_pcoef<KP>), dim3(blk_grid(P.ell, kp)), dim3(kBlock), 0, s, wk.pl, P.S1,
+                                       P.ell, P.d, wk.pc));
+  rows_gemm<double, double, double>(P.V, A.n, P.ell, P.ldv, wk.pc, kp, wk.pq, P.S2, s);
+}
+
+template <class V>
+static void blk_bwd(const BlkOp& A, const BlkPrec* P, int kp, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
+                    hipStream_t s) {
+  blk_prod<V>(A, true, vec.u_top, kp, (V*)wk.pn, s);
+  const unsigned g = blk_grid(A.n, kp);
+  if (!P) {
+    BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_bwd<V, KP, true>), dim3(g), dim3(kBlock), 0, s, (const V*)wk.pn, A.Sn,
+                                         A.n, delta, (const V*)vec.u_bot, vec.v, vec.g, (const GKState*)st,
+                                         st + kp, (const double*)wk.beta_part, wk.beta_count, wk.alpha_part));
+    wk.alpha_count = g;
+    return;
+  }
+  BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_bwd<V, KP, false>), dim3(g), dim3(kBlock), 0, s, (const V*)wk.pn, A.Sn,
+                                       A.n, delta, (const V*)vec.u_bot, vec.v, vec.g, (const GKState*)st, st + kp,
+                                       (const double*)wk.beta_part, wk.beta_count, wk.alpha_part));
+  blk_pcoef<V>(A, *P, kp, vec.g, wk, s);
+  BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_pa_bwd<V, KP>), dim3(g), dim3(kBlock), 0, s, (const double*)wk.pq, P->S2,
+                                       A.n, (const V*)vec.g, vec.v, (const GKState*)(st + kp), wk.alpha_part));
+  wk.alpha_count = g;
+}
+
+template <class V>
+void blk_phase_init(const BlkOp& A, const BlkPrec* P, int kp, const double* B, const double* Bbot, double bs,
+                    const double* X, bool x_zero, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
+                    hipStream_t s) {
+  double* pm = (double*)wk.pm;
+  if (!x_zero) {
+    if (A.f64)
+      rows_gemm<double, double, double>((const double*)A.A, A.m, A.n, A.ld, X, kp, pm, A.Sm, s);
+    else
+      rows_gemm<float, double, double>((const float*)A.A, A.m, A.n, A.ld, X, kp, pm, A.Sm, s);
+  }
+  const unsigned g = blk_grid(std::max(A.m, A.n), kp);
+  BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_resid<V, KP>), dim3(g), dim3(kBlock), 0, s,
+                                       (const double*)(x_zero ? nullptr : pm), A.Sm, A.m, A.n, B, Bbot, bs,
+                                       x_zero ? nullptr : X, delta, vec.u_top, vec.u_bot, wk.beta_part));
+  wk.beta_count = g;
+  fill_zero<V>(vec.y, A.n * kp, s);
+  fill_zero<V>(vec.w, A.n * kp, s);
+  blk_bwd<V>(A, P, kp, delta, vec, st, wk, s);
+}
+
+template <class V>
+void blk_iteration(const BlkOp& A, const BlkPrec* P, int kp, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
+                   hipStream_t s) {
+  const unsigned g = blk_grid(std::max(A.m, A.n), kp);
+  if (!P) {
+    blk_prod<V>(A, false, vec.v, kp, (V*)wk.pm, s);
+    BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_fwd<V, KP, kFwdPlain>), dim3(g), dim3(kBlock), 0, s,
+                                         (const V*)wk.pm, A.Sm, A.m, A.n, delta, (const V*)vec.v, vec.u_top,
+                                         vec.u_bot, (const V*)vec.v, vec.w, vec.y, (const GKState*)(st + kp), st,
+                                         (const double*)wk.alpha_part, wk.alpha_count, wk.beta_part));
+  } else {
+    blk_pcoef<V>(A, *P, kp, vec.v, wk, s);
+    const unsigned gn = blk_grid(A.n, kp);
+    BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_pa_fwd<V, KP>), dim3(gn), dim3(kBlock), 0, s, (const double*)wk.pq,
+                                         P->S2, A.n, (const V*)vec.v, vec.t, vec.w, vec.y, (const GKState*)(st + kp),
+                                         st, (const double*)wk.alpha_part, wk.alpha_count));
+    blk_prod<V>(A, false, vec.t, kp, (V*)wk.pm, s);
+    BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_fwd<V, KP, kFwdPre>), dim3(g), dim3(kBlock), 0, s, (const V*)wk.pm,
+                                         A.Sm, A.m, A.n, delta, (const V*)vec.t, vec.u_top, vec.u_bot,
+                                         (const V*)vec.v, vec.w, vec.y, (const GKState*)st, st,
+                                         (const double*)nullptr, 0, wk.beta_part));
+  }
+  wk.beta_count = g;
+  blk_bwd<V>(A, P, kp, delta, vec, st, wk, s);
+}
+
+template <class V>
+void blk_phase_finish(const BlkOp& A, const BlkPrec* P, int kp, BlkVecs<V> vec, double* X, BlkWork& wk,
+                      hipStream_t s) {
+  const double* pq = nullptr;
+  int S2 = 1;
+  if (P) {
+    blk_pcoef<V>(A, *P, kp, vec.y, wk, s);
+    pq = wk.pq;
+    S2 = P->S2;
+  }
+  hipLaunchKernelGGL((k_blk_add_x<V>), dim3(elem_grid(A.n * kp)), dim3(kBlock), 0, s, pq, S2, A.n * kp,
+                     (const V*)vec.y, X);
+}
+
+int blk_norms(const BlkOp& A, int kp, int mode, const double* B, const double* Bbot, double bs, const double* X,
+              double delta, double* tmp_m, double* tmp_n, BlkWork& wk, hipStream_t s) {
+  double* pn = (double*)wk.pn;
+  if (mode == 0 || mode == 3) {
+    const long long rows = mode == 0 ? A.m : A.n;
+    const unsigned g = blk_grid(rows, kp);
+    BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_colsq<KP>), dim3(g), dim3(kBlock), 0, s, mode == 0 ? B : Bbot,
+                                         (const double*)nullptr, 1, rows, 0.0, (const double*)nullptr, wk.norm_part));
+    return (int)g;
+  }
+  const double* top = B;
+  const double* rbot = nullptr;
+  if (mode == 2) {
+    {
+      double* pm = (double*)wk.pm;
+      if (A.f64)
+        rows_gemm<double, double, double>((const double*)A.A, A.m, A.n, A.ld, X, kp, pm, A.Sm, s);
+      else
+        rows_gemm<float, double, double>((const float*)A.A, A.m, A.n, A.ld, X, kp, pm, A.Sm, s);
+      const unsigned g = blk_grid(std::max(A.m, A.n), kp);
+      BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_resid<double, KP>), dim3(g), dim3(kBlock), 0, s,
+                                           (const double*)pm, A.Sm, A.m, A.n, B, Bbot, bs, X, delta, tmp_m, tmp_n,
+                                           wk.beta_part));
+      top = tmp_m;
+      rbot = tmp_n;
+    }
+  }
+  if (A.f64)
+    rows_gemm<double, double, double>((const double*)A.At, A.n, A.m, A.ldt, top, kp, pn, A.Sn, s);
+  else
+    rows_gemm<float, double, double>((const float*)A.At, A.n, A.m, A.ldt, top, kp, pn, A.Sn, s);
+  const unsigned g = blk_grid(A.n, kp);
+  BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_colsq<KP>), dim3(g), dim3(kBlock), 0, s, (const double*)nullptr,
+                                       (const double*)pn, A.Sn, A.n, delta, rbot, wk.norm_part));
+  return (int)g;
+}
+
+template void blk_phase_init<double>(const BlkOp&, const BlkPrec*, int, const double*, const double*, double,
+                                     const double*, bool, double, BlkVecs<double>, GKState*, BlkWork&, hipStream_t);
+template void blk_iteration<double>(const BlkOp&, const BlkPrec*, int, double, BlkVecs<double>, GKState*, BlkWork&,
+                                    hipStream_t);
+template void blk_phase_finish<double>(const BlkOp&, const BlkPrec*, int, BlkVecs<double>, double*, BlkWork&,
+                                       hipStream_t);
+
+}  // namespace aplicur

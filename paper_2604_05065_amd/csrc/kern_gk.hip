@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "gk_scalar.h"
 #include "kernels.h"
 
 namespace aplicur {
@@ -34,99 +35,6 @@ constexpr int kMaxGrid = 4096;                // grid-stride kernels
 constexpr int kStreamCap = 2048;              // CSR-stream: LDS products per workgroup
 constexpr int kPer = kStreamCap / kBlock;     // products per thread
 constexpr int kRowsMaxGrid = 512;             // row-wise P-apply kernels (their partials are re-read)
-
-// ---------------------------------------------------------------- scalar update
-// One LSQR scalar step on a state copy: the initial step (alpha_1, beta_1) or
-// the Givens rotation of the previous iteration with the new alpha.
-__device__ void scalar_step(GKState& s, double alpha) {
-  if (!(alpha == alpha) || isinf(alpha)) {
-    s.stop = 1;
-    s.reason = 6;
-    s.pending = 0;
-    return;
-  }
-  if (s.init) {
-    s.init = 0;
-    const double beta = s.beta;
-    s.alpha = alpha;
-    s.rhobar = alpha;
-    s.phibar = beta;
-    s.beta1 = beta;
-    s.h2 = (alpha * beta) * (alpha * beta);
-    s.anorm2 = alpha * alpha;
-    s.phibar_prev = beta;
-    s.have_rate1 = 0;
-    s.iter = 0;
-    s.coef_y = 0.0;
-    s.coef_w = 0.0;
-    s.pending = 1;  // w = v / alpha
-    s.arnorm = alpha * beta;
-    if (alpha == 0.0 || beta == 0.0) {
-      s.stop = 1;
-      s.reason = kStopExact;
-      s.pending = 0;
-    } else if (s.max_iter <= 0) {
-      s.stop = 1;
-      s.reason = kStopBudget;
-      s.pending = 0;
-    }
-    return;
-  }
-  const double beta = s.beta;
-  s.alpha = alpha;
-  s.anorm2 += alpha * alpha + beta * beta;
-  const double rho = hypot(s.rhobar, beta);
-  const double c = s.rhobar / rho, sn = beta / rho;
-  const double theta = sn * alpha;
-  s.rhobar = -c * alpha;
-  const double phi = c * s.phibar;
-  const double phibar = sn * s.phibar;
-  s.phibar = phibar;
-  s.coef_y = phi / rho;
-  s.coef_w = theta / rho;
-  s.pending = 1;
-  s.iter += 1;
-  const double arnorm = phibar * alpha * fabs(c);
-  s.arnorm = arnorm;
-  int reason = kStopNone;
-  if (beta == 0.0 || alpha == 0.0) {
-    reason = kStopExact;
-  } else if (s.pnorm * arnorm <= s.tol_abs || arnorm <= s.rel_tol * sqrt(s.h2)) {
-    reason = kStopMetric;
-  } else if (s.eps_lsqr > 0.0 && (arnorm <= s.eps_lsqr * sqrt(s.anorm2) * phibar || phibar <= s.baug_eps)) {
-    reason = kStopLsqr;
-  } else {
-    const double rate = phibar > 0.0 ? log(s.phibar_prev / phibar) : INFINITY;
-    if (!s.have_rate1) {
-      s.rate1 = rate;
-      s.have_rate1 = 1;
-    } else if (!isinf(s.nu)) {
-      const double ratio = rate <= 0.0 ? INFINITY : s.rate1 / rate;
-      if (ratio > s.nu || (s.phibar_prev - phibar) < s.sigma_l) reason = kStopDynamic;
-    }
-    if (reason == kStopNone) s.phibar_prev = phibar;
-  }
-  if (reason == kStopNone && s.iter >= s.max_iter) reason = kStopBudget;
-  if (reason != kStopNone) {
-    s.stop = 1;
-    s.reason = reason;
-  }
-}
-
-// beta = sqrt(sum of squares); flags non-finite values and a zero residual
-// at the phase start (nothing to do).
-__device__ __forceinline__ void beta_step(GKState& s, double b2) {
-  const double b = sqrt(b2);
-  s.beta = b;
-  if (!(b == b) || isinf(b)) {
-    s.stop = 1;
-    s.reason = 6;
-  } else if (b == 0.0 && s.init) {
-    s.beta1 = 0.0;
-    s.stop = 1;
-    s.reason = kStopExact;
-  }
-}
 
 // ---------------------------------------------------------------- consumer reductions
 // This thread's share of the producer partials part[0..count), in a fixed
@@ -206,10 +114,10 @@ struct RowBlk {
   int r0, k0;
 };
 
-template <class V, class TA, class X, class Pre, class Settle, class Epi>
+template <class V, class TA, class X, class SH, class Pre, class Settle, class Epi>
 __device__ __forceinline__ bool csr_stream(RowBlk a, RowBlk b, const int* __restrict__ rp,
                                            const int* __restrict__ ci, const TA* __restrict__ val,
-                                           const X* __restrict__ x, const Share& share, Pre&& pre,
+                                           const X* __restrict__ x, const SH& share, Pre&& pre,
                                            Settle&& settle, Epi&& epi) {
   __shared__ V prod[kStreamCap];
   __shared__ double red[kBlock / kWave];
@@ -314,11 +222,6 @@ void build_row_blocks(const int* rp, long long m, long long nnz, int T, int* rb,
 }
 
 // ---------------------------------------------------------------- forward kernels
-// Modes: PLAIN finishes alpha from the backward kernel's partials (slot 1 ->
-// slot 0) and applies the y/w update; PRE reads slot 0 (alpha finished by
-// the P^{-1} kernel); MATVEC uses slot 0 as given (alpha = beta = 1).
-enum FwdMode { kFwdPlain = 0, kFwdPre = 1, kFwdMatvec = 2 };
-
 template <class V>
 __device__ __forceinline__ void final_y(long long n, V* y, const V* w, const GKState& s, long long first,
                                         long long stride) {
@@ -791,7 +694,9 @@ __device__ __forceinline__ bool bwd_settle(const GKState* __restrict__ st_in, GK
   return true;
 }
 
-template <class TA, class V, bool PLAIN, bool BOT>
+// KS: producer partials held per thread (1 when the forward grid is at most
+// kBlock workgroups, which keeps the kernel at seven workgroups per CU).
+template <class TA, class V, bool PLAIN, bool BOT, int KS>
 __global__ void __launch_bounds__(kBlock)
     k_bwd_csr(const RowBlk* __restrict__ trbk, const int* __restrict__ tp, const int* __restrict__ ti,
               const TA* __restrict__ tv, const V* u_top, const V* u_bot, V* v, V* g,
@@ -800,7 +705,7 @@ __global__ void __launch_bounds__(kBlock)
   const RowBlk ra = trbk[blockIdx.x], rb = trbk[blockIdx.x + 1];
   const int stop0 = st_in->stop, init = st_in->init;
   const double delta = st_in->delta;
-  Share share;
+  ShareT<kBlock, KS> share;
   share.load(beta_part, beta_count);
   if (stop0) {
     store_state(st_out, *st_in);
@@ -1200,10 +1105,7 @@ static void launch_k(F kern, dim3 g, hipStream_t s, hipEvent_t e0, hipEvent_t e1
   launch_kx(kern, g, dim3(kBlock), 0u, s, e0, e1, args...);
 }
 
-// LDS available to the x copy of the LDS-resident forward kernel, and the
-// size from which it beats the CSR-stream kernel (below it, loading x into
-// every workgroup's LDS costs more than the gathers it saves).
-
+// Dynamic LDS of the LDS-resident forward kernels (kLxMaxBytes: the x copy).
 template <class TA, class V>
 static void lx_attr() {
   (void)hipFuncSetAttribute((const void*)k_fwd_csr_lx<TA, V, kFwdPlain>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1375,20 +1277,23 @@ static void launch_bwd(const OpDesc& A, const V* u_top, const V* u_bot, V* v, V*
     const RowBlk* trbk = (const RowBlk*)A.t_rb;
     const GKState* sin = st;
     GKState* sout = st + 1;
+    auto go = [&](auto kern, const auto* tv) {
+      launch_k(kern, dim3(grid), s, e0, e1, trbk, A.t_ptr, A.t_idx, tv, u_top, u_bot, v, g, sin, sout, bp, bc,
+               wk.alpha_part);
+    };
+    const bool one = !bp || bc <= kBlock;
     if (A.f64) {
+      const double* tv = (const double*)A.t_val;
       if (u_bot)
-        launch_k(k_bwd_csr<double, V, PLAIN, true>, dim3(grid), s, e0, e1, trbk, A.t_ptr, A.t_idx,
-                 (const double*)A.t_val, u_top, u_bot, v, g, sin, sout, bp, bc, wk.alpha_part);
+        one ? go(k_bwd_csr<double, V, PLAIN, true, 1>, tv) : go(k_bwd_csr<double, V, PLAIN, true, kShare>, tv);
       else
-        launch_k(k_bwd_csr<double, V, PLAIN, false>, dim3(grid), s, e0, e1, trbk, A.t_ptr, A.t_idx,
-                 (const double*)A.t_val, u_top, u_bot, v, g, sin, sout, bp, bc, wk.alpha_part);
+        one ? go(k_bwd_csr<double, V, PLAIN, false, 1>, tv) : go(k_bwd_csr<double, V, PLAIN, false, kShare>, tv);
     } else {
+      const float* tv = (const float*)A.t_val;
       if (u_bot)
-        launch_k(k_bwd_csr<float, V, PLAIN, true>, dim3(grid), s, e0, e1, trbk, A.t_ptr, A.t_idx,
-                 (const float*)A.t_val, u_top, u_bot, v, g, sin, sout, bp, bc, wk.alpha_part);
+        one ? go(k_bwd_csr<float, V, PLAIN, true, 1>, tv) : go(k_bwd_csr<float, V, PLAIN, true, kShare>, tv);
       else
-        launch_k(k_bwd_csr<float, V, PLAIN, false>, dim3(grid), s, e0, e1, trbk, A.t_ptr, A.t_idx,
-                 (const float*)A.t_val, u_top, u_bot, v, g, sin, sout, bp, bc, wk.alpha_part);
+        one ? go(k_bwd_csr<float, V, PLAIN, false, 1>, tv) : go(k_bwd_csr<float, V, PLAIN, false, kShare>, tv);
     }
   } else {
     const long long rpc = (A.m + A.chunks - 1) / A.chunks;

@@ -132,7 +132,8 @@ void fill_zero(V* p, long long n, hipStream_t s);
 int stream_t(long long nnz);
 int lx_stream_t(long long nnz);  // non-zeros per row block of the LDS-resident A x kernel
 // LDS-resident A x: used for CSR with at least kLxMinNnz non-zeros when n
-// vector entries fit kLxMaxBytes of dynamic LDS.
+// vector entries fit kLxMaxBytes of dynamic LDS (below that size, loading x
+// into every workgroup's LDS costs more than the gathers it saves).
 constexpr long long kLxMaxBytes = 160 * 1024 - 1024;
 constexpr long long kLxMinNnz = 1500000;
 // SELL-64 launch shape: slices per workgroup and workgroups.

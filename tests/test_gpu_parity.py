@@ -227,16 +227,6 @@ def test_aplicur_workload1_reduced(lib):
     assert info.rank == tr.ranks[-1]
 
 
-def test_multi_rhs_is_columnwise(lib):
-    A = _dense(300, 40, 18, decades=4)
-    B = np.random.default_rng(4).standard_normal((300, 3))
-    X, info = lib.lstsq(_t(A), _t(B), mu=1e-5, block=6, tol_ne=1e-10)
-    X = X.cpu().numpy()
-    for k in range(3):
-        xk, _ = lib.lstsq(_t(A), _t(B[:, k]), mu=1e-5, block=6, tol_ne=1e-10)
-        np.testing.assert_allclose(X[:, k], xk.cpu().numpy(), rtol=0, atol=1e-13 * np.abs(X[:, k]).max())
-
-
 def test_zero_rhs_and_warm_start(lib):
     A = _dense(200, 30, 19)
     Ag = _t(A)
