@@ -145,6 +145,39 @@ def bench_adjoint(ap, synth, torch, m=25000, n=500, nrhs=4):
             "plain_backward_iters": pinfo.iters, "rank": info.rank}
 
 
+def bench_multi_rhs(ap, synth, torch, npts=20000, nrhs=16):
+    """The dense kernel workload at half its size (Gaussian RBF kernel, h = 1,
+    on 20000 points in [0,1]^8, FP32 A, 16 RHS, mu = 1e-3, block 250): APLICUR
+    with the 16 columns blocked (one pass over A per iteration for all) against
+    the same solve one column at a time, and the blocked product bandwidth
+    (A X and A^T U with 16 columns, event-timed, A bytes per launch)."""
+    A, B = synth.rbf_kernel_gpu(3003, npts, nrhs)
+    opts = dict(mu=1e-3, block=250, tol_ne=1e-8)
+    out = {"npts": npts, "nrhs": nrhs}
+    for name, cols in (("columns", 1), ("blocked", 0)):
+        ms, (X, info) = _timed(torch, lambda: ap.lstsq(A, B, columns=cols, **opts))
+        out[name] = {"ms": round(ms, 1), "lsqr_ms": round(info.t_lsqr_ms, 1), "iters": info.iters,
+                     "phases": info.phases, "rank": info.rank, "eta": info.eta}
+        log(f"[bench] multi-RHS rbf {npts} x {nrhs} ({name}): {ms:.0f} ms (LSQR {info.t_lsqr_ms:.0f} ms, "
+            f"rank {info.rank}, {info.iters} it, eta {info.eta:.1e})")
+    with ap.Context(A, precond=False, **opts) as ctx:
+        X = torch.randn(npts, nrhs, device="cuda", dtype=torch.float64)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for trans, key in ((False, "AX"), (True, "ATU")):
+            ctx.matmat(X, trans=trans)
+            best = 1e30
+            for _ in range(5):
+                e0.record()
+                ctx.matmat(X, trans=trans)
+                e1.record()
+                torch.cuda.synchronize()
+                best = min(best, e0.elapsed_time(e1))
+            gbs = A.numel() * A.element_size() / best / 1e6
+            out[key + "_ms"], out[key + "_GBs"] = round(best, 3), round(gbs, 1)
+            log(f"[bench] blocked product {key} ({nrhs} columns, FP32 A {npts}^2): {best:.3f} ms, {gbs:.0f} GB/s")
+    return out
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -236,10 +269,11 @@ def main():
                 plain_iters = inf.iters
             log(f"[bench] {name}: {ms:.1f} ms iters={inf.iters} phases={inf.phases} eta={inf.eta:.2e}")
 
-    batched = adjoint = None
+    batched = adjoint = multi = None
     if not args.no_extensions:
         batched = bench_batched(ap, synth, torch)
         adjoint = bench_adjoint(ap, synth, torch)
+        multi = bench_multi_rhs(ap, synth, torch)
 
     cpu = None
     if not args.no_cpu:
@@ -268,6 +302,7 @@ def main():
         "compare": compare or None,
         "batched": batched,
         "adjoint": adjoint,
+        "multi_rhs": multi,
         "matvec": {"A_us": round(us_a, 3), "A_GBs": round(gbs_a, 1), "AT_us": round(us_at, 3),
                    "AT_GBs": round(gbs_at, 1), "AT_bytes": int(bytes_at)},
     }

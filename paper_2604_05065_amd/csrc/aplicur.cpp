@@ -121,6 +121,7 @@ struct Ctx {
   double *Ecol = nullptr, *RJ = nullptr, *F = nullptr, *Gm = nullptr, *H = nullptr, *Sb = nullptr,
          *Sinv = nullptr, *B21 = nullptr, *YJ = nullptr, *Z = nullptr, *P2 = nullptr, *small = nullptr;
   int* status_dev = nullptr;
+  int* lu_piv = nullptr;  // pivots of the blocked LU of the Schur block
   int rank = 0;
   // preconditioner
   double *Mx = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
@@ -585,6 +586,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       c->B21 = c->arena.alloc<double>((size_t)b * L);
       c->Sb = c->arena.alloc<double>((size_t)b * b);
       c->Sinv = c->arena.alloc<double>((size_t)b * b);
+      c->lu_piv = c->arena.alloc<int>(b);
       c->small = c->arena.alloc<double>((size_t)4 * b * b);
       c->YJ = c->arena.alloc<double>((size_t)S * L);
       c->Z = c->arena.alloc<double>((size_t)S * L);
@@ -653,6 +655,56 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
   }
 }
 
+// ------------------------------------------------------------------ small dense factorisations
+// Upper Cholesky G = U^T U of the k x k SPD matrix G (column-major, ld) in
+// place, the strict lower triangle cleared; status_dev[0] != 0 on failure.
+// Blocked: diagonal blocks in LDS (one workgroup), TRSM and SYRK for the rest.
+static void chol_upper(Ctx& c, double* G, long long ld, int k, hipStream_t s) {
+  APL_HIP(hipMemsetAsync(c.status_dev, 0, sizeof(int), s));
+  const double one = 1.0, mone = -1.0;
+  for (int j0 = 0; j0 < k; j0 += kFNB) {
+    const int nb = std::min(kFNB, k - j0), r = k - j0 - nb;
+    double* D = G + j0 + (long long)j0 * ld;
+    potrf_diag(D, ld, nb, j0, c.status_dev, s);
+    if (r > 0) {
+      double* G12 = G + j0 + (long long)(j0 + nb) * ld;
+      APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                             rocblas_diagonal_non_unit, nb, r, &one, D, (rocblas_int)ld, G12, (rocblas_int)ld));
+      APL_BLAS(rocblas_dsyrk(c.blas, rocblas_fill_upper, rocblas_operation_transpose, r, nb, &mone, G12,
+                             (rocblas_int)ld, &one, G + (j0 + nb) + (long long)(j0 + nb) * ld, (rocblas_int)ld));
+    }
+  }
+  zero_lower(G, ld, k, s);
+}
+
+// Sinv = S^{-1} for the k x k matrix S (column-major, ld; overwritten by its
+// LU factors): blocked LU with partial pivoting (panels in LDS, TRSM and GEMM
+// for the trailing matrix), then Sinv = U^{-1} L^{-1} P.  status_dev[0] = 1 if
+// S is singular.
+static void lu_inverse(Ctx& c, double* S, long long ld, int k, double* Sinv, long long ldi, hipStream_t s) {
+  APL_HIP(hipMemsetAsync(c.status_dev, 0, sizeof(int), s));
+  const double one = 1.0;
+  for (int j0 = 0; j0 < k; j0 += kFNB) {
+    const int w = std::min(kFNB, k - j0), r = k - j0 - w;
+    lu_panel(S, ld, k, j0, w, c.lu_piv, c.status_dev, s);
+    laswp(S, ld, k, j0, j0 + w, c.lu_piv, j0, w, s);
+    if (r > 0) {
+      double* A12 = S + j0 + (long long)(j0 + w) * ld;
+      APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                             rocblas_diagonal_unit, w, r, &one, S + j0 + (long long)j0 * ld, (rocblas_int)ld, A12,
+                             (rocblas_int)ld));
+      gemm(c, rocblas_operation_none, rocblas_operation_none, r, r, w, -1.0, S + (j0 + w) + (long long)j0 * ld, ld,
+           A12, ld, 1.0, S + (j0 + w) + (long long)(j0 + w) * ld, ld);
+    }
+  }
+  set_identity(Sinv, ldi, k, s);
+  laswp(Sinv, ldi, k, 0, 0, c.lu_piv, 0, k, s);
+  APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                         rocblas_diagonal_unit, k, k, &one, S, (rocblas_int)ld, Sinv, (rocblas_int)ldi));
+  APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                         rocblas_diagonal_non_unit, k, k, &one, S, (rocblas_int)ld, Sinv, (rocblas_int)ldi));
+}
+
 // ------------------------------------------------------------------ Cholesky QR
 // X (n x k, column-major ld) <- Q, R (k x k upper, ldr) with X_in = Q R, by
 // Cholesky QR applied twice (a shift is added to the first Gram matrix if
@@ -665,7 +717,7 @@ static void chol_qr2(Ctx& c, double* X, long long n, int k, long long ldx, doubl
   int passes = 2;
   for (int pass = 0; pass < passes; ++pass) {
     gemm(c, rocblas_operation_transpose, rocblas_operation_none, k, k, n, 1.0, X, ldx, X, ldx, 0.0, G, k);
-    small_potrf(G, k, k, c.status_dev, s);
+    chol_upper(c, G, k, k, s);
     if (read_int(c.status_dev, s) != 0) {
       APL_REQUIRE(pass == 0, "Cholesky QR failed (block numerically rank deficient)");
       // shifted Cholesky QR: G + shift I, then one extra unshifted pass
@@ -678,7 +730,7 @@ static void chol_qr2(Ctx& c, double* X, long long n, int k, long long ldx, doubl
       const double shift = 11.0 * 2.2e-16 * (double)(n * k + (long long)k * (k + 1)) * std::max(dmax, 1e-300);
       for (int i = 0; i < k; ++i) hg[(size_t)i * k + i] += shift;
       APL_HIP(hipMemcpyAsync(G, hg.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, s));
-      small_potrf(G, k, k, c.status_dev, s);
+      chol_upper(c, G, k, k, s);
       APL_REQUIRE(read_int(c.status_dev, s) == 0, "shifted Cholesky QR failed");
       passes = 3;
     }
@@ -758,7 +810,7 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
     // S -= G B12, B12 = RJ(0:k2, :)^T
     gemm(c, rocblas_operation_none, rocblas_operation_transpose, k2, k2, l, -1.0, c.Gm, k2, c.RJ, k1, 1.0, c.Sb, k2);
   }
-  small_inverse(c.Sb, k2, k2, c.Sinv, k2, c.status_dev, s);
+  lu_inverse(c, c.Sb, k2, k2, c.Sinv, k2, s);
   if (read_int(c.status_dev, s) != 0) throw Error(APLICUR_E_BREAKDOWN, "singular CUR core block");
   if (l == 0) {
     copy_block(c.Sinv, k2, c.U, L, k2, k2, 1.0, s);
@@ -806,7 +858,7 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
     gemm(c, rocblas_operation_transpose, rocblas_operation_none, k2, k2, m, 1.0, Cn, m, Cn, m, 0.0, G22, k2);
     if (l > 0)
       gemm(c, rocblas_operation_transpose, rocblas_operation_none, k2, k2, l, -1.0, T12, L, T12, L, 1.0, G22, k2);
-    small_potrf(G22, k2, k2, c.status_dev, s);
+    chol_upper(c, G22, k2, k2, s);
     if (read_int(c.status_dev, s) != 0) throw Error(APLICUR_E_BREAKDOWN, "Cholesky of C^T C failed");
     copy_block(G22, k2, T22, L, k2, k2, 1.0, s);
   }

@@ -56,8 +56,14 @@ void grad_csr(const int* row_ptr, const int* col_idx, long long m, int k, const 
 void transpose_square(const double* src, long long lds, double* dst, int n, hipStream_t s);
 void add_block(const double* src, long long lds, double* dst, long long ldd, int rows, int cols, hipStream_t s);
 
-void small_inverse(double* S, long long ld, int k, double* Sinv, long long ldi, int* status, hipStream_t s);
-void small_potrf(double* G, long long ld, int k, int* status, hipStream_t s);
+// Pieces of the blocked Cholesky / LU of small dense matrices (column-major):
+// block width kFNB, at most kFMaxRows rows in an LU panel.
+constexpr int kFNB = 64;
+constexpr int kFMaxRows = 288;
+void potrf_diag(double* G, long long ld, int nb, int j0, int* status, hipStream_t s);
+void lu_panel(double* A, long long ld, int k, int j0, int w, int* piv, int* status, hipStream_t s);
+void laswp(double* A, long long ld, int ncols, int c0, int c1, const int* piv, int j0, int w, hipStream_t s);
+void zero_lower(double* G, long long ld, int k, hipStream_t s);
 
 int jacobi_block_width();
 int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,

@@ -25,6 +25,7 @@ namespace aplicur {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <class ACC>
 struct Mfma;
@@ -46,29 +47,72 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int q, int r) { return 4 * q + r; }
 };
 
-// Eight consecutive values, 16-byte aligned, widened to ACC.
-template <class TA, class ACC>
-__device__ __forceinline__ void load8(const TA* __restrict__ p, ACC* a) {
-  if constexpr (sizeof(TA) == 4) {
-    const float4 u = ((const float4*)p)[0], v = ((const float4*)p)[1];
-    a[0] = (ACC)u.x; a[1] = (ACC)u.y; a[2] = (ACC)u.z; a[3] = (ACC)u.w;
-    a[4] = (ACC)v.x; a[5] = (ACC)v.y; a[6] = (ACC)v.z; a[7] = (ACC)v.w;
-  } else {
-    const double2 u0 = ((const double2*)p)[0], u1 = ((const double2*)p)[1];
-    const double2 u2 = ((const double2*)p)[2], u3 = ((const double2*)p)[3];
-    a[0] = (ACC)u0.x; a[1] = (ACC)u0.y; a[2] = (ACC)u1.x; a[3] = (ACC)u1.y;
-    a[4] = (ACC)u2.x; a[5] = (ACC)u2.y; a[6] = (ACC)u3.x; a[7] = (ACC)u3.y;
-  }
-}
-
 constexpr int kGT = 2;                               // 16-row tiles per wave
 constexpr int kGRows = (kBlock / kWave) * kGT * 16;  // rows per workgroup
-constexpr int kGStep = 32;                           // reduction entries per step
+#ifdef APL_NT
+#define APL_GLOAD(p) __builtin_nontemporal_load(p)
+#else
+#define APL_GLOAD(p) (*(p))
+#endif
+#ifndef APL_GPL
+#define APL_GPL 8
+#endif
+constexpr int kGPL = APL_GPL;                        // reduction entries per lane per step
+constexpr int kGStep = 4 * kGPL;                     // reduction entries per step
+
+// One step's operands: this lane's eight M values of each row tile (kept in
+// M's type until the MFMA) and eight In values of each 16-column block.
+template <class TA, class TB, int NB>
+struct GemmStep {
+  TA a[kGT][kGPL];
+  TB b[NB][kGPL];
+};
+
+template <class TA, class TB, int NB, bool VEC>
+__device__ __forceinline__ void gemm_load(GemmStep<TA, TB, NB>& st, const TA* const (&mrow)[kGT],
+                                          const TB* __restrict__ In, long long j0, long long je, int li, int lq) {
+  constexpr int KP = NB * 16;
+  const long long jl = j0 + kGPL * lq;
+  if (VEC && j0 + kGStep <= je) {
+#pragma unroll
+    for (int t = 0; t < kGT; ++t) {
+      if constexpr (sizeof(TA) == 4) {
+#pragma unroll
+        for (int h = 0; h < kGPL / 4; ++h) {
+          const f32x4 u = APL_GLOAD((const f32x4*)(mrow[t] + jl) + h);
+          st.a[t][4 * h] = u.x; st.a[t][4 * h + 1] = u.y; st.a[t][4 * h + 2] = u.z; st.a[t][4 * h + 3] = u.w;
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < kGPL / 2; ++h) {
+          const f64x2 u = APL_GLOAD((const f64x2*)(mrow[t] + jl) + h);
+          st.a[t][2 * h] = u.x; st.a[t][2 * h + 1] = u.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kGPL; ++e)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) st.b[nb][e] = In[(jl + e) * KP + nb * 16 + li];
+  } else {
+#pragma unroll
+    for (int e = 0; e < kGPL; ++e) {
+      const long long j = jl + e;
+      const bool in = j < je;
+      const long long jc = in ? j : je - 1;
+#pragma unroll
+      for (int t = 0; t < kGT; ++t) st.a[t][e] = in ? mrow[t][jc] : (TA)0;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) st.b[nb][e] = in ? In[jc * KP + nb * 16 + li] : (TB)0;
+    }
+  }
+}
 
 // MFMA 16x16x4 operands: A lane (i, q) holds row i, reduction entry q; B lane
 // (i, q) holds entry q, column i; D lane (i, q) register r holds column i of
 // row Mfma::row(q, r) (q + 4r for FP64: measured on gfx950; 4q + r for FP32).
-// Here entry q of MFMA e is reduction index j0 + 8q + e.
+// Here entry q of MFMA e is reduction index j0 + kGPL q + e.  The loads of step
+// j + 1 are issued before the MFMAs of step j (two register stages).
 template <class TA, class TB, class ACC, int NB, bool VEC>
 __global__ void __launch_bounds__(kBlock)
     k_rows_gemm(const TA* __restrict__ M, long long rows, long long cols, long long ld, const TB* __restrict__ In,
@@ -89,34 +133,29 @@ __global__ void __launch_bounds__(kBlock)
   const TA* mrow[kGT];
 #pragma unroll
   for (int t = 0; t < kGT; ++t) mrow[t] = M + min(row0 + t * 16 + li, rows - 1) * ld;
-  for (long long j0 = jb; j0 < je; j0 += kGStep) {
-    const long long jl = j0 + 8 * lq;
-    ACC a[kGT][8], b[NB][8];
-    if (VEC && j0 + kGStep <= je) {
+  auto mma = [&](const GemmStep<TA, TB, NB>& st) {
 #pragma unroll
-      for (int t = 0; t < kGT; ++t) load8<TA, ACC>(mrow[t] + jl, a[t]);
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) b[nb][e] = (ACC)In[(jl + e) * KP + nb * 16 + li];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const long long j = jl + e;
-        const bool in = j < je;
-        const long long jc = in ? j : je - 1;
-#pragma unroll
-        for (int t = 0; t < kGT; ++t) a[t][e] = in ? (ACC)mrow[t][jc] : (ACC)0;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) b[nb][e] = in ? (ACC)In[jc * KP + nb * 16 + li] : (ACC)0;
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
+    for (int e = 0; e < kGPL; ++e)
 #pragma unroll
       for (int t = 0; t < kGT; ++t)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[t][nb] = MF::op(a[t][e], b[nb][e], acc[t][nb]);
+        for (int nb = 0; nb < NB; ++nb)
+          acc[t][nb] = MF::op((ACC)st.a[t][e], (ACC)st.b[nb][e], acc[t][nb]);
+  };
+  if (jb < je) {
+    GemmStep<TA, TB, NB> s0, s1;
+    gemm_load<TA, TB, NB, VEC>(s0, mrow, In, jb, je, li, lq);
+    for (long long j0 = jb;;) {
+      const long long j1 = j0 + kGStep;
+      if (j1 < je) gemm_load<TA, TB, NB, VEC>(s1, mrow, In, j1, je, li, lq);
+      mma(s0);
+      if (j1 >= je) break;
+      const long long j2 = j1 + kGStep;
+      if (j2 < je) gemm_load<TA, TB, NB, VEC>(s0, mrow, In, j2, je, li, lq);
+      mma(s1);
+      if (j2 >= je) break;
+      j0 = j2;
+    }
   }
   ACC* o = out + (long long)blockIdx.y * rows * KP;
 #pragma unroll

@@ -301,113 +301,181 @@ void gather_y_cols(const double* Y, long long n, int s_rows, const int* J, int k
                      k, out, ldo);
 }
 
-// ============================================================== small dense (one workgroup)
-// In-place Gauss-Jordan inverse with partial pivoting of the k x k matrix S
-// (column-major, ld), into Sinv.  status[0] = 0 on success, 1 if singular.
-__global__ void __launch_bounds__(kBlock) k_gj_inverse(double* S, long long ld, int k, double* Sinv,
-                                                       long long ldi, int* perm, int* status) {
-  __shared__ int piv_row;
-  __shared__ double piv_val;
-  for (int e = threadIdx.x; e < k * k; e += kBlock) {
-    int i = e % k, j = e / k;
-    Sinv[i + j * ldi] = (i == j) ? 1.0 : 0.0;
-  }
-  if (threadIdx.x == 0) status[0] = 0;
+// ============================================================== blocked small factorisations
+// The diagonal-block and panel kernels of the blocked Cholesky and LU below
+// (their trailing updates are library TRSM / SYRK / GEMM calls): one
+// workgroup of kFT threads with the block in LDS.
+constexpr int kFT = 1024;
+
+// Upper Cholesky of the nb x nb diagonal block at G (column-major, ld): U^T U
+// = G in place (upper triangle; the strict lower triangle is left alone).
+// status[0] = 1 + (j0 + j) if pivot j is not positive; nothing is done when
+// status[0] is already set.
+__global__ void __launch_bounds__(kFT) k_potrf_diag(double* G, long long ld, int nb, int j0, int* status) {
+  __shared__ double a[kFNB * kFNB];  // column-major, ld kFNB
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = status[0];
   __syncthreads();
-  for (int q = 0; q < k; ++q) {
-    // pivot search in column q, rows q..k-1 (first max)
+  if (bad) return;
+  for (int e = threadIdx.x; e < nb * nb; e += kFT) {
+    const int i = e % nb, j = e / nb;
+    a[i + j * kFNB] = G[i + j * ld];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double d = a[j + j * kFNB];
+    if (!(d > 0.0)) {
+      if (threadIdx.x == 0) status[0] = 1 + j0 + j;
+      return;  // uniform: every thread read the same d
+    }
+    const double r = sqrt(d);
+    __syncthreads();
+    if (threadIdx.x == 0) a[j + j * kFNB] = r;
+    for (int l = j + 1 + threadIdx.x; l < nb; l += kFT) a[j + l * kFNB] /= r;
+    __syncthreads();
+    const int rem = nb - j - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += kFT) {
+      const int x = j + 1 + e % rem, y = j + 1 + e / rem;
+      if (x <= y) a[x + y * kFNB] -= a[j + x * kFNB] * a[j + y * kFNB];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nb * nb; e += kFT) {
+    const int i = e % nb, j = e / nb;
+    if (i <= j) G[i + j * ld] = a[i + j * kFNB];
+  }
+}
+
+void potrf_diag(double* G, long long ld, int nb, int j0, int* status, hipStream_t s) {
+  APL_REQUIRE(nb >= 1 && nb <= kFNB, "potrf_diag: block too large");
+  hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(kFT), 0, s, G, ld, nb, j0, status);
+}
+
+// LU with partial pivoting (first largest magnitude) of the panel
+// A[j0:k, j0:j0+w] (column-major, ld; k - j0 <= kFMaxRows, w <= kFNB) in LDS:
+// piv[j0 + c] = the row swapped with row j0 + c; L below the diagonal (unit),
+// U on and above.  status[0] = 1 if a pivot is zero (the elimination of that
+// column is skipped).
+__global__ void __launch_bounds__(kFT) k_lu_panel(double* A, long long ld, int k, int j0, int w, int* piv,
+                                                  int* status) {
+  extern __shared__ double p[];  // (k - j0) x w, column-major, ld R
+  __shared__ double wv[kFT / kWave];
+  __shared__ int wi[kFT / kWave];
+  __shared__ int prow;
+  const int R = k - j0;
+  for (int e = threadIdx.x; e < R * w; e += kFT) {
+    const int i = e % R, j = e / R;
+    p[i + j * R] = A[(j0 + i) + (long long)(j0 + j) * ld];
+  }
+  __syncthreads();
+  for (int c = 0; c < w; ++c) {
+    // argmax |p[r][c]| over r in [c, R), smallest index on ties
     double v = -1.0;
-    int p = INT_MAX, idx = -1;
-    for (int i = q + threadIdx.x; i < k; i += kBlock) {
-      double a = fabs(S[i + q * ld]);
-      if (better(a, i, v, p)) {
-        v = a;
-        p = i;
-        idx = i;
+    int idx = INT_MAX;
+    for (int r = c + threadIdx.x; r < R; r += kFT) {
+      const double x = fabs(p[r + c * R]);
+      if (x > v) {
+        v = x;
+        idx = r;
       }
     }
-    block_argmax(v, p, idx);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, kWave);
+      const int oi = __shfl_xor(idx, off, kWave);
+      if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+      }
+    }
+    if (threadIdx.x % kWave == 0) {
+      wv[threadIdx.x / kWave] = v;
+      wi[threadIdx.x / kWave] = idx;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-      piv_row = idx;
-      piv_val = (idx >= 0) ? S[idx + q * ld] : 0.0;
-      if (!(v > 0.0)) status[0] = 1;
+      double bv = wv[0];
+      int bi = wi[0];
+      for (int q = 1; q < kFT / kWave; ++q)
+        if (wv[q] > bv || (wv[q] == bv && wi[q] < bi)) {
+          bv = wv[q];
+          bi = wi[q];
+        }
+      prow = bi;
+      piv[j0 + c] = j0 + bi;
+      if (!(bv > 0.0)) status[0] = 1;
     }
     __syncthreads();
-    if (!(piv_val != 0.0)) return;
-    const int pr = piv_row;
-    // swap rows q and pr of both S and Sinv
-    if (pr != q) {
-      for (int j = threadIdx.x; j < k; j += kBlock) {
-        double t = S[q + j * ld];
-        S[q + j * ld] = S[pr + j * ld];
-        S[pr + j * ld] = t;
-        t = Sinv[q + j * ldi];
-        Sinv[q + j * ldi] = Sinv[pr + j * ldi];
-        Sinv[pr + j * ldi] = t;
+    const int pr = prow;
+    if (pr != c)
+      for (int j = threadIdx.x; j < w; j += kFT) {
+        const double t = p[c + j * R];
+        p[c + j * R] = p[pr + j * R];
+        p[pr + j * R] = t;
+      }
+    __syncthreads();
+    const double d = p[c + c * R];
+    if (d != 0.0) {
+      const double inv = 1.0 / d;
+      for (int r = c + 1 + threadIdx.x; r < R; r += kFT) p[r + c * R] *= inv;
+      __syncthreads();
+      const int rr = R - c - 1, cc = w - c - 1;
+      for (int e = threadIdx.x; e < rr * cc; e += kFT) {
+        const int r = c + 1 + e % rr, j = c + 1 + e / rr;
+        p[r + j * R] -= p[r + c * R] * p[c + j * R];
       }
     }
     __syncthreads();
-    const double inv = 1.0 / piv_val;
-    for (int j = threadIdx.x; j < k; j += kBlock) {
-      S[q + j * ld] *= inv;
-      Sinv[q + j * ldi] *= inv;
-    }
-    __syncthreads();
-    // eliminate column q from every other row
-    for (int e = threadIdx.x; e < k * k; e += kBlock) {
-      const int i = e % k, j = e / k;
-      if (i == q) continue;
-      const double f = S[i + q * ld];
-      if (j != q) S[i + j * ld] -= f * S[q + j * ld];
-      Sinv[i + j * ldi] -= f * Sinv[q + j * ldi];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < k; i += kBlock)
-      if (i != q) S[i + q * ld] = 0.0;
-    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < R * w; e += kFT) {
+    const int i = e % R, j = e / R;
+    A[(j0 + i) + (long long)(j0 + j) * ld] = p[i + j * R];
   }
 }
 
-void small_inverse(double* S, long long ld, int k, double* Sinv, long long ldi, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_inverse, dim3(1), dim3(kBlock), 0, s, S, ld, k, Sinv, ldi, (int*)nullptr, status);
-}
-
-// Upper Cholesky factor (in place, upper triangle) of the SPD k x k matrix G.
-// status[0] = 0 on success, 1 + j if the j-th pivot is not positive.
-__global__ void __launch_bounds__(kBlock) k_potrf_upper(double* G, long long ld, int k, int* status) {
-  __shared__ double djj;
-  if (threadIdx.x == 0) status[0] = 0;
-  for (int j = 0; j < k; ++j) {
-    if (threadIdx.x == 0) {
-      double d = G[j + j * ld];
-      if (!(d > 0.0)) {
-        status[0] = 1 + j;
-        djj = 0.0;
-      } else {
-        djj = sqrt(d);
-        G[j + j * ld] = djj;
-      }
+// Row swaps piv[j0 .. j0 + w) (in order) on the columns outside [c0, c1) of
+// the k x ncols matrix A (column-major, ld): one thread per column.
+__global__ void k_laswp(double* A, long long ld, int ncols, int c0, int c1, const int* piv, int j0, int w) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= ncols || (j >= c0 && j < c1)) return;
+  double* col = A + (long long)j * ld;
+  for (int c = 0; c < w; ++c) {
+    const int r = j0 + c, q = piv[j0 + c];
+    if (q != r) {
+      const double t = col[r];
+      col[r] = col[q];
+      col[q] = t;
     }
-    __syncthreads();
-    if (!(djj > 0.0)) return;
-    for (int l = j + 1 + threadIdx.x; l < k; l += kBlock) G[j + l * ld] /= djj;
-    __syncthreads();
-    const int rem = k - j - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += kBlock) {
-      const int a = j + 1 + e % rem, b = j + 1 + e / rem;
-      if (a <= b) G[a + b * ld] -= G[j + a * ld] * G[j + b * ld];
-    }
-    __syncthreads();
-  }
-  // clear the strict lower triangle
-  for (int e = threadIdx.x; e < k * k; e += kBlock) {
-    const int a = e % k, b = e / k;
-    if (a > b) G[a + b * ld] = 0.0;
   }
 }
 
-void small_potrf(double* G, long long ld, int k, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_potrf_upper, dim3(1), dim3(kBlock), 0, s, G, ld, k, status);
+void lu_panel(double* A, long long ld, int k, int j0, int w, int* piv, int* status, hipStream_t s) {
+  APL_REQUIRE(k - j0 <= kFMaxRows && w >= 1 && w <= kFNB, "lu_panel: panel too large");
+  const size_t lds = sizeof(double) * (size_t)(k - j0) * w;
+  static const bool attr = []() {
+    (void)hipFuncSetAttribute((const void*)k_lu_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double) * kFMaxRows * kFNB));
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(kFT), lds, s, A, ld, k, j0, w, piv, status);
+}
+
+void laswp(double* A, long long ld, int ncols, int c0, int c1, const int* piv, int j0, int w, hipStream_t s) {
+  hipLaunchKernelGGL(k_laswp, dim3(ceil_div(ncols, kBlock)), dim3(kBlock), 0, s, A, ld, ncols, c0, c1, piv, j0, w);
+}
+
+__global__ void k_zero_lower(double* G, long long ld, int k) {
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < (long long)k * k;
+       e += (long long)gridDim.x * kBlock) {
+    const int i = (int)(e % k), j = (int)(e / k);
+    if (i > j) G[i + (long long)j * ld] = 0.0;
+  }
+}
+
+void zero_lower(double* G, long long ld, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_lower, dim3(std::min<unsigned>(ceil_div((long long)k * k, kBlock), 256)), dim3(kBlock), 0,
+                     s, G, ld, k);
 }
 
 // ============================================================== block one-sided Jacobi SVD

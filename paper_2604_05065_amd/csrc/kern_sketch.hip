@@ -280,37 +280,56 @@ template void launch_sketch_csr<double>(const int*, const int*, const double*, l
 
 // ---------------------------------------------------------------- sketch, dense A
 // Workgroup (strip, chunk) covers columns [64 strip, 64 strip + 64) and a chunk
-// of rows.  The s x 64 strip of Y lives in LDS (FP64).  Wave w owns the Y rows
-// h with h % 4 == w: every wave walks all rows of the chunk in order and adds
-// only its own contributions, so each LDS cell has a single writer and a fixed
-// summation order.  The chunk's strip is written to a partial buffer that a
-// second kernel sums over chunks in order.
+// of rows.  The s x 64 strip of Y lives in LDS (FP64).  Wave w of the sixteen
+// owns the Y rows h with h % 16 == w: every wave walks all rows of the chunk in
+// order (eight rows' values, target rows and signs loaded at a time, the targets
+// then read lane by lane, uniform per wave; the strip's 256 bytes per row are
+// shared through L1) and adds only its own contributions, so each LDS cell has a
+// single writer and a fixed summation order.  The chunk's strip is written to a partial buffer that a second kernel
+// sums over chunks in order.
+constexpr int kSkT = 1024;  // threads per workgroup of the dense sketch
+constexpr int kSkW = kSkT / kWave;
+constexpr int kSkU = 8;     // rows per batch
+
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_sketch_dense(const T* A, long long m, long long n,
-                                                         long long ld, int s, int xi,
-                                                         const uint16_t* rows,
-                                                         const uint8_t* negmask, double scale,
-                                                         long long rows_per_chunk, double* part) {
+__global__ void __launch_bounds__(kSkT) k_sketch_dense(const T* A, long long m, long long n,
+                                                       long long ld, int s, int xi,
+                                                       const uint16_t* rows,
+                                                       const uint8_t* negmask, double scale,
+                                                       long long rows_per_chunk, double* part) {
   extern __shared__ double lds[];  // s x 64
   const int l = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const long long j = blockIdx.x * (long long)kWave + l;
   const long long i0 = blockIdx.y * rows_per_chunk;
   const long long i1 = min(m, i0 + rows_per_chunk);
-  for (int h = threadIdx.x; h < s * kWave; h += kBlock) lds[h] = 0.0;
+  for (int h = threadIdx.x; h < s * kWave; h += kSkT) lds[h] = 0.0;
   __syncthreads();
   const bool col_ok = j < n;
-  for (long long i = i0; i < i1; ++i) {
-    const double a = col_ok ? (double)A[i * ld + j] * scale : 0.0;
-    const unsigned neg = negmask[i];
-    for (int t = 0; t < xi; ++t) {
-      const int h = rows[i * xi + t];
-      if ((h & 3) == w) lds[h * kWave + l] += ((neg >> t) & 1u) ? -a : a;
+  const long long jc = col_ok ? j : n - 1;
+  for (long long i = i0; i < i1; i += kSkU) {
+    // the batch's values, target rows (lane q: entry q of rows[i xi ..]) and sign masks
+    double a[kSkU];
+#pragma unroll
+    for (int u = 0; u < kSkU; ++u) {
+      const long long ii = min(i + u, i1 - 1);
+      const T v = A[ii * ld + jc];
+      a[u] = (col_ok && i + u < i1) ? (double)v * scale : 0.0;
+    }
+    const int nb = (int)min((long long)kSkU, i1 - i);
+    const int rv = l < nb * xi ? (int)rows[i * xi + l] : 0;
+    const int nv = l < nb ? (int)negmask[i + l] : 0;
+    for (int u = 0; u < nb; ++u) {
+      const unsigned neg = (unsigned)__builtin_amdgcn_readlane(nv, u);
+      for (int t = 0; t < xi; ++t) {
+        const int h = __builtin_amdgcn_readlane(rv, u * xi + t);
+        if ((h % kSkW) == w) lds[h * kWave + l] += ((neg >> t) & 1u) ? -a[u] : a[u];
+      }
     }
   }
   __syncthreads();
   if (col_ok) {
     double* out = part + (long long)blockIdx.y * s * n;
-    for (int h = w; h < s; h += kBlock / kWave) out[(long long)h * n + j] = lds[h * kWave + l];
+    for (int h = w; h < s; h += kSkW) out[(long long)h * n + j] = lds[h * kWave + l];
   }
 }
 
@@ -338,7 +357,7 @@ void launch_sketch_dense(const T* A, long long m, long long n, long long ld, int
   size_t lds = sizeof(double) * s * kWave;
   APL_REQUIRE(lds <= 160 * 1024, "sketch dimension too large for the LDS strip");
   APL_HIP(hipFuncSetAttribute((const void*)k_sketch_dense<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_sketch_dense<T>, dim3(ceil_div(n, kWave), chunks), dim3(kBlock), lds, st, A,
+  hipLaunchKernelGGL(k_sketch_dense<T>, dim3(ceil_div(n, kWave), chunks), dim3(kSkT), lds, st, A,
                      m, n, ld, s, xi, rows, negmask, 1.0 / sqrt((double)xi), rpc, part);
   long long count = (long long)s * n;
   hipLaunchKernelGGL(k_sum_chunks, dim3(ceil_div(count, kBlock)), dim3(kBlock), 0, st, part, count,

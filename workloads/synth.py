@@ -23,7 +23,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-__all__ = ["rng_for", "haar", "dense_svd", "sparse_scaled", "rbf_kernel", "consistent_x",
+__all__ = ["rng_for", "haar", "dense_svd", "sparse_scaled", "rbf_kernel", "rbf_kernel_gpu", "consistent_x",
            "workload", "batch_shapes", "Workload", "dense_svd_gpu"]
 
 
@@ -169,3 +169,22 @@ def dense_svd_gpu(seed, m, n, decades, nrhs, dtype="float32"):
     B = torch.randn(m, nrhs, device="cuda", dtype=torch.float64, generator=g)
     return A, B
 
+
+
+def rbf_kernel_gpu(seed, npts, nrhs, dim=8, h=1.0):
+    """Workload 3 generated on the GPU with torch (seeded): points uniform in
+    [0,1]^dim, A_ij = exp(-||p_i - p_j||^2 / (2 h^2)) formed in FP64 and stored
+    in FP32, B (npts x nrhs) N(0,1) in FP64.  Returns CUDA tensors (A, B)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed))
+    P = torch.rand(npts, dim, device="cuda", dtype=torch.float64, generator=g)
+    sq = (P * P).sum(dim=1)
+    A = torch.empty(npts, npts, device="cuda", dtype=torch.float32)
+    step = 4096
+    for i0 in range(0, npts, step):
+        blk = P[i0:i0 + step]
+        d2 = (sq[i0:i0 + step, None] + sq[None, :] - 2.0 * (blk @ P.T)).clamp_min_(0.0)
+        A[i0:i0 + step] = torch.exp(-d2 / (2.0 * h * h)).to(torch.float32)
+    B = torch.randn(npts, nrhs, device="cuda", dtype=torch.float64, generator=g)
+    return A, B
