@@ -82,6 +82,8 @@ struct Arena {
   }
 };
 
+constexpr int kLuppNB = 32;  // pivots per panel of the blocked LU pivot search
+
 // Buffers of the blocked path (several right-hand sides of a dense A),
 // allocated on first use for kp columns.
 struct Blk {
@@ -641,6 +643,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       c->fw.pp = c->arena.alloc<int>(2048);
       c->fw.pi = c->arena.alloc<int>(2048);
       c->fw.lupp_state = c->arena.alloc<int>(4);
+      c->fw.lupp_g = c->arena.alloc<double>((size_t)kLuppNB * (std::max(c->s, b) + 8));
       c->fw.counter = c->counter + 1;
       fill(c->TR, (long long)L * L, 0.0, s);
       fill(c->TC, (long long)L * L, 0.0, s);
@@ -652,6 +655,31 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
   } catch (...) {
     delete c;
     throw;
+  }
+}
+
+// ------------------------------------------------------------------ LU pivots (Alg. 7)
+// First k partial-pivoting pivots of X (r x cols, column-major, ld), panel by
+// panel: within a panel of kLuppNB pivots the steps eliminate only the panel's
+// columns; the trailing columns are then updated at once (U12 = L11^{-1} A12 on
+// the panel's pivot rows, X(:, trail) -= X(:, panel) U12), which is the same
+// elimination in another summation order.  Pivot rows are never read again, so
+// the update runs over all rows.
+static void lupp_blocked(Ctx& c, double* X, int r, int cols, long long ld, int k, int* piv, hipStream_t s) {
+  const double one = 1.0;
+  lupp_begin(X, r, k, c.fw, s);
+  for (int q0 = 0; q0 < k; q0 += kLuppNB) {
+    const int qe = std::min(q0 + kLuppNB, k);
+    for (int q = q0; q < qe; ++q) lupp_step(X, r, cols, qe, ld, q, k, piv, c.fw, s);
+    if (qe >= k || qe >= cols) break;
+    const int nb = qe - q0, w = cols - q0;
+    double* G = c.fw.lupp_g;
+    lupp_gather(X, r, ld, piv, q0, nb, w, G, s);
+    APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                           rocblas_diagonal_unit, nb, cols - qe, &one, G, nb, G + (size_t)nb * nb, nb));
+    gemm(c, rocblas_operation_none, rocblas_operation_none, r, cols - qe, nb, -1.0, X + (long long)q0 * ld, ld,
+         G + (size_t)nb * nb, nb, 1.0, X + (long long)qe * ld, ld);
+    lupp_cand(X, r, ld, qe, c.fw, s);
   }
 }
 
@@ -765,7 +793,7 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
   }
   // (i)-(ii) column pivots from the sketched residual (E_row^T = E as n x s column-major)
   if (l > 0) zero_rows(c.E, n, c.J_dev, l, S, s);
-  lupp_pivots(c.E, (int)n, S, n, beff, c.Jp, c.fw, s);
+  lupp_blocked(c, c.E, (int)n, S, n, beff, c.Jp, s);
   const int k1 = lupp_read_keff(c.fw, s);
   if (k1 == 0) {
     res.exhausted = true;
@@ -783,7 +811,7 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
     zero_rows(c.Ecol, m, c.I_dev, l, k1, s);
   }
   // (iv) row pivots of E_col
-  lupp_pivots(c.Ecol, (int)m, k1, m, k1, c.Ip, c.fw, s);
+  lupp_blocked(c, c.Ecol, (int)m, k1, m, k1, c.Ip, s);
   const int k2 = lupp_read_keff(c.fw, s);
   if (k2 < beff) res.exhausted = true;
   if (k2 == 0) {

@@ -18,6 +18,7 @@ struct FactorWork {
   int *pp, *pi;
   void* lupp_state;
   unsigned* counter;
+  double* lupp_g;  // pivot rows of a panel, kLuppNB x (sketch columns)
 };
 
 // First k partial-pivoting pivots of the column-major r x c matrix X (X is
@@ -25,6 +26,17 @@ struct FactorWork {
 // lupp_read_keff (synchronises the stream).
 void lupp_pivots(double* X, int r, int c, long long ld, int k, int* piv, FactorWork& fw, hipStream_t s);
 int lupp_read_keff(FactorWork& fw, hipStream_t s);
+// Pieces of the same pivot sequence computed panel by panel (the host then
+// updates the trailing columns with a TRSM and a GEMM): lupp_begin (candidates
+// of column 0), lupp_step (pivot q; eliminates columns up to cend), lupp_cand
+// (candidates of column col after the trailing update), lupp_gather (the
+// panel's pivot rows, G = X(piv[q0..q0+nb), q0..q0+w), column-major nb x w).
+void lupp_begin(double* X, int r, int k, FactorWork& fw, hipStream_t s);
+void lupp_step(double* X, int r, int c, int cend, long long ld, int q, int k, int* piv, FactorWork& fw,
+               hipStream_t s);
+void lupp_cand(const double* X, int r, long long ld, int col, FactorWork& fw, hipStream_t s);
+void lupp_gather(const double* X, int r, long long ld, const int* piv, int q0, int nb, int w, double* G,
+                 hipStream_t s);
 
 void gather_cols(const AMat& A, const int* J, int k, double* out, long long ld_out, hipStream_t s);
 void gather_rows(const AMat& A, const int* I, int k, double* out, long long ld_out, hipStream_t s);

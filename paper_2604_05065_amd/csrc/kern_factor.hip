@@ -90,10 +90,16 @@ __global__ void __launch_bounds__(kBlock) k_lupp_init(const double* X, int r, in
   }
 }
 
+// One pivot step: the global best of the previous candidates is the pivot
+// (original row p) of position q; positions are updated as if the rows were
+// swapped (LAPACK order); the multipliers of the remaining rows are stored in
+// column q and columns q + 1 .. cend - 1 are eliminated; candidates for column
+// q + 1 are produced when q + 1 < cend (otherwise k_lupp_cand makes them after
+// the trailing update of a blocked factorisation).
 __global__ void __launch_bounds__(kBlock)
-    k_lupp_step(double* X, int r, int c, long long ld, int q, int k, const int* pos_cur, const int* row_cur,
-                int* pos_nxt, int* row_nxt, int* piv, LuppState* ls, const double* pv_in, const int* pp_in,
-                const int* pi_in, double* pv_out, int* pp_out, int* pi_out) {
+    k_lupp_step(double* X, int r, int c, int cend, long long ld, int q, int k, const int* pos_cur,
+                const int* row_cur, int* pos_nxt, int* row_nxt, int* piv, LuppState* ls, const double* pv_in,
+                const int* pp_in, const int* pi_in, double* pv_out, int* pp_out, int* pi_out) {
   if (ls->stop) return;
   double vmax;
   int p;
@@ -124,14 +130,17 @@ __global__ void __launch_bounds__(kBlock)
     if (pn <= q) continue;  // pivot rows (positions 0..q) are not updated
     const double l = X[i + q * ld] / piv_val;
     X[i + q * ld] = l;
-    for (int j = q + 1; j < c; ++j) X[i + j * ld] -= l * X[p + j * ld];
-    const double a = fabs(X[i + (q + 1) * ld]);
-    if (better(a, pn, v, bp)) {
-      v = a;
-      bp = pn;
-      idx = i;
+    for (int j = q + 1; j < cend; ++j) X[i + j * ld] -= l * X[p + j * ld];
+    if (q + 1 < cend) {
+      const double a = fabs(X[i + (q + 1) * ld]);
+      if (better(a, pn, v, bp)) {
+        v = a;
+        bp = pn;
+        idx = i;
+      }
     }
   }
+  if (q + 1 >= cend) return;  // uniform
   block_argmax(v, bp, idx);
   if (threadIdx.x == 0) {
     pv_out[blockIdx.x] = v;
@@ -140,23 +149,82 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-void lupp_pivots(double* X, int r, int c, long long ld, int k, int* piv, FactorWork& fw, hipStream_t s) {
+// Candidates for the pivot of column col among the rows at positions >= col.
+__global__ void __launch_bounds__(kBlock) k_lupp_cand(const double* X, int r, long long ld, int col, const int* pos,
+                                                      const LuppState* ls, double* pv, int* pp, int* pi) {
+  if (ls->stop) return;
+  double v = -1.0;
+  int bp = INT_MAX, idx = -1;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < r; i += gridDim.x * kBlock) {
+    const int pn = pos[i];
+    if (pn < col) continue;
+    const double a = fabs(X[i + col * ld]);
+    if (better(a, pn, v, bp)) {
+      v = a;
+      bp = pn;
+      idx = i;
+    }
+  }
+  block_argmax(v, bp, idx);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = v;
+    pp[blockIdx.x] = bp;
+    pi[blockIdx.x] = idx;
+  }
+}
+
+// G (nb x w, column-major) = X(piv[q0 .. q0 + nb), q0 .. q0 + w) (row indices clamped into range).
+__global__ void k_lupp_gather(const double* X, int r, long long ld, const int* piv, int q0, int nb, int w,
+                              double* G) {
+  for (int e = blockIdx.x * kBlock + threadIdx.x; e < nb * w; e += gridDim.x * kBlock) {
+    const int qq = e % nb, j = e / nb;
+    int p = piv[q0 + qq];
+    p = (p < 0 || p >= r) ? 0 : p;
+    G[e] = X[p + (long long)(q0 + j) * ld];
+  }
+}
+
+static int lupp_grid(int r) { return std::min((r + kBlock - 1) / kBlock, 1024); }
+
+void lupp_begin(double* X, int r, int k, FactorWork& fw, hipStream_t s) {
   APL_REQUIRE(r <= fw.lupp_rows, "lupp: workspace rows too small");
-  int grid = (r + kBlock - 1) / kBlock;
-  if (grid > 1024) grid = 1024;
   LuppState* ls = (LuppState*)fw.lupp_state;
-  // two buffers each for pos/row_at and for the candidates
+  hipLaunchKernelGGL(k_lupp_init, dim3(lupp_grid(r)), dim3(kBlock), 0, s, X, r, k, fw.pos, fw.row_at, ls, fw.pv,
+                     fw.pp, fw.pi);
+}
+
+// Buffers of step q: positions / rows and candidates are double-buffered by q % 2.
+void lupp_step(double* X, int r, int c, int cend, long long ld, int q, int k, int* piv, FactorWork& fw,
+               hipStream_t s) {
+  const int a = q & 1, b = a ^ 1;
   int* pos[2] = {fw.pos, fw.pos + r};
   int* row[2] = {fw.row_at, fw.row_at + r};
   double* pv[2] = {fw.pv, fw.pv + 1024};
   int* pp[2] = {fw.pp, fw.pp + 1024};
   int* pi[2] = {fw.pi, fw.pi + 1024};
-  hipLaunchKernelGGL(k_lupp_init, dim3(grid), dim3(kBlock), 0, s, X, r, k, pos[0], row[0], ls, pv[0], pp[0], pi[0]);
-  for (int q = 0; q < k; ++q) {
-    const int a = q & 1, b = a ^ 1;
-    hipLaunchKernelGGL(k_lupp_step, dim3(grid), dim3(kBlock), 0, s, X, r, c, ld, q, k, pos[a], row[a], pos[b],
-                       row[b], piv, ls, pv[a], pp[a], pi[a], pv[b], pp[b], pi[b]);
-  }
+  hipLaunchKernelGGL(k_lupp_step, dim3(lupp_grid(r)), dim3(kBlock), 0, s, X, r, c, cend, ld, q, k, pos[a], row[a],
+                     pos[b], row[b], piv, (LuppState*)fw.lupp_state, pv[a], pp[a], pi[a], pv[b], pp[b], pi[b]);
+}
+
+void lupp_cand(const double* X, int r, long long ld, int col, FactorWork& fw, hipStream_t s) {
+  const int a = col & 1;
+  int* pos = a ? fw.pos + r : fw.pos;
+  double* pv = fw.pv + (a ? 1024 : 0);
+  int* pp = fw.pp + (a ? 1024 : 0);
+  int* pi = fw.pi + (a ? 1024 : 0);
+  hipLaunchKernelGGL(k_lupp_cand, dim3(lupp_grid(r)), dim3(kBlock), 0, s, X, r, ld, col, (const int*)pos,
+                     (const LuppState*)fw.lupp_state, pv, pp, pi);
+}
+
+void lupp_gather(const double* X, int r, long long ld, const int* piv, int q0, int nb, int w, double* G,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_lupp_gather, dim3(std::min<unsigned>(ceil_div((long long)nb * w, kBlock), 256)), dim3(kBlock),
+                     0, s, X, r, ld, piv, q0, nb, w, G);
+}
+
+void lupp_pivots(double* X, int r, int c, long long ld, int k, int* piv, FactorWork& fw, hipStream_t s) {
+  lupp_begin(X, r, k, fw, s);
+  for (int q = 0; q < k; ++q) lupp_step(X, r, c, c, ld, q, k, piv, fw, s);
 }
 
 int lupp_read_keff(FactorWork& fw, hipStream_t s) {
@@ -478,10 +546,12 @@ void zero_lower(double* G, long long ld, int k, hipStream_t s) {
                      s, G, ld, k);
 }
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
 // ============================================================== block one-sided Jacobi SVD
 // X (rows x ncols, column-major) is orthogonalised column-block-pair by
-// column-block-pair: for the pair of width 2*kJW, the Gram matrix is formed,
-// diagonalised by cyclic Jacobi in LDS, and the rotation applied to the
+// column-block-pair: for the pair of width 2*kJW, the Gram matrix is formed
+// (FP64 MFMA), diagonalised by cyclic Jacobi in LDS, and the rotation applied to the
 // columns of X and of V.  Round-robin pairing covers every block pair once
 // per sweep (Hestenes' method, block form).  sweepmax receives the largest
 // relative off-diagonal |g_pq| / sqrt(g_pp g_qq) seen in the round.  Each
@@ -492,8 +562,8 @@ constexpr int kJW = 8;        // columns per block
 constexpr int kJP = 2 * kJW;  // columns per pair
 constexpr int kJInner = 1;    // inner sweeps per pair and round
 constexpr int kJT = 512;      // threads per pair
-constexpr int kJR = 64;       // rows per Gram tile
-constexpr int kJGE = (kJP * kJP + kJT - 1) / kJT;  // Gram entries per thread
+constexpr int kJR = (kJT / kWave) * 16;  // rows of the LDS buffer for the waves' partial Grams
+static_assert(kJP == 16, "the pair Gram uses one 16x16 MFMA tile");
 
 __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, int& b) {
   // circle method: block nblk-1 fixed, the others rotate
@@ -514,77 +584,79 @@ __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, i
 __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, int rows, double* Vm,
                                                          long long ldv, int vrows, int nblk, int round,
                                                          unsigned long long* offmax, double skip) {
-  __shared__ double G[kJP][kJP + 1];
-  __shared__ double Q[kJP][kJP + 1];
+  __shared__ double G[2][kJP][kJP + 1];  // double-buffered rotations
+  __shared__ double Q[2][kJP][kJP + 1];
   __shared__ double tile[kJR][kJP + 1];
-  __shared__ double cs[kJW], sn[kJW];
-  __shared__ int pp_[kJW], qq_[kJW];
-  __shared__ double block_off;
+  __shared__ double cs[kJP], sn[kJP];    // per index: its pair's rotation
+  __shared__ int mate[kJP], lowr[kJP];   // partner index; 1 if the index is the pair's p
+  __shared__ double wmax[kJT / kWave];
   int a, b;
   pair_of(round, nblk, blockIdx.x, a, b);
   int col[2] = {a * kJW, b * kJW};
   const int tid = threadIdx.x;
-  // 1) Gram matrix of the 2*kJW columns
-  double acc[kJGE];
-#pragma unroll
-  for (int t = 0; t < kJGE; ++t) acc[t] = 0.0;
-  for (int r0 = 0; r0 < rows; r0 += kJR) {
-    for (int e = tid; e < kJR * kJP; e += kJT) {
-      const int rr = e % kJR, cc = e / kJR;
-      const int gc = col[cc / kJW] + (cc % kJW);
-      tile[rr][cc] = (r0 + rr < rows) ? X[(long long)(r0 + rr) + (long long)gc * ldx] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < kJGE; ++t) {
-      const int e = tid + t * kJT;
-      if (e < kJP * kJP) {
-        const int i = e % kJP, j = e / kJP;
-        double s = 0.0;
-        for (int rr = 0; rr < kJR; ++rr) s += tile[rr][i] * tile[rr][j];
-        acc[t] += s;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int t = 0; t < kJGE; ++t) {
-    const int e = tid + t * kJT;
-    if (e < kJP * kJP) G[e % kJP][e / kJP] = acc[t];
-  }
-  for (int e = tid; e < kJP * kJP; e += kJT) Q[e % kJP][e / kJP] = (e % kJP == e / kJP) ? 1.0 : 0.0;
-  if (tid == 0) block_off = 0.0;
-  __syncthreads();
-  // measure off-diagonality of the pair
+  const int wave = tid / kWave, lane = tid % kWave;
+  // 1) Gram matrix of the 2*kJW = 16 columns on the FP64 16x16x4 MFMA: the
+  //    A and B operands are the same values (lane (i, q) holds column i at the
+  //    step's rows 4q + e, e < 4); wave w takes the 16-row steps w, w + 8, ...,
+  //    four steps' loads at a time, and the waves' partial Grams are summed in
+  //    order through LDS.
   {
-    double mx = 0.0;
-    for (int e = tid; e < kJP * kJP; e += kJT) {
-      const int i = e % kJP, j = e / kJP;
-      if (i < j) {
-        const double d = sqrt(G[i][i] * G[j][j]);
-        if (d > 0.0) mx = fmax(mx, fabs(G[i][j]) / d);
-      }
+    const int li = lane % 16, lq = lane / 16;
+    const double* xc = X + (long long)(col[li / kJW] + li % kJW) * ldx;
+    f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+    constexpr int kStep = (kJT / kWave) * 16;
+    for (int r0 = wave * 16; r0 < rows; r0 += 4 * kStep) {
+      double v[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + u * kStep + 4 * lq + e;
+          v[u][e] = r < rows ? xc[r] : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][e], v[u][e], acc, 0, 0, 0);
     }
-    // block max through LDS
-    __shared__ double red[kJT];
-    red[tid] = mx;
-    __syncthreads();
-    for (int off = kJT / 2; off > 0; off >>= 1) {
-      if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
-      __syncthreads();
-    }
-    if (tid == 0) {
-      block_off = red[0];
-      atomicMax(offmax, (unsigned long long)__double_as_longlong(red[0]));
-    }
-    __syncthreads();
+    // register r of lane (i, q) holds G[q + 4r][i]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tile[wave * 16 + lq + 4 * r][li] = acc[r];
   }
-  // 2) cyclic Jacobi on G (kJP x kJP), parallel round-robin over kJP/2 pairs
-  if (block_off <= skip) return;
-  for (int sweep = 0; sweep < kJInner; ++sweep) {
-    __shared__ int changed;
-    if (tid == 0) changed = 0;
-    __syncthreads();
+  __syncthreads();
+  // sum the partial Grams; largest relative off-diagonal entry of the pair
+  double mx = 0.0;
+  if (tid < kJP * kJP) {
+    const int i = tid % kJP, j = tid / kJP;
+    double g = 0.0;
+#pragma unroll
+    for (int w = 0; w < kJT / kWave; ++w) g += tile[w * 16 + i][j];
+    G[0][i][j] = g;
+    Q[0][i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (tid < kJP * kJP) {
+    const int i = tid % kJP, j = tid / kJP;
+    if (i < j) {
+      const double d = sqrt(G[0][i][i] * G[0][j][j]);
+      if (d > 0.0) mx = fabs(G[0][i][j]) / d;
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+  if (lane == 0) wmax[wave] = mx;
+  __syncthreads();
+  double block_off = 0.0;
+#pragma unroll
+  for (int w = 0; w < kJT / kWave; ++w) block_off = fmax(block_off, wmax[w]);
+  if (tid == 0) atomicMax(offmax, (unsigned long long)__double_as_longlong(block_off));
+  if (block_off <= skip) return;  // uniform
+  // 2) cyclic Jacobi on G (kJP x kJP): kJP - 1 rounds of kJW disjoint
+  //    rotations (round-robin); each round G <- J^T G J and Q <- Q J computed
+  //    entry by entry from the previous buffer.
+  int cur = 0;
+  static_assert(kJInner == 1, "one inner sweep per pair and round");
+  {
     for (int r = 0; r < kJP - 1; ++r) {
       if (tid < kJW) {
         int p, q;
@@ -600,48 +672,41 @@ __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, 
           p = q;
           q = t;
         }
-        const double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
-        double c = 1.0, s = 0.0;
+        const double gpp = G[cur][p][p], gqq = G[cur][q][q], gpq = G[cur][p][q];
+        double c = 1.0, sv = 0.0;
         if (fabs(gpq) > 1e-300 && fabs(gpq) > 2.2e-16 * sqrt(gpp * gqq)) {
           const double zeta = (gqq - gpp) / (2.0 * gpq);
           const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + t * t);
-          s = c * t;
-          changed = 1;
+          sv = c * t;
         }
-        pp_[tid] = p;
-        qq_[tid] = q;
-        cs[tid] = c;
-        sn[tid] = s;
+        mate[p] = q;
+        mate[q] = p;
+        lowr[p] = 1;
+        lowr[q] = 0;
+        cs[p] = cs[q] = c;
+        sn[p] = sn[q] = sv;
       }
       __syncthreads();
-      // columns of G and Q: G <- G J, Q <- Q J
-      for (int e = tid; e < kJW * kJP; e += kJT) {
-        const int pr = e / kJP, row = e % kJP;
-        const int p = pp_[pr], q = qq_[pr];
-        const double c = cs[pr], s = sn[pr];
-        const double gp = G[row][p], gq = G[row][q];
-        G[row][p] = c * gp - s * gq;
-        G[row][q] = s * gp + c * gq;
-        const double qp = Q[row][p], qq = Q[row][q];
-        Q[row][p] = c * qp - s * qq;
-        Q[row][q] = s * qp + c * qq;
+      // column j of G J: p' = c g_p - s g_q, q' = s g_p + c g_q (same for Q J);
+      // then row i of J^T (G J) likewise.
+      if (tid < kJP * kJP) {
+        const int i = tid % kJP, j = tid / kJP, nx = cur ^ 1;
+        const int mi = mate[i], mj = mate[j];
+        const double ci = cs[i], si = lowr[i] ? -sn[i] : sn[i];
+        const double cj = cs[j], sj = lowr[j] ? -sn[j] : sn[j];
+        // (G J)[k][j] = cj G[k][j] + sj G[k][mj], for k in {i, mi}
+        const double gij = cj * G[cur][i][j] + sj * G[cur][i][mj];
+        const double gmj = cj * G[cur][mi][j] + sj * G[cur][mi][mj];
+        G[nx][i][j] = ci * gij + si * gmj;
+        Q[nx][i][j] = cj * Q[cur][i][j] + sj * Q[cur][i][mj];
       }
-      __syncthreads();
-      // rows of G: G <- J^T G
-      for (int e = tid; e < kJW * kJP; e += kJT) {
-        const int pr = e / kJP, cc = e % kJP;
-        const int p = pp_[pr], q = qq_[pr];
-        const double c = cs[pr], s = sn[pr];
-        const double gp = G[p][cc], gq = G[q][cc];
-        G[p][cc] = c * gp - s * gq;
-        G[q][cc] = s * gp + c * gq;
-      }
+      cur ^= 1;
       __syncthreads();
     }
-    if (!changed) break;
   }
-  // 3) apply Q to the columns of X and of V
+  // 3) apply Q to the columns of X and of V: each thread's rows are loaded
+  //    together before the products.
   for (int pass = 0; pass < 2; ++pass) {
     double* M = pass == 0 ? X : Vm;
     const long long ld = pass == 0 ? ldx : ldv;
@@ -652,10 +717,10 @@ __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, 
       for (int cc = 0; cc < kJP; ++cc) in[cc] = M[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld];
 #pragma unroll 4
       for (int cc = 0; cc < kJP; ++cc) {
-        double s = 0.0;
+        double acc = 0.0;
 #pragma unroll
-        for (int t = 0; t < kJP; ++t) s += in[t] * Q[t][cc];
-        M[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld] = s;
+        for (int t = 0; t < kJP; ++t) acc += in[t] * Q[cur][t][cc];
+        M[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld] = acc;
       }
     }
   }
