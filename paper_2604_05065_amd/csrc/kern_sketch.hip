@@ -280,16 +280,22 @@ template void launch_sketch_csr<double>(const int*, const int*, const double*, l
 
 // ---------------------------------------------------------------- sketch, dense A
 // Workgroup (strip, chunk) covers columns [64 strip, 64 strip + 64) and a chunk
-// of rows.  The s x 64 strip of Y lives in LDS (FP64).  Wave w of the sixteen
-// owns the Y rows h with h % 16 == w: every wave walks all rows of the chunk in
-// order (eight rows' values, target rows and signs loaded at a time, the targets
-// then read lane by lane, uniform per wave; the strip's 256 bytes per row are
-// shared through L1) and adds only its own contributions, so each LDS cell has a
-// single writer and a fixed summation order.  The chunk's strip is written to a partial buffer that a second kernel
-// sums over chunks in order.
-constexpr int kSkT = 1024;  // threads per workgroup of the dense sketch
-constexpr int kSkW = kSkT / kWave;
-constexpr int kSkU = 8;     // rows per batch
+// of rows; the s x 64 strip of Y lives in LDS (FP64, rows padded to 65 against
+// bank conflicts).  Wave w owns the strip's columns 8w .. 8w + 7, and lane
+// (c, t) = (lane % 8, lane / 8) adds the row's contribution to its t-th target
+// row of Y in column 8w + c, as an LDS atomic add (no return value, so the
+// adds of consecutive rows do not wait for each other).  The targets of one
+// row are distinct, so one wave instruction never adds to a cell twice; a
+// wave's LDS operations complete in order and no two waves share a column, so
+// every cell is summed in row order.  Each wave loads
+// kSkB rows' values, targets and signs before using them and the waves run
+// without barriers, so several batches of the strip are in flight per CU.  The
+// chunk's strip goes to a partial buffer that a second kernel sums over chunks
+// in order.
+constexpr int kSkT = 512;        // threads per workgroup (8 waves x 8 columns)
+template <class T>
+constexpr int kSkB = sizeof(T) == 4 ? 64 : 32;  // rows per batch (registers)
+constexpr int kSkLd = kWave + 1; // LDS row stride of the Y strip (doubles)
 
 template <class T>
 __global__ void __launch_bounds__(kSkT) k_sketch_dense(const T* A, long long m, long long n,
@@ -297,39 +303,49 @@ __global__ void __launch_bounds__(kSkT) k_sketch_dense(const T* A, long long m, 
                                                        const uint16_t* rows,
                                                        const uint8_t* negmask, double scale,
                                                        long long rows_per_chunk, double* part) {
-  extern __shared__ double lds[];  // s x 64
-  const int l = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const long long j = blockIdx.x * (long long)kWave + l;
+  extern __shared__ double lds[];  // s x kSkLd
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int cl = wave * 8 + lane % 8, t = lane / 8;
+  const long long j = blockIdx.x * (long long)kWave + cl;
   const long long i0 = blockIdx.y * rows_per_chunk;
   const long long i1 = min(m, i0 + rows_per_chunk);
-  for (int h = threadIdx.x; h < s * kWave; h += kSkT) lds[h] = 0.0;
+  for (int h = threadIdx.x; h < s * kSkLd; h += kSkT) lds[h] = 0.0;
   __syncthreads();
-  const bool col_ok = j < n;
-  const long long jc = col_ok ? j : n - 1;
-  for (long long i = i0; i < i1; i += kSkU) {
-    // the batch's values, target rows (lane q: entry q of rows[i xi ..]) and sign masks
-    double a[kSkU];
+  const bool act = j < n && t < xi;
+  const long long jc = j < n ? j : n - 1;
+  const int tc = t < xi ? t : 0;
+  constexpr int B = kSkB<T>;
+  for (long long ib = i0; ib < i1; ib += B) {
+    T a[B];
+    int h[B];
+    unsigned sg[B / 4];
 #pragma unroll
-    for (int u = 0; u < kSkU; ++u) {
-      const long long ii = min(i + u, i1 - 1);
-      const T v = A[ii * ld + jc];
-      a[u] = (col_ok && i + u < i1) ? (double)v * scale : 0.0;
+    for (int u = 0; u < B; ++u) {
+      const long long ii = min(ib + u, i1 - 1);
+      a[u] = A[ii * ld + jc];
+      h[u] = rows[ii * xi + tc];
     }
-    const int nb = (int)min((long long)kSkU, i1 - i);
-    const int rv = l < nb * xi ? (int)rows[i * xi + l] : 0;
-    const int nv = l < nb ? (int)negmask[i + l] : 0;
-    for (int u = 0; u < nb; ++u) {
-      const unsigned neg = (unsigned)__builtin_amdgcn_readlane(nv, u);
-      for (int t = 0; t < xi; ++t) {
-        const int h = __builtin_amdgcn_readlane(rv, u * xi + t);
-        if ((h % kSkW) == w) lds[h * kWave + l] += ((neg >> t) & 1u) ? -a[u] : a[u];
+#pragma unroll
+    for (int q = 0; q < B / 4; ++q) {
+      unsigned w4 = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w4 |= (unsigned)negmask[min(ib + 4 * q + e, i1 - 1)] << (8 * e);
+      sg[q] = w4;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (ib + u < i1 && act) {
+        const double v = (double)a[u] * scale;
+        const bool neg = (sg[u / 4] >> (8 * (u % 4) + t)) & 1u;
+        (void)__hip_atomic_fetch_add(&lds[h[u] * kSkLd + cl], neg ? -v : v, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
   }
   __syncthreads();
-  if (col_ok) {
+  if (j < n) {
     double* out = part + (long long)blockIdx.y * s * n;
-    for (int h = w; h < s; h += kSkW) out[(long long)h * n + j] = lds[h * kWave + l];
+    for (int hh = t; hh < s; hh += 8) out[(long long)hh * n + j] = lds[hh * kSkLd + cl];
   }
 }
 
@@ -354,7 +370,7 @@ void launch_sketch_dense(const T* A, long long m, long long n, long long ld, int
                          const uint16_t* rows, const uint8_t* negmask, double* Y, double* part,
                          int chunks, hipStream_t st) {
   long long rpc = (m + chunks - 1) / chunks;
-  size_t lds = sizeof(double) * s * kWave;
+  size_t lds = sizeof(double) * s * kSkLd;
   APL_REQUIRE(lds <= 160 * 1024, "sketch dimension too large for the LDS strip");
   APL_HIP(hipFuncSetAttribute((const void*)k_sketch_dense<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_sketch_dense<T>, dim3(ceil_div(n, kWave), chunks), dim3(kSkT), lds, st, A,
