@@ -148,14 +148,15 @@ def bench_adjoint(ap, synth, torch, m=25000, n=500, nrhs=4):
 def bench_multi_rhs(ap, synth, torch, npts=20000, nrhs=16):
     """The dense kernel workload at half its size (Gaussian RBF kernel, h = 1,
     on 20000 points in [0,1]^8, FP32 A, 16 RHS, mu = 1e-3, block 250): APLICUR
-    with the 16 columns blocked (one pass over A per iteration for all) against
-    the same solve one column at a time, and the blocked product bandwidth
-    (A X and A^T U with 16 columns, event-timed, A bytes per launch)."""
+    with the 16 columns blocked (one pass over A per iteration for all; FP64,
+    and FP32 phases with FP64 refinement) against the same solve one column at
+    a time, and the blocked product bandwidth (A X and A^T U with 16 columns,
+    event-timed, A bytes per launch)."""
     A, B = synth.rbf_kernel_gpu(3003, npts, nrhs)
     opts = dict(mu=1e-3, block=250, tol_ne=1e-8)
     out = {"npts": npts, "nrhs": nrhs}
-    for name, cols in (("columns", 1), ("blocked", 0)):
-        ms, (X, info) = _timed(torch, lambda: ap.lstsq(A, B, columns=cols, **opts))
+    for name, cols, prec in (("columns", 1, 0), ("blocked", 0, 0), ("blocked_fp32_ir", 0, 1)):
+        ms, (X, info) = _timed(torch, lambda: ap.lstsq(A, B, columns=cols, precision=prec, **opts))
         out[name] = {"ms": round(ms, 1), "lsqr_ms": round(info.t_lsqr_ms, 1), "iters": info.iters,
                      "phases": info.phases, "rank": info.rank, "eta": info.eta}
         log(f"[bench] multi-RHS rbf {npts} x {nrhs} ({name}): {ms:.0f} ms (LSQR {info.t_lsqr_ms:.0f} ms, "

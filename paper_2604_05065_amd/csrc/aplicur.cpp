@@ -96,6 +96,12 @@ struct Blk {
   BlkVecs<double> vec{};
   BlkWork wk{};
   BlkOp op{};
+  // precision 1: the FP32 operator (FP32 values of A and of A^T), FP32 block
+  // vectors, and the right-hand side of the refinement corrections
+  BlkOp op32{};
+  void* At32 = nullptr;
+  BlkVecs<float> vec32{};
+  double* Nc = nullptr;
   GKState* st = nullptr;
   GKState* st_up = nullptr;    // pinned, 2 kp (uploads)
   GKState* st_down = nullptr;  // pinned, 2 kp (read-backs)
@@ -1335,7 +1341,7 @@ static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, lo
 constexpr int kBlkMaxCols = 64;
 
 static bool use_blocked(const Ctx& c, int nrhs) {
-  return nrhs >= 2 && !c.op.csr && !c.fp32 && !c.o.columns;
+  return nrhs >= 2 && !c.op.csr && !c.o.columns;
 }
 
 static int blk_kp(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
@@ -1362,8 +1368,29 @@ static void ensure_blk(Ctx& c, int kp, hipStream_t s) {
     b.op.Sm = gemm_splits(m, n);
     b.op.Sn = gemm_splits(n, m);
   }
+  if (c.fp32 && !b.op32.A) {
+    b.op32 = b.op;
+    b.op32.f64 = 0;
+    b.op32.A = c.op32.val;
+    b.op32.ld = c.op32.ld;
+    if (c.op.f64) {
+      b.At32 = c.arena.alloc<float>((size_t)n * b.ldt);
+      transpose_rect<float>((const float*)c.op32.val, m, n, c.op32.ld, (float*)b.At32, b.ldt, s);
+      b.op32.At = b.At32;
+    }
+  }
   if (b.kp >= kp) return;
   b.kp = kp;
+  if (c.fp32) {
+    b.vec32.u_top = c.arena.alloc<float>((size_t)m * kp);
+    b.vec32.u_bot = c.arena.alloc<float>((size_t)n * kp);
+    b.vec32.v = c.arena.alloc<float>((size_t)n * kp);
+    b.vec32.w = c.arena.alloc<float>((size_t)n * kp);
+    b.vec32.y = c.arena.alloc<float>((size_t)n * kp);
+    b.vec32.t = c.arena.alloc<float>((size_t)n * kp);
+    b.vec32.g = c.arena.alloc<float>((size_t)n * kp);
+    b.Nc = c.arena.alloc<double>((size_t)n * kp);
+  }
   const int L = std::max(c.L, 1);
   b.S1max = 64;
   b.S2max = gemm_splits(n, L);
@@ -1452,9 +1479,14 @@ struct BlkParam {
   int budget = 0;
 };
 
-// One warm-started phase for the active columns of min || A_mu X - [B; bs Bbot] ||.
-static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::vector<BlkParam>& prm,
-                                           const double* Bbot, double bs, bool x_zero, hipStream_t s) {
+// One warm-started phase for the active columns of min || A_mu X - [B; bs Bbot] ||:
+// FP64, or with precision 1 FP32 recurrences from an FP64 residual; FP32
+// refinement phases (nu = inf, eps_lsqr = 0, X warm, delta > 0) solve for the
+// correction with the right-hand side [0; A_mu^T r / delta], as the column path.
+template <class V>
+static std::vector<PhaseOut> run_phase_blk_t(Ctx& c, const BlkOp& A, BlkVecs<V> vec, const BlkPrec* P,
+                                             const std::vector<BlkParam>& prm, const double* B, const double* Bbot,
+                                             double bs, bool x_zero, double rel_tol, hipStream_t s) {
   Blk& b = *c.blk;
   const int kp = b.kp, k = (int)prm.size();
   long long budget = 0;
@@ -1464,6 +1496,7 @@ static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::
     h.alpha = 1.0;
     h.beta = 1.0;
     h.delta = c.delta;
+    h.rel_tol = rel_tol;
     if (j < k && prm[j].active) {
       const BlkParam& q = prm[j];
       h.pnorm = q.pnorm;
@@ -1482,7 +1515,7 @@ static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::
     b.st_up[kp + j] = h;
   }
   APL_HIP(hipMemcpyAsync(b.st, b.st_up, sizeof(GKState) * 2 * kp, hipMemcpyHostToDevice, s));
-  blk_phase_init<double>(b.op, P, kp, b.Bp, Bbot, bs, b.Xp, x_zero, c.delta, b.vec, b.st, b.wk, s);
+  blk_phase_init<V>(b.op, A, P, kp, B, Bbot, bs, b.Xp, x_zero, c.delta, vec, b.st, b.wk, s);
   auto read = [&]() {
     APL_HIP(hipMemcpyAsync(b.st_down, b.st, sizeof(GKState) * 2 * kp, hipMemcpyDeviceToHost, s));
     APL_HIP(hipStreamSynchronize(s));
@@ -1500,7 +1533,7 @@ static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::
   APL_HIP(hipGetLastError());
   bool done = read();
   while (!done) {
-    for (int i = 0; i < chunk; ++i) blk_iteration<double>(b.op, P, kp, c.delta, b.vec, b.st, b.wk, s);
+    for (int i = 0; i < chunk; ++i) blk_iteration<V>(A, P, kp, c.delta, vec, b.st, b.wk, s);
     launched += chunk;
     chunk = std::min(chunk * 2, 64);
     APL_HIP(hipGetLastError());
@@ -1517,8 +1550,26 @@ static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::
     if (h.reason == 6) throw Error(APLICUR_E_BREAKDOWN, "non-finite value in the LSQR recurrence");
     out[j] = PhaseOut{h.iter, h.reason};
   }
-  blk_phase_finish<double>(b.op, P, kp, b.vec, b.Xp, b.wk, s);
+  blk_phase_finish<V>(A, P, kp, vec, b.Xp, b.wk, s);
   return out;
+}
+
+static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::vector<BlkParam>& prm,
+                                           const double* Bbot, double bs, bool x_zero, hipStream_t s) {
+  Blk& b = *c.blk;
+  bool refinement = true;
+  for (const BlkParam& q : prm)
+    if (q.active) refinement &= std::isinf(q.nu) && q.eps_lsqr == 0.0;
+  if (c.fp32 && (x_zero || !refinement || c.delta > 0.0)) {
+    if (!x_zero && refinement) {
+      // N = A_mu^T r (FP64) of the current X, then the correction from zero
+      (void)blk_norms(b.op, b.kp, 2, b.Bp, Bbot, bs, b.Xp, c.delta, b.tm, b.tn, b.wk, s, b.Nc);
+      return run_phase_blk_t<float>(c, b.op32, b.vec32, P, prm, nullptr, b.Nc, 1.0 / c.delta, true,
+                                    kFp32PhaseRelTol, s);
+    }
+    return run_phase_blk_t<float>(c, b.op32, b.vec32, P, prm, b.Bp, Bbot, bs, x_zero, kFp32PhaseRelTol, s);
+  }
+  return run_phase_blk_t<double>(c, b.op, b.vec, P, prm, b.Bp, Bbot, bs, x_zero, 0.0, s);
 }
 
 // Restarted phases with nu = inf for every column not yet done, until each

@@ -69,11 +69,12 @@ struct BlkWork {
 
 constexpr int kBlkMaxGrid = 256;  // workgroups of the element-wise kernels (their partials are re-read)
 
-// Phase start: r = [B - A X; bs Bbot - delta X] (FP64; X = 0 when x_zero), then
-// as the single-column phase start (beta, the first A^T product and alpha).
+// Phase start: r = [B - Ares X; bs Bbot - delta X] (FP64 with the values of
+// Ares; X = 0 when x_zero) stored in the V vectors, then as the single-column
+// phase start with the operator A (beta, the first A^T product and alpha).
 template <class V>
-void blk_phase_init(const BlkOp& A, const BlkPrec* P, int kp, const double* B, const double* Bbot, double bs,
-                    const double* X, bool x_zero, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
+void blk_phase_init(const BlkOp& Ares, const BlkOp& A, const BlkPrec* P, int kp, const double* B, const double* Bbot,
+                    double bs, const double* X, bool x_zero, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
                     hipStream_t s);
 template <class V>
 void blk_iteration(const BlkOp& A, const BlkPrec* P, int kp, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
@@ -88,7 +89,8 @@ void blk_phase_finish(const BlkOp& A, const BlkPrec* P, int kp, BlkVecs<V> vec, 
 //   mode 2: ||A_mu^T r||^2 with r = [B - A X; bs Bbot - delta X]
 //   (A_mu^T r = A^T r_top + delta r_bot).
 // tmp_m (m x kp) and tmp_n (n x kp) are FP64 scratch.
+// outv (optional, modes 1 and 2): the vector itself (A^T B, or A_mu^T r), n x kp.
 int blk_norms(const BlkOp& A, int kp, int mode, const double* B, const double* Bbot, double bs, const double* X,
-              double delta, double* tmp_m, double* tmp_n, BlkWork& wk, hipStream_t s);
+              double delta, double* tmp_m, double* tmp_n, BlkWork& wk, hipStream_t s, double* outv = nullptr);
 
 }  // namespace aplicur

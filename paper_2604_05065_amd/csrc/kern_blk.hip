@@ -601,11 +601,12 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---------------------------------------------------------------- norms
 // Column partials of ||a||^2 over rows x kp (a given), or of
-// ||plane sum of pn + delta r_bot||^2 (the normal residual) when pn is given.
+// ||plane sum of pn + delta r_bot||^2 (the normal residual) when pn is given;
+// outv (optional) receives the summed vector.
 template <int KP>
 __global__ void __launch_bounds__(kBlock)
     k_blk_colsq(const double* __restrict__ a, const double* __restrict__ pn, int S, long long rows, double delta,
-                const double* __restrict__ r_bot, double* part) {
+                const double* __restrict__ r_bot, double* part, double* outv) {
   __shared__ double lds[kBlock];
   const long long np = rows * KP;
   double sq = 0.0;
@@ -617,6 +618,7 @@ __global__ void __launch_bounds__(kBlock)
     } else {
       x = a[e];
     }
+    if (outv) outv[e] = x;
     sq += x * x;
   }
   col_partials<KP>(sq, lds, part);
@@ -676,19 +678,19 @@ static void blk_bwd(const BlkOp& A, const BlkPrec* P, int kp, double delta, BlkV
 }
 
 template <class V>
-void blk_phase_init(const BlkOp& A, const BlkPrec* P, int kp, const double* B, const double* Bbot, double bs,
-                    const double* X, bool x_zero, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
+void blk_phase_init(const BlkOp& Ares, const BlkOp& A, const BlkPrec* P, int kp, const double* B, const double* Bbot,
+                    double bs, const double* X, bool x_zero, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
                     hipStream_t s) {
   double* pm = (double*)wk.pm;
   if (!x_zero) {
-    if (A.f64)
-      rows_gemm<double, double, double>((const double*)A.A, A.m, A.n, A.ld, X, kp, pm, A.Sm, s);
+    if (Ares.f64)
+      rows_gemm<double, double, double>((const double*)Ares.A, A.m, A.n, Ares.ld, X, kp, pm, Ares.Sm, s);
     else
-      rows_gemm<float, double, double>((const float*)A.A, A.m, A.n, A.ld, X, kp, pm, A.Sm, s);
+      rows_gemm<float, double, double>((const float*)Ares.A, A.m, A.n, Ares.ld, X, kp, pm, Ares.Sm, s);
   }
   const unsigned g = blk_grid(std::max(A.m, A.n), kp);
   BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_resid<V, KP>), dim3(g), dim3(kBlock), 0, s,
-                                       (const double*)(x_zero ? nullptr : pm), A.Sm, A.m, A.n, B, Bbot, bs,
+                                       (const double*)(x_zero ? nullptr : pm), Ares.Sm, A.m, A.n, B, Bbot, bs,
                                        x_zero ? nullptr : X, delta, vec.u_top, vec.u_bot, wk.beta_part));
   wk.beta_count = g;
   fill_zero<V>(vec.y, A.n * kp, s);
@@ -737,13 +739,14 @@ void blk_phase_finish(const BlkOp& A, const BlkPrec* P, int kp, BlkVecs<V> vec, 
 }
 
 int blk_norms(const BlkOp& A, int kp, int mode, const double* B, const double* Bbot, double bs, const double* X,
-              double delta, double* tmp_m, double* tmp_n, BlkWork& wk, hipStream_t s) {
+              double delta, double* tmp_m, double* tmp_n, BlkWork& wk, hipStream_t s, double* outv) {
   double* pn = (double*)wk.pn;
   if (mode == 0 || mode == 3) {
     const long long rows = mode == 0 ? A.m : A.n;
     const unsigned g = blk_grid(rows, kp);
     BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_colsq<KP>), dim3(g), dim3(kBlock), 0, s, mode == 0 ? B : Bbot,
-                                         (const double*)nullptr, 1, rows, 0.0, (const double*)nullptr, wk.norm_part));
+                                         (const double*)nullptr, 1, rows, 0.0, (const double*)nullptr, wk.norm_part,
+                                         (double*)nullptr));
     return (int)g;
   }
   const double* top = B;
@@ -769,15 +772,23 @@ int blk_norms(const BlkOp& A, int kp, int mode, const double* B, const double* B
     rows_gemm<float, double, double>((const float*)A.At, A.n, A.m, A.ldt, top, kp, pn, A.Sn, s);
   const unsigned g = blk_grid(A.n, kp);
   BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_colsq<KP>), dim3(g), dim3(kBlock), 0, s, (const double*)nullptr,
-                                       (const double*)pn, A.Sn, A.n, delta, rbot, wk.norm_part));
+                                       (const double*)pn, A.Sn, A.n, delta, rbot, wk.norm_part, outv));
   return (int)g;
 }
 
-template void blk_phase_init<double>(const BlkOp&, const BlkPrec*, int, const double*, const double*, double,
-                                     const double*, bool, double, BlkVecs<double>, GKState*, BlkWork&, hipStream_t);
+template void blk_phase_init<double>(const BlkOp&, const BlkOp&, const BlkPrec*, int, const double*, const double*,
+                                     double, const double*, bool, double, BlkVecs<double>, GKState*, BlkWork&,
+                                     hipStream_t);
+template void blk_phase_init<float>(const BlkOp&, const BlkOp&, const BlkPrec*, int, const double*, const double*,
+                                    double, const double*, bool, double, BlkVecs<float>, GKState*, BlkWork&,
+                                    hipStream_t);
 template void blk_iteration<double>(const BlkOp&, const BlkPrec*, int, double, BlkVecs<double>, GKState*, BlkWork&,
                                     hipStream_t);
+template void blk_iteration<float>(const BlkOp&, const BlkPrec*, int, double, BlkVecs<float>, GKState*, BlkWork&,
+                                   hipStream_t);
 template void blk_phase_finish<double>(const BlkOp&, const BlkPrec*, int, BlkVecs<double>, double*, BlkWork&,
                                        hipStream_t);
+template void blk_phase_finish<float>(const BlkOp&, const BlkPrec*, int, BlkVecs<float>, double*, BlkWork&,
+                                      hipStream_t);
 
 }  // namespace aplicur

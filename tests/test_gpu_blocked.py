@@ -143,3 +143,34 @@ def test_blocked_adjoint_matches_oracle(lib, precond):
     assert np.abs(Z.cpu().numpy() - Zr).max() <= 1e-8 * np.abs(Zr).max()
     assert np.abs(dB.cpu().numpy() - AZr).max() <= 1e-8 * np.abs(AZr).max()
     assert np.abs(dA.cpu().numpy() - dAr).max() <= 1e-8 * np.abs(dAr).max()
+
+
+@pytest.mark.parametrize("a_dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("precond", [False, True])
+@pytest.mark.parametrize("mu", [1e-4, 0.0])
+def test_blocked_fp32_phases_reach_fp64_tolerance(lib, a_dtype, precond, mu):
+    """Precision 1 with several columns: FP32 blocked phases (FP32 MFMA
+    products) and FP64 refinement reach the FP64 tolerance per column."""
+    m, n, tol = 800, 90, 1e-10
+    A = _dense(m, n, 60, decades=4)
+    if a_dtype == torch.float32:  # the FP32 values are the problem
+        A = A.astype(np.float32).astype(np.float64)
+    B = np.random.default_rng(61).standard_normal((m, 5))
+    X, info = lib.lstsq(_t(A, a_dtype), _t(B), mu=mu, block=10, tol_ne=tol, precond=precond, precision=1)
+    assert info.status == 0
+    assert info.phases >= 2  # the FP32 phases alone do not reach 1e-10
+    _check_columns(A, B, X.cpu().numpy(), mu, tol)
+
+
+def test_blocked_fp32_adjoint(lib):
+    r = np.random.default_rng(62)
+    A = synth.dense_svd(r, 500, 70, 10.0 ** (-2 * np.arange(70) / 69))
+    B = r.standard_normal((500, 4))
+    G = r.standard_normal((70, 4))
+    mu = 1e-3
+    with lib.Context(_t(A), mu=mu, block=8, tol_ne=1e-11, precision=1) as ctx:
+        X, _ = ctx.solve(_t(B))
+        Z, dB, dA, info = ctx.solve_backward(X, _t(B), _t(G), want_dA=False)
+    Zr = np.linalg.solve(A.T @ A + mu * np.eye(70), G)
+    assert info.eta <= 1.5e-11
+    assert np.abs(Z.cpu().numpy() - Zr).max() <= 1e-7 * np.abs(Zr).max()
