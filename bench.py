@@ -14,7 +14,8 @@ GPU LSQR (same kernels, P = I) and the FP32-phase variants to the same eta
 are timed beside it.  One JSON line on stdout; progress on stderr.
 
 --products-only runs just the timed A / A^T product loop and a 256 MiB copy
-of known size (for hardware-counter runs).
+of known size (for hardware-counter runs); --blocked-products does the same
+for the blocked products of several right-hand sides (dense FP32 A).
 """
 import argparse
 import hashlib
@@ -179,6 +180,38 @@ def bench_multi_rhs(ap, synth, torch, npts=20000, nrhs=16):
     return out
 
 
+def blocked_products(ap, synth, torch, npts=20000, nrhs=16, rounds=20):
+    """The blocked products alone (A X and A^T U, 16 columns, FP32 RBF kernel
+    on 20000 points) alternating for `rounds` rounds after a warm-up, event
+    timed, then three copies of 256 MiB used to calibrate the hardware
+    counters.  One JSON line."""
+    A, _ = synth.rbf_kernel_gpu(3003, npts, nrhs)
+    with ap.Context(A, precond=False, mu=1e-3) as ctx:
+        X = torch.randn(npts, nrhs, device="cuda", dtype=torch.float64)
+        ctx.matmat(X)
+        ctx.matmat(X, trans=True)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ta = tt = 0.0
+        for _ in range(rounds):
+            e[0].record()
+            ctx.matmat(X)
+            e[1].record()
+            ctx.matmat(X, trans=True)
+            e[2].record()
+            torch.cuda.synchronize()
+            ta += e[0].elapsed_time(e[1])
+            tt += e[1].elapsed_time(e[2])
+    big = torch.empty(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+    dst = torch.empty_like(big)
+    for _ in range(3):
+        dst.copy_(big)
+    torch.cuda.synchronize()
+    bytes_a = A.numel() * A.element_size()
+    print(json.dumps({"ms_AX": ta / rounds, "ms_ATU": tt / rounds, "bytes_A": bytes_a, "nrhs": nrhs,
+                      "GBs_AX": bytes_a / (ta / rounds) / 1e6, "GBs_ATU": bytes_a / (tt / rounds) / 1e6,
+                      "copy_bytes_each_way": big.numel() * 8}), flush=True)
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -188,6 +221,8 @@ def main():
     ap_.add_argument("--no-cpu", action="store_true")
     ap_.add_argument("--no-compare", action="store_true")
     ap_.add_argument("--products-only", action="store_true")
+    ap_.add_argument("--blocked-products", action="store_true",
+                     help="only the blocked products (FP32 RBF kernel 20000^2, 16 columns) and the calibration copy")
     ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
     args = ap_.parse_args()
     if args.gpus != 1:
@@ -199,6 +234,10 @@ def main():
 
     import paper_2604_05065_amd as ap
     from workloads import synth
+
+    if args.blocked_products:
+        blocked_products(ap, synth, torch)
+        return
 
     t0 = time.time()
     w = synth.workload(2, 1.0)
