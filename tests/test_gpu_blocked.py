@@ -174,3 +174,22 @@ def test_blocked_fp32_adjoint(lib):
     Zr = np.linalg.solve(A.T @ A + mu * np.eye(70), G)
     assert info.eta <= 1.5e-11
     assert np.abs(Z.cpu().numpy() - Zr).max() <= 1e-7 * np.abs(Zr).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_blocked_kernel_workload_half_size(lib, precision):
+    """The configuration bench.py times for several right-hand sides (RBF
+    kernel on 20000 points, FP32 A, 16 RHS, mu = 1e-3, block 250): every
+    column's eta recomputed on the CPU in FP64 from the FP32 values."""
+    A, B = synth.rbf_kernel_gpu(3003, 20000, 16)
+    tol, mu = 1e-8, 1e-3
+    X, info = lib.lstsq(A, B, mu=mu, block=250, tol_ne=tol, precision=precision)
+    assert info.status == 0
+    An = A.cpu().numpy().astype(np.float64)
+    Bn, Xn = B.cpu().numpy(), X.cpu().numpy()
+    R = Bn - An @ Xn
+    N = An.T @ R - mu * Xn
+    atb = np.linalg.norm(An.T @ Bn, axis=0)
+    eta = np.linalg.norm(N, axis=0) / atb
+    assert np.all(eta <= 1.05 * tol), eta
+    assert abs(eta.max() - info.eta) <= 1e-2 * tol
