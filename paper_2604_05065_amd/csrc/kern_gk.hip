@@ -502,15 +502,13 @@ __global__ void __launch_bounds__(kLxT)
     if (MODE == kFwdPlain) store_state(st_out, s);
     return;
   }
-  // x -> LDS, 12 loads per thread in flight
-  for (long long base = threadIdx.x; base < n; base += (long long)kLxT * 12) {
-    V tmp[12];
+  // x -> LDS with 12 loads per thread in flight; the first batch is issued
+  // before the first slice's values and columns, whose loads then overlap the
+  // rest of the copy.
+  long long xb = threadIdx.x;
+  V tmp[12];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) tmp[q] = tin[min(base + (long long)q * kLxT, n - 1)];
-#pragma unroll
-    for (int q = 0; q < 12; ++q)
-      if (base + (long long)q * kLxT < n) xs[base + (long long)q * kLxT] = tmp[q];
-  }
+  for (int q = 0; q < 12; ++q) tmp[q] = tin[min(xb + (long long)q * kLxT, n - 1)];
   // bottom slice [j0, j1) of the n rows
   const long long per = (n + gridDim.x - 1) / gridDim.x;
   const long long j0 = (long long)blockIdx.x * per, j1 = min(n, j0 + per);
@@ -534,6 +532,15 @@ __global__ void __launch_bounds__(kLxT)
     const long long e = (long long)off + (long long)(in ? q : 0) * kWave + lane;
     cidx[q] = in ? sci[e] : 0;
     vv[q] = in ? sval[e] : (TA)0;
+  }
+  for (;;) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+      if (xb + (long long)q * kLxT < n) xs[xb + (long long)q * kLxT] = tmp[q];
+    xb += (long long)kLxT * 12;
+    if (xb >= n) break;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) tmp[q] = tin[min(xb + (long long)q * kLxT, n - 1)];
   }
   publish(share, red);
   __syncthreads();
