@@ -150,33 +150,40 @@ def bench_multi_rhs(ap, synth, torch, npts=20000, nrhs=16):
     """The dense kernel workload at half its size (Gaussian RBF kernel, h = 1,
     on 20000 points in [0,1]^8, FP32 A, 16 RHS, mu = 1e-3, block 250): APLICUR
     with the 16 columns blocked (one pass over A per iteration for all; FP64,
-    and FP32 phases with FP64 refinement) against the same solve one column at
-    a time, and the blocked product bandwidth (A X and A^T U with 16 columns,
-    event-timed, A bytes per launch)."""
+    FP32 phases with FP64 refinement, and those with BF16 products) against
+    the same solve one column at a time, and the blocked product bandwidth (A X
+    and A^T U with 16 columns, event-timed whole matmat calls, bytes of the
+    matrix read: FP32 A for the FP64 and FP32 products, its BF16 copy for the
+    BF16 ones)."""
     A, B = synth.rbf_kernel_gpu(3003, npts, nrhs)
     opts = dict(mu=1e-3, block=250, tol_ne=1e-8)
     out = {"npts": npts, "nrhs": nrhs}
-    for name, cols, prec in (("columns", 1, 0), ("blocked", 0, 0), ("blocked_fp32_ir", 0, 1)):
+    for name, cols, prec in (("columns", 1, 0), ("blocked", 0, 0), ("blocked_fp32_ir", 0, 1),
+                             ("blocked_bf16_ir", 0, 2)):
         ms, (X, info) = _timed(torch, lambda: ap.lstsq(A, B, columns=cols, precision=prec, **opts))
         out[name] = {"ms": round(ms, 1), "lsqr_ms": round(info.t_lsqr_ms, 1), "iters": info.iters,
                      "phases": info.phases, "rank": info.rank, "eta": info.eta}
+        if prec == 2:
+            out[name]["phases_bf16"] = info.phases_bf16
         log(f"[bench] multi-RHS rbf {npts} x {nrhs} ({name}): {ms:.0f} ms (LSQR {info.t_lsqr_ms:.0f} ms, "
             f"rank {info.rank}, {info.iters} it, eta {info.eta:.1e})")
-    with ap.Context(A, precond=False, **opts) as ctx:
+    with ap.Context(A, precond=False, precision=2, **opts) as ctx:
         X = torch.randn(npts, nrhs, device="cuda", dtype=torch.float64)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        for trans, key in ((False, "AX"), (True, "ATU")):
-            ctx.matmat(X, trans=trans)
-            best = 1e30
-            for _ in range(5):
-                e0.record()
-                ctx.matmat(X, trans=trans)
-                e1.record()
-                torch.cuda.synchronize()
-                best = min(best, e0.elapsed_time(e1))
-            gbs = A.numel() * A.element_size() / best / 1e6
-            out[key + "_ms"], out[key + "_GBs"] = round(best, 3), round(gbs, 1)
-            log(f"[bench] blocked product {key} ({nrhs} columns, FP32 A {npts}^2): {best:.3f} ms, {gbs:.0f} GB/s")
+        for prec, tag, esize in ((0, "", 4), (1, "_fp32", 4), (2, "_bf16", 2)):
+            for trans, key in ((False, "AX"), (True, "ATU")):
+                ctx.matmat(X, trans=trans, prec=prec)
+                best = 1e30
+                for _ in range(5):
+                    e0.record()
+                    ctx.matmat(X, trans=trans, prec=prec)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    best = min(best, e0.elapsed_time(e1))
+                gbs = A.numel() * esize / best / 1e6
+                out[key + tag + "_ms"], out[key + tag + "_GBs"] = round(best, 3), round(gbs, 1)
+                log(f"[bench] blocked product {key} prec {prec} ({nrhs} columns, RBF {npts}^2): {best:.3f} ms, "
+                    f"{gbs:.0f} GB/s")
     return out
 
 

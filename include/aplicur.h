@@ -89,7 +89,15 @@ typedef struct aplicur_opts {
   int32_t precond;   /* 1: APLICUR (default); 0: plain LSQR on A_mu (no sketch, no CUR)   */
   int32_t precision; /* 0: FP64 vectors and products (default); 1: FP32 LSQR phases (FP32
                         values and vectors, FP64 scalars and reductions) with FP64
-                        refinement (an extension, not in the paper)                        */
+                        refinement (an extension, not in the paper); 2: as 1, and where
+                        the columns run blocked (dense A, nrhs >= 2) the products of the
+                        FP32 phases read BF16 copies of A and A^T (16x16x32 BF16 MFMA,
+                        FP32 accumulation, the FP32 input split into two BF16 parts); a
+                        BF16 phase stops at 1e-2 of its starting residual, and once a
+                        BF16 phase divides some column's eta by less than 10 the rest of
+                        that solve uses the FP32 products.  The copies (2 bytes per entry
+                        each, tiles of 32 x 64) are made on first use and held until the
+                        context is destroyed.  One column at a time, 2 behaves as 1      */
   int32_t max_outer; /* stop after this many outer steps (<= 0: no limit; for tests)       */
   int32_t workers;   /* aplicur_solve_batched: problems in flight at once, each on a stream
                         of its own (<= 0: 4)                                                  */
@@ -99,8 +107,8 @@ typedef struct aplicur_opts {
   int32_t graphs;    /* 1: replay the LSQR iterations as captured HIP graphs (same kernels,
                         same arithmetic); 0: launch each kernel                             */
   int32_t columns;   /* 1: one right-hand side at a time even where the blocked path applies
-                        (several right-hand sides of a dense A, precision 0); 0: blocked
-                        there (default).  Same method and stopping tests per column        */
+                        (several right-hand sides of a dense A); 0: blocked there
+                        (default).  Same method and stopping tests per column              */
   int32_t reserved[3];
 } aplicur_opts;
 
@@ -112,6 +120,9 @@ typedef struct aplicur_info { /* (host) */
   int32_t rank;        /* final CUR rank l                                         */
   int32_t rebuilds;    /* preconditioner builds                                    */
   int32_t outer;       /* outer (rank-increment) steps                             */
+  int32_t phases_bf16; /* phases of the blocked path whose products read the BF16
+                          copies of A (precision 2; 0 otherwise)                   */
+  int32_t reserved;
   double eta;          /* max over columns of the final eta, FP64 from a fresh residual */
   double rho;          /* last CUR error estimate                                  */
   double sigma_hat;    /* last target level sqrt(sigma_l^2 + mu)                   */
@@ -136,7 +147,7 @@ int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* stream,
  * column-major, ldb >= m) into X (n x nrhs, ldx >= n).  All columns share
  * the CUR sequence and every preconditioner (none depends on b); each
  * column runs its own LSQR recurrences with its own dynamic stopping.  For
- * a dense A with nrhs >= 2 and precision 0 the columns run together, up to
+ * a dense A with nrhs >= 2 (any precision) the columns run together, up to
  * 64 at a time, sharing each product (one pass over A per iteration for
  * the group; A^T products read a transposed copy of A made on first use,
  * held until the context is destroyed); otherwise one column at a time.  With
@@ -185,12 +196,18 @@ int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, 
 /* Y[:, j] = A X[:, j] (trans = 0) or A^T X[:, j] (trans = 1) for j < k: X and
  * Y device, FP64, column-major with leading dimensions ldx >= (trans ? m : n)
  * and ldy >= (trans ? n : m).  Dense A: one pass over A (or over its
- * transposed copy, made on first use) for up to 64 columns at a time, the
- * product on MFMA with FP64 accumulation of the FP32/FP64 values (the
- * products of the blocked multi-right-hand-side LSQR, Sec. 2.2); CSR A: one
- * product per column.  Enqueued on `stream`.                                */
+ * transposed copy, made on first use) for up to 64 columns at a time on
+ * MFMA (the products of the blocked multi-right-hand-side LSQR, Sec. 2.2);
+ * prec selects the arithmetic of the products the phases use:
+ *   0: FP64 accumulation of the stored FP32/FP64 values;
+ *   1: X rounded to FP32, FP32 values, FP32 accumulation (the FP32 phases;
+ *      a context of precision 1 or 2);
+ *   2: the BF16 copies of A / A^T, X split into two BF16 parts, FP32
+ *      accumulation (the BF16 products of precision 2).
+ * CSR A: one FP64 product per column (prec 0 only).  Enqueued on `stream`.
+ * Errors: E_INVALID (arguments, prec not available), E_HIP.               */
 int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx, int32_t k, double* Y, int64_t ldy,
-                   void* stream);
+                   int32_t prec, void* stream);
 
 /* Measures the product kernels the LSQR iteration uses: `reps` rounds of
  * y = A x - y followed by s = A^T y (s: library scratch), alternating as in
@@ -209,7 +226,8 @@ int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, doubl
  * 7 rho history (outer doubles), 8 rank history (outer int32),
  * 9 rebuild flags (outer int32), 10 sizes {m, n, s, xi, rank, outer, r} (int64),
  * 11 last preconditioner singular values sigma (rank doubles),
- * 12 per-phase iteration counts of column 0 (int32), 13 per-phase eta of column 0 (doubles).
+ * 12 per-phase iteration counts of column 0 (int32), 13 per-phase eta of column 0 (doubles),
+ * 14 Jacobi sweeps of each preconditioner build (int32).
  * Returns the number of bytes available (copies min(bytes, available)), or
  * a negative error.                                                        */
 int64_t aplicur_ctx_query(const aplicur_ctx* ctx, int32_t what, void* host_out, size_t bytes);

@@ -31,7 +31,8 @@ class Opts(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("status", C.c_int32), ("phases", C.c_int32), ("iters", C.c_int32), ("rank", C.c_int32),
-                ("rebuilds", C.c_int32), ("outer", C.c_int32), ("eta", C.c_double), ("rho", C.c_double),
+                ("rebuilds", C.c_int32), ("outer", C.c_int32), ("phases_bf16", C.c_int32),
+                ("reserved", C.c_int32), ("eta", C.c_double), ("rho", C.c_double),
                 ("sigma_hat", C.c_double), ("t_sketch_ms", C.c_double), ("t_cur_ms", C.c_double),
                 ("t_precond_ms", C.c_double), ("t_lsqr_ms", C.c_double)]
 
@@ -69,7 +70,7 @@ def load():
     lib.aplicur_solve_backward.restype = C.c_int
     lib.aplicur_matvec.argtypes = [vp, i32, dp, dp, vp]
     lib.aplicur_matvec.restype = C.c_int
-    lib.aplicur_matmat.argtypes = [vp, i32, dp, i64, i32, dp, i64, vp]
+    lib.aplicur_matmat.argtypes = [vp, i32, dp, i64, i32, dp, i64, i32, vp]
     lib.aplicur_matmat.restype = C.c_int
     lib.aplicur_time_product.argtypes = [vp, i32, dp, dp, i32, vp, C.POINTER(C.c_double)]
     lib.aplicur_time_product.restype = C.c_int

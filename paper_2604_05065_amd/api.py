@@ -151,13 +151,14 @@ class Context:
         L.check(self.lib.aplicur_matvec(self.ptr, int(bool(trans)), x.data_ptr(), y.data_ptr(), _stream()))
         return y
 
-    def matmat(self, X, trans=False):
-        """A X (or A^T X) for the columns of X (rows x k, or a vector)."""
+    def matmat(self, X, trans=False, prec=0):
+        """A X (or A^T X) for the columns of X (rows x k, or a vector); prec
+        1 / 2: the FP32 / BF16 products of the low-precision phases."""
         rows_in, rows_out = (self.m, self.n) if trans else (self.n, self.m)
         Xt, k, one = _cols(X, rows_in, "X")
         Yt = torch.empty((k, rows_out), dtype=torch.float64, device=Xt.device)
         L.check(self.lib.aplicur_matmat(self.ptr, int(bool(trans)), Xt.data_ptr(), rows_in, k, Yt.data_ptr(),
-                                        rows_out, _stream()))
+                                        rows_out, int(prec), _stream()))
         Y = Yt.t()
         return Y.reshape(-1) if one else Y
 
@@ -177,7 +178,7 @@ class Context:
         """Read internal state (see aplicur_ctx_query in include/aplicur.h)."""
         kinds = {1: np.float64, 2: np.int32, 3: np.int32, 4: np.float64, 5: np.int32, 6: np.int32,
                  7: np.float64, 8: np.int32, 9: np.int32, 10: np.int64, 11: np.float64, 12: np.int32,
-                 13: np.float64}
+                 13: np.float64, 14: np.int32}
         nbytes = self.lib.aplicur_ctx_query(self.ptr, what, None, 0)
         L.check(int(nbytes) if nbytes < 0 else 0)
         buf = (C.c_char * max(int(nbytes), 1))()

@@ -102,6 +102,13 @@ struct Blk {
   void* At32 = nullptr;
   BlkVecs<float> vec32{};
   double* Nc = nullptr;
+  // precision 2: op32 with BF16 tiled copies of A and A^T for the products;
+  // bf16_live is cleared for the rest of a solve once a BF16 phase gains too
+  // little, last_bf16 says whether the last phase used them
+  BlkOp op16{};
+  void *A16 = nullptr, *At16 = nullptr;
+  bool bf16_live = false, last_bf16 = false;
+  int phases16 = 0;
   GKState* st = nullptr;
   GKState* st_up = nullptr;    // pinned, 2 kp (uploads)
   GKState* st_down = nullptr;  // pinned, 2 kp (read-backs)
@@ -148,6 +155,7 @@ struct Ctx {
   double *u_top = nullptr, *u_bot = nullptr, *v = nullptr, *w = nullptr, *y = nullptr, *t = nullptr,
          *g = nullptr;
   bool fp32 = false;
+  bool bf16 = false;  // precision 2: BF16 copies for the blocked products of the FP32 phases
   OpDesc op32{};  // the same matrix with FP32 values (precision 1)
   float *u_top32 = nullptr, *u_bot32 = nullptr, *v32 = nullptr, *w32 = nullptr, *y32 = nullptr, *t32 = nullptr,
         *g32 = nullptr;
@@ -159,7 +167,7 @@ struct Ctx {
   FactorWork fw{};
   // histories
   std::vector<double> rho_hist;
-  std::vector<int> rank_hist, rebuild_hist;
+  std::vector<int> rank_hist, rebuild_hist, sweep_hist;
   std::vector<int> phase_iters0;
   std::vector<double> phase_eta0;
   double t_sketch = 0.0;
@@ -262,7 +270,8 @@ static void validate(const aplicur_mat* A, const aplicur_opts* o) {
   }
   APL_REQUIRE(o->mu >= 0.0 && std::isfinite(o->mu), "mu must be finite and >= 0");
   APL_REQUIRE(o->mu > 0.0 || A->m >= A->n, "mu = 0 needs m >= n");
-  APL_REQUIRE(o->precision == 0 || o->precision == 1, "precision must be 0 (FP64) or 1 (FP32 phases, FP64 refinement)");
+  APL_REQUIRE(o->precision >= 0 && o->precision <= 2,
+              "precision must be 0 (FP64), 1 (FP32 phases, FP64 refinement) or 2 (1 with BF16 blocked products)");
   if (o->precond) {
     APL_REQUIRE(o->block >= 1 && o->block <= 280, "block must be in [1, 280]");
     APL_REQUIRE(o->r_probes >= 1 && o->r_probes <= 64, "r_probes must be in [1, 64]");
@@ -464,9 +473,10 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       op.chunks = dense_chunks(m, n);
       op.part = c->arena.alloc<double>((size_t)std::min(1024, 4 * op.chunks) * n);
     }
-    if (o->precision == 1) {
+    if (o->precision >= 1) {
       // FP32 copy of the values (the CSR structure is shared)
       c->fp32 = true;
+      c->bf16 = o->precision == 2;
       c->op32 = op;
       c->op32.f64 = 0;
       if (op.f64) {
@@ -907,6 +917,9 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ preconditioner (Alg. 2 Part 2)
+// Sweeps of the one-sided Jacobi SVD end when every column pair's relative
+// off-diagonal Gram entry is at most this.
+constexpr double kJacobiTol = 1e-14;
 // Largest diagonal ratio of T_R for which the one-product form M2 is used.
 constexpr double kM2MaxDiagRatio = 1e3;
 
@@ -919,7 +932,7 @@ static void build_precond(Ctx& c, hipStream_t s) {
   gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Kr, l);
   gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Mx, L);
   set_identity(c.Vm, lp, lp, s);
-  jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.offmax, 1e-14, 40, s);
+  c.sweep_hist.push_back(jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.offmax, kJacobiTol, 40, s));
   precond_scalars(c.sigma, l, c.delta, c.d, c.pinfo, s);
   if (c.prec.implicit) {
     // K = T_R^{-1} V_M (column-major, ld l: the row-major K^T) and K row-major
@@ -1016,6 +1029,11 @@ static GKState read_state(Ctx& c, hipStream_t s) {
 // phase: below it the FP32 recurrences stop converging, and the next phase
 // restarts from the FP64 residual (iterative refinement).
 constexpr double kFp32PhaseRelTol = 1e-5;
+// BF16 blocked products (precision 2): a phase stops at 1e-2 of its starting
+// normal residual (about the relative rounding of the BF16 values), and BF16
+// stays in use while every phase divides eta by at least 1 / kBf16MinGain.
+constexpr double kBf16PhaseRelTol = 1e-2;
+constexpr double kBf16MinGain = 0.1;
 
 // Iterations per captured graph (graphs option).
 constexpr int kGraphChunk = 16;
@@ -1196,6 +1214,7 @@ static void outer_loop(Ctx& c, hipStream_t s, SolveLog& lg, Phases&& phases) {
   c.rho_hist.clear();
   c.rank_hist.clear();
   c.rebuild_hist.clear();
+  c.sweep_hist.clear();
   c.have_prec = false;
   APL_HIP(hipMemcpyAsync(c.E, c.Y, sizeof(double) * (size_t)c.s * c.n, hipMemcpyDeviceToDevice, s));
   double d_cur = INFINITY;
@@ -1379,6 +1398,15 @@ static void ensure_blk(Ctx& c, int kp, hipStream_t s) {
       b.op32.At = b.At32;
     }
   }
+  if (c.bf16 && !b.A16) {
+    b.A16 = c.arena.alloc<uint16_t>((size_t)bf16_tiled_elems(m, n));
+    b.At16 = c.arena.alloc<uint16_t>((size_t)bf16_tiled_elems(n, m));
+    tile_bf16((const float*)b.op32.A, m, n, b.op32.ld, b.A16, s);
+    tile_bf16((const float*)b.op32.At, n, m, b.op32.ldt, b.At16, s);
+    b.op16 = b.op32;
+    b.op16.A16 = b.A16;
+    b.op16.At16 = b.At16;
+  }
   if (b.kp >= kp) return;
   b.kp = kp;
   if (c.fp32) {
@@ -1560,16 +1588,31 @@ static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::
   bool refinement = true;
   for (const BlkParam& q : prm)
     if (q.active) refinement &= std::isinf(q.nu) && q.eps_lsqr == 0.0;
+  b.last_bf16 = false;
   if (c.fp32 && (x_zero || !refinement || c.delta > 0.0)) {
+    const bool use16 = c.bf16 && b.bf16_live;
+    const BlkOp& op = use16 ? b.op16 : b.op32;
+    const double rt = use16 ? kBf16PhaseRelTol : kFp32PhaseRelTol;
+    b.last_bf16 = use16;
+    b.phases16 += use16 ? 1 : 0;
     if (!x_zero && refinement) {
       // N = A_mu^T r (FP64) of the current X, then the correction from zero
       (void)blk_norms(b.op, b.kp, 2, b.Bp, Bbot, bs, b.Xp, c.delta, b.tm, b.tn, b.wk, s, b.Nc);
-      return run_phase_blk_t<float>(c, b.op32, b.vec32, P, prm, nullptr, b.Nc, 1.0 / c.delta, true,
-                                    kFp32PhaseRelTol, s);
+      return run_phase_blk_t<float>(c, op, b.vec32, P, prm, nullptr, b.Nc, 1.0 / c.delta, true, rt, s);
     }
-    return run_phase_blk_t<float>(c, b.op32, b.vec32, P, prm, b.Bp, Bbot, bs, x_zero, kFp32PhaseRelTol, s);
+    return run_phase_blk_t<float>(c, op, b.vec32, P, prm, b.Bp, Bbot, bs, x_zero, rt, s);
   }
   return run_phase_blk_t<double>(c, b.op, b.vec, P, prm, b.Bp, Bbot, bs, x_zero, 0.0, s);
+}
+
+// After a phase with BF16 products: if some column's eta fell by less than
+// kBf16MinGain, the rest of the solve takes the FP32 products.
+static void bf16_ladder(Ctx& c, const std::vector<BlkParam>& prm, const std::vector<double>& before,
+                        const std::vector<ColState>& cols) {
+  Blk& b = *c.blk;
+  if (!b.last_bf16) return;
+  for (size_t j = 0; j < prm.size(); ++j)
+    if (prm[j].active && cols[j].eta > kBf16MinGain * before[j]) b.bf16_live = false;
 }
 
 // Restarted phases with nu = inf for every column not yet done, until each
@@ -1611,6 +1654,7 @@ static void refine_blk(Ctx& c, const BlkPrec* P, std::vector<ColState>& cols, co
       if (po[j].iters == 0 || po[j].reason == kStopBudget) live[j] = false;
       stalls[j] = (cs.eta > 0.5 * prev[j]) ? stalls[j] + 1 : 0;
     }
+    bf16_ladder(c, prm, prev, cols);
   }
   for (auto& cs : cols) cs.done = true;
 }
@@ -1626,6 +1670,8 @@ static int solve_blocked(Ctx& c, const double* B, long long ldb, int nrhs, doubl
     const int kp = blk_kp(k);
     ensure_blk(c, kp, s);
     Blk& b = *c.blk;
+    b.bf16_live = c.bf16;
+    if (g0 == 0) b.phases16 = 0;
     pack_cols(B + (size_t)g0 * ldb, ldb, c.m, k, b.Bp, b.kp, s);
     if (warm)
       pack_cols(X + (size_t)g0 * ldx, ldx, c.n, k, b.Xp, b.kp, s);
@@ -1676,6 +1722,8 @@ static int solve_blocked(Ctx& c, const double* B, long long ldb, int nrhs, doubl
           q.sigma_l = c.p_sigma_l;
           q.budget = c.o.max_iter - cs.used;
         }
+        std::vector<double> before(k);  // eta before the phase (1 at a cold start: X = 0)
+        for (int j = 0; j < k; ++j) before[j] = (cols[j].phases == 0 && !warm) ? 1.0 : cols[j].eta;
         std::vector<PhaseOut> po = run_phase_blk(c, &P, prm, nullptr, 0.0, xz, s);
         const std::vector<double> eta = blk_col_norms(c, k, 2, c.blk->Bp, nullptr, 0.0, c.blk->Xp, s);
         bool rest = false;
@@ -1688,6 +1736,7 @@ static int solve_blocked(Ctx& c, const double* B, long long ldb, int nrhs, doubl
           if (cs.eta <= c.o.tol_ne || cs.used >= c.o.max_iter) cs.done = true;
           rest |= !cs.done;
         }
+        bf16_ladder(c, prm, before, cols);
         if (final_step && rest) refine_blk(c, &P, cols, nullptr, 0.0, c.p_pnorm, c.p_sigma_l, false, s);
         bool active = false;
         for (auto& cs : cols) active |= !cs.done;
@@ -1708,20 +1757,28 @@ static int solve_blocked(Ctx& c, const double* B, long long ldb, int nrhs, doubl
   APL_HIP(hipStreamSynchronize(s));
   int status = APLICUR_OK;
   fill_info(c, all, lg, info, status);
+  if (info) info->phases_bf16 = c.blk->phases16;
   return status;
 }
 
 // Y = A X (trans 0) or A^T X (trans 1) for k columns (column-major), in
 // groups of up to 64 columns through the blocked products (dense A).
+// prec 1 / 2: the FP32 / BF16 products of the low-precision phases.
 static void blk_apply(Ctx& c, int trans, const double* X, long long ldx, int k, double* Y, long long ldy,
-                      hipStream_t s) {
+                      hipStream_t s, int prec = 0) {
   for (int g0 = 0; g0 < k; g0 += kBlkMaxCols) {
     const int kg = std::min(kBlkMaxCols, k - g0);
     ensure_blk(c, blk_kp(kg), s);
     Blk& b = *c.blk;
-    double* in = trans ? b.tm : b.tn;
-    pack_cols(X + (size_t)g0 * ldx, ldx, trans ? c.m : c.n, kg, in, b.kp, s);
-    blk_matmat(b.op, trans != 0, in, b.kp, kg, Y + (size_t)g0 * ldy, ldy, s, (double*)(trans ? b.wk.pn : b.wk.pm));
+    void* part = trans ? b.wk.pn : b.wk.pm;
+    if (prec == 0) {
+      blk_matmat(b.op, trans != 0, X + (size_t)g0 * ldx, ldx, b.kp, kg, Y + (size_t)g0 * ldy, ldy, 0,
+                 trans ? b.tm : b.tn, part, s);
+    } else {
+      float* in = trans ? b.vec32.u_top : b.vec32.t;
+      blk_matmat(prec == 1 ? b.op32 : b.op16, trans != 0, X + (size_t)g0 * ldx, ldx, b.kp, kg,
+                 Y + (size_t)g0 * ldy, ldy, prec, in, part, s);
+    }
   }
 }
 
@@ -1755,6 +1812,8 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
     const int kg = std::min(kBlkMaxCols, nrhs - g0);
     ensure_blk(c, blk_kp(kg), s);
     Blk& b = *c.blk;
+    b.bf16_live = c.bf16;
+    if (g0 == 0) b.phases16 = 0;
     BlkPrec Pb{};
     if (c.have_prec) Pb = blk_prec(c, s);
     fill(b.Bp, c.m * b.kp, 0.0, s);
@@ -1849,6 +1908,7 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
     info->eta = eta_max;
     info->sigma_hat = c.p_target;
     info->t_lsqr_ms = ms_since(t0);
+    if (blocked) info->phases_bf16 = c.blk->phases16;
   }
   return status;
 }
@@ -2029,11 +2089,14 @@ int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, 
 }
 
 int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx, int32_t k, double* Y, int64_t ldy,
-                   void* stream) {
+                   int32_t prec, void* stream) {
   return guarded([&]() {
     APL_REQUIRE(ctx && ctx->impl && X && Y, "null argument");
     Ctx& c = *ctx->impl;
     APL_REQUIRE(k >= 1, "k must be >= 1");
+    APL_REQUIRE(prec >= 0 && prec <= 2, "prec must be 0, 1 or 2");
+    APL_REQUIRE(prec == 0 || (!c.op.csr && c.fp32), "prec 1 needs a dense A and a context of precision 1 or 2");
+    APL_REQUIRE(prec < 2 || c.bf16, "prec 2 needs a context of precision 2");
     APL_REQUIRE(ldx >= (trans ? c.m : c.n) && ldy >= (trans ? c.n : c.m), "leading dimensions too small");
     hipStream_t s = (hipStream_t)stream;
     set_stream(c, s);
@@ -2044,7 +2107,7 @@ int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx
         op_matvec(c.op, trans, X + (size_t)j * ldx, y, c.st_mv, c.wk, s);
       }
     } else {
-      blk_apply(c, trans, X, ldx, k, Y, ldy, s);
+      blk_apply(c, trans, X, ldx, k, Y, ldy, s, prec);
     }
     APL_HIP(hipGetLastError());
     return APLICUR_OK;
@@ -2133,6 +2196,7 @@ int64_t aplicur_ctx_query(const aplicur_ctx* ctx, int32_t what, void* host_out, 
       case 11: put(c.p_sigma_host.data(), c.p_sigma_host.size() * 8); break;
       case 12: put(c.phase_iters0.data(), c.phase_iters0.size() * 4); break;
       case 13: put(c.phase_eta0.data(), c.phase_eta0.size() * 8); break;
+      case 14: put(c.sweep_hist.data(), c.sweep_hist.size() * 4); break;
       default: g_last_error = "unknown query"; return APLICUR_E_INVALID;
     }
     if (host_out && bytes) std::memcpy(host_out, buf.data(), std::min(bytes, buf.size()));

@@ -34,10 +34,14 @@ void unpack_cols(const double* Xp, int kp, long long rows, int k, double* X, lon
 
 // Dense operator of the blocked path: A and its transposed copy.
 struct BlkOp;
-// Y[:, c] (column-major, ldy) = (A or A^T) In[:, c] for c < k (In row-major, kp
-// columns); part holds the product partials (S planes).
-void blk_matmat(const BlkOp& A, bool trans, const double* In, int kp, int k, double* Y, long long ldy, hipStream_t s,
-                double* part);
+// Y[:, c] (column-major, ldy) = (A or A^T) X[:, c] for c < k (X column-major,
+// ldx).  prec 0: X packed into `in` (FP64, kp columns), FP64 accumulation of
+// A's values; prec 1: X rounded to FP32, FP32 values and FP32 accumulation
+// (the products of the FP32 phases; A an FP32 operator); prec 2: the BF16
+// products (A with BF16 copies).  `part` holds the S product planes, summed
+// in order in the product's type.
+void blk_matmat(const BlkOp& A, bool trans, const double* X, long long ldx, int kp, int k, double* Y, long long ldy,
+                int prec, void* in, void* part, hipStream_t s);
 
 struct BlkOp {
   const void* A;   // m x n row-major (ld)
@@ -45,7 +49,21 @@ struct BlkOp {
   long long m, n, ld, ldt;
   int f64;         // values are double (else float)
   int Sm, Sn;      // splits of the A t and A^T u products
+  // BF16 copies of A and A^T in the tiled layout of tile_bf16 (precision 2),
+  // else null; when set, the FP32-vector products of the iteration use them
+  const void* A16;
+  const void* At16;
 };
+
+// BF16 copy of a row-major FP32 matrix (rows x cols, ld) in tiles of 32 rows
+// x 64 columns (zero-padded), rounded to nearest even; dst holds
+// bf16_tiled_elems(rows, cols) entries.
+long long bf16_tiled_elems(long long rows, long long cols);
+void tile_bf16(const float* src, long long rows, long long cols, long long ld, void* dst, hipStream_t s);
+// out[s][r][0..kp) = the s-th chunk of sum_j T[r][j] In[j][0..kp) for a tiled
+// BF16 T, FP32 In (cols x kp row-major) and FP32 accumulation (S chunks).
+void rows_gemm16(const void* T, long long rows, long long cols, const float* In, int kp, float* out, int S,
+                 hipStream_t s);
 
 // Explicit P^{-1} z = z + V (d .* (V^T z)) with V (n x ell, ldv) and V^T (ell x n, ldvt), FP64.
 struct BlkPrec {

@@ -20,6 +20,7 @@
 #include "blk.h"
 
 #include <cstdint>
+#include <type_traits>
 
 namespace aplicur {
 
@@ -239,13 +240,14 @@ void transpose_rect(const T* A, long long m, long long n, long long lda, T* At, 
 template void transpose_rect<double>(const double*, long long, long long, long long, double*, long long, hipStream_t);
 template void transpose_rect<float>(const float*, long long, long long, long long, float*, long long, hipStream_t);
 
-__global__ void k_pack_cols(const double* __restrict__ X, long long ldx, long long rows, int k, double* __restrict__ Xp,
+template <class TO>
+__global__ void k_pack_cols(const double* __restrict__ X, long long ldx, long long rows, int k, TO* __restrict__ Xp,
                             int kp) {
   const long long total = rows * kp;
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total; e += (long long)gridDim.x * kBlock) {
     const long long r = e / kp;
     const int c = (int)(e % kp);
-    Xp[e] = c < k ? X[(long long)c * ldx + r] : 0.0;
+    Xp[e] = c < k ? (TO)X[(long long)c * ldx + r] : (TO)0;
   }
 }
 
@@ -259,16 +261,17 @@ __global__ void k_unpack_cols(const double* __restrict__ Xp, int kp, long long r
   }
 }
 
-// Y[:, c] = sum of the S planes of part (rows x kp) at column c, for c < k.
-__global__ void k_planes_to_cols(const double* __restrict__ part, int S, long long rows, int kp, int k,
+// Y[:, c] = sum (in order, in TP) of the S planes of part (rows x kp) at column c, for c < k.
+template <class TP>
+__global__ void k_planes_to_cols(const TP* __restrict__ part, int S, long long rows, int kp, int k,
                                  double* __restrict__ Y, long long ldy) {
   const long long total = rows * k, plane = rows * kp;
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total; e += (long long)gridDim.x * kBlock) {
     const int c = (int)(e / rows);
     const long long r = e % rows;
-    double acc = part[r * kp + c];
+    TP acc = part[r * kp + c];
     for (int q = 1; q < S; ++q) acc += part[(long long)q * plane + r * kp + c];
-    Y[(long long)c * ldy + r] = acc;
+    Y[(long long)c * ldy + r] = (double)acc;
   }
 }
 
@@ -278,24 +281,198 @@ static unsigned elem_grid(long long count, long long cap = 4096) {
   return (unsigned)(g > cap ? cap : g);
 }
 
+// ---------------------------------------------------------------- BF16 products
+// BF16 copy of a row-major FP32 matrix in tiles of 32 rows x 64 columns:
+// element (r, j) at ((r / 32) NJ + j / 64) 2048 + (r % 32) 64 + j % 64 with
+// NJ = ceil(cols / 64), rows and columns padded with zeros, so that one step
+// of a wave in k_rows_gemm16 reads 4 KB of contiguous memory.  Values are
+// rounded to nearest even.  Thread g writes 8 consecutive entries of a tile
+// row (16 bytes) from 8 consecutive entries of the source row.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__global__ void __launch_bounds__(kBlock)
+    k_tile_bf16(const float* __restrict__ src, long long rows, long long cols, long long ld, long long NJ,
+                long long groups, __bf16* __restrict__ dst) {
+  for (long long g = (long long)blockIdx.x * kBlock + threadIdx.x; g < groups; g += (long long)gridDim.x * kBlock) {
+    const long long t = g / 256, w = g % 256;
+    const long long r = (t / NJ) * 32 + w / 8, j0 = (t % NJ) * 64 + (w % 8) * 8;
+    bf16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = (__bf16)((r < rows && j0 + e < cols) ? src[r * ld + j0 + e] : 0.0f);
+    *(bf16x8*)(dst + g * 8) = o;
+  }
+}
+
+long long bf16_tiled_elems(long long rows, long long cols) { return (rows + 31) / 32 * 32 * ((cols + 63) / 64 * 64); }
+
+void tile_bf16(const float* src, long long rows, long long cols, long long ld, void* dst, hipStream_t s) {
+  const long long groups = bf16_tiled_elems(rows, cols) / 8;
+  hipLaunchKernelGGL(k_tile_bf16, dim3(elem_grid(groups)), dim3(kBlock), 0, s, src, rows, cols, ld,
+                     (cols + 63) / 64, groups, (__bf16*)dst);
+}
+
+// out[s] = (the s-th chunk of the reduction index of) T In for a tiled BF16
+// T (rows x cols) and FP32 In (cols x KP row-major), FP32 accumulation, on
+// the 16x16x32 BF16 MFMA: A lane (i, q) holds row i, entries 8q .. 8q + 7 of
+// the 32; B lane (i, q) holds column i, the same entries; D lane (i, q)
+// register r holds row 4q + r, column i (the FP32 16x16x4 layout; checked on
+// gfx950).  Lane (i, q) loads T[row i][j0 + GPL q .. + GPL) (16 or 32
+// contiguous bytes) and sub-step h < GPL / 8 feeds entries GPL q + 8h + e
+// (e < 8) to one MFMA: a permutation of the reduction index.  In is split
+// into BF16 hi + lo parts (two MFMAs), so the product carries the rounding of
+// T and In's to about 2^-16 only.  Steps have 4 GPL entries; chunk bounds
+// are multiples of 64, and only In needs guarding in a step that crosses
+// cols (T is zero-padded to whole tiles).  Two register stages as in
+// k_rows_gemm.
+template <int NB, int GPL>
+struct Gemm16Step {
+  bf16x8 a[kGT][GPL / 8];
+  float b[NB][GPL];
+};
+
+template <int NB, int GPL>
+__global__ void __launch_bounds__(kBlock)
+    k_rows_gemm16(const __bf16* __restrict__ T, long long rows, long long cols, long long NJ,
+                  const float* __restrict__ In, float* __restrict__ out, long long kchunk) {
+  constexpr int KP = NB * 16, ST = 4 * GPL;
+  f32x4 acc[kGT][NB];
+#pragma unroll
+  for (int t = 0; t < kGT; ++t)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[t][b] = f32x4{0, 0, 0, 0};
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int li = lane % 16, lq = lane / 16;
+  const long long row0 = (long long)blockIdx.x * kGRows + (long long)wave * (kGT * 16);
+  const long long jb = (long long)blockIdx.y * kchunk;
+  const long long je = min(cols, jb + kchunk);
+  const long long R = min(row0 / 32, (rows + 31) / 32 - 1);  // waves past the last tile read it and store nothing
+  const __bf16* base[kGT];
+#pragma unroll
+  for (int t = 0; t < kGT; ++t) base[t] = T + R * NJ * 2048 + (16 * t + li) * 64 + GPL * lq;
+  auto load = [&](Gemm16Step<NB, GPL>& st, long long j0) {
+    const long long off = (j0 / 64) * 2048 + j0 % 64;
+#pragma unroll
+    for (int t = 0; t < kGT; ++t)
+#pragma unroll
+      for (int h = 0; h < GPL / 8; ++h) st.a[t][h] = *((const bf16x8*)(base[t] + off) + h);
+    const long long jl = j0 + GPL * lq;
+    if (j0 + ST <= je) {
+#pragma unroll
+      for (int e = 0; e < GPL; ++e)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) st.b[nb][e] = In[(jl + e) * KP + nb * 16 + li];
+    } else {
+#pragma unroll
+      for (int e = 0; e < GPL; ++e) {
+        const bool in = jl + e < je;
+        const long long jc = in ? jl + e : je - 1;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const float v = In[jc * KP + nb * 16 + li];
+          st.b[nb][e] = in ? v : 0.0f;
+        }
+      }
+    }
+  };
+  auto mma = [&](const Gemm16Step<NB, GPL>& st) {
+#pragma unroll
+    for (int h = 0; h < GPL / 8; ++h)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        bf16x8 hi, lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float x = st.b[nb][8 * h + e];
+          hi[e] = (__bf16)x;
+          lo[e] = (__bf16)(x - (float)hi[e]);
+        }
+#pragma unroll
+        for (int t = 0; t < kGT; ++t) {
+          acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(st.a[t][h], hi, acc[t][nb], 0, 0, 0);
+          acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(st.a[t][h], lo, acc[t][nb], 0, 0, 0);
+        }
+      }
+  };
+  if (jb < je) {
+    Gemm16Step<NB, GPL> s0, s1;
+    load(s0, jb);
+    for (long long j0 = jb;;) {
+      const long long j1 = j0 + ST;
+      if (j1 < je) load(s1, j1);
+      mma(s0);
+      if (j1 >= je) break;
+      const long long j2 = j1 + ST;
+      if (j2 < je) load(s0, j2);
+      mma(s1);
+      if (j2 >= je) break;
+      j0 = j2;
+    }
+  }
+  float* o = out + (long long)blockIdx.y * rows * KP;
+#pragma unroll
+  for (int t = 0; t < kGT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long row = row0 + t * 16 + 4 * lq + r;
+      if (row < rows) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) o[row * KP + nb * 16 + li] = acc[t][nb][r];
+      }
+    }
+}
+
+void rows_gemm16(const void* T, long long rows, long long cols, const float* In, int kp, float* out, int S,
+                 hipStream_t s) {
+  APL_REQUIRE(rows >= 1 && cols >= 1 && S >= 1, "rows_gemm16: empty product");
+  const long long kchunk = ((cols + S - 1) / S + 63) / 64 * 64;
+  const dim3 g((unsigned)ceil_div(rows, kGRows), (unsigned)S);
+  const long long NJ = (cols + 63) / 64;
+  const __bf16* M = (const __bf16*)T;
+  switch (kp) {
+    case 16:
+      hipLaunchKernelGGL((k_rows_gemm16<1, 16>), g, dim3(kBlock), 0, s, M, rows, cols, NJ, In, out, kchunk);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_rows_gemm16<2, 16>), g, dim3(kBlock), 0, s, M, rows, cols, NJ, In, out, kchunk);
+      break;
+    case 64:
+      hipLaunchKernelGGL((k_rows_gemm16<4, 8>), g, dim3(kBlock), 0, s, M, rows, cols, NJ, In, out, kchunk);
+      break;
+    default: APL_REQUIRE(false, "rows_gemm16: kp must be 16, 32 or 64");
+  }
+}
+
+
 void pack_cols(const double* X, long long ldx, long long rows, int k, double* Xp, int kp, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_cols, dim3(elem_grid(rows * kp)), dim3(kBlock), 0, s, X, ldx, rows, k, Xp, kp);
+  hipLaunchKernelGGL(k_pack_cols<double>, dim3(elem_grid(rows * kp)), dim3(kBlock), 0, s, X, ldx, rows, k, Xp, kp);
 }
 void unpack_cols(const double* Xp, int kp, long long rows, int k, double* X, long long ldx, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack_cols, dim3(elem_grid(rows * k)), dim3(kBlock), 0, s, Xp, kp, rows, k, X, ldx);
 }
 
-void blk_matmat(const BlkOp& A, bool trans, const double* In, int kp, int k, double* Y, long long ldy, hipStream_t s,
-                double* part) {
+void blk_matmat(const BlkOp& A, bool trans, const double* X, long long ldx, int kp, int k, double* Y, long long ldy,
+                int prec, void* in, void* part, hipStream_t s) {
   const long long rows = trans ? A.n : A.m, cols = trans ? A.m : A.n, ld = trans ? A.ldt : A.ld;
   const void* M = trans ? A.At : A.A;
   const int S = trans ? A.Sn : A.Sm;
-  if (A.f64)
-    rows_gemm<double, double, double>((const double*)M, rows, cols, ld, In, kp, part, S, s);
+  const unsigned gi = elem_grid(cols * kp), go = elem_grid(rows * k);
+  if (prec == 0) {
+    hipLaunchKernelGGL(k_pack_cols<double>, dim3(gi), dim3(kBlock), 0, s, X, ldx, cols, k, (double*)in, kp);
+    if (A.f64)
+      rows_gemm<double, double, double>((const double*)M, rows, cols, ld, (const double*)in, kp, (double*)part, S, s);
+    else
+      rows_gemm<float, double, double>((const float*)M, rows, cols, ld, (const double*)in, kp, (double*)part, S, s);
+    hipLaunchKernelGGL(k_planes_to_cols<double>, dim3(go), dim3(kBlock), 0, s, (const double*)part, S, rows, kp, k, Y,
+                       ldy);
+    return;
+  }
+  APL_REQUIRE(!A.f64 && (prec == 1 || A.A16), "blk_matmat: no FP32 / BF16 operator");
+  hipLaunchKernelGGL(k_pack_cols<float>, dim3(gi), dim3(kBlock), 0, s, X, ldx, cols, k, (float*)in, kp);
+  if (prec == 1)
+    rows_gemm<float, float, float>((const float*)M, rows, cols, ld, (const float*)in, kp, (float*)part, S, s);
   else
-    rows_gemm<float, double, double>((const float*)M, rows, cols, ld, In, kp, part, S, s);
-  hipLaunchKernelGGL(k_planes_to_cols, dim3(elem_grid(rows * k)), dim3(kBlock), 0, s, (const double*)part, S, rows, kp,
-                     k, Y, ldy);
+    rows_gemm16(trans ? A.At16 : A.A16, rows, cols, (const float*)in, kp, (float*)part, S, s);
+  hipLaunchKernelGGL(k_planes_to_cols<float>, dim3(go), dim3(kBlock), 0, s, (const float*)part, S, rows, kp, k, Y, ldy);
 }
 
 // ---------------------------------------------------------------- per-column reductions
@@ -641,6 +818,12 @@ static void blk_prod(const BlkOp& A, bool trans, const V* in, int kp, V* out, hi
   const long long rows = trans ? A.n : A.m, cols = trans ? A.m : A.n, ld = trans ? A.ldt : A.ld;
   const void* M = trans ? A.At : A.A;
   const int S = trans ? A.Sn : A.Sm;
+  if constexpr (std::is_same<V, float>::value) {
+    if (A.A16) {
+      rows_gemm16(trans ? A.At16 : A.A16, rows, cols, in, kp, out, S, s);
+      return;
+    }
+  }
   if (A.f64)
     rows_gemm<double, V, V>((const double*)M, rows, cols, ld, in, kp, out, S, s);
   else

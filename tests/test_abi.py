@@ -33,7 +33,8 @@ def test_struct_layouts_match_header():
     # sizes fixed by the header's field lists (natural alignment, x86-64)
     assert ctypes.sizeof(_lib.Mat) == 4 + 4 + 8 * 4 + 8 * 3
     assert ctypes.sizeof(_lib.Opts) == 8 + 8 + 8 * 6 + 4 * 5 + 4 * 7 + 0
-    assert ctypes.sizeof(_lib.Info) == 4 * 6 + 8 * 7
+    assert ctypes.sizeof(_lib.Info) == 4 * 8 + 8 * 7
+    assert _lib.Info.eta.offset == 32
 
 
 def test_defaults_and_errors_without_gpu():
@@ -51,4 +52,9 @@ def test_defaults_and_errors_without_gpu():
     m.val = 1  # non-null but mu = 0 with m < n is rejected before any device access
     assert lib.aplicur_sketch(ctypes.byref(m), ctypes.byref(o), None, ctypes.byref(ctx)) == _lib.E_INVALID
     assert b"m >= n" in lib.aplicur_last_error()
+    m2 = _lib.Mat(_lib.DENSE, _lib.F64, 20, 10, 10, 0, 1, None, None)
+    o.precision = 3
+    assert lib.aplicur_sketch(ctypes.byref(m2), ctypes.byref(o), None, ctypes.byref(ctx)) == _lib.E_INVALID
+    assert b"precision" in lib.aplicur_last_error()
+    o.precision = 0
     assert lib.aplicur_ctx_query(None, 1, None, 0) == _lib.E_INVALID

@@ -176,7 +176,7 @@ def test_blocked_fp32_adjoint(lib):
     assert np.abs(Z.cpu().numpy() - Zr).max() <= 1e-7 * np.abs(Zr).max()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_blocked_kernel_workload_half_size(lib, precision):
     """The configuration bench.py times for several right-hand sides (RBF
     kernel on 20000 points, FP32 A, 16 RHS, mu = 1e-3, block 250): every
@@ -193,3 +193,94 @@ def test_blocked_kernel_workload_half_size(lib, precision):
     eta = np.linalg.norm(N, axis=0) / atb
     assert np.all(eta <= 1.05 * tol), eta
     assert abs(eta.max() - info.eta) <= 1e-2 * tol
+
+
+def _bf16(a):
+    """Round-to-nearest-even BF16 values of an FP32 array, widened to FP64."""
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("m,n,k,pad", [(1000, 237, 5, 0), (333, 1025, 16, 0), (1201, 64, 17, 3),
+                                       (130, 2050, 40, 1), (517, 129, 70, 0)])
+def test_matmat_low_precision_products(lib, prec, dtype, m, n, k, pad):
+    """The FP32 (prec 1) and BF16 (prec 2) products of the low-precision
+    phases against the FP64 product of the rounded operands: X rounded to
+    FP32, A to FP32 (and to BF16 for prec 2; the tiles pad rows to 32 and
+    columns to 64).  Bound per entry: FP32 accumulation over the reduction
+    length plus the S plane sums, gamma_(len+64) with u = 2^-24, and for prec
+    2 the two-part BF16 split of X (|x - hi - lo| <= 2^-18 |x|)."""
+    r = np.random.default_rng(m + n + k + 7 * prec)
+    A = r.standard_normal((m, n)) * np.exp(r.uniform(-2, 2, (m, n)))
+    big = torch.zeros((m, n + pad), device=DEV, dtype=dtype)
+    big[:, :n] = _t(A, dtype)
+    A32 = A.astype(np.float32).astype(np.float64)
+    Aq = _bf16(A32) if prec == 2 else A32
+    X, U = r.standard_normal((n, k)), r.standard_normal((m, k))
+    X32, U32 = X.astype(np.float32).astype(np.float64), U.astype(np.float32).astype(np.float64)
+    with lib.Context(big[:, :n], mu=1e-3, precond=False, precision=prec) as ctx:
+        Y = ctx.matmat(_t(X), prec=prec).cpu().numpy()
+        Z = ctx.matmat(_t(U), trans=True, prec=prec).cpu().numpy()
+    split = 2.0 ** -18 if prec == 2 else 0.0
+    u = 2.0 ** -24
+    ref_y, ref_z = Aq @ X32, Aq.T @ U32
+    abs_y, abs_z = np.abs(Aq) @ np.abs(X32), np.abs(Aq).T @ np.abs(U32)
+    assert np.all(np.abs(Y - ref_y) <= ((n + 64) * u + split) * abs_y)
+    assert np.all(np.abs(Z - ref_z) <= ((m + 64) * u + split) * abs_z)
+    if prec == 2:  # the BF16 rounding of A is really there
+        assert np.abs(Y - A32 @ X32).max() > 10 * np.abs(Y - ref_y).max()
+
+
+def test_matmat_prec_needs_the_operator(lib):
+    A = _t(_dense(200, 40, 3))
+    with lib.Context(A, mu=1e-3, precond=False) as ctx:
+        with pytest.raises(RuntimeError, match="prec 1"):
+            ctx.matmat(_t(np.ones((40, 2))), prec=1)
+    with lib.Context(A, mu=1e-3, precond=False, precision=1) as ctx:
+        with pytest.raises(RuntimeError, match="prec 2"):
+            ctx.matmat(_t(np.ones((40, 2))), prec=2)
+
+
+@pytest.mark.parametrize("a_dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("precond", [False, True])
+@pytest.mark.parametrize("mu", [1e-4, 0.0])
+def test_blocked_bf16_phases_reach_fp64_tolerance(lib, a_dtype, precond, mu):
+    """Precision 2: BF16 products in the low-precision phases, FP32 products
+    once a BF16 phase gains too little, FP64 refinement: every column reaches
+    the FP64 tolerance."""
+    m, n, tol = 800, 90, 1e-10
+    A = _dense(m, n, 60, decades=4)
+    if a_dtype == torch.float32:
+        A = A.astype(np.float32).astype(np.float64)
+    B = np.random.default_rng(61).standard_normal((m, 5))
+    X, info = lib.lstsq(_t(A, a_dtype), _t(B), mu=mu, block=10, tol_ne=tol, precond=precond, precision=2)
+    assert info.status == 0
+    assert info.phases_bf16 >= 1
+    _check_columns(A, B, X.cpu().numpy(), mu, tol)
+
+
+def test_blocked_bf16_well_conditioned_stays_bf16(lib):
+    """A well-conditioned problem: the BF16 phases divide eta by more than 10
+    each, so the ladder keeps them; the FP64 tolerance is still reached."""
+    m, n, mu, tol = 1500, 100, 1e-2, 1e-10
+    A = _dense(m, n, 64, decades=0.5)
+    B = np.random.default_rng(65).standard_normal((m, 3))
+    X, info = lib.lstsq(_t(A), _t(B), mu=mu, tol_ne=tol, precond=False, precision=2)
+    assert info.status == 0
+    assert info.phases_bf16 == info.phases
+    _check_columns(A, B, X.cpu().numpy(), mu, tol)
+
+
+def test_blocked_bf16_adjoint(lib):
+    r = np.random.default_rng(66)
+    A = synth.dense_svd(r, 500, 70, 10.0 ** (-2 * np.arange(70) / 69))
+    B = r.standard_normal((500, 4))
+    G = r.standard_normal((70, 4))
+    mu = 1e-3
+    with lib.Context(_t(A), mu=mu, block=8, tol_ne=1e-11, precision=2) as ctx:
+        X, _ = ctx.solve(_t(B))
+        Z, dB, dA, info = ctx.solve_backward(X, _t(B), _t(G), want_dA=False)
+    Zr = np.linalg.solve(A.T @ A + mu * np.eye(70), G)
+    assert info.eta <= 1.5e-11
+    assert np.abs(Z.cpu().numpy() - Zr).max() <= 1e-7 * np.abs(Zr).max()
