@@ -617,7 +617,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
       c->Kr = c->arena.alloc<double>((size_t)L * L);
       c->d = c->arena.alloc<double>(L);
       c->pinfo = c->arena.alloc<double>(4);
-      c->offmax = c->arena.alloc<unsigned long long>(1);
+      c->offmax = c->arena.alloc<unsigned long long>(2);
       c->pa_c = c->arena.alloc<double>(L);
       c->prec.c = c->pa_c;
       c->prec.d = c->d;
@@ -917,9 +917,17 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ preconditioner (Alg. 2 Part 2)
-// Sweeps of the one-sided Jacobi SVD end when every column pair's relative
-// off-diagonal Gram entry is at most this.
-constexpr double kJacobiTol = 1e-14;
+// The one-sided Jacobi SVD of the core M stops when the off-diagonal of the
+// Gram matrix of the damped core [M; delta I] (entries scaled to unit
+// diagonal) has Frobenius norm at most kJacobiTol.  With V the accumulated
+// rotations (orthogonal to rounding) and Lambda_i^2 = ||M v_i||^2 + delta^2,
+// the core part of the preconditioned Gram, diag(sigma_hat / Lambda) V^T (M^T
+// M + delta^2 I) V diag(sigma_hat / Lambda), is sigma_hat^2 (I + E) with that
+// off-diagonal E, so its singular values lie within sqrt(1 +- kJacobiTol) of
+// the exact-SVD value sigma_hat.  Pairs below kJacobiSkip are not rotated
+// (their entries add at most l kJacobiSkip to the norm).
+constexpr double kJacobiTol = 1e-2;
+constexpr double kJacobiSkip = 1e-9;
 // Largest diagonal ratio of T_R for which the one-product form M2 is used.
 constexpr double kM2MaxDiagRatio = 1e3;
 
@@ -932,7 +940,8 @@ static void build_precond(Ctx& c, hipStream_t s) {
   gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Kr, l);
   gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Mx, L);
   set_identity(c.Vm, lp, lp, s);
-  c.sweep_hist.push_back(jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.offmax, kJacobiTol, 40, s));
+  c.sweep_hist.push_back(
+      jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.offmax, c.delta * c.delta, kJacobiTol, kJacobiSkip, 40, s));
   precond_scalars(c.sigma, l, c.delta, c.d, c.pinfo, s);
   if (c.prec.implicit) {
     // K = T_R^{-1} V_M (column-major, ld l: the row-major K^T) and K row-major

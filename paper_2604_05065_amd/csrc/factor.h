@@ -78,8 +78,16 @@ void laswp(double* A, long long ld, int ncols, int c0, int c1, const int* piv, i
 void zero_lower(double* G, long long ld, int k, hipStream_t s);
 
 int jacobi_block_width();
+// One-sided block Jacobi SVD of X (n x npad, column-major; columns n.. zero):
+// X <- X V, Vm <- Vm V (Vm = I on entry, npad x npad), sigma[i] = ||X(:, i)||
+// for i < n.  Sweeps end once the Frobenius norm of the off-diagonal of the
+// damped, scaled Gram matrix, e_pq = |g_pq| / sqrt((g_pp + delta2)(g_qq +
+// delta2)), summed as the sweep met each block pair, is at most tol_f; a block
+// pair with every e_pq <= skip is not rotated.  off_dev: two device words of
+// scratch.  Returns the number of sweeps.
 int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
-               unsigned long long* offmax_dev, double tol, int max_sweeps, hipStream_t s);
+               unsigned long long* off_dev, double delta2, double tol_f, double skip, int max_sweeps,
+               hipStream_t s);
 void precond_scalars(const double* sigma, int l, double delta, double* d, double* info, hipStream_t s);
 void rho_from_ew(const double* EW, int s_rows, int r, double* out, hipStream_t s);
 

@@ -553,11 +553,16 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 // column-block-pair: for the pair of width 2*kJW, the Gram matrix is formed
 // (FP64 MFMA), diagonalised by cyclic Jacobi in LDS, and the rotation applied to the
 // columns of X and of V.  Round-robin pairing covers every block pair once
-// per sweep (Hestenes' method, block form).  sweepmax receives the largest
-// relative off-diagonal |g_pq| / sqrt(g_pp g_qq) seen in the round.  Each
-// round takes a few inner sweeps on the pair's Gram matrix only (the outer
-// sweeps repeat the pairing until the whole matrix is orthogonal), and a
-// pair that is already orthogonal to the skip level leaves X and V as they are.
+// per sweep (Hestenes' method, block form).  Off-diagonal entries are measured
+// on the damped Gram matrix X^T X + d2 I (d2 = delta^2: the columns of the
+// damped core [X; delta V], whose right singular vectors are X's):
+// e_pq = |g_pq| / sqrt((g_pp + d2)(g_qq + d2)).  off[0] receives the largest
+// e_pq of the round (as the bits of a non-negative double), off[1] the sum of
+// e_pq^2 over the entries between the pair's two blocks, so that a sweep adds
+// up each such entry once.  Each round takes one inner sweep on the pair's
+// Gram matrix only (the outer sweeps repeat the pairing until the whole
+// matrix is orthogonal), and a pair whose largest e_pq is at most `skip`
+// leaves X and V as they are.
 constexpr int kJW = 8;        // columns per block
 constexpr int kJP = 2 * kJW;  // columns per pair
 constexpr int kJInner = 1;    // inner sweeps per pair and round
@@ -583,13 +588,13 @@ __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, i
 
 __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, int rows, double* Vm,
                                                          long long ldv, int vrows, int nblk, int round,
-                                                         unsigned long long* offmax, double skip) {
+                                                         unsigned long long* off, double d2, double skip) {
   __shared__ double G[2][kJP][kJP + 1];  // double-buffered rotations
   __shared__ double Q[2][kJP][kJP + 1];
   __shared__ double tile[kJR][kJP + 1];
   __shared__ double cs[kJP], sn[kJP];    // per index: its pair's rotation
   __shared__ int mate[kJP], lowr[kJP];   // partner index; 1 if the index is the pair's p
-  __shared__ double wmax[kJT / kWave];
+  __shared__ double wmax[kJT / kWave], wsq[kJT / kWave];
   int a, b;
   pair_of(round, nblk, blockIdx.x, a, b);
   int col[2] = {a * kJW, b * kJW};
@@ -635,21 +640,35 @@ __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, 
     Q[0][i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
+  double sq = 0.0;
   if (tid < kJP * kJP) {
     const int i = tid % kJP, j = tid / kJP;
     if (i < j) {
-      const double d = sqrt(G[0][i][i] * G[0][j][j]);
+      const double d = sqrt((G[0][i][i] + d2) * (G[0][j][j] + d2));
       if (d > 0.0) mx = fabs(G[0][i][j]) / d;
+      if (i < kJW && j >= kJW) sq = mx * mx;
     }
   }
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
-  if (lane == 0) wmax[wave] = mx;
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o, kWave));
+    sq += __shfl_xor(sq, o, kWave);
+  }
+  if (lane == 0) {
+    wmax[wave] = mx;
+    wsq[wave] = sq;
+  }
   __syncthreads();
-  double block_off = 0.0;
+  double block_off = 0.0, block_sq = 0.0;
 #pragma unroll
-  for (int w = 0; w < kJT / kWave; ++w) block_off = fmax(block_off, wmax[w]);
-  if (tid == 0) atomicMax(offmax, (unsigned long long)__double_as_longlong(block_off));
+  for (int w = 0; w < kJT / kWave; ++w) {
+    block_off = fmax(block_off, wmax[w]);
+    block_sq += wsq[w];
+  }
+  if (tid == 0) {
+    atomicMax(off, (unsigned long long)__double_as_longlong(block_off));
+    atomicAdd((double*)(off + 1), block_sq);
+  }
   if (block_off <= skip) return;  // uniform
   // 2) cyclic Jacobi on G (kJP x kJP): kJP - 1 rounds of kJW disjoint
   //    rotations (round-robin); each round G <- J^T G J and Q <- Q J computed
@@ -739,21 +758,23 @@ __global__ void k_col_norms(const double* X, long long ldx, int rows, int ncols,
 }
 
 int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
-               unsigned long long* offmax_dev, double tol, int max_sweeps, hipStream_t s) {
+               unsigned long long* off_dev, double delta2, double tol_f, double skip, int max_sweeps,
+               hipStream_t s) {
   // X: n x npad (columns n..npad-1 zero), Vm: npad x npad, set to I by the caller.
   const int nblk = npad / kJW;
   int sweeps = 0;
   for (; sweeps < max_sweeps; ++sweeps) {
-    APL_HIP(hipMemsetAsync(offmax_dev, 0, sizeof(unsigned long long), s));
+    APL_HIP(hipMemsetAsync(off_dev, 0, 2 * sizeof(unsigned long long), s));
     for (int r = 0; r < nblk - 1; ++r)
       hipLaunchKernelGGL(k_jacobi_round, dim3(nblk / 2), dim3(kJT), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
-                         offmax_dev, 0.01 * tol);
-    unsigned long long h = 0;
-    APL_HIP(hipMemcpyAsync(&h, offmax_dev, sizeof(h), hipMemcpyDeviceToHost, s));
+                         off_dev, delta2, skip);
+    unsigned long long h[2] = {0, 0};
+    APL_HIP(hipMemcpyAsync(h, off_dev, sizeof(h), hipMemcpyDeviceToHost, s));
     APL_HIP(hipStreamSynchronize(s));
-    double off;
-    memcpy(&off, &h, sizeof(off));
-    if (off <= tol) {
+    double sum_sq;
+    memcpy(&sum_sq, &h[1], sizeof(sum_sq));
+    // Frobenius norm of the damped off-diagonal (both triangles) as the sweep saw it
+    if (std::sqrt(2.0 * sum_sq) <= tol_f) {
       ++sweeps;
       break;
     }
