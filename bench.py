@@ -261,11 +261,24 @@ def main():
         ctx.time_product(xv, trans=False, reps=10)
         us_a = ctx.time_product(xv, trans=False, reps=PRODUCT_REPS)
         us_at = ctx.time_product(xv, trans=True, reps=PRODUCT_REPS)
+        # cold caches: 1 GiB read and written before each timed round (the
+        # product's matrix then comes from HBM, not from L2 or the 256 MB
+        # last-level cache that holds it in the LSQR loop)
+        # (not in --products-only runs, whose kernel statistics are the warm loop's)
+        us_a_cold = us_at_cold = float("nan")
+        if not args.products_only:
+            flush = torch.zeros(1 << 28, dtype=torch.int32, device="cuda")
+            us_a_cold = ctx.time_product(xv, trans=False, reps=20, flush=flush)
+            us_at_cold = ctx.time_product(xv, trans=True, reps=20, flush=flush)
+            del flush
     bytes_a = spmv_bytes(m, n, nnz)
     bytes_at = spmv_bytes(n, m, nnz) - n * 8  # A^T kernel stores its output without reading it
     gbs_a = bytes_a / (us_a * 1e-6) / 1e9
     gbs_at = bytes_at / (us_at * 1e-6) / 1e9
     log(f"[bench] A x: {us_a:.2f} us/launch -> {gbs_a:.0f} GB/s; A^T u: {us_at:.2f} us -> {gbs_at:.0f} GB/s")
+    if not args.products_only:
+        log(f"[bench] cold caches: A x {us_a_cold:.2f} us -> {bytes_a / us_a_cold / 1e3:.0f} GB/s; "
+            f"A^T u {us_at_cold:.2f} us -> {bytes_at / us_at_cold / 1e3:.0f} GB/s")
     if args.products_only:
         big = torch.empty(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
         dst = torch.empty_like(big)
@@ -351,7 +364,9 @@ def main():
         "adjoint": adjoint,
         "multi_rhs": multi,
         "matvec": {"A_us": round(us_a, 3), "A_GBs": round(gbs_a, 1), "AT_us": round(us_at, 3),
-                   "AT_GBs": round(gbs_at, 1), "AT_bytes": int(bytes_at)},
+                   "AT_GBs": round(gbs_at, 1), "AT_bytes": int(bytes_at),
+                   "A_us_cold": round(us_a_cold, 3), "A_GBs_cold": round(bytes_a / us_a_cold / 1e3, 1),
+                   "AT_us_cold": round(us_at_cold, 3), "AT_GBs_cold": round(bytes_at / us_at_cold / 1e3, 1)},
     }
     print(json.dumps(out), flush=True)
 

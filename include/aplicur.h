@@ -215,9 +215,15 @@ int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx
  * product (trans = 0) or of the A^T product (trans = 1) on `stream`
  * (hipExtLaunchKernelGGL start/stop events).
  * x: n doubles, y: m doubles (scratch; final contents unspecified).
- * *us_per_launch (host) receives the mean duration in microseconds.        */
-int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* stream,
-                         double* us_per_launch);
+ * flush (device, optional): a caller buffer of flush_bytes bytes (a
+ * multiple of 16; contents overwritten) that is read and written before
+ * each round, so that the timed product finds its matrix in neither L2
+ * nor the 256 MB last-level cache (cold-cache timing; give at least 512
+ * MB).  NULL: warm caches, as in the LSQR loop.
+ * *us_per_launch (host) receives the mean duration in microseconds.
+ * Errors: E_INVALID, E_HIP.                                                */
+int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* flush,
+                         int64_t flush_bytes, void* stream, double* us_per_launch);
 
 /* Read internal state back to host memory (tests and diagnostics).
  * what: 1 sketch Y (s x n row-major doubles), 2 sketch rows (m x xi int32),

@@ -72,7 +72,7 @@ def load():
     lib.aplicur_matvec.restype = C.c_int
     lib.aplicur_matmat.argtypes = [vp, i32, dp, i64, i32, dp, i64, i32, vp]
     lib.aplicur_matmat.restype = C.c_int
-    lib.aplicur_time_product.argtypes = [vp, i32, dp, dp, i32, vp, C.POINTER(C.c_double)]
+    lib.aplicur_time_product.argtypes = [vp, i32, dp, dp, i32, vp, i64, vp, C.POINTER(C.c_double)]
     lib.aplicur_time_product.restype = C.c_int
     lib.aplicur_ctx_query.argtypes = [vp, i32, vp, C.c_size_t]
     lib.aplicur_ctx_query.restype = i64

@@ -162,16 +162,19 @@ class Context:
         Y = Yt.t()
         return Y.reshape(-1) if one else Y
 
-    def time_product(self, x, trans=False, reps=100):
+    def time_product(self, x, trans=False, reps=100, flush=None):
         """Mean duration (us) of one launch of the A (or A^T) product kernel,
-        A and A^T products alternating; x has n entries."""
+        A and A^T products alternating; x has n entries.  flush: a device
+        buffer (overwritten) read and written before each round, for
+        cold-cache timing."""
         x = x.to(torch.float64).contiguous()
         if x.numel() != self.n:
             raise ValueError("x must have n entries")
         y = torch.empty(self.m, dtype=torch.float64, device=x.device)
         us = C.c_double()
+        fptr, fbytes = (flush.data_ptr(), flush.numel() * flush.element_size()) if flush is not None else (None, 0)
         L.check(self.lib.aplicur_time_product(self.ptr, int(bool(trans)), x.data_ptr(), y.data_ptr(), int(reps),
-                                              _stream(), C.byref(us)))
+                                              fptr, int(fbytes), _stream(), C.byref(us)))
         return us.value
 
     def query(self, what):

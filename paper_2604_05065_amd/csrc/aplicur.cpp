@@ -2123,10 +2123,11 @@ int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx
   });
 }
 
-int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* stream,
-                         double* us_per_launch) {
+int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* flush,
+                         int64_t flush_bytes, void* stream, double* us_per_launch) {
   return guarded([&]() {
     APL_REQUIRE(ctx && ctx->impl && x && y && us_per_launch && reps >= 1, "bad argument");
+    APL_REQUIRE(!flush || (flush_bytes >= 16 && flush_bytes % 16 == 0), "flush_bytes must be a positive multiple of 16");
     Ctx& c = *ctx->impl;
     hipStream_t s = (hipStream_t)stream;
     // y (m) = A x - y ; scratch (n) = A^T y, alternating as in the LSQR loop
@@ -2136,6 +2137,7 @@ int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, doubl
     std::vector<hipEvent_t> ev(2 * (size_t)reps);
     for (auto& e : ev) APL_HIP(hipEventCreate(&e));
     for (int i = 0; i < reps; ++i) {
+      if (flush) touch_buffer(flush, flush_bytes, s);
       if (!trans) {
         op_matvec(c.op, 0, x, y, c.st_mv, c.wk, s, ev[2 * i], ev[2 * i + 1]);
         op_matvec(c.op, 1, y, c.g, c.st_mv, c.wk, s);

@@ -355,6 +355,25 @@ void zero_rows(double* X, long long ldx, const int* rows, int nr, int ncols, hip
                      ncols);
 }
 
+// Adds one to every 32-bit word of buf (bytes a multiple of 16): a read and a
+// write of the whole buffer, which evicts other data from the caches.
+__global__ void k_touch(uint4* buf, long long n16) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (long long)gridDim.x * kBlock) {
+    uint4 v = buf[i];
+    v.x += 1u;
+    v.y += 1u;
+    v.z += 1u;
+    v.w += 1u;
+    buf[i] = v;
+  }
+}
+
+void touch_buffer(void* buf, long long bytes, hipStream_t s) {
+  const long long n16 = bytes / 16;
+  hipLaunchKernelGGL(k_touch, dim3((unsigned)std::min<long long>(ceil_div(n16, kBlock), 8192)), dim3(kBlock), 0, s,
+                     (uint4*)buf, n16);
+}
+
 void fill(double* X, long long n, double v, hipStream_t s) {
   if (n <= 0) return;
   unsigned g = ceil_div(n, kBlock);

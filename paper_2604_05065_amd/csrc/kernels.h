@@ -139,6 +139,9 @@ constexpr long long kLxMinNnz = 1500000;
 // SELL-64 launch shape: slices per workgroup and workgroups.
 void sell_layout(long long nslices, long long n, int* spw, int* grid);
 void gk_prepare();               // once per process: kernel attributes
+// A read and a write of every byte of buf (bytes a multiple of 16), enqueued
+// on s: evicts other data from the caches (cold-cache timing).
+void touch_buffer(void* buf, long long bytes, hipStream_t s);
 // SELL-64 copy: slice widths (returns padded entries), then the fill.
 long long sell_widths(const int* rp, long long m, int* wid_dev, std::vector<int>& wid_host, hipStream_t s);
 template <class TA>

@@ -332,3 +332,24 @@ def test_rank_cap_matches_oracle(lib):
     assert ranks == tr.ranks == [10, 20, 25]
     assert info.eta <= 1.5e-10
     assert np.linalg.norm(x.cpu().numpy() - x_or) <= 1e-6 * np.linalg.norm(x_or)
+
+
+def test_product_timer_warm_and_cold(lib):
+    """aplicur_time_product: finite positive durations with warm caches and
+    with a flush buffer read and written before each timed launch; the flush
+    leaves the product's result unchanged (y is recomputed each round) and
+    bad flush sizes are rejected."""
+    A = _csr(20000, 2000, 8, 31, decades=2)
+    x = np.random.default_rng(31).standard_normal(2000)
+    flush = torch.zeros(1 << 24, dtype=torch.int32, device=DEV)  # 64 MiB
+    with lib.Context(_gpu_csr(A), mu=1e-4, precond=False) as ctx:
+        xv = _t(x)
+        warm = ctx.time_product(xv, reps=5)
+        cold = ctx.time_product(xv, reps=5, flush=flush)
+        cold_t = ctx.time_product(xv, trans=True, reps=5, flush=flush)
+        assert all(np.isfinite(v) and v > 0 for v in (warm, cold, cold_t))
+        assert int(flush[0]) == 10 and int(flush[-1]) == 10  # one pass per round
+        with pytest.raises(RuntimeError, match="flush_bytes"):
+            ctx.time_product(xv, reps=1, flush=flush[:3])
+        y = ctx.matvec(xv).cpu().numpy()
+    assert np.abs(y - A @ x).max() <= 1e-13 * (abs(A) @ np.abs(x)).max()
