@@ -187,23 +187,25 @@ def bench_multi_rhs(ap, synth, torch, npts=20000, nrhs=16):
     return out
 
 
-def blocked_products(ap, synth, torch, npts=20000, nrhs=16, rounds=20):
+def blocked_products(ap, synth, torch, npts=20000, nrhs=16, rounds=20, prec=0):
     """The blocked products alone (A X and A^T U, 16 columns, FP32 RBF kernel
-    on 20000 points) alternating for `rounds` rounds after a warm-up, event
-    timed, then three copies of 256 MiB used to calibrate the hardware
-    counters.  One JSON line."""
+    on 20000 points; prec 0: FP64 accumulation, 1: FP32 products, 2: BF16
+    products) alternating for `rounds` rounds after a warm-up, event timed,
+    then three copies of 256 MiB used to calibrate the hardware counters.
+    One JSON line; bytes_A is the matrix as the kernel reads it (FP32, or the
+    padded BF16 copy)."""
     A, _ = synth.rbf_kernel_gpu(3003, npts, nrhs)
-    with ap.Context(A, precond=False, mu=1e-3) as ctx:
+    with ap.Context(A, precond=False, mu=1e-3, precision=prec) as ctx:
         X = torch.randn(npts, nrhs, device="cuda", dtype=torch.float64)
-        ctx.matmat(X)
-        ctx.matmat(X, trans=True)
+        ctx.matmat(X, prec=prec)
+        ctx.matmat(X, trans=True, prec=prec)
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ta = tt = 0.0
         for _ in range(rounds):
             e[0].record()
-            ctx.matmat(X)
+            ctx.matmat(X, prec=prec)
             e[1].record()
-            ctx.matmat(X, trans=True)
+            ctx.matmat(X, trans=True, prec=prec)
             e[2].record()
             torch.cuda.synchronize()
             ta += e[0].elapsed_time(e[1])
@@ -214,7 +216,9 @@ def blocked_products(ap, synth, torch, npts=20000, nrhs=16, rounds=20):
         dst.copy_(big)
     torch.cuda.synchronize()
     bytes_a = A.numel() * A.element_size()
-    print(json.dumps({"ms_AX": ta / rounds, "ms_ATU": tt / rounds, "bytes_A": bytes_a, "nrhs": nrhs,
+    if prec == 2:
+        bytes_a = ((npts + 31) // 32 * 32) * ((npts + 63) // 64 * 64) * 2
+    print(json.dumps({"ms_AX": ta / rounds, "ms_ATU": tt / rounds, "bytes_A": bytes_a, "nrhs": nrhs, "prec": prec,
                       "GBs_AX": bytes_a / (ta / rounds) / 1e6, "GBs_ATU": bytes_a / (tt / rounds) / 1e6,
                       "copy_bytes_each_way": big.numel() * 8}), flush=True)
 
@@ -230,6 +234,8 @@ def main():
     ap_.add_argument("--products-only", action="store_true")
     ap_.add_argument("--blocked-products", action="store_true",
                      help="only the blocked products (FP32 RBF kernel 20000^2, 16 columns) and the calibration copy")
+    ap_.add_argument("--blocked-prec", type=int, default=0, choices=(0, 1, 2),
+                     help="arithmetic of --blocked-products: 0 FP64 accumulation, 1 FP32, 2 BF16")
     ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
     args = ap_.parse_args()
     if args.gpus != 1:
@@ -243,7 +249,7 @@ def main():
     from workloads import synth
 
     if args.blocked_products:
-        blocked_products(ap, synth, torch)
+        blocked_products(ap, synth, torch, prec=args.blocked_prec)
         return
 
     t0 = time.time()
