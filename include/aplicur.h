@@ -135,13 +135,33 @@ typedef struct aplicur_ctx aplicur_ctx;
  * eps_lsqr 1e-10, tol_ne 1e-8, r_probes 10, seed 7, mu 0).                */
 void aplicur_opts_default(aplicur_opts* opts /* (host) */);
 
+/* Device memory a context needs for solves (and adjoint solves) with up to
+ * nrhs right-hand sides: its set-up buffers (sketch, CUR and preconditioner
+ * storage sized by the rank cap, product layouts, LSQR vectors), the blocked
+ * path's buffers for that many columns of a dense A (and the BF16 copies at
+ * precision 2), and the transient blocks of the set-up and of the adjoint.
+ * It is measured, not estimated: the call runs the set-up of A once on
+ * `stream` with library-allocated memory and releases it.  A context used
+ * with more columns than sized for runs out of its workspace (E_NOMEM).
+ * Returns the byte count (> 0) or a negative error (E_INVALID, E_NOMEM,
+ * E_HIP).  A, opts: (host).                                                */
+int64_t aplicur_workspace_bytes(const aplicur_mat* A, int32_t nrhs, const aplicur_opts* opts, void* stream);
+
 /* Set-up of Alg. 3 (initialisation): validates A, builds the CSR of A^T
  * (CSR input), draws the sparse sign embedding S (s x m) and the probes, and
  * forms the sketch Y = S A in FP64 once (Alg. 3, initialisation; Sec. 5.1).
  * A (host struct) describes device arrays, borrowed until ctx destruction.
  * opts (host) is copied.  *ctx_out (host) receives the new context.
- * Errors: E_INVALID (shape/options), E_NOMEM, E_HIP.                       */
-int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* stream, aplicur_ctx** ctx_out);
+ * ws (device, optional): a caller workspace of ws_bytes bytes, 256-byte
+ * aligned, owned by the caller and untouched after ctx destruction; every
+ * device buffer of the context is carved from it (size it with
+ * aplicur_workspace_bytes).  ws = NULL: the library allocates with
+ * hipMalloc and frees at destruction.  Either way rocBLAS keeps the device
+ * memory of its own handle, and small pinned host buffers hold the
+ * read-backs.  Errors: E_INVALID (shape/options/alignment), E_NOMEM
+ * (allocation failed or workspace exhausted), E_HIP.                       */
+int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* ws, size_t ws_bytes, void* stream,
+                   aplicur_ctx** ctx_out);
 
 /* The adaptive solve of Alg. 3 for nrhs right-hand sides B (m x nrhs,
  * column-major, ldb >= m) into X (n x nrhs, ldx >= n).  All columns share

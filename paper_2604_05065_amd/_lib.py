@@ -40,7 +40,7 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ["aplicur_opts_default", "aplicur_sketch", "aplicur_solve", "aplicur_solve_batched",
+EXPORTS = ["aplicur_opts_default", "aplicur_workspace_bytes", "aplicur_sketch", "aplicur_solve", "aplicur_solve_batched",
            "aplicur_solve_backward", "aplicur_matvec", "aplicur_matmat", "aplicur_time_product", "aplicur_ctx_query", "aplicur_ctx_destroy",
            "aplicur_last_error", "aplicur_version"]
 
@@ -58,8 +58,10 @@ def load():
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p
     lib.aplicur_opts_default.argtypes = [C.POINTER(Opts)]
     lib.aplicur_opts_default.restype = None
-    lib.aplicur_sketch.argtypes = [C.POINTER(Mat), C.POINTER(Opts), vp, C.POINTER(vp)]
+    lib.aplicur_sketch.argtypes = [C.POINTER(Mat), C.POINTER(Opts), vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.aplicur_sketch.restype = C.c_int
+    lib.aplicur_workspace_bytes.argtypes = [C.POINTER(Mat), i32, C.POINTER(Opts), vp]
+    lib.aplicur_workspace_bytes.restype = C.c_int64
     lib.aplicur_solve.argtypes = [vp, dp, i64, i32, dp, i64, i32, C.POINTER(Info), vp]
     lib.aplicur_solve.restype = C.c_int
     lib.aplicur_solve_batched.argtypes = [i32, C.POINTER(Mat), C.POINTER(vp), C.POINTER(i64), i32,

@@ -65,6 +65,10 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _device(A):
+    return A.val.device if isinstance(A, CSRMatrix) else A.device
+
+
 def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.0, eps_lsqr=1e-10,
               tol_ne=1e-8, max_iter=100000, max_rank=0, precond=True, precision=0, max_outer=0,
               r_probes=10, workers=0, tune=0, graphs=0, columns=0):
@@ -94,13 +98,25 @@ def _cols(B, rows, name):
 class Context:
     """Sketch of A (Alg. 3 initialisation) plus the state of later solves."""
 
-    def __init__(self, A, **opts):
+    def __init__(self, A, workspace=0, **opts):
+        """workspace = k > 0: the context's device memory is one PyTorch
+        tensor sized by aplicur_workspace_bytes for solves with up to k
+        right-hand sides; 0: the library allocates it."""
         self.lib = L.load()
         self.mat, self._keep = _mat(A)
         self.m, self.n = int(self.mat.m), int(self.mat.n)
         self.opts = make_opts(**opts)
+        self.workspace = None
+        ws, ws_bytes = None, 0
+        if workspace:
+            ws_bytes = self.lib.aplicur_workspace_bytes(C.byref(self.mat), int(workspace), C.byref(self.opts),
+                                                        _stream())
+            L.check(int(ws_bytes) if ws_bytes < 0 else 0)
+            self.workspace = torch.empty(int(ws_bytes), dtype=torch.uint8, device=_device(A))
+            ws = self.workspace.data_ptr()
         ptr = C.c_void_p()
-        L.check(self.lib.aplicur_sketch(C.byref(self.mat), C.byref(self.opts), _stream(), C.byref(ptr)))
+        L.check(self.lib.aplicur_sketch(C.byref(self.mat), C.byref(self.opts), ws, int(ws_bytes), _stream(),
+                                        C.byref(ptr)))
         self.ptr = ptr
 
     def solve(self, B, X0=None):

@@ -60,11 +60,54 @@ static double ms_since(Clock::time_point t0) {
 }
 
 // Device arena: every allocation of a context, released together.
+// Device buffers of a context: from hipMalloc, or carved (256-byte aligned)
+// from a caller workspace [base, base + cap).  used counts the aligned bytes
+// of the permanent buffers, peak the most ever needed at once (permanent
+// plus the largest transient one): the workspace a context needs.
 struct Arena {
   std::vector<void*> ptrs;
+  char* base = nullptr;
+  size_t cap = 0, used = 0, peak = 0;
+  static constexpr size_t kAlign = 256;
+  static size_t aligned(size_t bytes) { return (std::max<size_t>(bytes, 1) + kAlign - 1) / kAlign * kAlign; }
+  void room(size_t bytes) const {
+    if (bytes > cap - used)
+      throw Error(APLICUR_E_NOMEM, "workspace of " + std::to_string(cap) + " bytes exhausted (" +
+                                       std::to_string(used) + " used, " + std::to_string(bytes) +
+                                       " more requested); size it with aplicur_workspace_bytes");
+  }
+  // A transient buffer that lives until the next alloc: in workspace mode the
+  // space after the permanent buffers (owned = false), else a hipMalloc the
+  // caller frees (owned = true).
+  void* transient(size_t bytes, bool& owned) {
+    bytes = aligned(bytes);
+    peak = std::max(peak, used + bytes);
+    owned = base == nullptr;
+    if (base) {
+      room(bytes);
+      return base + used;
+    }
+    void* p = nullptr;
+    SyncGuard g(g_capture_mu);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(APLICUR_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+  }
   template <class T>
   T* alloc(size_t count) {
     if (count == 0) count = 1;
+    const size_t bytes = aligned(count * sizeof(T));
+    if (base) {
+      room(bytes);
+      void* p = base + used;
+      used += bytes;
+      peak = std::max(peak, used);
+      return (T*)p;
+    }
+    used += bytes;
+    peak = std::max(peak, used);
     void* p = nullptr;
     SyncGuard g(g_capture_mu);
     hipError_t e = hipMalloc(&p, count * sizeof(T));
@@ -371,7 +414,8 @@ static void tune_tiles(Ctx& c, hipStream_t s) {
   APL_HIP(hipStreamSynchronize(s));
 }
 
-static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) {
+static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, void* ws = nullptr,
+                   size_t ws_bytes = 0) {
   validate(Am, o);
   {
     SyncGuard g(g_capture_mu);
@@ -379,6 +423,8 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
   }
   auto t0 = Clock::now();
   Ctx* c = new Ctx();
+  c->arena.base = (char*)ws;
+  c->arena.cap = ws ? ws_bytes : 0;
   try {
     c->A = *Am;
     c->o = *o;
@@ -570,11 +616,8 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
                                    c->S_neg, c->Y, s);
       } else {
         const int chunks = sketch_dense_chunks(m, n);
-        double* part = nullptr;
-        {
-          SyncGuard g(g_capture_mu);
-          APL_HIP(hipMalloc((void**)&part, sizeof(double) * (size_t)chunks * S * n));
-        }
+        bool owned = false;
+        double* part = (double*)c->arena.transient(sizeof(double) * (size_t)chunks * S * n, owned);
         if (op.f64)
           launch_sketch_dense<double>((const double*)op.val, m, n, op.ld, S, c->xi, c->S_rows, c->S_neg, c->Y,
                                       part, chunks, s);
@@ -582,8 +625,10 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s) 
           launch_sketch_dense<float>((const float*)op.val, m, n, op.ld, S, c->xi, c->S_rows, c->S_neg, c->Y,
                                      part, chunks, s);
         APL_HIP(hipStreamSynchronize(s));
-        SyncGuard g(g_capture_mu);
-        APL_HIP(hipFree(part));
+        if (owned) {
+          SyncGuard g(g_capture_mu);
+          APL_HIP(hipFree(part));
+        }
       }
       // CUR / preconditioner storage (sized by the rank cap L)
       c->I_dev = c->arena.alloc<int>(L);
@@ -1395,6 +1440,10 @@ static void ensure_blk(Ctx& c, int kp, hipStream_t s) {
     b.op.f64 = c.op.f64;
     b.op.Sm = gemm_splits(m, n);
     b.op.Sn = gemm_splits(n, m);
+    if (c.o.precond) {
+      b.ldvt = (n + 1) / 2 * 2;
+      b.Vt = c.arena.alloc<double>((size_t)std::max(c.L, 1) * b.ldvt);
+    }
   }
   if (c.fp32 && !b.op32.A) {
     b.op32 = b.op;
@@ -1469,10 +1518,7 @@ static void ensure_blk(Ctx& c, int kp, hipStream_t s) {
 static BlkPrec blk_prec(Ctx& c, hipStream_t s) {
   Blk& b = *c.blk;
   const int l = c.prec.ell;
-  if (!b.Vt) {
-    b.ldvt = (c.n + 1) / 2 * 2;
-    b.Vt = c.arena.alloc<double>((size_t)std::max(c.L, 1) * b.ldvt);
-  }
+  APL_REQUIRE(b.Vt, "blocked P buffers missing");
   if (b.vt_gen != c.prec_gen) {
     // V^T (l x n row-major) is V = Q_R V_M column-major
     const int jw2 = 2 * jacobi_block_width();
@@ -1870,11 +1916,9 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
   }
   if (dA) {
     // R = B - A X (m x k), then the rank-2k gradient
-    double* work = nullptr;
-    {
-      SyncGuard g(g_capture_mu);
-      APL_HIP(hipMalloc((void**)&work, sizeof(double) * (size_t)c.m * nrhs * 2));
-    }
+    if (blocked) ensure_blk(c, blk_kp(std::min(nrhs, kBlkMaxCols)), s);  // no allocation while work lives
+    bool owned = false;
+    double* work = (double*)c.arena.transient(sizeof(double) * (size_t)c.m * nrhs * 2, owned);
     try {
       double* AX = work;
       double* R = work + (size_t)c.m * nrhs;
@@ -1899,12 +1943,16 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
       APL_HIP(hipGetLastError());
       APL_HIP(hipStreamSynchronize(s));
     } catch (...) {
-      SyncGuard g(g_capture_mu);
-      (void)hipFree(work);
+      if (owned) {
+        SyncGuard g(g_capture_mu);
+        (void)hipFree(work);
+      }
       throw;
     }
-    SyncGuard g(g_capture_mu);
-    APL_HIP(hipFree(work));
+    if (owned) {
+      SyncGuard g(g_capture_mu);
+      APL_HIP(hipFree(work));
+    }
   }
   APL_HIP(hipGetLastError());
   APL_HIP(hipStreamSynchronize(s));
@@ -1920,6 +1968,17 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
     if (blocked) info->phases_bf16 = c.blk->phases16;
   }
   return status;
+}
+
+// Workspace of a context for solves (and adjoint solves) with up to nrhs
+// columns: its set-up buffers, the blocked path's buffers for that many
+// columns, and the adjoint's transient residual block.
+static size_t workspace_for(const aplicur_mat* A, const aplicur_opts* o, int nrhs, hipStream_t s) {
+  std::unique_ptr<Ctx> c(create(A, o, s));
+  if (use_blocked(*c, nrhs)) ensure_blk(*c, blk_kp(std::min(nrhs, kBlkMaxCols)), s);
+  APL_HIP(hipStreamSynchronize(s));
+  const size_t adj = Arena::aligned(sizeof(double) * (size_t)c->m * nrhs * 2);
+  return std::max(c->arena.peak, c->arena.used + adj);
 }
 
 // ------------------------------------------------------------------ batched solves
@@ -2046,14 +2105,27 @@ void aplicur_opts_default(aplicur_opts* o) {
   o->max_outer = 0;
 }
 
-int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* stream, aplicur_ctx** ctx_out) {
+int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* ws, size_t ws_bytes, void* stream,
+                   aplicur_ctx** ctx_out) {
   return guarded([&]() {
     APL_REQUIRE(ctx_out, "ctx_out is null");
     *ctx_out = nullptr;
-    Ctx* c = create(A, opts, (hipStream_t)stream);
+    APL_REQUIRE(!ws || ws_bytes > 0, "ws_bytes must be > 0 with a workspace");
+    APL_REQUIRE(((uintptr_t)ws % Arena::kAlign) == 0, "the workspace must be 256-byte aligned");
+    Ctx* c = create(A, opts, (hipStream_t)stream, ws, ws ? ws_bytes : 0);
     *ctx_out = new aplicur_ctx{c};
     return APLICUR_OK;
   });
+}
+
+int64_t aplicur_workspace_bytes(const aplicur_mat* A, int32_t nrhs, const aplicur_opts* opts, void* stream) {
+  int64_t bytes = 0;
+  const int rc = guarded([&]() {
+    APL_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    bytes = (int64_t)workspace_for(A, opts, nrhs, (hipStream_t)stream);
+    return APLICUR_OK;
+  });
+  return rc == APLICUR_OK ? bytes : (int64_t)rc;
 }
 
 int aplicur_solve(aplicur_ctx* ctx, const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,

@@ -47,14 +47,22 @@ def test_defaults_and_errors_without_gpu():
     # argument validation happens before any device work
     m = _lib.Mat(_lib.DENSE, _lib.F64, 10, 20, 20, 0, None, None, None)
     ctx = ctypes.c_void_p()
-    assert lib.aplicur_sketch(ctypes.byref(m), ctypes.byref(o), None, ctypes.byref(ctx)) == _lib.E_INVALID
+    assert lib.aplicur_sketch(ctypes.byref(m), ctypes.byref(o), None, 0, None, ctypes.byref(ctx)) == _lib.E_INVALID
     assert b"null" in lib.aplicur_last_error()
     m.val = 1  # non-null but mu = 0 with m < n is rejected before any device access
-    assert lib.aplicur_sketch(ctypes.byref(m), ctypes.byref(o), None, ctypes.byref(ctx)) == _lib.E_INVALID
+    assert lib.aplicur_sketch(ctypes.byref(m), ctypes.byref(o), None, 0, None, ctypes.byref(ctx)) == _lib.E_INVALID
     assert b"m >= n" in lib.aplicur_last_error()
     m2 = _lib.Mat(_lib.DENSE, _lib.F64, 20, 10, 10, 0, 1, None, None)
     o.precision = 3
-    assert lib.aplicur_sketch(ctypes.byref(m2), ctypes.byref(o), None, ctypes.byref(ctx)) == _lib.E_INVALID
+    assert lib.aplicur_sketch(ctypes.byref(m2), ctypes.byref(o), None, 0, None, ctypes.byref(ctx)) == _lib.E_INVALID
     assert b"precision" in lib.aplicur_last_error()
     o.precision = 0
     assert lib.aplicur_ctx_query(None, 1, None, 0) == _lib.E_INVALID
+    # workspace arguments are checked before any device access
+    o.mu = 0.0
+    assert lib.aplicur_sketch(ctypes.byref(m2), ctypes.byref(o), 4096, 0, None, ctypes.byref(ctx)) == _lib.E_INVALID
+    assert b"ws_bytes" in lib.aplicur_last_error()
+    assert lib.aplicur_sketch(ctypes.byref(m2), ctypes.byref(o), 4096 + 8, 1 << 20, None,
+                              ctypes.byref(ctx)) == _lib.E_INVALID
+    assert b"aligned" in lib.aplicur_last_error()
+    assert lib.aplicur_workspace_bytes(ctypes.byref(m2), 0, ctypes.byref(o), None) == _lib.E_INVALID
