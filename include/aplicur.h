@@ -52,6 +52,8 @@ extern "C" {
 
 /* ------------------------------------------------------------------ matrix */
 #define APLICUR_DENSE 0 /* row-major m x n, leading dimension ld >= n            */
+#define APLICUR_DENSE_COL 1 /* column-major m x n, leading dimension ld >= m: the
+                               context keeps a row-major copy (m n values)        */
 #define APLICUR_CSR 2   /* CSR: row_ptr[m+1], col_idx[nnz] (int32, any order), val[nnz] */
 #define APLICUR_F64 0
 #define APLICUR_F32 1
@@ -199,9 +201,10 @@ int aplicur_solve_batched(int32_t batch, const aplicur_mat* A, const double* con
  *                                    right-hand side [0; G / sqrt(mu)] and
  *                                    the context's final preconditioner,
  *    dB = A Z                        (m x nrhs, lddb)          = dL/dB,
- *    dA = (B - A X) Z^T - (A Z) X^T  (dense A: m x n row-major with
- *                                    leading dimension ldda; CSR A: nnz
- *                                    values on the sparsity pattern)   = dL/dA.
+ *    dA = (B - A X) Z^T - (A Z) X^T  (dense A: m x n in A's layout,
+ *                                    row-major with ldda >= n, or
+ *                                    column-major with ldda >= m; CSR A:
+ *                                    nnz values on the sparsity pattern) = dL/dA.
  * X, B are the forward solution and right-hand sides.  Requires mu > 0 and
  * a context on which aplicur_solve has run.  dA may be NULL (skipped); Z
  * (n x nrhs, ldz) receives Z.  Errors: E_INVALID, E_HIP, E_BREAKDOWN.      */

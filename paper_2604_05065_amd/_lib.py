@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaplicur.so")
 
 OK, W_MAXITER, E_INVALID, E_HIP, E_BREAKDOWN, E_NOMEM = 0, 1, -1, -3, -4, -5
-DENSE, CSR = 0, 2
+DENSE, DENSE_COL, CSR = 0, 1, 2
 F64, F32 = 0, 1
 
 

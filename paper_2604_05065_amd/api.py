@@ -54,9 +54,12 @@ def _mat(A):
         raise TypeError("A must be a 2-D torch tensor or a CSRMatrix")
     if not A.is_cuda:
         raise ValueError("A must live on the GPU")
+    m, n = A.shape
+    if A.stride(0) == 1 and A.stride(1) >= max(m, 1) and n > 1:  # column-major (e.g. a transposed view)
+        st = L.Mat(L.DENSE_COL, _dtype_code(A.dtype), m, n, A.stride(1), 0, A.data_ptr(), None, None)
+        return st, (A,)
     if A.stride(1) != 1:
         A = A.contiguous()
-    m, n = A.shape
     st = L.Mat(L.DENSE, _dtype_code(A.dtype), m, n, A.stride(0), 0, A.data_ptr(), None, None)
     return st, (A,)
 
@@ -145,6 +148,9 @@ class Context:
         if want_dA:
             if self.mat.format == L.CSR:
                 dA = torch.empty(int(self.mat.nnz), dtype=torch.float64, device=dev)
+            elif self.mat.format == L.DENSE_COL:  # dA in A's (column-major) layout
+                dAt = torch.empty((self.n, self.m), dtype=torch.float64, device=dev)
+                dA, ldda = dAt.t(), self.m
             else:
                 dA = torch.empty((self.m, self.n), dtype=torch.float64, device=dev)
                 ldda = self.n

@@ -308,8 +308,9 @@ static void validate(const aplicur_mat* A, const aplicur_opts* o) {
     APL_REQUIRE(A->row_ptr && A->col_idx, "CSR needs row_ptr and col_idx");
     APL_REQUIRE(A->nnz >= 0 && A->nnz < (1LL << 31), "nnz out of range");
   } else {
-    APL_REQUIRE(A->format == APLICUR_DENSE, "format must be DENSE or CSR");
-    APL_REQUIRE(A->ld >= A->n, "dense ld must be >= n");
+    APL_REQUIRE(A->format == APLICUR_DENSE || A->format == APLICUR_DENSE_COL, "format must be DENSE, DENSE_COL or CSR");
+    APL_REQUIRE(A->ld >= (A->format == APLICUR_DENSE ? A->n : A->m),
+                A->format == APLICUR_DENSE ? "dense ld must be >= n" : "column-major ld must be >= m");
   }
   APL_REQUIRE(o->mu >= 0.0 && std::isfinite(o->mu), "mu must be finite and >= 0");
   APL_REQUIRE(o->mu > 0.0 || A->m >= A->n, "mu = 0 needs m >= n");
@@ -443,6 +444,19 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
     op.n = n;
     op.ld = op.csr ? 0 : Am->ld;
     op.val = Am->val;
+    if (Am->format == APLICUR_DENSE_COL) {
+      // row-major copy: the column-major m x n matrix is the row-major A^T (n x m, ld)
+      if (op.f64) {
+        double* a = c->arena.alloc<double>((size_t)m * n);
+        transpose_rect<double>((const double*)Am->val, n, m, Am->ld, a, n, s);
+        op.val = a;
+      } else {
+        float* a = c->arena.alloc<float>((size_t)m * n);
+        transpose_rect<float>((const float*)Am->val, n, m, Am->ld, a, n, s);
+        op.val = a;
+      }
+      op.ld = n;
+    }
     const size_t vs = op.f64 ? 8 : 4;
     if (op.csr) {
       op.row_ptr = Am->row_ptr;
@@ -1853,7 +1867,8 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
   if (dA) {
     APL_REQUIRE(X && B, "dA needs X and B");
     APL_REQUIRE(ldx >= c.n && ldb >= c.m, "leading dimensions too small");
-    APL_REQUIRE(c.op.csr || ldda >= c.n, "ldda must be >= n for dense A");
+    APL_REQUIRE(c.op.csr || ldda >= (c.A.format == APLICUR_DENSE_COL ? c.m : c.n),
+                "ldda must be >= n (row-major A) or >= m (column-major A)");
   }
   set_stream(c, s);
   auto t0 = Clock::now();
@@ -1934,11 +1949,19 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
       if (c.op.csr) {
         grad_csr(c.op.row_ptr, c.op.col_idx, c.m, nrhs, R, c.m, Z, ldz, dB, lddb, X, ldx, dA, s);
       } else {
-        // row-major dA (m x n) is the column-major n x m matrix dA^T = Z R^T - X (AZ)^T
-        gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.n, c.m, nrhs, 1.0, Z, ldz, R, c.m, 0.0, dA,
-             ldda);
-        gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.n, c.m, nrhs, -1.0, X, ldx, dB, lddb, 1.0, dA,
-             ldda);
+        if (c.A.format == APLICUR_DENSE_COL) {
+          // column-major dA (m x n) = R Z^T - (AZ) X^T
+          gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.m, c.n, nrhs, 1.0, R, c.m, Z, ldz, 0.0, dA,
+               ldda);
+          gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.m, c.n, nrhs, -1.0, dB, lddb, X, ldx, 1.0,
+               dA, ldda);
+        } else {
+          // row-major dA (m x n) is the column-major n x m matrix dA^T = Z R^T - X (AZ)^T
+          gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.n, c.m, nrhs, 1.0, Z, ldz, R, c.m, 0.0, dA,
+               ldda);
+          gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.n, c.m, nrhs, -1.0, X, ldx, dB, lddb, 1.0,
+               dA, ldda);
+        }
       }
       APL_HIP(hipGetLastError());
       APL_HIP(hipStreamSynchronize(s));

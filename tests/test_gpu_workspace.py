@@ -70,3 +70,27 @@ def test_workspace_too_small_for_more_columns(lib):
         assert info.status == 0
         with pytest.raises(RuntimeError, match="workspace"):
             ctx.solve(B)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_column_major_input(lib, dtype):
+    """A column-major A (a transposed view, format DENSE_COL) gives the
+    row-major input's results: solves bit for bit (the context keeps a
+    row-major copy), dA in A's column-major layout."""
+    A = _dense(500, 60, 89, decades=2)
+    Arow = _t(A, dtype)
+    Acol = _t(A.T, dtype).t()  # same values, column-major storage
+    assert Acol.stride() == (1, 500)
+    r = np.random.default_rng(90)
+    B, G = _t(r.standard_normal((500, 3))), _t(r.standard_normal((60, 3)))
+    opts = dict(mu=1e-3, block=8, tol_ne=1e-11)
+    res = []
+    for Am in (Arow, Acol):
+        with lib.Context(Am, **opts) as ctx:
+            X, info = ctx.solve(B)
+            Z, dB, dA, _ = ctx.solve_backward(X, B, G)
+        res.append((X, Z, dB, dA))
+    for a, b in zip(res[0][:3], res[1][:3]):
+        assert torch.equal(a, b)
+    assert res[1][3].stride() == (1, 500)
+    assert torch.allclose(res[0][3], res[1][3], rtol=1e-12, atol=1e-12 * float(res[0][3].abs().max()))
