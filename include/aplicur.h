@@ -111,7 +111,9 @@ typedef struct aplicur_opts {
   int32_t columns;   /* 1: one right-hand side at a time even where the blocked path applies
                         (several right-hand sides of a dense A); 0: blocked there
                         (default).  Same method and stopping tests per column              */
-  int32_t reserved[3];
+  int32_t xi;        /* non-zeros per column of the sparse sign sketch, 1..8 (default 8,
+                        Sec. 5.1; 0 selects the default); the sketch uses min(xi, s)     */
+  int32_t reserved[2];
 } aplicur_opts;
 
 /* ------------------------------------------------------------------ info  */

@@ -52,6 +52,7 @@ class Options:
     max_iter: int = 100000
     max_rank: int = 0          # <= 0: min(m, n)
     r_probes: int = 10
+    xi: int = 8                # non-zeros per column of the sparse sign sketch (1..8)
 
 
 @dataclass
@@ -117,7 +118,7 @@ def aplicur(A, b, mu, opts=None, trace=None):
     max_rank = min(m, n) if opts.max_rank <= 0 else min(opts.max_rank, m, n)
     # initialisation
     s = sketch_rows(opts.block, m)
-    S = rng.sparse_sign_matrix(opts.seed, s, m)
+    S = rng.sparse_sign_matrix(opts.seed, s, m, opts.xi)
     Y = np.asarray((S @ A).toarray() if sp.issparse(A) else S @ A, dtype=np.float64)
     probes = rng.gaussian_probes(opts.seed, n, opts.r_probes)
     E_row = Y.copy()

@@ -62,19 +62,24 @@ def draw(seed, stream, ctr):
         return mix64(k + GOLDEN * (ctr + np.uint64(1)))
 
 
-def sketch_nnz(s):
-    """xi' = min(8, s): non-zeros per column of S (Alg. 3 initialisation, App. B.3)."""
-    return min(8, s)
+def sketch_nnz(s, xi=8):
+    """xi' = min(xi, s): non-zeros per column of S (Alg. 3 initialisation,
+    App. B.3; the paper's default xi = 8).  The counters below give each
+    column 8 slots, so 1 <= xi <= 8."""
+    if not 1 <= xi <= 8:
+        raise ValueError("xi must be in [1, 8]")
+    return min(xi, s)
 
 
-def sparse_sign(seed, s, m):
-    """Sparse sign embedding S in R^{s x m} (Definition 5.1).
+def sparse_sign(seed, s, m, xi=8):
+    """Sparse sign embedding S in R^{s x m} (Definition 5.1) with min(xi, s)
+    non-zeros per column.
 
-    Returns (rows, signs, xi): ``rows[i, t]`` is the row of non-zero t of
+    Returns (rows, signs, xi'): ``rows[i, t]`` is the row of non-zero t of
     column i (distinct within a column), ``signs[i, t]`` is +-1, and each
-    non-zero equals signs / sqrt(xi).
+    non-zero equals signs / sqrt(xi').
     """
-    xi = sketch_nnz(s)
+    xi = sketch_nnz(s, xi)
     rows = np.full((m, xi), -1, dtype=np.int64)
     cols = np.arange(m, dtype=np.uint64)
     for t in range(xi):
@@ -101,10 +106,10 @@ def sparse_sign(seed, s, m):
     return rows, signs, xi
 
 
-def sparse_sign_matrix(seed, s, m):
+def sparse_sign_matrix(seed, s, m, xi=8):
     """S as a scipy CSR matrix (s x m)."""
     import scipy.sparse as sp
-    rows, signs, xi = sparse_sign(seed, s, m)
+    rows, signs, xi = sparse_sign(seed, s, m, xi)
     cols = np.repeat(np.arange(m), xi)
     vals = signs.reshape(-1) / np.sqrt(xi)
     return sp.csr_matrix((vals, (rows.reshape(-1), cols)), shape=(s, m))

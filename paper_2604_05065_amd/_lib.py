@@ -26,7 +26,8 @@ class Opts(C.Structure):
                 ("eps_lsqr", C.c_double), ("tol_ne", C.c_double), ("max_iter", C.c_int32),
                 ("max_rank", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
                 ("max_outer", C.c_int32), ("workers", C.c_int32), ("tune", C.c_int32),
-                ("graphs", C.c_int32), ("columns", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("graphs", C.c_int32), ("columns", C.c_int32), ("xi", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class Info(C.Structure):

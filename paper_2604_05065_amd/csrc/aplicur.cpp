@@ -321,6 +321,7 @@ static void validate(const aplicur_mat* A, const aplicur_opts* o) {
     APL_REQUIRE(o->r_probes >= 1 && o->r_probes <= 64, "r_probes must be in [1, 64]");
   }
   APL_REQUIRE(o->max_iter >= 0, "max_iter must be >= 0");
+  APL_REQUIRE(o->xi >= 0 && o->xi <= 8, "xi must be in [1, 8] (0: the default 8)");
 }
 
 // ------------------------------------------------------------------ product tiles
@@ -599,11 +600,11 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
     }
     if (o->tune) tune_tiles(*c, s);
     if (o->precond) {
-      // sketch dimensions (Alg. 3: s = ceil(1.1 b), xi = min(8, s))
+      // sketch dimensions (Alg. 3: s = ceil(1.1 b), xi' = min(xi, s), xi = 8 by default)
       int s_rows = (int)std::ceil(1.1 * o->block - 1e-12);
       s_rows = (int)std::max<long long>(1, std::min<long long>(s_rows, m));
       c->s = s_rows;
-      c->xi = std::min(8, s_rows);
+      c->xi = std::min(o->xi > 0 ? o->xi : 8, s_rows);
       c->r = o->r_probes;
       long long Lmax = std::min<long long>(std::min(m, n), 4096);
       if (o->max_rank > 0) Lmax = std::min<long long>(std::min(m, n), o->max_rank);
@@ -2126,6 +2127,7 @@ void aplicur_opts_default(aplicur_opts* o) {
   o->precond = 1;
   o->precision = 0;
   o->max_outer = 0;
+  o->xi = 8;
 }
 
 int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* ws, size_t ws_bytes, void* stream,

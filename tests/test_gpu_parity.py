@@ -45,7 +45,7 @@ def _gpu_csr(A, dtype=torch.float64):
 # ----------------------------------------------------------------- sketch
 @pytest.mark.parametrize("kind,m,n,block", [("dense", 300, 37, 6), ("dense", 1000, 130, 20),
                                              ("csr", 2000, 300, 10), ("csr", 513, 64, 3)])
-def test_sketch_matches_oracle(lib, kind, m, n, block):
+def test_sketch_matches_oracle(lib, kind, m, n, block, xi=8):
     seed = 11
     if kind == "dense":
         A = _dense(m, n, 1)
@@ -53,19 +53,42 @@ def test_sketch_matches_oracle(lib, kind, m, n, block):
     else:
         A = _csr(m, n, 5, 2)
         Ag = _gpu_csr(A)
-    with lib.Context(Ag, mu=1e-4, block=block, seed=seed, max_outer=1) as ctx:
+    with lib.Context(Ag, mu=1e-4, block=block, seed=seed, max_outer=1, xi=xi) as ctx:
         sz = ctx.sizes()
         s = sz["s"]
         assert s == min(m, math.ceil(1.1 * block))
-        rows, signs, xi = orng.sparse_sign(seed, s, m)
+        rows, signs, xi = orng.sparse_sign(seed, s, m, xi)
         assert sz["xi"] == xi
         np.testing.assert_array_equal(ctx.query(2).reshape(m, xi), rows)       # bit-exact
         np.testing.assert_array_equal(ctx.query(3).reshape(m, xi), signs)
         Y = ctx.query(1).reshape(s, n)
-        Yref = orng.sparse_sign_matrix(seed, s, m) @ (A.toarray() if sp.issparse(A) else A)
+        Yref = orng.sparse_sign_matrix(seed, s, m, xi) @ (A.toarray() if sp.issparse(A) else A)
         assert np.abs(Y - Yref).max() <= 1e-13 * np.abs(Yref).max()
         W = ctx.query(4).reshape(10, n).T
         np.testing.assert_allclose(W, orng.gaussian_probes(seed, n, 10), rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+@pytest.mark.parametrize("xi", [1, 3])
+def test_sketch_other_xi_matches_oracle(lib, kind, xi):
+    test_sketch_matches_oracle(lib, kind, 3001, 120, 20, xi)
+
+
+def test_solution_with_xi_matches_oracle(lib):
+    """A whole APLICUR solve with xi = 4: the same CUR indices as the oracle's
+    first outer steps and the dense-QR solution."""
+    A = _dense(600, 70, 21, decades=5)
+    b = np.random.default_rng(3).standard_normal(600)
+    mu, block = 1e-6, 7
+    tr = Trace()
+    aplicur(A, b, mu, Options(block=block, tol_ne=1e-30, max_rank=3 * block, xi=4), tr)
+    with lib.Context(_t(A), mu=mu, block=block, tol_ne=1e-30, max_rank=3 * block, max_outer=3, xi=4) as ctx:
+        ctx.solve(_t(b))
+        np.testing.assert_array_equal(ctx.query(5), tr.J[:len(ctx.query(5))])
+        np.testing.assert_array_equal(ctx.query(6), tr.I[:len(ctx.query(6))])
+    x, info = lib.lstsq(_t(A), _t(b), mu=mu, block=block, tol_ne=1e-10, xi=4)
+    xr = solve_dense_qr(A, b, mu)
+    assert info.status == 0 and np.linalg.norm(x.cpu().numpy() - xr) <= 1e-6 * np.linalg.norm(xr)
 
 
 # ----------------------------------------------------------------- products

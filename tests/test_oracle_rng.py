@@ -47,6 +47,28 @@ def test_sparse_sign_structure(s, m):
     assert np.all(np.count_nonzero(S, axis=0) == xi)
 
 
+@pytest.mark.parametrize("xi", [1, 3, 5, 8])
+@pytest.mark.parametrize("s,m", [(22, 500), (4, 300)])
+def test_sparse_sign_other_xi(xi, s, m):
+    """xi' = min(xi, s) distinct rows per column, entries +-1/sqrt(xi'), unit
+    columns; a column's t-th draw does not depend on xi (the counters give
+    each column 8 slots), so the xi' rows are the first xi' of the default's
+    when xi' <= 8; out-of-range xi is refused."""
+    rows, signs, k = rng.sparse_sign(7, s, m, xi)
+    assert k == min(xi, s)
+    for i in range(m):
+        assert len(set(rows[i].tolist())) == k
+    S = rng.sparse_sign_matrix(7, s, m, xi).toarray()
+    np.testing.assert_allclose(np.linalg.norm(S, axis=0), 1.0, rtol=0, atol=1e-15)
+    assert np.all(np.count_nonzero(S, axis=0) == k)
+    r8, s8, _ = rng.sparse_sign(7, s, m)
+    np.testing.assert_array_equal(rows, r8[:, :k])
+    np.testing.assert_array_equal(signs, s8[:, :k])
+    for bad in (0, 9):
+        with pytest.raises(ValueError):
+            rng.sparse_sign(7, s, m, bad)
+
+
 def test_sparse_sign_statistics():
     s, m = 50, 40000
     rows, signs, xi = rng.sparse_sign(11, s, m)
