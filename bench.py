@@ -110,13 +110,26 @@ def bench_batched(ap, synth, torch, count=16, scale=0.25, nrhs=2):
     tuned tiles) against one-at-a-time APLICUR and one-at-a-time plain LSQR."""
     shapes = synth.batch_shapes(count, m_range=(int(5000 * scale), int(100000 * scale)),
                                 n_range=(int(500 * scale), int(5000 * scale)))
-    probs = [synth.dense_svd_gpu(4000 + i, m, n, k, nrhs) for i, (m, n, k) in enumerate(shapes)]
+    probs = []
+    for i, (m, n, k) in enumerate(shapes):
+        probs.append(synth.dense_svd_gpu(4000 + i, m, n, k, nrhs))
+        if (i + 1) % 16 == 0:
+            log(f"[bench] batched: {i + 1} of {count} problems generated")
     opts = dict(mu=1e-6, block=50, tol_ne=1e-8)
     As, Bs = [p[0] for p in probs], [p[1] for p in probs]
+
+    def one_at_a_time(**kw):
+        out = []
+        for i, (A, B) in enumerate(zip(As, Bs)):
+            out.append(ap.lstsq(A, B, **opts, **kw)[1])
+            if (i + 1) % 16 == 0:
+                log(f"[bench] batched: {i + 1} of {count} one-at-a-time solves ({kw or 'APLICUR'})")
+        return out
     ap.solve_batched(As[:2], Bs[:2], workers=2, **opts)  # warm-up
     ms_b, (_, infos) = _timed(torch, lambda: ap.solve_batched(As, Bs, workers=8, **opts))
-    ms_s, inf_s = _timed(torch, lambda: [ap.lstsq(A, B, **opts)[1] for A, B in zip(As, Bs)])
-    ms_p, inf_p = _timed(torch, lambda: [ap.lstsq(A, B, precond=False, **opts)[1] for A, B in zip(As, Bs)])
+    log(f"[bench] batched: one call {ms_b:.0f} ms")
+    ms_s, inf_s = _timed(torch, lambda: one_at_a_time())
+    ms_p, inf_p = _timed(torch, lambda: one_at_a_time(precond=False))
     ok = all(i.status == 0 for i in list(infos) + inf_s + inf_p)
     log(f"[bench] batched {count} problems: batched {ms_b:.0f} ms, one-at-a-time APLICUR {ms_s:.0f} ms, "
         f"plain LSQR {ms_p:.0f} ms (all converged: {ok})")
@@ -237,6 +250,9 @@ def main():
     ap_.add_argument("--blocked-prec", type=int, default=0, choices=(0, 1, 2),
                      help="arithmetic of --blocked-products: 0 FP64 accumulation, 1 FP32, 2 BF16")
     ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
+    ap_.add_argument("--full-configs", action="store_true",
+                     help="only the batched, dense-kernel and adjoint workloads at their full sizes (64 problems "
+                          "x 8 RHS; RBF 40000^2 x 16 RHS; 100000 x 2000 x 32 RHS), one JSON line")
     args = ap_.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): every problem here fits one MI355X and "
@@ -250,6 +266,14 @@ def main():
 
     if args.blocked_products:
         blocked_products(ap, synth, torch, prec=args.blocked_prec)
+        return
+    if args.full_configs:
+        full = {"adjoint": bench_adjoint(ap, synth, torch, m=100000, n=2000, nrhs=32)}
+        torch.cuda.empty_cache()
+        full["multi_rhs"] = bench_multi_rhs(ap, synth, torch, npts=40000, nrhs=16)
+        torch.cuda.empty_cache()
+        full["batched"] = bench_batched(ap, synth, torch, count=64, scale=1.0, nrhs=8)
+        print(json.dumps({"full_configs": full}), flush=True)
         return
 
     t0 = time.time()
