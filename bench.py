@@ -236,6 +236,53 @@ def blocked_products(ap, synth, torch, npts=20000, nrhs=16, rounds=20, prec=0):
                       "copy_bytes_each_way": big.numel() * 8}), flush=True)
 
 
+def sketch_study(ap, synth, torch):
+    """Sparse sign against Gaussian sketch: set-up time of the sketch and the
+    whole solve with each, on the dense kernel workload at half size (FP32 A,
+    16 RHS) and on the sparse workload (CSR 200000 x 20000, rank cap 256);
+    and the error of the Gaussian sketch of FP32 A (FP32 GEMM) against the
+    same sketch of the values widened to FP64 (FP64 GEMM).  One JSON line."""
+    out = {}
+    A, B = synth.rbf_kernel_gpu(3003, 20000, 16)
+    opts = dict(mu=1e-3, block=250, tol_ne=1e-8)
+    dense = {}
+    for kind in ("sparse", "gaussian"):
+        ap.lstsq(A, B, sketch=kind, **opts)  # warm-up (library and rocBLAS initialisation)
+        ms, (X, info) = _timed(torch, lambda: ap.lstsq(A, B, sketch=kind, **opts))
+        dense[kind] = {"ms": round(ms, 1), "t_sketch_ms": round(info.t_sketch_ms, 2), "rank": info.rank,
+                       "iters": info.iters, "eta": info.eta}
+        log(f"[bench] sketch study rbf 20000 ({kind}): {ms:.0f} ms (sketch {info.t_sketch_ms:.1f} ms), "
+            f"rank {info.rank}, {info.iters} it")
+    with ap.Context(A, sketch="gaussian", max_outer=1, **opts) as c32:
+        s = c32.sizes()["s"]
+        y32 = torch.as_tensor(c32.query(1)).reshape(s, -1)
+    A64 = A.to(torch.float64)
+    with ap.Context(A64, sketch="gaussian", max_outer=1, **opts) as c64:
+        y64 = torch.as_tensor(c64.query(1)).reshape(s, -1)
+    del A64
+    err = (y32 - y64).abs()
+    dense["gaussian_fp32_vs_fp64"] = {"max_abs_err_over_max_abs": float(err.max() / y64.abs().max()),
+                                      "rel_frobenius": float(err.norm() / y64.norm())}
+    log(f"[bench] Gaussian sketch of FP32 A, FP32 GEMM vs FP64 GEMM: {dense['gaussian_fp32_vs_fp64']}")
+    out["rbf20000"] = dense
+    del A, B
+    torch.cuda.empty_cache()
+    w = synth.workload(2, 1.0)
+    Ag = ap.CSRMatrix.from_scipy(w.A, device="cuda", dtype=torch.float64)
+    bg = torch.as_tensor(w.B, device="cuda")
+    sparse = {}
+    for kind in ("sparse", "gaussian"):
+        ap.lstsq(Ag, bg, mu=w.mu, block=w.block, tol_ne=w.tol, max_rank=256, sketch=kind)  # warm-up
+        ms, (x, info) = _timed(torch, lambda: ap.lstsq(Ag, bg, mu=w.mu, block=w.block, tol_ne=w.tol, max_rank=256,
+                                                      sketch=kind))
+        sparse[kind] = {"ms": round(ms, 1), "t_sketch_ms": round(info.t_sketch_ms, 2), "rank": info.rank,
+                        "iters": info.iters, "eta": info.eta}
+        log(f"[bench] sketch study CSR 200000x20000 ({kind}): {ms:.0f} ms (sketch {info.t_sketch_ms:.1f} ms), "
+            f"{info.iters} it")
+    out["csr200000"] = sparse
+    print(json.dumps({"sketch_study": out}), flush=True)
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -250,6 +297,8 @@ def main():
     ap_.add_argument("--blocked-prec", type=int, default=0, choices=(0, 1, 2),
                      help="arithmetic of --blocked-products: 0 FP64 accumulation, 1 FP32, 2 BF16")
     ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
+    ap_.add_argument("--sketch-study", action="store_true",
+                     help="only the sparse sign against Gaussian sketch comparison, one JSON line")
     ap_.add_argument("--full-configs", action="store_true",
                      help="only the batched, dense-kernel and adjoint workloads at their full sizes (64 problems "
                           "x 8 RHS; RBF 40000^2 x 16 RHS; 100000 x 2000 x 32 RHS), one JSON line")
@@ -266,6 +315,9 @@ def main():
 
     if args.blocked_products:
         blocked_products(ap, synth, torch, prec=args.blocked_prec)
+        return
+    if args.sketch_study:
+        sketch_study(ap, synth, torch)
         return
     if args.full_configs:
         full = {"adjoint": bench_adjoint(ap, synth, torch, m=100000, n=2000, nrhs=32)}

@@ -113,7 +113,11 @@ typedef struct aplicur_opts {
                         (default).  Same method and stopping tests per column              */
   int32_t xi;        /* non-zeros per column of the sparse sign sketch, 1..8 (default 8,
                         Sec. 5.1; 0 selects the default); the sketch uses min(xi, s)     */
-  int32_t reserved[2];
+  int32_t sketch;    /* 0: sparse sign embedding (default); 1: Gaussian embedding, i.i.d.
+                        N(0, 1/s) entries from the counter-based stream 3, Y = S A by
+                        rocBLAS GEMM for dense A (FP32 A: FP32 S and accumulation,
+                        widened), or a column-wise kernel over the CSR of A^T         */
+  int32_t reserved[1];
 } aplicur_opts;
 
 /* ------------------------------------------------------------------ info  */
@@ -251,7 +255,8 @@ int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, doubl
                          int64_t flush_bytes, void* stream, double* us_per_launch);
 
 /* Read internal state back to host memory (tests and diagnostics).
- * what: 1 sketch Y (s x n row-major doubles), 2 sketch rows (m x xi int32),
+ * what: 1 sketch Y (s x n row-major doubles), 2 sketch rows (m x xi int32;
+ * none for the Gaussian sketch),
  * 3 sketch signs (m x xi int32, +-1), 4 probes (n x r doubles, column-major),
  * 5 column indices J (rank int32), 6 row indices I (rank int32),
  * 7 rho history (outer doubles), 8 rank history (outer int32),

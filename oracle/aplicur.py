@@ -53,6 +53,7 @@ class Options:
     max_rank: int = 0          # <= 0: min(m, n)
     r_probes: int = 10
     xi: int = 8                # non-zeros per column of the sparse sign sketch (1..8)
+    sketch: str = "sparse"     # "sparse" (sparse sign, the default) or "gaussian"
 
 
 @dataclass
@@ -118,8 +119,12 @@ def aplicur(A, b, mu, opts=None, trace=None):
     max_rank = min(m, n) if opts.max_rank <= 0 else min(opts.max_rank, m, n)
     # initialisation
     s = sketch_rows(opts.block, m)
-    S = rng.sparse_sign_matrix(opts.seed, s, m, opts.xi)
-    Y = np.asarray((S @ A).toarray() if sp.issparse(A) else S @ A, dtype=np.float64)
+    if opts.sketch == "gaussian":
+        S = rng.gaussian_sketch(opts.seed, s, m)  # dense s x m
+        Y = np.asarray((A.T @ S.T).T if sp.issparse(A) else S @ A, dtype=np.float64)
+    else:
+        S = rng.sparse_sign_matrix(opts.seed, s, m, opts.xi)
+        Y = np.asarray((S @ A).toarray() if sp.issparse(A) else S @ A, dtype=np.float64)
     probes = rng.gaussian_probes(opts.seed, n, opts.r_probes)
     E_row = Y.copy()
     I = np.zeros(0, np.int64)

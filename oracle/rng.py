@@ -31,7 +31,11 @@ Stream layout (all counters 0-based):
             Box-Muller with u1 = ((d0 >> 11) + 1) 2^-53, u2 = (d1 >> 11) 2^-53
             where d0 = draw(2c), d1 = draw(2c + 1):
             z = sqrt(-2 ln u1) cos(2 pi u2).
+  stream 3: Gaussian sketch entry (h, i): c = i s + h, the same Box-Muller,
+            divided by sqrt(s).
 """
+import math
+
 import numpy as np
 
 GOLDEN = np.uint64(0x9E3779B97F4A7C15)
@@ -113,6 +117,21 @@ def sparse_sign_matrix(seed, s, m, xi=8):
     cols = np.repeat(np.arange(m), xi)
     vals = signs.reshape(-1) / np.sqrt(xi)
     return sp.csr_matrix((vals, (rows.reshape(-1), cols)), shape=(s, m))
+
+
+def gaussian_sketch(seed, s, m):
+    """Gaussian embedding S in R^{s x m} with i.i.d. N(0, 1/s) entries (the
+    Gaussian sketch of Sec. 5.1 / App. B.3): entry (h, i) is a Box-Muller
+    normal of the stream-3 draws 2c and 2c + 1, c = i s + h (column-major
+    order, so the first m columns do not depend on m), divided by sqrt(s)."""
+    h = np.arange(s, dtype=np.uint64)[:, None]
+    i = np.arange(m, dtype=np.uint64)[None, :]
+    c = i * np.uint64(s) + h
+    d0 = draw(seed, 3, np.uint64(2) * c)
+    d1 = draw(seed, 3, np.uint64(2) * c + np.uint64(1))
+    u1 = ((d0 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (d1 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2) / math.sqrt(s)
 
 
 def gaussian_probes(seed, n, r):

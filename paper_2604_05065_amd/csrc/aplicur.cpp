@@ -322,6 +322,7 @@ static void validate(const aplicur_mat* A, const aplicur_opts* o) {
   }
   APL_REQUIRE(o->max_iter >= 0, "max_iter must be >= 0");
   APL_REQUIRE(o->xi >= 0 && o->xi <= 8, "xi must be in [1, 8] (0: the default 8)");
+  APL_REQUIRE(o->sketch == 0 || o->sketch == 1, "sketch must be 0 (sparse sign) or 1 (Gaussian)");
 }
 
 // ------------------------------------------------------------------ product tiles
@@ -620,9 +621,43 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
       c->W = c->arena.alloc<double>((size_t)n * r);
       c->EW = c->arena.alloc<double>((size_t)S * r);
       c->rho_dev = c->arena.alloc<double>(4);
-      launch_gen_sketch(o->seed, S, m, c->xi, c->S_rows, c->S_neg, s);
       launch_gen_probes(o->seed, n, r, c->W, s);
-      if (op.csr) {
+      if (o->sketch == 1) {
+        // Gaussian S (s x m, column-major) in transient memory, Y = S A
+        const size_t sm = (size_t)S * m;
+        const bool f32 = !op.csr && !op.f64;
+        const size_t extra = f32 ? (sizeof(float) * sm + sizeof(float) * (size_t)S * n + 512) : 0;
+        bool owned = false;
+        char* tb = (char*)c->arena.transient(sizeof(double) * sm + extra, owned);
+        double* Sg = (double*)tb;
+        launch_gen_gauss_sketch(o->seed, S, m, Sg, s);
+        if (op.csr) {
+          if (op.f64)
+            launch_sketch_gauss_csr<double>(op.t_ptr, op.t_idx, (const double*)op.t_val, n, S, Sg, c->Y, s);
+          else
+            launch_sketch_gauss_csr<float>(op.t_ptr, op.t_idx, (const float*)op.t_val, n, S, Sg, c->Y, s);
+        } else if (op.f64) {
+          // Y^T (n x s, column-major) = A_cm (n x m) S^T: A row-major is column-major n x m with ld
+          const double one = 1.0, zero = 0.0;
+          APL_BLAS(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, (int)n, S, (int)m,
+                                 &one, (const double*)op.val, (int)op.ld, Sg, S, &zero, c->Y, (int)n));
+        } else {
+          // FP32 product (FP32 S and A, FP32 accumulation), widened to FP64
+          float* S32 = (float*)(tb + (sizeof(double) * sm + 255) / 256 * 256);
+          float* Y32 = (float*)((char*)S32 + (sizeof(float) * sm + 255) / 256 * 256);
+          to_f32(Sg, S, S32, S, m, S, s);
+          const float one = 1.0f, zero = 0.0f;
+          APL_BLAS(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, (int)n, S, (int)m,
+                                 &one, (const float*)op.val, (int)op.ld, S32, S, &zero, Y32, (int)n));
+          widen(Y32, c->Y, (long long)S * n, s);
+        }
+        APL_HIP(hipStreamSynchronize(s));
+        if (owned) {
+          SyncGuard g(g_capture_mu);
+          APL_HIP(hipFree(tb));
+        }
+      } else if (op.csr) {
+        launch_gen_sketch(o->seed, S, m, c->xi, c->S_rows, c->S_neg, s);
         if (op.f64)
           launch_sketch_csr<double>(op.t_ptr, op.t_idx, (const double*)op.t_val, n, S, c->xi, c->S_rows,
                                     c->S_neg, c->Y, s);
@@ -630,6 +665,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
           launch_sketch_csr<float>(op.t_ptr, op.t_idx, (const float*)op.t_val, n, S, c->xi, c->S_rows,
                                    c->S_neg, c->Y, s);
       } else {
+        launch_gen_sketch(o->seed, S, m, c->xi, c->S_rows, c->S_neg, s);
         const int chunks = sketch_dense_chunks(m, n);
         bool owned = false;
         double* part = (double*)c->arena.transient(sizeof(double) * (size_t)chunks * S * n, owned);
@@ -2276,6 +2312,10 @@ int64_t aplicur_ctx_query(const aplicur_ctx* ctx, int32_t what, void* host_out, 
     switch (what) {
       case 1: dev(c.Y, sizeof(double) * (size_t)c.s * c.n); break;
       case 2: case 3: {
+        if (c.o.sketch == 1) {  // Gaussian sketch: no sparse sign structure
+          buf.clear();
+          break;
+        }
         std::vector<uint16_t> rows((size_t)c.m * c.xi);
         std::vector<uint8_t> neg(c.m);
         APL_HIP(hipDeviceSynchronize());

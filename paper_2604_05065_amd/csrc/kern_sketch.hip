@@ -64,6 +64,64 @@ __global__ void k_gen_probes(uint64_t seed, long long n, int r, double* W) {
   W[idx] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
 }
 
+// Gaussian sketch S (s x m, column-major): entry (h, i) the Box-Muller normal
+// of the stream-3 draws 2c and 2c + 1, c = i s + h, divided by sqrt(s).
+__global__ void k_gen_gauss_sketch(uint64_t seed, int s, long long m, double* S) {
+  const long long idx = blockIdx.x * (long long)kBlock + threadIdx.x;
+  if (idx >= m * s) return;
+  const uint64_t k3 = stream_key(seed, 3);
+  const uint64_t c = (uint64_t)idx;
+  const uint64_t d0 = draw(k3, 2 * c), d1 = draw(k3, 2 * c + 1);
+  const double u1 = ((double)(d0 >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = (double)(d1 >> 11) * 0x1.0p-53;
+  S[idx] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2) / sqrt((double)s);
+}
+
+void launch_gen_gauss_sketch(uint64_t seed, int s, long long m, double* S, hipStream_t st) {
+  hipLaunchKernelGGL(k_gen_gauss_sketch, dim3(ceil_div(m * s, kBlock)), dim3(kBlock), 0, st, seed, s, m, S);
+}
+
+// Y(:, j) = S A(:, j) for CSR A through the CSR of A^T (row j lists the
+// entries of column j of A in row order): one wave per j, lane h < s sums
+// a_ij S(h, i) over the column's entries in order; Y row-major s x n.
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+    k_sketch_gauss_csr(const int* __restrict__ t_ptr, const int* __restrict__ t_idx, const T* __restrict__ t_val,
+                       long long n, int s, const double* __restrict__ S, double* __restrict__ Y) {
+  const long long j = blockIdx.x * (long long)(kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (j >= n) return;
+  const int e0 = t_ptr[j], e1 = t_ptr[j + 1];
+  for (int h0 = 0; h0 < s; h0 += kWave) {
+    const int h = h0 + lane;
+    double acc = 0.0;
+    if (h < s)
+      for (int e = e0; e < e1; ++e) acc += (double)t_val[e] * S[(long long)t_idx[e] * s + h];
+    if (h < s) Y[(long long)h * n + j] = acc;
+  }
+}
+
+template <class T>
+void launch_sketch_gauss_csr(const int* t_ptr, const int* t_idx, const T* t_val, long long n, int s, const double* S,
+                             double* Y, hipStream_t st) {
+  hipLaunchKernelGGL((k_sketch_gauss_csr<T>), dim3(ceil_div(n, kBlock / kWave)), dim3(kBlock), 0, st, t_ptr, t_idx,
+                     t_val, n, s, S, Y);
+}
+template void launch_sketch_gauss_csr<double>(const int*, const int*, const double*, long long, int, const double*,
+                                              double*, hipStream_t);
+template void launch_sketch_gauss_csr<float>(const int*, const int*, const float*, long long, int, const double*,
+                                             double*, hipStream_t);
+
+__global__ void k_widen(const float* __restrict__ a, double* __restrict__ b, long long count) {
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < count; i += (long long)gridDim.x * kBlock)
+    b[i] = (double)a[i];
+}
+
+void widen(const float* a, double* b, long long count, hipStream_t st) {
+  hipLaunchKernelGGL(k_widen, dim3((unsigned)std::min<long long>(ceil_div(count, kBlock), 4096)), dim3(kBlock), 0,
+                     st, a, b, count);
+}
+
 void launch_gen_sketch(uint64_t seed, int s, long long m, int xi, uint16_t* rows,
                        uint8_t* negmask, hipStream_t st) {
   hipLaunchKernelGGL(k_gen_sketch, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, st, seed, s, m,

@@ -13,6 +13,13 @@ void launch_gen_sketch(uint64_t seed, int s, long long m, int xi, uint16_t* rows
 int check_csr(const int* row_ptr, const int* col_idx, long long m, long long n, long long nnz, int* bad_dev,
               hipStream_t st);
 void launch_gen_probes(uint64_t seed, long long n, int r, double* W, hipStream_t st);
+// Gaussian sketch S (s x m column-major, N(0, 1/s) entries, stream 3) and
+// Y = S A for CSR A through the CSR of A^T (Y row-major s x n).
+void launch_gen_gauss_sketch(uint64_t seed, int s, long long m, double* S, hipStream_t st);
+template <class T>
+void launch_sketch_gauss_csr(const int* t_ptr, const int* t_idx, const T* t_val, long long n, int s, const double* S,
+                             double* Y, hipStream_t st);
+void widen(const float* a, double* b, long long count, hipStream_t st);  // b = (double) a
 template <class T>
 void launch_csr_transpose(const int* row_ptr, const int* col_idx, const T* val, long long m,
                           long long n, long long nnz, int* t_ptr, int* t_idx, T* t_val,

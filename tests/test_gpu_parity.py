@@ -74,6 +74,63 @@ def test_sketch_other_xi_matches_oracle(lib, kind, xi):
     test_sketch_matches_oracle(lib, kind, 3001, 120, 20, xi)
 
 
+@pytest.mark.parametrize("kind,dtype", [("dense", torch.float64), ("dense", torch.float32),
+                                        ("csr", torch.float64), ("csr", torch.float32)])
+def test_gaussian_sketch_matches_oracle(lib, kind, dtype):
+    """Gaussian sketch (option sketch = 1): Y = S A against the oracle's S
+    (same counter-based stream) times A.  FP64 products, and CSR with FP64
+    accumulation: within 1e-12 of |S| |A| per entry (the Box-Muller values
+    agree to a few ulps).  Dense FP32 A: the FP32 GEMM with S rounded to
+    FP32, bound (m + 4) 2^-24 |S| |A| -- the FP32 error of the sketch."""
+    seed, block, m, n = 13, 20, 3001, 150
+    if kind == "dense":
+        A = _dense(m, n, 5)
+        if dtype == torch.float32:
+            A = A.astype(np.float32).astype(np.float64)
+        Ag, Ad = _t(A, dtype), A
+    else:
+        A = _csr(m, n, 5, 6)
+        if dtype == torch.float32:
+            A = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
+        Ag, Ad = _gpu_csr(A, dtype), A.toarray()
+    with lib.Context(Ag, mu=1e-4, block=block, seed=seed, max_outer=1, sketch="gaussian") as ctx:
+        s = ctx.sizes()["s"]
+        Y = ctx.query(1).reshape(s, n)
+        assert ctx.query(2).size == 0
+        W = ctx.query(4).reshape(10, n).T
+    S = orng.gaussian_sketch(seed, s, m)
+    Yref = S @ Ad
+    mag = np.abs(S) @ np.abs(Ad)
+    tol = (m + 4) * 2.0 ** -24 if (kind == "dense" and dtype == torch.float32) else 1e-12
+    assert np.all(np.abs(Y - Yref) <= tol * mag + 1e-300)
+    np.testing.assert_allclose(W, orng.gaussian_probes(seed, n, 10), rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+def test_gaussian_sketch_solution_matches_oracle(lib, kind):
+    """APLICUR with the Gaussian sketch: the oracle's CUR indices over the
+    first outer steps, and the dense-QR solution."""
+    if kind == "dense":
+        A = _dense(600, 70, 22, decades=5)
+        Ag = _t(A)
+    else:
+        A = _csr(5000, 300, 8, 23, decades=4)
+        Ag = _gpu_csr(A)
+    b = np.random.default_rng(4).standard_normal(A.shape[0])
+    mu, block = 1e-6, 7
+    tr = Trace()
+    aplicur(A, b, mu, Options(block=block, tol_ne=1e-30, max_rank=3 * block, sketch="gaussian"), tr)
+    with lib.Context(Ag, mu=mu, block=block, tol_ne=1e-30, max_rank=3 * block, max_outer=3,
+                     sketch="gaussian") as ctx:
+        ctx.solve(_t(b))
+        J, I = ctx.query(5), ctx.query(6)
+    np.testing.assert_array_equal(J, tr.J[:len(J)])
+    np.testing.assert_array_equal(I, tr.I[:len(I)])
+    x, info = lib.lstsq(Ag, _t(b), mu=mu, block=block, tol_ne=1e-10, sketch="gaussian")
+    xr = solve_dense_qr(A, b, mu)
+    assert info.status == 0 and np.linalg.norm(x.cpu().numpy() - xr) <= 1e-6 * np.linalg.norm(xr)
+
+
 def test_solution_with_xi_matches_oracle(lib):
     """A whole APLICUR solve with xi = 4: the same CUR indices as the oracle's
     first outer steps and the dense-QR solution."""

@@ -130,3 +130,13 @@ def test_adjoint_matches_finite_differences():
         E = r.standard_normal((m, k)); E /= np.linalg.norm(E)
         fd = (loss(A, B + h * E) - loss(A, B - h * E)) / (2 * h)
         assert abs(fd - np.sum(dB * E)) <= 1e-5 * max(1.0, abs(fd))
+
+
+def test_aplicur_gaussian_sketch_reaches_dense_qr():
+    """The Gaussian sketch changes the CUR indices, not the solution."""
+    r = np.random.default_rng(31)
+    A = synth.dense_svd(r, 400, 50, 10.0 ** (-4 * np.arange(50) / 49))
+    b = r.standard_normal(400)
+    x = aplicur(A, b, 1e-6, Options(block=6, tol_ne=1e-10, sketch="gaussian"))
+    xr = solve_dense_qr(A, b, 1e-6)
+    assert np.linalg.norm(x - xr) <= 1e-7 * np.linalg.norm(xr)

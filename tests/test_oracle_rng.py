@@ -107,3 +107,25 @@ def test_gaussian_probes():
     assert kstest(W[:, 0], "norm").pvalue > 1e-6
     # columns are independent streams
     assert abs(np.corrcoef(W[:, 0], W[:, 1])[0, 1]) < 0.03
+
+
+def test_gaussian_sketch():
+    """Gaussian embedding: N(0, 1/s) entries (mean and variance within 6
+    standard errors), E ||S x||^2 = ||x||^2 on average over columns, column
+    order independent of m, a different seed gives a different S, and S A by
+    the oracle's route equals the explicit product for dense and CSR A."""
+    import scipy.sparse as sp
+    s, m = 40, 20000
+    S = rng.gaussian_sketch(5, s, m)
+    N = S.size
+    assert abs(S.mean()) < 6 * (1 / math.sqrt(s)) / math.sqrt(N)
+    var = S.var() * s
+    assert abs(var - 1.0) < 6 * math.sqrt(2.0 / N)
+    col = (S ** 2).sum(axis=0)  # chi-square(s) / s per column: mean 1, variance 2/s
+    assert abs(col.mean() - 1.0) < 6 * math.sqrt(2.0 / s / m)
+    np.testing.assert_array_equal(rng.gaussian_sketch(5, s, 500), S[:, :500])
+    assert np.mean(rng.gaussian_sketch(6, s, 500) != S[:, :500]) > 0.99
+    r = np.random.default_rng(1)
+    A = sp.random(300, 30, density=0.1, random_state=2, format="csr")
+    Sg = rng.gaussian_sketch(9, 12, 300)
+    np.testing.assert_allclose((A.T @ Sg.T).T, Sg @ A.toarray(), rtol=1e-13, atol=1e-13)
