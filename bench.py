@@ -283,6 +283,38 @@ def sketch_study(ap, synth, torch):
     print(json.dumps({"sketch_study": out}), flush=True)
 
 
+def schedule_study(ap, synth, torch):
+    """Sec. 7.1 variants on the dense kernel workload at half size (FP32 A,
+    16 RHS, mu = 1e-3, block 250) and on the sparse workload (rank cap 256):
+    fully adaptive (schedule 0), rank-adaptive single shot (1), fixed-rank
+    single shot at the rank the adaptive run reached (2).  One JSON line."""
+    out = {}
+    A, B = synth.rbf_kernel_gpu(3003, 20000, 16)
+    w = synth.workload(2, 1.0)
+    Ag = ap.CSRMatrix.from_scipy(w.A, device="cuda", dtype=torch.float64)
+    bg = torch.as_tensor(w.B, device="cuda")
+    cases = (("rbf20000", A, B, dict(mu=1e-3, block=250, tol_ne=1e-8)),
+             ("csr200000", Ag, bg, dict(mu=w.mu, block=w.block, tol_ne=w.tol, max_rank=256)))
+    for name, M, R, opts in cases:
+        res, rank0 = {}, None
+        for sched in (0, 1, 2):
+            o = dict(opts)
+            if sched == 2:
+                o["max_rank"] = rank0
+            ap.lstsq(M, R, schedule=sched, **o)  # warm-up
+            ms, (X, info) = _timed(torch, lambda: ap.lstsq(M, R, schedule=sched, **o))
+            if sched == 0:
+                rank0 = info.rank
+            res[f"schedule{sched}"] = {"ms": round(ms, 1), "rank": info.rank, "iters": info.iters,
+                                       "phases": info.phases, "rebuilds": info.rebuilds, "eta": info.eta,
+                                       "t_cur_ms": round(info.t_cur_ms, 1), "t_precond_ms": round(info.t_precond_ms, 1),
+                                       "t_lsqr_ms": round(info.t_lsqr_ms, 1)}
+            log(f"[bench] schedule study {name} schedule {sched}: {ms:.0f} ms rank {info.rank} "
+                f"{info.iters} it {info.rebuilds} builds")
+        out[name] = res
+    print(json.dumps({"schedule_study": out}), flush=True)
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -297,6 +329,8 @@ def main():
     ap_.add_argument("--blocked-prec", type=int, default=0, choices=(0, 1, 2),
                      help="arithmetic of --blocked-products: 0 FP64 accumulation, 1 FP32, 2 BF16")
     ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
+    ap_.add_argument("--schedule-study", action="store_true",
+                     help="only the adaptive against single-shot schedules comparison, one JSON line")
     ap_.add_argument("--sketch-study", action="store_true",
                      help="only the sparse sign against Gaussian sketch comparison, one JSON line")
     ap_.add_argument("--full-configs", action="store_true",
@@ -315,6 +349,9 @@ def main():
 
     if args.blocked_products:
         blocked_products(ap, synth, torch, prec=args.blocked_prec)
+        return
+    if args.schedule_study:
+        schedule_study(ap, synth, torch)
         return
     if args.sketch_study:
         sketch_study(ap, synth, torch)

@@ -117,7 +117,11 @@ typedef struct aplicur_opts {
                         N(0, 1/s) entries from the counter-based stream 3, Y = S A by
                         rocBLAS GEMM for dense A (FP32 A: FP32 S and accumulation,
                         widened), or a column-wise kernel over the CSR of A^T         */
-  int32_t reserved[1];
+  int32_t schedule;  /* 0: fully adaptive (default, Alg. 3: phases interleaved with the rank
+                        growth and the re-preconditioning test); 1: rank-adaptive single
+                        shot (the rank grows until rho <= eps_cur or the cap, then one P and
+                        one final phase); 2: fixed-rank single shot (the rank grows to the
+                        cap max_rank, then one P and one final phase).  Sec. 7.1       */
 } aplicur_opts;
 
 /* ------------------------------------------------------------------ info  */

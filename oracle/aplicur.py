@@ -54,6 +54,7 @@ class Options:
     r_probes: int = 10
     xi: int = 8                # non-zeros per column of the sparse sign sketch (1..8)
     sketch: str = "sparse"     # "sparse" (sparse sign, the default) or "gaussian"
+    schedule: int = 0          # 0 fully adaptive; 1 rank-adaptive single shot; 2 fixed-rank single shot
 
 
 @dataclass
@@ -152,14 +153,17 @@ def aplicur(A, b, mu, opts=None, trace=None):
         # Part 2: update the QR factorisation of R^T
         if len(I_plus):
             Q_R, T_R = augment_qr(Q_R, T_R, A[I_plus, :].T)
-        final = rho <= eps_cur or exhausted or len(J) >= max_rank
+        # Sec. 7.1 variants: single shot builds P once, at the final rank
+        # (schedule 2: the rank cap, whatever rho)
+        grown = exhausted or len(J) >= max_rank
+        final = grown or (opts.schedule != 2 and rho <= eps_cur)
         if trace is not None:
             trace.ranks.append(len(J))
             trace.rhos.append(rho)
             trace.I, trace.J = I.copy(), J.copy()
         # Part 3: re-precondition and run LSQR
         gap = rho - eps_cur
-        rebuild = final or (d_cur / gap >= opts.nu_prec)
+        rebuild = final or (opts.schedule == 0 and d_cur / gap >= opts.nu_prec)
         if trace is not None:
             trace.rebuild.append(rebuild)
         if rebuild:

@@ -74,7 +74,7 @@ def _device(A):
 
 def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.0, eps_lsqr=1e-10,
               tol_ne=1e-8, max_iter=100000, max_rank=0, precond=True, precision=0, max_outer=0,
-              r_probes=10, workers=0, tune=0, graphs=0, columns=0, xi=8, sketch=0):
+              r_probes=10, workers=0, tune=0, graphs=0, columns=0, xi=8, sketch=0, schedule=0):
     lib = L.load()
     o = L.Opts()
     lib.aplicur_opts_default(C.byref(o))
@@ -86,6 +86,7 @@ def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.
     o.columns = int(bool(columns))
     o.xi = int(xi)
     o.sketch = {"sparse": 0, "gaussian": 1}[sketch] if isinstance(sketch, str) else int(sketch)
+    o.schedule = int(schedule)
     return o
 
 

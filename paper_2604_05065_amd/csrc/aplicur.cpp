@@ -323,6 +323,7 @@ static void validate(const aplicur_mat* A, const aplicur_opts* o) {
   APL_REQUIRE(o->max_iter >= 0, "max_iter must be >= 0");
   APL_REQUIRE(o->xi >= 0 && o->xi <= 8, "xi must be in [1, 8] (0: the default 8)");
   APL_REQUIRE(o->sketch == 0 || o->sketch == 1, "sketch must be 0 (sparse sign) or 1 (Gaussian)");
+  APL_REQUIRE(o->schedule >= 0 && o->schedule <= 2, "schedule must be 0, 1 or 2");
 }
 
 // ------------------------------------------------------------------ product tiles
@@ -1330,10 +1331,12 @@ static void outer_loop(Ctx& c, hipStream_t s, SolveLog& lg, Phases&& phases) {
     ++lg.outer;
     if (sr.added == 0 && c.rank == 0) break;
     lg.last_rho = sr.rho;
-    const bool final_step = sr.rho <= c.eps_cur || sr.exhausted || c.rank >= c.L ||
-                            (c.o.max_outer > 0 && lg.outer >= c.o.max_outer);
+    // schedule 0: Alg. 3; 1 / 2: single shot, P built once at the final rank
+    // (2: the rank cap regardless of rho)
+    const bool grown = sr.exhausted || c.rank >= c.L || (c.o.max_outer > 0 && lg.outer >= c.o.max_outer);
+    const bool final_step = grown || (c.o.schedule != 2 && sr.rho <= c.eps_cur);
     const double gap = sr.rho - c.eps_cur;
-    const bool rebuild = final_step || (d_cur / gap >= c.o.nu_prec);
+    const bool rebuild = final_step || (c.o.schedule == 0 && d_cur / gap >= c.o.nu_prec);
     c.rho_hist.push_back(sr.rho);
     c.rank_hist.push_back(c.rank);
     c.rebuild_hist.push_back(rebuild ? 1 : 0);

@@ -131,6 +131,35 @@ def test_gaussian_sketch_solution_matches_oracle(lib, kind):
     assert info.status == 0 and np.linalg.norm(x.cpu().numpy() - xr) <= 1e-6 * np.linalg.norm(xr)
 
 
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_single_shot_schedules_match_oracle(lib, kind, schedule):
+    """Single-shot schedules (Sec. 7.1): the oracle's rank sequence, rebuild
+    flags (one build, at the end) and CUR indices; the dense-QR solution."""
+    if kind == "dense":
+        A = _dense(500, 60, 24, decades=6)
+        Ag = _t(A)
+    else:
+        A = _csr(4000, 250, 8, 25, decades=5)
+        Ag = _gpu_csr(A)
+    b = np.random.default_rng(5).standard_normal(A.shape[0])
+    mu, block, cap, tol = 1e-8, 5, 30, 1e-10
+    tr = Trace()
+    x_or = aplicur(A, b, mu, Options(block=block, tol_ne=tol, max_rank=cap, schedule=schedule), tr)
+    with lib.Context(Ag, mu=mu, block=block, tol_ne=tol, max_rank=cap, schedule=schedule) as ctx:
+        x, info = ctx.solve(_t(b))
+        ranks, reb = ctx.query(8), ctx.query(9)
+        J, I = ctx.query(5), ctx.query(6)
+    assert list(ranks) == tr.ranks
+    assert list(reb) == [int(v) for v in tr.rebuild]
+    assert int(np.sum(reb)) == 1 and info.rebuilds == 1
+    np.testing.assert_array_equal(J, tr.J)
+    np.testing.assert_array_equal(I, tr.I)
+    xr = solve_dense_qr(A, b, mu)
+    assert info.status == 0 and np.linalg.norm(x.cpu().numpy() - xr) <= 1e-6 * np.linalg.norm(xr)
+    assert np.linalg.norm(x_or - xr) <= 1e-6 * np.linalg.norm(xr)
+
+
 def test_solution_with_xi_matches_oracle(lib):
     """A whole APLICUR solve with xi = 4: the same CUR indices as the oracle's
     first outer steps and the dense-QR solution."""

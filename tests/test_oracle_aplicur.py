@@ -140,3 +140,26 @@ def test_aplicur_gaussian_sketch_reaches_dense_qr():
     x = aplicur(A, b, 1e-6, Options(block=6, tol_ne=1e-10, sketch="gaussian"))
     xr = solve_dense_qr(A, b, 1e-6)
     assert np.linalg.norm(x - xr) <= 1e-7 * np.linalg.norm(xr)
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_single_shot_schedules(schedule):
+    """Sec. 7.1 variants: one preconditioner build, at the final rank (the rank
+    where rho <= eps_cur for the rank-adaptive single shot, the cap for the
+    fixed-rank one), followed by the final phase; same solution."""
+    r = np.random.default_rng(32)
+    A = synth.dense_svd(r, 500, 60, 10.0 ** (-6 * np.arange(60) / 59))
+    b = r.standard_normal(500)
+    mu, cap = 1e-8, 30
+    tr = Trace()
+    x = aplicur(A, b, mu, Options(block=5, tol_ne=1e-10, max_rank=cap, schedule=schedule), tr)
+    assert tr.rebuild == [False] * (len(tr.rebuild) - 1) + [True]
+    assert len(tr.phase_iters) >= 1
+    if schedule == 2:
+        assert tr.ranks[-1] == cap
+    else:
+        from oracle.aplicur import default_eps_cur
+        assert tr.rhos[-1] <= default_eps_cur(mu) or tr.ranks[-1] == cap
+        assert all(rho > default_eps_cur(mu) for rho in tr.rhos[:-1])
+    xr = solve_dense_qr(A, b, mu)
+    assert np.linalg.norm(x - xr) <= 1e-6 * np.linalg.norm(xr)
