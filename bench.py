@@ -283,6 +283,53 @@ def sketch_study(ap, synth, torch):
     print(json.dumps({"sketch_study": out}), flush=True)
 
 
+def paper_workloads(ap, synth, torch, tol=1e-8, budget=30000):
+    """The paper's own test sets (Sec. 6.3, the experiments of Secs. 7-8 without
+    the comparison systems): APLICUR against plain LSQR, both FP64 on the GPU,
+    time to eta <= tol (iteration budget `budget` each), block b = n/50.  Dense
+    incoherent / coherent U Sigma V^T with sharp (kappa 1e7, 1e15) or smooth
+    (kappa 1e15) decay and consistent-x right-hand sides (noise 1e-2 of
+    ||A x*||); sparse 1% density, incoherent / coherent.  One JSON line."""
+    cases = [
+        ("dense 6000x5000 incoherent sharp 1e7", "dense", (6000, 5000, "sharp7", False), [1e-4, 1e-8]),
+        ("dense 6000x5000 incoherent sharp 1e15", "dense", (6000, 5000, "sharp15", False), [1e-8]),
+        ("dense 6000x5000 coherent sharp 1e7", "dense", (6000, 5000, "sharp7", True), [1e-4]),
+        ("dense 15000x2000 incoherent sharp 1e7", "dense", (15000, 2000, "sharp7", False), [1e-4]),
+        ("dense 6000x5000 incoherent smooth 1e15", "dense", (6000, 5000, "smooth", False), [1e-4, 1e-6, 1e-8, 0.0]),
+        ("sparse 12000x10000 1% incoherent sharp 1e7", "sparse", (12000, 10000, "sharp7", False), [1e-4]),
+        ("sparse 30000x4000 1% incoherent sharp 1e7", "sparse", (30000, 4000, "sharp7", False), [1e-4]),
+        ("sparse 12000x10000 1% coherent sharp 1e7", "sparse", (12000, 10000, "sharp7", True), [1e-4]),
+    ]
+    out = []
+    Aw, bw = synth.paper_dense_gpu(1, 300, 60, "sharp7")
+    ap.lstsq(Aw, bw, mu=1e-4, block=6)  # warm-up (library and rocBLAS initialisation)
+    for ci, (name, kind, (m, n, decay, coh), mus) in enumerate(cases):
+        if kind == "dense":
+            A, b = synth.paper_dense_gpu(6000 + ci, m, n, decay, coherent=coh, noise=1e-2)
+        else:
+            As, bh = synth.paper_sparse(6000 + ci, m, n, decay, coherent=coh)
+            A = ap.CSRMatrix.from_scipy(As, device="cuda", dtype=torch.float64)
+            b = torch.as_tensor(bh, device="cuda")
+        for mu in mus:
+            row = {"workload": name, "mu": mu}
+            for label, pc in (("aplicur", True), ("plain_lsqr", False)):
+                o = dict(mu=mu, block=max(1, n // 50), tol_ne=tol, max_iter=budget, precond=pc)
+                try:
+                    ms, (x, info) = _timed(torch, lambda: ap.lstsq(A, b, **o))
+                except RuntimeError as e:  # a breakdown the method reports (e.g. CholQR of C)
+                    row[label] = {"error": str(e)}
+                    log(f"[bench] paper workload {name} mu={mu:g} {label}: {e}")
+                    continue
+                row[label] = {"ms": round(ms, 1), "iters": info.iters, "eta": info.eta, "status": info.status,
+                              "rank": info.rank}
+                log(f"[bench] paper workload {name} mu={mu:g} {label}: {ms:.0f} ms, {info.iters} it, "
+                    f"eta {info.eta:.1e}, rank {info.rank}, status {info.status}")
+            out.append(row)
+        del A, b
+        torch.cuda.empty_cache()
+    print(json.dumps({"paper_workloads": out}), flush=True)
+
+
 def schedule_study(ap, synth, torch):
     """Sec. 7.1 variants on the dense kernel workload at half size (FP32 A,
     16 RHS, mu = 1e-3, block 250) and on the sparse workload (rank cap 256):
@@ -329,6 +376,8 @@ def main():
     ap_.add_argument("--blocked-prec", type=int, default=0, choices=(0, 1, 2),
                      help="arithmetic of --blocked-products: 0 FP64 accumulation, 1 FP32, 2 BF16")
     ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
+    ap_.add_argument("--paper-workloads", action="store_true",
+                     help="only the paper's test sets, APLICUR against plain LSQR, one JSON line")
     ap_.add_argument("--schedule-study", action="store_true",
                      help="only the adaptive against single-shot schedules comparison, one JSON line")
     ap_.add_argument("--sketch-study", action="store_true",
@@ -349,6 +398,9 @@ def main():
 
     if args.blocked_products:
         blocked_products(ap, synth, torch, prec=args.blocked_prec)
+        return
+    if args.paper_workloads:
+        paper_workloads(ap, synth, torch)
         return
     if args.schedule_study:
         schedule_study(ap, synth, torch)

@@ -24,7 +24,8 @@ import numpy as np
 import scipy.sparse as sp
 
 __all__ = ["rng_for", "haar", "dense_svd", "sparse_scaled", "rbf_kernel", "rbf_kernel_gpu", "consistent_x",
-           "workload", "batch_shapes", "Workload", "dense_svd_gpu"]
+           "workload", "batch_shapes", "Workload", "dense_svd_gpu", "paper_sigma", "paper_dense_gpu",
+           "paper_sparse"]
 
 
 def rng_for(c, k):
@@ -188,3 +189,67 @@ def rbf_kernel_gpu(seed, npts, nrhs, dim=8, h=1.0):
         A[i0:i0 + step] = torch.exp(-d2 / (2.0 * h * h)).to(torch.float32)
     B = torch.randn(npts, nrhs, device="cuda", dtype=torch.float64, generator=g)
     return A, B
+
+
+# ---------------------------------------------------------------- the paper's test sets (Sec. 6.3)
+def paper_sigma(n, decay):
+    """Singular values of the paper's test matrices (largest first):
+    'sharp7'  [logspace(2, -2, 0.2n), logspace(-4.8, -5, 0.8n)]  (kappa 1e7);
+    'sharp15' [logspace(2, -2, 0.2n), logspace(-12, -13, 0.8n)]  (kappa 1e15);
+    'smooth'  10^(2 - 15 sqrt((i - 1)/(n - 1))), i = 1..n: a root-exponential
+              decay with kappa 1e15 (the text gives the type and kappa only;
+              this law is a reading)."""
+    if decay == "smooth":
+        return 10.0 ** (2.0 - 15.0 * np.sqrt(np.arange(n) / max(n - 1, 1)))
+    k = int(round(0.2 * n))
+    lo = {"sharp7": (-4.8, -5.0), "sharp15": (-12.0, -13.0)}[decay]
+    return np.concatenate([np.logspace(2, -2, k), np.logspace(lo[0], lo[1], n - k)])
+
+
+def paper_dense_gpu(seed, m, n, decay, coherent=False, noise=0.0):
+    """Dense test matrix A = U diag(sigma) V^T of Sec. 6.3.2 generated on the
+    GPU (FP64, torch, seeded): incoherent U, V from QR of Gaussians (Haar), or
+    coherent U = orth([I_n; 0] + 1e-8 J), V = orth(I_n + 1e-8 J) (J all ones);
+    and a consistent-x right-hand side b = A x* + e, x* ~ N(0, I), e Gaussian
+    projected off range(A) twice and scaled to noise ||A x*|| (the noise level
+    is read as relative).  Returns CUDA tensors (A, b)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed))
+    dev, f64 = "cuda", torch.float64
+    if coherent:
+        U0 = torch.full((m, n), 1e-8, device=dev, dtype=f64)
+        U0[:n, :n] += torch.eye(n, device=dev, dtype=f64)
+        V0 = torch.full((n, n), 1e-8, device=dev, dtype=f64) + torch.eye(n, device=dev, dtype=f64)
+    else:
+        U0 = torch.randn(m, n, device=dev, dtype=f64, generator=g)
+        V0 = torch.randn(n, n, device=dev, dtype=f64, generator=g)
+    U, _ = torch.linalg.qr(U0)
+    V, _ = torch.linalg.qr(V0)
+    sig = torch.as_tensor(paper_sigma(n, decay), device=dev, dtype=f64)
+    A = ((U * sig) @ V.T).contiguous()
+    xs = torch.randn(n, device=dev, dtype=f64, generator=g)
+    b = A @ xs
+    if noise > 0.0:
+        e = torch.randn(m, device=dev, dtype=f64, generator=g)
+        for _ in range(2):
+            e = e - U @ (U.T @ e)
+        b = b + noise * float(b.norm()) * e / e.norm()
+    return A, b
+
+
+def paper_sparse(seed, m, n, decay, coherent=False, density=0.01):
+    """Sparse test matrix of Sec. 6.3.2: B with ~density m n N(0,1) entries at
+    uniform positions, C~ = D^f B with D = diag(N(0,1)) (f = 0 incoherent, 20
+    coherent), columns of C~ normalised, A = C diag(sigma); b ~ N(0, I).
+    Returns (scipy CSR A, b) on the host."""
+    rng = np.random.Generator(np.random.PCG64(int(seed)))
+    B = sp.random(m, n, density=density, format="csr", random_state=rng, data_rvs=rng.standard_normal)
+    if coherent:
+        d = rng.standard_normal(m) ** 20
+        B = sp.diags(d) @ B
+    norms = np.sqrt(np.asarray(B.multiply(B).sum(axis=0))).ravel()
+    norms[norms == 0] = 1.0
+    A = (B @ sp.diags(paper_sigma(n, decay) / norms)).tocsr()
+    A.sort_indices()
+    return A, rng.standard_normal(m)
