@@ -47,7 +47,10 @@ extern "C" {
 #define APLICUR_W_MAXITER 1      /* iteration budget reached before tol_ne (x valid) */
 #define APLICUR_E_INVALID (-1)   /* bad argument (shape, null pointer, option range) */
 #define APLICUR_E_HIP (-3)       /* HIP runtime / rocBLAS failure */
-#define APLICUR_E_BREAKDOWN (-4) /* non-finite value met (NaN/Inf in A or B, or overflow) */
+#define APLICUR_E_BREAKDOWN (-4) /* non-finite value met (NaN/Inf in A or B, or overflow), or the
+                                    first CUR block is singular; a later block whose columns are
+                                    numerically dependent on C is dropped instead and ends the
+                                    rank growth (Alg. 2, chol(C^T C)) */
 #define APLICUR_E_NOMEM (-5)     /* device allocation failed */
 
 /* ------------------------------------------------------------------ matrix */

@@ -107,6 +107,16 @@ def lsqr_plain(A, b, mu, tol_ne=1e-8, eps_lsqr=0.0, max_iter=100000, x0=None):
     return x, total
 
 
+def _chol_ok(C):
+    """Whether C^T C (C dense or sparse) has a floating-point Cholesky factor."""
+    CtC = C.T @ C
+    try:
+        np.linalg.cholesky(CtC.toarray() if sp.issparse(CtC) else np.asarray(CtC))
+        return True
+    except np.linalg.LinAlgError:
+        return False
+
+
 def aplicur(A, b, mu, opts=None, trace=None):
     """Alg. 3 for one right-hand side; returns x (and fills ``trace``)."""
     opts = opts or Options()
@@ -146,6 +156,7 @@ def aplicur(A, b, mu, opts=None, trace=None):
         I_plus, J_plus, exhausted = augment_cur(A, E_row, I, J, C, W, R, min(opts.block, max_rank - len(J)))
         if len(J_plus) == 0 and len(J) == 0:
             break
+        prev = (I, J, C, W, R, E_row, Q_R, T_R, rho if len(J) else None)
         I = np.concatenate([I, I_plus])
         J = np.concatenate([J, J_plus])
         C, W, R, E_row = core_and_residual(A, Y, I, J)
@@ -153,6 +164,13 @@ def aplicur(A, b, mu, opts=None, trace=None):
         # Part 2: update the QR factorisation of R^T
         if len(I_plus):
             Q_R, T_R = augment_qr(Q_R, T_R, A[I_plus, :].T)
+        # Reading: new columns numerically dependent on C (C^T C no longer
+        # positive definite in floating point, so Alg. 2's chol(C^T C) would
+        # break down) end the rank growth: the step is undone and treated as
+        # exhaustion.
+        if len(prev[1]) and not _chol_ok(C):
+            I, J, C, W, R, E_row, Q_R, T_R, rho = prev
+            exhausted = True
         # Sec. 7.1 variants: single shot builds P once, at the final rank
         # (schedule 2: the rank cap, whatever rho)
         grown = exhausted or len(J) >= max_rank

@@ -1000,7 +1000,20 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
     if (l > 0)
       gemm(c, rocblas_operation_transpose, rocblas_operation_none, k2, k2, l, -1.0, T12, L, T12, L, 1.0, G22, k2);
     chol_upper(c, G22, k2, k2, s);
-    if (read_int(c.status_dev, s) != 0) throw Error(APLICUR_E_BREAKDOWN, "Cholesky of C^T C failed");
+    if (read_int(c.status_dev, s) != 0) {
+      if (l == 0) throw Error(APLICUR_E_BREAKDOWN, "Cholesky of C^T C failed");
+      // The new columns are numerically dependent on C: undo the step (U11
+      // back to its old value; the new slots of I, J, C, R, Q_R, T_R lie
+      // beyond the rank and are ignored) and end the rank growth.
+      gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, k2, -1.0, c.F, L, c.H, k2, 1.0, c.U, L);
+      c.J.resize(l);
+      c.I.resize(l);
+      APL_HIP(hipStreamSynchronize(s));
+      res.exhausted = true;
+      res.added = 0;
+      res.rho = c.rho_hist.empty() ? 0.0 : c.rho_hist.back();
+      return res;
+    }
     copy_block(G22, k2, T22, L, k2, k2, 1.0, s);
   }
   double rho = 0.0;

@@ -160,6 +160,22 @@ def test_single_shot_schedules_match_oracle(lib, kind, schedule):
     assert np.linalg.norm(x_or - xr) <= 1e-6 * np.linalg.norm(xr)
 
 
+def test_dependent_columns_end_rank_growth(lib):
+    """A CUR step whose columns are numerically dependent on C (the block
+    Cholesky of C^T C breaks down) is undone and ends the rank growth, as in
+    the oracle; the solve reaches its tolerance."""
+    r = np.random.default_rng(0)
+    A = synth.dense_svd(r, 1200, 1000, synth.paper_sigma(1000, "smooth"))
+    b = A @ r.standard_normal(1000)
+    tr = Trace()
+    aplicur(A, b, 0.0, Options(block=20, tol_ne=1e-8, max_iter=20000), tr)
+    with lib.Context(_t(A), mu=0.0, block=20, tol_ne=1e-8, max_iter=20000) as ctx:
+        x, info = ctx.solve(_t(b))
+        ranks = ctx.query(8)
+    assert ranks[-1] == ranks[-2] and abs(int(ranks[-1]) - tr.ranks[-1]) <= 20
+    assert info.status == 0 and ne_residual(A, b, x.cpu().numpy(), 0.0) <= 1.5e-8
+
+
 def test_solution_with_xi_matches_oracle(lib):
     """A whole APLICUR solve with xi = 4: the same CUR indices as the oracle's
     first outer steps and the dense-QR solution."""

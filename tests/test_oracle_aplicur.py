@@ -163,3 +163,17 @@ def test_single_shot_schedules(schedule):
         assert all(rho > default_eps_cur(mu) for rho in tr.rhos[:-1])
     xr = solve_dense_qr(A, b, mu)
     assert np.linalg.norm(x - xr) <= 1e-6 * np.linalg.norm(xr)
+
+
+def test_dependent_columns_end_rank_growth():
+    """Root-exponential decay to 1e-13 with mu = 0: the cross approximation
+    reaches columns numerically dependent on C (C^T C not positive definite in
+    floating point); that step is undone and the growth ends there (the rank
+    repeats in the trace), and the solve still reaches its tolerance."""
+    r = np.random.default_rng(0)
+    A = synth.dense_svd(r, 1200, 1000, synth.paper_sigma(1000, "smooth"))
+    b = A @ r.standard_normal(1000)
+    tr = Trace()
+    x = aplicur(A, b, 0.0, Options(block=20, tol_ne=1e-8, max_iter=20000), tr)
+    assert tr.ranks[-1] == tr.ranks[-2] and tr.rebuild[-1]
+    assert ne_residual(A, b, x, 0.0) <= 1e-8
