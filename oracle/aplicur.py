@@ -9,7 +9,8 @@
               E_row = Y - Y(:,J) U R; rho = randomized 2-norm bound (Sec. 5.3.1).
     Part 2    [Q_R, T_R] = augmentQR(Q_R, T_R, A(I+,:)^T) (Alg. 9).
     Part 3    if d_cur/(rho - eps_cur) >= nu_prec or rho <= eps_cur:
-                 P = CURPreconditioner Part 2 (Alg. 2); nu = inf in the final phase;
+                 P = CURPreconditioner Part 2 (Alg. 2, or the SVD-free Alg. 8
+                 when mu = 0 and precond = "svdfree"); nu = inf in the final phase;
                  x = lsqr(A_mu, b_aug, P, x, eps_lsqr, nu)  (warm start, Sec. 3.2);
                  d_cur = rho - eps_cur.
   until rho <= eps_cur.
@@ -35,8 +36,8 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import rng
-from .cur import (Preconditioner, augment_cur, augment_qr, core_and_residual,
-                  rho_estimate)
+from .cur import (Preconditioner, SvdFreePreconditioner, augment_cur, augment_qr,
+                  core_and_residual, rho_estimate)
 from .lsqr import STOP_BUDGET, plsqr_phase
 
 
@@ -55,6 +56,7 @@ class Options:
     xi: int = 8                # non-zeros per column of the sparse sign sketch (1..8)
     sketch: str = "sparse"     # "sparse" (sparse sign, the default) or "gaussian"
     schedule: int = 0          # 0 fully adaptive; 1 rank-adaptive single shot; 2 fixed-rank single shot
+    precond: str = "svd"       # "svd" (Alg. 2) or "svdfree" (Alg. 8, mu = 0 only)
 
 
 @dataclass
@@ -126,6 +128,11 @@ def aplicur(A, b, mu, opts=None, trace=None):
     A = A.tocsr() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
     m, n = A.shape
     delta = math.sqrt(mu)
+    svdfree = opts.precond == "svdfree"
+    if svdfree and mu != 0.0:
+        # Sec. 3.1 defines the SVD-free variant for the unregularised problem;
+        # its regularised form (a CUR of A_mu) is not built.
+        raise ValueError("the SVD-free preconditioner needs mu = 0")
     eps_cur = opts.eps_cur if opts.eps_cur > 0 else default_eps_cur(mu)
     max_rank = min(m, n) if opts.max_rank <= 0 else min(opts.max_rank, m, n)
     # initialisation
@@ -185,9 +192,14 @@ def aplicur(A, b, mu, opts=None, trace=None):
         if trace is not None:
             trace.rebuild.append(rebuild)
         if rebuild:
-            P = Preconditioner(C, W, Q_R, T_R, delta)
+            if svdfree:
+                P = SvdFreePreconditioner(C, W, Q_R, T_R, rho, eps_cur)
+                pinv_t = P.inv_t
+            else:
+                P = Preconditioner(C, W, Q_R, T_R, delta)
+                pinv_t = None
             nu = math.inf if final else opts.nu_lsqr
-            x, it, why = plsqr_phase(A, delta, b, x, P.inv, nu=nu, sigma_l=P.sigma_l,
+            x, it, why = plsqr_phase(A, delta, b, x, P.inv, pinv_t=pinv_t, nu=nu, sigma_l=P.sigma_l,
                                      eps_lsqr=0.0 if final else opts.eps_lsqr,
                                      tol_ne=opts.tol_ne,
                                      atb_norm=atb, pnorm=P.pnorm, baug_norm=bnorm,
@@ -207,7 +219,7 @@ def aplicur(A, b, mu, opts=None, trace=None):
                 stalls = 0
                 while eta > opts.tol_ne and total < opts.max_iter and stalls < 3:
                     eta_prev = eta
-                    x, it, why = plsqr_phase(A, delta, b, x, P.inv, sigma_l=P.sigma_l,
+                    x, it, why = plsqr_phase(A, delta, b, x, P.inv, pinv_t=pinv_t, sigma_l=P.sigma_l,
                                              eps_lsqr=0.0, tol_ne=opts.tol_ne,
                                              atb_norm=atb, pnorm=P.pnorm, baug_norm=bnorm,
                                              max_iter=opts.max_iter - total)

@@ -12,6 +12,11 @@
                         re-orthogonalisation, then QR of the remainder).
 * ``Preconditioner``  -- Alg. 2, Part 2 (SVD-based CUR preconditioner, eq. of
                         Sec. 3.1 with target level sqrt(sigma_l^2 + delta^2)).
+* ``SvdFreePreconditioner`` -- Alg. 8 (SVD-free variant of Sec. 3.1 for mu = 0):
+                        M^{-1} = T_R^{-T} A(I,J) T_C^{-1} by two triangular
+                        solves, P~^{-1} = s Q_R M^{-1} Q_R^T + (I - Q_R Q_R^T)
+                        with target level s = rho; not symmetric, so its
+                        transpose is applied separately.
 
 Readings: ties in the pivot search go to the first maximal entry in the
 current row order (LAPACK idamax); a zero pivot column means the residual is
@@ -151,3 +156,55 @@ class Preconditioner:
     def dense_inverse(self):
         n = self.V.shape[0]
         return np.eye(n) + (self.V * self.d) @ self.V.T
+
+
+class SvdFreePreconditioner:
+    """SVD-free CUR preconditioner (Alg. 8; the SVD-free variant of Sec. 3.1),
+    defined for mu = 0.
+
+    T_C = chol(C^T C) (upper), [Q_R, T_R] the QR of R^T with a positive
+    diagonal of T_R (the factorisation is then unique; P~ depends on the sign
+    convention, its singular values do not), M^{-1} = T_R^{-T} W T_C^{-1} with
+    W = A(I,J), and
+
+        P~^{-1}   = target Q_R M^{-1}   Q_R^T + (I - Q_R Q_R^T),
+        P~^{-T}   = target Q_R M^{-T}   Q_R^T + (I - Q_R Q_R^T),
+
+    with target = rho, the CUR error estimate (Alg. 8 takes the estimate of
+    Sec. 5.3.1 as the target level).  Readings: rho = 0 (an exact CUR) would
+    make P~^{-1} singular, so the target is then eps_cur; the dynamic rule's
+    smallest resolved singular value is taken as the target; ||P~|| =
+    max(1, ||M|| / target) is bounded above by the Frobenius norm of
+    M = T_C W^{-1} T_R^T.
+    """
+
+    def __init__(self, C, W, Q_R, T_R, rho, eps_cur):
+        CtC = _dense(C.T @ C)
+        T_C = np.linalg.cholesky(CtC).T
+        sg = np.where(np.diag(T_R) < 0, -1.0, 1.0)
+        self.Q = Q_R * sg
+        T_R = T_R * sg[:, None]
+        W = _dense(W)
+        # M^{-1} = T_R^{-T} (W T_C^{-1})
+        WTi = sla.solve_triangular(T_C, W.T, trans=1, lower=False).T  # W T_C^{-1}
+        self.Minv = sla.solve_triangular(T_R, WTi, trans=1, lower=False)
+        M = T_C @ np.linalg.solve(W, T_R.T)
+        self.target = float(rho) if rho > 0.0 else float(eps_cur)
+        self.sigma_l = self.target
+        self.pnorm = max(1.0, float(np.linalg.norm(M, "fro")) / self.target)
+        self.T_R = T_R
+
+    def inv(self, z):
+        """P~^{-1} z = z + Q_R (target M^{-1} - I) Q_R^T z."""
+        c = self.Q.T @ z
+        return z + self.Q @ (self.target * (self.Minv @ c) - c)
+
+    def inv_t(self, z):
+        """P~^{-T} z = z + Q_R (target M^{-T} - I) Q_R^T z."""
+        c = self.Q.T @ z
+        return z + self.Q @ (self.target * (self.Minv.T @ c) - c)
+
+    def dense_inverse(self):
+        n = self.Q.shape[0]
+        H = self.target * self.Minv - np.eye(self.Minv.shape[0])
+        return np.eye(n) + self.Q @ H @ self.Q.T

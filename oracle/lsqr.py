@@ -27,14 +27,17 @@ STOP_NONE, STOP_METRIC, STOP_LSQR, STOP_DYNAMIC, STOP_BUDGET, STOP_EXACT = range
 
 def plsqr_phase(A, delta, b, x, pinv, *, nu=math.inf, sigma_l=0.0, eps_lsqr=1e-10,
                 tol_ne=1e-8, atb_norm=1.0, pnorm=1.0, baug_norm=1.0, max_iter=10**9,
-                history=None):
+                history=None, pinv_t=None):
     """Run one warm-started PLSQR phase; returns (x_new, iterations, reason).
 
-    ``pinv(z)`` applies P^{-1} (symmetric, so it also serves as P^{-T});
-    ``pinv=None`` means P = I (plain LSQR).
+    ``pinv(z)`` applies P^{-1}; ``pinv_t(z)`` applies P^{-T} (None: P is
+    symmetric and ``pinv`` serves for both); ``pinv=None`` means P = I
+    (plain LSQR).
     """
     if pinv is None:
         pinv = lambda z: z  # noqa: E731
+    if pinv_t is None:
+        pinv_t = pinv
     m, n = A.shape
     aug = delta > 0.0
     u_t = b - A @ x
@@ -45,7 +48,7 @@ def plsqr_phase(A, delta, b, x, pinv, *, nu=math.inf, sigma_l=0.0, eps_lsqr=1e-1
     u_t = u_t / beta
     u_b = u_b / beta
     g = A.T @ u_t + (delta * u_b if aug else 0.0)
-    v = pinv(g)
+    v = pinv_t(g)
     alpha = math.sqrt(float(v @ v))
     if alpha == 0.0:
         return x.copy(), 0, STOP_EXACT
@@ -69,7 +72,7 @@ def plsqr_phase(A, delta, b, x, pinv, *, nu=math.inf, sigma_l=0.0, eps_lsqr=1e-1
             u_t = u_t / beta
             u_b = u_b / beta
             g = A.T @ u_t + (delta * u_b if aug else 0.0)
-            v = pinv(g) - beta * v
+            v = pinv_t(g) - beta * v
             alpha = math.sqrt(float(v @ v))
             if alpha > 0.0:
                 v = v / alpha
