@@ -91,7 +91,13 @@ typedef struct aplicur_opts {
   int32_t max_iter;  /* LSQR iteration budget per right-hand side (default 100000)         */
   int32_t max_rank;  /* cap on the CUR rank l (<= 0: min(m, n, 4096)); reaching it ends the
                         rank growth like rho <= eps_cur                                      */
-  int32_t precond;   /* 1: APLICUR (default); 0: plain LSQR on A_mu (no sketch, no CUR)   */
+  int32_t precond;   /* 1: APLICUR (default); 0: plain LSQR on A_mu (no sketch, no CUR);
+                        2: APLICUR with the SVD-free preconditioner (Alg. 8, Sec. 3.1):
+                        P~^{-1} = t Q_R M^{-1} Q_R^T + (I - Q_R Q_R^T), M^{-1} =
+                        T_R^{-T} A(I,J) T_C^{-1}, target level t = max(rho, eps_cur);
+                        applied through the orthonormal Q_R (n x l, dense and CSR A);
+                        mu = 0 only
+                        (E_INVALID otherwise); one right-hand side at a time        */
   int32_t precision; /* 0: FP64 vectors and products (default); 1: FP32 LSQR phases (FP32
                         values and vectors, FP64 scalars and reductions) with FP64
                         refinement (an extension, not in the paper); 2: as 1, and where
@@ -270,7 +276,10 @@ int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, doubl
  * 9 rebuild flags (outer int32), 10 sizes {m, n, s, xi, rank, outer, r} (int64),
  * 11 last preconditioner singular values sigma (rank doubles),
  * 12 per-phase iteration counts of column 0 (int32), 13 per-phase eta of column 0 (doubles),
- * 14 Jacobi sweeps of each preconditioner build (int32).
+ * 14 Jacobi sweeps of each preconditioner build (int32; 0 for the SVD-free form),
+ * 15 the middle matrix H = t M^{-1} - I of the last SVD-free preconditioner
+ * (P~^{-1} z = z + Q_R H Q_R^T z; rank x rank doubles, row-major; none
+ * otherwise).
  * Returns the number of bytes available (copies min(bytes, available)), or
  * a negative error.                                                        */
 int64_t aplicur_ctx_query(const aplicur_ctx* ctx, int32_t what, void* host_out, size_t bytes);

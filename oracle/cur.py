@@ -15,7 +15,7 @@
 * ``SvdFreePreconditioner`` -- Alg. 8 (SVD-free variant of Sec. 3.1 for mu = 0):
                         M^{-1} = T_R^{-T} A(I,J) T_C^{-1} by two triangular
                         solves, P~^{-1} = s Q_R M^{-1} Q_R^T + (I - Q_R Q_R^T)
-                        with target level s = rho; not symmetric, so its
+                        with target level s = max(rho, eps_cur); not symmetric, so its
                         transpose is applied separately.
 
 Readings: ties in the pivot search go to the first maximal entry in the
@@ -170,9 +170,12 @@ class SvdFreePreconditioner:
         P~^{-1}   = target Q_R M^{-1}   Q_R^T + (I - Q_R Q_R^T),
         P~^{-T}   = target Q_R M^{-T}   Q_R^T + (I - Q_R Q_R^T),
 
-    with target = rho, the CUR error estimate (Alg. 8 takes the estimate of
-    Sec. 5.3.1 as the target level).  Readings: rho = 0 (an exact CUR) would
-    make P~^{-1} singular, so the target is then eps_cur; the dynamic rule's
+    with target = max(rho, eps_cur): rho is the CUR error estimate (Alg. 8
+    takes the estimate of Sec. 5.3.1 as the target level).  Readings: the
+    target is not taken below the requested CUR accuracy eps_cur -- a CUR
+    more accurate than that (rho at rounding level at full rank, or rho = 0
+    for an exact CUR) would flatten the captured spectrum to a level that
+    rounding dominates, or make P~^{-1} singular; the dynamic rule's
     smallest resolved singular value is taken as the target; ||P~|| =
     max(1, ||M|| / target) is bounded above by the Frobenius norm of
     M = T_C W^{-1} T_R^T.
@@ -189,7 +192,7 @@ class SvdFreePreconditioner:
         WTi = sla.solve_triangular(T_C, W.T, trans=1, lower=False).T  # W T_C^{-1}
         self.Minv = sla.solve_triangular(T_R, WTi, trans=1, lower=False)
         M = T_C @ np.linalg.solve(W, T_R.T)
-        self.target = float(rho) if rho > 0.0 else float(eps_cur)
+        self.target = max(float(rho), float(eps_cur))
         self.sigma_l = self.target
         self.pnorm = max(1.0, float(np.linalg.norm(M, "fro")) / self.target)
         self.T_R = T_R

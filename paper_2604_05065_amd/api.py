@@ -80,7 +80,10 @@ def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.
     lib.aplicur_opts_default(C.byref(o))
     o.mu, o.block, o.seed, o.eps_cur = float(mu), int(block), int(seed), float(eps_cur)
     o.nu_prec, o.nu_lsqr, o.eps_lsqr, o.tol_ne = float(nu_prec), float(nu_lsqr), float(eps_lsqr), float(tol_ne)
-    o.max_iter, o.max_rank, o.precond = int(max_iter), int(max_rank), int(bool(precond))
+    # precond: True / "svd" (APLICUR), "svdfree" (Alg. 8, mu = 0), False (plain LSQR)
+    if isinstance(precond, str):
+        precond = {"svd": 1, "svdfree": 2}[precond]
+    o.max_iter, o.max_rank, o.precond = int(max_iter), int(max_rank), int(precond)
     o.precision, o.max_outer, o.r_probes = int(precision), int(max_outer), int(r_probes)
     o.workers, o.tune, o.graphs = int(workers), int(bool(tune)), int(bool(graphs))
     o.columns = int(bool(columns))
@@ -206,7 +209,7 @@ class Context:
         """Read internal state (see aplicur_ctx_query in include/aplicur.h)."""
         kinds = {1: np.float64, 2: np.int32, 3: np.int32, 4: np.float64, 5: np.int32, 6: np.int32,
                  7: np.float64, 8: np.int32, 9: np.int32, 10: np.int64, 11: np.float64, 12: np.int32,
-                 13: np.float64, 14: np.int32}
+                 13: np.float64, 14: np.int32, 15: np.float64}
         nbytes = self.lib.aplicur_ctx_query(self.ptr, what, None, 0)
         L.check(int(nbytes) if nbytes < 0 else 0)
         buf = (C.c_char * max(int(nbytes), 1))()

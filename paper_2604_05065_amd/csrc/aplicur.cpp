@@ -184,7 +184,7 @@ struct Ctx {
   // preconditioner
   double *Mx = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
          *pa_part = nullptr, *pa_c = nullptr, *Kc = nullptr, *Kr = nullptr, *pc1 = nullptr, *pc2 = nullptr,
-         *M2 = nullptr;
+         *M2 = nullptr, *M2t = nullptr;
   int *rr_ptr = nullptr, *rr_idx = nullptr, *rt_ptr = nullptr, *rt_idx = nullptr, *rscratch = nullptr;
   double *rr_val = nullptr, *rt_val = nullptr;
   unsigned long long* offmax = nullptr;
@@ -316,6 +316,8 @@ static void validate(const aplicur_mat* A, const aplicur_opts* o) {
   APL_REQUIRE(o->mu > 0.0 || A->m >= A->n, "mu = 0 needs m >= n");
   APL_REQUIRE(o->precision >= 0 && o->precision <= 2,
               "precision must be 0 (FP64), 1 (FP32 phases, FP64 refinement) or 2 (1 with BF16 blocked products)");
+  APL_REQUIRE(o->precond >= 0 && o->precond <= 2, "precond must be 0 (plain LSQR), 1 (APLICUR) or 2 (SVD-free)");
+  APL_REQUIRE(o->precond != 2 || o->mu == 0.0, "the SVD-free preconditioner (precond = 2) needs mu = 0");
   if (o->precond) {
     APL_REQUIRE(o->block >= 1 && o->block <= 280, "block must be in [1, 280]");
     APL_REQUIRE(o->r_probes >= 1 && o->r_probes <= 64, "r_probes must be in [1, 64]");
@@ -718,7 +720,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
       c->pa_c = c->arena.alloc<double>(L);
       c->prec.c = c->pa_c;
       c->prec.d = c->d;
-      if (op.csr) {
+      if (op.csr && c->o.precond != 2) {
         // implicit P-apply: R = A(I,:) and its transpose, capacity nnz(A)
         c->prec.implicit = 1;
         c->rr_ptr = c->arena.alloc<int>(L + 1);
@@ -740,6 +742,9 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
         c->prec.c1 = c->pc1;
         c->prec.c2 = c->pc2;
       } else {
+        // explicit P-apply through V (n x l): always for a dense A, and for the
+        // SVD-free form, whose non-normal middle factor would amplify the
+        // rounding of I - Q_R Q_R^T formed through Q_R = R^T T_R^{-1}
         c->prec.implicit = 0;
         c->Vhat = c->arena.alloc<double>((size_t)L * n);
         const int pchunks = (int)std::max<long long>(1, std::min<long long>(256, n / 64));
@@ -747,6 +752,12 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
         c->prec.chunks = pchunks;
         c->prec.part = c->pa_part;
         c->prec.V = c->Vhat;
+        if (c->o.precond == 2) {
+          c->M2 = c->arena.alloc<double>((size_t)L * L);
+          c->M2t = c->arena.alloc<double>((size_t)L * L);
+          c->pc2 = c->arena.alloc<double>(L);
+          c->prec.c2 = c->pc2;
+        }
       }
       long long lrows = std::max(m, n);
       c->fw.lupp_rows = (int)lrows;
@@ -1041,7 +1052,72 @@ constexpr double kJacobiSkip = 1e-9;
 // Largest diagonal ratio of T_R for which the one-product form M2 is used.
 constexpr double kM2MaxDiagRatio = 1e3;
 
+// CSR of R = A(I,:) and of R^T (the implicit P-apply reads R^T rows).
+static void build_r_csr(Ctx& c, hipStream_t s) {
+  const int l = c.rank;
+  long long nnzR;
+  if (c.op.f64)
+    nnzR = launch_gather_csr_rows<double>(c.op.row_ptr, c.op.col_idx, (const double*)c.op.val, c.I_dev, l, c.rr_ptr,
+                                          c.rr_idx, c.rr_val, c.op.nnz, c.rscratch, s);
+  else
+    nnzR = launch_gather_csr_rows<float>(c.op.row_ptr, c.op.col_idx, (const float*)c.op.val, c.I_dev, l, c.rr_ptr,
+                                         c.rr_idx, c.rr_val, c.op.nnz, c.rscratch, s);
+  launch_csr_transpose<double>(c.rr_ptr, c.rr_idx, c.rr_val, l, c.n, nnzR, c.rt_ptr, c.rt_idx, c.rt_val, c.rscratch,
+                               s);
+}
+
+// SVD-free preconditioner (Alg. 8, the SVD-free variant of Sec. 3.1; mu = 0):
+//   P~^{-1} = t Q_R M^{-1} Q_R^T + (I - Q_R Q_R^T),   M^{-1} = T_R^{-T} A(I,J) T_C^{-1},
+// with target level t = max(rho, eps_cur), rho of the last CUR step (a CUR
+// more accurate than eps_cur, rho at rounding level at full rank, would
+// flatten the captured spectrum to a level that rounding dominates).  With
+// H = t M^{-1} - I the apply is z + Q_R H Q_R^T z with the orthonormal Q_R of
+// augmentQR as V (dense and CSR alike); H is formed once per build by two
+// triangular solves and costs one l x l product per apply.  P~ is not
+// symmetric: the transpose apply uses H^T.  ||P~|| = max(1, ||M||_2 / t) is
+// bounded with ||M||_F, M = T_C U T_R^T.
+static void build_precond_svdfree(Ctx& c, hipStream_t s) {
+  const int l = c.rank, L = c.L;
+  const double rho = c.rho_hist.empty() ? 0.0 : c.rho_hist.back();
+  const double target = std::max(rho, c.eps_cur);
+  const double one = 1.0;
+  gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Kr, l);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Kc, l);
+  double mfro = 0.0;
+  APL_BLAS(rocblas_dnrm2(c.blas, l * l, c.Kc, 1, &mfro));
+  // H = target T_R^{-T} W T_C^{-1} - I with W = A(I,J) = C(I,:), column-major in Mx (ld l)
+  gather_sub_rows(c.C, c.m, c.I_dev, l, l, c.Mx, l, s);
+  APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                         rocblas_diagonal_non_unit, l, l, &target, c.TC, L, c.Mx, l));
+  APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                         rocblas_diagonal_non_unit, l, l, &one, c.TR, L, c.Mx, l));
+  add_diag(c.Mx, l, l, -1.0, s);
+  // V = Q_R, row-major n x l
+  transpose_rect<double>(c.Q, l, c.n, c.n, c.Vhat, l, s);
+  c.prec.ldv = l;
+  // H (column-major in Mx) row-major for the forward apply, and H^T row-major
+  // (= H column-major) for the transpose apply
+  transpose_square(c.Mx, l, c.M2, l, s);
+  copy_block(c.Mx, l, c.M2t, l, l, l, 1.0, s);
+  c.prec.M2 = c.M2;
+  c.prec.M2t = c.M2t;
+  APL_HIP(hipGetLastError());
+  APL_HIP(hipStreamSynchronize(s));
+  c.sweep_hist.push_back(0);
+  c.p_sigma_host.clear();
+  c.p_sigma_l = target;
+  c.p_target = target;
+  c.p_pnorm = std::max(1.0, mfro / target);
+  c.prec.ell = l;
+  c.have_prec = true;
+  ++c.prec_gen;
+}
+
 static void build_precond(Ctx& c, hipStream_t s) {
+  if (c.o.precond == 2) {
+    build_precond_svdfree(c, s);
+    return;
+  }
   const int l = c.rank, L = c.L;
   const int jw2 = 2 * jacobi_block_width();
   const int lp = ((l + jw2 - 1) / jw2) * jw2;
@@ -1079,16 +1155,7 @@ static void build_precond(Ctx& c, hipStream_t s) {
       transpose_square(c.Kc, l, c.Kr, l, s);
       c.prec.M2 = nullptr;
     }
-    // CSR of R = A(I,:) and of R^T
-    long long nnzR;
-    if (c.op.f64)
-      nnzR = launch_gather_csr_rows<double>(c.op.row_ptr, c.op.col_idx, (const double*)c.op.val, c.I_dev, l,
-                                            c.rr_ptr, c.rr_idx, c.rr_val, c.op.nnz, c.rscratch, s);
-    else
-      nnzR = launch_gather_csr_rows<float>(c.op.row_ptr, c.op.col_idx, (const float*)c.op.val, c.I_dev, l,
-                                           c.rr_ptr, c.rr_idx, c.rr_val, c.op.nnz, c.rscratch, s);
-    launch_csr_transpose<double>(c.rr_ptr, c.rr_idx, c.rr_val, l, c.n, nnzR, c.rt_ptr, c.rt_idx, c.rt_val,
-                                 c.rscratch, s);
+    build_r_csr(c, s);
   } else {
     // V = Q_R V_M stored row-major n x l  (= column-major l x n: V^T = V_M^T Q_R^T)
     gemm(c, rocblas_operation_transpose, rocblas_operation_transpose, l, c.n, l, 1.0, c.Vm, lp, c.Q, c.n, 0.0,
@@ -1481,7 +1548,8 @@ static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, lo
 constexpr int kBlkMaxCols = 64;
 
 static bool use_blocked(const Ctx& c, int nrhs) {
-  return nrhs >= 2 && !c.op.csr && !c.o.columns;
+  // the blocked P-apply has the SVD form's diagonal middle factor only
+  return nrhs >= 2 && !c.op.csr && !c.o.columns && c.o.precond != 2;
 }
 
 static int blk_kp(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
@@ -2361,6 +2429,10 @@ int64_t aplicur_ctx_query(const aplicur_ctx* ctx, int32_t what, void* host_out, 
       case 12: put(c.phase_iters0.data(), c.phase_iters0.size() * 4); break;
       case 13: put(c.phase_eta0.data(), c.phase_eta0.size() * 8); break;
       case 14: put(c.sweep_hist.data(), c.sweep_hist.size() * 4); break;
+      case 15:
+        if (c.o.precond == 2 && c.have_prec) dev(c.M2, sizeof(double) * (size_t)c.prec.ell * c.prec.ell);
+        else buf.clear();
+        break;
       default: g_last_error = "unknown query"; return APLICUR_E_INVALID;
     }
     if (host_out && bytes) std::memcpy(host_out, buf.data(), std::min(bytes, buf.size()));

@@ -51,6 +51,8 @@ void copy_block(const double* src, long long lds, double* dst, long long ldd, in
 void splitk_reduce(const double* W, int parts, long long m, long long n, double alpha, double beta, double* C,
                    long long ldc, hipStream_t s);
 void set_identity(double* X, long long ld, int n, hipStream_t s);
+// X(i, i) += v for i < n (column-major, ld).
+void add_diag(double* X, long long ld, int n, double v, hipStream_t s);
 // out (column-major, ld) = X diag(d): column j scaled by d[j].
 void scale_cols(const double* X, long long ld, int rows, int cols, const double* d, double* out, hipStream_t s);
 // dst (rows x cols, row-major, ldd) = (float) src (row-major, lds); contiguous when rows = 1.

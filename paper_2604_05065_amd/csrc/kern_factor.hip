@@ -913,6 +913,16 @@ void set_identity(double* X, long long ld, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_set_identity, dim3(ceil_div(n, kBlock), n), dim3(kBlock), 0, s, X, ld, n);
 }
 
+__global__ void k_add_diag(double* X, long long ld, int n, double v) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) X[i + (long long)i * ld] += v;
+}
+
+void add_diag(double* X, long long ld, int n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_add_diag, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, X, ld, n, v);
+}
+
 // Column-major dst = src^T (n x n): dst[i n + j] = src[j lds + i], 32 x 32
 // tiles through LDS so that both the loads and the stores are coalesced.
 __global__ void __launch_bounds__(kBlock) k_transpose(const double* src, long long lds, double* dst, int n) {

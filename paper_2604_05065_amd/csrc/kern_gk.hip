@@ -825,7 +825,7 @@ __global__ void __launch_bounds__(kBlock)
     double t = 0.0;
 #pragma unroll
     for (int i = 0; i < kBlock / kWave; ++i) t += acc4[i][threadIdx.x];
-    c[col] = d[col] * t;
+    c[col] = d ? d[col] * t : t;
   }
 }
 
@@ -1317,16 +1317,25 @@ static void launch_bwd(const OpDesc& A, const V* u_top, const V* u_bot, V* v, V*
   wk.alpha_count = grid;
 }
 
-// P.c <- the coefficients of (P^{-1} - I) z (stop check on slot sl, or none).
+// P.c <- the coefficients of (P^{-1} - I) z, or of (P^{-T} - I) z when trans
+// (stop check on slot sl, or none).
 template <class V>
-static void launch_pcoef(const OpDesc& A, const PrecDesc& P, long long n, const V* z, const GKState* sl,
+static void launch_pcoef(const OpDesc& A, const PrecDesc& P, long long n, const V* z, const GKState* sl, bool trans,
                          hipStream_t s) {
+  const double* Mid = (trans && P.M2t) ? P.M2t : P.M2;
   if (!P.implicit) {
     const long long rpc = (n + P.chunks - 1) / P.chunks;
     hipLaunchKernelGGL((k_pa_part<V>), dim3(ceil_div(P.ell, kBlock), P.chunks), dim3(kBlock), 0, s, P.V, n, P.ell,
                        P.ldv, z, P.part, rpc, sl);
-    hipLaunchKernelGGL(k_pa_red, dim3(ceil_div(P.ell, kWave)), dim3(kBlock), 0, s, P.part, P.chunks, P.ell, P.d,
-                       P.c, sl);
+    if (!Mid) {
+      hipLaunchKernelGGL(k_pa_red, dim3(ceil_div(P.ell, kWave)), dim3(kBlock), 0, s, P.part, P.chunks, P.ell, P.d,
+                         P.c, sl);
+      return;
+    }
+    hipLaunchKernelGGL(k_pa_red, dim3(ceil_div(P.ell, kWave)), dim3(kBlock), 0, s, P.part, P.chunks, P.ell,
+                       (const double*)nullptr, P.c2, sl);
+    hipLaunchKernelGGL(k_pr_gemv, dim3(ceil_div(P.ell, kBlock / kWave)), dim3(kBlock), 0, s, Mid, P.ell,
+                       (const double*)P.c2, (const double*)nullptr, P.c, sl);
     return;
   }
   const unsigned g1 = ceil_div(P.ell, kBlock / 16);
@@ -1337,8 +1346,8 @@ static void launch_pcoef(const OpDesc& A, const PrecDesc& P, long long n, const 
     hipLaunchKernelGGL((k_pr_rz<float, V>), dim3(g1), dim3(kBlock), 0, s, A.row_ptr, A.col_idx,
                        (const float*)A.val, P.I, P.ell, z, P.c1, sl);
   const unsigned g2 = ceil_div(P.ell, kBlock / kWave);
-  if (P.M2) {
-    hipLaunchKernelGGL(k_pr_gemv, dim3(g2), dim3(kBlock), 0, s, P.M2, P.ell, (const double*)P.c1,
+  if (Mid) {
+    hipLaunchKernelGGL(k_pr_gemv, dim3(g2), dim3(kBlock), 0, s, Mid, P.ell, (const double*)P.c1,
                        (const double*)nullptr, P.c, sl);
     return;
   }
@@ -1355,12 +1364,12 @@ void gk_iteration(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, GKState* st
     return;
   }
   const unsigned pg = prec_grid(*P, A.n);
-  launch_pcoef<V>(A, *P, A.n, vec.v, &st[1], s);
+  launch_pcoef<V>(A, *P, A.n, vec.v, &st[1], false, s);
   hipLaunchKernelGGL((k_pa_fwd<V>), dim3(pg), dim3(kBlock), 0, s, *P, A.n, (const V*)vec.v, vec.t, vec.w, vec.y,
                      (const GKState*)(st + 1), st, (const double*)wk.alpha_part, (int)wk.alpha_count);
   launch_fwd<V, kFwdPre>(A, vec.t, vec, st, wk, s);
   launch_bwd<V, false>(A, vec.u_top, vec.u_bot, vec.v, vec.g, st, wk, true, s);
-  launch_pcoef<V>(A, *P, A.n, vec.g, &st[1], s);
+  launch_pcoef<V>(A, *P, A.n, vec.g, &st[1], true, s);
   hipLaunchKernelGGL((k_pa_bwd<V>), dim3(pg), dim3(kBlock), 0, s, *P, A.n, (const V*)vec.g, vec.v,
                      (const GKState*)(st + 1), wk.alpha_part);
   wk.alpha_count = pg;
@@ -1405,7 +1414,7 @@ void gk_phase_init(const OpDesc& Ares, const OpDesc& A, const PrecDesc* P, const
     launch_bwd<V, true>(A, (const V*)vec.u_top, (const V*)vec.u_bot, vec.v, vec.g, st, wk, true, s);
   } else {
     launch_bwd<V, false>(A, (const V*)vec.u_top, (const V*)vec.u_bot, vec.v, vec.g, st, wk, true, s);
-    launch_pcoef<V>(A, *P, A.n, vec.g, &st[1], s);
+    launch_pcoef<V>(A, *P, A.n, vec.g, &st[1], true, s);
     const unsigned pg = prec_grid(*P, A.n);
     hipLaunchKernelGGL((k_pa_bwd<V>), dim3(pg), dim3(kBlock), 0, s, *P, A.n, (const V*)vec.g, vec.v,
                        (const GKState*)(st + 1), wk.alpha_part);
@@ -1421,7 +1430,7 @@ void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* 
     hipLaunchKernelGGL((k_axpy_x<V>), dim3(clamp_grid(ceil_div(A.n, kBlock))), dim3(kBlock), 0, s, A.n,
                        (const V*)vec.y, x);
   } else {
-    launch_pcoef<V>(A, *P, A.n, vec.y, nullptr, s);
+    launch_pcoef<V>(A, *P, A.n, vec.y, nullptr, false, s);
     hipLaunchKernelGGL((k_pa_x<V>), dim3(prec_grid(*P, A.n)), dim3(kBlock), 0, s, *P, A.n, (const V*)vec.y, x);
   }
 }

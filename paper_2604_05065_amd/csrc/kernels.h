@@ -77,15 +77,18 @@ struct PrecDesc {
   int ell;
   const double* d;
   double* c;      // ell
-  // explicit
+  // explicit: P^{-1} z = z + V (d .* (V^T z)), or z + V (M2 (V^T z)) when M2 is set
   long long ldv;
   const double* V;
   double* part;   // chunks x ell
   int chunks;
-  // implicit
+  // implicit: P^{-1} z = z + R^T (M (R z)), M = K diag(d) K^T as Kr (d .* (Kt .)) or M2
   const int* I;                    // rows of A forming R
   const double *Kt, *Kr;           // K^T and K, row-major ell x ell
-  const double* M2;                // K diag(d) K^T (ell x ell) when used instead of Kt / Kr, else null
+  const double* M2;                // the middle ell x ell matrix (row-major) when used instead of Kt / Kr /
+                                   // d, else null
+  const double* M2t;               // M2^T (row-major) for the transpose apply P^{-T} when M2 is not
+                                   // symmetric (the SVD-free form), else null
   const int *rt_ptr, *rt_idx;      // CSR of R^T (n rows)
   const double* rt_val;
   double *c1, *c2;                 // ell

@@ -57,6 +57,14 @@ def test_defaults_and_errors_without_gpu():
     assert lib.aplicur_sketch(ctypes.byref(m2), ctypes.byref(o), None, 0, None, ctypes.byref(ctx)) == _lib.E_INVALID
     assert b"precision" in lib.aplicur_last_error()
     o.precision = 0
+    # the SVD-free preconditioner is defined for mu = 0 only; precond is 0..2
+    o.precond, o.mu = 2, 1e-4
+    assert lib.aplicur_sketch(ctypes.byref(m2), ctypes.byref(o), None, 0, None, ctypes.byref(ctx)) == _lib.E_INVALID
+    assert b"SVD-free" in lib.aplicur_last_error()
+    o.precond, o.mu = 3, 0.0
+    assert lib.aplicur_sketch(ctypes.byref(m2), ctypes.byref(o), None, 0, None, ctypes.byref(ctx)) == _lib.E_INVALID
+    assert b"precond" in lib.aplicur_last_error()
+    o.precond = 1
     assert lib.aplicur_ctx_query(None, 1, None, 0) == _lib.E_INVALID
     # workspace arguments are checked before any device access
     o.mu = 0.0
