@@ -330,6 +330,50 @@ def paper_workloads(ap, synth, torch, tol=1e-8, budget=30000):
     print(json.dumps({"paper_workloads": out}), flush=True)
 
 
+def svdfree_study(ap, synth, torch, tol=1e-8, budget=30000):
+    """SVD-based (Alg. 2) against SVD-free (Alg. 8) preconditioner builds at
+    mu = 0, FP64 on the GPU, time to eta <= tol: the small dense workload
+    (2000 x 200, tol 1e-10) and the paper's test sets at mu = 0 (b = n/50).
+    Per variant: total time, P-build time and count, CUR time, iterations,
+    rank.  One JSON line."""
+    cases = [("dense 2000x200 (sigma 10^(-6i/200))", None, 1e-10),
+             ("dense 6000x5000 incoherent sharp 1e15", ("dense", 6000, 5000, "sharp15"), tol),
+             ("dense 6000x5000 incoherent smooth 1e15", ("dense", 6000, 5000, "smooth"), tol),
+             ("dense 15000x2000 incoherent sharp 1e15", ("dense", 15000, 2000, "sharp15"), tol),
+             ("sparse 12000x10000 1% incoherent sharp 1e15", ("sparse", 12000, 10000, "sharp15"), tol)]
+    out = []
+    Aw, bw = synth.paper_dense_gpu(1, 300, 60, "sharp7")
+    for pc in (1, 2):
+        ap.lstsq(Aw, bw, mu=0.0, block=6, precond=pc)  # warm-up
+    for ci, (name, spec, t) in enumerate(cases):
+        if spec is None:
+            w = synth.workload(1, 1.0)
+            A, b, block = torch.as_tensor(w.A, device="cuda"), torch.as_tensor(w.B, device="cuda"), w.block
+        elif spec[0] == "dense":
+            A, b = synth.paper_dense_gpu(7000 + ci, spec[1], spec[2], spec[3], noise=1e-2)
+            block = spec[2] // 50
+        else:
+            As, bh = synth.paper_sparse(7000 + ci, spec[1], spec[2], spec[3])
+            A = ap.CSRMatrix.from_scipy(As, device="cuda", dtype=torch.float64)
+            b, block = torch.as_tensor(bh, device="cuda"), spec[2] // 50
+        row = {"workload": name, "mu": 0.0, "tol": t}
+        for label, pc in (("svd", 1), ("svd_free", 2)):
+            o = dict(mu=0.0, block=block, tol_ne=t, max_iter=budget, precond=pc)
+            ap.lstsq(A, b, **o)  # warm-up at this shape (rocBLAS kernels, allocator)
+            ms, (x, info) = _timed(torch, lambda: ap.lstsq(A, b, **o))
+            row[label] = {"ms": round(ms, 1), "t_precond_ms": round(info.t_precond_ms, 1),
+                          "builds": info.rebuilds, "t_cur_ms": round(info.t_cur_ms, 1),
+                          "t_lsqr_ms": round(info.t_lsqr_ms, 1), "iters": info.iters, "rank": info.rank,
+                          "eta": info.eta, "status": info.status}
+            log(f"[bench] svd-free study {name} {label}: {ms:.0f} ms (P builds {info.t_precond_ms:.0f} ms / "
+                f"{info.rebuilds}, CUR {info.t_cur_ms:.0f} ms, LSQR {info.t_lsqr_ms:.0f} ms), {info.iters} it, "
+                f"rank {info.rank}, eta {info.eta:.1e}, status {info.status}")
+        out.append(row)
+        del A, b
+        torch.cuda.empty_cache()
+    print(json.dumps({"svdfree_study": out}), flush=True)
+
+
 def schedule_study(ap, synth, torch):
     """Sec. 7.1 variants on the dense kernel workload at half size (FP32 A,
     16 RHS, mu = 1e-3, block 250) and on the sparse workload (rank cap 256):
@@ -380,6 +424,8 @@ def main():
                      help="only the paper's test sets, APLICUR against plain LSQR, one JSON line")
     ap_.add_argument("--schedule-study", action="store_true",
                      help="only the adaptive against single-shot schedules comparison, one JSON line")
+    ap_.add_argument("--svdfree-study", action="store_true",
+                     help="only the SVD-based against SVD-free preconditioner comparison at mu = 0, one JSON line")
     ap_.add_argument("--sketch-study", action="store_true",
                      help="only the sparse sign against Gaussian sketch comparison, one JSON line")
     ap_.add_argument("--full-configs", action="store_true",
@@ -407,6 +453,9 @@ def main():
         return
     if args.sketch_study:
         sketch_study(ap, synth, torch)
+        return
+    if args.svdfree_study:
+        svdfree_study(ap, synth, torch)
         return
     if args.full_configs:
         full = {"adjoint": bench_adjoint(ap, synth, torch, m=100000, n=2000, nrhs=32)}
