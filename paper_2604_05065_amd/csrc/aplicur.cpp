@@ -504,7 +504,17 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
         const long long ns = (m + 63) / 64;
         int* wid = c->arena.alloc<int>(ns);
         std::vector<int> wh;
-        const long long padded = sell_widths(Am->row_ptr, m, wid, wh, s);
+        long long padded = sell_widths(Am->row_ptr, m, wid, wh, s);
+        // one width for all slices when that pads by at most 1/32: the kernel
+        // then computes each slice's offset instead of loading it
+        const int wmax = wh.empty() ? 0 : *std::max_element(wh.begin(), wh.end());
+        const long long upad = ns * 64 * (long long)wmax;
+        int uw = 0;
+        if (wmax > 0 && upad <= Am->nnz + Am->nnz / 32 && upad < (1LL << 31)) {
+          uw = wmax;
+          std::fill(wh.begin(), wh.end(), wmax);
+          padded = upad;
+        }
         if (padded <= Am->nnz + Am->nnz / 4 && padded < (1LL << 31)) {
           std::vector<int> offh(ns);
           long long acc = 0;
@@ -514,6 +524,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
           }
           int* off = c->arena.alloc<int>(ns);
           APL_HIP(hipMemcpyAsync(off, offh.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+          if (uw > 0) APL_HIP(hipMemcpyAsync(wid, wh.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
           int* sci = c->arena.alloc<int>(std::max<long long>(1, padded));
           void* sval = c->arena.alloc<char>(vs * (size_t)std::max<long long>(1, padded));
           if (op.f64)
@@ -526,6 +537,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
           op.sell_ci = sci;
           op.sell_val = sval;
           op.sell_slices = (int)ns;
+          op.sell_uw = uw;
           op.sell_padded = padded;
           sell_layout(ns, n, &op.sell_spw, &op.sell_grid);
         }

@@ -354,13 +354,61 @@ __global__ void __launch_bounds__(kBlock)
 constexpr int kLxT = 1024;
 constexpr int kLxChunk = 12;
 
+template <class V>
+struct Wide16;
+template <>
+struct Wide16<double> {
+  using type = double2;
+};
+template <>
+struct Wide16<float> {
+  using type = float4;
+};
+
+// x (n entries, n sizeof(V) <= kLxMaxBytes) -> xs in LDS in one batch of loads
+// per thread: 16-byte loads when x is 16-byte aligned (ten per thread cover
+// the largest n; they move the copy at about 1.5 times the rate of 8-byte
+// loads), else batches of single-entry loads.  Loads issued before the call
+// stay in flight.
+template <class V>
+__device__ __forceinline__ void x_to_lds(const V* __restrict__ x, long long n, V* xs) {
+  using V16 = typename Wide16<V>::type;
+  constexpr int kW = (int)(16 / sizeof(V));
+  const long long np = n / kW;
+  if ((((unsigned long long)x) & 15ull) == 0 && np > 0) {
+    constexpr int kB = (int)((kLxMaxBytes / 16 + kLxT - 1) / kLxT);
+    const V16* x16 = (const V16*)x;
+    V16* xs16 = (V16*)xs;
+    V16 t[kB];
+#pragma unroll
+    for (int q = 0; q < kB; ++q) t[q] = x16[min((long long)threadIdx.x + (long long)q * kLxT, np - 1)];
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const long long i = (long long)threadIdx.x + (long long)q * kLxT;
+      if (i < np) xs16[i] = t[q];
+    }
+    const long long i = np * kW + threadIdx.x;  // the last n mod kW entries
+    if (i < n) xs[i] = x[i];
+  } else {
+    // unaligned x (a view into a larger tensor): batches of 8 entries
+    for (long long base = threadIdx.x; base < n; base += (long long)kLxT * 8) {
+      V t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = x[min(base + (long long)q * kLxT, n - 1)];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (base + (long long)q * kLxT < n) xs[base + (long long)q * kLxT] = t[q];
+    }
+  }
+}
+
 template <class TA, class V, int MODE>
 __global__ void __launch_bounds__(kLxT)
     k_fwd_csr_lx(const RowBlk* __restrict__ rbk, const int* __restrict__ rp, const int* __restrict__ ci,
                  const TA* __restrict__ val, long long n, const V* tin, V* u_top, V* u_bot, const V* v, V* w, V* y,
                  const GKState* __restrict__ st_in, GKState* __restrict__ st_out, const double* alpha_part,
                  int alpha_count, double* beta_part) {
-  extern __shared__ double lx_raw[];
+  extern __shared__ __align__(16) double lx_raw[];
   V* xs = (V*)lx_raw;
   __shared__ double red[kLxT / kWave];
   const RowBlk ra = rbk[blockIdx.x], rb = rbk[blockIdx.x + 1];
@@ -371,15 +419,6 @@ __global__ void __launch_bounds__(kLxT)
   if (MODE != kFwdMatvec && s.stop) {
     if (MODE == kFwdPlain) store_state(st_out, s);
     return;
-  }
-  // x -> LDS, 12 loads per thread in flight
-  for (long long base = threadIdx.x; base < n; base += (long long)kLxT * 12) {
-    V tmp[12];
-#pragma unroll
-    for (int q = 0; q < 12; ++q) tmp[q] = tin[min(base + (long long)q * kLxT, n - 1)];
-#pragma unroll
-    for (int q = 0; q < 12; ++q)
-      if (base + (long long)q * kLxT < n) xs[base + (long long)q * kLxT] = tmp[q];
   }
   // bottom slice [j0, j1) of the n rows
   const long long per = (n + gridDim.x - 1) / gridDim.x;
@@ -395,6 +434,7 @@ __global__ void __launch_bounds__(kLxT)
       by = y[jb];
     }
   }
+  x_to_lds(tin, n, xs);
   const int r0 = ra.r0, rows = rb.r0 - ra.r0;
   double sq = 0.0;
   bool go = true;
@@ -468,16 +508,19 @@ __global__ void __launch_bounds__(kLxT)
 // [64 s, 64 s + 64) padded to the slice's longest row (width w_s), column-major
 // inside the slice: entry q of row 64 s + l at off_s + 64 q + l (padding: column
 // 0, value 0).  One wave per slice, one lane per row: the value and column
-// loads are fully coalesced and need only (off_s, w_s), so a workgroup's loads
-// form two dependent stages (slice bounds, then values / columns) next to the
-// copy of x into LDS.  Sums run in entry order (the CSR row order).
+// loads are fully coalesced and need only (off_s, w_s).  When every slice has
+// one width uw (uw > 0) the offsets are 64 uw s, and a workgroup's first
+// slice loads go out before the copy of x into LDS (one batch of 16-byte
+// loads): a single dependent global round trip before the sums.  Otherwise
+// (uw = 0) the slice bounds are loaded first.  Sums run in entry order (the
+// CSR row order).
 template <class TA, class V, int MODE>
 __global__ void __launch_bounds__(kLxT)
-    k_fwd_sell_lx(const int* __restrict__ soff, const int* __restrict__ swid, int nslices, int spw,
+    k_fwd_sell_lx(const int* __restrict__ soff, const int* __restrict__ swid, int nslices, int spw, int uw,
                   const int* __restrict__ sci, const TA* __restrict__ sval, long long m, long long n, const V* tin,
                   V* u_top, V* u_bot, const V* v, V* w, V* y, const GKState* __restrict__ st_in,
                   GKState* __restrict__ st_out, const double* alpha_part, int alpha_count, double* beta_part) {
-  extern __shared__ double lx_raw[];
+  extern __shared__ __align__(16) double lx_raw[];
   V* xs = (V*)lx_raw;
   __shared__ double red[kLxT / kWave];
   GKState s = *st_in;
@@ -492,8 +535,13 @@ __global__ void __launch_bounds__(kLxT)
   const bool has_a = sa < sl1;
   int off = 0, wid = 0;
   if (has_a) {
-    off = soff[sa];
-    wid = swid[sa];
+    if (uw > 0) {
+      off = sa * kWave * uw;
+      wid = uw;
+    } else {
+      off = soff[sa];
+      wid = swid[sa];
+    }
   }
   const long long ra = (long long)sa * kWave + lane;
   V uo = 0;
@@ -502,13 +550,6 @@ __global__ void __launch_bounds__(kLxT)
     if (MODE == kFwdPlain) store_state(st_out, s);
     return;
   }
-  // x -> LDS with 12 loads per thread in flight; the first batch is issued
-  // before the first slice's values and columns, whose loads then overlap the
-  // rest of the copy.
-  long long xb = threadIdx.x;
-  V tmp[12];
-#pragma unroll
-  for (int q = 0; q < 12; ++q) tmp[q] = tin[min(xb + (long long)q * kLxT, n - 1)];
   // bottom slice [j0, j1) of the n rows
   const long long per = (n + gridDim.x - 1) / gridDim.x;
   const long long j0 = (long long)blockIdx.x * per, j1 = min(n, j0 + per);
@@ -533,15 +574,8 @@ __global__ void __launch_bounds__(kLxT)
     cidx[q] = in ? sci[e] : 0;
     vv[q] = in ? sval[e] : (TA)0;
   }
-  for (;;) {
-#pragma unroll
-    for (int q = 0; q < 12; ++q)
-      if (xb + (long long)q * kLxT < n) xs[xb + (long long)q * kLxT] = tmp[q];
-    xb += (long long)kLxT * 12;
-    if (xb >= n) break;
-#pragma unroll
-    for (int q = 0; q < 12; ++q) tmp[q] = tin[min(xb + (long long)q * kLxT, n - 1)];
-  }
+  // x -> LDS while the slice and bottom loads above are in flight
+  x_to_lds(tin, n, xs);
   publish(share, red);
   __syncthreads();
   V ts, cu, cy = 0, cw = 0;
@@ -563,8 +597,13 @@ __global__ void __launch_bounds__(kLxT)
   for (int sl = sa; sl < sl1; sl += kLxT / kWave) {
     const long long r = (long long)sl * kWave + lane;
     if (sl != sa) {
-      off = soff[sl];
-      wid = swid[sl];
+      if (uw > 0) {
+        off = sl * kWave * uw;
+        wid = uw;
+      } else {
+        off = soff[sl];
+        wid = swid[sl];
+      }
       uo = r < m ? u_top[r] : (V)0;
 #pragma unroll
       for (int q = 0; q < kLxChunk; ++q) {
@@ -1226,11 +1265,11 @@ static void launch_fwd(const OpDesc& A, const V* tin, GKVecs<V> vec, GKState* st
     const unsigned shm = (unsigned)(A.n * sizeof(V));
     if (A.f64)
       launch_kx(k_fwd_sell_lx<double, V, MODE>, dim3(lg), dim3(kLxT), shm, s, e0, e1, A.sell_off, A.sell_w,
-                A.sell_slices, A.sell_spw, A.sell_ci, (const double*)A.sell_val, A.m, A.n, tin, vec.u_top, vec.u_bot,
+                A.sell_slices, A.sell_spw, A.sell_uw, A.sell_ci, (const double*)A.sell_val, A.m, A.n, tin, vec.u_top, vec.u_bot,
                 (const V*)vec.v, vec.w, vec.y, sin, sout, (const double*)wk.alpha_part, ac, wk.beta_part);
     else
       launch_kx(k_fwd_sell_lx<float, V, MODE>, dim3(lg), dim3(kLxT), shm, s, e0, e1, A.sell_off, A.sell_w,
-                A.sell_slices, A.sell_spw, A.sell_ci, (const float*)A.sell_val, A.m, A.n, tin, vec.u_top, vec.u_bot,
+                A.sell_slices, A.sell_spw, A.sell_uw, A.sell_ci, (const float*)A.sell_val, A.m, A.n, tin, vec.u_top, vec.u_bot,
                 (const V*)vec.v, vec.w, vec.y, sin, sout, (const double*)wk.alpha_part, ac, wk.beta_part);
     wk.beta_count = lg;
     return;

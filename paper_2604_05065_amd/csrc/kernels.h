@@ -55,6 +55,7 @@ struct OpDesc {
   const int *sell_off, *sell_w, *sell_ci;
   const void* sell_val;
   int sell_slices, sell_spw, sell_grid;  // slices, slices per workgroup, workgroups
+  int sell_uw;                           // > 0: every slice has this width (offsets 64 uw s)
   long long sell_padded;                 // entries including padding
   const int *row_ptr, *col_idx;  // CSR of A
   const void* val;

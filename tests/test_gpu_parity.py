@@ -412,6 +412,13 @@ def test_lds_resident_products(lib, shape, dtype):
     with lib.Context(_gpu_csr(A, dtype), mu=1e-4, precond=False) as ctx:
         y = ctx.matvec(_t(x)).cpu().numpy()
         z = ctx.matvec(_t(u), trans=True).cpu().numpy()
+        # x not 16-byte aligned (a view one entry into a buffer): the copy of x
+        # into LDS takes its single-entry path; the sums are the same
+        xb = torch.zeros(n + 1, dtype=torch.float64, device=DEV)
+        xb[1:] = _t(x)
+        assert xb[1:].data_ptr() % 16 == 8
+        y_un = ctx.matvec(xb[1:]).cpu().numpy()
+    np.testing.assert_array_equal(y_un, y)
     yr, zr = A @ x, A.T @ u
     absA = abs(A)
     assert np.abs(y - yr).max() <= 1e-13 * (absA @ np.abs(x)).max()
