@@ -1,9 +1,10 @@
-"""The dense kernel and adjoint workloads at their full sizes, in the launch
-configuration the benchmark times, checked through properties that hold at
-any size (the oracle cannot run them): every column's normal-equation
-residual recomputed in FP64 (torch, row chunks of A widened exactly), and for
-the adjoint the Gram equation (A^T A + mu I) Z = G that defines Z and
-dL/dB = A Z."""
+"""The workloads at their full sizes, in the launch configuration the
+benchmark times.  The small dense one (2000 x 200) is compared with the
+oracle's trace and the dense-QR minimiser; the dense kernel and adjoint ones,
+which the oracle cannot run, are checked through properties that hold at any
+size: every column's normal-equation residual recomputed in FP64 (torch, row
+chunks of A widened exactly), and for the adjoint the Gram equation
+(A^T A + mu I) Z = G that defines Z and dL/dB = A Z."""
 import pytest
 import torch
 
@@ -69,3 +70,30 @@ def test_adjoint_workload_full_size(lib):
     assert float((dB - AZ).norm() / AZ.norm()) <= 1e-12
     del A, B, X, Z, dB, AZ
     torch.cuda.empty_cache()
+
+
+def test_small_dense_workload_full_size(lib):
+    """Dense FP64 2000 x 200, sigma_i = 10^(-6 i / 200), mu = 0, tol 1e-10: at
+    full size the oracle runs too, so the CUR sequence is compared with its
+    trace and the solution with the dense-QR minimiser."""
+    import numpy as np
+
+    from oracle.aplicur import Options, Trace, aplicur, ne_residual
+    from oracle.dense import solve_dense_qr
+
+    w = synth.workload(1, 1.0)
+    tr = Trace()
+    aplicur(w.A, w.B, 0.0, Options(block=w.block, tol_ne=w.tol), tr)
+    At = torch.as_tensor(w.A, device="cuda")
+    with lib.Context(At, mu=0.0, block=w.block, tol_ne=w.tol) as ctx:
+        x, info = ctx.solve(torch.as_tensor(w.B, device="cuda"))
+        ranks = ctx.query(8).tolist()
+    x = x.cpu().numpy()
+    eta = ne_residual(w.A, w.B, x, 0.0)
+    assert info.status == 0 and eta <= 1.05 * w.tol
+    k = min(len(ranks), len(tr.ranks))
+    assert abs(len(ranks) - len(tr.ranks)) <= 1 and ranks[:k] == tr.ranks[:k]
+    xr = solve_dense_qr(w.A, w.B, 0.0)
+    smin = np.linalg.svd(w.A, compute_uv=False)[-1]
+    bound = eta * np.linalg.norm(w.A.T @ w.B) / smin ** 2
+    assert np.linalg.norm(x - xr) <= 2 * bound + 1e-9 * np.linalg.norm(xr)
