@@ -425,6 +425,38 @@ def test_lds_resident_products(lib, shape, dtype):
     assert np.abs(z - zr).max() <= 1e-13 * (absA.T @ np.abs(u)).max()
 
 
+def _uniform_csr(m, n, per_row, seed):
+    """per_row distinct columns in every row (a random start, then steps of n / per_row)."""
+    r = np.random.default_rng(seed)
+    ci = (r.integers(0, n, (m, 1)) + (n // per_row) * np.arange(per_row)[None, :]) % n
+    ci = np.sort(ci, axis=1).reshape(-1)
+    rp = np.arange(0, m * per_row + 1, per_row)
+    return sp.csr_matrix((r.standard_normal(m * per_row), ci, rp), shape=(m, n))
+
+
+@pytest.mark.parametrize("n", [20352, 20353])
+def test_lds_products_at_the_size_limit(lib, n):
+    """x in LDS holds at most 159 KB: n = 20352 FP64 entries is the largest n
+    the LDS-resident product takes (the whole copy in one batch), n + 1 takes
+    the other path; both give A x within the FP64 bound."""
+    A = _uniform_csr(150016, n, 10, n)
+    x = np.random.default_rng(1).standard_normal(n)
+    with lib.Context(_gpu_csr(A), mu=1e-4, precond=False) as ctx:
+        y = ctx.matvec(_t(x)).cpu().numpy()
+    assert np.abs(y - A @ x).max() <= 1e-13 * (abs(A) @ np.abs(x)).max()
+
+
+def test_fp32_phases_at_the_lds_size_limit(lib):
+    """FP32 phases keep x in LDS up to n = 40704 FP32 entries (159 KB); the
+    solve reaches the FP64 tolerance through that largest copy."""
+    n = 40704
+    A = _uniform_csr(160000, n, 10, 5)
+    b = np.random.default_rng(6).standard_normal(A.shape[0])
+    x, info = lib.lstsq(_gpu_csr(A), _t(b), mu=1e-1, precond=False, precision=1, tol_ne=1e-8)
+    assert info.status == 0
+    assert ne_residual(A, b, x.cpu().numpy(), 1e-1) <= 1.05e-8
+
+
 def test_full_size_fp32_phases(lib, workload2):
     """FP32 LSQR phases (FP32 values, A x from the FP32 SELL copy) with FP64
     refinement reach the FP64 tolerance at the benchmark size."""
