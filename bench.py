@@ -491,6 +491,22 @@ def main():
             us_a_cold = ctx.time_product(xv, trans=False, reps=20, flush=flush)
             us_at_cold = ctx.time_product(xv, trans=True, reps=20, flush=flush)
             del flush
+    # measured device-copy rate (1 GiB each way, torch's copy on its current
+    # stream, event-timed there): a measured peak beside the published 8 TB/s
+    copy_gbs = float("nan")
+    if not args.products_only:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del src, dst
+        log(f"[bench] device copy, 1 GiB each way: {copy_gbs:.0f} GB/s (read + write)")
     bytes_a = spmv_bytes(m, n, nnz)
     bytes_at = spmv_bytes(n, m, nnz) - n * 8  # A^T kernel stores its output without reading it
     gbs_a = bytes_a / (us_a * 1e-6) / 1e9
@@ -586,7 +602,9 @@ def main():
         "matvec": {"A_us": round(us_a, 3), "A_GBs": round(gbs_a, 1), "AT_us": round(us_at, 3),
                    "AT_GBs": round(gbs_at, 1), "AT_bytes": int(bytes_at),
                    "A_us_cold": round(us_a_cold, 3), "A_GBs_cold": round(bytes_a / us_a_cold / 1e3, 1),
-                   "AT_us_cold": round(us_at_cold, 3), "AT_GBs_cold": round(bytes_at / us_at_cold / 1e3, 1)},
+                   "AT_us_cold": round(us_at_cold, 3), "AT_GBs_cold": round(bytes_at / us_at_cold / 1e3, 1),
+                   "copy_GBs": round(copy_gbs, 1), "A_frac_of_copy": round(gbs_a / copy_gbs, 4),
+                   "AT_frac_of_copy": round(gbs_at / copy_gbs, 4)},
     }
     print(json.dumps(out), flush=True)
 
