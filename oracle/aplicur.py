@@ -57,6 +57,7 @@ class Options:
     sketch: str = "sparse"     # "sparse" (sparse sign, the default) or "gaussian"
     schedule: int = 0          # 0 fully adaptive; 1 rank-adaptive single shot; 2 fixed-rank single shot
     precond: str = "svd"       # "svd" (Alg. 2) or "svdfree" (Alg. 8, mu = 0 only)
+    svdfree_floor: bool = True  # Alg. 8 target max(rho, eps_cur); False: rho as printed
 
 
 @dataclass
@@ -71,6 +72,31 @@ class Trace:
     J: list = field(default_factory=list)
     sigma_hat: list = field(default_factory=list)
     iters: int = 0
+
+
+class RebuildRule:
+    """The re-preconditioning test of Alg. 3, Part 3 (Sec. 5.3.2).
+
+    A new preconditioner is built when the step is final (rho <= eps_cur, or
+    the rank can grow no further), or when the CUR error has dropped enough
+    since the last build: d_cur / (rho - eps_cur) >= nu_prec, where d_cur is
+    rho - eps_cur at the last build (+inf before the first, so the first
+    step always builds).  ``adaptive=False`` (the single-shot schedules of
+    Sec. 7.1) builds at the final step only.
+    """
+
+    def __init__(self, eps_cur, nu_prec, adaptive=True):
+        self.eps_cur = eps_cur
+        self.nu_prec = nu_prec
+        self.adaptive = adaptive
+        self.d_cur = math.inf
+
+    def __call__(self, rho, final):
+        gap = rho - self.eps_cur
+        rebuild = final or (self.adaptive and self.d_cur / gap >= self.nu_prec)
+        if rebuild:
+            self.d_cur = gap
+        return rebuild
 
 
 def default_eps_cur(mu):
@@ -149,7 +175,7 @@ def aplicur(A, b, mu, opts=None, trace=None):
     J = np.zeros(0, np.int64)
     C = W = R = None
     Q_R = T_R = None
-    d_cur = math.inf
+    rule = RebuildRule(eps_cur, opts.nu_prec, adaptive=opts.schedule == 0)
     x = np.zeros(n)
     atb = float(np.linalg.norm(A.T @ b))
     bnorm = float(np.linalg.norm(b))
@@ -187,13 +213,12 @@ def aplicur(A, b, mu, opts=None, trace=None):
             trace.rhos.append(rho)
             trace.I, trace.J = I.copy(), J.copy()
         # Part 3: re-precondition and run LSQR
-        gap = rho - eps_cur
-        rebuild = final or (opts.schedule == 0 and d_cur / gap >= opts.nu_prec)
+        rebuild = rule(rho, final)
         if trace is not None:
             trace.rebuild.append(rebuild)
         if rebuild:
             if svdfree:
-                P = SvdFreePreconditioner(C, W, Q_R, T_R, rho, eps_cur)
+                P = SvdFreePreconditioner(C, W, Q_R, T_R, rho, eps_cur, floor=opts.svdfree_floor)
                 pinv_t = P.inv_t
             else:
                 P = Preconditioner(C, W, Q_R, T_R, delta)
@@ -205,7 +230,6 @@ def aplicur(A, b, mu, opts=None, trace=None):
                                      atb_norm=atb, pnorm=P.pnorm, baug_norm=bnorm,
                                      max_iter=opts.max_iter - total)
             total += it
-            d_cur = gap
             eta = ne_residual(A, b, x, mu)
             if trace is not None:
                 trace.phase_iters.append(it)

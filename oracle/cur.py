@@ -172,16 +172,19 @@ class SvdFreePreconditioner:
 
     with target = max(rho, eps_cur): rho is the CUR error estimate (Alg. 8
     takes the estimate of Sec. 5.3.1 as the target level).  Readings: the
-    target is not taken below the requested CUR accuracy eps_cur -- a CUR
-    more accurate than that (rho at rounding level at full rank, or rho = 0
-    for an exact CUR) would flatten the captured spectrum to a level that
-    rounding dominates, or make P~^{-1} singular; the dynamic rule's
-    smallest resolved singular value is taken as the target; ||P~|| =
-    max(1, ||M|| / target) is bounded above by the Frobenius norm of
-    M = T_C W^{-1} T_R^T.
+    target is not taken below the requested CUR accuracy eps_cur, so the
+    final build (reached when rho <= eps_cur) uses eps_cur.  The literal
+    level flattens the captured spectrum to a rho far below the requested
+    accuracy, and ||P~|| = ||M|| / rho then makes the certified stop much
+    stricter than the normal-equation residual needs (more than three times
+    the iterations on the sparse sharp kappa = 1e15 set; ``floor=False``
+    keeps it for that comparison); rho = 0, an exact CUR, would make
+    P~^{-1} singular.  The dynamic rule's smallest resolved singular value
+    is taken as the target; ||P~|| = max(1, ||M|| / target) is bounded
+    above by the Frobenius norm of M = T_C W^{-1} T_R^T.
     """
 
-    def __init__(self, C, W, Q_R, T_R, rho, eps_cur):
+    def __init__(self, C, W, Q_R, T_R, rho, eps_cur, floor=True):
         CtC = _dense(C.T @ C)
         T_C = np.linalg.cholesky(CtC).T
         sg = np.where(np.diag(T_R) < 0, -1.0, 1.0)
@@ -192,7 +195,9 @@ class SvdFreePreconditioner:
         WTi = sla.solve_triangular(T_C, W.T, trans=1, lower=False).T  # W T_C^{-1}
         self.Minv = sla.solve_triangular(T_R, WTi, trans=1, lower=False)
         M = T_C @ np.linalg.solve(W, T_R.T)
-        self.target = max(float(rho), float(eps_cur))
+        # floor=False: the literal Alg. 8 level (rho itself), kept for the
+        # test that compares the two readings
+        self.target = max(float(rho), float(eps_cur)) if floor else float(rho)
         self.sigma_l = self.target
         self.pnorm = max(1.0, float(np.linalg.norm(M, "fro")) / self.target)
         self.T_R = T_R
