@@ -123,14 +123,23 @@ typedef struct aplicur_opts {
   int32_t xi;        /* non-zeros per column of the sparse sign sketch, 1..8 (default 8,
                         Sec. 5.1; 0 selects the default); the sketch uses min(xi, s)     */
   int32_t sketch;    /* 0: sparse sign embedding (default); 1: Gaussian embedding, i.i.d.
-                        N(0, 1/s) entries from the counter-based stream 3, Y = S A by
-                        rocBLAS GEMM for dense A (FP32 A: FP32 S and accumulation,
-                        widened), or a column-wise kernel over the CSR of A^T         */
+                        N(0, 1/s) entries from the counter-based stream 3 (Sec. 5.1), Y = S A by
+                        the library's MFMA products: FP64 GEMM for FP64 A; for FP32 A, S
+                        rounded to FP32, FP32 MFMA sums of 16 terms accumulated in FP64; a
+                        column-wise kernel over the CSR of A^T for CSR A; 2: as 1, but for
+                        dense FP32 A both S and A rounded to BF16 (BF16 MFMA, 32-term FP32
+                        sums accumulated in FP64; about 2^-8 relative to |S| |A| per entry) */
   int32_t schedule;  /* 0: fully adaptive (default, Alg. 3: phases interleaved with the rank
                         growth and the re-preconditioning test); 1: rank-adaptive single
                         shot (the rank grows until rho <= eps_cur or the cap, then one P and
                         one final phase); 2: fixed-rank single shot (the rank grows to the
                         cap max_rank, then one P and one final phase).  Sec. 7.1       */
+  double jacobi_tol; /* accuracy of the SVD of the l x l core M (Alg. 2 Part 2), by one-sided
+                        Jacobi: sweeps stop once the Frobenius norm of the off-diagonal of
+                        the damped core's Gram matrix, scaled to unit diagonal, is at most
+                        this; the preconditioned singular values then lie within
+                        sqrt(1 +- jacobi_tol) of the exact-SVD level.  <= 0: 1e-2
+                        (default); tiny values run the sweeps to convergence (at most 40) */
 } aplicur_opts;
 
 /* ------------------------------------------------------------------ info  */
@@ -251,6 +260,16 @@ int aplicur_matvec(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, 
 int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx, int32_t k, double* Y, int64_t ldy,
                    int32_t prec, void* stream);
 
+/* y = P^{-1} z (trans = 0) or y = P^{-T} z (trans = 1) with the context's
+ * last preconditioner (Alg. 2 Part 2: P^{-1} z = z + V ((sigma/Lambda - 1) .*
+ * (V^T z)), V = Q_R V_M, symmetric; or the SVD-free P~^{-1} of Alg. 8, whose
+ * transpose differs), through the same kernels as the LSQR iteration (the
+ * implicit R^T K form for CSR A, the explicit V for dense A).  z, y: n
+ * doubles (device), distinct.  Enqueued on `stream`.  For tests and
+ * diagnostics.  Errors: E_INVALID (null argument, no preconditioner built
+ * yet: run aplicur_solve first), E_HIP.                                     */
+int aplicur_precond_apply(aplicur_ctx* ctx, int32_t trans, const double* z, double* y, void* stream);
+
 /* Measures the product kernels the LSQR iteration uses: `reps` rounds of
  * y = A x - y followed by s = A^T y (s: library scratch), alternating as in
  * the iteration, with a HIP event pair attached to every dispatch of the A
@@ -266,6 +285,20 @@ int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx
  * Errors: E_INVALID, E_HIP.                                                */
 int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* flush,
                          int64_t flush_bytes, void* stream, double* us_per_launch);
+
+/* Measures the blocked product kernel of the several-right-hand-side path
+ * (dense A): `reps` calls of Y = A X (trans = 0) or A^T X (trans = 1) for k
+ * columns (1 <= k <= 64) in the arithmetic prec of aplicur_matmat, with a
+ * HIP event pair attached to the dispatch of the product kernel itself (the
+ * MFMA row-streaming kernel that reads A once; the packing and partial-sum
+ * kernels around it are not timed).  X, Y: column-major FP64 (device),
+ * ldx >= (trans ? m : n), ldy >= (trans ? n : m).  flush: as in
+ * aplicur_time_product (cold caches), or NULL.  One untimed call first makes
+ * any copy of A the product needs.  *us_per_launch (host) receives the mean
+ * kernel duration in microseconds.  Errors: E_INVALID, E_HIP.             */
+int aplicur_time_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx, int32_t k, double* Y,
+                        int64_t ldy, int32_t prec, int32_t reps, void* flush, int64_t flush_bytes, void* stream,
+                        double* us_per_launch);
 
 /* Read internal state back to host memory (tests and diagnostics).
  * what: 1 sketch Y (s x n row-major doubles), 2 sketch rows (m x xi int32;

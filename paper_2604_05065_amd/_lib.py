@@ -27,7 +27,7 @@ class Opts(C.Structure):
                 ("max_rank", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
                 ("max_outer", C.c_int32), ("workers", C.c_int32), ("tune", C.c_int32),
                 ("graphs", C.c_int32), ("columns", C.c_int32), ("xi", C.c_int32),
-                ("sketch", C.c_int32), ("schedule", C.c_int32)]
+                ("sketch", C.c_int32), ("schedule", C.c_int32), ("jacobi_tol", C.c_double)]
 
 
 class Info(C.Structure):
@@ -42,7 +42,7 @@ class Info(C.Structure):
 
 
 EXPORTS = ["aplicur_opts_default", "aplicur_workspace_bytes", "aplicur_sketch", "aplicur_solve", "aplicur_solve_batched",
-           "aplicur_solve_backward", "aplicur_matvec", "aplicur_matmat", "aplicur_time_product", "aplicur_ctx_query", "aplicur_ctx_destroy",
+           "aplicur_solve_backward", "aplicur_matvec", "aplicur_matmat", "aplicur_time_product", "aplicur_time_matmat", "aplicur_precond_apply", "aplicur_ctx_query", "aplicur_ctx_destroy",
            "aplicur_last_error", "aplicur_version"]
 
 _lib = None
@@ -75,6 +75,10 @@ def load():
     lib.aplicur_matvec.restype = C.c_int
     lib.aplicur_matmat.argtypes = [vp, i32, dp, i64, i32, dp, i64, i32, vp]
     lib.aplicur_matmat.restype = C.c_int
+    lib.aplicur_time_matmat.argtypes = [vp, i32, dp, i64, i32, dp, i64, i32, i32, vp, i64, vp, C.POINTER(C.c_double)]
+    lib.aplicur_time_matmat.restype = C.c_int
+    lib.aplicur_precond_apply.argtypes = [vp, i32, dp, dp, vp]
+    lib.aplicur_precond_apply.restype = C.c_int
     lib.aplicur_time_product.argtypes = [vp, i32, dp, dp, i32, vp, i64, vp, C.POINTER(C.c_double)]
     lib.aplicur_time_product.restype = C.c_int
     lib.aplicur_ctx_query.argtypes = [vp, i32, vp, C.c_size_t]

@@ -5,6 +5,7 @@ memory and the current stream.  Inputs may be FP32 or FP64 for A; right-hand
 sides and solutions are FP64.
 """
 import ctypes as C
+import math
 
 import numpy as np
 import torch
@@ -74,7 +75,8 @@ def _device(A):
 
 def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.0, eps_lsqr=1e-10,
               tol_ne=1e-8, max_iter=100000, max_rank=0, precond=True, precision=0, max_outer=0,
-              r_probes=10, workers=0, tune=0, graphs=0, columns=0, xi=8, sketch=0, schedule=0):
+              r_probes=10, workers=0, tune=0, graphs=0, columns=0, xi=8, sketch=0, schedule=0,
+              jacobi_tol=0.0):
     lib = L.load()
     o = L.Opts()
     lib.aplicur_opts_default(C.byref(o))
@@ -88,8 +90,9 @@ def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.
     o.workers, o.tune, o.graphs = int(workers), int(bool(tune)), int(bool(graphs))
     o.columns = int(bool(columns))
     o.xi = int(xi)
-    o.sketch = {"sparse": 0, "gaussian": 1}[sketch] if isinstance(sketch, str) else int(sketch)
+    o.sketch = {"sparse": 0, "gaussian": 1, "gaussian_bf16": 2}[sketch] if isinstance(sketch, str) else int(sketch)
     o.schedule = int(schedule)
+    o.jacobi_tol = float(jacobi_tol)
     return o
 
 
@@ -189,6 +192,28 @@ class Context:
                                         rows_out, int(prec), _stream()))
         Y = Yt.t()
         return Y.reshape(-1) if one else Y
+
+    def time_matmat(self, X, trans=False, prec=0, reps=20, flush=None):
+        """Mean duration (us) of the blocked product kernel for the columns
+        of X (rows x k, k <= 64); flush as in time_product."""
+        rows_in, rows_out = (self.m, self.n) if trans else (self.n, self.m)
+        Xt, k, _ = _cols(X, rows_in, "X")
+        Yt = torch.empty((k, rows_out), dtype=torch.float64, device=Xt.device)
+        us = C.c_double()
+        fptr, fbytes = (flush.data_ptr(), flush.numel() * flush.element_size()) if flush is not None else (None, 0)
+        L.check(self.lib.aplicur_time_matmat(self.ptr, int(bool(trans)), Xt.data_ptr(), rows_in, k, Yt.data_ptr(),
+                                             rows_out, int(prec), int(reps), fptr, int(fbytes), _stream(),
+                                             C.byref(us)))
+        return us.value
+
+    def precond_apply(self, z, trans=False):
+        """P^{-1} z (trans: P^{-T} z) with the last preconditioner built."""
+        z = z.to(torch.float64).contiguous()
+        if z.numel() != self.n:
+            raise ValueError("z must have n entries")
+        y = torch.empty(self.n, dtype=torch.float64, device=z.device)
+        L.check(self.lib.aplicur_precond_apply(self.ptr, int(bool(trans)), z.data_ptr(), y.data_ptr(), _stream()))
+        return y
 
     def time_product(self, x, trans=False, reps=100, flush=None):
         """Mean duration (us) of one launch of the A (or A^T) product kernel,

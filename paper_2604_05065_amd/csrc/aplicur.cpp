@@ -12,9 +12,7 @@
 //   if re-preconditioning: M = T_C U T_R^T, one-sided Jacobi SVD of M,
 //     V = Q_R V_M, P^{-1} z = z + V ((sigma^/Lam - 1) .* V^T z), then an LSQR
 //     phase per right-hand side warm-started from x.
-// Plain GEMM/TRSM steps use rocBLAS; everything else is in the HIP kernels.
-#include <rocblas/rocblas.h>
-
+// The GEMM / TRSM steps run on the library's own FP64 MFMA kernels (kern_blas.hip).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -31,12 +29,14 @@
 #include <vector>
 
 #include "../../include/aplicur.h"
+#include "blas.h"
 #include "blk.h"
 #include "factor.h"
 
 namespace aplicur {
 
 static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 // Host calls that may synchronise with the legacy stream behind the scenes
 // (allocation and release, library handles, library calls, which may load or
@@ -45,14 +45,6 @@ static thread_local std::string g_last_error;
 // is an error.
 static std::shared_mutex g_capture_mu;
 using SyncGuard = std::shared_lock<std::shared_mutex>;
-
-#define APL_BLAS(x)                                                                        \
-  do {                                                                                     \
-    SyncGuard blas_guard_(g_capture_mu);                                                   \
-    rocblas_status s_ = (x);                                                               \
-    if (s_ != rocblas_status_success)                                                      \
-      throw ::aplicur::Error(-3, std::string(#x) + ": rocblas status " + std::to_string((int)s_)); \
-  } while (0)
 
 using Clock = std::chrono::steady_clock;
 static double ms_since(Clock::time_point t0) {
@@ -126,6 +118,7 @@ struct Arena {
 };
 
 constexpr int kLuppNB = 32;  // pivots per panel of the blocked LU pivot search
+constexpr double kJacobiTol = 1e-2;  // default stopping level of the core SVD (see build_precond)
 
 // Buffers of the blocked path (several right-hand sides of a dense A),
 // allocated on first use for kp columns.
@@ -163,11 +156,13 @@ struct Ctx {
   aplicur_mat A{};
   aplicur_opts o{};
   OpDesc op{};
-  rocblas_handle blas = nullptr;
+  hipStream_t stream = nullptr;  // the stream of the current call (set_stream)
+  double* nrm_tmp = nullptr;     // dnrm2 partials
   Arena arena;
   long long m = 0, n = 0;
   int s = 0, xi = 0, r = 0, L = 0, Lpad = 0, bmax = 0;
   double delta = 0.0, eps_cur = 0.0;
+  double jacobi_tol = 0.0;  // stopping level of the core SVD's Jacobi sweeps
   // sketch / probes
   uint16_t* S_rows = nullptr;
   uint8_t* S_neg = nullptr;
@@ -187,7 +182,7 @@ struct Ctx {
          *M2 = nullptr, *M2t = nullptr;
   int *rr_ptr = nullptr, *rr_idx = nullptr, *rt_ptr = nullptr, *rt_idx = nullptr, *rscratch = nullptr;
   double *rr_val = nullptr, *rt_val = nullptr;
-  unsigned long long* offmax = nullptr;
+  double* jac_part = nullptr;  // per-pair partial sums of the Jacobi sweeps
   double* splitk = nullptr;
   size_t splitk_count = 0;
   PrecDesc prec{};
@@ -225,7 +220,6 @@ struct Ctx {
     {
       SyncGuard g(g_capture_mu);
       if (gexec) (void)hipGraphExecDestroy(gexec);
-      if (blas) rocblas_destroy_handle(blas);
       if (st_host) (void)hipHostFree(st_host);
       if (blk) {
         if (blk->st_up) (void)hipHostFree(blk->st_up);
@@ -243,51 +237,25 @@ static int group_for(double avg) {
   return g;
 }
 
-static void set_stream(Ctx& c, hipStream_t s) { APL_BLAS(rocblas_set_stream(c.blas, s)); }
+static void set_stream(Ctx& c, hipStream_t s) { c.stream = s; }
 
-// Split-K scratch for tall-skinny C = A^T B products (inner dimension m or n
-// of A, only a few columns): rocBLAS tiles the output only, so these run on
-// a handful of workgroups; here the inner dimension is cut into chunks run
-// as one strided-batched GEMM and the chunk results are summed in order.
-static double* splitk_ws(Ctx& c, size_t count);
+// Scratch of the k-chunked products (dgemm sums the chunk products in
+// order): one fixed block per context, reserved at set-up, so that every
+// product is cut the same way in every call and in both memory modes.
+constexpr size_t kGemmWorkMax = size_t(4) << 20;  // doubles (32 MiB)
 
-static void gemm(Ctx& c, rocblas_operation ta, rocblas_operation tb, long long m, long long n, long long k,
-                 double alpha, const double* A, long long lda, const double* B, long long ldb, double beta,
-                 double* Cm, long long ldc) {
+// C = alpha op(A) op(B) + beta C on the library's FP64 MFMA GEMM, on the
+// context's current stream.
+static void gemm(Ctx& c, Op ta, Op tb, long long m, long long n, long long k, double alpha, const double* A,
+                 long long lda, const double* B, long long ldb, double beta, double* Cm, long long ldc) {
   if (m <= 0 || n <= 0) return;
-  const long long mn = m * n;
-  if (ta == rocblas_operation_transpose && tb == rocblas_operation_none && k >= 16384 && mn <= (1LL << 21)) {
-    long long P = std::min<long long>(64, k / 4096);
-    P = std::min<long long>(P, std::max<long long>(2, (8LL << 20) / mn));
-    if (P >= 2) {
-      const long long kc = (k + P - 1) / P;
-      const long long full = k / kc;                 // chunks of exactly kc rows
-      const long long rem = k - full * kc;
-      const long long nparts = full + (rem > 0 ? 1 : 0);
-      double* W = splitk_ws(c, (size_t)(nparts * mn));
-      const double one = 1.0, zero = 0.0;
-      APL_BLAS(rocblas_dgemm_strided_batched(c.blas, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)kc, &one, A,
-                                             (rocblas_int)lda, kc, B, (rocblas_int)ldb, kc, &zero, W, (rocblas_int)m, mn,
-                                             (rocblas_int)full));
-      if (rem > 0)
-        APL_BLAS(rocblas_dgemm(c.blas, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)rem, &one, A + full * kc,
-                               (rocblas_int)lda, B + full * kc, (rocblas_int)ldb, &zero, W + full * mn, (rocblas_int)m));
-      hipStream_t s;
-      APL_BLAS(rocblas_get_stream(c.blas, &s));
-      splitk_reduce(W, (int)nparts, m, n, alpha, beta, Cm, ldc, s);
-      return;
-    }
-  }
-  APL_BLAS(rocblas_dgemm(c.blas, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)k, &alpha, A,
-                         (rocblas_int)lda, B, (rocblas_int)ldb, &beta, Cm, (rocblas_int)ldc));
+  dgemm(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, Cm, ldc, c.splitk, c.splitk_count, c.stream);
 }
 
-static double* splitk_ws(Ctx& c, size_t count) {
-  if (count > c.splitk_count) {
-    c.splitk = c.arena.alloc<double>(count);
-    c.splitk_count = count;
-  }
-  return c.splitk;
+// B <- alpha op(T)^{-1} B or alpha B op(T)^{-1}.
+static void trsm(Ctx& c, Side side, Uplo uplo, Op trans, Diag diag, long long m, long long n, double alpha,
+                 const double* T, long long ldt, double* B, long long ldb) {
+  dtrsm(side, uplo, trans, diag, m, n, alpha, T, ldt, B, ldb, c.splitk, c.splitk_count, c.stream);
 }
 
 static int read_int(const int* dev, hipStream_t s) {
@@ -298,7 +266,7 @@ static int read_int(const int* dev, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ set-up
-static void validate(const aplicur_mat* A, const aplicur_opts* o) {
+void validate(const aplicur_mat* A, const aplicur_opts* o) {
   APL_REQUIRE(A && o, "null matrix or options");
   APL_REQUIRE(A->m >= 1 && A->n >= 1, "m and n must be >= 1");
   APL_REQUIRE(A->m < (1LL << 31) && A->n < (1LL << 31), "m and n must be < 2^31");
@@ -324,8 +292,10 @@ static void validate(const aplicur_mat* A, const aplicur_opts* o) {
   }
   APL_REQUIRE(o->max_iter >= 0, "max_iter must be >= 0");
   APL_REQUIRE(o->xi >= 0 && o->xi <= 8, "xi must be in [1, 8] (0: the default 8)");
-  APL_REQUIRE(o->sketch == 0 || o->sketch == 1, "sketch must be 0 (sparse sign) or 1 (Gaussian)");
+  APL_REQUIRE(o->sketch >= 0 && o->sketch <= 2,
+              "sketch must be 0 (sparse sign), 1 (Gaussian) or 2 (Gaussian, BF16 products for FP32 A)");
   APL_REQUIRE(o->schedule >= 0 && o->schedule <= 2, "schedule must be 0, 1 or 2");
+  APL_REQUIRE(std::isfinite(o->jacobi_tol) && o->jacobi_tol < 1.0, "jacobi_tol must be finite and < 1");
 }
 
 // ------------------------------------------------------------------ product tiles
@@ -438,9 +408,18 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
     c->n = Am->n;
     c->delta = std::sqrt(o->mu);
     c->eps_cur = o->eps_cur > 0 ? o->eps_cur : (o->mu > 0 ? 30.0 * std::sqrt(o->mu) : 3e-7);
-    APL_BLAS(rocblas_create_handle(&c->blas));
-    APL_BLAS(rocblas_set_pointer_mode(c->blas, rocblas_pointer_mode_host));
+    c->jacobi_tol = o->jacobi_tol > 0 ? o->jacobi_tol : kJacobiTol;
     set_stream(*c, s);
+    c->nrm_tmp = c->arena.alloc<double>(kNrm2Parts + 1);
+    {
+      // k-chunk scratch of the set-up products: the tall products have at
+      // most 64 chunks of (rank cap) x (block) or s x r outputs
+      const long long L = std::min<long long>(std::min(Am->m, Am->n), o->max_rank > 0 ? o->max_rank : 4096);
+      const long long b = std::max<long long>(1, std::min<long long>(o->block, 280));
+      const size_t want = (size_t)64 * (size_t)(L * b + 2 * b * b + 310 * 64);
+      c->splitk_count = std::min(kGemmWorkMax, want);
+      c->splitk = c->arena.alloc<double>(c->splitk_count);
+    }
     const long long m = c->m, n = c->n;
     OpDesc& op = c->op;
     op.csr = (Am->format == APLICUR_CSR);
@@ -637,13 +616,11 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
       c->EW = c->arena.alloc<double>((size_t)S * r);
       c->rho_dev = c->arena.alloc<double>(4);
       launch_gen_probes(o->seed, n, r, c->W, s);
-      if (o->sketch == 1) {
+      if (o->sketch >= 1) {
         // Gaussian S (s x m, column-major) in transient memory, Y = S A
         const size_t sm = (size_t)S * m;
-        const bool f32 = !op.csr && !op.f64;
-        const size_t extra = f32 ? (sizeof(float) * sm + sizeof(float) * (size_t)S * n + 512) : 0;
         bool owned = false;
-        char* tb = (char*)c->arena.transient(sizeof(double) * sm + extra, owned);
+        char* tb = (char*)c->arena.transient(sizeof(double) * sm, owned);
         double* Sg = (double*)tb;
         launch_gen_gauss_sketch(o->seed, S, m, Sg, s);
         if (op.csr) {
@@ -653,18 +630,11 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
             launch_sketch_gauss_csr<float>(op.t_ptr, op.t_idx, (const float*)op.t_val, n, S, Sg, c->Y, s);
         } else if (op.f64) {
           // Y^T (n x s, column-major) = A_cm (n x m) S^T: A row-major is column-major n x m with ld
-          const double one = 1.0, zero = 0.0;
-          APL_BLAS(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, (int)n, S, (int)m,
-                                 &one, (const double*)op.val, (int)op.ld, Sg, S, &zero, c->Y, (int)n));
+          gemm(*c, Op::N, Op::T, n, S, m, 1.0, (const double*)op.val, op.ld, Sg, S, 0.0, c->Y, n);
         } else {
-          // FP32 product (FP32 S and A, FP32 accumulation), widened to FP64
-          float* S32 = (float*)(tb + (sizeof(double) * sm + 255) / 256 * 256);
-          float* Y32 = (float*)((char*)S32 + (sizeof(float) * sm + 255) / 256 * 256);
-          to_f32(Sg, S, S32, S, m, S, s);
-          const float one = 1.0f, zero = 0.0f;
-          APL_BLAS(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, (int)n, S, (int)m,
-                                 &one, (const float*)op.val, (int)op.ld, S32, S, &zero, Y32, (int)n));
-          widen(Y32, c->Y, (long long)S * n, s);
+          // FP32 A: the product with FP32 (sketch 1) or BF16 (sketch 2) inputs on
+          // MFMA, chunk sums accumulated in FP64
+          sketch_gemm_f32((const float*)op.val, m, n, op.ld, Sg, S, c->Y, o->sketch == 2, s);
         }
         APL_HIP(hipStreamSynchronize(s));
         if (owned) {
@@ -728,7 +698,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
       c->Kr = c->arena.alloc<double>((size_t)L * L);
       c->d = c->arena.alloc<double>(L);
       c->pinfo = c->arena.alloc<double>(4);
-      c->offmax = c->arena.alloc<unsigned long long>(2);
+      c->jac_part = c->arena.alloc<double>((size_t)jacobi_part_words(Lp));
       c->pa_c = c->arena.alloc<double>(L);
       c->prec.c = c->pa_c;
       c->prec.d = c->d;
@@ -802,7 +772,6 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
 // elimination in another summation order.  Pivot rows are never read again, so
 // the update runs over all rows.
 static void lupp_blocked(Ctx& c, double* X, int r, int cols, long long ld, int k, int* piv, hipStream_t s) {
-  const double one = 1.0;
   lupp_begin(X, r, k, c.fw, s);
   for (int q0 = 0; q0 < k; q0 += kLuppNB) {
     const int qe = std::min(q0 + kLuppNB, k);
@@ -811,9 +780,8 @@ static void lupp_blocked(Ctx& c, double* X, int r, int cols, long long ld, int k
     const int nb = qe - q0, w = cols - q0;
     double* G = c.fw.lupp_g;
     lupp_gather(X, r, ld, piv, q0, nb, w, G, s);
-    APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                           rocblas_diagonal_unit, nb, cols - qe, &one, G, nb, G + (size_t)nb * nb, nb));
-    gemm(c, rocblas_operation_none, rocblas_operation_none, r, cols - qe, nb, -1.0, X + (long long)q0 * ld, ld,
+    trsm(c, Side::Left, Uplo::Lower, Op::N, Diag::Unit, nb, cols - qe, 1.0, G, nb, G + (size_t)nb * nb, nb);
+    gemm(c, Op::N, Op::N, r, cols - qe, nb, -1.0, X + (long long)q0 * ld, ld,
          G + (size_t)nb * nb, nb, 1.0, X + (long long)qe * ld, ld);
     lupp_cand(X, r, ld, qe, c.fw, s);
   }
@@ -825,17 +793,15 @@ static void lupp_blocked(Ctx& c, double* X, int r, int cols, long long ld, int k
 // Blocked: diagonal blocks in LDS (one workgroup), TRSM and SYRK for the rest.
 static void chol_upper(Ctx& c, double* G, long long ld, int k, hipStream_t s) {
   APL_HIP(hipMemsetAsync(c.status_dev, 0, sizeof(int), s));
-  const double one = 1.0, mone = -1.0;
   for (int j0 = 0; j0 < k; j0 += kFNB) {
     const int nb = std::min(kFNB, k - j0), r = k - j0 - nb;
     double* D = G + j0 + (long long)j0 * ld;
     potrf_diag(D, ld, nb, j0, c.status_dev, s);
     if (r > 0) {
       double* G12 = G + j0 + (long long)(j0 + nb) * ld;
-      APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
-                             rocblas_diagonal_non_unit, nb, r, &one, D, (rocblas_int)ld, G12, (rocblas_int)ld));
-      APL_BLAS(rocblas_dsyrk(c.blas, rocblas_fill_upper, rocblas_operation_transpose, r, nb, &mone, G12,
-                             (rocblas_int)ld, &one, G + (j0 + nb) + (long long)(j0 + nb) * ld, (rocblas_int)ld));
+      trsm(c, Side::Left, Uplo::Upper, Op::T, Diag::NonUnit, nb, r, 1.0, D, ld, G12, ld);
+      // trailing update G22 -= G12^T G12 (both triangles; the lower one is cleared at the end)
+      gemm(c, Op::T, Op::N, r, r, nb, -1.0, G12, ld, G12, ld, 1.0, G + (j0 + nb) + (long long)(j0 + nb) * ld, ld);
     }
   }
   zero_lower(G, ld, k, s);
@@ -847,26 +813,21 @@ static void chol_upper(Ctx& c, double* G, long long ld, int k, hipStream_t s) {
 // S is singular.
 static void lu_inverse(Ctx& c, double* S, long long ld, int k, double* Sinv, long long ldi, hipStream_t s) {
   APL_HIP(hipMemsetAsync(c.status_dev, 0, sizeof(int), s));
-  const double one = 1.0;
   for (int j0 = 0; j0 < k; j0 += kFNB) {
     const int w = std::min(kFNB, k - j0), r = k - j0 - w;
     lu_panel(S, ld, k, j0, w, c.lu_piv, c.status_dev, s);
     laswp(S, ld, k, j0, j0 + w, c.lu_piv, j0, w, s);
     if (r > 0) {
       double* A12 = S + j0 + (long long)(j0 + w) * ld;
-      APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                             rocblas_diagonal_unit, w, r, &one, S + j0 + (long long)j0 * ld, (rocblas_int)ld, A12,
-                             (rocblas_int)ld));
-      gemm(c, rocblas_operation_none, rocblas_operation_none, r, r, w, -1.0, S + (j0 + w) + (long long)j0 * ld, ld,
+      trsm(c, Side::Left, Uplo::Lower, Op::N, Diag::Unit, w, r, 1.0, S + j0 + (long long)j0 * ld, ld, A12, ld);
+      gemm(c, Op::N, Op::N, r, r, w, -1.0, S + (j0 + w) + (long long)j0 * ld, ld,
            A12, ld, 1.0, S + (j0 + w) + (long long)(j0 + w) * ld, ld);
     }
   }
   set_identity(Sinv, ldi, k, s);
   laswp(Sinv, ldi, k, 0, 0, c.lu_piv, 0, k, s);
-  APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                         rocblas_diagonal_unit, k, k, &one, S, (rocblas_int)ld, Sinv, (rocblas_int)ldi));
-  APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                         rocblas_diagonal_non_unit, k, k, &one, S, (rocblas_int)ld, Sinv, (rocblas_int)ldi));
+  trsm(c, Side::Left, Uplo::Lower, Op::N, Diag::Unit, k, k, 1.0, S, ld, Sinv, ldi);
+  trsm(c, Side::Left, Uplo::Upper, Op::N, Diag::NonUnit, k, k, 1.0, S, ld, Sinv, ldi);
 }
 
 // ------------------------------------------------------------------ Cholesky QR
@@ -877,15 +838,14 @@ static void chol_qr2(Ctx& c, double* X, long long n, int k, long long ldx, doubl
   double* G = c.small;                             // k x k
   double* R1 = c.small + (size_t)c.bmax * c.bmax;  // k x k
   double* Racc = c.small + 2 * (size_t)c.bmax * c.bmax;
-  const double one = 1.0;
   int passes = 2;
   for (int pass = 0; pass < passes; ++pass) {
-    gemm(c, rocblas_operation_transpose, rocblas_operation_none, k, k, n, 1.0, X, ldx, X, ldx, 0.0, G, k);
+    gemm(c, Op::T, Op::N, k, k, n, 1.0, X, ldx, X, ldx, 0.0, G, k);
     chol_upper(c, G, k, k, s);
     if (read_int(c.status_dev, s) != 0) {
       APL_REQUIRE(pass == 0, "Cholesky QR failed (block numerically rank deficient)");
       // shifted Cholesky QR: G + shift I, then one extra unshifted pass
-      gemm(c, rocblas_operation_transpose, rocblas_operation_none, k, k, n, 1.0, X, ldx, X, ldx, 0.0, G, k);
+      gemm(c, Op::T, Op::N, k, k, n, 1.0, X, ldx, X, ldx, 0.0, G, k);
       std::vector<double> hg((size_t)k * k);
       APL_HIP(hipMemcpyAsync(hg.data(), G, sizeof(double) * k * k, hipMemcpyDeviceToHost, s));
       APL_HIP(hipStreamSynchronize(s));
@@ -898,12 +858,11 @@ static void chol_qr2(Ctx& c, double* X, long long n, int k, long long ldx, doubl
       APL_REQUIRE(read_int(c.status_dev, s) == 0, "shifted Cholesky QR failed");
       passes = 3;
     }
-    APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                           rocblas_diagonal_non_unit, (rocblas_int)n, k, &one, G, k, X, (rocblas_int)ldx));
+    trsm(c, Side::Right, Uplo::Upper, Op::N, Diag::NonUnit, n, k, 1.0, G, k, X, ldx);
     if (pass == 0) {
       copy_block(G, k, Racc, k, k, k, 1.0, s);
     } else {
-      gemm(c, rocblas_operation_none, rocblas_operation_none, k, k, k, 1.0, G, k, Racc, k, 0.0, R1, k);
+      gemm(c, Op::N, Op::N, k, k, k, 1.0, G, k, Racc, k, 0.0, R1, k);
       copy_block(R1, k, Racc, k, k, k, 1.0, s);
     }
   }
@@ -942,8 +901,8 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
   copy_block(Cn, m, c.Ecol, m, (int)m, k1, 1.0, s);
   if (l > 0) {
     gather_sub_rows(c.Rt, n, c.Jp, k1, l, c.RJ, k1, s);  // RJ = R(:,J+)^T, k1 x l
-    gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, k1, l, 1.0, c.U, L, c.RJ, k1, 0.0, c.F, L);
-    gemm(c, rocblas_operation_none, rocblas_operation_none, m, k1, l, -1.0, c.C, m, c.F, L, 1.0, c.Ecol, m);
+    gemm(c, Op::N, Op::T, l, k1, l, 1.0, c.U, L, c.RJ, k1, 0.0, c.F, L);
+    gemm(c, Op::N, Op::N, m, k1, l, -1.0, c.C, m, c.F, L, 1.0, c.Ecol, m);
     zero_rows(c.Ecol, m, c.I_dev, l, k1, s);
   }
   // (iv) row pivots of E_col
@@ -970,18 +929,18 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
   gather_sub_rows(Cn, m, c.Ip, k2, k2, c.Sb, k2, s);  // A(I+, J+)
   if (l > 0) {
     gather_sub_rows(c.C, m, c.Ip, k2, l, c.B21, k2, s);  // A(I+, J_old), k2 x l
-    gemm(c, rocblas_operation_none, rocblas_operation_none, k2, l, l, 1.0, c.B21, k2, c.U, L, 0.0, c.Gm, k2);
+    gemm(c, Op::N, Op::N, k2, l, l, 1.0, c.B21, k2, c.U, L, 0.0, c.Gm, k2);
     // S -= G B12, B12 = RJ(0:k2, :)^T
-    gemm(c, rocblas_operation_none, rocblas_operation_transpose, k2, k2, l, -1.0, c.Gm, k2, c.RJ, k1, 1.0, c.Sb, k2);
+    gemm(c, Op::N, Op::T, k2, k2, l, -1.0, c.Gm, k2, c.RJ, k1, 1.0, c.Sb, k2);
   }
   lu_inverse(c, c.Sb, k2, k2, c.Sinv, k2, s);
   if (read_int(c.status_dev, s) != 0) throw Error(APLICUR_E_BREAKDOWN, "singular CUR core block");
   if (l == 0) {
     copy_block(c.Sinv, k2, c.U, L, k2, k2, 1.0, s);
   } else {
-    gemm(c, rocblas_operation_none, rocblas_operation_none, k2, l, k2, 1.0, c.Sinv, k2, c.Gm, k2, 0.0, c.H, k2);
-    gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, k2, 1.0, c.F, L, c.H, k2, 1.0, c.U, L);
-    gemm(c, rocblas_operation_none, rocblas_operation_none, l, k2, k2, -1.0, c.F, L, c.Sinv, k2, 0.0,
+    gemm(c, Op::N, Op::N, k2, l, k2, 1.0, c.Sinv, k2, c.Gm, k2, 0.0, c.H, k2);
+    gemm(c, Op::N, Op::N, l, l, k2, 1.0, c.F, L, c.H, k2, 1.0, c.U, L);
+    gemm(c, Op::N, Op::N, l, k2, k2, -1.0, c.F, L, c.Sinv, k2, 0.0,
          c.U + (size_t)l * L, L);
     copy_block(c.H, k2, c.U + l, L, k2, l, -1.0, s);
     copy_block(c.Sinv, k2, c.U + l + (size_t)l * L, L, k2, k2, 1.0, s);
@@ -989,21 +948,21 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
   const int ln = l + k2;
   // (vi) E_row = Y - (Y(:,J) U) R   (E as n x s column-major = E_row^T)
   gather_y_cols(c.Y, n, S, c.J_dev, ln, c.YJ, S, s);
-  gemm(c, rocblas_operation_none, rocblas_operation_none, S, ln, ln, 1.0, c.YJ, S, c.U, L, 0.0, c.Z, S);
+  gemm(c, Op::N, Op::N, S, ln, ln, 1.0, c.YJ, S, c.U, L, 0.0, c.Z, S);
   APL_HIP(hipMemcpyAsync(c.E, c.Y, sizeof(double) * (size_t)S * n, hipMemcpyDeviceToDevice, s));
-  gemm(c, rocblas_operation_none, rocblas_operation_transpose, n, S, ln, -1.0, c.Rt, n, c.Z, S, 1.0, c.E, n);
+  gemm(c, Op::N, Op::T, n, S, ln, -1.0, c.Rt, n, c.Z, S, 1.0, c.E, n);
   // (vii) rho = 10 sqrt(2/pi) max_i ||E_row w_i||
-  gemm(c, rocblas_operation_transpose, rocblas_operation_none, S, c.r, n, 1.0, c.E, n, c.W, n, 0.0, c.EW, S);
+  gemm(c, Op::T, Op::N, S, c.r, n, 1.0, c.E, n, c.W, n, 0.0, c.EW, S);
   rho_from_ew(c.EW, S, c.r, c.rho_dev, s);
   // (viii) augmentQR (Alg. 9) with the new columns A(I+,:)^T
   double* Qn = c.Q + (size_t)l * n;
   copy_block(Rn, n, Qn, n, (int)n, k2, 1.0, s);
   if (l > 0) {
     double* P1 = c.TR + (size_t)l * L;  // T_R(0:l, l:ln)
-    gemm(c, rocblas_operation_transpose, rocblas_operation_none, l, k2, n, 1.0, c.Q, n, Rn, n, 0.0, P1, L);
-    gemm(c, rocblas_operation_none, rocblas_operation_none, n, k2, l, -1.0, c.Q, n, P1, L, 1.0, Qn, n);
-    gemm(c, rocblas_operation_transpose, rocblas_operation_none, l, k2, n, 1.0, c.Q, n, Qn, n, 0.0, c.P2, l);
-    gemm(c, rocblas_operation_none, rocblas_operation_none, n, k2, l, -1.0, c.Q, n, c.P2, l, 1.0, Qn, n);
+    gemm(c, Op::T, Op::N, l, k2, n, 1.0, c.Q, n, Rn, n, 0.0, P1, L);
+    gemm(c, Op::N, Op::N, n, k2, l, -1.0, c.Q, n, P1, L, 1.0, Qn, n);
+    gemm(c, Op::T, Op::N, l, k2, n, 1.0, c.Q, n, Qn, n, 0.0, c.P2, l);
+    gemm(c, Op::N, Op::N, n, k2, l, -1.0, c.Q, n, c.P2, l, 1.0, Qn, n);
     // P1 += P2
     add_block(c.P2, l, P1, L, l, k2, s);
   }
@@ -1013,22 +972,20 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
     double* T12 = c.TC + (size_t)l * L;
     double* T22 = c.TC + l + (size_t)l * L;
     if (l > 0) {
-      gemm(c, rocblas_operation_transpose, rocblas_operation_none, l, k2, m, 1.0, c.C, m, Cn, m, 0.0, T12, L);
-      const double one = 1.0;
-      APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
-                             rocblas_diagonal_non_unit, l, k2, &one, c.TC, L, T12, L));
+      gemm(c, Op::T, Op::N, l, k2, m, 1.0, c.C, m, Cn, m, 0.0, T12, L);
+      trsm(c, Side::Left, Uplo::Upper, Op::T, Diag::NonUnit, l, k2, 1.0, c.TC, L, T12, L);
     }
     double* G22 = c.small;
-    gemm(c, rocblas_operation_transpose, rocblas_operation_none, k2, k2, m, 1.0, Cn, m, Cn, m, 0.0, G22, k2);
+    gemm(c, Op::T, Op::N, k2, k2, m, 1.0, Cn, m, Cn, m, 0.0, G22, k2);
     if (l > 0)
-      gemm(c, rocblas_operation_transpose, rocblas_operation_none, k2, k2, l, -1.0, T12, L, T12, L, 1.0, G22, k2);
+      gemm(c, Op::T, Op::N, k2, k2, l, -1.0, T12, L, T12, L, 1.0, G22, k2);
     chol_upper(c, G22, k2, k2, s);
     if (read_int(c.status_dev, s) != 0) {
       if (l == 0) throw Error(APLICUR_E_BREAKDOWN, "Cholesky of C^T C failed");
       // The new columns are numerically dependent on C: undo the step (U11
       // back to its old value; the new slots of I, J, C, R, Q_R, T_R lie
       // beyond the rank and are ignored) and end the rank growth.
-      gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, k2, -1.0, c.F, L, c.H, k2, 1.0, c.U, L);
+      gemm(c, Op::N, Op::N, l, l, k2, -1.0, c.F, L, c.H, k2, 1.0, c.U, L);
       c.J.resize(l);
       c.I.resize(l);
       APL_HIP(hipStreamSynchronize(s));
@@ -1052,14 +1009,13 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
 // ------------------------------------------------------------------ preconditioner (Alg. 2 Part 2)
 // The one-sided Jacobi SVD of the core M stops when the off-diagonal of the
 // Gram matrix of the damped core [M; delta I] (entries scaled to unit
-// diagonal) has Frobenius norm at most kJacobiTol.  With V the accumulated
+// diagonal) has Frobenius norm at most jacobi_tol (option; kJacobiTol by default).  With V the accumulated
 // rotations (orthogonal to rounding) and Lambda_i^2 = ||M v_i||^2 + delta^2,
 // the core part of the preconditioned Gram, diag(sigma_hat / Lambda) V^T (M^T
 // M + delta^2 I) V diag(sigma_hat / Lambda), is sigma_hat^2 (I + E) with that
-// off-diagonal E, so its singular values lie within sqrt(1 +- kJacobiTol) of
+// off-diagonal E, so its singular values lie within sqrt(1 +- jacobi_tol) of
 // the exact-SVD value sigma_hat.  Pairs below kJacobiSkip are not rotated
 // (their entries add at most l kJacobiSkip to the norm).
-constexpr double kJacobiTol = 1e-2;
 constexpr double kJacobiSkip = 1e-9;
 // Largest diagonal ratio of T_R for which the one-product form M2 is used.
 constexpr double kM2MaxDiagRatio = 1e3;
@@ -1092,17 +1048,14 @@ static void build_precond_svdfree(Ctx& c, hipStream_t s) {
   const int l = c.rank, L = c.L;
   const double rho = c.rho_hist.empty() ? 0.0 : c.rho_hist.back();
   const double target = std::max(rho, c.eps_cur);
-  const double one = 1.0;
-  gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Kr, l);
-  gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Kc, l);
+  gemm(c, Op::N, Op::T, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Kr, l);
+  gemm(c, Op::N, Op::N, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Kc, l);
   double mfro = 0.0;
-  APL_BLAS(rocblas_dnrm2(c.blas, l * l, c.Kc, 1, &mfro));
+  mfro = dnrm2((long long)l * l, c.Kc, c.nrm_tmp, s);
   // H = target T_R^{-T} W T_C^{-1} - I with W = A(I,J) = C(I,:), column-major in Mx (ld l)
   gather_sub_rows(c.C, c.m, c.I_dev, l, l, c.Mx, l, s);
-  APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                         rocblas_diagonal_non_unit, l, l, &target, c.TC, L, c.Mx, l));
-  APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
-                         rocblas_diagonal_non_unit, l, l, &one, c.TR, L, c.Mx, l));
+  trsm(c, Side::Right, Uplo::Upper, Op::N, Diag::NonUnit, l, l, target, c.TC, L, c.Mx, l);
+  trsm(c, Side::Left, Uplo::Upper, Op::T, Diag::NonUnit, l, l, 1.0, c.TR, L, c.Mx, l);
   add_diag(c.Mx, l, l, -1.0, s);
   // V = Q_R, row-major n x l
   transpose_rect<double>(c.Q, l, c.n, c.n, c.Vhat, l, s);
@@ -1135,18 +1088,16 @@ static void build_precond(Ctx& c, hipStream_t s) {
   const int lp = ((l + jw2 - 1) / jw2) * jw2;
   // M = T_C U T_R^T  (l x l) into Mx (ld L, lp columns, padding zero)
   fill(c.Mx, (long long)L * lp, 0.0, s);
-  gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Kr, l);
-  gemm(c, rocblas_operation_none, rocblas_operation_none, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Mx, L);
+  gemm(c, Op::N, Op::T, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Kr, l);
+  gemm(c, Op::N, Op::N, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Mx, L);
   set_identity(c.Vm, lp, lp, s);
   c.sweep_hist.push_back(
-      jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.offmax, c.delta * c.delta, kJacobiTol, kJacobiSkip, 40, s));
+      jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.jac_part, c.delta * c.delta, c.jacobi_tol, kJacobiSkip, 40, s));
   precond_scalars(c.sigma, l, c.delta, c.d, c.pinfo, s);
   if (c.prec.implicit) {
     // K = T_R^{-1} V_M (column-major, ld l: the row-major K^T) and K row-major
     copy_block(c.Vm, lp, c.Kc, l, l, l, 1.0, s);
-    const double one = 1.0;
-    APL_BLAS(rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                           rocblas_diagonal_non_unit, l, l, &one, c.TR, L, c.Kc, l));
+    trsm(c, Side::Left, Uplo::Upper, Op::N, Diag::NonUnit, l, l, 1.0, c.TR, L, c.Kc, l);
     // M2 = K diag(d) K^T replaces the two K products when T_R is well
     // conditioned (its rounding error grows with cond(T_R)^2, the two-product
     // form's with cond(T_R)); the diagonal ratio of T_R is the indicator.
@@ -1161,7 +1112,7 @@ static void build_precond(Ctx& c, hipStream_t s) {
     }
     if (dmin > 0.0 && dmax / dmin <= kM2MaxDiagRatio) {
       scale_cols(c.Kc, l, l, l, c.d, c.Kr, s);
-      gemm(c, rocblas_operation_none, rocblas_operation_transpose, l, l, l, 1.0, c.Kr, l, c.Kc, l, 0.0, c.M2, l);
+      gemm(c, Op::N, Op::T, l, l, l, 1.0, c.Kr, l, c.Kc, l, 0.0, c.M2, l);
       c.prec.M2 = c.M2;
     } else {
       transpose_square(c.Kc, l, c.Kr, l, s);
@@ -1170,7 +1121,7 @@ static void build_precond(Ctx& c, hipStream_t s) {
     build_r_csr(c, s);
   } else {
     // V = Q_R V_M stored row-major n x l  (= column-major l x n: V^T = V_M^T Q_R^T)
-    gemm(c, rocblas_operation_transpose, rocblas_operation_transpose, l, c.n, l, 1.0, c.Vm, lp, c.Q, c.n, 0.0,
+    gemm(c, Op::T, Op::T, l, c.n, l, 1.0, c.Vm, lp, c.Q, c.n, 0.0,
          c.Vhat, l);
     c.prec.ldv = l;
   }
@@ -1670,7 +1621,7 @@ static BlkPrec blk_prec(Ctx& c, hipStream_t s) {
     // V^T (l x n row-major) is V = Q_R V_M column-major
     const int jw2 = 2 * jacobi_block_width();
     const int lp = ((l + jw2 - 1) / jw2) * jw2;
-    gemm(c, rocblas_operation_none, rocblas_operation_none, c.n, l, l, 1.0, c.Q, c.n, c.Vm, lp, 0.0, b.Vt, b.ldvt);
+    gemm(c, Op::N, Op::N, c.n, l, l, 1.0, c.Q, c.n, c.Vm, lp, 0.0, b.Vt, b.ldvt);
     b.vt_gen = c.prec_gen;
   }
   BlkPrec P{};
@@ -1966,8 +1917,9 @@ static int solve_blocked(Ctx& c, const double* B, long long ldb, int nrhs, doubl
 // Y = A X (trans 0) or A^T X (trans 1) for k columns (column-major), in
 // groups of up to 64 columns through the blocked products (dense A).
 // prec 1 / 2: the FP32 / BF16 products of the low-precision phases.
+// e0 / e1 (optional, k <= kBlkMaxCols): events on the product kernel's dispatch.
 static void blk_apply(Ctx& c, int trans, const double* X, long long ldx, int k, double* Y, long long ldy,
-                      hipStream_t s, int prec = 0) {
+                      hipStream_t s, int prec = 0, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   for (int g0 = 0; g0 < k; g0 += kBlkMaxCols) {
     const int kg = std::min(kBlkMaxCols, k - g0);
     ensure_blk(c, blk_kp(kg), s);
@@ -1975,11 +1927,11 @@ static void blk_apply(Ctx& c, int trans, const double* X, long long ldx, int k, 
     void* part = trans ? b.wk.pn : b.wk.pm;
     if (prec == 0) {
       blk_matmat(b.op, trans != 0, X + (size_t)g0 * ldx, ldx, b.kp, kg, Y + (size_t)g0 * ldy, ldy, 0,
-                 trans ? b.tm : b.tn, part, s);
+                 trans ? b.tm : b.tn, part, s, e0, e1);
     } else {
       float* in = trans ? b.vec32.u_top : b.vec32.t;
       blk_matmat(prec == 1 ? b.op32 : b.op16, trans != 0, X + (size_t)g0 * ldx, ldx, b.kp, kg,
-                 Y + (size_t)g0 * ldy, ldy, prec, in, part, s);
+                 Y + (size_t)g0 * ldy, ldy, prec, in, part, s, e0, e1);
     }
   }
 }
@@ -2066,10 +2018,12 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
     // R = B - A X (m x k), then the rank-2k gradient
     if (blocked) ensure_blk(c, blk_kp(std::min(nrhs, kBlkMaxCols)), s);  // no allocation while work lives
     bool owned = false;
-    double* work = (double*)c.arena.transient(sizeof(double) * (size_t)c.m * nrhs * 2, owned);
+    // dense A: [R, -AZ] (m x 2k) and [Z, X] (n x 2k) for one rank-2k product
+    const size_t extra = c.op.csr ? 0 : (size_t)c.n * nrhs * 2;
+    double* work = (double*)c.arena.transient(sizeof(double) * ((size_t)c.m * nrhs * 2 + extra), owned);
     try {
-      double* AX = work;
-      double* R = work + (size_t)c.m * nrhs;
+      double* R = work;                         // m x k, then -AZ in the next k columns
+      double* AX = work + (size_t)c.m * nrhs;
       if (blocked) {
         blk_apply(c, 0, X, ldx, nrhs, AX, c.m, s);
       } else {
@@ -2082,19 +2036,16 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
       if (c.op.csr) {
         grad_csr(c.op.row_ptr, c.op.col_idx, c.m, nrhs, R, c.m, Z, ldz, dB, lddb, X, ldx, dA, s);
       } else {
-        if (c.A.format == APLICUR_DENSE_COL) {
-          // column-major dA (m x n) = R Z^T - (AZ) X^T
-          gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.m, c.n, nrhs, 1.0, R, c.m, Z, ldz, 0.0, dA,
-               ldda);
-          gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.m, c.n, nrhs, -1.0, dB, lddb, X, ldx, 1.0,
-               dA, ldda);
-        } else {
-          // row-major dA (m x n) is the column-major n x m matrix dA^T = Z R^T - X (AZ)^T
-          gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.n, c.m, nrhs, 1.0, Z, ldz, R, c.m, 0.0, dA,
-               ldda);
-          gemm(c, rocblas_operation_none, rocblas_operation_transpose, c.n, c.m, nrhs, -1.0, X, ldx, dB, lddb, 1.0,
-               dA, ldda);
-        }
+        copy_block(dB, lddb, AX, c.m, (int)c.m, nrhs, -1.0, s);  // AX <- -AZ
+        double* ZX = work + (size_t)c.m * nrhs * 2;
+        copy_block(Z, ldz, ZX, c.n, (int)c.n, nrhs, 1.0, s);
+        copy_block(X, ldx, ZX + (size_t)c.n * nrhs, c.n, (int)c.n, nrhs, 1.0, s);
+        if (c.A.format == APLICUR_DENSE_COL)
+          // column-major dA (m x n) = R Z^T - (AZ) X^T = [R, -AZ] [Z, X]^T
+          gemm(c, Op::N, Op::T, c.m, c.n, 2 * nrhs, 1.0, R, c.m, ZX, c.n, 0.0, dA, ldda);
+        else
+          // row-major dA is the column-major n x m matrix dA^T = [Z, X] [R, -AZ]^T
+          gemm(c, Op::N, Op::T, c.n, c.m, 2 * nrhs, 1.0, ZX, c.n, R, c.m, 0.0, dA, ldda);
       }
       APL_HIP(hipGetLastError());
       APL_HIP(hipStreamSynchronize(s));
@@ -2133,7 +2084,8 @@ static size_t workspace_for(const aplicur_mat* A, const aplicur_opts* o, int nrh
   std::unique_ptr<Ctx> c(create(A, o, s));
   if (use_blocked(*c, nrhs)) ensure_blk(*c, blk_kp(std::min(nrhs, kBlkMaxCols)), s);
   APL_HIP(hipStreamSynchronize(s));
-  const size_t adj = Arena::aligned(sizeof(double) * (size_t)c->m * nrhs * 2);
+  // the adjoint's transient block: [R, -AZ] (m x 2k) and, for a dense A, [Z, X] (n x 2k)
+  const size_t adj = Arena::aligned(sizeof(double) * ((size_t)c->m * nrhs * 2 + (c->op.csr ? 0 : (size_t)c->n * nrhs * 2)));
   return std::max(c->arena.peak, c->arena.used + adj);
 }
 
@@ -2352,6 +2304,17 @@ int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx
   });
 }
 
+int aplicur_precond_apply(aplicur_ctx* ctx, int32_t trans, const double* z, double* y, void* stream) {
+  return guarded([&]() {
+    APL_REQUIRE(ctx && ctx->impl && z && y, "null argument");
+    Ctx& c = *ctx->impl;
+    APL_REQUIRE(c.have_prec, "no preconditioner has been built (run aplicur_solve with precond 1 or 2 first)");
+    gk_precond_apply(c.op, c.prec, trans != 0, z, y, (hipStream_t)stream);
+    APL_HIP(hipGetLastError());
+    return APLICUR_OK;
+  });
+}
+
 int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, double* y, int32_t reps, void* flush,
                          int64_t flush_bytes, void* stream, double* us_per_launch) {
   return guarded([&]() {
@@ -2389,6 +2352,42 @@ int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, doubl
   });
 }
 
+int aplicur_time_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx, int32_t k, double* Y,
+                        int64_t ldy, int32_t prec, int32_t reps, void* flush, int64_t flush_bytes, void* stream,
+                        double* us_per_launch) {
+  return guarded([&]() {
+    APL_REQUIRE(ctx && ctx->impl && X && Y && us_per_launch && reps >= 1, "bad argument");
+    Ctx& c = *ctx->impl;
+    APL_REQUIRE(!c.op.csr, "aplicur_time_matmat needs a dense A");
+    APL_REQUIRE(k >= 1 && k <= kBlkMaxCols, "k must be in [1, 64]");
+    APL_REQUIRE(prec >= 0 && prec <= 2, "prec must be 0, 1 or 2");
+    APL_REQUIRE(prec == 0 || c.fp32, "prec 1 needs a context of precision 1 or 2");
+    APL_REQUIRE(prec < 2 || c.bf16, "prec 2 needs a context of precision 2");
+    APL_REQUIRE(ldx >= (trans ? c.m : c.n) && ldy >= (trans ? c.n : c.m), "leading dimensions too small");
+    APL_REQUIRE(!flush || (flush_bytes >= 16 && flush_bytes % 16 == 0), "flush_bytes must be a positive multiple of 16");
+    hipStream_t s = (hipStream_t)stream;
+    set_stream(c, s);
+    blk_apply(c, trans, X, ldx, k, Y, ldy, s, prec);  // copies made on first use, before the timed launches
+    std::vector<hipEvent_t> ev(2 * (size_t)reps);
+    for (auto& e : ev) APL_HIP(hipEventCreate(&e));
+    for (int i = 0; i < reps; ++i) {
+      if (flush) touch_buffer(flush, flush_bytes, s);
+      blk_apply(c, trans, X, ldx, k, Y, ldy, s, prec, ev[2 * i], ev[2 * i + 1]);
+    }
+    APL_HIP(hipEventSynchronize(ev.back()));
+    double tot = 0.0;
+    for (int i = 0; i < reps; ++i) {
+      float ms = 0.f;
+      APL_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      tot += ms;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    APL_HIP(hipGetLastError());
+    *us_per_launch = 1e3 * tot / reps;
+    return APLICUR_OK;
+  });
+}
+
 int64_t aplicur_ctx_query(const aplicur_ctx* ctx, int32_t what, void* host_out, size_t bytes) {
   if (!ctx || !ctx->impl) {
     g_last_error = "null context";
@@ -2408,7 +2407,7 @@ int64_t aplicur_ctx_query(const aplicur_ctx* ctx, int32_t what, void* host_out, 
     switch (what) {
       case 1: dev(c.Y, sizeof(double) * (size_t)c.s * c.n); break;
       case 2: case 3: {
-        if (c.o.sketch == 1) {  // Gaussian sketch: no sparse sign structure
+        if (c.o.sketch >= 1) {  // Gaussian sketch: no sparse sign structure
           buf.clear();
           break;
         }

@@ -19,9 +19,10 @@ namespace aplicur {
 // out[s][r][0..kp) = sum over the s-th chunk of the columns j of M[r][j] In[j][0..kp)
 // (M row-major rows x cols with leading dimension ld, In row-major cols x kp).
 // S chunks of the reduction index; the consumer sums the S planes in order.
+// e0 / e1 (optional): events recording the product kernel's own start and end.
 template <class TA, class TB, class ACC>
 void rows_gemm(const TA* M, long long rows, long long cols, long long ld, const TB* In, int kp, ACC* out, int S,
-               hipStream_t s);
+               hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int gemm_splits(long long rows, long long cols);  // S for a product with this many rows and columns
 
 // At (n x m row-major, leading dimension ldt) = A^T for A m x n row-major.
@@ -41,7 +42,7 @@ struct BlkOp;
 // products (A with BF16 copies).  `part` holds the S product planes, summed
 // in order in the product's type.
 void blk_matmat(const BlkOp& A, bool trans, const double* X, long long ldx, int kp, int k, double* Y, long long ldy,
-                int prec, void* in, void* part, hipStream_t s);
+                int prec, void* in, void* part, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 struct BlkOp {
   const void* A;   // m x n row-major (ld)
@@ -63,7 +64,7 @@ void tile_bf16(const float* src, long long rows, long long cols, long long ld, v
 // out[s][r][0..kp) = the s-th chunk of sum_j T[r][j] In[j][0..kp) for a tiled
 // BF16 T, FP32 In (cols x kp row-major) and FP32 accumulation (S chunks).
 void rows_gemm16(const void* T, long long rows, long long cols, const float* In, int kp, float* out, int S,
-                 hipStream_t s);
+                 hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Explicit P^{-1} z = z + V (d .* (V^T z)) with V (n x ell, ldv) and V^T (ell x n, ldvt), FP64.
 struct BlkPrec {

@@ -85,11 +85,13 @@ int jacobi_block_width();
 // for i < n.  Sweeps end once the Frobenius norm of the off-diagonal of the
 // damped, scaled Gram matrix, e_pq = |g_pq| / sqrt((g_pp + delta2)(g_qq +
 // delta2)), summed as the sweep met each block pair, is at most tol_f; a block
-// pair with every e_pq <= skip is not rotated.  off_dev: two device words of
-// scratch.  Returns the number of sweeps.
+// pair with every e_pq <= skip is not rotated.  sq_part: jacobi_part_words(npad)
+// device doubles of scratch (one partial per pair and round, summed in a
+// fixed order, so the sweep count does not depend on the order in which
+// workgroups finish).  Returns the number of sweeps.
 int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
-               unsigned long long* off_dev, double delta2, double tol_f, double skip, int max_sweeps,
-               hipStream_t s);
+               double* sq_part, double delta2, double tol_f, double skip, int max_sweeps, hipStream_t s);
+long long jacobi_part_words(int npad);
 void precond_scalars(const double* sigma, int l, double delta, double* d, double* info, hipStream_t s);
 void rho_from_ew(const double* EW, int s_rows, int r, double* out, hipStream_t s);
 

@@ -17,6 +17,8 @@
 // partial per workgroup and column, and every workgroup of the consumer sums
 // them in a fixed order, so all workgroups hold bitwise-identical scalars;
 // threads c < kp advance the state of column c.
+#include <hip/hip_ext.h>
+
 #include "blk.h"
 
 #include <cstdint>
@@ -50,15 +52,7 @@ struct Mfma<float> {
 
 constexpr int kGT = 2;                               // 16-row tiles per wave
 constexpr int kGRows = (kBlock / kWave) * kGT * 16;  // rows per workgroup
-#ifdef APL_NT
-#define APL_GLOAD(p) __builtin_nontemporal_load(p)
-#else
-#define APL_GLOAD(p) (*(p))
-#endif
-#ifndef APL_GPL
-#define APL_GPL 8
-#endif
-constexpr int kGPL = APL_GPL;                        // reduction entries per lane per step
+constexpr int kGPL = 8;                              // reduction entries per lane per step
 constexpr int kGStep = 4 * kGPL;                     // reduction entries per step
 
 // One step's operands: this lane's eight M values of each row tile (kept in
@@ -80,13 +74,13 @@ __device__ __forceinline__ void gemm_load(GemmStep<TA, TB, NB>& st, const TA* co
       if constexpr (sizeof(TA) == 4) {
 #pragma unroll
         for (int h = 0; h < kGPL / 4; ++h) {
-          const f32x4 u = APL_GLOAD((const f32x4*)(mrow[t] + jl) + h);
+          const f32x4 u = ((const f32x4*)(mrow[t] + jl))[h];
           st.a[t][4 * h] = u.x; st.a[t][4 * h + 1] = u.y; st.a[t][4 * h + 2] = u.z; st.a[t][4 * h + 3] = u.w;
         }
       } else {
 #pragma unroll
         for (int h = 0; h < kGPL / 2; ++h) {
-          const f64x2 u = APL_GLOAD((const f64x2*)(mrow[t] + jl) + h);
+          const f64x2 u = ((const f64x2*)(mrow[t] + jl))[h];
           st.a[t][2 * h] = u.x; st.a[t][2 * h + 1] = u.y;
         }
       }
@@ -178,39 +172,48 @@ int gemm_splits(long long rows, long long cols) {
   return (int)std::max<long long>(1, std::min<long long>(S, 64));
 }
 
+// Launch; with events, through the dispatch-timed launch (the events take
+// the kernel's own start and end timestamps).
+template <class F, class... Args>
+static void launch_ev(F kern, dim3 g, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kern, g, dim3(kBlock), 0, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kern, g, dim3(kBlock), 0, s, args...);
+}
+
 template <class TA, class TB, class ACC, int NB>
 static void rows_gemm_nb(const TA* M, long long rows, long long cols, long long ld, const TB* In, ACC* out, int S,
-                         hipStream_t s) {
+                         hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const long long per = ceil_div(cols, S);
   const long long kchunk = ((per + kGStep - 1) / kGStep) * kGStep;
   const bool vec = ((uintptr_t)M % 16 == 0) && ((ld * (long long)sizeof(TA)) % 16 == 0);
   const dim3 g(ceil_div(rows, kGRows), S);
   if (vec)
-    hipLaunchKernelGGL((k_rows_gemm<TA, TB, ACC, NB, true>), g, dim3(kBlock), 0, s, M, rows, cols, ld, In, out, kchunk);
+    launch_ev(k_rows_gemm<TA, TB, ACC, NB, true>, g, s, e0, e1, M, rows, cols, ld, In, out, kchunk);
   else
-    hipLaunchKernelGGL((k_rows_gemm<TA, TB, ACC, NB, false>), g, dim3(kBlock), 0, s, M, rows, cols, ld, In, out,
-                       kchunk);
+    launch_ev(k_rows_gemm<TA, TB, ACC, NB, false>, g, s, e0, e1, M, rows, cols, ld, In, out, kchunk);
 }
 
 template <class TA, class TB, class ACC>
 void rows_gemm(const TA* M, long long rows, long long cols, long long ld, const TB* In, int kp, ACC* out, int S,
-               hipStream_t s) {
+               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   APL_REQUIRE(rows >= 1 && cols >= 1 && S >= 1, "rows_gemm: empty product");
   switch (kp) {
-    case 16: rows_gemm_nb<TA, TB, ACC, 1>(M, rows, cols, ld, In, out, S, s); break;
-    case 32: rows_gemm_nb<TA, TB, ACC, 2>(M, rows, cols, ld, In, out, S, s); break;
-    case 64: rows_gemm_nb<TA, TB, ACC, 4>(M, rows, cols, ld, In, out, S, s); break;
+    case 16: rows_gemm_nb<TA, TB, ACC, 1>(M, rows, cols, ld, In, out, S, s, e0, e1); break;
+    case 32: rows_gemm_nb<TA, TB, ACC, 2>(M, rows, cols, ld, In, out, S, s, e0, e1); break;
+    case 64: rows_gemm_nb<TA, TB, ACC, 4>(M, rows, cols, ld, In, out, S, s, e0, e1); break;
     default: APL_REQUIRE(false, "rows_gemm: kp must be 16, 32 or 64");
   }
 }
 template void rows_gemm<double, double, double>(const double*, long long, long long, long long, const double*, int,
-                                                double*, int, hipStream_t);
+                                                double*, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void rows_gemm<float, double, double>(const float*, long long, long long, long long, const double*, int,
-                                               double*, int, hipStream_t);
+                                               double*, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void rows_gemm<float, float, float>(const float*, long long, long long, long long, const float*, int, float*,
-                                             int, hipStream_t);
+                                             int, hipStream_t, hipEvent_t, hipEvent_t);
 template void rows_gemm<double, float, double>(const double*, long long, long long, long long, const float*, int,
-                                               double*, int, hipStream_t);
+                                               double*, int, hipStream_t, hipEvent_t, hipEvent_t);
 
 // ---------------------------------------------------------------- layout helpers
 template <class T>
@@ -422,7 +425,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 void rows_gemm16(const void* T, long long rows, long long cols, const float* In, int kp, float* out, int S,
-                 hipStream_t s) {
+                 hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   APL_REQUIRE(rows >= 1 && cols >= 1 && S >= 1, "rows_gemm16: empty product");
   const long long kchunk = ((cols + S - 1) / S + 63) / 64 * 64;
   const dim3 g((unsigned)ceil_div(rows, kGRows), (unsigned)S);
@@ -430,13 +433,13 @@ void rows_gemm16(const void* T, long long rows, long long cols, const float* In,
   const __bf16* M = (const __bf16*)T;
   switch (kp) {
     case 16:
-      hipLaunchKernelGGL((k_rows_gemm16<1, 16>), g, dim3(kBlock), 0, s, M, rows, cols, NJ, In, out, kchunk);
+      launch_ev(k_rows_gemm16<1, 16>, g, s, e0, e1, M, rows, cols, NJ, In, out, kchunk);
       break;
     case 32:
-      hipLaunchKernelGGL((k_rows_gemm16<2, 16>), g, dim3(kBlock), 0, s, M, rows, cols, NJ, In, out, kchunk);
+      launch_ev(k_rows_gemm16<2, 16>, g, s, e0, e1, M, rows, cols, NJ, In, out, kchunk);
       break;
     case 64:
-      hipLaunchKernelGGL((k_rows_gemm16<4, 8>), g, dim3(kBlock), 0, s, M, rows, cols, NJ, In, out, kchunk);
+      launch_ev(k_rows_gemm16<4, 8>, g, s, e0, e1, M, rows, cols, NJ, In, out, kchunk);
       break;
     default: APL_REQUIRE(false, "rows_gemm16: kp must be 16, 32 or 64");
   }
@@ -451,7 +454,7 @@ void unpack_cols(const double* Xp, int kp, long long rows, int k, double* X, lon
 }
 
 void blk_matmat(const BlkOp& A, bool trans, const double* X, long long ldx, int kp, int k, double* Y, long long ldy,
-                int prec, void* in, void* part, hipStream_t s) {
+                int prec, void* in, void* part, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const long long rows = trans ? A.n : A.m, cols = trans ? A.m : A.n, ld = trans ? A.ldt : A.ld;
   const void* M = trans ? A.At : A.A;
   const int S = trans ? A.Sn : A.Sm;
@@ -459,9 +462,11 @@ void blk_matmat(const BlkOp& A, bool trans, const double* X, long long ldx, int 
   if (prec == 0) {
     hipLaunchKernelGGL(k_pack_cols<double>, dim3(gi), dim3(kBlock), 0, s, X, ldx, cols, k, (double*)in, kp);
     if (A.f64)
-      rows_gemm<double, double, double>((const double*)M, rows, cols, ld, (const double*)in, kp, (double*)part, S, s);
+      rows_gemm<double, double, double>((const double*)M, rows, cols, ld, (const double*)in, kp, (double*)part, S, s,
+                                        e0, e1);
     else
-      rows_gemm<float, double, double>((const float*)M, rows, cols, ld, (const double*)in, kp, (double*)part, S, s);
+      rows_gemm<float, double, double>((const float*)M, rows, cols, ld, (const double*)in, kp, (double*)part, S, s,
+                                       e0, e1);
     hipLaunchKernelGGL(k_planes_to_cols<double>, dim3(go), dim3(kBlock), 0, s, (const double*)part, S, rows, kp, k, Y,
                        ldy);
     return;
@@ -469,9 +474,9 @@ void blk_matmat(const BlkOp& A, bool trans, const double* X, long long ldx, int 
   APL_REQUIRE(!A.f64 && (prec == 1 || A.A16), "blk_matmat: no FP32 / BF16 operator");
   hipLaunchKernelGGL(k_pack_cols<float>, dim3(gi), dim3(kBlock), 0, s, X, ldx, cols, k, (float*)in, kp);
   if (prec == 1)
-    rows_gemm<float, float, float>((const float*)M, rows, cols, ld, (const float*)in, kp, (float*)part, S, s);
+    rows_gemm<float, float, float>((const float*)M, rows, cols, ld, (const float*)in, kp, (float*)part, S, s, e0, e1);
   else
-    rows_gemm16(trans ? A.At16 : A.A16, rows, cols, (const float*)in, kp, (float*)part, S, s);
+    rows_gemm16(trans ? A.At16 : A.A16, rows, cols, (const float*)in, kp, (float*)part, S, s, e0, e1);
   hipLaunchKernelGGL(k_planes_to_cols<float>, dim3(go), dim3(kBlock), 0, s, (const float*)part, S, rows, kp, k, Y, ldy);
 }
 

@@ -575,10 +575,10 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 // per sweep (Hestenes' method, block form).  Off-diagonal entries are measured
 // on the damped Gram matrix X^T X + d2 I (d2 = delta^2: the columns of the
 // damped core [X; delta V], whose right singular vectors are X's):
-// e_pq = |g_pq| / sqrt((g_pp + d2)(g_qq + d2)).  off[0] receives the largest
-// e_pq of the round (as the bits of a non-negative double), off[1] the sum of
-// e_pq^2 over the entries between the pair's two blocks, so that a sweep adds
-// up each such entry once.  Each round takes one inner sweep on the pair's
+// e_pq = |g_pq| / sqrt((g_pp + d2)(g_qq + d2)).  sq_part[blockIdx.x] receives
+// the sum of e_pq^2 over the entries between the pair's two blocks (the
+// caller offsets sq_part by round), so that the partials of a sweep cover
+// each such entry once and are summed afterwards in a fixed order.  Each round takes one inner sweep on the pair's
 // Gram matrix only (the outer sweeps repeat the pairing until the whole
 // matrix is orthogonal), and a pair whose largest e_pq is at most `skip`
 // leaves X and V as they are.
@@ -607,7 +607,7 @@ __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, i
 
 __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, int rows, double* Vm,
                                                          long long ldv, int vrows, int nblk, int round,
-                                                         unsigned long long* off, double d2, double skip) {
+                                                         double* sq_part, double d2, double skip) {
   __shared__ double G[2][kJP][kJP + 1];  // double-buffered rotations
   __shared__ double Q[2][kJP][kJP + 1];
   __shared__ double tile[kJR][kJP + 1];
@@ -684,10 +684,7 @@ __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, 
     block_off = fmax(block_off, wmax[w]);
     block_sq += wsq[w];
   }
-  if (tid == 0) {
-    atomicMax(off, (unsigned long long)__double_as_longlong(block_off));
-    atomicAdd((double*)(off + 1), block_sq);
-  }
+  if (tid == 0) sq_part[blockIdx.x] = block_sq;
   if (block_off <= skip) return;  // uniform
   // 2) cyclic Jacobi on G (kJP x kJP): kJP - 1 rounds of kJW disjoint
   //    rotations (round-robin); each round G <- J^T G J and Q <- Q J computed
@@ -776,22 +773,30 @@ __global__ void k_col_norms(const double* X, long long ldx, int rows, int ncols,
   if (threadIdx.x == 0) out[c] = sqrt(s);
 }
 
+// out[0] = sum of part[0..count) in a fixed order (thread-strided sums, a
+// shuffle tree, the waves in order): the same value on every run.
+__global__ void __launch_bounds__(kBlock) k_sum_fixed(const double* part, int count, double* out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += kBlock) v += part[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
 int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
-               unsigned long long* off_dev, double delta2, double tol_f, double skip, int max_sweeps,
-               hipStream_t s) {
+               double* sq_part, double delta2, double tol_f, double skip, int max_sweeps, hipStream_t s) {
   // X: n x npad (columns n..npad-1 zero), Vm: npad x npad, set to I by the caller.
   const int nblk = npad / kJW;
+  const int npairs = nblk / 2, rounds = nblk - 1;
+  double* sum_dev = sq_part + (long long)rounds * npairs;
   int sweeps = 0;
   for (; sweeps < max_sweeps; ++sweeps) {
-    APL_HIP(hipMemsetAsync(off_dev, 0, 2 * sizeof(unsigned long long), s));
-    for (int r = 0; r < nblk - 1; ++r)
-      hipLaunchKernelGGL(k_jacobi_round, dim3(nblk / 2), dim3(kJT), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
-                         off_dev, delta2, skip);
-    unsigned long long h[2] = {0, 0};
-    APL_HIP(hipMemcpyAsync(h, off_dev, sizeof(h), hipMemcpyDeviceToHost, s));
+    for (int r = 0; r < rounds; ++r)
+      hipLaunchKernelGGL(k_jacobi_round, dim3(npairs), dim3(kJT), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
+                         sq_part + (long long)r * npairs, delta2, skip);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kBlock), 0, s, (const double*)sq_part, rounds * npairs, sum_dev);
+    double sum_sq = 0.0;
+    APL_HIP(hipMemcpyAsync(&sum_sq, sum_dev, sizeof(sum_sq), hipMemcpyDeviceToHost, s));
     APL_HIP(hipStreamSynchronize(s));
-    double sum_sq;
-    memcpy(&sum_sq, &h[1], sizeof(sum_sq));
     // Frobenius norm of the damped off-diagonal (both triangles) as the sweep saw it
     if (std::sqrt(2.0 * sum_sq) <= tol_f) {
       ++sweeps;
@@ -800,6 +805,11 @@ int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long 
   }
   hipLaunchKernelGGL(k_col_norms, dim3(n), dim3(kBlock), 0, s, X, ldx, n, n, sigma);
   return sweeps;
+}
+
+long long jacobi_part_words(int npad) {
+  const long long nblk = npad / kJW;
+  return (nblk - 1) * (nblk / 2) + 1;
 }
 
 int jacobi_block_width() { return kJW; }

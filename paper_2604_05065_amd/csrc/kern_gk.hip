@@ -1474,6 +1474,14 @@ void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* 
   }
 }
 
+// y = P^{-1} z (trans = false) or P^{-T} z (trans = true) with the
+// coefficient kernels of the LSQR iteration and the row pass of the phase end.
+void gk_precond_apply(const OpDesc& A, const PrecDesc& P, bool trans, const double* z, double* y, hipStream_t s) {
+  fill_zero<double>(y, A.n, s);
+  launch_pcoef<double>(A, P, A.n, z, nullptr, trans, s);
+  hipLaunchKernelGGL((k_pa_x<double>), dim3(prec_grid(P, A.n)), dim3(kBlock), 0, s, P, A.n, z, y);
+}
+
 template void gk_iteration<double>(const OpDesc&, const PrecDesc*, GKVecs<double>, GKState*, GKWork&, hipStream_t);
 template void gk_iteration<float>(const OpDesc&, const PrecDesc*, GKVecs<float>, GKState*, GKWork&, hipStream_t);
 template void gk_phase_init<double>(const OpDesc&, const OpDesc&, const PrecDesc*, const double*, const double*,

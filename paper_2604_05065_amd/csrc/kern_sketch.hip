@@ -153,9 +153,21 @@ __global__ void k_check_csr(const int* row_ptr, const int* col_idx, long long m,
   }
 }
 
+// p[0..count) = 0 (a kernel, not a memset, so that a captured graph may hold it).
+__global__ void k_zero_int(int* p, long long count) {
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < count; i += (long long)gridDim.x * kBlock)
+    p[i] = 0;
+}
+
+static void zero_int(int* p, long long count, hipStream_t st) {
+  if (count <= 0) return;
+  const long long g = (count + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_zero_int, dim3((unsigned)(g < 1024 ? g : 1024)), dim3(kBlock), 0, st, p, count);
+}
+
 int check_csr(const int* row_ptr, const int* col_idx, long long m, long long n, long long nnz, int* bad_dev,
               hipStream_t st) {
-  APL_HIP(hipMemsetAsync(bad_dev, 0, sizeof(int), st));
+  zero_int(bad_dev, 1, st);
   hipLaunchKernelGGL(k_check_csr, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, st, row_ptr, col_idx, m, n, nnz,
                      bad_dev);
   int h = 0;
@@ -234,7 +246,7 @@ template <class T>
 void launch_csr_transpose(const int* row_ptr, const int* col_idx, const T* val, long long m,
                           long long n, long long nnz, int* t_ptr, int* t_idx, T* t_val,
                           int* scratch_n, hipStream_t st) {
-  APL_HIP(hipMemsetAsync(scratch_n, 0, sizeof(int) * n, st));
+  zero_int(scratch_n, n, st);
   if (nnz > 0)
     hipLaunchKernelGGL(k_count_cols, dim3(ceil_div(nnz, kBlock)), dim3(kBlock), 0, st, col_idx,
                        nnz, scratch_n);

@@ -125,6 +125,8 @@ void gk_phase_init(const OpDesc& Ares, const OpDesc& A, const PrecDesc* P, const
 template <class V>
 void gk_phase_finish(const OpDesc& A, const PrecDesc* P, GKVecs<V> vec, double* x, GKState* st, hipStream_t s);
 // ||A_mu^T r||^2 -> st[0].h2 for r = [b - A x; bot_scale b_bot - delta x].
+// y = P^{-1} z (trans = false) or P^{-T} z (trans = true), FP64 (n entries).
+void gk_precond_apply(const OpDesc& A, const PrecDesc& P, bool trans, const double* z, double* y, hipStream_t s);
 void gk_normal_residual(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,
                         GKVecs<double> vec, GKState* st, GKWork& wk, hipStream_t s);
 void gk_normal_vector(const OpDesc& A, const double* b, const double* b_bot, double bot_scale, const double* x,

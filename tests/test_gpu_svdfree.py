@@ -14,6 +14,8 @@ from oracle.cur import (SvdFreePreconditioner, augment_cur, augment_qr, core_and
 from oracle.dense import solve_dense_qr
 from workloads import synth
 
+from bounds import check_solution
+
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
@@ -119,7 +121,7 @@ def test_svdfree_fp32_phases_and_columns(lib):
     with lib.Context(_t(w.A), mu=0.0, block=w.block, tol_ne=1e-9, precond="svdfree") as ctx:
         x1, _ = ctx.solve(_t(B[:, 1]))
     xr = solve_dense_qr(w.A, B[:, 1], 0.0)
-    assert np.linalg.norm(x1.cpu().numpy() - xr) <= 1e-6 * np.linalg.norm(xr)
+    check_solution(x1.cpu().numpy(), xr, w.A, B[:, 1], 0.0, "SVD-free, second column")
 
 
 def test_svdfree_rejects_mu(lib):
