@@ -193,6 +193,26 @@ int64_t aplicur_workspace_bytes(const aplicur_mat* A, int32_t nrhs, const aplicu
 int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* ws, size_t ws_bytes, void* stream,
                    aplicur_ctx** ctx_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sketch
+ * Y = S A of aplicur_sketch (Alg. 3 initialisation, the sparse sign embedding
+ * of Definition 5.1 with the same seed, block and xi options, so the same S)
+ * written into caller memory, with no context and no device allocation.
+ * Y (device): s x n doubles, row-major, s = min(m, ceil(1.1 block)).  A as in
+ * aplicur_sketch, but row-major dense or CSR (APLICUR_DENSE_COL: E_INVALID);
+ * opts.precond must be 1 or 2 and opts.sketch 0.  Scratch (the sketch's rows
+ * and signs; for CSR A the validation flag and the CSR of A^T; for dense A the
+ * row-chunk partials when more than one chunk fits) lives in a fixed array of
+ * 64 MiB per device that the library holds until the process ends; an input
+ * whose scratch would exceed it is rejected (E_INVALID, the message gives the
+ * bytes needed) before any device work.  A dense sketch that fits fewer row
+ * chunks than aplicur_sketch uses sums its chunks in another order (equal to
+ * rounding).  Calls on one device share that array: calls that overlap on
+ * one GPU (different streams, or different host threads) race; serialise
+ * them.  CSR validation reads one flag back (the call synchronises the
+ * stream).  Errors: E_INVALID, E_HIP.                                       */
+int aplicur_sketch_noalloc(const aplicur_mat* A, const aplicur_opts* opts, double* Y, void* stream);
+
 /* The adaptive solve of Alg. 3 for nrhs right-hand sides B (m x nrhs,
  * column-major, ldb >= m) into X (n x nrhs, ldx >= n).  All columns share
  * the CUR sequence and every preconditioner (none depends on b); each

@@ -41,7 +41,7 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ["aplicur_opts_default", "aplicur_workspace_bytes", "aplicur_sketch", "aplicur_solve", "aplicur_solve_batched",
+EXPORTS = ["aplicur_opts_default", "aplicur_workspace_bytes", "aplicur_sketch", "aplicur_sketch_noalloc", "aplicur_solve", "aplicur_solve_batched",
            "aplicur_solve_backward", "aplicur_matvec", "aplicur_matmat", "aplicur_time_product", "aplicur_time_matmat", "aplicur_precond_apply", "aplicur_ctx_query", "aplicur_ctx_destroy",
            "aplicur_last_error", "aplicur_version"]
 
@@ -61,6 +61,8 @@ def load():
     lib.aplicur_opts_default.restype = None
     lib.aplicur_sketch.argtypes = [C.POINTER(Mat), C.POINTER(Opts), vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.aplicur_sketch.restype = C.c_int
+    lib.aplicur_sketch_noalloc.argtypes = [C.POINTER(Mat), C.POINTER(Opts), dp, vp]
+    lib.aplicur_sketch_noalloc.restype = C.c_int
     lib.aplicur_workspace_bytes.argtypes = [C.POINTER(Mat), i32, C.POINTER(Opts), vp]
     lib.aplicur_workspace_bytes.restype = C.c_int64
     lib.aplicur_solve.argtypes = [vp, dp, i64, i32, dp, i64, i32, C.POINTER(Info), vp]

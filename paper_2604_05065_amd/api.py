@@ -263,6 +263,21 @@ class Context:
         self.close()
 
 
+def sketch_noalloc(A, Y=None, **opts):
+    """Y = S A (s x n, FP64) through aplicur_sketch_noalloc: no context and no
+    device allocation inside the library (Y is allocated here unless given)."""
+    lib = L.load()
+    mat, keep = _mat(A)
+    o = make_opts(**opts)
+    s = max(1, min(int(mat.m), math.ceil(1.1 * o.block - 1e-12)))
+    if Y is None:
+        Y = torch.empty((s, int(mat.n)), dtype=torch.float64, device=_device(A))
+    if Y.shape != (s, int(mat.n)) or not Y.is_contiguous() or Y.dtype != torch.float64:
+        raise ValueError(f"Y must be a contiguous FP64 ({s}, {int(mat.n)}) tensor")
+    L.check(lib.aplicur_sketch_noalloc(C.byref(mat), C.byref(o), Y.data_ptr(), _stream()))
+    return Y
+
+
 def sketch(A, **opts):
     return Context(A, **opts)
 

@@ -15,7 +15,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libaplicur.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
-SOURCES = ["kern_sketch.hip", "kern_gk.hip", "kern_blk.hip", "kern_factor.hip", "kern_blas.hip", "aplicur.cpp"]
+SOURCES = ["kern_sketch.hip", "kern_gk.hip", "kern_blk.hip", "kern_factor.hip", "kern_blas.hip", "aplicur.cpp",
+           "noalloc.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-I" + os.path.join(ROCM, "include")]

@@ -76,3 +76,18 @@ def test_defaults_and_errors_without_gpu():
     assert b"aligned" in lib.aplicur_last_error()
     assert lib.aplicur_workspace_bytes(ctypes.byref(m2), 0, ctypes.byref(o), None) == _lib.E_INVALID
 
+def test_sketch_noalloc_rejects_what_does_not_fit():
+    """aplicur_sketch_noalloc checks its scratch need on the host before any
+    device access: 2^22 rows need 2^22 * 17 bytes for the sketch's rows and
+    signs alone, more than its fixed 64 MiB (the values are never read)."""
+    from paper_2604_05065_amd import _lib
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.aplicur_opts_default(ctypes.byref(o))
+    o.block = 100
+    m = _lib.Mat(_lib.DENSE, _lib.F64, 1 << 22, 64, 64, 0, 256, None, None)
+    assert lib.aplicur_sketch_noalloc(ctypes.byref(m), ctypes.byref(o), 4096, None) == _lib.E_INVALID
+    assert b"bytes of scratch" in lib.aplicur_last_error()
+    o.sketch = 1
+    assert lib.aplicur_sketch_noalloc(ctypes.byref(m), ctypes.byref(o), 4096, None) == _lib.E_INVALID
+    assert b"sparse sign" in lib.aplicur_last_error()
