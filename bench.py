@@ -1,21 +1,33 @@
-"""Benchmark: time to a 1e-8 relative normal-equation residual on the sparse
-ill-conditioned workload, plus the A / A^T product bandwidth against the HBM
-roofline.
+"""Benchmark: time to a 1e-8 relative normal-equation residual on the dense
+kernel workload (the largest single-GPU configuration), with the product
+kernel against the HBM roofline; the sparse, adjoint and batched workloads
+beside it.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-compare]
-                    [--max-rank L] [--products-only]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                    [--no-extensions] [--max-rank L] [--products-only]
 
-Workload: CSR A 200000 x 20000 with 10 distinct uniformly random columns per
-row (2.0e6 non-zeros), N(0,1) values, column j scaled by 10^(-6 j/(n-1));
-b ~ N(0,1); mu = 1e-4; block 100 (sketch dimension s = 110); FP64.  One step
-is one whole APLICUR solve (sketch + adaptive CUR + preconditioned LSQR
-phases, FP64) to eta <= 1e-8 with A and b already resident in HBM.  Plain
-GPU LSQR (same kernels, P = I) and the FP32-phase variants to the same eta
-are timed beside it.  One JSON line on stdout; progress on stderr.
+Headline (value): A = exp(-||p_i - p_j||^2 / 2) on 40000 points uniform in
+[0,1]^8, 40000 x 40000 FP32 (6.4 GB), 16 right-hand sides N(0,1), mu = 1e-3,
+block 250 (sketch dimension 275).  One step is one whole APLICUR solve
+(sketch, adaptive CUR, preconditioner builds, LSQR phases with the 16
+columns blocked on FP64-accumulated MFMA products, FP64 eta checks) to eta
+<= 1e-8 for every column, with A and B already resident in HBM; step t uses
+sketch seed 10 + 100 (t mod 5), and the line reports the median and range
+over the steps.  roofline: the blocked product kernel (A X and A^T U, 16
+columns), every launch of the timed steps timed by events on its own
+dispatch.  Beside it, on the same problem:
+FP32 phases, BF16 products, plain LSQR.  Then the sparse workload (CSR
+200000 x 20000: product bandwidth warm and cold, APLICUR and plain LSQR), the
+adjoint workload (dense FP32 100000 x 2000, 32 RHS: forward, backward, plain
+LSQR) and the batched workload (64 uneven problems, 8 RHS: one batched
+call, one at a time, plain LSQR on the first 8).  The CPU baseline is the
+FP64 oracle on a bounded sample of the headline recipe.  One JSON line on
+stdout; progress on stderr.
 
---products-only runs just the timed A / A^T product loop and a 256 MiB copy
-of known size (for hardware-counter runs); --blocked-products does the same
-for the blocked products of several right-hand sides (dense FP32 A).
+--products-only runs just the timed sparse A / A^T product loop and a 256
+MiB copy of known size (for hardware-counter runs); --blocked-products does
+the same for the blocked products of several right-hand sides (dense FP32
+A).
 """
 import argparse
 import hashlib
@@ -32,8 +44,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "time to 1e-8 rel. NE residual & A/A^T matvec GB/s; batched+adjoint vs plain"
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_05065_amd", "csrc", "kern_gk.hip")
+BLK_SRC = os.path.join(ROOT, "paper_2604_05065_amd", "csrc", "kern_blk.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "spmv_csr_200000x20000_counters.txt")
+BLK_COUNTERS = os.path.join(ROOT, "profiles", "blocked_products_rbf40000_k16_counters.txt")
 PRODUCT_REPS = 200
+FP64_PEAK_TFS = 78.6
+# the dense kernel workload: RBF kernel on 40000 points in [0,1]^8, FP32, 16 RHS
+NPTS, NRHS, MU3, BLOCK3, TOL3 = 40000, 16, 1e-3, 250, 1e-8
+SEEDS3 = [10 + 100 * t for t in range(5)]  # sketch seeds 7 + 3 + 100 t: five trials
 
 
 def log(*a):
@@ -47,57 +65,50 @@ def spmv_bytes(rows, cols, nnz, vbytes=8):
     return nnz * (vbytes + 4) + (rows + 1) * 4 + cols * 8 + 2 * rows * 8
 
 
-def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_hash(path=KERNEL_SRC):
+    with open(path, "rb") as f:
         return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
-def counter_traffic():
-    """HBM bytes per launch of the A-product kernel from the committed
-    counter summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel
-    calibration), or None when it is missing or was taken on other kernel
-    source."""
+def counter_traffic(path=COUNTERS, src=KERNEL_SRC, key="traffic_bytes_per_launch_A"):
+    """HBM bytes per launch of a product kernel from a committed counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration),
+    or None when it is missing or was taken on other kernel source."""
     try:
-        txt = open(COUNTERS).read()
+        txt = open(path).read()
     except OSError:
         return None
     h = re.search(r"^kernel_source_sha1:\s*(\S+)", txt, re.M)
-    t = re.search(r"^traffic_bytes_per_launch_A:\s*([0-9.eE+]+)", txt, re.M)
-    if not h or not t or h.group(1) != kernel_hash():
+    t = re.search(r"^" + key + r":\s*([0-9.eE+]+)", txt, re.M)
+    if not h or not t or h.group(1) != kernel_hash(src):
         return None
     return float(t.group(1))
 
 
-def cpu_baseline(A, b, mu, plain_iters, budget_s=15.0):
-    """The oracle's plain damped LSQR on the full matrix, on one host thread
-    (scipy's CSR products are single-threaded; the BLAS pool is limited to
-    one thread for the vector operations), for a bounded number of
-    iterations (about budget_s seconds), scaled to the iterations plain LSQR
-    needs to reach the tolerance (the GPU plain run's count: the same
-    recurrence)."""
-    import contextlib
-
+def cpu_baseline_dense_kernel(npts=5000, budget_s=30.0):
+    """The FP64 oracle (NumPy/SciPy APLICUR, Alg. 3) timed to eta <= 1e-8 on
+    a bounded sample of the dense kernel workload: the same RBF kernel recipe
+    on npts points (CPU generator), one right-hand side, mu = 1e-3, block 250,
+    sketch seed 10, on the host cores (BLAS threads as the pool runs them)."""
     import numpy as np
-    from oracle.lsqr import plsqr_phase
+    from oracle.aplicur import Options, aplicur, ne_residual
+    from workloads import synth
     try:
-        from threadpoolctl import threadpool_limits
-        one_thread = threadpool_limits(limits=1)
+        from threadpoolctl import threadpool_info
+        threads = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
     except Exception:
-        one_thread = contextlib.nullcontext()
-    n = A.shape[1]
-    with one_thread:
-        t0 = time.perf_counter()
-        plsqr_phase(A, math.sqrt(mu), b, np.zeros(n), None, eps_lsqr=0.0, tol_ne=0.0, max_iter=5)
-        per = (time.perf_counter() - t0) / 5
-        k = max(10, int(budget_s / max(per, 1e-6)))
-        t0 = time.perf_counter()
-        plsqr_phase(A, math.sqrt(mu), b, np.zeros(n), None, eps_lsqr=0.0, tol_ne=0.0, max_iter=k)
-        per = (time.perf_counter() - t0) / k
-    value = per * plain_iters * 1e3
-    return {"value": round(value, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle plain damped LSQR (R1), {k} iterations on the full 200000 x 20000 matrix "
-                       f"({per * 1e3:.2f} ms/iteration, scipy CSR products), scaled to the {plain_iters} "
-                       f"iterations plain LSQR needs for eta <= 1e-8")}
+        threads = len(os.sched_getaffinity(0))
+    A = synth.rbf_kernel(np.random.default_rng(3002), npts).astype(np.float64)
+    b = np.random.default_rng(3001).standard_normal(npts)
+    t0 = time.perf_counter()
+    x = aplicur(A, b, MU3, Options(block=BLOCK3, tol_ne=TOL3, seed=SEEDS3[0]))
+    ms = (time.perf_counter() - t0) * 1e3
+    eta = ne_residual(A, b, x, MU3)
+    return {"value": round(ms, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle APLICUR (FP64, NumPy/SciPy) to eta <= 1e-8 (reached {eta:.1e}) on the RBF kernel "
+                       f"recipe at {npts} points (one right-hand side, mu = 1e-3, block 250), not the 40000-point, "
+                       f"16-column workload of value; {threads} BLAS threads of "
+                       f"{len(os.sched_getaffinity(0))} host cores")}
 
 
 def _timed(torch, fn):
@@ -108,11 +119,189 @@ def _timed(torch, fn):
     return (time.perf_counter() - t) * 1e3, out
 
 
-def bench_batched(ap, synth, torch, count=16, scale=0.25, nrhs=2):
-    """The batched workload at 1/4 of its sizes (m ~ U{1250..25000}, n ~
-    U{125..min(1250, m/4)}, sigma_i = 10^(-k i/n), k ~ U[2,8], FP32, 2 RHS,
-    mu = 1e-6, block 50): one batched call (worker streams, graph replay,
-    tuned tiles) against one-at-a-time APLICUR and one-at-a-time plain LSQR."""
+def bench_headline(ap, synth, torch, args):
+    """The dense kernel workload at full size: A = exp(-||p_i - p_j||^2 / 2) on
+    40000 points uniform in [0,1]^8 (FP32, 6.4 GB), 16 right-hand sides N(0,1),
+    mu = 1e-3, block 250, every column to eta <= 1e-8; the 16 columns run
+    blocked (FP64-accumulated MFMA products).  One step is one whole solve
+    (context creation with the sketch, CUR increments, preconditioner builds,
+    LSQR phases, FP64 eta checks); step t uses sketch seed SEEDS3[t mod 5].
+    Beside it: the blocked product kernel, timed by events on each of its
+    dispatches in the timed steps and alone (20 launches back to back), the
+    same solve with FP32 and BF16 phases, and plain LSQR on the same problem
+    (iteration budget 2000)."""
+    A, B = synth.rbf_kernel_gpu(3003, NPTS, NRHS)
+    opts = dict(mu=MU3, block=BLOCK3, tol_ne=TOL3)
+    log(f"[bench] dense kernel workload {NPTS}^2 FP32 x {NRHS} generated")
+
+    def solve(seed, **kw):
+        return _timed(torch, lambda: ap.lstsq(A, B, seed=seed, **opts, **kw))
+
+    # event timing of the product kernel on its own dispatches, on during the
+    # warm-up (which creates the events) and the timed steps
+    ap.prof_products(True)
+    for i in range(args.warmup):
+        ms, (_, info) = solve(SEEDS3[0])
+        log(f"[bench] warmup {i}: {ms:.1f} ms rank={info.rank} iters={info.iters} eta={info.eta:.2e}")
+    ap.prof_read()
+    times, infos = [], []
+    torch.cuda.synchronize()
+    for t in range(args.steps):
+        seed = SEEDS3[t % len(SEEDS3)]
+        ms, (_, info) = solve(seed)
+        times.append(ms)
+        infos.append(info)
+        log(f"[bench] step {t} (seed {seed}): {ms:.1f} ms rank={info.rank} phases={info.phases} iters={info.iters} "
+            f"eta={info.eta:.2e} (sketch {info.t_sketch_ms:.1f}, cur {info.t_cur_ms:.1f}, "
+            f"precond {info.t_precond_ms:.1f}, lsqr {info.t_lsqr_ms:.1f} ms)")
+        if info.status != 0 or info.eta > TOL3:
+            log(f"[bench] WARNING: step {t} did not reach eta <= {TOL3:g} (status {info.status})")
+    prof = ap.prof_read()
+    ap.prof_products(False)
+    ms_step = sum(times) / len(times)
+    srt = sorted(times)
+    med = srt[len(srt) // 2] if len(srt) % 2 else 0.5 * (srt[len(srt) // 2 - 1] + srt[len(srt) // 2])
+    info = infos[-1]
+    # the product kernel inside the timed steps: A X and A^T U (16 columns, FP64
+    # accumulation), each launch timed by events on its own dispatch
+    n_ax, us_ax_live, _ = prof.get("AX_f64", (0, float("nan"), 0))
+    n_atu, us_atu_live, _ = prof.get("ATX_f64", (0, float("nan"), 0))
+    untimed = sum(v[2] for v in prof.values())
+    us_live = (n_ax * us_ax_live + n_atu * us_atu_live) / max(1, n_ax + n_atu)
+    bytes_prod = 4 * NPTS * NPTS + 2 * NPTS * NRHS * 8  # A (or its transposed copy) once in FP32, X read, Y written
+    flops_prod = 2.0 * NPTS * NPTS * NRHS
+    gbs = bytes_prod / (us_live * 1e-6) / 1e9
+    log(f"[bench] product kernel in the timed steps: {n_ax} A X launches {us_ax_live:.0f} us, {n_atu} A^T U "
+        f"launches {us_atu_live:.0f} us (untimed {untimed}); mean {us_live:.0f} us = {gbs:.0f} GB/s, "
+        f"{flops_prod / us_live / 1e6:.1f} TFLOP/s")
+    # the same kernel alone, 20 launches back to back
+    with ap.Context(A, precond=False, **opts) as ctx:
+        X = torch.randn(NPTS, NRHS, device="cuda", dtype=torch.float64)
+        us_ax = ctx.time_matmat(X, trans=False, reps=20)
+        us_atu = ctx.time_matmat(X, trans=True, reps=20)
+    log(f"[bench] product kernel alone (20 back to back): A X {us_ax:.0f} us, A^T U {us_atu:.0f} us")
+    compare = {}
+    for name, kw in (("aplicur_fp32_phases", dict(precision=1)), ("aplicur_bf16_products", dict(precision=2)),
+                     ("plain_lsqr", dict(precond=False, max_iter=2000))):
+        if name != "plain_lsqr":
+            solve(SEEDS3[0], **kw)  # warm-up of the mode (its copies of A)
+        ms, (_, inf) = solve(SEEDS3[0], **kw)
+        compare[name] = {"ms": round(ms, 1), "iters": inf.iters, "phases": inf.phases, "eta": inf.eta,
+                         "status": inf.status, "rank": inf.rank,
+                         "reached": bool(inf.status == 0 and inf.eta <= TOL3)}
+        log(f"[bench] {name}: {ms:.0f} ms iters={inf.iters} phases={inf.phases} eta={inf.eta:.2e} "
+            f"status={inf.status}")
+    del A, B
+    traffic = counter_traffic(BLK_COUNTERS, BLK_SRC, "traffic_bytes_per_launch_AX")
+    return {
+        "ms_per_step": round(ms_step, 3),
+        "config": {"workload": (f"APLICUR solve of the dense RBF kernel workload to eta<=1e-8 per column: "
+                                f"A = exp(-|p_i-p_j|^2/2), {NPTS} points in [0,1]^8, {NPTS}x{NPTS} FP32, "
+                                f"{NRHS} right-hand sides, mu={MU3:g}, block {BLOCK3}, columns blocked on "
+                                f"FP64-accumulated MFMA products"),
+                   "npts": NPTS, "nrhs": NRHS, "mu": MU3, "block": BLOCK3, "tol_ne": TOL3,
+                   "sketch_seeds": SEEDS3},
+        "seeds": {"median_ms": round(med, 1), "min_ms": round(srt[0], 1), "max_ms": round(srt[-1], 1),
+                  "per_step_ms": [round(t, 1) for t in times]},
+        "aplicur": {"rank": info.rank, "phases": info.phases, "iters": info.iters, "outer": info.outer,
+                    "rebuilds": info.rebuilds, "eta": max(i.eta for i in infos),
+                    "all_reached": all(i.status == 0 and i.eta <= TOL3 for i in infos),
+                    "t_sketch_ms": round(info.t_sketch_ms, 2), "t_cur_ms": round(info.t_cur_ms, 2),
+                    "t_precond_ms": round(info.t_precond_ms, 2), "t_lsqr_ms": round(info.t_lsqr_ms, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": ("k_rows_gemm<float, double, double> (A X and A^T U for 16 columns, FP32 A "
+                                "widened, FP64 16x16x4 MFMA), launches of the timed steps"),
+                     "launches": n_ax + n_atu, "bytes_per_launch": int(bytes_prod),
+                     "us_per_launch": round(us_live, 3),
+                     "mfma_tflops": round(flops_prod / us_live / 1e6, 2),
+                     "mfma_frac_fp64": round(flops_prod / us_live / 1e6 / FP64_PEAK_TFS, 4)},
+        "products": {"timed_steps": {"AX_launches": n_ax, "AX_us": round(us_ax_live, 1), "ATU_launches": n_atu,
+                                     "ATU_us": round(us_atu_live, 1), "untimed": untimed},
+                     "alone_back_to_back": {"AX_us": round(us_ax, 1), "ATU_us": round(us_atu, 1),
+                                            "AX_GBs": round(bytes_prod / (us_ax * 1e-6) / 1e9, 1),
+                                            "ATU_GBs": round(bytes_prod / (us_atu * 1e-6) / 1e9, 1)}},
+        "compare": compare,
+    }
+
+
+def bench_c2(ap, synth, torch, args):
+    """The sparse workload (CSR 200000 x 20000, 10 random columns per row,
+    column scaling 1e-6, mu = 1e-4, block 100, rank cap args.max_rank): the A
+    and A^T product kernels (warm, and cold with 1 GiB read and written before
+    each timed launch), a measured device copy, and APLICUR against plain
+    LSQR to eta <= 1e-8 (FP64)."""
+    t0 = time.time()
+    w = synth.workload(2, 1.0)
+    A, b, mu, block, tol = w.A, w.B, w.mu, w.block, w.tol
+    m, n = A.shape
+    nnz = int(A.nnz)
+    log(f"[bench] sparse workload {m}x{n} nnz={nnz} generated in {time.time() - t0:.1f}s")
+    Ag = ap.CSRMatrix.from_scipy(A, device="cuda", dtype=torch.float64)
+    bg = torch.as_tensor(b, device="cuda")
+    with ap.Context(Ag, precond=False, mu=mu) as ctx:
+        xv = torch.randn(n, device="cuda", dtype=torch.float64)
+        ctx.time_product(xv, trans=False, reps=10)
+        us_a = ctx.time_product(xv, trans=False, reps=PRODUCT_REPS)
+        us_at = ctx.time_product(xv, trans=True, reps=PRODUCT_REPS)
+        us_a_cold = us_at_cold = float("nan")
+        if not args.products_only:
+            flush = torch.zeros(1 << 28, dtype=torch.int32, device="cuda")
+            us_a_cold = ctx.time_product(xv, trans=False, reps=20, flush=flush)
+            us_at_cold = ctx.time_product(xv, trans=True, reps=20, flush=flush)
+            del flush
+    bytes_a = spmv_bytes(m, n, nnz)
+    bytes_at = spmv_bytes(n, m, nnz) - n * 8  # the A^T kernel stores its output without reading it
+    if args.products_only:
+        big = torch.empty(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(big)
+        for _ in range(3):
+            dst.copy_(big)
+        torch.cuda.synchronize()
+        print(json.dumps({"us_A": us_a, "us_AT": us_at, "bytes_A": bytes_a, "bytes_AT": bytes_at,
+                          "copy_bytes_each_way": big.numel() * 8}), flush=True)
+        return None
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    gbs = lambda b_, us: b_ / (us * 1e-6) / 1e9  # noqa: E731
+    log(f"[bench] CSR A x: {us_a:.2f} us ({gbs(bytes_a, us_a):.0f} GB/s), cold {us_a_cold:.2f} us "
+        f"({gbs(bytes_a, us_a_cold):.0f} GB/s); A^T u: {us_at:.2f} us ({gbs(bytes_at, us_at):.0f} GB/s), cold "
+        f"{us_at_cold:.2f} us ({gbs(bytes_at, us_at_cold):.0f} GB/s); device copy {copy_gbs:.0f} GB/s")
+    res = {}
+    for name, pc, prec in (("aplicur_f64", True, 0), ("plain_lsqr_f64", False, 0), ("aplicur_f32_phases", True, 1),
+                           ("plain_lsqr_f32_phases", False, 1)):
+        o = dict(mu=mu, block=block, tol_ne=tol, seed=7, max_rank=args.max_rank, precond=pc, precision=prec)
+        ap.lstsq(Ag, bg, **o)  # warm-up
+        ms, (_, inf) = _timed(torch, lambda: ap.lstsq(Ag, bg, **o))
+        res[name] = {"ms": round(ms, 1), "iters": inf.iters, "phases": inf.phases, "eta": inf.eta,
+                     "rank": inf.rank, "us_per_iter": round(inf.t_lsqr_ms * 1e3 / max(inf.iters, 1), 2)}
+        log(f"[bench] CSR {name}: {ms:.0f} ms iters={inf.iters} eta={inf.eta:.2e} rank={inf.rank}")
+    return {"m": m, "n": n, "nnz": nnz, "mu": mu, "block": block, "max_rank": args.max_rank,
+            "A_us": round(us_a, 3), "A_GBs": round(gbs(bytes_a, us_a), 1),
+            "AT_us": round(us_at, 3), "AT_GBs": round(gbs(bytes_at, us_at), 1),
+            "A_us_cold": round(us_a_cold, 3), "A_GBs_cold": round(gbs(bytes_a, us_a_cold), 1),
+            "A_frac_cold": round(gbs(bytes_a, us_a_cold) / HBM_PEAK_GBS, 4),
+            "AT_us_cold": round(us_at_cold, 3), "AT_GBs_cold": round(gbs(bytes_at, us_at_cold), 1),
+            "AT_frac_cold": round(gbs(bytes_at, us_at_cold) / HBM_PEAK_GBS, 4),
+            "A_bytes": int(bytes_a), "AT_bytes": int(bytes_at), "A_traffic": counter_traffic(),
+            "copy_GBs": round(copy_gbs, 1), "solves": res}
+
+
+def bench_batched(ap, synth, torch, count=16, scale=0.25, nrhs=2, plain_subset=None):
+    """The batched workload (count problems, m ~ U{5000..100000} scale, n ~
+    U{500..min(5000, m/4)} scale, sigma_i = 10^(-k i/n), k ~ U[2,8], FP32,
+    nrhs RHS, mu = 1e-6, block 50): one batched call (worker streams, graph
+    replay, tuned tiles) against one-at-a-time APLICUR and one-at-a-time
+    plain LSQR (on the first plain_subset problems when given)."""
     shapes = synth.batch_shapes(count, m_range=(int(5000 * scale), int(100000 * scale)),
                                 n_range=(int(500 * scale), int(5000 * scale)))
     probs = []
@@ -123,24 +312,28 @@ def bench_batched(ap, synth, torch, count=16, scale=0.25, nrhs=2):
     opts = dict(mu=1e-6, block=50, tol_ne=1e-8)
     As, Bs = [p[0] for p in probs], [p[1] for p in probs]
 
-    def one_at_a_time(**kw):
+    def one_at_a_time(limit=None, **kw):
         out = []
-        for i, (A, B) in enumerate(zip(As, Bs)):
+        for i, (A, B) in enumerate(zip(As[:limit], Bs[:limit])):
             out.append(ap.lstsq(A, B, **opts, **kw)[1])
-            if (i + 1) % 16 == 0:
-                log(f"[bench] batched: {i + 1} of {count} one-at-a-time solves ({kw or 'APLICUR'})")
+            if (i + 1) % 8 == 0:
+                log(f"[bench] batched: {i + 1} one-at-a-time solves ({kw or 'APLICUR'})")
         return out
     ap.solve_batched(As[:2], Bs[:2], workers=2, **opts)  # warm-up
     ms_b, (_, infos) = _timed(torch, lambda: ap.solve_batched(As, Bs, workers=8, **opts))
     log(f"[bench] batched: one call {ms_b:.0f} ms")
     ms_s, inf_s = _timed(torch, lambda: one_at_a_time())
-    ms_p, inf_p = _timed(torch, lambda: one_at_a_time(precond=False))
+    sub = plain_subset or count
+    ms_p, inf_p = _timed(torch, lambda: one_at_a_time(limit=sub, precond=False))
+    ms_ps, inf_ps = _timed(torch, lambda: one_at_a_time(limit=sub))  # APLICUR on the same subset
     ok = all(i.status == 0 for i in list(infos) + inf_s + inf_p)
-    log(f"[bench] batched {count} problems: batched {ms_b:.0f} ms, one-at-a-time APLICUR {ms_s:.0f} ms, "
-        f"plain LSQR {ms_p:.0f} ms (all converged: {ok})")
+    log(f"[bench] batched {count} problems: batched {ms_b:.0f} ms, one-at-a-time APLICUR {ms_s:.0f} ms; "
+        f"first {sub}: plain LSQR {ms_p:.0f} ms, APLICUR {ms_ps:.0f} ms (all converged: {ok})")
     return {"problems": count, "nrhs": nrhs, "sum_mn": int(sum(m * n for m, n, _ in shapes)),
             "batched_ms": round(ms_b, 1), "sequential_aplicur_ms": round(ms_s, 1),
-            "sequential_plain_ms": round(ms_p, 1), "workers": 8, "all_converged": ok,
+            "plain_subset": sub, "sequential_plain_subset_ms": round(ms_p, 1),
+            "sequential_aplicur_subset_ms": round(ms_ps, 1), "workers": 8, "all_converged": ok,
+            "max_eta": max(i.eta for i in list(infos) + inf_s + inf_p),
             "max_iters_aplicur": max(i.iters for i in inf_s), "max_iters_plain": max(i.iters for i in inf_p)}
 
 
@@ -155,12 +348,15 @@ def bench_adjoint(ap, synth, torch, m=25000, n=500, nrhs=4):
         ms_f, (X, info) = _timed(torch, lambda: ctx.solve(B))
         ms_b, (Z, dB, dA, binfo) = _timed(torch, lambda: ctx.solve_backward(X, B, 2.0 * X))
     with ap.Context(A, precond=False, **opts) as ctx:
-        X0, _ = ctx.solve(B)
+        ms_pf, (X0, pfinfo) = _timed(torch, lambda: ctx.solve(B))
         ms_p, (_, _, _, pinfo) = _timed(torch, lambda: ctx.solve_backward(X0, B, 2.0 * X0))
-    log(f"[bench] adjoint {m}x{n}: forward {ms_f:.0f} ms, backward {ms_b:.0f} ms (eta {binfo.eta:.1e}, "
-        f"{binfo.iters} it), plain backward {ms_p:.0f} ms ({pinfo.iters} it)")
-    return {"m": m, "n": n, "nrhs": nrhs, "forward_ms": round(ms_f, 1), "backward_ms": round(ms_b, 1),
-            "backward_eta": binfo.eta, "backward_iters": binfo.iters, "plain_backward_ms": round(ms_p, 1),
+    log(f"[bench] adjoint {m}x{n}: forward {ms_f:.0f} ms (eta {info.eta:.1e}), backward {ms_b:.0f} ms "
+        f"(eta {binfo.eta:.1e}, {binfo.iters} it); plain LSQR forward {ms_pf:.0f} ms ({pfinfo.iters} it), "
+        f"plain backward {ms_p:.0f} ms ({pinfo.iters} it)")
+    return {"m": m, "n": n, "nrhs": nrhs, "forward_ms": round(ms_f, 1), "forward_eta": info.eta,
+            "backward_ms": round(ms_b, 1), "backward_eta": binfo.eta, "backward_iters": binfo.iters,
+            "plain_forward_ms": round(ms_pf, 1), "plain_forward_iters": pfinfo.iters,
+            "plain_forward_eta": pfinfo.eta, "plain_backward_ms": round(ms_p, 1),
             "plain_backward_iters": pinfo.iters, "rank": info.rank}
 
 
@@ -207,7 +403,7 @@ def bench_multi_rhs(ap, synth, torch, npts=20000, nrhs=16):
 
 def blocked_products(ap, synth, torch, npts=20000, nrhs=16, rounds=20, prec=0):
     """The blocked products alone (A X and A^T U, 16 columns, FP32 RBF kernel
-    on 20000 points; prec 0: FP64 accumulation, 1: FP32 products, 2: BF16
+    on npts points; prec 0: FP64 accumulation, 1: FP32 products, 2: BF16
     products) alternating for `rounds` rounds after a warm-up, event timed,
     then three copies of 256 MiB used to calibrate the hardware counters.
     One JSON line; bytes_A is the matrix as the kernel reads it (FP32, or the
@@ -414,14 +610,14 @@ def schedule_study(ap, synth, torch):
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
-    ap_.add_argument("--steps", type=int, default=3)
+    ap_.add_argument("--steps", type=int, default=5)
     ap_.add_argument("--warmup", type=int, default=1)
     ap_.add_argument("--max-rank", type=int, default=256)
     ap_.add_argument("--no-cpu", action="store_true")
-    ap_.add_argument("--no-compare", action="store_true")
     ap_.add_argument("--products-only", action="store_true")
     ap_.add_argument("--blocked-products", action="store_true",
                      help="only the blocked products (FP32 RBF kernel 20000^2, 16 columns) and the calibration copy")
+    ap_.add_argument("--npts", type=int, default=40000, help="points of the kernel matrix for --blocked-products")
     ap_.add_argument("--blocked-prec", type=int, default=0, choices=(0, 1, 2),
                      help="arithmetic of --blocked-products: 0 FP64 accumulation, 1 FP32, 2 BF16")
     ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
@@ -448,7 +644,7 @@ def main():
     from workloads import synth
 
     if args.blocked_products:
-        blocked_products(ap, synth, torch, prec=args.blocked_prec)
+        blocked_products(ap, synth, torch, npts=args.npts, prec=args.blocked_prec)
         return
     if args.paper_workloads:
         paper_workloads(ap, synth, torch)
@@ -471,145 +667,39 @@ def main():
         print(json.dumps({"full_configs": full}), flush=True)
         return
 
-    t0 = time.time()
-    w = synth.workload(2, 1.0)
-    A, b, mu, block, tol = w.A, w.B, w.mu, w.block, w.tol
-    m, n = A.shape
-    nnz = int(A.nnz)
-    log(f"[bench] workload {m}x{n} nnz={nnz} generated in {time.time() - t0:.1f}s")
-    Ag = ap.CSRMatrix.from_scipy(A, device="cuda", dtype=torch.float64)
-    bg = torch.as_tensor(b, device="cuda")
-
-    # ---- A and A^T products: the LSQR product kernels, HIP events on their launch stream
-    with ap.Context(Ag, precond=False, mu=mu) as ctx:
-        xv = torch.randn(n, device="cuda", dtype=torch.float64)
-        ctx.time_product(xv, trans=False, reps=10)
-        us_a = ctx.time_product(xv, trans=False, reps=PRODUCT_REPS)
-        us_at = ctx.time_product(xv, trans=True, reps=PRODUCT_REPS)
-        # cold caches: 1 GiB read and written before each timed round (the
-        # product's matrix then comes from HBM, not from L2 or the 256 MB
-        # last-level cache that holds it in the LSQR loop)
-        # (not in --products-only runs, whose kernel statistics are the warm loop's)
-        us_a_cold = us_at_cold = float("nan")
-        if not args.products_only:
-            flush = torch.zeros(1 << 28, dtype=torch.int32, device="cuda")
-            us_a_cold = ctx.time_product(xv, trans=False, reps=20, flush=flush)
-            us_at_cold = ctx.time_product(xv, trans=True, reps=20, flush=flush)
-            del flush
-    # measured device-copy rate (1 GiB each way, torch's copy on its current
-    # stream, event-timed there): a measured peak beside the published 8 TB/s
-    copy_gbs = float("nan")
-    if not args.products_only:
-        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            dst.copy_(src)
-        e1.record()
-        torch.cuda.synchronize()
-        copy_gbs = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        del src, dst
-        log(f"[bench] device copy, 1 GiB each way: {copy_gbs:.0f} GB/s (read + write)")
-    bytes_a = spmv_bytes(m, n, nnz)
-    bytes_at = spmv_bytes(n, m, nnz) - n * 8  # A^T kernel stores its output without reading it
-    gbs_a = bytes_a / (us_a * 1e-6) / 1e9
-    gbs_at = bytes_at / (us_at * 1e-6) / 1e9
-    log(f"[bench] A x: {us_a:.2f} us/launch -> {gbs_a:.0f} GB/s; A^T u: {us_at:.2f} us -> {gbs_at:.0f} GB/s")
-    if not args.products_only:
-        log(f"[bench] cold caches: A x {us_a_cold:.2f} us -> {bytes_a / us_a_cold / 1e3:.0f} GB/s; "
-            f"A^T u {us_at_cold:.2f} us -> {bytes_at / us_at_cold / 1e3:.0f} GB/s")
     if args.products_only:
-        big = torch.empty(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
-        dst = torch.empty_like(big)
-        for _ in range(3):
-            dst.copy_(big)
-        torch.cuda.synchronize()
-        print(json.dumps({"us_A": us_a, "us_AT": us_at, "bytes_A": bytes_a, "bytes_AT": bytes_at,
-                          "copy_bytes_each_way": big.numel() * 8}), flush=True)
+        bench_c2(ap, synth, torch, args)
         return
 
-    opts = dict(mu=mu, block=block, tol_ne=tol, seed=7, max_rank=args.max_rank)
-
-    def run_once(precond, precision=0):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        with ap.Context(Ag, precond=precond, precision=precision, **opts) as c:
-            x, info = c.solve(bg)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) * 1e3, x, info
-
-    for i in range(args.warmup):
-        ms, _, info = run_once(True)
-        log(f"[bench] warmup {i}: {ms:.1f} ms rank={info.rank} iters={info.iters} eta={info.eta:.2e}")
-    torch.cuda.synchronize()
-    times, infos = [], []
-    for i in range(args.steps):
-        ms, x, info = run_once(True)
-        times.append(ms)
-        infos.append(info)
-        log(f"[bench] step {i}: {ms:.1f} ms rank={info.rank} phases={info.phases} iters={info.iters} "
-            f"eta={info.eta:.2e} (sketch {info.t_sketch_ms:.1f}, cur {info.t_cur_ms:.1f}, "
-            f"precond {info.t_precond_ms:.1f}, lsqr {info.t_lsqr_ms:.1f} ms)")
-    ms_step = sum(times) / len(times)
-    info = infos[-1]
-    if info.status != 0 or info.eta > tol:
-        log(f"[bench] WARNING: the solve did not reach eta <= {tol:g} (status {info.status})")
-
-    compare = {}
-    plain_iters = None
-    if not args.no_compare:
-        for name, pc, prec in (("plain_lsqr_f64", False, 0), ("plain_lsqr_f32_ir", False, 1),
-                               ("aplicur_f32_ir", True, 1)):
-            run_once(pc, prec)
-            ms, _, inf = run_once(pc, prec)
-            compare[name] = {"ms": round(ms, 2), "iters": inf.iters, "phases": inf.phases, "eta": inf.eta,
-                             "rank": inf.rank}
-            if name == "plain_lsqr_f64":
-                plain_iters = inf.iters
-            log(f"[bench] {name}: {ms:.1f} ms iters={inf.iters} phases={inf.phases} eta={inf.eta:.2e}")
-
-    batched = adjoint = multi = None
+    head = bench_headline(ap, synth, torch, args)
+    torch.cuda.empty_cache()
+    c2 = bench_c2(ap, synth, torch, args)
+    torch.cuda.empty_cache()
+    adjoint = batched = None
     if not args.no_extensions:
-        batched = bench_batched(ap, synth, torch)
-        adjoint = bench_adjoint(ap, synth, torch)
-        multi = bench_multi_rhs(ap, synth, torch)
-
+        adjoint = bench_adjoint(ap, synth, torch, m=100000, n=2000, nrhs=32)
+        torch.cuda.empty_cache()
+        batched = bench_batched(ap, synth, torch, count=64, scale=1.0, nrhs=8, plain_subset=8)
+        torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(A, b, mu, plain_iters or 8400)
+        cpu = cpu_baseline_dense_kernel()
         log(f"[bench] cpu baseline: {cpu['value']:.0f} ms ({cpu['sample']})")
 
-    traffic = counter_traffic()
     out = {
-        "metric": METRIC, "value": round(ms_step, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": False,
+        "metric": METRIC, "value": head["ms_per_step"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": (f"APLICUR solve to eta<=1e-8 (sketch+CUR+preconditioned LSQR), CSR {m}x{n}, "
-                                f"10 random columns per row, column scaling 1e-6, mu={mu:g}, block {block}, "
-                                f"rank cap {args.max_rank}, FP64"),
-                   "m": m, "n": n, "nnz": nnz, "mu": mu, "block": block, "tol_ne": tol,
-                   "max_rank": args.max_rank},
-        "roofline": {"bound": "hbm", "achieved": round(gbs_a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs_a / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_fwd_sell_lx (A x - y, SELL-64 copy of A, x resident in LDS, FP64)",
-                     "bytes_per_launch": int(bytes_a), "us_per_launch": round(us_a, 3)},
+        "config": head["config"],
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "aplicur": {"rank": info.rank, "phases": info.phases, "iters": info.iters, "outer": info.outer,
-                    "rebuilds": info.rebuilds, "eta": info.eta, "t_sketch_ms": round(info.t_sketch_ms, 2),
-                    "t_cur_ms": round(info.t_cur_ms, 2), "t_precond_ms": round(info.t_precond_ms, 2),
-                    "t_lsqr_ms": round(info.t_lsqr_ms, 2)},
-        "compare": compare or None,
-        "batched": batched,
+        "seeds": head["seeds"],
+        "aplicur": head["aplicur"],
+        "compare": head["compare"],
+        "products": head["products"],
+        "csr_200000x20000": c2,
         "adjoint": adjoint,
-        "multi_rhs": multi,
-        "matvec": {"A_us": round(us_a, 3), "A_GBs": round(gbs_a, 1), "AT_us": round(us_at, 3),
-                   "AT_GBs": round(gbs_at, 1), "AT_bytes": int(bytes_at),
-                   "A_us_cold": round(us_a_cold, 3), "A_GBs_cold": round(bytes_a / us_a_cold / 1e3, 1),
-                   "AT_us_cold": round(us_at_cold, 3), "AT_GBs_cold": round(bytes_at / us_at_cold / 1e3, 1),
-                   "copy_GBs": round(copy_gbs, 1), "A_frac_of_copy": round(gbs_a / copy_gbs, 4),
-                   "AT_frac_of_copy": round(gbs_at / copy_gbs, 4)},
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -202,12 +202,12 @@ int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* ws, siz
  * aplicur_sketch, but row-major dense or CSR (APLICUR_DENSE_COL: E_INVALID);
  * opts.precond must be 1 or 2 and opts.sketch 0.  Scratch (the sketch's rows
  * and signs; for CSR A the validation flag and the CSR of A^T; for dense A the
- * row-chunk partials when more than one chunk fits) lives in a fixed array of
- * 64 MiB per device that the library holds until the process ends; an input
- * whose scratch would exceed it is rejected (E_INVALID, the message gives the
- * bytes needed) before any device work.  A dense sketch that fits fewer row
- * chunks than aplicur_sketch uses sums its chunks in another order (equal to
- * rounding).  Calls on one device share that array: calls that overlap on
+ * inverse of the embedding, 4 xi m bytes and a few per target row) lives in
+ * a fixed array of 64 MiB per device that the library holds until the
+ * process ends; an input whose scratch would exceed it is rejected
+ * (E_INVALID, the message gives the bytes needed) before any device work.
+ * The result equals aplicur_sketch's bit for bit (same kernels, same
+ * summation order).  Calls on one device share that array: calls that overlap on
  * one GPU (different streams, or different host threads) race; serialise
  * them.  CSR validation reads one flag back (the call synchronises the
  * stream).  Errors: E_INVALID, E_HIP.                                       */
@@ -319,6 +319,26 @@ int aplicur_time_product(aplicur_ctx* ctx, int32_t trans, const double* x, doubl
 int aplicur_time_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx, int32_t k, double* Y,
                         int64_t ldy, int32_t prec, int32_t reps, void* flush, int64_t flush_bytes, void* stream,
                         double* us_per_launch);
+
+/* Event timing of the blocked product kernel inside solves (measurement of
+ * the several-right-hand-side path of Sec. 2.2's products, dense A): while
+ * enabled, every dispatch of the row-streaming product kernel, by any
+ * context of this process on the device that was current at enable time,
+ * carries a HIP event pair taking the kernel's own start and end (at most
+ * 65536 launches between reads; later ones are counted as untimed).  The
+ * events are created on first use and reused, so a warm-up with timing on
+ * keeps event creation out of a later timed region.  enable = 0 stops
+ * timing and keeps the record.  Switching device needs an empty record.
+ * Errors: E_INVALID, E_HIP.                                                  */
+int aplicur_prof_products(int32_t enable);
+
+/* Reads and clears the record of aplicur_prof_products, waiting for the
+ * recorded launches: per kind k (0: A X, 1: A^T X with FP64 accumulation;
+ * 2, 3: the same with FP32 products; 4, 5: with BF16 products) the timed
+ * launches, their summed kernel durations in microseconds, and the launches
+ * left untimed.  All three arrays (host) hold 6 entries.
+ * Errors: E_INVALID, E_HIP.                                                  */
+int aplicur_prof_read(int64_t* launches, double* total_us, int64_t* untimed);
 
 /* Read internal state back to host memory (tests and diagnostics).
  * what: 1 sketch Y (s x n row-major doubles), 2 sketch rows (m x xi int32;

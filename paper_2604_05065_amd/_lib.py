@@ -43,7 +43,7 @@ class Info(C.Structure):
 
 EXPORTS = ["aplicur_opts_default", "aplicur_workspace_bytes", "aplicur_sketch", "aplicur_sketch_noalloc", "aplicur_solve", "aplicur_solve_batched",
            "aplicur_solve_backward", "aplicur_matvec", "aplicur_matmat", "aplicur_time_product", "aplicur_time_matmat", "aplicur_precond_apply", "aplicur_ctx_query", "aplicur_ctx_destroy",
-           "aplicur_last_error", "aplicur_version"]
+           "aplicur_prof_products", "aplicur_prof_read", "aplicur_last_error", "aplicur_version"]
 
 _lib = None
 
@@ -83,6 +83,10 @@ def load():
     lib.aplicur_precond_apply.restype = C.c_int
     lib.aplicur_time_product.argtypes = [vp, i32, dp, dp, i32, vp, i64, vp, C.POINTER(C.c_double)]
     lib.aplicur_time_product.restype = C.c_int
+    lib.aplicur_prof_products.argtypes = [i32]
+    lib.aplicur_prof_products.restype = C.c_int
+    lib.aplicur_prof_read.argtypes = [C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(i64)]
+    lib.aplicur_prof_read.restype = C.c_int
     lib.aplicur_ctx_query.argtypes = [vp, i32, vp, C.c_size_t]
     lib.aplicur_ctx_query.restype = i64
     lib.aplicur_ctx_destroy.argtypes = [vp]

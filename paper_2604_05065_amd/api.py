@@ -278,6 +278,26 @@ def sketch_noalloc(A, Y=None, **opts):
     return Y
 
 
+PROF_KINDS = ("AX_f64", "ATX_f64", "AX_f32", "ATX_f32", "AX_bf16", "ATX_bf16")
+
+
+def prof_products(enable=True):
+    """Switch event timing of the blocked product kernel inside solves on or
+    off (aplicur_prof_products)."""
+    L.check(L.load().aplicur_prof_products(int(bool(enable))))
+
+
+def prof_read():
+    """Read and clear the product-kernel event record: {kind: (launches,
+    mean microseconds, untimed launches)} for the kinds with any launch."""
+    lib = L.load()
+    n = len(PROF_KINDS)
+    cnt, tot, unt = (C.c_int64 * n)(), (C.c_double * n)(), (C.c_int64 * n)()
+    L.check(lib.aplicur_prof_read(cnt, tot, unt))
+    return {k: (int(cnt[i]), tot[i] / cnt[i] if cnt[i] else float("nan"), int(unt[i]))
+            for i, k in enumerate(PROF_KINDS) if cnt[i] or unt[i]}
+
+
 def sketch(A, **opts):
     return Context(A, **opts)
 

@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libaplicur.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 SOURCES = ["kern_sketch.hip", "kern_gk.hip", "kern_blk.hip", "kern_factor.hip", "kern_blas.hip", "aplicur.cpp",
-           "noalloc.cpp"]
+           "noalloc.cpp", "prof.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-I" + os.path.join(ROCM, "include")]

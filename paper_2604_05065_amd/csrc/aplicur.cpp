@@ -177,7 +177,7 @@ struct Ctx {
   int* lu_piv = nullptr;  // pivots of the blocked LU of the Schur block
   int rank = 0;
   // preconditioner
-  double *Mx = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
+  double *Mx = nullptr, *Mx2 = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
          *pa_part = nullptr, *pa_c = nullptr, *Kc = nullptr, *Kr = nullptr, *pc1 = nullptr, *pc2 = nullptr,
          *M2 = nullptr, *M2t = nullptr;
   int *rr_ptr = nullptr, *rr_idx = nullptr, *rt_ptr = nullptr, *rt_idx = nullptr, *rscratch = nullptr;
@@ -187,6 +187,8 @@ struct Ctx {
   size_t splitk_count = 0;
   PrecDesc prec{};
   bool have_prec = false;
+  int vm_rank = 0;       // rank of the right singular vectors held in Vm (warm start of the next build)
+  long long vm_ld = 0;   // their leading dimension
   double p_target = 0.0, p_pnorm = 1.0, p_sigma_l = 0.0;
   std::vector<double> p_sigma_host;
   // LSQR vectors and state (FP64; FP32 copies for the low-precision phases)
@@ -651,15 +653,14 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
                                    c->S_neg, c->Y, s);
       } else {
         launch_gen_sketch(o->seed, S, m, c->xi, c->S_rows, c->S_neg, s);
-        const int chunks = sketch_dense_chunks(m, n);
         bool owned = false;
-        double* part = (double*)c->arena.transient(sizeof(double) * (size_t)chunks * S * n, owned);
+        void* part = c->arena.transient(sketch_dense_scratch(m, S, c->xi), owned);
         if (op.f64)
           launch_sketch_dense<double>((const double*)op.val, m, n, op.ld, S, c->xi, c->S_rows, c->S_neg, c->Y,
-                                      part, chunks, s);
+                                      part, s);
         else
           launch_sketch_dense<float>((const float*)op.val, m, n, op.ld, S, c->xi, c->S_rows, c->S_neg, c->Y,
-                                     part, chunks, s);
+                                     part, s);
         APL_HIP(hipStreamSynchronize(s));
         if (owned) {
           SyncGuard g(g_capture_mu);
@@ -692,6 +693,7 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
       c->P2 = c->arena.alloc<double>((size_t)L * b);
       c->status_dev = c->arena.alloc<int>(4);
       c->Mx = c->arena.alloc<double>((size_t)L * Lp);
+      if (c->o.precond != 2) c->Mx2 = c->arena.alloc<double>((size_t)L * Lp);  // the Jacobi rounds' second buffer
       c->Vm = c->arena.alloc<double>((size_t)Lp * Lp);
       c->sigma = c->arena.alloc<double>(Lp);
       c->Kc = c->arena.alloc<double>((size_t)L * L);
@@ -1014,9 +1016,12 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
 // the core part of the preconditioned Gram, diag(sigma_hat / Lambda) V^T (M^T
 // M + delta^2 I) V diag(sigma_hat / Lambda), is sigma_hat^2 (I + E) with that
 // off-diagonal E, so its singular values lie within sqrt(1 +- jacobi_tol) of
-// the exact-SVD value sigma_hat.  Pairs below kJacobiSkip are not rotated
-// (their entries add at most l kJacobiSkip to the norm).
-constexpr double kJacobiSkip = 1e-9;
+// the exact-SVD value sigma_hat.  A block pair whose scaled entries are all
+// at most skip = jacobi_tol / (4 l) (and at most kJacobiSkip) is not rotated:
+// such entries still count in the stopping test, and all l^2 of them
+// together are at most jacobi_tol / 4 in Frobenius norm, so skipping them
+// cannot keep the sweeps from reaching the test.
+constexpr double kJacobiSkip = 1e-6;
 // Largest diagonal ratio of T_R for which the one-product form M2 is used.
 constexpr double kM2MaxDiagRatio = 1e3;
 
@@ -1090,9 +1095,27 @@ static void build_precond(Ctx& c, hipStream_t s) {
   fill(c.Mx, (long long)L * lp, 0.0, s);
   gemm(c, Op::N, Op::T, l, l, l, 1.0, c.U, L, c.TR, L, 0.0, c.Kr, l);
   gemm(c, Op::N, Op::N, l, l, l, 1.0, c.TC, L, c.Kr, l, 0.0, c.Mx, L);
-  set_identity(c.Vm, lp, lp, s);
+  // Warm start: the Jacobi iteration accepts any orthogonal starting basis V0
+  // (it computes M V0 times rotations).  The previous build's right singular
+  // vectors V_old (rank l_old) are coordinates in the leading l_old columns of
+  // Q_R, which augmentQR keeps, and the dominant directions of the grown CUR
+  // stay close to them; V0 = blkdiag(V_old, I) starts the sweeps nearly
+  // converged in those directions.  X0 = M V0 replaces the first l_old columns.
+  const int lo = (c.vm_rank > 0 && c.vm_rank < l) ? c.vm_rank : 0;
+  if (lo > 0) {
+    copy_block(c.Vm, c.vm_ld, c.Kc, lo, lo, lo, 1.0, s);  // V_old (lo x lo, ld lo)
+    set_identity(c.Vm, lp, lp, s);
+    copy_block(c.Kc, lo, c.Vm, lp, lo, lo, 1.0, s);
+    gemm(c, Op::N, Op::N, l, lo, lo, 1.0, c.Mx, L, c.Kc, lo, 0.0, c.Kr, l);  // M(:, 0:lo) V_old
+    copy_block(c.Kr, l, c.Mx, L, l, lo, 1.0, s);
+  } else {
+    set_identity(c.Vm, lp, lp, s);
+  }
   c.sweep_hist.push_back(
-      jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.jac_part, c.delta * c.delta, c.jacobi_tol, kJacobiSkip, 40, s));
+      jacobi_svd(c.Mx, c.Mx2, L, l, lp, c.Vm, lp, c.sigma, c.jac_part, c.delta * c.delta, c.jacobi_tol,
+                 std::min(kJacobiSkip, c.jacobi_tol / (4.0 * l)), 40, s));
+  c.vm_rank = l;
+  c.vm_ld = lp;
   precond_scalars(c.sigma, l, c.delta, c.d, c.pinfo, s);
   if (c.prec.implicit) {
     // K = T_R^{-1} V_M (column-major, ld l: the row-major K^T) and K row-major
@@ -1365,6 +1388,7 @@ static void outer_loop(Ctx& c, hipStream_t s, SolveLog& lg, Phases&& phases) {
   c.rebuild_hist.clear();
   c.sweep_hist.clear();
   c.have_prec = false;
+  c.vm_rank = 0;
   APL_HIP(hipMemcpyAsync(c.E, c.Y, sizeof(double) * (size_t)c.s * c.n, hipMemcpyDeviceToDevice, s));
   double d_cur = INFINITY;
   for (;;) {
@@ -1618,10 +1642,9 @@ static BlkPrec blk_prec(Ctx& c, hipStream_t s) {
   const int l = c.prec.ell;
   APL_REQUIRE(b.Vt, "blocked P buffers missing");
   if (b.vt_gen != c.prec_gen) {
-    // V^T (l x n row-major) is V = Q_R V_M column-major
-    const int jw2 = 2 * jacobi_block_width();
-    const int lp = ((l + jw2 - 1) / jw2) * jw2;
-    gemm(c, Op::N, Op::N, c.n, l, l, 1.0, c.Q, c.n, c.Vm, lp, 0.0, b.Vt, b.ldvt);
+    // V^T (l x n row-major): the transpose of the explicit V (n x l row-major)
+    // the build formed, so both layouts hold the same values
+    transpose_rect<double>(c.Vhat, c.n, l, l, b.Vt, b.ldvt, s);
     b.vt_gen = c.prec_gen;
   }
   BlkPrec P{};

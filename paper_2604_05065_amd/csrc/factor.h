@@ -89,7 +89,9 @@ int jacobi_block_width();
 // device doubles of scratch (one partial per pair and round, summed in a
 // fixed order, so the sweep count does not depend on the order in which
 // workgroups finish).  Returns the number of sweeps.
-int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
+// X2: a second n x npad buffer (ld ldx): the rounds alternate between X and
+// X2; on return the rotated X is in either, and X2's old contents are lost.
+int jacobi_svd(double* X, double* X2, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
                double* sq_part, double delta2, double tol_f, double skip, int max_sweeps, hipStream_t s);
 long long jacobi_part_words(int npad);
 void precond_scalars(const double* sigma, int l, double delta, double* d, double* info, hipStream_t s);

@@ -30,7 +30,9 @@ constexpr int kGPad = 2;      // LDS row padding (doubles)
 // Registers of one stage of a 128 x 16 operand tile.  Element (i, kk) of the
 // operand (i < 128 the tile row, kk < 16 the stage's k) lives at X[i + kk ld]
 // (KC = false: rows contiguous) or X[kk + i ld] (KC = true: k contiguous).
-// Out-of-range entries are 0 (their addresses are clamped into range).
+// tile_load only issues the loads (addresses clamped into range) so that
+// they stay in flight during the MFMAs of the current stage; tile_store
+// zeroes the out-of-range entries when it writes the stage to LDS.
 template <bool KC, class T>
 __device__ __forceinline__ void tile_load(const T* __restrict__ X, long long ld, long long rows, long long i0,
                                           long long k0, long long kend, T (&r)[8]) {
@@ -38,39 +40,32 @@ __device__ __forceinline__ void tile_load(const T* __restrict__ X, long long ld,
   if (!KC) {
     const long long kk = k0 + t / 16;
     const long long ib = i0 + (t % 16) * 8;
-    const bool kin = kk < kend;
-    const T* p = X + (kin ? kk : 0) * ld;
+    const T* p = X + (kk < kend ? kk : 0) * ld;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const bool in = kin && ib + e < rows;
-      const T v = p[in ? ib + e : 0];
-      r[e] = in ? v : (T)0;
-    }
+    for (int e = 0; e < 8; ++e) r[e] = p[ib + e < rows ? ib + e : 0];
   } else {
     const long long i = i0 + t / 2;
     const long long kb = k0 + (t % 2) * 8;
-    const bool iin = i < rows;
-    const T* p = X + (iin ? i : 0) * ld;
+    const T* p = X + (i < rows ? i : 0) * ld;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const bool in = iin && kb + e < kend;
-      const T v = p[in ? kb + e : 0];
-      r[e] = in ? v : (T)0;
-    }
+    for (int e = 0; e < 8; ++e) r[e] = p[kb + e < kend ? kb + e : 0];
   }
 }
 
 template <bool KC, class T, int LD>
-__device__ __forceinline__ void tile_store(T (*Xs)[LD], const T (&r)[8]) {
+__device__ __forceinline__ void tile_store(T (*Xs)[LD], const T (&r)[8], long long rows, long long i0, long long k0,
+                                           long long kend) {
   const int t = threadIdx.x;
   if (!KC) {
     const int kk = t / 16, ib = (t % 16) * 8;
+    const bool kin = k0 + kk < kend;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) Xs[kk][ib + e] = r[e];
+    for (int e = 0; e < 8; ++e) Xs[kk][ib + e] = (kin && i0 + ib + e < rows) ? r[e] : (T)0;
   } else {
     const int i = t / 2, kb = (t % 2) * 8;
+    const bool iin = i0 + i < rows;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) Xs[kb + e][i] = r[e];
+    for (int e = 0; e < 8; ++e) Xs[kb + e][i] = (iin && k0 + kb + e < kend) ? r[e] : (T)0;
   }
 }
 
@@ -99,8 +94,8 @@ __global__ void __launch_bounds__(kGThreads)
   }
   for (long long k0 = kbeg; k0 < kend; k0 += kGKs) {
     __syncthreads();
-    tile_store<TA, double, kGM + kGPad>(As, ra);
-    tile_store<!TB, double, kGM + kGPad>(Bs, rb);
+    tile_store<TA, double, kGM + kGPad>(As, ra, M, i0, k0, kend);
+    tile_store<!TB, double, kGM + kGPad>(Bs, rb, N, j0, k0, kend);
     __syncthreads();
     if (k0 + kGKs < kend) {
       tile_load<TA>(A, lda, M, i0, k0 + kGKs, kend, ra);
@@ -417,18 +412,19 @@ constexpr int kSKs = 32;  // reduction depth per stage
 template <class T>
 __device__ __forceinline__ void sk_load(const T* __restrict__ X, long long ld, long long rows, long long i0,
                                         long long k0, long long kend, T (&r)[16]) {
-  // 128 x 32 tile, thread t: kk = t / 8, rows i0 + (t % 8) * 16 + e
+  // 128 x 32 tile, thread t: kk = t / 8, rows i0 + (t % 8) * 16 + e; loads
+  // only (clamped addresses); sk_mask zeroes the out-of-range entries later
   const int t = threadIdx.x;
   const long long kk = k0 + t / 8;
   const long long ib = i0 + (t % 8) * 16;
-  const bool kin = kk < kend;
-  const T* p = X + (kin ? kk : 0) * ld;
+  const T* p = X + (kk < kend ? kk : 0) * ld;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const bool in = kin && ib + e < rows;
-    const T v = p[in ? ib + e : 0];
-    r[e] = in ? v : (T)0;
-  }
+  for (int e = 0; e < 16; ++e) r[e] = p[ib + e < rows ? ib + e : 0];
+}
+
+__device__ __forceinline__ bool sk_in(long long rows, long long i0, long long k0, long long kend, int e) {
+  const int t = threadIdx.x;
+  return k0 + t / 8 < kend && i0 + (t % 8) * 16 + e < rows;
 }
 
 template <bool BF16>
@@ -456,8 +452,8 @@ __global__ void __launch_bounds__(kGThreads)
       const int t = threadIdx.x, kk = t / 8, ib = (t % 8) * 16;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        As[kk][ib + e] = ra[e];
-        Bs[kk][ib + e] = (float)rs[e];
+        As[kk][ib + e] = sk_in(n, i0, k0, m, e) ? ra[e] : 0.0f;
+        Bs[kk][ib + e] = sk_in(srows, j0, k0, m, e) ? (float)rs[e] : 0.0f;
       }
     }
     __syncthreads();

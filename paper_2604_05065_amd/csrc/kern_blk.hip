@@ -20,6 +20,7 @@
 #include <hip/hip_ext.h>
 
 #include "blk.h"
+#include "prof.h"
 
 #include <cstdint>
 #include <type_traits>
@@ -823,16 +824,19 @@ static void blk_prod(const BlkOp& A, bool trans, const V* in, int kp, V* out, hi
   const long long rows = trans ? A.n : A.m, cols = trans ? A.m : A.n, ld = trans ? A.ldt : A.ld;
   const void* M = trans ? A.At : A.A;
   const int S = trans ? A.Sn : A.Sm;
-  if constexpr (std::is_same<V, float>::value) {
+  constexpr bool f32 = std::is_same<V, float>::value;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  prof_take((trans ? 1 : 0) + (f32 ? (A.A16 ? 4 : 2) : 0), &e0, &e1);
+  if constexpr (f32) {
     if (A.A16) {
-      rows_gemm16(trans ? A.At16 : A.A16, rows, cols, in, kp, out, S, s);
+      rows_gemm16(trans ? A.At16 : A.A16, rows, cols, in, kp, out, S, s, e0, e1);
       return;
     }
   }
   if (A.f64)
-    rows_gemm<double, V, V>((const double*)M, rows, cols, ld, in, kp, out, S, s);
+    rows_gemm<double, V, V>((const double*)M, rows, cols, ld, in, kp, out, S, s, e0, e1);
   else
-    rows_gemm<float, V, V>((const float*)M, rows, cols, ld, in, kp, out, S, s);
+    rows_gemm<float, V, V>((const float*)M, rows, cols, ld, in, kp, out, S, s, e0, e1);
 }
 
 // c = d .* V^T z, then pq = V c (S2 planes).

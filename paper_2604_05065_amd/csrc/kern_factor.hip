@@ -605,8 +605,13 @@ __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, i
   }
 }
 
-__global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, int rows, double* Vm,
-                                                         long long ldv, int vrows, int nblk, int round,
+// Two workgroups per pair (blockIdx.x = 2 pair + half): both form the same
+// Gram matrix and rotation from X (bitwise the same arithmetic); half 0
+// writes the rotated columns of X to Xo (X and Xo alternate between rounds,
+// so no workgroup reads a column another one is writing), half 1 rotates the
+// columns of V in place.
+__global__ void __launch_bounds__(kJT) k_jacobi_round(const double* X, double* Xo, long long ldx, int rows,
+                                                         double* Vm, long long ldv, int vrows, int nblk, int round,
                                                          double* sq_part, double d2, double skip) {
   __shared__ double G[2][kJP][kJP + 1];  // double-buffered rotations
   __shared__ double Q[2][kJP][kJP + 1];
@@ -614,8 +619,9 @@ __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, 
   __shared__ double cs[kJP], sn[kJP];    // per index: its pair's rotation
   __shared__ int mate[kJP], lowr[kJP];   // partner index; 1 if the index is the pair's p
   __shared__ double wmax[kJT / kWave], wsq[kJT / kWave];
+  const int pair = blockIdx.x / 2, half = blockIdx.x % 2;
   int a, b;
-  pair_of(round, nblk, blockIdx.x, a, b);
+  pair_of(round, nblk, pair, a, b);
   int col[2] = {a * kJW, b * kJW};
   const int tid = threadIdx.x;
   const int wave = tid / kWave, lane = tid % kWave;
@@ -684,8 +690,16 @@ __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, 
     block_off = fmax(block_off, wmax[w]);
     block_sq += wsq[w];
   }
-  if (tid == 0) sq_part[blockIdx.x] = block_sq;
-  if (block_off <= skip) return;  // uniform
+  if (tid == 0 && half == 0) sq_part[pair] = block_sq;
+  if (block_off <= skip) {  // uniform: the pair's columns go to Xo unrotated
+    if (half == 0)
+      for (int e = tid; e < rows * kJP; e += kJT) {
+        const int r = e % rows, cc = e / rows;
+        const long long at = (long long)r + (long long)(col[cc / kJW] + cc % kJW) * ldx;
+        Xo[at] = X[at];
+      }
+    return;
+  }
   // 2) cyclic Jacobi on G (kJP x kJP): kJP - 1 rounds of kJW disjoint
   //    rotations (round-robin); each round G <- J^T G J and Q <- Q J computed
   //    entry by entry from the previous buffer.
@@ -740,22 +754,23 @@ __global__ void __launch_bounds__(kJT) k_jacobi_round(double* X, long long ldx, 
       __syncthreads();
     }
   }
-  // 3) apply Q to the columns of X and of V: each thread's rows are loaded
-  //    together before the products.
-  for (int pass = 0; pass < 2; ++pass) {
-    double* M = pass == 0 ? X : Vm;
-    const long long ld = pass == 0 ? ldx : ldv;
-    const int nr = pass == 0 ? rows : vrows;
+  // 3) apply Q to the columns of X (half 0, into Xo) or of V (half 1, in
+  //    place): each thread's rows are loaded together before the products.
+  {
+    const double* Mi = half == 0 ? X : Vm;
+    double* Mo = half == 0 ? Xo : Vm;
+    const long long ld = half == 0 ? ldx : ldv;
+    const int nr = half == 0 ? rows : vrows;
     for (int r = tid; r < nr; r += kJT) {
       double in[kJP];
 #pragma unroll
-      for (int cc = 0; cc < kJP; ++cc) in[cc] = M[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld];
+      for (int cc = 0; cc < kJP; ++cc) in[cc] = Mi[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld];
 #pragma unroll 4
       for (int cc = 0; cc < kJP; ++cc) {
         double acc = 0.0;
 #pragma unroll
         for (int t = 0; t < kJP; ++t) acc += in[t] * Q[cur][t][cc];
-        M[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld] = acc;
+        Mo[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld] = acc;
       }
     }
   }
@@ -782,17 +797,21 @@ __global__ void __launch_bounds__(kBlock) k_sum_fixed(const double* part, int co
   if (threadIdx.x == 0) out[0] = v;
 }
 
-int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
+int jacobi_svd(double* X, double* X2, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
                double* sq_part, double delta2, double tol_f, double skip, int max_sweeps, hipStream_t s) {
   // X: n x npad (columns n..npad-1 zero), Vm: npad x npad, set to I by the caller.
   const int nblk = npad / kJW;
   const int npairs = nblk / 2, rounds = nblk - 1;
   double* sum_dev = sq_part + (long long)rounds * npairs;
+  double* buf[2] = {X, X2};
+  int cur = 0;
   int sweeps = 0;
   for (; sweeps < max_sweeps; ++sweeps) {
-    for (int r = 0; r < rounds; ++r)
-      hipLaunchKernelGGL(k_jacobi_round, dim3(npairs), dim3(kJT), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
-                         sq_part + (long long)r * npairs, delta2, skip);
+    for (int r = 0; r < rounds; ++r) {
+      hipLaunchKernelGGL(k_jacobi_round, dim3(2 * npairs), dim3(kJT), 0, s, (const double*)buf[cur], buf[cur ^ 1], ldx,
+                         n, Vm, ldv, npad, nblk, r, sq_part + (long long)r * npairs, delta2, skip);
+      cur ^= 1;
+    }
     hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kBlock), 0, s, (const double*)sq_part, rounds * npairs, sum_dev);
     double sum_sq = 0.0;
     APL_HIP(hipMemcpyAsync(&sum_sq, sum_dev, sizeof(sum_sq), hipMemcpyDeviceToHost, s));
@@ -803,7 +822,7 @@ int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long 
       break;
     }
   }
-  hipLaunchKernelGGL(k_col_norms, dim3(n), dim3(kBlock), 0, s, X, ldx, n, n, sigma);
+  hipLaunchKernelGGL(k_col_norms, dim3(n), dim3(kBlock), 0, s, (const double*)buf[cur], ldx, n, n, sigma);
   return sweeps;
 }
 

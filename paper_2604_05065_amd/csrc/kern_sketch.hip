@@ -315,6 +315,7 @@ __global__ void __launch_bounds__(kWave) k_sketch_csr(const int* t_ptr, const in
                                                       const T* t_val, long long n, int s, int xi,
                                                       const uint16_t* rows, const uint8_t* negmask,
                                                       double scale, double* Y) {
+#pragma clang fp contract(off)
   extern __shared__ double lds[];  // s x 64
   const int l = threadIdx.x;
   const long long j = blockIdx.x * (long long)kWave + l;
@@ -349,111 +350,203 @@ template void launch_sketch_csr<double>(const int*, const int*, const double*, l
                                         const uint16_t*, const uint8_t*, double*, hipStream_t);
 
 // ---------------------------------------------------------------- sketch, dense A
-// Workgroup (strip, chunk) covers columns [64 strip, 64 strip + 64) and a chunk
-// of rows; the s x 64 strip of Y lives in LDS (FP64, rows padded to 65 against
-// bank conflicts).  Wave w owns the strip's columns 8w .. 8w + 7, and lane
-// (c, t) = (lane % 8, lane / 8) adds the row's contribution to its t-th target
-// row of Y in column 8w + c, as an LDS atomic add (no return value, so the
-// adds of consecutive rows do not wait for each other).  The targets of one
-// row are distinct, so one wave instruction never adds to a cell twice; a
-// wave's LDS operations complete in order and no two waves share a column, so
-// every cell is summed in row order.  Each wave loads
-// kSkB rows' values, targets and signs before using them and the waves run
-// without barriers, so several batches of the strip are in flight per CU.  The
-// chunk's strip goes to a partial buffer that a second kernel sums over chunks
-// in order.
-constexpr int kSkT = 512;        // threads per workgroup (8 waves x 8 columns)
-template <class T>
-constexpr int kSkB = sizeof(T) == 4 ? 64 : 32;  // rows per batch (registers)
-constexpr int kSkLd = kWave + 1; // LDS row stride of the Y strip (doubles)
+// Y(h, :) = sum over the rows i of A that S sends to target row h of
+// +-scale A(i, :), the rows taken in increasing i: each entry is the same
+// row-order sum of the same rounded terms as in the CSR sketch.  Three small
+// kernels first build the inverse of the embedding (for every target row h,
+// the list of (i, sign) in increasing i, as a counting sort over 256-row
+// chunks of A), then one wave per (h, 256-column strip) accumulates its
+// strip in FP64 registers, reading the rows of its list.  Each row of A is
+// read by the xi waves of its targets; the workgroups of one strip go to one
+// XCD (workgroup ids reach the XCDs round robin), whose waves walk their lists
+// in step, so the rows they share are read from HBM once and from L2 after.
+constexpr int kInvRows = 256;          // rows of A per chunk of the inverse map
+constexpr int kSgW = 4;                // waves per gather workgroup (one target row each)
+constexpr int kSgCols = 4 * kWave;     // columns per strip (four per lane)
+constexpr int kSgU = 8;                // rows in flight per wave
+constexpr int kXcds = 8;
 
-template <class T>
-__global__ void __launch_bounds__(kSkT) k_sketch_dense(const T* A, long long m, long long n,
-                                                       long long ld, int s, int xi,
-                                                       const uint16_t* rows,
-                                                       const uint8_t* negmask, double scale,
-                                                       long long rows_per_chunk, double* part) {
-  extern __shared__ double lds[];  // s x kSkLd
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int cl = wave * 8 + lane % 8, t = lane / 8;
-  const long long j = blockIdx.x * (long long)kWave + cl;
-  const long long i0 = blockIdx.y * rows_per_chunk;
-  const long long i1 = min(m, i0 + rows_per_chunk);
-  for (int h = threadIdx.x; h < s * kSkLd; h += kSkT) lds[h] = 0.0;
+struct SketchInv {
+  int* cnt;   // nchunk x s: per-chunk counts, then their exclusive prefix over chunks
+  int* tot;   // s: list lengths
+  int* ptr;   // s + 1: list offsets
+  int* list;  // m xi: 2 i + (1 if the sign is negative), grouped by target row
+};
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static SketchInv carve_inv(void* scratch, long long m, int s, int xi) {
+  const long long nchunk = (m + kInvRows - 1) / kInvRows;
+  char* p = (char*)scratch;
+  SketchInv v;
+  v.cnt = (int*)p;
+  p += al256(sizeof(int) * (size_t)nchunk * s);
+  v.tot = (int*)p;
+  p += al256(sizeof(int) * (size_t)s);
+  v.ptr = (int*)p;
+  p += al256(sizeof(int) * (size_t)(s + 1));
+  v.list = (int*)p;
+  return v;
+}
+
+size_t sketch_dense_scratch(long long m, int s, int xi) {
+  const long long nchunk = (m + kInvRows - 1) / kInvRows;
+  return al256(sizeof(int) * (size_t)nchunk * s) + al256(sizeof(int) * (size_t)s) +
+         al256(sizeof(int) * (size_t)(s + 1)) + al256(sizeof(int) * (size_t)m * xi);
+}
+
+// count of target h among the chunk's rows, for every h < s
+__global__ void __launch_bounds__(kBlock) k_inv_count(const uint16_t* rows, long long m, int s, int xi, int* cnt) {
+  __shared__ uint16_t tg[kInvRows * 8];
+  const long long i0 = blockIdx.x * (long long)kInvRows;
+  const int ne = (int)min((long long)kInvRows, m - i0) * xi;
+  for (int e = threadIdx.x; e < ne; e += kBlock) tg[e] = rows[i0 * xi + e];
   __syncthreads();
-  const bool act = j < n && t < xi;
-  const long long jc = j < n ? j : n - 1;
-  const int tc = t < xi ? t : 0;
-  constexpr int B = kSkB<T>;
-  for (long long ib = i0; ib < i1; ib += B) {
-    T a[B];
-    int h[B];
-    unsigned sg[B / 4];
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const long long ii = min(ib + u, i1 - 1);
-      a[u] = A[ii * ld + jc];
-      h[u] = rows[ii * xi + tc];
-    }
-#pragma unroll
-    for (int q = 0; q < B / 4; ++q) {
-      unsigned w4 = 0;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) w4 |= (unsigned)negmask[min(ib + 4 * q + e, i1 - 1)] << (8 * e);
-      sg[q] = w4;
-    }
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      if (ib + u < i1 && act) {
-        const double v = (double)a[u] * scale;
-        const bool neg = (sg[u / 4] >> (8 * (u % 4) + t)) & 1u;
-        (void)__hip_atomic_fetch_add(&lds[h[u] * kSkLd + cl], neg ? -v : v, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+  for (int h = threadIdx.x; h < s; h += kBlock) {
+    int c = 0;
+    for (int e = 0; e < ne; ++e) c += tg[e] == h;
+    cnt[blockIdx.x * (long long)s + h] = c;
+  }
+}
+
+// per target row: exclusive prefix of its counts over the chunks, and the total
+__global__ void k_inv_prefix(int* cnt, long long nchunk, int s, int* tot) {
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  if (h >= s) return;
+  int acc = 0;
+  for (long long c = 0; c < nchunk; ++c) {
+    const int v = cnt[c * s + h];
+    cnt[c * s + h] = acc;
+    acc += v;
+  }
+  tot[h] = acc;
+}
+
+// each target row's entries of the chunk, in row order, at its place in the list
+__global__ void __launch_bounds__(kBlock) k_inv_fill(const uint16_t* rows, const uint8_t* negmask, long long m,
+                                                     int s, int xi, const int* cnt, const int* ptr, int* list) {
+  __shared__ uint16_t tg[kInvRows * 8];
+  __shared__ uint8_t ng[kInvRows];
+  const long long i0 = blockIdx.x * (long long)kInvRows;
+  const int nr = (int)min((long long)kInvRows, m - i0), ne = nr * xi;
+  for (int e = threadIdx.x; e < ne; e += kBlock) tg[e] = rows[i0 * xi + e];
+  for (int r = threadIdx.x; r < nr; r += kBlock) ng[r] = negmask[i0 + r];
+  __syncthreads();
+  for (int h = threadIdx.x; h < s; h += kBlock) {
+    int pos = ptr[h] + cnt[blockIdx.x * (long long)s + h];
+    for (int e = 0; e < ne; ++e) {
+      if (tg[e] == h) {
+        const int r = e / xi, t = e - r * xi;
+        list[pos++] = (int)(2 * (i0 + r)) + ((ng[r] >> t) & 1);
       }
     }
   }
-  __syncthreads();
-  if (j < n) {
-    double* out = part + (long long)blockIdx.y * s * n;
-    for (int hh = t; hh < s; hh += 8) out[(long long)hh * n + j] = lds[hh * kSkLd + cl];
-  }
-}
-
-__global__ void k_sum_chunks(const double* part, long long count, int chunks, double* Y) {
-  long long e = blockIdx.x * (long long)kBlock + threadIdx.x;
-  if (e >= count) return;
-  double acc = 0.0;
-  for (int c = 0; c < chunks; ++c) acc += part[(long long)c * count + e];
-  Y[e] = acc;
-}
-
-int sketch_dense_chunks(long long m, long long n) {
-  long long strips = (n + kWave - 1) / kWave;
-  long long want = (2048 + strips - 1) / strips;
-  long long maxc = (m + 15) / 16;
-  long long c = want < maxc ? want : maxc;
-  return (int)(c < 1 ? 1 : c);
 }
 
 template <class T>
-void launch_sketch_dense(const T* A, long long m, long long n, long long ld, int s, int xi,
-                         const uint16_t* rows, const uint8_t* negmask, double* Y, double* part,
-                         int chunks, hipStream_t st) {
-  long long rpc = (m + chunks - 1) / chunks;
-  size_t lds = sizeof(double) * s * kSkLd;
-  APL_REQUIRE(lds <= 160 * 1024, "sketch dimension too large for the LDS strip");
-  APL_HIP(hipFuncSetAttribute((const void*)k_sketch_dense<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_sketch_dense<T>, dim3(ceil_div(n, kWave), chunks), dim3(kSkT), lds, st, A,
-                     m, n, ld, s, xi, rows, negmask, 1.0 / sqrt((double)xi), rpc, part);
-  long long count = (long long)s * n;
-  hipLaunchKernelGGL(k_sum_chunks, dim3(ceil_div(count, kBlock)), dim3(kBlock), 0, st, part, count,
-                     chunks, Y);
+struct Quad;
+template <>
+struct Quad<float> {
+  float v[4];
+};
+template <>
+struct Quad<double> {
+  double v[4];
+};
+
+// four consecutive elements of a row; VEC: the address is 16-byte aligned
+// (FP32) or the two halves are (FP64), and all four lie inside the row
+template <class T, bool VEC>
+__device__ __forceinline__ Quad<T> load_quad(const T* p, long long j, long long n) {
+  Quad<T> q;
+  if constexpr (VEC) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 f = *(const float4*)(p + j);
+      q.v[0] = f.x; q.v[1] = f.y; q.v[2] = f.z; q.v[3] = f.w;
+    } else {
+      const double2 f0 = *(const double2*)(p + j), f1 = *(const double2*)(p + j + 2);
+      q.v[0] = f0.x; q.v[1] = f0.y; q.v[2] = f1.x; q.v[3] = f1.y;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) q.v[c] = p[min(j + c, n - 1)];
+  }
+  return q;
 }
-template void launch_sketch_dense<float>(const float*, long long, long long, long long, int, int,
-                                         const uint16_t*, const uint8_t*, double*, double*, int,
-                                         hipStream_t);
+
+// kSgU rows of a list (the first cnt of them when TAIL), their loads issued
+// before the first add; the adds go in list order
+template <class T, bool VEC, bool TAIL>
+__device__ __forceinline__ void gather_batch(const T* A, long long ld, long long n, long long jl, const int* lp,
+                                             int cnt, double scale, double (&acc)[4]) {
+#pragma clang fp contract(off)
+  int code[kSgU];
+#pragma unroll
+  for (int u = 0; u < kSgU; ++u) code[u] = lp[TAIL ? min(u, cnt - 1) : u];
+  Quad<T> a[kSgU];
+#pragma unroll
+  for (int u = 0; u < kSgU; ++u) a[u] = load_quad<T, VEC>(A + (long long)(code[u] >> 1) * ld, jl, n);
+#pragma unroll
+  for (int u = 0; u < kSgU; ++u) {
+    if (!TAIL || u < cnt) {
+      const double sc = (code[u] & 1) ? -scale : scale;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] += (double)a[u].v[c] * sc;
+    }
+  }
+}
+
+template <class T, bool VEC>
+__global__ void __launch_bounds__(kSgW * kWave) k_sketch_gather(const T* A, long long n, long long ld, int s,
+                                                                const int* ptr, const int* list, double scale,
+                                                                int strips, int hgroups, double* Y) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x / kXcds;
+  const int strip = (k / hgroups) * kXcds + (int)(blockIdx.x % kXcds);
+  const int h = (k % hgroups) * kSgW + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (strip >= strips || h >= s) return;
+  const int lane = threadIdx.x % kWave;
+  const long long j = (long long)strip * kSgCols + 4 * lane;
+  const long long jl = j < n ? j : 0;  // lanes past the end read a valid quad and store nothing
+  const int p0 = ptr[h], p1 = ptr[h + 1];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int p = p0;
+  for (; p + kSgU <= p1; p += kSgU) gather_batch<T, VEC, false>(A, ld, n, jl, list + p, kSgU, scale, acc);
+  if (p < p1) gather_batch<T, VEC, true>(A, ld, n, jl, list + p, p1 - p, scale, acc);
+  double* y = Y + (long long)h * n;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (j + c < n) y[j + c] = acc[c];
+}
+
+template <class T>
+void launch_sketch_dense(const T* A, long long m, long long n, long long ld, int s, int xi, const uint16_t* rows,
+                         const uint8_t* negmask, double* Y, void* scratch, hipStream_t st) {
+  APL_REQUIRE(m < (1LL << 30), "the dense sparse-sign sketch takes fewer than 2^30 rows");
+  APL_REQUIRE(xi >= 1 && xi <= 8, "xi must be in [1, 8]");
+  const long long nchunk = (m + kInvRows - 1) / kInvRows;
+  const SketchInv v = carve_inv(scratch, m, s, xi);
+  hipLaunchKernelGGL(k_inv_count, dim3((unsigned)nchunk), dim3(kBlock), 0, st, rows, m, s, xi, v.cnt);
+  hipLaunchKernelGGL(k_inv_prefix, dim3(ceil_div(s, kBlock)), dim3(kBlock), 0, st, v.cnt, nchunk, s, v.tot);
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kBlock), 0, st, (const int*)v.tot, s, v.ptr);
+  hipLaunchKernelGGL(k_inv_fill, dim3((unsigned)nchunk), dim3(kBlock), 0, st, rows, negmask, m, s, xi,
+                     (const int*)v.cnt, (const int*)v.ptr, v.list);
+  if (n == 0) return;
+  const int strips = (int)ceil_div(n, kSgCols), hgroups = (int)ceil_div(s, kSgW);
+  const long long grid = (long long)ceil_div(strips, kXcds) * kXcds * hgroups;
+  APL_REQUIRE(grid < (1LL << 31), "sketch grid too large");
+  const double scale = 1.0 / sqrt((double)xi);
+  const bool vec = (ld % 4 == 0) && (n % 4 == 0) && ((uintptr_t)A % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL((k_sketch_gather<T, true>), dim3((unsigned)grid), dim3(kSgW * kWave), 0, st, A, n, ld, s,
+                       (const int*)v.ptr, (const int*)v.list, scale, strips, hgroups, Y);
+  else
+    hipLaunchKernelGGL((k_sketch_gather<T, false>), dim3((unsigned)grid), dim3(kSgW * kWave), 0, st, A, n, ld, s,
+                       (const int*)v.ptr, (const int*)v.list, scale, strips, hgroups, Y);
+}
+template void launch_sketch_dense<float>(const float*, long long, long long, long long, int, int, const uint16_t*,
+                                         const uint8_t*, double*, void*, hipStream_t);
 template void launch_sketch_dense<double>(const double*, long long, long long, long long, int, int,
-                                          const uint16_t*, const uint8_t*, double*, double*, int,
-                                          hipStream_t);
+                                          const uint16_t*, const uint8_t*, double*, void*, hipStream_t);
 
 }  // namespace aplicur

@@ -34,11 +34,12 @@ template <class T>
 void launch_sketch_csr(const int* t_ptr, const int* t_idx, const T* t_val, long long n, int s,
                        int xi, const uint16_t* rows, const uint8_t* negmask, double* Y,
                        hipStream_t st);
-int sketch_dense_chunks(long long m, long long n);
+// device scratch (bytes) of the dense sketch: the inverse of the embedding
+size_t sketch_dense_scratch(long long m, int s, int xi);
 template <class T>
 void launch_sketch_dense(const T* A, long long m, long long n, long long ld, int s, int xi,
-                         const uint16_t* rows, const uint8_t* negmask, double* Y, double* part,
-                         int chunks, hipStream_t st);
+                         const uint16_t* rows, const uint8_t* negmask, double* Y, void* scratch,
+                         hipStream_t st);
 
 // ---- Golub-Kahan / LSQR (kern_gk.hip)
 // Operator description shared by the products: CSR (row_ptr/col_idx/val and

@@ -59,10 +59,10 @@ static char* scratch_of_current_device() {
 }
 
 // Scratch layout of one call: sketch rows and signs, then (CSR) the
-// validation flag and the CSR of A^T, or (dense) the row-chunk partials of
-// the sketch when more than one chunk fits.
+// validation flag and the CSR of A^T, or (dense) the inverse of the
+// embedding (per target row, the rows of A it sums).
 struct NoAllocPlan {
-  int s = 0, xi = 0, chunks = 1;
+  int s = 0, xi = 0;
   size_t rows = 0, neg = 0, bad = 0, tp = 0, ti = 0, tv = 0, tsc = 0, part = 0, total = 0;
 };
 
@@ -88,13 +88,7 @@ static NoAllocPlan plan_noalloc(const aplicur_mat* A, const aplicur_opts* o) {
     p.tv = take(vs * (size_t)std::max<long long>(1, A->nnz));
     p.tsc = take(sizeof(int) * (size_t)n);
   } else {
-    // as many row chunks as aplicur_sketch uses, fewer when they do not fit;
-    // one chunk writes Y directly (no partials)
-    const size_t strip = sizeof(double) * (size_t)p.s * (size_t)n;
-    const long long want = sketch_dense_chunks(m, n);
-    const long long fit = off < kNoAllocScratchBytes ? (long long)((kNoAllocScratchBytes - off) / (strip + 256)) : 0;
-    p.chunks = (int)std::max<long long>(1, std::min(want, fit));
-    if (p.chunks > 1) p.part = take(strip * (size_t)p.chunks);
+    p.part = take(sketch_dense_scratch(m, p.s, p.xi));
   }
   p.total = off;
   return p;
@@ -142,12 +136,12 @@ int aplicur_sketch_noalloc(const aplicur_mat* A, const aplicur_opts* opts, doubl
       else
         launch_sketch_csr<float>(tp, ti, (const float*)tv, n, p.s, p.xi, rows, neg, Y, s);
     } else {
-      double* part = p.chunks > 1 ? (double*)(base + p.part) : Y;
+      void* part = base + p.part;
       launch_gen_sketch(opts->seed, p.s, m, p.xi, rows, neg, s);
       if (f64)
-        launch_sketch_dense<double>((const double*)A->val, m, n, A->ld, p.s, p.xi, rows, neg, Y, part, p.chunks, s);
+        launch_sketch_dense<double>((const double*)A->val, m, n, A->ld, p.s, p.xi, rows, neg, Y, part, s);
       else
-        launch_sketch_dense<float>((const float*)A->val, m, n, A->ld, p.s, p.xi, rows, neg, Y, part, p.chunks, s);
+        launch_sketch_dense<float>((const float*)A->val, m, n, A->ld, p.s, p.xi, rows, neg, Y, part, s);
     }
     APL_HIP(hipGetLastError());
     return APLICUR_OK;

@@ -91,3 +91,16 @@ def test_sketch_noalloc_rejects_what_does_not_fit():
     o.sketch = 1
     assert lib.aplicur_sketch_noalloc(ctypes.byref(m), ctypes.byref(o), 4096, None) == _lib.E_INVALID
     assert b"sparse sign" in lib.aplicur_last_error()
+
+
+def test_product_timing_record_without_gpu():
+    """aplicur_prof_read on an empty record returns zeros without device
+    work, rejects null arrays, and switching timing off needs no device."""
+    from paper_2604_05065_amd import _lib
+    lib = _lib.load()
+    n = 6
+    cnt, tot, unt = (ctypes.c_int64 * n)(), (ctypes.c_double * n)(), (ctypes.c_int64 * n)()
+    assert lib.aplicur_prof_products(0) == _lib.OK
+    assert lib.aplicur_prof_read(cnt, tot, unt) == _lib.OK
+    assert list(cnt) == [0] * n and list(tot) == [0.0] * n and list(unt) == [0] * n
+    assert lib.aplicur_prof_read(None, tot, unt) == _lib.E_INVALID

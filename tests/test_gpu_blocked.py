@@ -72,6 +72,30 @@ def test_blocked_solve_matches_oracle(lib, precond, k):
     _check_columns(A, B, X.cpu().numpy(), mu, tol)
 
 
+def test_product_kernel_event_timing(lib):
+    """aplicur_prof_products / aplicur_prof_read: with timing on, a blocked
+    solve's A X and A^T U launches are recorded with positive durations and
+    the solution is unchanged; off, nothing more is recorded."""
+    m, n, mu, tol = 700, 90, 1e-6, 1e-10
+    A = _dense(m, n, 44, decades=4)
+    B = np.random.default_rng(3).standard_normal((m, 4))
+    X0, _ = lib.lstsq(_t(A), _t(B), mu=mu, block=10, tol_ne=tol)
+    lib.prof_read()
+    lib.prof_products(True)
+    try:
+        X1, info = lib.lstsq(_t(A), _t(B), mu=mu, block=10, tol_ne=tol)
+        rec = lib.prof_read()
+    finally:
+        lib.prof_products(False)
+    print(f"[prof] {rec}")
+    assert torch.equal(X0, X1)
+    for kind in ("AX_f64", "ATX_f64"):
+        launches, mean_us, untimed = rec[kind]
+        assert launches >= info.iters and mean_us > 0.0 and untimed == 0
+    lib.lstsq(_t(A), _t(B), mu=mu, block=10, tol_ne=tol)
+    assert lib.prof_read() == {}
+
+
 def test_blocked_fp32_values_mu_zero(lib):
     """FP32 A (values widened exactly), mu = 0 (m > n), APLICUR."""
     m, n, tol = 800, 70, 1e-10

@@ -109,6 +109,25 @@ def test_sketch_at_benchmark_sizes(lib, kind, block):
     assert np.all(np.abs(Y - Yref) <= 1e-13 * mag + 1e-300)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_dense_sketch_equals_csr_sketch(lib, dtype):
+    """Both sketch kernels sum each entry of Y over the rows of A in
+    increasing order, each term the rounded +-a/sqrt(xi): the dense sketch of
+    a matrix with no zero entries equals the CSR sketch of the same matrix bit
+    for bit (ragged sizes: n not a multiple of the 256-column strip, m not a
+    multiple of the 256-row chunk of the inverse map)."""
+    m, n, block, seed = 5003, 517, 60, 4
+    A = np.random.default_rng(2).standard_normal((m, n))
+    assert np.all(A != 0)
+    Ys = []
+    for Ag in (_t(A, dtype), lib.CSRMatrix.from_scipy(sp.csr_matrix(A), device=DEV, dtype=dtype)):
+        with lib.Context(Ag, mu=1e-4, block=block, seed=seed, max_outer=1, max_iter=1) as ctx:
+            s = ctx.sizes()["s"]
+            Ys.append(ctx.query(1).reshape(s, n))
+    print(f"[parity] dense vs CSR sketch {dtype}: max |diff| {np.abs(Ys[0] - Ys[1]).max():.3e}")
+    np.testing.assert_array_equal(Ys[0], Ys[1])
+
+
 # ----------------------------------------------------------------- Alg. 2: the core SVD and P itself
 def _oracle_factors(A, I, J):
     C = A[:, J]

@@ -1,10 +1,10 @@
 """aplicur_sketch_noalloc (no device allocation; scratch in a fixed
 per-device array) against the sketch of aplicur_sketch (Alg. 3
 initialisation, Definition 5.1) on the same inputs: two calls in a row, the
-second with a smaller input, for dense and CSR A.  Same kernels and, where
-the row chunks fit, the same summation order: the test asks for the FP64
-sketch bound (every entry a sum of at most m terms |S_hi a_ij|, 1e-13 of
-their magnitudes) and reports whether the two are bitwise equal."""
+second with a smaller input, for dense and CSR A.  Both run the same kernels
+in the same summation order, so the two must agree bit for bit; both are also
+held to the FP64 sketch bound against the oracle's S A (every entry a sum of
+at most m terms |S_hi a_ij|, 1e-13 of their magnitudes)."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -51,5 +51,5 @@ def test_sketch_noalloc_matches_sketch(lib, kind, dtype):
         mag = np.asarray(abs(S) @ np.abs(Ad))
         print(f"[no-alloc]   bitwise equal to aplicur_sketch: {np.array_equal(Yn, Yref)}; "
               f"max |diff| {np.abs(Yn - Yref).max():.3e}", flush=True)
-        assert np.all(np.abs(Yn - Yref) <= 1e-13 * mag + 1e-300)
+        np.testing.assert_array_equal(Yn, Yref)
         assert np.all(np.abs(Yn - np.asarray(S @ Ad)) <= 1e-13 * mag + 1e-300)
