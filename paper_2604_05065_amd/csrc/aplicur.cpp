@@ -177,12 +177,12 @@ struct Ctx {
   int* lu_piv = nullptr;  // pivots of the blocked LU of the Schur block
   int rank = 0;
   // preconditioner
-  double *Mx = nullptr, *Mx2 = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
+  double *Mx = nullptr, *Vm = nullptr, *sigma = nullptr, *Vhat = nullptr, *d = nullptr, *pinfo = nullptr,
          *pa_part = nullptr, *pa_c = nullptr, *Kc = nullptr, *Kr = nullptr, *pc1 = nullptr, *pc2 = nullptr,
          *M2 = nullptr, *M2t = nullptr;
   int *rr_ptr = nullptr, *rr_idx = nullptr, *rt_ptr = nullptr, *rt_idx = nullptr, *rscratch = nullptr;
   double *rr_val = nullptr, *rt_val = nullptr;
-  double* jac_part = nullptr;  // per-pair partial sums of the Jacobi sweeps
+  double* jac_part = nullptr;  // Jacobi scratch: stopping partials, pair Grams and rotations
   double* splitk = nullptr;
   size_t splitk_count = 0;
   PrecDesc prec{};
@@ -693,14 +693,13 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
       c->P2 = c->arena.alloc<double>((size_t)L * b);
       c->status_dev = c->arena.alloc<int>(4);
       c->Mx = c->arena.alloc<double>((size_t)L * Lp);
-      if (c->o.precond != 2) c->Mx2 = c->arena.alloc<double>((size_t)L * Lp);  // the Jacobi rounds' second buffer
       c->Vm = c->arena.alloc<double>((size_t)Lp * Lp);
       c->sigma = c->arena.alloc<double>(Lp);
       c->Kc = c->arena.alloc<double>((size_t)L * L);
       c->Kr = c->arena.alloc<double>((size_t)L * L);
       c->d = c->arena.alloc<double>(L);
       c->pinfo = c->arena.alloc<double>(4);
-      c->jac_part = c->arena.alloc<double>((size_t)jacobi_part_words(Lp));
+      if (c->o.precond != 2) c->jac_part = c->arena.alloc<double>((size_t)jacobi_work_words(Lp));
       c->pa_c = c->arena.alloc<double>(L);
       c->prec.c = c->pa_c;
       c->prec.d = c->d;
@@ -1112,7 +1111,7 @@ static void build_precond(Ctx& c, hipStream_t s) {
     set_identity(c.Vm, lp, lp, s);
   }
   c.sweep_hist.push_back(
-      jacobi_svd(c.Mx, c.Mx2, L, l, lp, c.Vm, lp, c.sigma, c.jac_part, c.delta * c.delta, c.jacobi_tol,
+      jacobi_svd(c.Mx, L, l, lp, c.Vm, lp, c.sigma, c.jac_part, c.delta * c.delta, c.jacobi_tol,
                  std::min(kJacobiSkip, c.jacobi_tol / (4.0 * l)), 40, s));
   c.vm_rank = l;
   c.vm_ld = lp;

@@ -81,19 +81,19 @@ void zero_lower(double* G, long long ld, int k, hipStream_t s);
 
 int jacobi_block_width();
 // One-sided block Jacobi SVD of X (n x npad, column-major; columns n.. zero):
-// X <- X V, Vm <- Vm V (Vm = I on entry, npad x npad), sigma[i] = ||X(:, i)||
-// for i < n.  Sweeps end once the Frobenius norm of the off-diagonal of the
-// damped, scaled Gram matrix, e_pq = |g_pq| / sqrt((g_pp + delta2)(g_qq +
-// delta2)), summed as the sweep met each block pair, is at most tol_f; a block
-// pair with every e_pq <= skip is not rotated.  sq_part: jacobi_part_words(npad)
-// device doubles of scratch (one partial per pair and round, summed in a
-// fixed order, so the sweep count does not depend on the order in which
-// workgroups finish).  Returns the number of sweeps.
-// X2: a second n x npad buffer (ld ldx): the rounds alternate between X and
-// X2; on return the rotated X is in either, and X2's old contents are lost.
-int jacobi_svd(double* X, double* X2, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
-               double* sq_part, double delta2, double tol_f, double skip, int max_sweeps, hipStream_t s);
-long long jacobi_part_words(int npad);
+// X <- X V, Vm <- Vm V (Vm holds the starting orthogonal basis on entry,
+// npad x npad; npad a multiple of 2 jacobi_block_width()), sigma[i] =
+// ||X(:, i)|| for i < n.  Sweeps end once the Frobenius norm of the
+// off-diagonal of the damped, scaled Gram matrix, e_pq = |g_pq| / sqrt((g_pp
+// + delta2)(g_qq + delta2)), summed as the sweep met each block pair, is at
+// most tol_f; a block pair with every e_pq <= skip is not rotated.  work:
+// jacobi_work_words(npad) device doubles of scratch (per pair and round the
+// partial sums of the stopping test, summed in a fixed order so that the
+// sweep count does not depend on the order in which workgroups finish; the
+// pairs' partial Gram matrices and rotations).  Returns the number of sweeps.
+int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma, double* work,
+               double delta2, double tol_f, double skip, int max_sweeps, hipStream_t s);
+long long jacobi_work_words(int npad);
 void precond_scalars(const double* sigma, int l, double delta, double* d, double* info, hipStream_t s);
 void rho_from_ew(const double* EW, int s_rows, int r, double* out, hipStream_t s);
 

@@ -568,26 +568,31 @@ void zero_lower(double* G, long long ld, int k, hipStream_t s) {
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
 // ============================================================== block one-sided Jacobi SVD
-// X (rows x ncols, column-major) is orthogonalised column-block-pair by
-// column-block-pair: for the pair of width 2*kJW, the Gram matrix is formed
-// (FP64 MFMA), diagonalised by cyclic Jacobi in LDS, and the rotation applied to the
-// columns of X and of V.  Round-robin pairing covers every block pair once
-// per sweep (Hestenes' method, block form).  Off-diagonal entries are measured
-// on the damped Gram matrix X^T X + d2 I (d2 = delta^2: the columns of the
-// damped core [X; delta V], whose right singular vectors are X's):
-// e_pq = |g_pq| / sqrt((g_pp + d2)(g_qq + d2)).  sq_part[blockIdx.x] receives
-// the sum of e_pq^2 over the entries between the pair's two blocks (the
-// caller offsets sq_part by round), so that the partials of a sweep cover
-// each such entry once and are summed afterwards in a fixed order.  Each round takes one inner sweep on the pair's
-// Gram matrix only (the outer sweeps repeat the pairing until the whole
-// matrix is orthogonal), and a pair whose largest e_pq is at most `skip`
-// leaves X and V as they are.
-constexpr int kJW = 8;        // columns per block
+// X (rows x npad, column-major) is orthogonalised column-block-pair by
+// column-block-pair (Hestenes' method, block form): for the pair of blocks
+// (a, b), 2 kJW columns, the Gram matrix is formed, one cyclic Jacobi sweep
+// diagonalises it approximately, and the rotation Q is applied to those
+// columns of X and of V.  Round-robin (circle) pairing covers every block pair
+// once per sweep; the pairs of a round touch disjoint columns.  One round is
+// three launches:
+//   k_jac_gram   row chunks x pairs: partial Gram matrices of the pair's
+//                columns over a chunk of rows (FP64 16x16x4 MFMA);
+//   k_jac_rot    one workgroup per pair: the partials summed in chunk order,
+//                the off-diagonal measure, the inner sweep in LDS, Q stored;
+//   k_jac_apply  row chunks x pairs x {X, V}: rows times Q on the MFMA, in
+//                place (a wave reads its rows' pair columns before writing).
+// Off-diagonal entries are measured on the damped Gram matrix X^T X + d2 I
+// (d2 = delta^2: the columns of the damped core [X; delta V], whose right
+// singular vectors are X's): e_pq = |g_pq| / sqrt((g_pp + d2)(g_qq + d2)).
+// sq_part[round * npairs + pair] receives the sum of e_pq^2 over the entries
+// between the pair's two blocks, so that a sweep's partials cover each such
+// entry once; they are summed afterwards in a fixed order.  A pair whose
+// largest e_pq is at most `skip` leaves X and V as they are.
+constexpr int kJW = 16;       // columns per block
 constexpr int kJP = 2 * kJW;  // columns per pair
-constexpr int kJInner = 1;    // inner sweeps per pair and round
-constexpr int kJT = 512;      // threads per pair
-constexpr int kJR = (kJT / kWave) * 16;  // rows of the LDS buffer for the waves' partial Grams
-static_assert(kJP == 16, "the pair Gram uses one 16x16 MFMA tile");
+constexpr int kJT = 256;      // threads per workgroup (4 waves)
+constexpr int kJMaxChunks = 16;
+static_assert(kJP % 16 == 0 && (kJP / 16) * (kJP / 16) <= 4, "pair Gram: at most one 16x16 tile per wave");
 
 __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, int& b) {
   // circle method: block nblk-1 fixed, the others rotate
@@ -605,74 +610,171 @@ __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, i
   }
 }
 
-// Two workgroups per pair (blockIdx.x = 2 pair + half): both form the same
-// Gram matrix and rotation from X (bitwise the same arithmetic); half 0
-// writes the rotated columns of X to Xo (X and Xo alternate between rounds,
-// so no workgroup reads a column another one is writing), half 1 rotates the
-// columns of V in place.
-__global__ void __launch_bounds__(kJT) k_jacobi_round(const double* X, double* Xo, long long ldx, int rows,
-                                                         double* Vm, long long ldv, int vrows, int nblk, int round,
-                                                         double* sq_part, double d2, double skip) {
-  __shared__ double G[2][kJP][kJP + 1];  // double-buffered rotations
-  __shared__ double Q[2][kJP][kJP + 1];
-  __shared__ double tile[kJR][kJP + 1];
-  __shared__ double cs[kJP], sn[kJP];    // per index: its pair's rotation
-  __shared__ int mate[kJP], lowr[kJP];   // partner index; 1 if the index is the pair's p
-  __shared__ double wmax[kJT / kWave], wsq[kJT / kWave];
-  const int pair = blockIdx.x / 2, half = blockIdx.x % 2;
+// column of X of the pair's column c (block a's kJW columns, then block b's)
+__device__ __forceinline__ int pair_col(int a, int b, int c) { return c < kJW ? a * kJW + c : b * kJW + (c - kJW); }
+
+// Partial Gram of the pair's columns over rows [chunk * rpc, ...): each wave
+// forms all (kJP/16)^2 16x16 tiles over the 16-row steps wave, wave + 4, ...
+// (lane (i, q) loads column i of each 16-column slab at rows 4q .. 4q + 3 of
+// the step, which serve as the A operand of the slab's tile rows and the B
+// operand of its tile columns); the waves' partials are summed in wave
+// order.  gpart[(pair * nchunk + chunk) * kJP^2 + i kJP + j].
+__global__ void __launch_bounds__(kJT) k_jac_gram(const double* __restrict__ X, long long ldx, int rows, int nblk,
+                                                   int round, int rpc, int nchunk, double* __restrict__ gpart) {
+  constexpr int NT = kJP / 16, NW = kJT / kWave;
+  __shared__ double red[NW][kJP][kJP + 1];
+  const int chunk = blockIdx.x, pair = blockIdx.y;
   int a, b;
   pair_of(round, nblk, pair, a, b);
-  int col[2] = {a * kJW, b * kJW};
-  const int tid = threadIdx.x;
-  const int wave = tid / kWave, lane = tid % kWave;
-  // 1) Gram matrix of the 2*kJW = 16 columns on the FP64 16x16x4 MFMA: the
-  //    A and B operands are the same values (lane (i, q) holds column i at the
-  //    step's rows 4q + e, e < 4); wave w takes the 16-row steps w, w + 8, ...,
-  //    four steps' loads at a time, and the waves' partial Grams are summed in
-  //    order through LDS.
-  {
-    const int li = lane % 16, lq = lane / 16;
-    const double* xc = X + (long long)(col[li / kJW] + li % kJW) * ldx;
-    f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-    constexpr int kStep = (kJT / kWave) * 16;
-    for (int r0 = wave * 16; r0 < rows; r0 += 4 * kStep) {
-      double v[4][4];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, li = lane % 16, lq = lane / 16;
+  const double* xs[NT];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+  for (int s = 0; s < NT; ++s) xs[s] = X + (long long)pair_col(a, b, s * 16 + li) * ldx;
+  const int r_begin = chunk * rpc, r_end = min(rows, r_begin + rpc);
+  f64x4_t acc[NT][NT];
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+  constexpr int kU = 2;  // 16-row steps in flight per wave
+  for (int r0 = r_begin + wave * 16; r0 < r_end; r0 += NW * 16 * kU) {
+    double v[kU][NT][4];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int s = 0; s < NT; ++s)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int r = r0 + u * kStep + 4 * lq + e;
-          v[u][e] = r < rows ? xc[r] : 0.0;
+          const int r = r0 + u * NW * 16 + 4 * lq + e;
+          v[u][s][e] = r < r_end ? xs[s][r] : 0.0;
         }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kU; ++u)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][e], v[u][e], acc, 0, 0, 0);
-    }
-    // register r of lane (i, q) holds G[q + 4r][i]
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) tile[wave * 16 + lq + 4 * r][li] = acc[r];
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < NT; ++tj)
+            acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][ti][e], v[u][tj][e], acc[ti][tj], 0, 0, 0);
   }
+  // register r of lane (i, q) holds G[ti 16 + q + 4r][tj 16 + i]
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave][ti * 16 + lq + 4 * r][tj * 16 + li] = acc[ti][tj][r];
   __syncthreads();
-  // sum the partial Grams; largest relative off-diagonal entry of the pair
-  double mx = 0.0;
-  if (tid < kJP * kJP) {
-    const int i = tid % kJP, j = tid / kJP;
+  double* out = gpart + ((long long)pair * nchunk + chunk) * (kJP * kJP);
+  for (int e = threadIdx.x; e < kJP * kJP; e += kJT) {
+    const int i = e / kJP, j = e % kJP;
     double g = 0.0;
 #pragma unroll
-    for (int w = 0; w < kJT / kWave; ++w) g += tile[w * 16 + i][j];
+    for (int w = 0; w < NW; ++w) g += red[w][i][j];
+    out[e] = g;
+  }
+}
+
+// Partner of index i in step r of a cyclic sweep over kJP indices (circle
+// method: index kJP - 1 fixed, the others rotate).
+__device__ __forceinline__ int circle_mate(int r, int i) {
+  constexpr int n1 = kJP - 1;
+  if (i == n1) return r;
+  if (i == r) return n1;
+  return (2 * r - i + 2 * n1) % n1;
+}
+
+// Partner of index i in step k of a cross sweep: step k rotates the planes
+// (i, kJW + (i + k) mod kJW), i < kJW, so kJW steps meet every pair of one
+// column of each block once.
+__device__ __forceinline__ int cross_mate(int k, int i) {
+  return i < kJW ? kJW + (i + k) % kJW : (i - kJW - k + 2 * kJW) % kJW;
+}
+
+// plane `slot` of step r: (p, q), p < q
+__device__ __forceinline__ void step_plane(bool full, int r, int slot, int& p, int& q) {
+  if (full) {
+    p = slot == 0 ? r : min(circle_mate(r, (r + slot) % (kJP - 1)), (r + slot) % (kJP - 1));
+    q = circle_mate(r, p);
+  } else {
+    p = slot;
+    q = cross_mate(r, slot);
+  }
+}
+
+// Rotation of the plane (p, q), p < q, that zeroes g_pq: c and s with
+// column p of G J = c g_p - s g_q and column q = s g_p + c g_q.  t = tan of
+// the angle is the smaller root of t^2 + 2 (a / b) t - 1 = 0, a = g_qq -
+// g_pp, b = 2 g_pq: t = sign(a) b / (|a| + sqrt(a^2 + b^2)).  Any t close to
+// it gives an exactly orthogonal rotation that nearly zeroes g_pq (the
+// sweeps repeat until the off-diagonal is small), so t is formed with the
+// hardware's approximate square root and reciprocal, after an exact scaling
+// of a and b by a power of two; c = 1 / sqrt(1 + t^2) takes the hardware's
+// reciprocal square root and two Newton steps (about one ulp), and s = c t,
+// so that c^2 + s^2 = 1 to rounding.
+__device__ __forceinline__ void jacobi_rot(double gpp, double gqq, double gpq, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (!(fabs(gpq) > 1e-300 && gpq * gpq > 0x1p-104 * fabs(gpp * gqq))) return;
+  double a = gqq - gpp, b = 2.0 * gpq;
+  const int ex = ilogb(fmax(fabs(a), fabs(b)));
+  a = ldexp(a, -ex);
+  b = ldexp(b, -ex);
+  const double hyp = __builtin_amdgcn_sqrt(fma(a, a, b * b));
+  const double tn = (a >= 0.0 ? b : -b) * __builtin_amdgcn_rcp(fabs(a) + hyp);
+  const double x = fma(tn, tn, 1.0);
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  c = y;
+  s = y * tn;
+}
+
+// Per pair: G = the partials summed in chunk order; the measure (sq_part,
+// largest e_pq against skip); then kJW disjoint rotations per step, G <- J^T
+// G J and Q <- Q J, one thread per entry: with `full` (the first round of an
+// outer sweep) a cyclic sweep over all kJP indices (kJP - 1 steps), else a
+// cross sweep (kJW steps: every pair of one column from each block once, the
+// blocks' own pairs having had their turn in the sweep's first round, where
+// every block meets its partner in a full sweep).  One
+// barrier per step: thread k < kJW first forms the three entries of the next
+// G that the next step's k-th plane needs and computes that rotation
+// (rotations double-buffered by step parity), then, like every thread, its
+// entry of the next G and Q with the step's rotations.  Q to qbuf
+// (row-major) and flag[pair] = 0, or flag = 1 (skip: X and V keep the
+// pair's columns).
+constexpr int kJRT = kJP * kJP;  // threads of k_jac_rot (one per entry)
+__global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpart, int nchunk, int full, double d2,
+                                                   double skip, double* __restrict__ sq_part,
+                                                   double* __restrict__ qbuf, int* __restrict__ flag) {
+  __shared__ double G[2][kJP][kJP + 1];
+  __shared__ double Q[2][kJP][kJP + 1];
+  __shared__ double cs[2][kJP], sn[2][kJP];  // per step parity and index: its plane's c and signed s
+  __shared__ double wmax[kJRT / kWave], wsq[kJRT / kWave];
+  const int pair = blockIdx.x, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int i = tid / kJP, j = tid % kJP;
+  const double* gp = gpart + (long long)pair * nchunk * (kJP * kJP);
+  {
+    double v[kJMaxChunks];
+#pragma unroll
+    for (int c = 0; c < kJMaxChunks; ++c) v[c] = c < nchunk ? gp[(long long)c * (kJP * kJP) + tid] : 0.0;
+    double g = 0.0;
+#pragma unroll
+    for (int c = 0; c < kJMaxChunks; ++c) g += v[c];
     G[0][i][j] = g;
     Q[0][i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  double sq = 0.0;
-  if (tid < kJP * kJP) {
-    const int i = tid % kJP, j = tid / kJP;
-    if (i < j) {
-      const double d = sqrt((G[0][i][i] + d2) * (G[0][j][j] + d2));
-      if (d > 0.0) mx = fabs(G[0][i][j]) / d;
-      if (i < kJW && j >= kJW) sq = mx * mx;
-    }
+  double mx = 0.0, sq = 0.0;
+  if (i < j) {
+    const double d = sqrt((G[0][i][i] + d2) * (G[0][j][j] + d2));
+    const double v = d > 0.0 ? fabs(G[0][i][j]) / d : 0.0;
+    mx = v;
+    if (i < kJW && j >= kJW) sq = v * v;
   }
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -683,97 +785,126 @@ __global__ void __launch_bounds__(kJT) k_jacobi_round(const double* X, double* X
     wmax[wave] = mx;
     wsq[wave] = sq;
   }
+  // step 0's rotations from G itself
+  if (tid < kJW) {
+    int p, q;
+    step_plane(full != 0, 0, tid, p, q);
+    double c, s;
+    jacobi_rot(G[0][p][p], G[0][q][q], G[0][p][q], c, s);
+    cs[0][p] = cs[0][q] = c;
+    sn[0][p] = -s;
+    sn[0][q] = s;
+  }
   __syncthreads();
   double block_off = 0.0, block_sq = 0.0;
 #pragma unroll
-  for (int w = 0; w < kJT / kWave; ++w) {
+  for (int w = 0; w < kJRT / kWave; ++w) {
     block_off = fmax(block_off, wmax[w]);
     block_sq += wsq[w];
   }
-  if (tid == 0 && half == 0) sq_part[pair] = block_sq;
-  if (block_off <= skip) {  // uniform: the pair's columns go to Xo unrotated
-    if (half == 0)
-      for (int e = tid; e < rows * kJP; e += kJT) {
-        const int r = e % rows, cc = e / rows;
-        const long long at = (long long)r + (long long)(col[cc / kJW] + cc % kJW) * ldx;
-        Xo[at] = X[at];
-      }
+  if (tid == 0) sq_part[pair] = block_sq;
+  if (block_off <= skip) {  // uniform
+    if (tid == 0) flag[pair] = 1;
     return;
   }
-  // 2) cyclic Jacobi on G (kJP x kJP): kJP - 1 rounds of kJW disjoint
-  //    rotations (round-robin); each round G <- J^T G J and Q <- Q J computed
-  //    entry by entry from the previous buffer.
+  const bool fl = full != 0;
+  const int steps = fl ? kJP - 1 : kJW;
+  auto mate = [&](int r, int x) { return fl ? circle_mate(r, x) : cross_mate(r, x); };
   int cur = 0;
-  static_assert(kJInner == 1, "one inner sweep per pair and round");
-  {
-    for (int r = 0; r < kJP - 1; ++r) {
-      if (tid < kJW) {
-        int p, q;
-        if (tid == 0) {
-          p = kJP - 1;
-          q = r;
-        } else {
-          p = (r + tid) % (kJP - 1);
-          q = (r - tid + (kJP - 1)) % (kJP - 1);
-        }
-        if (p > q) {
-          int t = p;
-          p = q;
-          q = t;
-        }
-        const double gpp = G[cur][p][p], gqq = G[cur][q][q], gpq = G[cur][p][q];
-        double c = 1.0, sv = 0.0;
-        if (fabs(gpq) > 1e-300 && fabs(gpq) > 2.2e-16 * sqrt(gpp * gqq)) {
-          const double zeta = (gqq - gpp) / (2.0 * gpq);
-          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sv = c * t;
-        }
-        mate[p] = q;
-        mate[q] = p;
-        lowr[p] = 1;
-        lowr[q] = 0;
-        cs[p] = cs[q] = c;
-        sn[p] = sn[q] = sv;
-      }
-      __syncthreads();
-      // column j of G J: p' = c g_p - s g_q, q' = s g_p + c g_q (same for Q J);
-      // then row i of J^T (G J) likewise.
-      if (tid < kJP * kJP) {
-        const int i = tid % kJP, j = tid / kJP, nx = cur ^ 1;
-        const int mi = mate[i], mj = mate[j];
-        const double ci = cs[i], si = lowr[i] ? -sn[i] : sn[i];
-        const double cj = cs[j], sj = lowr[j] ? -sn[j] : sn[j];
-        // (G J)[k][j] = cj G[k][j] + sj G[k][mj], for k in {i, mi}
-        const double gij = cj * G[cur][i][j] + sj * G[cur][i][mj];
-        const double gmj = cj * G[cur][mi][j] + sj * G[cur][mi][mj];
-        G[nx][i][j] = ci * gij + si * gmj;
-        Q[nx][i][j] = cj * Q[cur][i][j] + sj * Q[cur][i][mj];
-      }
-      cur ^= 1;
-      __syncthreads();
+  for (int r = 0; r < steps; ++r) {
+    const int nx = cur ^ 1, par = r & 1;
+    if (tid < kJW && r + 1 < steps) {
+      // the next step's plane tid: its entries of the next G, then its rotation
+      int p, q;
+      step_plane(fl, r + 1, tid, p, q);
+      auto next = [&](int x, int y) {
+        const int mx_ = mate(r, x), my = mate(r, y);
+        const double cx = cs[par][x], sx = sn[par][x], cy = cs[par][y], sy = sn[par][y];
+        const double gxy = cy * G[cur][x][y] + sy * G[cur][x][my];
+        const double gmy = cy * G[cur][mx_][y] + sy * G[cur][mx_][my];
+        return cx * gxy + sx * gmy;
+      };
+      const double gpp = next(p, p), gqq = next(q, q), gpq = next(p, q);
+      double c, s;
+      jacobi_rot(gpp, gqq, gpq, c, s);
+      cs[par ^ 1][p] = cs[par ^ 1][q] = c;
+      sn[par ^ 1][p] = -s;
+      sn[par ^ 1][q] = s;
     }
+    {
+      // entry (i, j) of J^T G J and of Q J for this step's planes
+      const int mi = mate(r, i), mj = mate(r, j);
+      const double ci = cs[par][i], si = sn[par][i], cj = cs[par][j], sj = sn[par][j];
+      const double gij = cj * G[cur][i][j] + sj * G[cur][i][mj];
+      const double gmj = cj * G[cur][mi][j] + sj * G[cur][mi][mj];
+      G[nx][i][j] = ci * gij + si * gmj;
+      Q[nx][i][j] = cj * Q[cur][i][j] + sj * Q[cur][i][mj];
+    }
+    cur = nx;
+    __syncthreads();
   }
-  // 3) apply Q to the columns of X (half 0, into Xo) or of V (half 1, in
-  //    place): each thread's rows are loaded together before the products.
-  {
-    const double* Mi = half == 0 ? X : Vm;
-    double* Mo = half == 0 ? Xo : Vm;
-    const long long ld = half == 0 ? ldx : ldv;
-    const int nr = half == 0 ? rows : vrows;
-    for (int r = tid; r < nr; r += kJT) {
-      double in[kJP];
+  qbuf[(long long)pair * (kJP * kJP) + tid] = Q[cur][i][j];
+  if (tid == 0) flag[pair] = 0;
+}
+
+// Rows [64 (4 blockIdx.x + wave), + 64) of X (blockIdx.z = 0) or V (1), the
+// pair's columns, times Q: D = Q^T X_rows^T on the FP64 16x16x4 MFMA (A lane
+// (i, q) = Q[k + q][16 It + i] from LDS, B lane (i, q) = X[row0 + i][col(k + q)],
+// D lane (i, q) register r = the new X[row0 + i][col(16 It + q + 4r)]).  All of
+// the wave's loads precede its stores, and no other wave touches these rows
+// and columns, so the update is in place.
+__global__ void __launch_bounds__(kJT) k_jac_apply(double* __restrict__ X, long long ldx, int xrows,
+                                                    double* __restrict__ V, long long ldv, int vrows, int nblk,
+                                                    int round, const double* __restrict__ qbuf,
+                                                    const int* __restrict__ flag) {
+  constexpr int NI = kJP / 16, KS = kJP / 4, NJ = 4;
+  __shared__ double Qs[kJP][kJP + 1];
+  const int pair = blockIdx.y;
+  if (flag[pair]) return;  // uniform
+  double* M = blockIdx.z ? V : X;
+  const long long ld = blockIdx.z ? ldv : ldx;
+  const int rows = blockIdx.z ? vrows : xrows;
+  if ((long long)blockIdx.x * kJT >= rows) return;  // uniform
+  int a, b;
+  pair_of(round, nblk, pair, a, b);
+  const double* qp = qbuf + (long long)pair * (kJP * kJP);
+  for (int e = threadIdx.x; e < kJP * kJP; e += kJT) Qs[e / kJP][e % kJP] = qp[e];
+  __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, li = lane % 16, lq = lane / 16;
+  const int r0 = blockIdx.x * kJT + wave * 64;
+  if (r0 >= rows) return;  // no barrier follows
+  double xv[NJ][KS];
 #pragma unroll
-      for (int cc = 0; cc < kJP; ++cc) in[cc] = Mi[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld];
-#pragma unroll 4
-      for (int cc = 0; cc < kJP; ++cc) {
-        double acc = 0.0;
+  for (int jt = 0; jt < NJ; ++jt)
 #pragma unroll
-        for (int t = 0; t < kJP; ++t) acc += in[t] * Q[cur][t][cc];
-        Mo[(long long)r + (long long)(col[cc / kJW] + cc % kJW) * ld] = acc;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int r = r0 + 16 * jt + li;
+      xv[jt][ks] = r < rows ? M[(long long)pair_col(a, b, 4 * ks + lq) * ld + r] : 0.0;
+    }
+  f64x4_t acc[NI][NJ];
+#pragma unroll
+  for (int it = 0; it < NI; ++it)
+#pragma unroll
+    for (int jt = 0; jt < NJ; ++jt) acc[it][jt] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const double qa = Qs[4 * ks + lq][16 * it + li];
+#pragma unroll
+      for (int jt = 0; jt < NJ; ++jt)
+        acc[it][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa, xv[jt][ks], acc[it][jt], 0, 0, 0);
+    }
+#pragma unroll
+  for (int it = 0; it < NI; ++it)
+#pragma unroll
+    for (int jt = 0; jt < NJ; ++jt) {
+      const int r = r0 + 16 * jt + li;
+      if (r < rows) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) M[(long long)pair_col(a, b, 16 * it + lq + 4 * rr) * ld + r] = acc[it][jt][rr];
       }
     }
-  }
 }
 
 __global__ void k_col_norms(const double* X, long long ldx, int rows, int ncols, double* out) {
@@ -797,24 +928,57 @@ __global__ void __launch_bounds__(kBlock) k_sum_fixed(const double* part, int co
   if (threadIdx.x == 0) out[0] = v;
 }
 
-int jacobi_svd(double* X, double* X2, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma,
-               double* sq_part, double delta2, double tol_f, double skip, int max_sweeps, hipStream_t s) {
-  // X: n x npad (columns n..npad-1 zero), Vm: npad x npad, set to I by the caller.
+// Row chunks of the Gram launch: about 512 workgroups per round, chunks of
+// at least 64 rows (a multiple of 16), at most kJMaxChunks.
+static void jacobi_chunks(int rows, int npairs, int& nchunk, int& rpc) {
+  int want = (512 + npairs - 1) / npairs;
+  want = std::max(1, std::min(std::min(want, kJMaxChunks), (rows + 63) / 64));
+  rpc = ((rows + want - 1) / want + 15) / 16 * 16;
+  nchunk = std::max(1, (rows + rpc - 1) / rpc);
+}
+
+struct JacWork {
+  double *sq_part, *sum, *gpart, *qbuf;
+  int* flag;
+};
+
+static JacWork carve_jacobi(double* w, int rows, int npad) {
+  const long long nblk = npad / kJW, npairs = nblk / 2, rounds = nblk - 1;
+  JacWork j;
+  j.sq_part = w;
+  j.sum = w + rounds * npairs;
+  j.gpart = j.sum + 1;
+  j.qbuf = j.gpart + npairs * (long long)kJMaxChunks * kJP * kJP;
+  j.flag = (int*)(j.qbuf + npairs * (long long)kJP * kJP);
+  (void)rows;
+  return j;
+}
+
+int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long ldv, double* sigma, double* work,
+               double delta2, double tol_f, double skip, int max_sweeps, hipStream_t s) {
+  // X: n x npad (columns n..npad-1 zero), Vm: npad x npad, set by the caller.
+  APL_REQUIRE(npad % kJP == 0 && npad >= kJP, "jacobi_svd: npad must be a positive multiple of the pair width");
   const int nblk = npad / kJW;
   const int npairs = nblk / 2, rounds = nblk - 1;
-  double* sum_dev = sq_part + (long long)rounds * npairs;
-  double* buf[2] = {X, X2};
-  int cur = 0;
+  int nchunk, rpc;
+  jacobi_chunks(n, npairs, nchunk, rpc);
+  const JacWork jw = carve_jacobi(work, n, npad);
+  const int arows = std::max(n, npad);
+  const dim3 ga(ceil_div(arows, kJT), npairs, 2);
   int sweeps = 0;
   for (; sweeps < max_sweeps; ++sweeps) {
     for (int r = 0; r < rounds; ++r) {
-      hipLaunchKernelGGL(k_jacobi_round, dim3(2 * npairs), dim3(kJT), 0, s, (const double*)buf[cur], buf[cur ^ 1], ldx,
-                         n, Vm, ldv, npad, nblk, r, sq_part + (long long)r * npairs, delta2, skip);
-      cur ^= 1;
+      hipLaunchKernelGGL(k_jac_gram, dim3(nchunk, npairs), dim3(kJT), 0, s, (const double*)X, ldx, n, nblk, r, rpc,
+                         nchunk, jw.gpart);
+      hipLaunchKernelGGL(k_jac_rot, dim3(npairs), dim3(kJRT), 0, s, (const double*)jw.gpart, nchunk, r == 0 ? 1 : 0,
+                         delta2, skip,
+                         jw.sq_part + (long long)r * npairs, jw.qbuf, jw.flag);
+      hipLaunchKernelGGL(k_jac_apply, ga, dim3(kJT), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
+                         (const double*)jw.qbuf, (const int*)jw.flag);
     }
-    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kBlock), 0, s, (const double*)sq_part, rounds * npairs, sum_dev);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kBlock), 0, s, (const double*)jw.sq_part, rounds * npairs, jw.sum);
     double sum_sq = 0.0;
-    APL_HIP(hipMemcpyAsync(&sum_sq, sum_dev, sizeof(sum_sq), hipMemcpyDeviceToHost, s));
+    APL_HIP(hipMemcpyAsync(&sum_sq, jw.sum, sizeof(sum_sq), hipMemcpyDeviceToHost, s));
     APL_HIP(hipStreamSynchronize(s));
     // Frobenius norm of the damped off-diagonal (both triangles) as the sweep saw it
     if (std::sqrt(2.0 * sum_sq) <= tol_f) {
@@ -822,13 +986,14 @@ int jacobi_svd(double* X, double* X2, long long ldx, int n, int npad, double* Vm
       break;
     }
   }
-  hipLaunchKernelGGL(k_col_norms, dim3(n), dim3(kBlock), 0, s, (const double*)buf[cur], ldx, n, n, sigma);
+  hipLaunchKernelGGL(k_col_norms, dim3(n), dim3(kBlock), 0, s, (const double*)X, ldx, n, n, sigma);
   return sweeps;
 }
 
-long long jacobi_part_words(int npad) {
-  const long long nblk = npad / kJW;
-  return (nblk - 1) * (nblk / 2) + 1;
+long long jacobi_work_words(int npad) {
+  const long long nblk = npad / kJW, npairs = nblk / 2, rounds = nblk - 1;
+  return rounds * npairs + 1 + npairs * (long long)kJMaxChunks * kJP * kJP + npairs * (long long)kJP * kJP +
+         (npairs + 1) / 2 + 1;
 }
 
 int jacobi_block_width() { return kJW; }
