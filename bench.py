@@ -489,45 +489,56 @@ def paper_workloads(ap, synth, torch, tol=1e-8, budget=30000):
     the comparison systems): APLICUR against plain LSQR, both FP64 on the GPU,
     time to eta <= tol (iteration budget `budget` each), block b = n/50.  Dense
     incoherent / coherent U Sigma V^T with sharp (kappa 1e7, 1e15) or smooth
-    (kappa 1e15) decay and consistent-x right-hand sides (noise 1e-2 of
-    ||A x*||); sparse 1% density, incoherent / coherent.  One JSON line."""
+    (kappa 1e15) decay and consistent-x right-hand sides (noise 0, 1e-12 or
+    1e-2 of ||A x*||), the mu sweep {1e-4, 1e-6, 1e-8, 0} on the incoherent
+    sharp and smooth sets; sparse 1% density 12000 x 10000 and 30000 x 4000,
+    incoherent / coherent, sharp / smooth.  One JSON line."""
+    # (name, kind, (m, n, decay, coherent), [(mu, noise), ...]); dense right-hand
+    # sides are consistent-x with the given relative noise, sparse ones N(0, I)
+    sweep = [(1e-4, 1e-2), (1e-6, 1e-2), (1e-8, 1e-2), (0.0, 1e-2)]
+    noises = [(1e-4, 1e-2), (1e-4, 0.0), (1e-4, 1e-12)]
     cases = [
-        ("dense 6000x5000 incoherent sharp 1e7", "dense", (6000, 5000, "sharp7", False), [1e-4, 1e-8]),
-        ("dense 6000x5000 incoherent sharp 1e15", "dense", (6000, 5000, "sharp15", False), [1e-8]),
-        ("dense 6000x5000 coherent sharp 1e7", "dense", (6000, 5000, "sharp7", True), [1e-4]),
-        ("dense 15000x2000 incoherent sharp 1e7", "dense", (15000, 2000, "sharp7", False), [1e-4]),
-        ("dense 6000x5000 incoherent smooth 1e15", "dense", (6000, 5000, "smooth", False), [1e-4, 1e-6, 1e-8, 0.0]),
-        ("sparse 12000x10000 1% incoherent sharp 1e7", "sparse", (12000, 10000, "sharp7", False), [1e-4]),
-        ("sparse 30000x4000 1% incoherent sharp 1e7", "sparse", (30000, 4000, "sharp7", False), [1e-4]),
-        ("sparse 12000x10000 1% coherent sharp 1e7", "sparse", (12000, 10000, "sharp7", True), [1e-4]),
+        ("dense 6000x5000 incoherent sharp 1e7", "dense", (6000, 5000, "sharp7", False), sweep + noises[1:]),
+        ("dense 6000x5000 incoherent sharp 1e15", "dense", (6000, 5000, "sharp15", False), sweep),
+        ("dense 6000x5000 coherent sharp 1e7", "dense", (6000, 5000, "sharp7", True), noises),
+        ("dense 15000x2000 incoherent sharp 1e7", "dense", (15000, 2000, "sharp7", False), noises),
+        ("dense 6000x5000 incoherent smooth 1e15", "dense", (6000, 5000, "smooth", False), sweep + noises[1:]),
+        ("sparse 12000x10000 1% incoherent sharp 1e7", "sparse", (12000, 10000, "sharp7", False), [(1e-4, None)]),
+        ("sparse 12000x10000 1% coherent sharp 1e7", "sparse", (12000, 10000, "sharp7", True), [(1e-4, None)]),
+        ("sparse 30000x4000 1% incoherent sharp 1e7", "sparse", (30000, 4000, "sharp7", False), [(1e-4, None)]),
+        ("sparse 30000x4000 1% coherent sharp 1e7", "sparse", (30000, 4000, "sharp7", True), [(1e-4, None)]),
+        ("sparse 30000x4000 1% incoherent smooth 1e15", "sparse", (30000, 4000, "smooth", False), [(1e-4, None)]),
+        ("sparse 30000x4000 1% coherent smooth 1e15", "sparse", (30000, 4000, "smooth", True), [(1e-4, None)]),
     ]
     out = []
     Aw, bw = synth.paper_dense_gpu(1, 300, 60, "sharp7")
-    ap.lstsq(Aw, bw, mu=1e-4, block=6)  # warm-up (library and rocBLAS initialisation)
-    for ci, (name, kind, (m, n, decay, coh), mus) in enumerate(cases):
-        if kind == "dense":
-            A, b = synth.paper_dense_gpu(6000 + ci, m, n, decay, coherent=coh, noise=1e-2)
-        else:
+    ap.lstsq(Aw, bw, mu=1e-4, block=6)  # warm-up (library initialisation)
+    for ci, (name, kind, (m, n, decay, coh), runs) in enumerate(cases):
+        As = bh = None
+        if kind == "sparse":
             As, bh = synth.paper_sparse(6000 + ci, m, n, decay, coherent=coh)
-            A = ap.CSRMatrix.from_scipy(As, device="cuda", dtype=torch.float64)
-            b = torch.as_tensor(bh, device="cuda")
-        for mu in mus:
-            row = {"workload": name, "mu": mu}
+        for mu, noise in runs:
+            if kind == "dense":
+                A, b = synth.paper_dense_gpu(6000 + ci, m, n, decay, coherent=coh, noise=noise)
+            else:
+                A = ap.CSRMatrix.from_scipy(As, device="cuda", dtype=torch.float64)
+                b = torch.as_tensor(bh, device="cuda")
+            row = {"workload": name, "mu": mu, "noise": noise}
             for label, pc in (("aplicur", True), ("plain_lsqr", False)):
                 o = dict(mu=mu, block=max(1, n // 50), tol_ne=tol, max_iter=budget, precond=pc)
                 try:
                     ms, (x, info) = _timed(torch, lambda: ap.lstsq(A, b, **o))
                 except RuntimeError as e:  # a breakdown the method reports (e.g. CholQR of C)
                     row[label] = {"error": str(e)}
-                    log(f"[bench] paper workload {name} mu={mu:g} {label}: {e}")
+                    log(f"[bench] paper workload {name} mu={mu:g} noise={noise} {label}: {e}")
                     continue
                 row[label] = {"ms": round(ms, 1), "iters": info.iters, "eta": info.eta, "status": info.status,
                               "rank": info.rank}
-                log(f"[bench] paper workload {name} mu={mu:g} {label}: {ms:.0f} ms, {info.iters} it, "
-                    f"eta {info.eta:.1e}, rank {info.rank}, status {info.status}")
+                log(f"[bench] paper workload {name} mu={mu:g} noise={noise} {label}: {ms:.0f} ms, "
+                    f"{info.iters} it, eta {info.eta:.1e}, rank {info.rank}, status {info.status}")
             out.append(row)
-        del A, b
-        torch.cuda.empty_cache()
+            del A, b
+            torch.cuda.empty_cache()
     print(json.dumps({"paper_workloads": out}), flush=True)
 
 
