@@ -186,9 +186,8 @@ int64_t aplicur_workspace_bytes(const aplicur_mat* A, int32_t nrhs, const aplicu
  * aligned, owned by the caller and untouched after ctx destruction; every
  * device buffer of the context is carved from it (size it with
  * aplicur_workspace_bytes).  ws = NULL: the library allocates with
- * hipMalloc and frees at destruction.  Either way rocBLAS keeps the device
- * memory of its own handle, and small pinned host buffers hold the
- * read-backs.  Errors: E_INVALID (shape/options/alignment), E_NOMEM
+ * hipMalloc and frees at destruction.  Either way small pinned host buffers
+ * hold the read-backs.  Errors: E_INVALID (shape/options/alignment), E_NOMEM
  * (allocation failed or workspace exhausted), E_HIP.                       */
 int aplicur_sketch(const aplicur_mat* A, const aplicur_opts* opts, void* ws, size_t ws_bytes, void* stream,
                    aplicur_ctx** ctx_out);
@@ -237,10 +236,26 @@ int aplicur_solve(aplicur_ctx* ctx, const double* B, int64_t ldb, int32_t nrhs, 
  * kernels as aplicur_solve (opts.graphs: its LSQR iterations replay as HIP
  * graphs; opts.tune: product tiles autotuned per shape).  All work is done
  * when the call returns.  Every problem is validated before any work starts.
- * Returns the first error (naming the problem), else the largest warning.  */
+ * ws (device, optional): a caller workspace of ws_bytes bytes, 256-byte
+ * aligned, sized with aplicur_batched_workspace_bytes: worker w carves the
+ * context of every problem it runs from slice w (each slice fits the largest
+ * problem's context), so the call allocates no device memory for contexts;
+ * ws = NULL: each context allocates with hipMalloc and frees when its
+ * problem is done.  Errors: E_INVALID (also a workspace below the size the
+ * call needs; the message gives it), E_NOMEM, E_HIP.  Returns the first
+ * error (naming the problem), else the largest warning.                     */
 int aplicur_solve_batched(int32_t batch, const aplicur_mat* A, const double* const* B, const int64_t* ldb,
                           int32_t nrhs, double* const* X, const int64_t* ldx, const aplicur_opts* opts,
-                          aplicur_info* info, void* stream);
+                          void* ws, size_t ws_bytes, aplicur_info* info, void* stream);
+
+/* Workspace bytes of aplicur_solve_batched for these problems, nrhs and
+ * options: min(batch, opts.workers (0: 4)) slices, each the largest context
+ * any problem needs (measured as aplicur_workspace_bytes does, by running
+ * each problem's set-up once on `stream` with library-allocated memory).
+ * Returns the byte count (> 0) or a negative error (E_INVALID, E_NOMEM,
+ * E_HIP).                                                                    */
+int64_t aplicur_batched_workspace_bytes(int32_t batch, const aplicur_mat* A, int32_t nrhs, const aplicur_opts* opts,
+                                        void* stream);
 
 /* Adjoint of the solve (not in the paper; implicit differentiation of the
  * normal equations A^T (B - A X) = mu X).  For a loss with G = dL/dX

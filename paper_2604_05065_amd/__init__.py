@@ -6,8 +6,8 @@ Every entry point loads the built library and fails loudly if it is missing
 -- there is no CPU fallback.
 """
 from ._lib import AplicurError, load as load_library
-from .api import (Context, CSRMatrix, LstsqFunction, lstsq, lstsq_autograd, make_opts, prof_products, prof_read,
-                  sketch, sketch_noalloc, solve_batched)
+from .api import (Context, CSRMatrix, LstsqFunction, batched_workspace_bytes, lstsq, lstsq_autograd, make_opts,
+                  prof_products, prof_read, sketch, sketch_noalloc, solve_batched)
 
-__all__ = ["AplicurError", "load_library", "Context", "CSRMatrix", "LstsqFunction", "lstsq", "lstsq_autograd",
+__all__ = ["AplicurError", "load_library", "Context", "CSRMatrix", "LstsqFunction", "batched_workspace_bytes", "lstsq", "lstsq_autograd",
            "make_opts", "prof_products", "prof_read", "sketch", "sketch_noalloc", "solve_batched"]

@@ -41,7 +41,7 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ["aplicur_opts_default", "aplicur_workspace_bytes", "aplicur_sketch", "aplicur_sketch_noalloc", "aplicur_solve", "aplicur_solve_batched",
+EXPORTS = ["aplicur_opts_default", "aplicur_workspace_bytes", "aplicur_sketch", "aplicur_sketch_noalloc", "aplicur_solve", "aplicur_solve_batched", "aplicur_batched_workspace_bytes",
            "aplicur_solve_backward", "aplicur_matvec", "aplicur_matmat", "aplicur_time_product", "aplicur_time_matmat", "aplicur_precond_apply", "aplicur_ctx_query", "aplicur_ctx_destroy",
            "aplicur_prof_products", "aplicur_prof_read", "aplicur_last_error", "aplicur_version"]
 
@@ -68,7 +68,10 @@ def load():
     lib.aplicur_solve.argtypes = [vp, dp, i64, i32, dp, i64, i32, C.POINTER(Info), vp]
     lib.aplicur_solve.restype = C.c_int
     lib.aplicur_solve_batched.argtypes = [i32, C.POINTER(Mat), C.POINTER(vp), C.POINTER(i64), i32,
-                                          C.POINTER(vp), C.POINTER(i64), C.POINTER(Opts), C.POINTER(Info), vp]
+                                          C.POINTER(vp), C.POINTER(i64), C.POINTER(Opts), vp, C.c_size_t,
+                                          C.POINTER(Info), vp]
+    lib.aplicur_batched_workspace_bytes.argtypes = [i32, C.POINTER(Mat), i32, C.POINTER(Opts), vp]
+    lib.aplicur_batched_workspace_bytes.restype = C.c_int64
     lib.aplicur_solve_batched.restype = C.c_int
     lib.aplicur_solve_backward.argtypes = [vp, dp, i64, dp, i64, dp, i64, i32, dp, i64, dp, i64, dp, i64,
                                            C.POINTER(Info), vp]

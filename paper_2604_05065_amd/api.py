@@ -346,10 +346,28 @@ def lstsq_autograd(A, B, **opts):
     return LstsqFunction.apply(A, B, None, opts)
 
 
-def solve_batched(As, Bs, workers=0, tune=True, graphs=True, **opts):
+def batched_workspace_bytes(As, nrhs, workers=0, tune=True, graphs=True, **opts):
+    """Bytes of the workspace solve_batched(..., workspace=...) needs."""
+    lib = L.load()
+    o = make_opts(workers=workers, tune=tune, graphs=graphs, **opts)
+    mats, keep = [], []
+    for A in As:
+        st, kp = _mat(A)
+        mats.append(st)
+        keep.append(kp)
+    marr = (L.Mat * len(As))(*mats)
+    n = lib.aplicur_batched_workspace_bytes(len(As), marr, int(nrhs), C.byref(o), _stream())
+    if n < 0:
+        L.check(int(n))
+    return int(n)
+
+
+def solve_batched(As, Bs, workers=0, tune=True, graphs=True, workspace=None, **opts):
     """Independent problems min ||A_p X_p - B_p||^2 + mu ||X_p||^2 (same
     options, same number of right-hand sides), solved concurrently by the
-    library's worker streams; returns ([X_p], [info_p])."""
+    library's worker streams; returns ([X_p], [info_p]).  workspace: an
+    optional device tensor (uint8, 256-byte aligned) of at least
+    batched_workspace_bytes bytes that every context is carved from."""
     lib = L.load()
     o = make_opts(workers=workers, tune=tune, graphs=graphs, **opts)
     mats, keep = [], []
@@ -370,7 +388,10 @@ def solve_batched(As, Bs, workers=0, tune=True, graphs=True, **opts):
     ldb = (C.c_int64 * p)(*[int(A.shape[0]) for A in As])
     ldx = (C.c_int64 * p)(*[int(A.shape[1]) for A in As])
     infos = (L.Info * p)()
-    L.check(lib.aplicur_solve_batched(p, marr, bptr, ldb, k, xptr, ldx, C.byref(o), infos, _stream()))
+    ws_ptr, ws_bytes = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None \
+        else (None, 0)
+    L.check(lib.aplicur_solve_batched(p, marr, bptr, ldb, k, xptr, ldx, C.byref(o), ws_ptr, ws_bytes, infos,
+                                      _stream()))
     outs = [x.t() for x in Xs]
     if cols[0][2]:
         outs = [x.reshape(-1) for x in outs]

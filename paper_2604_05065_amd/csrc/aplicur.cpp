@@ -2119,17 +2119,39 @@ static size_t workspace_for(const aplicur_mat* A, const aplicur_opts* o, int nrh
 // same kernels as aplicur_solve; with the graphs option its LSQR iterations
 // replay as captured graphs on that stream.  Returns after all streams are
 // done; the first error (in problem order) is rethrown.
+static int batched_workers(int batch, const aplicur_opts& o) {
+  return std::max(1, std::min(batch, o.workers > 0 ? o.workers : 4));
+}
+
+// Bytes of one worker's slice of a batched call's workspace: the largest
+// context any of the problems needs (each measured as aplicur_workspace_bytes
+// does), rounded to the arena alignment.
+static size_t batched_slice_bytes(int batch, const aplicur_mat* A, int nrhs, const aplicur_opts& o, hipStream_t s) {
+  size_t slice = 0;
+  for (int p = 0; p < batch; ++p) slice = std::max(slice, workspace_for(&A[p], &o, nrhs, s));
+  return Arena::aligned(slice);
+}
+
 static int solve_batched(int batch, const aplicur_mat* A, const double* const* B, const int64_t* ldb, int nrhs,
                          double* const* X, const int64_t* ldx, const aplicur_opts& o, aplicur_info* info,
-                         hipStream_t caller) {
+                         void* ws, size_t ws_bytes, hipStream_t caller) {
   for (int p = 0; p < batch; ++p) validate(&A[p], &o);
+  const int workers = batched_workers(batch, o);
+  // with a caller workspace, worker w carves every context it runs from
+  // slice w; the slice fits the largest problem's context
+  size_t slice = 0;
+  if (ws) {
+    slice = batched_slice_bytes(batch, A, nrhs, o, caller);
+    APL_REQUIRE(ws_bytes >= slice * (size_t)workers,
+                "the workspace needs " + std::to_string(slice * (size_t)workers) + " bytes (" +
+                    std::to_string(workers) + " workers x " + std::to_string(slice) + ")");
+  }
   std::vector<int> order(batch);
   std::iota(order.begin(), order.end(), 0);
   auto work = [&](int p) {
     return A[p].format == APLICUR_CSR ? (double)A[p].nnz : (double)A[p].m * (double)A[p].n;
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-  const int workers = std::max(1, std::min(batch, o.workers > 0 ? o.workers : 4));
   int dev = 0;
   APL_HIP(hipGetDevice(&dev));
   hipEvent_t ready = nullptr;
@@ -2138,8 +2160,9 @@ static int solve_batched(int batch, const aplicur_mat* A, const double* const* B
   std::atomic<int> next{0};
   std::vector<int> status(batch, APLICUR_OK), code(batch, 0);
   std::vector<std::string> msg(batch);
-  auto worker = [&]() {
+  auto worker = [&](int wid) {
     hipStream_t s = nullptr;
+    char* my_ws = ws ? (char*)ws + slice * (size_t)wid : nullptr;
     bool ok;
     {
       SyncGuard g(g_capture_mu);
@@ -2161,7 +2184,7 @@ static int solve_batched(int batch, const aplicur_mat* A, const double* const* B
       const int p = order[i];
       Ctx* c = nullptr;
       try {
-        c = create(&A[p], &o, s);
+        c = create(&A[p], &o, s, my_ws, my_ws ? slice : 0);
         status[p] = solve(*c, B[p], ldb[p], nrhs, X[p], ldx[p], false, info ? &info[p] : nullptr, s);
       } catch (const Error& e) {
         code[p] = e.code;
@@ -2177,8 +2200,8 @@ static int solve_batched(int batch, const aplicur_mat* A, const double* const* B
     (void)hipStreamDestroy(s);
   };
   std::vector<std::thread> pool;
-  for (int w = 1; w < workers; ++w) pool.emplace_back(worker);
-  worker();
+  for (int w = 1; w < workers; ++w) pool.emplace_back(worker, w);
+  worker(0);
   for (auto& t : pool) t.join();
   (void)hipEventDestroy(ready);
   int worst = APLICUR_OK;
@@ -2267,14 +2290,30 @@ int aplicur_solve(aplicur_ctx* ctx, const double* B, int64_t ldb, int32_t nrhs, 
   });
 }
 
+int64_t aplicur_batched_workspace_bytes(int32_t batch, const aplicur_mat* A, int32_t nrhs, const aplicur_opts* opts,
+                                        void* stream) {
+  int64_t bytes = 0;
+  const int rc = guarded([&]() {
+    APL_REQUIRE(batch >= 1 && A && opts, "need batch >= 1 problems and options");
+    APL_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    for (int p = 0; p < batch; ++p) validate(&A[p], opts);
+    const size_t slice = batched_slice_bytes(batch, A, nrhs, *opts, (hipStream_t)stream);
+    bytes = (int64_t)(slice * (size_t)batched_workers(batch, *opts));
+    return APLICUR_OK;
+  });
+  return rc == APLICUR_OK ? bytes : (int64_t)rc;
+}
+
 int aplicur_solve_batched(int32_t batch, const aplicur_mat* A, const double* const* B, const int64_t* ldb,
                           int32_t nrhs, double* const* X, const int64_t* ldx, const aplicur_opts* opts,
-                          aplicur_info* info, void* stream) {
+                          void* ws, size_t ws_bytes, aplicur_info* info, void* stream) {
   return guarded([&]() {
     APL_REQUIRE(batch >= 0, "batch must be >= 0");
     if (batch == 0) return (int)APLICUR_OK;
     APL_REQUIRE(A && B && ldb && X && ldx && opts, "null batch arrays");
-    return solve_batched(batch, A, B, ldb, nrhs, X, ldx, *opts, info, (hipStream_t)stream);
+    APL_REQUIRE(!ws || ws_bytes > 0, "ws_bytes must be > 0 with a workspace");
+    APL_REQUIRE(((uintptr_t)ws % Arena::kAlign) == 0, "the workspace must be 256-byte aligned");
+    return solve_batched(batch, A, B, ldb, nrhs, X, ldx, *opts, info, ws, ws ? ws_bytes : 0, (hipStream_t)stream);
   });
 }
 

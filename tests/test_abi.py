@@ -104,3 +104,19 @@ def test_product_timing_record_without_gpu():
     assert lib.aplicur_prof_read(cnt, tot, unt) == _lib.OK
     assert list(cnt) == [0] * n and list(tot) == [0.0] * n and list(unt) == [0] * n
     assert lib.aplicur_prof_read(None, tot, unt) == _lib.E_INVALID
+
+
+def test_batched_workspace_arguments_checked_without_gpu():
+    """aplicur_solve_batched rejects a misaligned workspace and
+    aplicur_batched_workspace_bytes an empty batch before any device work."""
+    from paper_2604_05065_amd import _lib
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.aplicur_opts_default(ctypes.byref(o))
+    m = (_lib.Mat * 1)(_lib.Mat(_lib.DENSE, _lib.F64, 20, 10, 10, 0, 1, None, None))
+    ptrs = (ctypes.c_void_p * 1)(8)
+    lds = (ctypes.c_int64 * 1)(20)
+    infos = (_lib.Info * 1)()
+    rc = lib.aplicur_solve_batched(1, m, ptrs, lds, 1, ptrs, lds, ctypes.byref(o), 4096 + 8, 1 << 20, infos, None)
+    assert rc == _lib.E_INVALID and b"aligned" in lib.aplicur_last_error()
+    assert lib.aplicur_batched_workspace_bytes(0, m, 1, ctypes.byref(o), None) == _lib.E_INVALID

@@ -115,3 +115,26 @@ def test_batched_rejects_invalid_problem(lib):
     Bs = [_t(r.standard_normal(50)), _t(r.standard_normal(5))]
     with pytest.raises(lib.AplicurError):
         lib.solve_batched(As, Bs, mu=0.0)
+
+
+def test_batched_caller_workspace(lib):
+    """With a caller workspace (aplicur_batched_workspace_bytes, one slice
+    per worker) every context is carved from it, and the solutions are
+    bitwise those of the library-allocated run; one byte short is rejected
+    with the size in the message before any problem runs."""
+    probs = _batch(count=6)
+    As = [_gpu(lib, A) for A, _ in probs]
+    Bs = [_t(B) for _, B in probs]
+    kw = dict(workers=3, tune=False, graphs=True, **OPTS)
+    need = lib.batched_workspace_bytes(As, 2, **kw)
+    assert need > 0
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    assert ws.data_ptr() % 256 == 0
+    Xw, iw = lib.solve_batched(As, Bs, workspace=ws, **kw)
+    Xr, ir = lib.solve_batched(As, Bs, **kw)
+    print(f"[batched] workspace {need} bytes for 3 workers")
+    for a, b, ia, ib in zip(Xw, Xr, iw, ir):
+        assert ia.status == 0 and ia.iters == ib.iters
+        assert torch.equal(a, b)
+    with pytest.raises(lib.AplicurError, match="workspace needs"):
+        lib.solve_batched(As, Bs, workspace=ws[: need - 256], **kw)
