@@ -210,8 +210,8 @@ def bench_headline(ap, synth, torch, args):
                     "t_precond_ms": round(info.t_precond_ms, 2), "t_lsqr_ms": round(info.t_lsqr_ms, 2)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": ("k_rows_gemm<float, double, double> (A X and A^T U for 16 columns, FP32 A "
-                                "widened, FP64 16x16x4 MFMA), launches of the timed steps"),
+                     "kernel": ("k_rows_gemm_xl (A X and A^T U for 16 columns, FP32 A widened, FP64 16x16x4 "
+                                "MFMA, X staged in LDS per workgroup), launches of the timed steps"),
                      "launches": n_ax + n_atu, "bytes_per_launch": int(bytes_prod),
                      "us_per_launch": round(us_live, 3),
                      "mfma_tflops": round(flops_prod / us_live / 1e6, 2),

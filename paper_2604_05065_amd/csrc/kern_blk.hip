@@ -166,6 +166,124 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// The same product for FP32 M, FP64 In and 16 columns (the several-RHS
+// product of a dense FP32 A), with In staged through LDS: the workgroup's
+// four waves share one copy of each 128-entry chunk of In (16 KB, loaded with
+// 16-byte loads by all threads during the previous chunk, double-buffered),
+// so the L1 carries M once and In once per workgroup instead of once per
+// wave.  M stays in registers (two stages), as above.  LDS rows of the chunk
+// are 18 doubles apart, so the four 16-lane groups of a B-operand read fall
+// on two bank halves.
+constexpr int kXC = 4;               // steps per In chunk
+constexpr int kXE = kXC * kGStep;    // entries per chunk
+constexpr int kXLd = 18;             // LDS row stride of a chunk (doubles)
+
+struct AStep {
+  float a[kGT][kGPL];
+};
+
+template <bool VEC>
+__device__ __forceinline__ void astep_load(AStep& st, const float* const (&mrow)[kGT], long long j0, long long je,
+                                           int lq) {
+  const long long jl = j0 + kGPL * lq;
+  if (VEC && j0 + kGStep <= je) {
+#pragma unroll
+    for (int t = 0; t < kGT; ++t)
+#pragma unroll
+      for (int h = 0; h < kGPL / 4; ++h) {
+        const f32x4 u = ((const f32x4*)(mrow[t] + jl))[h];
+        st.a[t][4 * h] = u.x; st.a[t][4 * h + 1] = u.y; st.a[t][4 * h + 2] = u.z; st.a[t][4 * h + 3] = u.w;
+      }
+  } else {
+#pragma unroll
+    for (int e = 0; e < kGPL; ++e) {
+      const long long j = jl + e;
+      const bool in = j < je;
+      const long long jc = in ? j : je - 1;
+#pragma unroll
+      for (int t = 0; t < kGT; ++t) st.a[t][e] = in ? mrow[t][jc] : 0.0f;
+    }
+  }
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(kBlock)
+    k_rows_gemm_xl(const float* __restrict__ M, long long rows, long long cols, long long ld,
+                   const double* __restrict__ In, double* __restrict__ out, long long kchunk) {
+  constexpr int KP = 16;
+  constexpr int NX = kXE * KP / 2 / kBlock;  // 16-byte loads of a chunk per thread
+  __shared__ double Xs[2][kXE][kXLd];
+  f64x4 acc[kGT];
+#pragma unroll
+  for (int t = 0; t < kGT; ++t) acc[t] = f64x4{0, 0, 0, 0};
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int li = lane % 16, lq = lane / 16;
+  const long long row0 = (long long)blockIdx.x * kGRows + (long long)wave * (kGT * 16);
+  const long long jb = (long long)blockIdx.y * kchunk;
+  const long long je = min(cols, jb + kchunk);
+  const float* mrow[kGT];
+#pragma unroll
+  for (int t = 0; t < kGT; ++t) mrow[t] = M + min(row0 + t * 16 + li, rows - 1) * ld;
+  auto xload = [&](long long c0, f64x2 (&r)[NX]) {
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      const int idx = tid + k * kBlock;
+      const long long j = c0 + idx / (KP / 2);
+      r[k] = j < je ? ((const f64x2*)(In + j * KP))[idx % (KP / 2)] : f64x2{0.0, 0.0};
+    }
+  };
+  auto xstore = [&](int buf, const f64x2 (&r)[NX]) {
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      const int idx = tid + k * kBlock;
+      *(f64x2*)&Xs[buf][idx / (KP / 2)][2 * (idx % (KP / 2))] = r[k];
+    }
+  };
+  auto mma = [&](const AStep& st, int buf, int s) {
+#pragma unroll
+    for (int e = 0; e < kGPL; ++e) {
+      const double bv = Xs[buf][s * kGStep + kGPL * lq + e][li];
+#pragma unroll
+      for (int t = 0; t < kGT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)st.a[t][e], bv, acc[t], 0, 0, 0);
+    }
+  };
+  if (jb < je) {  // uniform
+    f64x2 xr[NX];
+    xload(jb, xr);
+    xstore(0, xr);
+    __syncthreads();
+    AStep s0, s1;
+    astep_load<VEC>(s0, mrow, jb, je, lq);
+    int buf = 0;
+    for (long long c0 = jb; c0 < je; c0 += kXE) {
+      const long long c1 = c0 + kXE;
+      if (c1 < je) xload(c1, xr);  // in flight during this chunk's steps
+      // kXC is even, so every chunk starts with its first step in s0
+#pragma unroll
+      for (int s = 0; s < kXC; s += 2) {
+        const long long j0 = c0 + s * kGStep, j1 = j0 + kGStep, j2 = j1 + kGStep;
+        if (j0 >= je) break;
+        if (j1 < je) astep_load<VEC>(s1, mrow, j1, je, lq);
+        mma(s0, buf, s);
+        if (j1 >= je) break;
+        if (j2 < je) astep_load<VEC>(s0, mrow, j2, je, lq);
+        mma(s1, buf, s + 1);
+      }
+      if (c1 < je) xstore(buf ^ 1, xr);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  double* o = out + (long long)blockIdx.y * rows * KP;
+#pragma unroll
+  for (int t = 0; t < kGT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long row = row0 + t * 16 + lq + 4 * r;
+      if (row < rows) o[row * KP + li] = acc[t][r];
+    }
+}
+
 int gemm_splits(long long rows, long long cols) {
   const long long gx = ceil_div(rows, kGRows);
   long long S = (1024 + gx - 1) / gx;  // about four workgroups per CU
@@ -190,6 +308,15 @@ static void rows_gemm_nb(const TA* M, long long rows, long long cols, long long 
   const long long kchunk = ((per + kGStep - 1) / kGStep) * kGStep;
   const bool vec = ((uintptr_t)M % 16 == 0) && ((ld * (long long)sizeof(TA)) % 16 == 0);
   const dim3 g(ceil_div(rows, kGRows), S);
+  if constexpr (std::is_same<TA, float>::value && std::is_same<TB, double>::value &&
+                std::is_same<ACC, double>::value && NB == 1) {
+    // FP32 M, FP64 In, 16 columns: In staged in LDS once per workgroup
+    if (vec)
+      launch_ev(k_rows_gemm_xl<true>, g, s, e0, e1, M, rows, cols, ld, In, out, kchunk);
+    else
+      launch_ev(k_rows_gemm_xl<false>, g, s, e0, e1, M, rows, cols, ld, In, out, kchunk);
+    return;
+  }
   if (vec)
     launch_ev(k_rows_gemm<TA, TB, ACC, NB, true>, g, s, e0, e1, M, rows, cols, ld, In, out, kchunk);
   else
