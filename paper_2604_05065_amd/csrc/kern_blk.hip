@@ -166,34 +166,44 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// The same product for FP32 M, FP64 In and 16 columns (the several-RHS
-// product of a dense FP32 A), with In staged through LDS: the workgroup's
-// four waves share one copy of each 128-entry chunk of In (16 KB, loaded with
-// 16-byte loads by all threads during the previous chunk, double-buffered),
-// so the L1 carries M once and In once per workgroup instead of once per
-// wave.  M stays in registers (two stages), as above.  LDS rows of the chunk
-// are 18 doubles apart, so the four 16-lane groups of a B-operand read fall
-// on two bank halves.
+// The same product for FP64 In and 16 columns with FP64 accumulation (the
+// several-RHS products of a dense A, and the blocked P-apply products), with
+// In staged through LDS: the workgroup's four waves share one copy of each
+// 128-entry chunk of In (16 KB, loaded with 16-byte loads by all threads
+// during the previous chunk, double-buffered), so the L1 carries M once and
+// In once per workgroup instead of once per wave.  M stays in registers (two
+// stages), as above.  LDS rows of the chunk are 18 doubles apart, so the four
+// 16-lane groups of a B-operand read fall on two bank halves.
 constexpr int kXC = 4;               // steps per In chunk
 constexpr int kXE = kXC * kGStep;    // entries per chunk
 constexpr int kXLd = 18;             // LDS row stride of a chunk (doubles)
 
+template <class TA>
 struct AStep {
-  float a[kGT][kGPL];
+  TA a[kGT][kGPL];
 };
 
-template <bool VEC>
-__device__ __forceinline__ void astep_load(AStep& st, const float* const (&mrow)[kGT], long long j0, long long je,
+template <class TA, bool VEC>
+__device__ __forceinline__ void astep_load(AStep<TA>& st, const TA* const (&mrow)[kGT], long long j0, long long je,
                                            int lq) {
   const long long jl = j0 + kGPL * lq;
   if (VEC && j0 + kGStep <= je) {
 #pragma unroll
-    for (int t = 0; t < kGT; ++t)
+    for (int t = 0; t < kGT; ++t) {
+      if constexpr (sizeof(TA) == 4) {
 #pragma unroll
-      for (int h = 0; h < kGPL / 4; ++h) {
-        const f32x4 u = ((const f32x4*)(mrow[t] + jl))[h];
-        st.a[t][4 * h] = u.x; st.a[t][4 * h + 1] = u.y; st.a[t][4 * h + 2] = u.z; st.a[t][4 * h + 3] = u.w;
+        for (int h = 0; h < kGPL / 4; ++h) {
+          const f32x4 u = ((const f32x4*)(mrow[t] + jl))[h];
+          st.a[t][4 * h] = u.x; st.a[t][4 * h + 1] = u.y; st.a[t][4 * h + 2] = u.z; st.a[t][4 * h + 3] = u.w;
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < kGPL / 2; ++h) {
+          const f64x2 u = ((const f64x2*)(mrow[t] + jl))[h];
+          st.a[t][2 * h] = u.x; st.a[t][2 * h + 1] = u.y;
+        }
       }
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < kGPL; ++e) {
@@ -201,14 +211,14 @@ __device__ __forceinline__ void astep_load(AStep& st, const float* const (&mrow)
       const bool in = j < je;
       const long long jc = in ? j : je - 1;
 #pragma unroll
-      for (int t = 0; t < kGT; ++t) st.a[t][e] = in ? mrow[t][jc] : 0.0f;
+      for (int t = 0; t < kGT; ++t) st.a[t][e] = in ? mrow[t][jc] : (TA)0;
     }
   }
 }
 
-template <bool VEC>
+template <class TA, bool VEC>
 __global__ void __launch_bounds__(kBlock)
-    k_rows_gemm_xl(const float* __restrict__ M, long long rows, long long cols, long long ld,
+    k_rows_gemm_xl(const TA* __restrict__ M, long long rows, long long cols, long long ld,
                    const double* __restrict__ In, double* __restrict__ out, long long kchunk) {
   constexpr int KP = 16;
   constexpr int NX = kXE * KP / 2 / kBlock;  // 16-byte loads of a chunk per thread
@@ -221,7 +231,7 @@ __global__ void __launch_bounds__(kBlock)
   const long long row0 = (long long)blockIdx.x * kGRows + (long long)wave * (kGT * 16);
   const long long jb = (long long)blockIdx.y * kchunk;
   const long long je = min(cols, jb + kchunk);
-  const float* mrow[kGT];
+  const TA* mrow[kGT];
 #pragma unroll
   for (int t = 0; t < kGT; ++t) mrow[t] = M + min(row0 + t * 16 + li, rows - 1) * ld;
   auto xload = [&](long long c0, f64x2 (&r)[NX]) {
@@ -239,7 +249,7 @@ __global__ void __launch_bounds__(kBlock)
       *(f64x2*)&Xs[buf][idx / (KP / 2)][2 * (idx % (KP / 2))] = r[k];
     }
   };
-  auto mma = [&](const AStep& st, int buf, int s) {
+  auto mma = [&](const AStep<TA>& st, int buf, int s) {
 #pragma unroll
     for (int e = 0; e < kGPL; ++e) {
       const double bv = Xs[buf][s * kGStep + kGPL * lq + e][li];
@@ -252,8 +262,8 @@ __global__ void __launch_bounds__(kBlock)
     xload(jb, xr);
     xstore(0, xr);
     __syncthreads();
-    AStep s0, s1;
-    astep_load<VEC>(s0, mrow, jb, je, lq);
+    AStep<TA> s0, s1;
+    astep_load<TA, VEC>(s0, mrow, jb, je, lq);
     int buf = 0;
     for (long long c0 = jb; c0 < je; c0 += kXE) {
       const long long c1 = c0 + kXE;
@@ -263,10 +273,10 @@ __global__ void __launch_bounds__(kBlock)
       for (int s = 0; s < kXC; s += 2) {
         const long long j0 = c0 + s * kGStep, j1 = j0 + kGStep, j2 = j1 + kGStep;
         if (j0 >= je) break;
-        if (j1 < je) astep_load<VEC>(s1, mrow, j1, je, lq);
+        if (j1 < je) astep_load<TA, VEC>(s1, mrow, j1, je, lq);
         mma(s0, buf, s);
         if (j1 >= je) break;
-        if (j2 < je) astep_load<VEC>(s0, mrow, j2, je, lq);
+        if (j2 < je) astep_load<TA, VEC>(s0, mrow, j2, je, lq);
         mma(s1, buf, s + 1);
       }
       if (c1 < je) xstore(buf ^ 1, xr);
@@ -308,13 +318,12 @@ static void rows_gemm_nb(const TA* M, long long rows, long long cols, long long 
   const long long kchunk = ((per + kGStep - 1) / kGStep) * kGStep;
   const bool vec = ((uintptr_t)M % 16 == 0) && ((ld * (long long)sizeof(TA)) % 16 == 0);
   const dim3 g(ceil_div(rows, kGRows), S);
-  if constexpr (std::is_same<TA, float>::value && std::is_same<TB, double>::value &&
-                std::is_same<ACC, double>::value && NB == 1) {
-    // FP32 M, FP64 In, 16 columns: In staged in LDS once per workgroup
+  if constexpr (std::is_same<TB, double>::value && std::is_same<ACC, double>::value && NB == 1) {
+    // FP64 In, 16 columns, FP64 accumulation: In staged in LDS once per workgroup
     if (vec)
-      launch_ev(k_rows_gemm_xl<true>, g, s, e0, e1, M, rows, cols, ld, In, out, kchunk);
+      launch_ev(k_rows_gemm_xl<TA, true>, g, s, e0, e1, M, rows, cols, ld, In, out, kchunk);
     else
-      launch_ev(k_rows_gemm_xl<false>, g, s, e0, e1, M, rows, cols, ld, In, out, kchunk);
+      launch_ev(k_rows_gemm_xl<TA, false>, g, s, e0, e1, M, rows, cols, ld, In, out, kchunk);
     return;
   }
   if (vec)
