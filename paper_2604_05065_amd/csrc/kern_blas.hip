@@ -33,10 +33,25 @@ constexpr int kGPad = 2;      // LDS row padding (doubles)
 // tile_load only issues the loads (addresses clamped into range) so that
 // they stay in flight during the MFMAs of the current stage; tile_store
 // zeroes the out-of-range entries when it writes the stage to LDS.
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
 template <bool KC, class T>
 __device__ __forceinline__ void tile_load(const T* __restrict__ X, long long ld, long long rows, long long i0,
-                                          long long k0, long long kend, T (&r)[8]) {
+                                          long long k0, long long kend, T (&r)[8], bool vec) {
   const int t = threadIdx.x;
+  if constexpr (sizeof(T) == 8) {
+    // whole stage in range and 16-byte aligned rows: four 16-byte loads
+    if (vec && i0 + kGM <= rows && k0 + kGKs <= kend) {
+      const T* p = KC ? X + (i0 + t / 2) * ld + k0 + (t % 2) * 8 : X + (k0 + t / 16) * ld + i0 + (t % 16) * 8;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const f64x2_t u = ((const f64x2_t*)p)[h];
+        r[2 * h] = u.x;
+        r[2 * h + 1] = u.y;
+      }
+      return;
+    }
+  }
   if (!KC) {
     const long long kk = k0 + t / 16;
     const long long ib = i0 + (t % 16) * 8;
@@ -69,11 +84,13 @@ __device__ __forceinline__ void tile_store(T (*Xs)[LD], const T (&r)[8], long lo
   }
 }
 
+// Two waves per SIMD (at most 256 registers, 128 of them the accumulators),
+// so that one wave's MFMAs overlap the other's LDS reads and barriers.
 template <bool TA, bool TB>
-__global__ void __launch_bounds__(kGThreads)
+__global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
     k_dgemm(long long M, long long N, long long K, long long kchunk, double alpha, const double* __restrict__ A,
             long long lda, const double* __restrict__ B, long long ldb, double beta, double* __restrict__ C,
-            long long ldc, double* __restrict__ part) {
+            long long ldc, double* __restrict__ part, int vec_a, int vec_b) {
   __shared__ double As[kGKs][kGM + kGPad];
   __shared__ double Bs[kGKs][kGM + kGPad];
   const long long i0 = (long long)blockIdx.x * kGM, j0 = (long long)blockIdx.y * kGM;
@@ -89,8 +106,8 @@ __global__ void __launch_bounds__(kGThreads)
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4_t{0.0, 0.0, 0.0, 0.0};
   double ra[8], rb[8];
   if (kbeg < kend) {
-    tile_load<TA>(A, lda, M, i0, kbeg, kend, ra);
-    tile_load<!TB>(B, ldb, N, j0, kbeg, kend, rb);
+    tile_load<TA>(A, lda, M, i0, kbeg, kend, ra, vec_a != 0);
+    tile_load<!TB>(B, ldb, N, j0, kbeg, kend, rb, vec_b != 0);
   }
   for (long long k0 = kbeg; k0 < kend; k0 += kGKs) {
     __syncthreads();
@@ -98,8 +115,8 @@ __global__ void __launch_bounds__(kGThreads)
     tile_store<!TB, double, kGM + kGPad>(Bs, rb, N, j0, k0, kend);
     __syncthreads();
     if (k0 + kGKs < kend) {
-      tile_load<TA>(A, lda, M, i0, k0 + kGKs, kend, ra);
-      tile_load<!TB>(B, ldb, N, j0, k0 + kGKs, kend, rb);
+      tile_load<TA>(A, lda, M, i0, k0 + kGKs, kend, ra, vec_a != 0);
+      tile_load<!TB>(B, ldb, N, j0, k0 + kGKs, kend, rb, vec_b != 0);
     }
 #pragma unroll
     for (int kk = 0; kk < kGKs; kk += 4) {
@@ -195,18 +212,22 @@ void dgemm(Op ta, Op tb, long long m, long long n, long long k, double alpha, co
   const dim3 g((unsigned)((m + kGM - 1) / kGM), (unsigned)((n + kGM - 1) / kGM), (unsigned)parts);
   double* part = parts > 1 ? work : nullptr;
   const bool tA = ta == Op::T, tB = tb == Op::T;
+  // 16-byte loads need even leading dimensions and 16-byte aligned bases
+  // (the k chunks and tile origins are even)
+  const int va = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
+  const int vb = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
   if (!tA && !tB)
     hipLaunchKernelGGL((k_dgemm<false, false>), g, dim3(kGThreads), 0, s, m, n, k, kc, alpha, A, lda, B, ldb, beta, C,
-                       ldc, part);
+                       ldc, part, va, vb);
   else if (!tA && tB)
     hipLaunchKernelGGL((k_dgemm<false, true>), g, dim3(kGThreads), 0, s, m, n, k, kc, alpha, A, lda, B, ldb, beta, C,
-                       ldc, part);
+                       ldc, part, va, vb);
   else if (tA && !tB)
     hipLaunchKernelGGL((k_dgemm<true, false>), g, dim3(kGThreads), 0, s, m, n, k, kc, alpha, A, lda, B, ldb, beta, C,
-                       ldc, part);
+                       ldc, part, va, vb);
   else
     hipLaunchKernelGGL((k_dgemm<true, true>), g, dim3(kGThreads), 0, s, m, n, k, kc, alpha, A, lda, B, ldb, beta, C,
-                       ldc, part);
+                       ldc, part, va, vb);
   if (parts > 1)
     hipLaunchKernelGGL(k_gemm_reduce, dim3(std::min<unsigned>(ceil_div(m * n, kBlock), 4096)), dim3(kBlock), 0, s,
                        (const double*)part, parts, m, n, alpha, beta, C, ldc);
