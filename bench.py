@@ -175,14 +175,17 @@ def bench_headline(ap, synth, torch, args):
         f"launches {us_atu_live:.0f} us (untimed {untimed}); mean {us_live:.0f} us = {gbs:.0f} GB/s, "
         f"{flops_prod / us_live / 1e6:.1f} TFLOP/s")
     # the same kernel alone, 20 launches back to back
-    with ap.Context(A, precond=False, **opts) as ctx:
-        X = torch.randn(NPTS, NRHS, device="cuda", dtype=torch.float64)
-        us_ax = ctx.time_matmat(X, trans=False, reps=20)
-        us_atu = ctx.time_matmat(X, trans=True, reps=20)
-    log(f"[bench] product kernel alone (20 back to back): A X {us_ax:.0f} us, A^T U {us_atu:.0f} us")
+    us_ax = us_atu = float("nan")
+    if not args.headline_only:
+        with ap.Context(A, precond=False, **opts) as ctx:
+            X = torch.randn(NPTS, NRHS, device="cuda", dtype=torch.float64)
+            us_ax = ctx.time_matmat(X, trans=False, reps=20)
+            us_atu = ctx.time_matmat(X, trans=True, reps=20)
+        log(f"[bench] product kernel alone (20 back to back): A X {us_ax:.0f} us, A^T U {us_atu:.0f} us")
     compare = {}
-    for name, kw in (("aplicur_fp32_phases", dict(precision=1)), ("aplicur_bf16_products", dict(precision=2)),
-                     ("plain_lsqr", dict(precond=False, max_iter=2000))):
+    for name, kw in (() if args.headline_only else
+                     (("aplicur_fp32_phases", dict(precision=1)), ("aplicur_bf16_products", dict(precision=2)),
+                      ("plain_lsqr", dict(precond=False, max_iter=2000)))):
         if name != "plain_lsqr":
             solve(SEEDS3[0], **kw)  # warm-up of the mode (its copies of A)
         ms, (_, inf) = solve(SEEDS3[0], **kw)
@@ -218,9 +221,10 @@ def bench_headline(ap, synth, torch, args):
                      "mfma_frac_fp64": round(flops_prod / us_live / 1e6 / FP64_PEAK_TFS, 4)},
         "products": {"timed_steps": {"AX_launches": n_ax, "AX_us": round(us_ax_live, 1), "ATU_launches": n_atu,
                                      "ATU_us": round(us_atu_live, 1), "untimed": untimed},
-                     "alone_back_to_back": {"AX_us": round(us_ax, 1), "ATU_us": round(us_atu, 1),
-                                            "AX_GBs": round(bytes_prod / (us_ax * 1e-6) / 1e9, 1),
-                                            "ATU_GBs": round(bytes_prod / (us_atu * 1e-6) / 1e9, 1)}},
+                     "alone_back_to_back": None if args.headline_only else {
+                         "AX_us": round(us_ax, 1), "ATU_us": round(us_atu, 1),
+                         "AX_GBs": round(bytes_prod / (us_ax * 1e-6) / 1e9, 1),
+                         "ATU_GBs": round(bytes_prod / (us_atu * 1e-6) / 1e9, 1)}},
         "compare": compare,
     }
 
@@ -632,6 +636,9 @@ def main():
     ap_.add_argument("--blocked-prec", type=int, default=0, choices=(0, 1, 2),
                      help="arithmetic of --blocked-products: 0 FP64 accumulation, 1 FP32, 2 BF16")
     ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
+    ap_.add_argument("--headline-only", action="store_true",
+                     help="only the warm-up and timed solves of the dense kernel workload (no comparisons, no "
+                          "other workloads): the run that profiles the product kernel of value's steps")
     ap_.add_argument("--paper-workloads", action="store_true",
                      help="only the paper's test sets, APLICUR against plain LSQR, one JSON line")
     ap_.add_argument("--schedule-study", action="store_true",
@@ -683,6 +690,11 @@ def main():
         return
 
     head = bench_headline(ap, synth, torch, args)
+    if args.headline_only:
+        print(json.dumps({"value": head["ms_per_step"], "unit": "ms", "steps": args.steps, "warmup": args.warmup,
+                          "roofline": head["roofline"], "seeds": head["seeds"], "aplicur": head["aplicur"],
+                          "products": head["products"]}), flush=True)
+        return
     torch.cuda.empty_cache()
     c2 = bench_c2(ap, synth, torch, args)
     torch.cuda.empty_cache()

@@ -140,6 +140,13 @@ typedef struct aplicur_opts {
                         this; the preconditioned singular values then lie within
                         sqrt(1 +- jacobi_tol) of the exact-SVD level.  <= 0: 1e-2
                         (default); tiny values run the sweeps to convergence (at most 40) */
+  int32_t tc_sketched; /* T_C (Alg. 2) when the Cholesky of C^T C breaks down after a CUR
+                        increment (the new columns nearly dependent on C): 0 (default): the
+                        increment is undone and the rank growth ends; 1: T_C is recomputed by
+                        sketched Cholesky QR of C (Gaussian embedding of 2 l rows from stream 3
+                        of seed + 7919, two shifted and two plain Cholesky QR passes on the
+                        sketch, then one Cholesky QR of C R^{-1}), the growth continues, and
+                        the increment is undone only if that breaks down too          */
 } aplicur_opts;
 
 /* ------------------------------------------------------------------ info  */

@@ -15,7 +15,7 @@
                  d_cur = rho - eps_cur.
   until rho <= eps_cur.
 
-Readings (all listed in the design doc): delta = sqrt(mu); s = ceil(1.1 b) capped at
+Readings (where the text leaves a choice): delta = sqrt(mu); s = ceil(1.1 b) capped at
 m; eps_cur defaults to 30 sqrt(mu) (3e-7 when mu = 0, Sec. 8.3); the step is
 also final when the rank reaches min(n, max_rank) or the residual is exhausted;
 the final phase stops on the certified normal-equation bound (the
@@ -36,7 +36,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import rng
-from .cur import (Preconditioner, SvdFreePreconditioner, augment_cur, augment_qr,
+from .cur import (Preconditioner, SvdFreePreconditioner, augment_cur, augment_qr, t_c_factor,
                   core_and_residual, rho_estimate)
 from .lsqr import STOP_BUDGET, plsqr_phase
 
@@ -58,6 +58,7 @@ class Options:
     schedule: int = 0          # 0 fully adaptive; 1 rank-adaptive single shot; 2 fixed-rank single shot
     precond: str = "svd"       # "svd" (Alg. 2) or "svdfree" (Alg. 8, mu = 0 only)
     svdfree_floor: bool = True  # Alg. 8 target max(rho, eps_cur); False: rho as printed
+    tc: str = "chol"            # T_C when chol(C^T C) breaks down: "chol" undo the step, "sketched" sketched CholQR
 
 
 @dataclass
@@ -135,16 +136,6 @@ def lsqr_plain(A, b, mu, tol_ne=1e-8, eps_lsqr=0.0, max_iter=100000, x0=None):
     return x, total
 
 
-def _chol_ok(C):
-    """Whether C^T C (C dense or sparse) has a floating-point Cholesky factor."""
-    CtC = C.T @ C
-    try:
-        np.linalg.cholesky(CtC.toarray() if sp.issparse(CtC) else np.asarray(CtC))
-        return True
-    except np.linalg.LinAlgError:
-        return False
-
-
 def aplicur(A, b, mu, opts=None, trace=None):
     """Alg. 3 for one right-hand side; returns x (and fills ``trace``)."""
     opts = opts or Options()
@@ -197,12 +188,16 @@ def aplicur(A, b, mu, opts=None, trace=None):
         # Part 2: update the QR factorisation of R^T
         if len(I_plus):
             Q_R, T_R = augment_qr(Q_R, T_R, A[I_plus, :].T)
-        # Reading: new columns numerically dependent on C (C^T C no longer
-        # positive definite in floating point, so Alg. 2's chol(C^T C) would
-        # break down) end the rank growth: the step is undone and treated as
-        # exhaustion.
-        if len(prev[1]) and not _chol_ok(C):
+        # T_C of Alg. 2: chol(C^T C); when C^T C is no longer positive
+        # definite in floating point (new columns nearly dependent on C),
+        # with tc = "sketched" the sketched Cholesky QR that Alg. 2 and Alg. 3
+        # Part 3 name for stability.  Reading: when no T_C results, the step is
+        # undone and treated as exhaustion.
+        sk = opts.tc == "sketched"
+        T_C = t_c_factor(C, opts.seed, sketched=sk)
+        if T_C is None and len(prev[1]):
             I, J, C, W, R, E_row, Q_R, T_R, rho = prev
+            T_C = t_c_factor(C, opts.seed, sketched=sk)
             exhausted = True
         # Sec. 7.1 variants: single shot builds P once, at the final rank
         # (schedule 2: the rank cap, whatever rho)
@@ -218,10 +213,10 @@ def aplicur(A, b, mu, opts=None, trace=None):
             trace.rebuild.append(rebuild)
         if rebuild:
             if svdfree:
-                P = SvdFreePreconditioner(C, W, Q_R, T_R, rho, eps_cur, floor=opts.svdfree_floor)
+                P = SvdFreePreconditioner(C, W, Q_R, T_R, rho, eps_cur, floor=opts.svdfree_floor, T_C=T_C)
                 pinv_t = P.inv_t
             else:
-                P = Preconditioner(C, W, Q_R, T_R, delta)
+                P = Preconditioner(C, W, Q_R, T_R, delta, T_C=T_C)
                 pinv_t = None
             nu = math.inf if final else opts.nu_lsqr
             x, it, why = plsqr_phase(A, delta, b, x, P.inv, pinv_t=pinv_t, nu=nu, sigma_l=P.sigma_l,

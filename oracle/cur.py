@@ -12,6 +12,10 @@
                         re-orthogonalisation, then QR of the remainder).
 * ``Preconditioner``  -- Alg. 2, Part 2 (SVD-based CUR preconditioner, eq. of
                         Sec. 3.1 with target level sqrt(sigma_l^2 + delta^2)).
+* ``sketched_cholqr``  -- T_C by sketched Cholesky QR (the stable choice Alg. 2
+                        and Alg. 3 Part 3 name): the R factor of a Gaussian
+                        sketch Theta C (two shifted and two plain Cholesky QR
+                        passes), then one Cholesky QR of C R^{-1}.
 * ``SvdFreePreconditioner`` -- Alg. 8 (SVD-free variant of Sec. 3.1 for mu = 0):
                         M^{-1} = T_R^{-T} A(I,J) T_C^{-1} by two triangular
                         solves, P~^{-1} = s Q_R M^{-1} Q_R^T + (I - Q_R Q_R^T)
@@ -128,6 +132,66 @@ def augment_qr(Q, T, Cnew):
     return np.hstack([Q, Qe]), Tn
 
 
+# Stream offset of the embedding Theta of sketched Cholesky QR: Theta is the
+# Gaussian embedding of seed + TC_SEED_OFFSET (stream 3), so it never
+# coincides with the Gaussian sketch of A.
+TC_SEED_OFFSET = 7919
+U64 = 2.0 ** -53
+
+
+def _chol_upper(G):
+    """Upper U with U^T U = G, or None when the Cholesky breaks down."""
+    try:
+        return np.linalg.cholesky(G).T
+    except np.linalg.LinAlgError:
+        return None
+
+
+def sketched_cholqr(C, seed):
+    """T_C (upper, positive diagonal, T_C^T T_C = C^T C to rounding) for a
+    C (m x l) too ill-conditioned for chol(C^T C), or None when even this
+    breaks down (the columns are dependent to working precision).
+
+    Steps (sketched Cholesky QR, Balabanov 2022, with the sketch's own R
+    factor by shifted Cholesky QR, Fukaya et al. 2020):
+      Theta: k x m Gaussian embedding, k = min(m, 2 l);  X_0 = Theta C;
+      two shifted passes  R_i = chol(X^T X + s I),  s = 11 (k l + l (l + 1)) u ||X||_F^2,
+      then two plain passes  R_i = chol(X^T X);  each pass X <- X R_i^{-1};
+      R = R_4 R_3 R_2 R_1 (the R factor of Theta C);
+      Q = C R^{-1};  R' = chol(Q^T Q);  T_C = R' R.
+    One shifted pass brings cond(X) to about sqrt(cond(X_0) / sqrt(u)); the
+    second makes the plain passes safe up to cond(C) near 1/u.
+    """
+    from oracle import rng
+    C = _dense(C)
+    m, l = C.shape
+    k = min(m, 2 * l)
+    X = rng.gaussian_sketch(seed + TC_SEED_OFFSET, k, m) @ C
+    R = np.eye(l)
+    for shifted in (True, True, False, False):
+        shift = 11.0 * (k * l + l * (l + 1)) * U64 * float(np.sum(X * X)) if shifted else 0.0
+        Ri = _chol_upper(X.T @ X + shift * np.eye(l))
+        if Ri is None:
+            return None
+        X = sla.solve_triangular(Ri, X.T, trans=1, lower=False).T
+        R = Ri @ R
+    Q = sla.solve_triangular(R, C.T, trans=1, lower=False).T
+    Rp = _chol_upper(Q.T @ Q)
+    if Rp is None:
+        return None
+    return np.triu(Rp @ R)
+
+
+def t_c_factor(C, seed, sketched=True):
+    """T_C of Alg. 2: chol(C^T C) when it exists, else (sketched) sketched
+    Cholesky QR; None when what was tried breaks down."""
+    CtC = C.T @ C
+    T = _chol_upper(CtC.toarray() if sp.issparse(CtC) else np.asarray(CtC))
+    if T is None and sketched:
+        T = sketched_cholqr(C, seed)
+    return T
+
+
 class Preconditioner:
     """SVD-based CUR preconditioner (Alg. 2, Part 2; Sec. 3.1).
 
@@ -136,9 +200,9 @@ class Preconditioner:
     M = T_C U T_R^T = U_M Sigma V_M^T and V = Q_R V_M.
     """
 
-    def __init__(self, C, W, Q_R, T_R, delta):
-        CtC = _dense(C.T @ C)
-        T_C = np.linalg.cholesky(CtC).T  # upper, T_C^T T_C = C^T C
+    def __init__(self, C, W, Q_R, T_R, delta, T_C=None):
+        if T_C is None:
+            T_C = np.linalg.cholesky(_dense(C.T @ C)).T  # upper, T_C^T T_C = C^T C
         M = T_C @ sla.lu_solve(sla.lu_factor(W), T_R.T)
         _, sig, VmT = np.linalg.svd(M)
         self.sigma = sig
@@ -184,9 +248,9 @@ class SvdFreePreconditioner:
     above by the Frobenius norm of M = T_C W^{-1} T_R^T.
     """
 
-    def __init__(self, C, W, Q_R, T_R, rho, eps_cur, floor=True):
-        CtC = _dense(C.T @ C)
-        T_C = np.linalg.cholesky(CtC).T
+    def __init__(self, C, W, Q_R, T_R, rho, eps_cur, floor=True, T_C=None):
+        if T_C is None:
+            T_C = np.linalg.cholesky(_dense(C.T @ C)).T
         sg = np.where(np.diag(T_R) < 0, -1.0, 1.0)
         self.Q = Q_R * sg
         T_R = T_R * sg[:, None]

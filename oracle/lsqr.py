@@ -9,7 +9,7 @@ with the warm start of Sec. 3.2 (x <- x + P^{-1} y after the phase) and the
 dynamic stopping rule of Sec. 5.3.2.  The left vector u is kept explicitly
 augmented (m + n entries), because A_mu P^{-1} has no [A~; delta I] form.
 
-Readings (listed with the others in the design doc):
+Readings (where the text leaves a choice):
 * delta = sqrt(mu): the objective weight mu of Sec. 1 enters A_mu as sqrt(mu).
 * cvgrate_j = log(phibar_{j-1}/phibar_j), cvgdiff_j = phibar_{j-1} - phibar_j
   with phibar_0 = beta_1; the dynamic rule is tested from j = 2 on, a zero

@@ -27,7 +27,8 @@ class Opts(C.Structure):
                 ("max_rank", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
                 ("max_outer", C.c_int32), ("workers", C.c_int32), ("tune", C.c_int32),
                 ("graphs", C.c_int32), ("columns", C.c_int32), ("xi", C.c_int32),
-                ("sketch", C.c_int32), ("schedule", C.c_int32), ("jacobi_tol", C.c_double)]
+                ("sketch", C.c_int32), ("schedule", C.c_int32), ("jacobi_tol", C.c_double),
+                ("tc_sketched", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -76,7 +76,7 @@ def _device(A):
 def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.0, eps_lsqr=1e-10,
               tol_ne=1e-8, max_iter=100000, max_rank=0, precond=True, precision=0, max_outer=0,
               r_probes=10, workers=0, tune=0, graphs=0, columns=0, xi=8, sketch=0, schedule=0,
-              jacobi_tol=0.0):
+              jacobi_tol=0.0, tc_sketched=False):
     lib = L.load()
     o = L.Opts()
     lib.aplicur_opts_default(C.byref(o))
@@ -93,6 +93,7 @@ def make_opts(mu=0.0, block=20, seed=7, eps_cur=-1.0, nu_prec=10.0, nu_lsqr=100.
     o.sketch = {"sparse": 0, "gaussian": 1, "gaussian_bf16": 2}[sketch] if isinstance(sketch, str) else int(sketch)
     o.schedule = int(schedule)
     o.jacobi_tol = float(jacobi_tol)
+    o.tc_sketched = int(bool(tc_sketched))
     return o
 
 

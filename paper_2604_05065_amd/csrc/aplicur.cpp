@@ -150,6 +150,17 @@ struct Blk {
   GKState* st_down = nullptr;  // pinned, 2 kp (read-backs)
   double* norm_host = nullptr; // pinned, kBlkMaxGrid x kp
   int S1max = 1, S2max = 1;
+  // The last normal-residual evaluation (blk_col_norms, mode 1: A^T B; mode
+  // 2: r = [B - A X; bs Bbot - delta X] in tm / tn and A^T r_top in wk.pn,
+  // FP64).  The next FP64 phase start on the same B, bottom block and X takes
+  // r_top and the planes from there instead of running both products again.
+  // Cleared by every phase and by anything else that writes Bp, Xp, tm, tn or
+  // wk.pn.
+  struct {
+    bool ok = false, x_zero = false;
+    const double* Bbot = nullptr;
+    double bs = 0.0;
+  } nres;
 };
 
 struct Ctx {
@@ -298,6 +309,7 @@ void validate(const aplicur_mat* A, const aplicur_opts* o) {
               "sketch must be 0 (sparse sign), 1 (Gaussian) or 2 (Gaussian, BF16 products for FP32 A)");
   APL_REQUIRE(o->schedule >= 0 && o->schedule <= 2, "schedule must be 0, 1 or 2");
   APL_REQUIRE(std::isfinite(o->jacobi_tol) && o->jacobi_tol < 1.0, "jacobi_tol must be finite and < 1");
+  APL_REQUIRE(o->tc_sketched == 0 || o->tc_sketched == 1, "tc_sketched must be 0 or 1");
 }
 
 // ------------------------------------------------------------------ product tiles
@@ -871,6 +883,80 @@ static void chol_qr2(Ctx& c, double* X, long long n, int k, long long ldx, doubl
 }
 
 // ------------------------------------------------------------------ one outer step
+// ------------------------------------------------------------------ T_C by sketched Cholesky QR
+// Stream offset of the embedding Theta below: the Gaussian embedding of seed
+// + kTcSeedOffset (stream 3), never the Gaussian sketch of A.
+constexpr uint64_t kTcSeedOffset = 7919;
+
+// T_C(0:ln, 0:ln) by sketched Cholesky QR of C(:, 0:ln), the stable choice
+// Alg. 2 and Alg. 3 Part 3 name for T_C, used when chol(C^T C) breaks down:
+// Theta (k x m Gaussian, k = min(m, 2 ln)), X = Theta C; two shifted passes
+// R_i = chol(X^T X + s I), s = 11 (k ln + ln (ln + 1)) u ||X||_F^2, and two
+// plain passes R_i = chol(X^T X), each followed by X <- X R_i^{-1}; R = R_4 R_3
+// R_2 R_1; Q = C R^{-1}; T_C = chol(Q^T Q) R.  Returns false (T_C untouched)
+// when a Cholesky breaks down or the transient memory is not available.
+static bool tc_sketched(Ctx& c, int ln, hipStream_t s) {
+  const long long m = c.m;
+  const int k = (int)std::min<long long>(m, 2LL * ln);
+  const size_t nTh = (size_t)k * m, nX = (size_t)k * ln, nQ = (size_t)m * ln, nR = (size_t)ln * ln;
+  const size_t parts[6] = {nTh, nX, nQ, nR, nR, nR};
+  size_t bytes = 0;
+  for (size_t p : parts) bytes += Arena::aligned(sizeof(double) * p);
+  bool owned = false;
+  char* tb = nullptr;
+  try {
+    tb = (char*)c.arena.transient(bytes, owned);
+  } catch (const Error&) {
+    return false;
+  }
+  double* ptr[6];
+  {
+    char* q = tb;
+    for (int i = 0; i < 6; ++i) {
+      ptr[i] = (double*)q;
+      q += Arena::aligned(sizeof(double) * parts[i]);
+    }
+  }
+  double *Th = ptr[0], *X = ptr[1], *Q = ptr[2], *G = ptr[3], *R = ptr[4], *Rt = ptr[5];
+  bool ok = true;
+  launch_gen_gauss_sketch(c.o.seed + kTcSeedOffset, k, m, Th, s);
+  gemm(c, Op::N, Op::N, k, ln, m, 1.0, Th, k, c.C, m, 0.0, X, k);
+  set_identity(R, ln, ln, s);
+  for (int pass = 0; pass < 4 && ok; ++pass) {
+    gemm(c, Op::T, Op::N, ln, ln, k, 1.0, X, k, X, k, 0.0, G, ln);
+    if (pass < 2) {
+      const double nf = dnrm2((long long)k * ln, X, c.nrm_tmp, s);
+      add_diag(G, ln, ln, 11.0 * ((double)k * ln + (double)ln * (ln + 1)) * 0x1p-53 * nf * nf, s);
+    }
+    chol_upper(c, G, ln, ln, s);
+    if (read_int(c.status_dev, s) != 0) {
+      ok = false;
+      break;
+    }
+    trsm(c, Side::Right, Uplo::Upper, Op::N, Diag::NonUnit, k, ln, 1.0, G, ln, X, k);
+    gemm(c, Op::N, Op::N, ln, ln, ln, 1.0, G, ln, R, ln, 0.0, Rt, ln);
+    std::swap(R, Rt);
+  }
+  if (ok) {
+    copy_block(c.C, m, Q, m, (int)m, ln, 1.0, s);
+    trsm(c, Side::Right, Uplo::Upper, Op::N, Diag::NonUnit, m, ln, 1.0, R, ln, Q, m);
+    gemm(c, Op::T, Op::N, ln, ln, m, 1.0, Q, m, Q, m, 0.0, G, ln);
+    chol_upper(c, G, ln, ln, s);
+    if (read_int(c.status_dev, s) != 0) ok = false;
+  }
+  if (ok) {
+    gemm(c, Op::N, Op::N, ln, ln, ln, 1.0, G, ln, R, ln, 0.0, Rt, ln);
+    zero_lower(Rt, ln, ln, s);
+    copy_block(Rt, ln, c.TC, c.L, ln, ln, 1.0, s);
+  }
+  APL_HIP(hipStreamSynchronize(s));
+  if (owned) {
+    SyncGuard g(g_capture_mu);
+    APL_HIP(hipFree(tb));
+  }
+  return ok;
+}
+
 struct StepResult {
   double rho;
   bool exhausted;
@@ -968,7 +1054,8 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
     add_block(c.P2, l, P1, L, l, k2, s);
   }
   chol_qr2(c, Qn, n, k2, n, c.TR + l + (size_t)l * L, L, s);
-  // (ix) T_C = chol(C^T C), extended: T12 = T_C^{-T} C_old^T C_new, T22 = chol(C_new^T C_new - T12^T T12)
+  // (ix) T_C = chol(C^T C), extended: T12 = T_C^{-T} C_old^T C_new, T22 = chol(C_new^T C_new - T12^T T12);
+  //      when that Cholesky breaks down, the whole T_C by sketched Cholesky QR (option tc_sketched)
   {
     double* T12 = c.TC + (size_t)l * L;
     double* T22 = c.TC + l + (size_t)l * L;
@@ -981,11 +1068,15 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
     if (l > 0)
       gemm(c, Op::T, Op::N, k2, k2, l, -1.0, T12, L, T12, L, 1.0, G22, k2);
     chol_upper(c, G22, k2, k2, s);
-    if (read_int(c.status_dev, s) != 0) {
-      if (l == 0) throw Error(APLICUR_E_BREAKDOWN, "Cholesky of C^T C failed");
-      // The new columns are numerically dependent on C: undo the step (U11
-      // back to its old value; the new slots of I, J, C, R, Q_R, T_R lie
-      // beyond the rank and are ignored) and end the rank growth.
+    if (read_int(c.status_dev, s) == 0) {
+      copy_block(G22, k2, T22, L, k2, k2, 1.0, s);
+    } else if (!(c.o.tc_sketched && tc_sketched(c, ln, s))) {
+      // C^T C is not positive definite in floating point (the new columns
+      // are nearly dependent on C), and sketched Cholesky QR is off or
+      // breaks down too.  Undo the step (U11 back to its old value; the new
+      // slots of I, J, C, R, Q_R, T_R lie beyond the rank and are ignored)
+      // and end the rank growth.
+      if (l == 0) throw Error(APLICUR_E_BREAKDOWN, "the first CUR columns are dependent (T_C)");
       gemm(c, Op::N, Op::N, l, l, k2, -1.0, c.F, L, c.H, k2, 1.0, c.U, L);
       c.J.resize(l);
       c.I.resize(l);
@@ -995,7 +1086,6 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
       res.rho = c.rho_hist.empty() ? 0.0 : c.rho_hist.back();
       return res;
     }
-    copy_block(G22, k2, T22, L, k2, k2, 1.0, s);
   }
   double rho = 0.0;
   APL_HIP(hipGetLastError());
@@ -1543,6 +1633,7 @@ static int blk_kp(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
 static void ensure_blk(Ctx& c, int kp, hipStream_t s) {
   if (!c.blk) c.blk = std::make_unique<Blk>();
   Blk& b = *c.blk;
+  b.nres.ok = false;  // every caller goes on to write Bp, Xp, tm / tn or the planes
   const long long m = c.m, n = c.n;
   const size_t vs = c.op.f64 ? 8 : 4;
   if (!b.At) {
@@ -1664,6 +1755,12 @@ static std::vector<double> blk_col_norms(Ctx& c, int k, int mode, const double* 
   Blk& b = *c.blk;
   const int kp = b.kp;
   const int cnt = blk_norms(b.op, kp, mode, B, Bbot, bs, X, c.delta, b.tm, b.tn, b.wk, s);
+  if (mode == 1 || mode == 2) {
+    b.nres.ok = B == b.Bp && (mode == 1 || X == b.Xp);
+    b.nres.x_zero = mode == 1;
+    b.nres.Bbot = Bbot;
+    b.nres.bs = bs;
+  }
   APL_HIP(hipMemcpyAsync(b.norm_host, b.wk.norm_part, sizeof(double) * cnt * kp, hipMemcpyDeviceToHost, s));
   APL_HIP(hipStreamSynchronize(s));
   std::vector<double> out(k, 0.0);
@@ -1682,6 +1779,11 @@ struct BlkParam {
   int budget = 0;
 };
 
+// Work per queued chunk of blocked iterations (seconds at an assumed stream
+// rate of the products).
+constexpr double kBlkChunkSeconds = 1.0e-3;
+constexpr double kBlkChunkBytesPerSecond = 4.0e12;
+
 // One warm-started phase for the active columns of min || A_mu X - [B; bs Bbot] ||:
 // FP64, or with precision 1 FP32 recurrences from an FP64 residual; FP32
 // refinement phases (nu = inf, eps_lsqr = 0, X warm, delta > 0) solve for the
@@ -1689,7 +1791,8 @@ struct BlkParam {
 template <class V>
 static std::vector<PhaseOut> run_phase_blk_t(Ctx& c, const BlkOp& A, BlkVecs<V> vec, const BlkPrec* P,
                                              const std::vector<BlkParam>& prm, const double* B, const double* Bbot,
-                                             double bs, bool x_zero, double rel_tol, hipStream_t s) {
+                                             double bs, bool x_zero, double rel_tol, hipStream_t s,
+                                             const double* r_ready = nullptr) {
   Blk& b = *c.blk;
   const int kp = b.kp, k = (int)prm.size();
   long long budget = 0;
@@ -1718,7 +1821,7 @@ static std::vector<PhaseOut> run_phase_blk_t(Ctx& c, const BlkOp& A, BlkVecs<V> 
     b.st_up[kp + j] = h;
   }
   APL_HIP(hipMemcpyAsync(b.st, b.st_up, sizeof(GKState) * 2 * kp, hipMemcpyHostToDevice, s));
-  blk_phase_init<V>(b.op, A, P, kp, B, Bbot, bs, b.Xp, x_zero, c.delta, vec, b.st, b.wk, s);
+  blk_phase_init<V>(b.op, A, P, kp, B, Bbot, bs, b.Xp, x_zero, c.delta, vec, b.st, b.wk, s, r_ready);
   auto read = [&]() {
     APL_HIP(hipMemcpyAsync(b.st_down, b.st, sizeof(GKState) * 2 * kp, hipMemcpyDeviceToHost, s));
     APL_HIP(hipStreamSynchronize(s));
@@ -1731,14 +1834,23 @@ static std::vector<PhaseOut> run_phase_blk_t(Ctx& c, const BlkOp& A, BlkVecs<V> 
     }
     return all;
   };
-  int chunk = 8;
+  // Iterations are queued in chunks between reads of the stop flags.  The
+  // blocked products do their whole work even after every column has stopped,
+  // so the chunk is capped to about kBlkChunkSeconds of estimated work: one
+  // iteration per read when an iteration streams gigabytes (the wait for the
+  // read is then a small fraction of it), up to 64 when it is short.
+  const double elem = A.A16 ? 2.0 : (A.f64 ? 8.0 : 4.0);
+  double iter_bytes = 2.0 * (double)A.m * (double)A.n * elem;
+  if (P) iter_bytes += 4.0 * (double)A.n * (double)P->ell * 8.0;
+  const int cap = (int)std::max(1.0, std::min(64.0, kBlkChunkSeconds * kBlkChunkBytesPerSecond / iter_bytes));
+  int chunk = std::min(8, cap);
   long long launched = 0;
   APL_HIP(hipGetLastError());
   bool done = read();
   while (!done) {
     for (int i = 0; i < chunk; ++i) blk_iteration<V>(A, P, kp, c.delta, vec, b.st, b.wk, s);
     launched += chunk;
-    chunk = std::min(chunk * 2, 64);
+    chunk = std::min(chunk * 2, cap);
     APL_HIP(hipGetLastError());
     done = read();
     if (!done && launched > budget + 128)
@@ -1764,6 +1876,8 @@ static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::
   for (const BlkParam& q : prm)
     if (q.active) refinement &= std::isinf(q.nu) && q.eps_lsqr == 0.0;
   b.last_bf16 = false;
+  const bool reuse = b.nres.ok && b.nres.x_zero == x_zero && b.nres.Bbot == Bbot && b.nres.bs == bs;
+  b.nres.ok = false;
   if (c.fp32 && (x_zero || !refinement || c.delta > 0.0)) {
     const bool use16 = c.bf16 && b.bf16_live;
     const BlkOp& op = use16 ? b.op16 : b.op32;
@@ -1777,7 +1891,8 @@ static std::vector<PhaseOut> run_phase_blk(Ctx& c, const BlkPrec* P, const std::
     }
     return run_phase_blk_t<float>(c, op, b.vec32, P, prm, b.Bp, Bbot, bs, x_zero, rt, s);
   }
-  return run_phase_blk_t<double>(c, b.op, b.vec, P, prm, b.Bp, Bbot, bs, x_zero, 0.0, s);
+  const double* r_ready = reuse ? (x_zero ? b.Bp : b.tm) : nullptr;
+  return run_phase_blk_t<double>(c, b.op, b.vec, P, prm, b.Bp, Bbot, bs, x_zero, 0.0, s, r_ready);
 }
 
 // After a phase with BF16 products: if some column's eta fell by less than

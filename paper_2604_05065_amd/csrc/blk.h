@@ -91,10 +91,13 @@ constexpr int kBlkMaxGrid = 256;  // workgroups of the element-wise kernels (the
 // Phase start: r = [B - Ares X; bs Bbot - delta X] (FP64 with the values of
 // Ares; X = 0 when x_zero) stored in the V vectors, then as the single-column
 // phase start with the operator A (beta, the first A^T product and alpha).
+// r_ready (V = double only): the top block of r as already formed (B - Ares X,
+// or B when x_zero) with wk.pn holding the planes of A^T r_top from the same
+// kernels; both products are then skipped and the results are unchanged.
 template <class V>
 void blk_phase_init(const BlkOp& Ares, const BlkOp& A, const BlkPrec* P, int kp, const double* B, const double* Bbot,
                     double bs, const double* X, bool x_zero, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
-                    hipStream_t s);
+                    hipStream_t s, const double* r_ready = nullptr);
 template <class V>
 void blk_iteration(const BlkOp& A, const BlkPrec* P, int kp, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
                    hipStream_t s);

@@ -986,8 +986,8 @@ static void blk_pcoef(const BlkOp& A, const BlkPrec& P, int kp, const V* z, BlkW
 
 template <class V>
 static void blk_bwd(const BlkOp& A, const BlkPrec* P, int kp, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
-                    hipStream_t s) {
-  blk_prod<V>(A, true, vec.u_top, kp, (V*)wk.pn, s);
+                    hipStream_t s, bool pn_ready = false) {
+  if (!pn_ready) blk_prod<V>(A, true, vec.u_top, kp, (V*)wk.pn, s);
   const unsigned g = blk_grid(A.n, kp);
   if (!P) {
     BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_bwd<V, KP, true>), dim3(g), dim3(kBlock), 0, s, (const V*)wk.pn, A.Sn,
@@ -1008,9 +1008,11 @@ static void blk_bwd(const BlkOp& A, const BlkPrec* P, int kp, double delta, BlkV
 template <class V>
 void blk_phase_init(const BlkOp& Ares, const BlkOp& A, const BlkPrec* P, int kp, const double* B, const double* Bbot,
                     double bs, const double* X, bool x_zero, double delta, BlkVecs<V> vec, GKState* st, BlkWork& wk,
-                    hipStream_t s) {
+                    hipStream_t s, const double* r_ready) {
+  APL_REQUIRE((!r_ready || std::is_same<V, double>::value), "blk_phase_init: a formed residual needs FP64 vectors");
   double* pm = (double*)wk.pm;
-  if (!x_zero) {
+  const bool prod = !x_zero && !r_ready;
+  if (prod) {
     if (Ares.f64)
       rows_gemm<double, double, double>((const double*)Ares.A, A.m, A.n, Ares.ld, X, kp, pm, Ares.Sm, s);
     else
@@ -1018,12 +1020,13 @@ void blk_phase_init(const BlkOp& Ares, const BlkOp& A, const BlkPrec* P, int kp,
   }
   const unsigned g = blk_grid(std::max(A.m, A.n), kp);
   BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_resid<V, KP>), dim3(g), dim3(kBlock), 0, s,
-                                       (const double*)(x_zero ? nullptr : pm), Ares.Sm, A.m, A.n, B, Bbot, bs,
-                                       x_zero ? nullptr : X, delta, vec.u_top, vec.u_bot, wk.beta_part));
+                                       (const double*)(prod ? pm : nullptr), Ares.Sm, A.m, A.n,
+                                       r_ready ? r_ready : B, Bbot, bs, x_zero ? nullptr : X, delta, vec.u_top,
+                                       vec.u_bot, wk.beta_part));
   wk.beta_count = g;
   fill_zero<V>(vec.y, A.n * kp, s);
   fill_zero<V>(vec.w, A.n * kp, s);
-  blk_bwd<V>(A, P, kp, delta, vec, st, wk, s);
+  blk_bwd<V>(A, P, kp, delta, vec, st, wk, s, r_ready != nullptr);
 }
 
 template <class V>
@@ -1106,10 +1109,10 @@ int blk_norms(const BlkOp& A, int kp, int mode, const double* B, const double* B
 
 template void blk_phase_init<double>(const BlkOp&, const BlkOp&, const BlkPrec*, int, const double*, const double*,
                                      double, const double*, bool, double, BlkVecs<double>, GKState*, BlkWork&,
-                                     hipStream_t);
+                                     hipStream_t, const double*);
 template void blk_phase_init<float>(const BlkOp&, const BlkOp&, const BlkPrec*, int, const double*, const double*,
                                     double, const double*, bool, double, BlkVecs<float>, GKState*, BlkWork&,
-                                    hipStream_t);
+                                    hipStream_t, const double*);
 template void blk_iteration<double>(const BlkOp&, const BlkPrec*, int, double, BlkVecs<double>, GKState*, BlkWork&,
                                     hipStream_t);
 template void blk_iteration<float>(const BlkOp&, const BlkPrec*, int, double, BlkVecs<float>, GKState*, BlkWork&,

@@ -32,8 +32,8 @@ def test_struct_layouts_match_header():
     from paper_2604_05065_amd import _lib
     # sizes fixed by the header's field lists (natural alignment, x86-64)
     assert ctypes.sizeof(_lib.Mat) == 4 + 4 + 8 * 4 + 8 * 3
-    assert ctypes.sizeof(_lib.Opts) == 8 + 8 + 8 * 6 + 4 * 5 + 4 * 7 + 8
-    assert _lib.Opts.jacobi_tol.offset == 112
+    assert ctypes.sizeof(_lib.Opts) == 8 + 8 + 8 * 6 + 4 * 5 + 4 * 7 + 8 + 8  # tc_sketched + pad
+    assert _lib.Opts.jacobi_tol.offset == 112 and _lib.Opts.tc_sketched.offset == 120
     assert ctypes.sizeof(_lib.Info) == 4 * 8 + 8 * 7
     assert _lib.Info.eta.offset == 32
 

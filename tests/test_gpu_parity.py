@@ -1,9 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
 Tolerances: FP64 element-wise results 1e-10 relative to the operand norms
-(the stated FP64 bar); solutions within the conditioning floor of the
-normal-equation residual they reach (parity tolerances);
-integer / index results bit-exact.
+(the stated FP64 bar); solutions within the conditioning bound of the
+normal-equation residual they reach (tests/bounds.py); integer / index
+results bit-exact.
 """
 import math
 
@@ -187,6 +187,37 @@ def test_dependent_columns_end_rank_growth(lib):
         ranks = ctx.query(8)
     assert ranks[-1] == ranks[-2] and abs(int(ranks[-1]) - tr.ranks[-1]) <= 20
     assert info.status == 0 and ne_residual(A, b, x.cpu().numpy(), 0.0) <= 1.5e-8
+
+
+def test_sketched_cholqr_option_continues_rank_growth(lib):
+    """With tc_sketched, a breakdown of chol(C^T C) takes T_C from sketched
+    Cholesky QR (the same Gaussian embedding, seed and passes as the oracle's
+    tc = "sketched") instead of undoing the step.  Single-shot schedule 2
+    grows the CUR to the rank cap before the one build, so the rank sequence
+    is decided by the breakdowns alone: by default the growth ends at 260 (the
+    rank repeats), with the option it reaches the cap of 400 as in the oracle;
+    the indices equal the oracle's up to rank 260, and the larger P needs
+    fewer iterations to the same tolerance."""
+    r = np.random.default_rng(0)
+    A = synth.dense_svd(r, 1200, 1000, synth.paper_sigma(1000, "smooth"))
+    b = A @ r.standard_normal(1000)
+    mu, opts = 1e-10, dict(block=20, tol_ne=1e-8, max_iter=20000, schedule=2, max_rank=400)
+    tr = Trace()
+    aplicur(A, b, mu, Options(tc="sketched", **opts), tr)
+    out = {}
+    for sk in (False, True):
+        with lib.Context(_t(A), mu=mu, tc_sketched=sk, **opts) as ctx:
+            x, info = ctx.solve(_t(b))
+            out[sk] = ([int(v) for v in ctx.query(8)], ctx.query(5), info, x.cpu().numpy())
+    (r0, _, i0, x0), (r1, J1, i1, x1) = out[False], out[True]
+    print(f"[parity] sketched T_C: GPU ranks {r1} ({i1.iters} it), default {r0} ({i0.iters} it), "
+          f"oracle {tr.ranks} ({tr.iters} it)")
+    assert r0[-1] == r0[-2] == 260
+    assert r1 == tr.ranks == list(range(20, 401, 20))
+    np.testing.assert_array_equal(J1[:260], tr.J[:260])
+    assert i0.status == 0 and ne_residual(A, b, x0, mu) <= 1.5e-8
+    assert i1.status == 0 and ne_residual(A, b, x1, mu) <= 1.5e-8
+    assert i1.iters < i0.iters
 
 
 def test_solution_with_xi_matches_oracle(lib):

@@ -168,8 +168,9 @@ def test_single_shot_schedules(schedule):
 def test_dependent_columns_end_rank_growth():
     """Root-exponential decay to 1e-13 with mu = 0: the cross approximation
     reaches columns numerically dependent on C (C^T C not positive definite in
-    floating point); that step is undone and the growth ends there (the rank
-    repeats in the trace), and the solve still reaches its tolerance."""
+    floating point); by default that step is undone and the growth ends there
+    (the rank repeats in the trace), and the solve still reaches its
+    tolerance."""
     r = np.random.default_rng(0)
     A = synth.dense_svd(r, 1200, 1000, synth.paper_sigma(1000, "smooth"))
     b = A @ r.standard_normal(1000)
@@ -177,3 +178,29 @@ def test_dependent_columns_end_rank_growth():
     x = aplicur(A, b, 0.0, Options(block=20, tol_ne=1e-8, max_iter=20000), tr)
     assert tr.ranks[-1] == tr.ranks[-2] and tr.rebuild[-1]
     assert ne_residual(A, b, x, 0.0) <= 1e-8
+
+
+def test_sketched_cholqr_continues_the_rank_growth():
+    """The same set at mu = 1e-10, single-shot schedule 2 (the CUR grows to the
+    rank cap of 400 before the one build): by default the breakdown of
+    chol(C^T C) at rank 280 ends the growth at 260; with tc = "sketched" T_C
+    comes from sketched Cholesky QR (T^T T = C^T C to rounding while the
+    plain Cholesky of the final C^T C fails), the ranks reach the cap, and the
+    larger P needs fewer iterations to the same tolerance."""
+    from oracle.cur import t_c_factor
+    r = np.random.default_rng(0)
+    A = synth.dense_svd(r, 1200, 1000, synth.paper_sigma(1000, "smooth"))
+    b = A @ r.standard_normal(1000)
+    mu, opts = 1e-10, dict(block=20, tol_ne=1e-8, max_iter=20000, schedule=2, max_rank=400)
+    tr0, tr = Trace(), Trace()
+    x0 = aplicur(A, b, mu, Options(**opts), tr0)
+    x = aplicur(A, b, mu, Options(tc="sketched", **opts), tr)
+    assert tr0.ranks[-1] == tr0.ranks[-2] == 260
+    assert tr.ranks == list(range(20, 401, 20))
+    C = A[:, tr.J]
+    with pytest.raises(np.linalg.LinAlgError):
+        np.linalg.cholesky(C.T @ C)
+    T = t_c_factor(C, Options().seed)
+    assert T is not None and np.linalg.norm(C.T @ C - T.T @ T) <= 1e-14 * np.linalg.norm(C) ** 2
+    assert ne_residual(A, b, x0, mu) <= 1e-8 and ne_residual(A, b, x, mu) <= 1e-8
+    assert tr.iters < tr0.iters

@@ -183,3 +183,44 @@ def test_sparse_and_dense_paths_agree():
     b = augment_cur(Ad, Yd, np.zeros(0, int), np.zeros(0, int), None, None, None, 6)
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("kappa", [1e6, 1e10, 1e14])
+def test_sketched_cholqr_is_the_r_factor(kappa):
+    """Sketched Cholesky QR (T_C when chol(C^T C) breaks down): an upper
+    triangular T with positive diagonal and T^T T = C^T C to rounding,
+    through condition numbers where the plain Cholesky of C^T C fails
+    (kappa^2 u > 1), and the same factor as that Cholesky where it exists;
+    the rows of C T^{-1} span range(C) with a Gram matrix near I."""
+    from oracle.cur import sketched_cholqr
+    r = np.random.default_rng(int(np.log10(kappa)))
+    m, l = 2500, 150
+    U, _ = np.linalg.qr(r.standard_normal((m, l)))
+    V, _ = np.linalg.qr(r.standard_normal((l, l)))
+    C = (U * np.logspace(0, -np.log10(kappa), l)) @ V.T
+    T = sketched_cholqr(C, 5)
+    assert T is not None
+    assert np.allclose(T, np.triu(T)) and np.all(np.diag(T) > 0)
+    assert np.linalg.norm(C.T @ C - T.T @ T) <= 1e-14 * np.linalg.norm(C) ** 2
+    Q = np.linalg.solve(T.T, C.T).T
+    assert np.linalg.norm(Q.T @ Q - np.eye(l), 2) <= 1e-15 * kappa * 1e2
+    try:
+        Tc = np.linalg.cholesky(C.T @ C).T
+    except np.linalg.LinAlgError:
+        assert kappa ** 2 * 2.0 ** -53 > 1.0  # the plain Cholesky fails only past its limit
+    else:
+        assert np.abs(T - Tc).max() <= 1e-12 * kappa * np.abs(Tc).max()
+
+
+def test_sketched_cholqr_equals_the_qr_r_factor():
+    """Whatever the embedding, T = R' R is the R factor of C: C = (C R^{-1}
+    R'^{-1}) (R' R) with an orthonormal first factor and a positive-diagonal
+    upper second one, which is unique; T equals numpy's QR factor (signs
+    made positive) to rounding (here with k = min(m, 2 l) = m)."""
+    from oracle.cur import sketched_cholqr
+    r = np.random.default_rng(3)
+    C = r.standard_normal((40, 30)) @ np.diag(np.logspace(0, -5, 30))
+    T = sketched_cholqr(C, 2)  # k = min(m, 2 l) = 40 = m
+    Rq = np.linalg.qr(C)[1]
+    Rq = Rq * np.sign(np.diag(Rq))[:, None]
+    assert np.abs(T - Rq).max() <= 1e-9 * np.abs(Rq).max()
