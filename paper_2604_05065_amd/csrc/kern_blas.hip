@@ -3,6 +3,7 @@
 // blocked triangular solves, a fixed-order 2-norm, and the Gaussian sketch
 // product with FP32 or BF16 inputs and FP64 accumulation.
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "blas.h"
@@ -167,18 +168,36 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// k chunks for a shape: enough workgroups for the chip when the output has
-// few tiles, chunks of at least 512 (a multiple of the stage depth).
+// k chunks for a shape.  Two workgroups of k_dgemm fit a CU (waves_per_eu 2),
+// so kGConcurrent of them run at once and a launch takes about
+// ceil(tiles parts / kGConcurrent) rounds of kchunk-deep tiles; each part
+// beyond the first adds a plane of the output written and read again.  The
+// count (1 to 64, chunks of at least 256, a multiple of the stage depth)
+// minimises that estimate: MFMA time per round and k from the FP64 peak at
+// about 0.7 (kGRoundUsPerK), plane traffic at about 5 TB/s.  A function of the
+// shape only.
+constexpr long long kGConcurrent = 512;
+constexpr double kGRoundUsPerK = 0.3;
+constexpr double kGPlaneUsPerWord = 8.0 / 5.0e6;
 static int gemm_chunks(long long m, long long n, long long k, long long* kchunk) {
   const long long tiles = ((m + kGM - 1) / kGM) * ((n + kGM - 1) / kGM);
-  long long parts = 1;
-  if (tiles < 256 && k >= 1024) parts = std::min<long long>((512 + tiles - 1) / tiles, k / 512);
-  parts = std::max<long long>(1, std::min<long long>(parts, 64));
-  long long kc = (k + parts - 1) / parts;
-  kc = (kc + kGKs - 1) / kGKs * kGKs;
-  parts = (k + kc - 1) / kc;
-  *kchunk = kc;
-  return (int)parts;
+  const long long pmax = std::max<long long>(1, std::min<long long>(64, k / 256));
+  long long best_p = 1, best_kc = (k + kGKs - 1) / kGKs * kGKs;
+  double best = INFINITY;
+  for (long long p = 1; p <= pmax; ++p) {
+    const long long kc = ((k + p - 1) / p + kGKs - 1) / kGKs * kGKs;
+    const long long parts = (k + kc - 1) / kc;
+    const long long rounds = (tiles * parts + kGConcurrent - 1) / kGConcurrent;
+    double cost = (double)rounds * (double)kc * kGRoundUsPerK;
+    if (parts > 1) cost += (double)(2 * parts + 1) * (double)(m * n) * kGPlaneUsPerWord;
+    if (cost < best * 0.98) {  // more parts only for a clear gain
+      best = cost;
+      best_p = parts;
+      best_kc = kc;
+    }
+  }
+  *kchunk = best_kc;
+  return (int)best_p;
 }
 
 size_t dgemm_work(Op ta, Op tb, long long m, long long n, long long k) {
@@ -246,7 +265,20 @@ __device__ __forceinline__ void load_diag(double (*Ts)[kTB + 1], const double* T
   }
 }
 
-// Left: op(T) X = B for the k x ncols block B (k <= kTB); thread = column.
+// v from lane src of the wave (src uniform)
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Left: op(T) X = B for the k x ncols block B (k <= kTB): one wave per column,
+// lane i holding x_i.  Column-oriented substitution: at step i the lane of
+// the pivot finishes x_i (division by the diagonal), and every lane still to
+// come subtracts op(T)(lane, i) x_i, so each x_j takes its terms in the order
+// of i (ascending for LOWER, descending otherwise).
+constexpr int kTrsmCols = kBlock / kWave;  // columns per workgroup
 template <bool LOWER>
 __global__ void __launch_bounds__(kBlock)
     k_trsm_left(int k, long long ncols, const double* __restrict__ T, long long ldt, int trans, int unit, double* B,
@@ -254,37 +286,25 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ double Ts[kTB][kTB + 1];
   load_diag(Ts, T, ldt, k, trans);
   __syncthreads();
-  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= ncols) return;
+  const int lane = threadIdx.x % kWave;
+  const long long c = (long long)blockIdx.x * kTrsmCols + threadIdx.x / kWave;
+  if (c >= ncols) return;  // whole waves leave together; no barrier follows
   double* col = B + c * ldb;
-  double x[kTB];
-#pragma unroll
-  for (int i = 0; i < kTB; ++i) x[i] = i < k ? col[i] : 0.0;
+  double x = lane < k ? col[lane] : 0.0;
   if (LOWER) {
-#pragma unroll
-    for (int i = 0; i < kTB; ++i) {
-      if (i < k) {
-        double acc = x[i];
-#pragma unroll
-        for (int j = 0; j < i; ++j) acc -= Ts[i][j] * x[j];
-        x[i] = unit ? acc : acc / Ts[i][i];
-      }
+    for (int i = 0; i < k; ++i) {
+      if (lane == i && !unit) x = x / Ts[i][i];
+      const double xi = lane_bcast(x, i);
+      if (lane > i && lane < k) x -= Ts[lane][i] * xi;
     }
   } else {
-#pragma unroll
-    for (int i = kTB - 1; i >= 0; --i) {
-      if (i < k) {
-        double acc = x[i];
-#pragma unroll
-        for (int j = i + 1; j < kTB; ++j)
-          if (j < k) acc -= Ts[i][j] * x[j];
-        x[i] = unit ? acc : acc / Ts[i][i];
-      }
+    for (int i = k - 1; i >= 0; --i) {
+      if (lane == i && !unit) x = x / Ts[i][i];
+      const double xi = lane_bcast(x, i);
+      if (lane < i) x -= Ts[lane][i] * xi;
     }
   }
-#pragma unroll
-  for (int i = 0; i < kTB; ++i)
-    if (i < k) col[i] = x[i];
+  if (lane < k) col[lane] = x;
 }
 
 // Right: X op(T) = B for the nrows x k block B (k <= kTB); thread = row.
@@ -353,7 +373,7 @@ void dtrsm(Side side, Uplo uplo, Op trans, Diag diag, long long m, long long n, 
     for (long long q = 0; q < nb; ++q) {
       const long long blk = lower ? q : nb - 1 - q;
       const long long j0 = blk * kTB, jb = std::min<long long>(kTB, k - j0);
-      const unsigned g = ceil_div(n, kBlock);
+      const unsigned g = ceil_div(n, kTrsmCols);
       if (lower)
         hipLaunchKernelGGL(k_trsm_left<true>, dim3(g), dim3(kBlock), 0, s, (int)jb, n, sub(j0, j0), ldt, tr, unit,
                            B + j0, ldb);
