@@ -90,6 +90,8 @@ __global__ void __launch_bounds__(kBlock) k_lupp_init(const double* X, int r, in
   }
 }
 
+constexpr int kLuppUnroll = 16;  // columns of a row updated per batch of loads
+
 // One pivot step: the global best of the previous candidates is the pivot
 // (original row p) of position q; positions are updated as if the rows were
 // swapped (LAPACK order); the multipliers of the remaining rows are stored in
@@ -130,9 +132,29 @@ __global__ void __launch_bounds__(kBlock)
     if (pn <= q) continue;  // pivot rows (positions 0..q) are not updated
     const double l = X[i + q * ld] / piv_val;
     X[i + q * ld] = l;
-    for (int j = q + 1; j < cend; ++j) X[i + j * ld] -= l * X[p + j * ld];
+    // the row's entries and the pivot row's, kLuppUnroll columns at a time,
+    // all loaded before any is updated (independent loads in flight)
+    double first = 0.0;
+    for (int j0 = q + 1; j0 < cend; j0 += kLuppUnroll) {
+      double xv[kLuppUnroll], pr[kLuppUnroll];
+#pragma unroll
+      for (int u = 0; u < kLuppUnroll; ++u) {
+        const int j = j0 + u;
+        xv[u] = j < cend ? X[i + j * ld] : 0.0;
+        pr[u] = j < cend ? X[p + j * ld] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kLuppUnroll; ++u) {
+        const int j = j0 + u;
+        if (j < cend) {
+          const double nv = xv[u] - l * pr[u];
+          X[i + j * ld] = nv;
+          if (j == q + 1) first = nv;
+        }
+      }
+    }
     if (q + 1 < cend) {
-      const double a = fabs(X[i + (q + 1) * ld]);
+      const double a = fabs(first);
       if (better(a, pn, v, bp)) {
         v = a;
         bp = pn;
