@@ -711,7 +711,8 @@ __device__ __forceinline__ int circle_mate(int r, int i) {
 // (i, kJW + (i + k) mod kJW), i < kJW, so kJW steps meet every pair of one
 // column of each block once.
 __device__ __forceinline__ int cross_mate(int k, int i) {
-  return i < kJW ? kJW + (i + k) % kJW : (i - kJW - k + 2 * kJW) % kJW;
+  static_assert((kJW & (kJW - 1)) == 0, "cross_mate: kJW a power of two");
+  return i < kJW ? kJW + ((unsigned)(i + k) & (kJW - 1)) : ((unsigned)(i - kJW - k + 2 * kJW) & (kJW - 1));
 }
 
 // plane `slot` of step r: (p, q), p < q
@@ -770,7 +771,8 @@ __device__ __forceinline__ void jacobi_rot(double gpp, double gqq, double gpq, d
 // (row-major) and flag[pair] = 0, or flag = 1 (skip: X and V keep the
 // pair's columns).
 constexpr int kJRT = kJP * kJP;  // threads of k_jac_rot (one per entry)
-__global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpart, int nchunk, int full, double d2,
+template <bool FULL>
+__global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpart, int nchunk, double d2,
                                                    double skip, double* __restrict__ sq_part,
                                                    double* __restrict__ qbuf, int* __restrict__ flag) {
   __shared__ double G[2][kJP][kJP + 1];
@@ -810,7 +812,7 @@ __global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpa
   // step 0's rotations from G itself
   if (tid < kJW) {
     int p, q;
-    step_plane(full != 0, 0, tid, p, q);
+    step_plane(FULL, 0, tid, p, q);
     double c, s;
     jacobi_rot(G[0][p][p], G[0][q][q], G[0][p][q], c, s);
     cs[0][p] = cs[0][q] = c;
@@ -829,7 +831,7 @@ __global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpa
     if (tid == 0) flag[pair] = 1;
     return;
   }
-  const bool fl = full != 0;
+  constexpr bool fl = FULL;
   const int steps = fl ? kJP - 1 : kJW;
   auto mate = [&](int r, int x) { return fl ? circle_mate(r, x) : cross_mate(r, x); };
   int cur = 0;
@@ -992,9 +994,12 @@ int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long 
     for (int r = 0; r < rounds; ++r) {
       hipLaunchKernelGGL(k_jac_gram, dim3(nchunk, npairs), dim3(kJT), 0, s, (const double*)X, ldx, n, nblk, r, rpc,
                          nchunk, jw.gpart);
-      hipLaunchKernelGGL(k_jac_rot, dim3(npairs), dim3(kJRT), 0, s, (const double*)jw.gpart, nchunk, r == 0 ? 1 : 0,
-                         delta2, skip,
-                         jw.sq_part + (long long)r * npairs, jw.qbuf, jw.flag);
+      if (r == 0)
+        hipLaunchKernelGGL(k_jac_rot<true>, dim3(npairs), dim3(kJRT), 0, s, (const double*)jw.gpart, nchunk, delta2,
+                           skip, jw.sq_part + (long long)r * npairs, jw.qbuf, jw.flag);
+      else
+        hipLaunchKernelGGL(k_jac_rot<false>, dim3(npairs), dim3(kJRT), 0, s, (const double*)jw.gpart, nchunk,
+                           delta2, skip, jw.sq_part + (long long)r * npairs, jw.qbuf, jw.flag);
       hipLaunchKernelGGL(k_jac_apply, ga, dim3(kJT), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
                          (const double*)jw.qbuf, (const int*)jw.flag);
     }
