@@ -25,27 +25,40 @@ __device__ __forceinline__ bool better(double va, int pa, double vb, int pb) {
   return va > vb || (va == vb && pa < pb);
 }
 
+// The workgroup's best (value, position, row) by `better`: a butterfly over
+// each wave's lanes, then the waves' results in order.  `better` is a total
+// order on distinct positions, so the result does not depend on the tree.
 __device__ void block_argmax(double& v, int& p, int& idx) {
-  __shared__ double sv[kBlock];
-  __shared__ int sp[kBlock], si[kBlock];
-  sv[threadIdx.x] = v;
-  sp[threadIdx.x] = p;
-  si[threadIdx.x] = idx;
-  __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      int o = threadIdx.x + off;
-      if (better(sv[o], sp[o], sv[threadIdx.x], sp[threadIdx.x])) {
-        sv[threadIdx.x] = sv[o];
-        sp[threadIdx.x] = sp[o];
-        si[threadIdx.x] = si[o];
-      }
+  constexpr int NW = kBlock / kWave;
+  __shared__ double sv[NW];
+  __shared__ int sp[NW], si[NW];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, kWave);
+    const int op = __shfl_xor(p, off, kWave);
+    const int oi = __shfl_xor(idx, off, kWave);
+    if (better(ov, op, v, p)) {
+      v = ov;
+      p = op;
+      idx = oi;
     }
-    __syncthreads();
   }
+  if (threadIdx.x % kWave == 0) {
+    sv[threadIdx.x / kWave] = v;
+    sp[threadIdx.x / kWave] = p;
+    si[threadIdx.x / kWave] = idx;
+  }
+  __syncthreads();
   v = sv[0];
   p = sp[0];
   idx = si[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w)
+    if (better(sv[w], sp[w], v, p)) {
+      v = sv[w];
+      p = sp[w];
+      idx = si[w];
+    }
   __syncthreads();
 }
 
