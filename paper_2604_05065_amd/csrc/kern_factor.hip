@@ -627,6 +627,8 @@ constexpr int kJW = 16;       // columns per block
 constexpr int kJP = 2 * kJW;  // columns per pair
 constexpr int kJT = 256;      // threads per workgroup (4 waves)
 constexpr int kJMaxChunks = 16;
+constexpr int kJAJ = 1;       // 16-row tiles per wave in k_jac_apply
+constexpr int kJARows = (kJT / kWave) * 16 * kJAJ;  // rows per workgroup of k_jac_apply
 static_assert(kJP % 16 == 0 && (kJP / 16) * (kJP / 16) <= 4, "pair Gram: at most one 16x16 tile per wave");
 
 __device__ __forceinline__ void pair_of(int round, int nblk, int slot, int& a, int& b) {
@@ -884,8 +886,8 @@ __global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpa
   if (tid == 0) flag[pair] = 0;
 }
 
-// Rows [64 (4 blockIdx.x + wave), + 64) of X (blockIdx.z = 0) or V (1), the
-// pair's columns, times Q: D = Q^T X_rows^T on the FP64 16x16x4 MFMA (A lane
+// Rows [kJARows blockIdx.x + 16 kJAJ wave, + 16 kJAJ) of X (blockIdx.z = 0)
+// or V (1), the pair's columns, times Q: D = Q^T X_rows^T on the FP64 16x16x4 MFMA (A lane
 // (i, q) = Q[k + q][16 It + i] from LDS, B lane (i, q) = X[row0 + i][col(k + q)],
 // D lane (i, q) register r = the new X[row0 + i][col(16 It + q + 4r)]).  All of
 // the wave's loads precede its stores, and no other wave touches these rows
@@ -894,21 +896,21 @@ __global__ void __launch_bounds__(kJT) k_jac_apply(double* __restrict__ X, long 
                                                     double* __restrict__ V, long long ldv, int vrows, int nblk,
                                                     int round, const double* __restrict__ qbuf,
                                                     const int* __restrict__ flag) {
-  constexpr int NI = kJP / 16, KS = kJP / 4, NJ = 4;
+  constexpr int NI = kJP / 16, KS = kJP / 4, NJ = kJAJ;
   __shared__ double Qs[kJP][kJP + 1];
   const int pair = blockIdx.y;
   if (flag[pair]) return;  // uniform
   double* M = blockIdx.z ? V : X;
   const long long ld = blockIdx.z ? ldv : ldx;
   const int rows = blockIdx.z ? vrows : xrows;
-  if ((long long)blockIdx.x * kJT >= rows) return;  // uniform
+  if ((long long)blockIdx.x * kJARows >= rows) return;  // uniform
   int a, b;
   pair_of(round, nblk, pair, a, b);
   const double* qp = qbuf + (long long)pair * (kJP * kJP);
   for (int e = threadIdx.x; e < kJP * kJP; e += kJT) Qs[e / kJP][e % kJP] = qp[e];
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, li = lane % 16, lq = lane / 16;
-  const int r0 = blockIdx.x * kJT + wave * 64;
+  const int r0 = blockIdx.x * kJARows + wave * (16 * NJ);
   if (r0 >= rows) return;  // no barrier follows
   double xv[NJ][KS];
 #pragma unroll
@@ -1001,7 +1003,7 @@ int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long 
   jacobi_chunks(n, npairs, nchunk, rpc);
   const JacWork jw = carve_jacobi(work, n, npad);
   const int arows = std::max(n, npad);
-  const dim3 ga(ceil_div(arows, kJT), npairs, 2);
+  const dim3 ga(ceil_div(arows, kJARows), npairs, 2);
   int sweeps = 0;
   for (; sweeps < max_sweeps; ++sweeps) {
     for (int r = 0; r < rounds; ++r) {
