@@ -967,10 +967,10 @@ __global__ void __launch_bounds__(kBlock) k_sum_fixed(const double* part, int co
   if (threadIdx.x == 0) out[0] = v;
 }
 
-// Row chunks of the Gram launch: about 512 workgroups per round, chunks of
+// Row chunks of the Gram launch: about 1024 workgroups per round, chunks of
 // at least 64 rows (a multiple of 16), at most kJMaxChunks.
 static void jacobi_chunks(int rows, int npairs, int& nchunk, int& rpc) {
-  int want = (512 + npairs - 1) / npairs;
+  int want = (1024 + npairs - 1) / npairs;
   want = std::max(1, std::min(std::min(want, kJMaxChunks), (rows + 63) / 64));
   rpc = ((rows + want - 1) / want + 15) / 16 * 16;
   nchunk = std::max(1, (rows + rpc - 1) / rpc);
