@@ -175,8 +175,10 @@ def bench_headline(ap, synth, torch, args):
     ap.prof_products(False)
     # the same solve with library-allocated memory (hipMalloc / hipFree of
     # the context's buffers inside the solve), for reference
-    ms_libmem, (_, info_lm) = solve(SEEDS3[1 % len(SEEDS3)])
-    log(f"[bench] seed {SEEDS3[1 % len(SEEDS3)]} with library memory: {ms_libmem:.1f} ms (eta {info_lm.eta:.2e})")
+    ms_libmem = float("nan")
+    if not args.headline_only:
+        ms_libmem, (_, info_lm) = solve(SEEDS3[1 % len(SEEDS3)])
+        log(f"[bench] seed {SEEDS3[1 % len(SEEDS3)]} with library memory: {ms_libmem:.1f} ms (eta {info_lm.eta:.2e})")
     ms_step = sum(times) / len(times)
     srt = sorted(times)
     med = srt[len(srt) // 2] if len(srt) % 2 else 0.5 * (srt[len(srt) // 2 - 1] + srt[len(srt) // 2])
@@ -226,7 +228,8 @@ def bench_headline(ap, synth, torch, args):
         "seeds": {"median_ms": round(med, 1), "min_ms": round(srt[0], 1), "max_ms": round(srt[-1], 1),
                   "per_step_ms": [round(t, 1) for t in times]},
         "memory": {"caller_workspace_bytes": int(ws_bytes),
-                   "library_memory_ms": {"seed": SEEDS3[1 % len(SEEDS3)], "ms": round(ms_libmem, 1)}},
+                   "library_memory_ms": None if args.headline_only else
+                   {"seed": SEEDS3[1 % len(SEEDS3)], "ms": round(ms_libmem, 1)}},
         "aplicur": {"rank": info.rank, "phases": info.phases, "iters": info.iters, "outer": info.outer,
                     "rebuilds": info.rebuilds, "eta": max(i.eta for i in infos),
                     "all_reached": all(i.status == 0 and i.eta <= TOL3 for i in infos),
