@@ -786,10 +786,15 @@ __device__ __forceinline__ void jacobi_rot(double gpp, double gqq, double gpq, d
 // (row-major) and flag[pair] = 0, or flag = 1 (skip: X and V keep the
 // pair's columns).
 constexpr int kJRT = kJP * kJP;  // threads of k_jac_rot (one per entry)
-template <bool FULL>
+// MEAS: only the sums and the measure (a measurement pass: no rotation);
+// with `blocks` (the pass's first round, where every block sits in exactly
+// one pair) the entries within each block count too, so that the pass sums
+// every off-diagonal entry of the state once.
+template <bool FULL, bool MEAS = false>
 __global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpart, int nchunk, double d2,
                                                    double skip, double* __restrict__ sq_part,
-                                                   double* __restrict__ qbuf, int* __restrict__ flag) {
+                                                   double* __restrict__ qbuf, int* __restrict__ flag,
+                                                   int blocks = 0) {
   __shared__ double G[2][kJP][kJP + 1];
   __shared__ double Q[2][kJP][kJP + 1];
   __shared__ double cs[2][kJP], sn[2][kJP];  // per step parity and index: its plane's c and signed s
@@ -813,7 +818,7 @@ __global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpa
     const double d = sqrt((G[0][i][i] + d2) * (G[0][j][j] + d2));
     const double v = d > 0.0 ? fabs(G[0][i][j]) / d : 0.0;
     mx = v;
-    if (i < kJW && j >= kJW) sq = v * v;
+    if ((i < kJW && j >= kJW) || (MEAS && blocks)) sq = v * v;
   }
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -825,7 +830,7 @@ __global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpa
     wsq[wave] = sq;
   }
   // step 0's rotations from G itself
-  if (tid < kJW) {
+  if (!MEAS && tid < kJW) {
     int p, q;
     step_plane(FULL, 0, tid, p, q);
     double c, s;
@@ -842,6 +847,7 @@ __global__ void __launch_bounds__(kJRT) k_jac_rot(const double* __restrict__ gpa
     block_sq += wsq[w];
   }
   if (tid == 0) sq_part[pair] = block_sq;
+  if (MEAS) return;
   if (block_off <= skip) {  // uniform
     if (tid == 0) flag[pair] = 1;
     return;
@@ -967,6 +973,10 @@ __global__ void __launch_bounds__(kBlock) k_sum_fixed(const double* part, int co
   if (threadIdx.x == 0) out[0] = v;
 }
 
+// A measurement pass runs when the last two sweeps' measures extrapolate to
+// at most this multiple of the stopping level.
+constexpr double kJacMeasureFactor = 2.0;
+
 // Row chunks of the Gram launch: about 1024 workgroups per round, chunks of
 // at least 64 rows (a multiple of 16), at most kJMaxChunks.
 static void jacobi_chunks(int rows, int npairs, int& nchunk, int& rpc) {
@@ -1004,6 +1014,15 @@ int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long 
   const JacWork jw = carve_jacobi(work, n, npad);
   const int arows = std::max(n, npad);
   const dim3 ga(ceil_div(arows, kJARows), npairs, 2);
+  // the fixed-order sum of the per-pair measures of the last pass
+  auto read_measure = [&]() {
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kBlock), 0, s, (const double*)jw.sq_part, rounds * npairs, jw.sum);
+    double sum_sq = 0.0;
+    APL_HIP(hipMemcpyAsync(&sum_sq, jw.sum, sizeof(sum_sq), hipMemcpyDeviceToHost, s));
+    APL_HIP(hipStreamSynchronize(s));
+    return std::sqrt(2.0 * sum_sq);
+  };
+  double prev_eps = INFINITY;
   int sweeps = 0;
   for (; sweeps < max_sweeps; ++sweeps) {
     for (int r = 0; r < rounds; ++r) {
@@ -1018,15 +1037,30 @@ int jacobi_svd(double* X, long long ldx, int n, int npad, double* Vm, long long 
       hipLaunchKernelGGL(k_jac_apply, ga, dim3(kJT), 0, s, X, ldx, n, Vm, ldv, npad, nblk, r,
                          (const double*)jw.qbuf, (const int*)jw.flag);
     }
-    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kBlock), 0, s, (const double*)jw.sq_part, rounds * npairs, jw.sum);
-    double sum_sq = 0.0;
-    APL_HIP(hipMemcpyAsync(&sum_sq, jw.sum, sizeof(sum_sq), hipMemcpyDeviceToHost, s));
-    APL_HIP(hipStreamSynchronize(s));
     // Frobenius norm of the damped off-diagonal (both triangles) as the sweep saw it
-    if (std::sqrt(2.0 * sum_sq) <= tol_f) {
+    const double eps = read_measure();
+    if (eps <= tol_f) {
       ++sweeps;
       break;
     }
+    // When the measures of the last two sweeps extrapolate (geometrically)
+    // to the stopping level, measure the state this sweep left, pair by
+    // pair without rotating (every off-diagonal entry once, the entries
+    // within blocks included): if that meets the test, the next sweep is not
+    // needed (its rotations would only refine a state that already passes).
+    if (sweeps >= 1 && eps * (eps / prev_eps) <= kJacMeasureFactor * tol_f) {
+      for (int r = 0; r < rounds; ++r) {
+        hipLaunchKernelGGL(k_jac_gram, dim3(nchunk, npairs), dim3(kJT), 0, s, (const double*)X, ldx, n, nblk, r,
+                           rpc, nchunk, jw.gpart);
+        hipLaunchKernelGGL((k_jac_rot<false, true>), dim3(npairs), dim3(kJRT), 0, s, (const double*)jw.gpart,
+                           nchunk, delta2, skip, jw.sq_part + (long long)r * npairs, jw.qbuf, jw.flag, r == 0 ? 1 : 0);
+      }
+      if (read_measure() <= tol_f) {
+        ++sweeps;
+        break;
+      }
+    }
+    prev_eps = eps;
   }
   hipLaunchKernelGGL(k_col_norms, dim3(n), dim3(kBlock), 0, s, (const double*)X, ldx, n, n, sigma);
   return sweeps;
