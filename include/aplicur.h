@@ -137,7 +137,8 @@ typedef struct aplicur_opts {
   double jacobi_tol; /* accuracy of the SVD of the l x l core M (Alg. 2 Part 2), by one-sided
                         Jacobi: sweeps stop once the Frobenius norm of the off-diagonal of
                         the damped core's Gram matrix, scaled to unit diagonal, is at most
-                        this; the preconditioned singular values then lie within
+                        this (as summed over the last sweep, or measured on the state a
+                        sweep left); the preconditioned singular values then lie within
                         sqrt(1 +- jacobi_tol) of the exact-SVD level.  <= 0: 1e-2
                         (default); tiny values run the sweeps to convergence (at most 40) */
   int32_t tc_sketched; /* T_C (Alg. 2) when the Cholesky of C^T C breaks down after a CUR
