@@ -700,8 +700,10 @@ static Ctx* create(const aplicur_mat* Am, const aplicur_opts* o, hipStream_t s, 
       c->Sinv = c->arena.alloc<double>((size_t)b * b);
       c->lu_piv = c->arena.alloc<int>(b);
       c->small = c->arena.alloc<double>((size_t)4 * b * b);
-      c->YJ = c->arena.alloc<double>((size_t)S * L);
-      c->Z = c->arena.alloc<double>((size_t)S * L);
+      // Y(:, J) and Z = Y(:, J) U with an even leading dimension, so that
+      // the GEMMs read them with 16-byte loads
+      c->YJ = c->arena.alloc<double>((size_t)(S + (S & 1)) * L);
+      c->Z = c->arena.alloc<double>((size_t)(S + (S & 1)) * L);
       c->P2 = c->arena.alloc<double>((size_t)L * b);
       c->status_dev = c->arena.alloc<int>(4);
       c->Mx = c->arena.alloc<double>((size_t)L * Lp);
@@ -1034,10 +1036,11 @@ static StepResult outer_step(Ctx& c, hipStream_t s) {
   }
   const int ln = l + k2;
   // (vi) E_row = Y - (Y(:,J) U) R   (E as n x s column-major = E_row^T)
-  gather_y_cols(c.Y, n, S, c.J_dev, ln, c.YJ, S, s);
-  gemm(c, Op::N, Op::N, S, ln, ln, 1.0, c.YJ, S, c.U, L, 0.0, c.Z, S);
+  const int Sp = S + (S & 1);  // leading dimension of YJ and Z
+  gather_y_cols(c.Y, n, S, c.J_dev, ln, c.YJ, Sp, s);
+  gemm(c, Op::N, Op::N, S, ln, ln, 1.0, c.YJ, Sp, c.U, L, 0.0, c.Z, Sp);
   APL_HIP(hipMemcpyAsync(c.E, c.Y, sizeof(double) * (size_t)S * n, hipMemcpyDeviceToDevice, s));
-  gemm(c, Op::N, Op::T, n, S, ln, -1.0, c.Rt, n, c.Z, S, 1.0, c.E, n);
+  gemm(c, Op::N, Op::T, n, S, ln, -1.0, c.Rt, n, c.Z, Sp, 1.0, c.E, n);
   // (vii) rho = 10 sqrt(2/pi) max_i ||E_row w_i||
   gemm(c, Op::T, Op::N, S, c.r, n, 1.0, c.E, n, c.W, n, 0.0, c.EW, S);
   rho_from_ew(c.EW, S, c.r, c.rho_dev, s);
