@@ -126,8 +126,8 @@ struct Blk {
   int kp = 0;
   void* At = nullptr;  // A^T, n x ldt row-major
   long long ldt = 0;
-  double* Vt = nullptr;  // V^T of the explicit P, ell x ldvt row-major
-  long long ldvt = 0, vt_gen = -1;
+  double* W = nullptr;  // V_M diag(d) V_M^T of the explicit P, ell x ell (symmetric)
+  long long w_gen = -1;
   double *Bp = nullptr, *Bbot = nullptr, *Xp = nullptr, *tm = nullptr, *tn = nullptr;
   BlkVecs<double> vec{};
   BlkWork wk{};
@@ -198,6 +198,10 @@ struct Ctx {
   size_t splitk_count = 0;
   PrecDesc prec{};
   bool have_prec = false;
+  // what Vhat holds for the explicit P of generation vhat_gen: 1 V = Q_R V_M
+  // (one-column paths), 2 Q_R row-major (blocked path), 0 nothing yet
+  int vhat_kind = 0;
+  long long vhat_gen = -1;
   int vm_rank = 0;       // rank of the right singular vectors held in Vm (warm start of the next build)
   long long vm_ld = 0;   // their leading dimension
   double p_target = 0.0, p_pnorm = 1.0, p_sigma_l = 0.0;
@@ -1235,9 +1239,10 @@ static void build_precond(Ctx& c, hipStream_t s) {
     }
     build_r_csr(c, s);
   } else {
-    // V = Q_R V_M stored row-major n x l  (= column-major l x n: V^T = V_M^T Q_R^T)
-    gemm(c, Op::T, Op::T, l, c.n, l, 1.0, c.Vm, lp, c.Q, c.n, 0.0,
-         c.Vhat, l);
+    // V = Q_R V_M (n x l row-major in Vhat) is formed by ensure_vhat for the
+    // one-column paths when they first apply this P; the blocked path applies
+    // Q_R and V_M diag(d) V_M^T as factors (blk_prec)
+    c.vhat_kind = 0;
     c.prec.ldv = l;
   }
   double info[4];
@@ -1251,6 +1256,17 @@ static void build_precond(Ctx& c, hipStream_t s) {
   c.prec.ell = l;
   c.have_prec = true;
   ++c.prec_gen;
+}
+
+// V = Q_R V_M (n x l row-major in Vhat) of the explicit P, formed once per
+// build for the one-column P-apply (the blocked path does without it).
+static void ensure_vhat(Ctx& c, hipStream_t s) {
+  if (!c.have_prec || c.o.precond != 1 || c.prec.implicit) return;
+  if (c.vhat_kind == 1 && c.vhat_gen == c.prec_gen) return;
+  const int l = c.prec.ell;
+  gemm(c, Op::T, Op::T, l, c.n, l, 1.0, c.Vm, c.vm_ld, c.Q, c.n, 0.0, c.Vhat, l);
+  c.vhat_kind = 1;
+  c.vhat_gen = c.prec_gen;
 }
 
 // ------------------------------------------------------------------ LSQR phases
@@ -1586,6 +1602,7 @@ static int solve(Ctx& c, const double* B, long long ldb, int nrhs, double* X, lo
     lg.t_lsqr += ms_since(t0);
   } else if (any_active) {
     outer_loop(c, s, lg, [&](bool final_step, double nu, double epsl) {
+      ensure_vhat(c, s);
       bool active = false;
       for (int k = 0; k < nrhs; ++k) {
         ColState& cs = cols[k];
@@ -1655,10 +1672,7 @@ static void ensure_blk(Ctx& c, int kp, hipStream_t s) {
     b.op.f64 = c.op.f64;
     b.op.Sm = gemm_splits(m, n);
     b.op.Sn = gemm_splits(n, m);
-    if (c.o.precond) {
-      b.ldvt = (n + 1) / 2 * 2;
-      b.Vt = c.arena.alloc<double>((size_t)std::max(c.L, 1) * b.ldvt);
-    }
+    if (c.o.precond) b.W = c.arena.alloc<double>((size_t)std::max(c.L, 1) * std::max(c.L, 1));
   }
   if (c.fp32 && !b.op32.A) {
     b.op32 = b.op;
@@ -1712,6 +1726,7 @@ static void ensure_blk(Ctx& c, int kp, hipStream_t s) {
   if (c.o.precond) {
     b.wk.pl = c.arena.alloc<double>((size_t)b.S1max * L * kp);
     b.wk.pc = c.arena.alloc<double>((size_t)L * kp);
+    b.wk.pc2 = c.arena.alloc<double>((size_t)L * kp);
     b.wk.pq = c.arena.alloc<double>((size_t)b.S2max * n * kp);
   }
   b.wk.beta_part = c.arena.alloc<double>((size_t)kBlkMaxGrid * kp);
@@ -1729,26 +1744,38 @@ static void ensure_blk(Ctx& c, int kp, hipStream_t s) {
   APL_HIP(hipHostMalloc((void**)&b.norm_host, sizeof(double) * kBlkMaxGrid * kp, hipHostMallocDefault));
 }
 
-// The explicit P for the blocked kernels (V^T refreshed after each rebuild).
+// The explicit P for the blocked kernels in factored form: V = Q_R V_M, so
+// V diag(d) V^T = Q_R W Q_R^T with W = V_M diag(d) V_M^T (ell x ell,
+// symmetric; an ell^3 product per build instead of the n ell^2 one that
+// forms V).  Q_R^T z is a product with Q itself (column-major n x l =
+// row-major l x n), then W, then Q_R (its row-major copy in Vhat).  W and
+// the copy are refreshed after each rebuild.
 static BlkPrec blk_prec(Ctx& c, hipStream_t s) {
   Blk& b = *c.blk;
-  const int l = c.prec.ell;
-  APL_REQUIRE(b.Vt, "blocked P buffers missing");
-  if (b.vt_gen != c.prec_gen) {
-    // V^T (l x n row-major): the transpose of the explicit V (n x l row-major)
-    // the build formed, so both layouts hold the same values
-    transpose_rect<double>(c.Vhat, c.n, l, l, b.Vt, b.ldvt, s);
-    b.vt_gen = c.prec_gen;
+  const int l = c.prec.ell, lp = c.vm_ld;
+  APL_REQUIRE(b.W, "blocked P buffers missing");
+  if (c.vhat_kind != 2 || c.vhat_gen != c.prec_gen) {
+    transpose_rect<double>(c.Q, l, c.n, c.n, c.Vhat, l, s);  // Q_R row-major, n x l
+    c.vhat_kind = 2;
+    c.vhat_gen = c.prec_gen;
+  }
+  if (b.w_gen != c.prec_gen) {
+    copy_block(c.Vm, lp, c.Kc, l, l, l, 1.0, s);  // V_M (ld l)
+    scale_cols(c.Kc, l, l, l, c.d, c.Kr, s);       // V_M diag(d)
+    gemm(c, Op::N, Op::T, l, l, l, 1.0, c.Kr, l, c.Kc, l, 0.0, b.W, l);
+    b.w_gen = c.prec_gen;
   }
   BlkPrec P{};
-  P.V = c.prec.V;
-  P.Vt = b.Vt;
+  P.V = c.Vhat;
+  P.ldv = l;
+  P.Vt = c.Q;
+  P.ldvt = c.n;
+  P.W = b.W;
   P.d = c.prec.d;
-  P.ldv = c.prec.ldv;
-  P.ldvt = b.ldvt;
   P.ell = l;
   P.S1 = std::min(b.S1max, gemm_splits(l, c.n));
   P.S2 = std::min(b.S2max, gemm_splits(c.n, l));
+  P.S3 = std::min(b.S1max, gemm_splits(l, l));
   return P;
 }
 
@@ -2099,9 +2126,10 @@ static int solve_backward(Ctx& c, const double* X, long long ldx, const double* 
   auto t0 = Clock::now();
   const PrecDesc* P = c.have_prec ? &c.prec : nullptr;
   const double pnorm = c.have_prec ? c.p_pnorm : 1.0, sigma_l = c.have_prec ? c.p_sigma_l : 0.0;
+  const bool blocked = use_blocked(c, nrhs);
+  if (!blocked) ensure_vhat(c, s);
   int status = APLICUR_OK, iters = 0, phases = 0;
   double eta_max = 0.0;
-  const bool blocked = use_blocked(c, nrhs);
   for (int g0 = 0; blocked && g0 < nrhs; g0 += kBlkMaxCols) {
     // the k columns of Z together (blocked path)
     const int kg = std::min(kBlkMaxCols, nrhs - g0);
@@ -2488,6 +2516,8 @@ int aplicur_precond_apply(aplicur_ctx* ctx, int32_t trans, const double* z, doub
     APL_REQUIRE(ctx && ctx->impl && z && y, "null argument");
     Ctx& c = *ctx->impl;
     APL_REQUIRE(c.have_prec, "no preconditioner has been built (run aplicur_solve with precond 1 or 2 first)");
+    set_stream(c, (hipStream_t)stream);
+    ensure_vhat(c, (hipStream_t)stream);
     gk_precond_apply(c.op, c.prec, trans != 0, z, y, (hipStream_t)stream);
     APL_HIP(hipGetLastError());
     return APLICUR_OK;

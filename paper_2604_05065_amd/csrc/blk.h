@@ -67,10 +67,14 @@ void rows_gemm16(const void* T, long long rows, long long cols, const float* In,
                  hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Explicit P^{-1} z = z + V (d .* (V^T z)) with V (n x ell, ldv) and V^T (ell x n, ldvt), FP64.
+// The explicit P for the blocked kernels, V diag(d) V^T: with W null, V (n x
+// ell row-major) and V^T (ell x n row-major); with W set, the factored form
+// Q_R W Q_R^T, V holding Q_R (n x ell row-major), Vt Q_R^T (ell x n
+// row-major) and W = V_M diag(d) V_M^T (ell x ell, symmetric).
 struct BlkPrec {
-  const double *V, *Vt, *d;
+  const double *V, *Vt, *d, *W;
   long long ldv, ldvt;
-  int ell, S1, S2;  // splits of V^T z and of V c
+  int ell, S1, S2, S3;  // splits of V^T z, of V c and of W c
 };
 
 template <class V>
@@ -81,6 +85,7 @@ struct BlkVecs {
 struct BlkWork {
   void *pm, *pn;        // product partials: Sm x m x kp and Sn x n x kp (V)
   double *pl, *pc, *pq; // P: S1 x ell x kp partials, ell x kp coefficients, S2 x n x kp partials
+  double* pc2;          // P in factored form: W times the coefficients
   double *beta_part, *alpha_part;  // at most kBlkMaxGrid x kp each
   int beta_count, alpha_count;
   double* norm_part;    // column partials of the norm kernels (kBlkMaxGrid x kp)

@@ -818,13 +818,13 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------- explicit P^{-1}
-// c = d .* (sum of the S planes of V^T z), ell x kp.
+// c = d .* (sum of the S planes of V^T z), ell x kp (d null: the plain sum).
 template <int KP>
 __global__ void __launch_bounds__(kBlock)
     k_blk_pcoef(const double* __restrict__ pl, int S, int ell, const double* __restrict__ d, double* c) {
   const long long lp = (long long)ell * KP;
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < lp; e += (long long)gridDim.x * kBlock)
-    c[e] = d[e / KP] * plane_sum(pl, S, lp, e);
+    c[e] = d ? d[e / KP] * plane_sum(pl, S, lp, e) : plane_sum(pl, S, lp, e);
 }
 
 // First kernel of a preconditioned iteration: alpha (slot 1 -> slot 0), the
@@ -975,13 +975,25 @@ static void blk_prod(const BlkOp& A, bool trans, const V* in, int kp, V* out, hi
     rows_gemm<float, V, V>((const float*)M, rows, cols, ld, in, kp, out, S, s, e0, e1);
 }
 
-// c = d .* V^T z, then pq = V c (S2 planes).
+// c = d .* V^T z, then pq = V c (S2 planes); in factored form c = W (Q_R^T z)
+// and pq = Q_R c.
 template <class V>
 static void blk_pcoef(const BlkOp& A, const BlkPrec& P, int kp, const V* z, BlkWork& wk, hipStream_t s) {
+  auto coef = [&](int S, const double* d, double* out) {
+    BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_pcoef<KP>), dim3(blk_grid(P.ell, kp)), dim3(kBlock), 0, s, wk.pl, S,
+                                         P.ell, d, out));
+  };
   rows_gemm<double, V, double>(P.Vt, P.ell, A.n, P.ldvt, z, kp, wk.pl, P.S1, s);
-  BLK_KP_SWITCH(kp, hipLaunchKernelGGL((k_blk_pcoef<KP>), dim3(blk_grid(P.ell, kp)), dim3(kBlock), 0, s, wk.pl, P.S1,
-                                       P.ell, P.d, wk.pc));
-  rows_gemm<double, double, double>(P.V, A.n, P.ell, P.ldv, wk.pc, kp, wk.pq, P.S2, s);
+  double* c = wk.pc;
+  if (P.W) {
+    coef(P.S1, nullptr, wk.pc);
+    rows_gemm<double, double, double>(P.W, P.ell, P.ell, P.ell, wk.pc, kp, wk.pl, P.S3, s);
+    coef(P.S3, nullptr, wk.pc2);
+    c = wk.pc2;
+  } else {
+    coef(P.S1, P.d, wk.pc);
+  }
+  rows_gemm<double, double, double>(P.V, A.n, P.ell, P.ldv, c, kp, wk.pq, P.S2, s);
 }
 
 template <class V>
