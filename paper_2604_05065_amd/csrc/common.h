@@ -72,6 +72,14 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// v from lane src of the wave (src uniform)
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Sum over the whole workgroup (kBlock threads); result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double red[kBlock / kWave];

@@ -265,14 +265,6 @@ __device__ __forceinline__ void load_diag(double (*Ts)[kTB + 1], const double* T
   }
 }
 
-// v from lane src of the wave (src uniform)
-__device__ __forceinline__ double lane_bcast(double v, int src) {
-  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, src);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), src);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Left: op(T) X = B for the k x ncols block B (k <= kTB): one wave per column,
 // lane i holding x_i.  Column-oriented substitution: at step i the lane of
 // the pivot finishes x_i (division by the diagonal), and every lane still to

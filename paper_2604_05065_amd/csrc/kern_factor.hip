@@ -432,39 +432,55 @@ constexpr int kFT = 1024;
 // Upper Cholesky of the nb x nb diagonal block at G (column-major, ld): U^T U
 // = G in place (upper triangle; the strict lower triangle is left alone).
 // status[0] = 1 + (j0 + j) if pivot j is not positive; nothing is done when
-// status[0] is already set.
+// status[0] is already set.  The block stays in registers: lane i holds row
+// i of the columns w, w + 16, w + 32, w + 48 of wave w.  Step j reads row j
+// of the current matrix from LDS (published by the lanes that own it at the
+// end of step j - 1, double-buffered), forms r = sqrt(g_jj) and the scaled
+// row u = g_j. / r, makes row j that row of U (diagonal r) and updates g_xy
+// -= u_x u_y for j < x <= y; one barrier per step.
+constexpr int kPW = kFT / kWave;        // waves of the register-resident block kernels
+constexpr int kPCols = kFNB / kPW;      // columns per wave
+static_assert(kFNB == kWave && kFNB % kPW == 0, "register-resident blocks: kFNB rows, one per lane");
 __global__ void __launch_bounds__(kFT) k_potrf_diag(double* G, long long ld, int nb, int j0, int* status) {
-  __shared__ double a[kFNB * kFNB];  // column-major, ld kFNB
+  __shared__ double row[2][kFNB];
   __shared__ int bad;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   if (threadIdx.x == 0) bad = status[0];
-  __syncthreads();
-  if (bad) return;
-  for (int e = threadIdx.x; e < nb * nb; e += kFT) {
-    const int i = e % nb, j = e / nb;
-    a[i + j * kFNB] = G[i + j * ld];
+  double x[kPCols];
+#pragma unroll
+  for (int b = 0; b < kPCols; ++b) {
+    const int y = wave + kPW * b;
+    x[b] = (lane <= y && y < nb) ? G[lane + (long long)y * ld] : 0.0;
+    if (lane == 0 && y < nb) row[0][y] = x[b];
   }
   __syncthreads();
+  if (bad) return;  // uniform
   for (int j = 0; j < nb; ++j) {
-    const double d = a[j + j * kFNB];
+    const int par = j & 1;
+    const double d = row[par][j];
     if (!(d > 0.0)) {
       if (threadIdx.x == 0) status[0] = 1 + j0 + j;
       return;  // uniform: every thread read the same d
     }
     const double r = sqrt(d);
-    __syncthreads();
-    if (threadIdx.x == 0) a[j + j * kFNB] = r;
-    for (int l = j + 1 + threadIdx.x; l < nb; l += kFT) a[j + l * kFNB] /= r;
-    __syncthreads();
-    const int rem = nb - j - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += kFT) {
-      const int x = j + 1 + e % rem, y = j + 1 + e / rem;
-      if (x <= y) a[x + y * kFNB] -= a[j + x * kFNB] * a[j + y * kFNB];
+    const double ux = row[par][lane] / r;
+#pragma unroll
+    for (int b = 0; b < kPCols; ++b) {
+      const int y = wave + kPW * b;
+      if (y >= nb || y < j) continue;
+      if (lane == j) {
+        x[b] = y == j ? r : row[par][y] / r;
+      } else if (lane > j && lane <= y) {
+        x[b] -= ux * (row[par][y] / r);
+      }
+      if (lane == j + 1 && y >= j + 1) row[par ^ 1][y] = x[b];
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < nb * nb; e += kFT) {
-    const int i = e % nb, j = e / nb;
-    if (i <= j) G[i + j * ld] = a[i + j * kFNB];
+#pragma unroll
+  for (int b = 0; b < kPCols; ++b) {
+    const int y = wave + kPW * b;
+    if (lane <= y && y < nb) G[lane + (long long)y * ld] = x[b];
   }
 }
 
@@ -474,84 +490,139 @@ void potrf_diag(double* G, long long ld, int nb, int j0, int* status, hipStream_
 }
 
 // LU with partial pivoting (first largest magnitude) of the panel
-// A[j0:k, j0:j0+w] (column-major, ld; k - j0 <= kFMaxRows, w <= kFNB) in LDS:
+// A[j0:k, j0:j0+w] (column-major, ld; k - j0 <= kFMaxRows, w <= kFNB):
 // piv[j0 + c] = the row swapped with row j0 + c; L below the diagonal (unit),
 // U on and above.  status[0] = 1 if a pivot is zero (the elimination of that
-// column is skipped).
+// column is skipped).  The panel stays in registers: lane i holds rows i,
+// i + 64, ... of the columns w, w + 16, w + 32, w + 48 of wave w.  Column c
+// belongs to one wave, which finds the pivot (a wave reduction), swaps the
+// two rows in its columns, scales the multipliers and publishes them, the
+// pivot row and the pivot through LDS (double-buffered); after the step's
+// one barrier every other wave swaps the two rows in its columns (lane reads
+// and writes, the rows being uniform) and updates its columns right of c.
+constexpr int kLuRows = (kFMaxRows + kWave - 1) / kWave;  // rows per lane
+static_assert(kFNB <= kWave, "k_lu_panel: the panel's pivot rows (c < w <= kFNB) sit in the first row slot");
 __global__ void __launch_bounds__(kFT) k_lu_panel(double* A, long long ld, int k, int j0, int w, int* piv,
                                                   int* status) {
-  extern __shared__ double p[];  // (k - j0) x w, column-major, ld R
-  __shared__ double wv[kFT / kWave];
-  __shared__ int wi[kFT / kWave];
-  __shared__ int prow;
+  __shared__ double mult[2][kLuRows * kWave];
+  __shared__ double s_d[2];
+  __shared__ int s_pr[2];
+  __shared__ double prow[kPW][kPCols];  // per wave: the pivot row's entries before the swap
   const int R = k - j0;
-  for (int e = threadIdx.x; e < R * w; e += kFT) {
-    const int i = e % R, j = e / R;
-    p[i + j * R] = A[(j0 + i) + (long long)(j0 + j) * ld];
-  }
-  __syncthreads();
-  for (int c = 0; c < w; ++c) {
-    // argmax |p[r][c]| over r in [c, R), smallest index on ties
-    double v = -1.0;
-    int idx = INT_MAX;
-    for (int r = c + threadIdx.x; r < R; r += kFT) {
-      const double x = fabs(p[r + c * R]);
-      if (x > v) {
-        v = x;
-        idx = r;
-      }
-    }
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  double x[kPCols][kLuRows];
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off, kWave);
-      const int oi = __shfl_xor(idx, off, kWave);
-      if (ov > v || (ov == v && oi < idx)) {
-        v = ov;
-        idx = oi;
-      }
+  for (int b = 0; b < kPCols; ++b) {
+    const int j = wave + kPW * b;
+#pragma unroll
+    for (int a = 0; a < kLuRows; ++a) {
+      const int r = lane + kWave * a;
+      x[b][a] = (r < R && j < w) ? A[(j0 + r) + (long long)(j0 + j) * ld] : 0.0;
     }
-    if (threadIdx.x % kWave == 0) {
-      wv[threadIdx.x / kWave] = v;
-      wi[threadIdx.x / kWave] = idx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double bv = wv[0];
-      int bi = wi[0];
-      for (int q = 1; q < kFT / kWave; ++q)
-        if (wv[q] > bv || (wv[q] == bv && wi[q] < bi)) {
-          bv = wv[q];
-          bi = wi[q];
-        }
-      prow = bi;
-      piv[j0 + c] = j0 + bi;
-      if (!(bv > 0.0)) status[0] = 1;
-    }
-    __syncthreads();
-    const int pr = prow;
-    if (pr != c)
-      for (int j = threadIdx.x; j < w; j += kFT) {
-        const double t = p[c + j * R];
-        p[c + j * R] = p[pr + j * R];
-        p[pr + j * R] = t;
-      }
-    __syncthreads();
-    const double d = p[c + c * R];
-    if (d != 0.0) {
-      const double inv = 1.0 / d;
-      for (int r = c + 1 + threadIdx.x; r < R; r += kFT) p[r + c * R] *= inv;
-      __syncthreads();
-      const int rr = R - c - 1, cc = w - c - 1;
-      for (int e = threadIdx.x; e < rr * cc; e += kFT) {
-        const int r = c + 1 + e % rr, j = c + 1 + e / rr;
-        p[r + j * R] -= p[r + c * R] * p[c + j * R];
-      }
-    }
-    __syncthreads();
   }
-  for (int e = threadIdx.x; e < R * w; e += kFT) {
-    const int i = e % R, j = e / R;
-    A[(j0 + i) + (long long)(j0 + j) * ld] = p[i + j * R];
+  // Rows c (slot 0 of lane c, as c < kWave) and pr exchanged in this wave's
+  // columns: row pr's entries pass through the wave's LDS row (written by
+  // its owner lane, read back by every lane: in order within the wave).
+  auto swap_rows = [&](int c, int pr) {
+    if (pr == c) return;
+#pragma unroll
+    for (int a = 0; a < kLuRows; ++a)
+      if (lane + kWave * a == pr) {
+#pragma unroll
+        for (int b = 0; b < kPCols; ++b) prow[wave][b] = x[b][a];
+      }
+    double vc[kPCols];
+#pragma unroll
+    for (int b = 0; b < kPCols; ++b) vc[b] = lane_bcast(x[b][0], c);
+#pragma unroll
+    for (int b = 0; b < kPCols; ++b) {
+      const double vp = prow[wave][b];
+      if (lane == c) x[b][0] = vp;
+#pragma unroll
+      for (int a = 0; a < kLuRows; ++a)
+        if (lane + kWave * a == pr) x[b][a] = vc[b];
+    }
+  };
+#pragma unroll
+  for (int bc = 0; bc < kPCols; ++bc) {
+    for (int wc = 0; wc < kPW; ++wc) {
+      const int c = kPW * bc + wc;
+      if (c >= w) break;  // uniform
+      const int par = c & 1;
+      if (wave == wc) {
+        // argmax |A(r, c)| over r in [c, R), smallest index on ties
+        double v = -1.0;
+        int idx = INT_MAX;
+#pragma unroll
+        for (int a = 0; a < kLuRows; ++a) {
+          const int r = lane + kWave * a;
+          if (r >= c && r < R) {
+            const double t = fabs(x[bc][a]);
+            if (t > v) {
+              v = t;
+              idx = r;
+            }
+          }
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+          const double ov = __shfl_xor(v, off, kWave);
+          const int oi = __shfl_xor(idx, off, kWave);
+          if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+          }
+        }
+        if (idx == INT_MAX) idx = c;  // no comparable entry (NaN): no swap, and status flags it
+        const int pr = __builtin_amdgcn_readfirstlane(idx);
+        if (lane == 0) {
+          piv[j0 + c] = j0 + pr;
+          if (!(v > 0.0)) status[0] = 1;
+        }
+        swap_rows(c, pr);
+        const double d = lane_bcast(x[bc][0], c);
+        if (d != 0.0) {
+          const double inv = 1.0 / d;
+#pragma unroll
+          for (int a = 0; a < kLuRows; ++a) {
+            const int r = lane + kWave * a;
+            if (r > c && r < R) x[bc][a] *= inv;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < kLuRows; ++a) mult[par][lane + kWave * a] = x[bc][a];
+        if (lane == 0) {
+          s_pr[par] = pr;
+          s_d[par] = d;
+        }
+      }
+      __syncthreads();
+      const int pr = __builtin_amdgcn_readfirstlane(s_pr[par]);
+      const double d = s_d[par];
+      if (wave != wc) swap_rows(c, pr);
+      if (d != 0.0) {
+#pragma unroll
+        for (int b = 0; b < kPCols; ++b) {
+          const int j = wave + kPW * b;
+          if (j <= c || j >= w) continue;
+          const double pc = lane_bcast(x[b][0], c);
+#pragma unroll
+          for (int a = 0; a < kLuRows; ++a) {
+            const int r = lane + kWave * a;
+            if (r > c && r < R) x[b][a] -= mult[par][r] * pc;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < kPCols; ++b) {
+    const int j = wave + kPW * b;
+#pragma unroll
+    for (int a = 0; a < kLuRows; ++a) {
+      const int r = lane + kWave * a;
+      if (r < R && j < w) A[(j0 + r) + (long long)(j0 + j) * ld] = x[b][a];
+    }
   }
 }
 
@@ -572,15 +643,8 @@ __global__ void k_laswp(double* A, long long ld, int ncols, int c0, int c1, cons
 }
 
 void lu_panel(double* A, long long ld, int k, int j0, int w, int* piv, int* status, hipStream_t s) {
-  APL_REQUIRE(k - j0 <= kFMaxRows && w >= 1 && w <= kFNB, "lu_panel: panel too large");
-  const size_t lds = sizeof(double) * (size_t)(k - j0) * w;
-  static const bool attr = []() {
-    (void)hipFuncSetAttribute((const void*)k_lu_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double) * kFMaxRows * kFNB));
-    return true;
-  }();
-  (void)attr;
-  hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(kFT), lds, s, A, ld, k, j0, w, piv, status);
+  APL_REQUIRE(k - j0 <= kFMaxRows && w >= 1 && w <= kFNB && w <= k - j0, "lu_panel: panel too large");
+  hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(kFT), 0, s, A, ld, k, j0, w, piv, status);
 }
 
 void laswp(double* A, long long ld, int ncols, int c0, int c1, const int* piv, int j0, int w, hipStream_t s) {
