@@ -436,8 +436,9 @@ constexpr int kFT = 1024;
 // i of the columns w, w + 16, w + 32, w + 48 of wave w.  Step j reads row j
 // of the current matrix from LDS (published by the lanes that own it at the
 // end of step j - 1, double-buffered), forms r = sqrt(g_jj) and the scaled
-// row u = g_j. / r, makes row j that row of U (diagonal r) and updates g_xy
-// -= u_x u_y for j < x <= y; one barrier per step.
+// row u = g_j. / r (lane x divides entry x; the others come by readlane),
+// makes row j that row of U (diagonal r) and updates g_xy -= u_x u_y for j <
+// x <= y; one barrier per step.
 constexpr int kPW = kFT / kWave;        // waves of the register-resident block kernels
 constexpr int kPCols = kFNB / kPW;      // columns per wave
 static_assert(kFNB == kWave && kFNB % kPW == 0, "register-resident blocks: kFNB rows, one per lane");
@@ -451,7 +452,7 @@ __global__ void __launch_bounds__(kFT) k_potrf_diag(double* G, long long ld, int
   for (int b = 0; b < kPCols; ++b) {
     const int y = wave + kPW * b;
     x[b] = (lane <= y && y < nb) ? G[lane + (long long)y * ld] : 0.0;
-    if (lane == 0 && y < nb) row[0][y] = x[b];
+    if (lane == 0) row[0][y] = x[b];
   }
   __syncthreads();
   if (bad) return;  // uniform
@@ -463,15 +464,16 @@ __global__ void __launch_bounds__(kFT) k_potrf_diag(double* G, long long ld, int
       return;  // uniform: every thread read the same d
     }
     const double r = sqrt(d);
-    const double ux = row[par][lane] / r;
+    const double u = row[par][lane] / r;  // u_x for x = lane; u_y from lane y
 #pragma unroll
     for (int b = 0; b < kPCols; ++b) {
       const int y = wave + kPW * b;
       if (y >= nb || y < j) continue;
+      const double uy = lane_bcast(u, y);
       if (lane == j) {
-        x[b] = y == j ? r : row[par][y] / r;
+        x[b] = y == j ? r : uy;
       } else if (lane > j && lane <= y) {
-        x[b] -= ux * (row[par][y] / r);
+        x[b] -= u * uy;
       }
       if (lane == j + 1 && y >= j + 1) row[par ^ 1][y] = x[b];
     }
