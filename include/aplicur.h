@@ -306,11 +306,13 @@ int aplicur_matmat(aplicur_ctx* ctx, int32_t trans, const double* X, int64_t ldx
 /* y = P^{-1} z (trans = 0) or y = P^{-T} z (trans = 1) with the context's
  * last preconditioner (Alg. 2 Part 2: P^{-1} z = z + V ((sigma/Lambda - 1) .*
  * (V^T z)), V = Q_R V_M, symmetric; or the SVD-free P~^{-1} of Alg. 8, whose
- * transpose differs), through the same kernels as the LSQR iteration (the
- * implicit R^T K form for CSR A, the explicit V for dense A).  z, y: n
- * doubles (device), distinct.  Enqueued on `stream`.  For tests and
- * diagnostics.  Errors: E_INVALID (null argument, no preconditioner built
- * yet: run aplicur_solve first), E_HIP.                                     */
+ * transpose differs), through the same kernels as the one-column LSQR
+ * iteration (the implicit R^T K form for CSR A, the explicit V for dense A;
+ * the first call after a solve with several right-hand sides, which applies
+ * P as z + Q_R W Q_R^T z with W = V_M diag(sigma/Lambda - 1) V_M^T, forms V
+ * once on `stream`).  z, y: n doubles (device), distinct.  Enqueued on
+ * `stream`.  For tests and diagnostics.  Errors: E_INVALID (null argument,
+ * no preconditioner built yet: run aplicur_solve first), E_HIP.           */
 int aplicur_precond_apply(aplicur_ctx* ctx, int32_t trans, const double* z, double* y, void* stream);
 
 /* Measures the product kernels the LSQR iteration uses: `reps` rounds of
