@@ -660,6 +660,9 @@ def main():
     ap_.add_argument("--blocked-prec", type=int, default=0, choices=(0, 1, 2),
                      help="arithmetic of --blocked-products: 0 FP64 accumulation, 1 FP32, 2 BF16")
     ap_.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
+    ap_.add_argument("--sparse-only", action="store_true",
+                     help="only the sparse workload (CSR 200000 x 20000): its product loop and its APLICUR and "
+                          "plain LSQR solves, one JSON line")
     ap_.add_argument("--headline-only", action="store_true",
                      help="only the warm-up and timed solves of the dense kernel workload (no comparisons, no "
                           "other workloads): the run that profiles the product kernel of value's steps")
@@ -711,6 +714,9 @@ def main():
 
     if args.products_only:
         bench_c2(ap, synth, torch, args)
+        return
+    if args.sparse_only:
+        print(json.dumps({"csr_200000x20000": bench_c2(ap, synth, torch, args)}), flush=True)
         return
 
     head = bench_headline(ap, synth, torch, args)
